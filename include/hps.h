@@ -1,0 +1,257 @@
+/*
+ * hps.h -- C ABI of the MI355X composite spectral direct solver.
+ *
+ * Method: Gillman & Martinsson, "A direct solver with O(N) complexity for
+ * variable coefficient elliptic PDEs discretized via a high-order composite
+ * spectral collocation method" (arXiv:1307.2665), dense path of sections 2-5:
+ *   - leaf DtN maps by p x p Chebyshev collocation with q Gauss nodes per leaf
+ *     edge (section 3, T = L4 L3 L2 L1),
+ *   - level-by-level merges of sibling DtNs (section 4, eq:U_parent and
+ *     eq:merge; Algorithm 1),
+ *   - the downward solve (Algorithm 2).
+ *
+ * Problem (section 1.1, eq:basic and eq:defA): A u = 0 on a rectangle, u = f on
+ * its boundary, with
+ *   A u = -c11 u_11 - 2 c12 u_12 - c22 u_22 + c1 u_1 + c2 u_2 + c u.
+ *
+ * Conventions shared by every entry point:
+ *   - Leaves: nx-by-ny equal leaves; leaf index i + nx*j, i along x1.
+ *   - Chebyshev nodes of a leaf: Chebyshev-Lobatto points, ascending in each
+ *     direction; node (a, b) has index a + p*b.
+ *   - Coefficients: double [nx*ny][6][p*p], the six fields in the order
+ *     c11, c12, c22, c1, c2, c, sampled at each leaf's Chebyshev nodes.
+ *   - Gauss nodes: q Gauss-Legendre points per leaf edge.  Global numbering:
+ *     horizontal edge (i, j), i < nx, j <= ny, has id j*nx + i; vertical edge
+ *     (i, j), i <= nx, j < ny, has id nx*(ny+1) + j*(nx+1) + i; node k of an
+ *     edge is id*q + k, ascending along the edge.  N = q*(nx*(ny+1)+(nx+1)*ny).
+ *   - Box boundaries (including the domain boundary Gamma) are ordered S (x1
+ *     ascending), E (x2 ascending), N (x1 ascending), W (x2 ascending);
+ *     n_bdry = 2*q*(nx+ny).
+ *   - Fluxes follow section 2: v = du/dx2 on horizontal edges, du/dx1 on
+ *     vertical edges (so a DtN here is not the outward-normal map).
+ *   - Tree: the root is the whole rectangle; a box is split across its longer
+ *     side (in leaf units) at floor(n/2), x1 first on ties; boxes are numbered
+ *     breadth first (root 0, children 2k+1... in creation order), so every
+ *     parent precedes its children (section 2).  alpha = west/south child.
+ *   - All matrices are row-major FP64 unless stated otherwise.
+ *
+ * Memory: pointers are host pointers unless the options say device_ptrs = 1,
+ * in which case they are device pointers on the current HIP device.  The
+ * library never keeps a caller pointer after a call returns.  An hps_op owns
+ * all of its device memory until hps_destroy.
+ *
+ * Streams: all device work is enqueued on the given hipStream_t (NULL means
+ * the default stream) and every call synchronizes that stream before it
+ * returns, so outputs are ready on return.
+ *
+ * Errors: no C++ exception crosses this ABI.  A non-OK status leaves output
+ * handles NULL, and hps_last_error() returns a thread-local message.
+ *
+ * Threading: one hps_op must not be used from two threads at once.
+ */
+#ifndef HPS_H
+#define HPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hps_op hps_op;
+typedef struct hps_surrogate hps_surrogate;
+
+typedef enum {
+  HPS_OK = 0,
+  HPS_EINVAL = 1,      /* bad argument: sizes, q > p, p < 4, non-finite data, ... */
+  HPS_ESINGULAR = 2,   /* a pivot of a leaf or merge elimination fell below pivot_tol */
+  HPS_ENOMEM = 3,      /* device allocation failed */
+  HPS_EDEVICE = 4,     /* HIP runtime error (no device, launch failure) */
+  HPS_ENOTCONV = 5,    /* iterative refinement did not reach refine_tol in max_iter */
+  HPS_ESURROGATE = 6   /* surrogate unusable for this problem (shape mismatch) */
+} hps_status;
+
+typedef enum {
+  HPS_FP64 = 0,           /* every step in FP64 */
+  HPS_MIXED_SPLIT32 = 1,  /* Schur products on FP32 MFMA with hi/lo splits; LU and TRSM FP64 */
+  HPS_SURROGATE = 2       /* leaf DtNs from a trained surrogate, judged by the FP64 leaf build */
+} hps_mode;
+
+typedef struct {
+  int mode;                        /* hps_mode */
+  void* stream;                    /* hipStream_t */
+  int device_ptrs;                 /* coeffs is a device pointer */
+  int keep_leaf_ops;               /* keep leaf DtNs (needed by refinement; forced on in mixed mode) */
+  int keep_factors;                /* keep LU(M), pivots and Q = [T13a; T23b] per merge (upward pass) */
+  int compute_root_dtn;            /* 1: form T^1 at the root (default), 0: skip its Schur product */
+  double pivot_tol;                /* |pivot| <= pivot_tol * max|column| -> HPS_ESINGULAR; 0: exact 0 only */
+  const hps_surrogate* surrogate;  /* mode HPS_SURROGATE only */
+  int judge_samples;               /* surrogate: number of leaves re-built in FP64 to judge it */
+  double judge_tol;                /* surrogate: max rel. leaf-DtN error before fallback */
+} hps_build_opts;
+
+typedef struct {
+  void* stream;          /* hipStream_t */
+  int device_ptrs;       /* f and u are device pointers */
+  int refine;            /* iterative refinement against the FP64 leaf DtNs */
+  double refine_tol;     /* stop when max|delta| <= refine_tol * max|u| */
+  int max_iter;          /* refinement sweeps allowed */
+} hps_solve_opts;
+
+typedef struct {
+  int iters;                 /* refinement sweeps done */
+  double last_update_rel;    /* max|delta| / max|u| of the last sweep */
+  double first_update_rel;   /* same for the first sweep */
+  int n_fallback_leaves;     /* surrogate leaves replaced by the FP64 leaf build */
+} hps_solve_info;
+
+typedef struct {
+  int nx, ny, p, q;
+  int N;              /* Gauss nodes */
+  int n_bdry;         /* nodes on Gamma */
+  int n_boxes;        /* boxes in the tree */
+  int n_levels;       /* tree depth + 1 */
+  int mode;
+  int n_fallback_leaves;
+  double box[4];
+  int64_t bytes_S;    /* device bytes of all solution operators S */
+  int64_t bytes_total;
+  int64_t flops_build;/* algorithmic FP64 FLOPs of the build (leaf + LU + TRSM + Schur) */
+} hps_op_info;
+
+/* One problem of a heterogeneous batch (hps_build_batch). */
+typedef struct {
+  const double* coeffs;   /* [nx*ny][6][p*p] */
+  double box[4];
+  int nleaf[2];
+  int p, q;
+} hps_problem;
+
+/* ---- discretization helpers (host outputs) ------------------------------ */
+
+/* Chebyshev node coordinates of every leaf: xy[nx*ny][p*p][2] (section 3.1). */
+hps_status hps_cheb_nodes(const double box[4], const int nleaf[2], int p, double* xy);
+
+/* Coordinates of all N Gauss nodes in the global numbering: xy[N][2] (section 2).
+   Also returns N. */
+hps_status hps_gauss_nodes_grid(const double box[4], const int nleaf[2], int q, double* xy, int* N);
+
+/* Global ids of the nodes on Gamma in S,E,N,W order: ids[n_bdry]. */
+hps_status hps_boundary_ids(const int nleaf[2], int q, int* ids, int* n_bdry);
+
+/* ---- leaf stage (section 3) --------------------------------------------- */
+
+/* Leaf DtN maps of nleaf equal leaves of size hx-by-hy (section 3.2):
+   coeffs [nleaf][6][p*p] -> T [nleaf][4q][4q].  Both device pointers. */
+hps_status hps_leaf_dtn(const double* coeffs, int nleaf, double hx, double hy, int p, int q,
+                        double* T, void* stream);
+
+/* ---- build (Algorithm 1) and solve (Algorithm 2) ------------------------ */
+
+/* Builds every S^tau and the root DtN T^1 for one problem.  coeffs as above;
+   box = {x0, x1, y0, y1}; nleaf = {nx, ny}; requires 4 <= p <= 24 and
+   1 <= q <= p (with q > p the merge matrices are singular).  opts may be NULL. */
+hps_status hps_build_solution_operator(const double* coeffs, const double box[4],
+                                       const int nleaf[2], int p, int q,
+                                       const hps_build_opts* opts, hps_op** out);
+
+/* Gauss node coordinates of an operator's grid: xy[N][2]. */
+hps_status hps_gauss_nodes(const hps_op* op, double* xy, int* N);
+
+/* Coordinates of the n_bdry boundary nodes in S,E,N,W order: xy[n_bdry][2]. */
+hps_status hps_boundary_nodes(const hps_op* op, double* xy, int* n_bdry);
+
+/* Algorithm 2: f [nrhs][n_bdry] -> u [nrhs][N] (u on Gamma equals f).
+   With opts->refine, corrections from the interface residual of the FP64
+   leaf DtNs are added until max|delta| <= refine_tol*max|u|. */
+hps_status hps_solve(hps_op* op, const double* f, int nrhs, double* u,
+                     const hps_solve_opts* opts, hps_solve_info* info);
+
+/* Root DtN apply: v = T^1 f, f [nrhs][n_bdry] -> v [nrhs][n_bdry] (Table 1's T_apply). */
+hps_status hps_root_dtn_apply(const hps_op* op, const double* f, int nrhs, double* v,
+                              const hps_solve_opts* opts);
+
+/* ---- iterative-refinement building blocks (device pointers) ------------- */
+
+/* Flux jump v_alpha - v_beta of the FP64 leaf DtNs at every Gauss node
+   (0 on Gamma): u [nrhs][N] -> r [nrhs][N]. */
+hps_status hps_interface_residual(const hps_op* op, const double* u, int nrhs, double* r,
+                                  void* stream);
+
+/* Solution of "jump = s at interior nodes, u = f on Gamma": upward pass for the
+   sources s [nrhs][N], then the downward pass.  Needs keep_factors. */
+hps_status hps_solve_with_sources(hps_op* op, const double* f, const double* s, int nrhs,
+                                  double* u, void* stream);
+
+/* ---- heterogeneous batches --------------------------------------------- */
+
+/* Builds nprob operators; leaves of equal (p, q, h) and merges at equal tree depth
+   of all problems share launches.  out[nprob]. */
+hps_status hps_build_batch(const hps_problem* probs, int nprob, const hps_build_opts* opts,
+                           hps_op** out);
+
+/* Solves every problem of a batch: f[i] [nrhs[i]][n_bdry_i] -> u[i] [nrhs[i]][N_i];
+   the downward passes of all problems share one launch per depth. */
+hps_status hps_solve_batch(hps_op* const* ops, int nprob, const double* const* f,
+                           const int* nrhs, double* const* u, const hps_solve_opts* opts);
+
+/* ---- introspection for tests ------------------------------------------- */
+
+hps_status hps_op_query(const hps_op* op, hps_op_info* info);
+
+/* Box record: {i0, i1, j0, j1, level, parent, child_alpha, child_beta} (children -1 for leaves). */
+hps_status hps_box(const hps_op* op, int box, int rec[8]);
+
+/* S^tau of a parent box (host copy): [m3][m1+m2], rows in I_i order, columns in I_e order. */
+hps_status hps_export_S(const hps_op* op, int box, double* S, int* rows, int* cols);
+
+/* Root DtN T^1 (host copy), [n_bdry][n_bdry]. */
+hps_status hps_export_root_dtn(const hps_op* op, double* T);
+
+/* Leaf DtN of leaf index i + nx*j (host copy), [4q][4q]; needs keep_leaf_ops. */
+hps_status hps_export_leaf_dtn(const hps_op* op, int leaf, double* T);
+
+/* ---- batched dense layer (device pointers) ------------------------------- */
+
+/* X_i = M_i^-1 B_i for nprob independent systems by LU with partial pivoting
+   (the elimination used for eq:leaf_solve and eq:U_parent).  M [nprob][n][n],
+   B [nprob][n][m], X [nprob][n][m]; inputs are not modified.  A zero or
+   non-finite pivot gives HPS_ESINGULAR (X is then unspecified). */
+hps_status hps_batched_solve(const double* M, const double* B, int n, int m, int nprob, double* X,
+                             void* stream);
+
+/* C_i = C_i + alpha A_i B_i for nprob products, A [nprob][Mr][K], B [nprob][K][Nc],
+   C [nprob][Mr][Nc]; split32 = 1 uses the split-FP32 MFMA form of the Schur
+   products (three FP32 products of hi/lo halves, FP64 accumulation per slab). */
+hps_status hps_batched_gemm(const double* A, const double* B, double* C, int Mr, int Nc, int K,
+                            int nprob, double alpha, int split32, void* stream);
+
+/* ---- host-side planner queries (no device work; used by CPU tests) ------ */
+
+/* Coefficient-independent leaf tables for a hx-by-hy leaf (section 3.2),
+   n = (p-2)^2, m = 4q: Dx, Dy, Dxx, Dyy [p][p]; G [5][n][m] (the images of L1
+   under D1^2, D1 D2, D2^2, D1, D2 restricted to interior rows); P0 = L4 L3e L1
+   [m][m]; P1 = L4 L3i [m][n]; Ji [n] interior node indices.  Any output may be
+   NULL. */
+hps_status hps_leaf_tables(int p, int q, double hx, double hy, double* Dx, double* Dy, double* Dxx,
+                           double* Dyy, double* G, double* P0, double* P1, int* Ji);
+
+/* Tree and merge maps of an nx-by-ny grid without building anything.
+   rec as in hps_box; for a parent box sizes = {m1+m2, m3, n_alpha, n_beta} and
+   pmap [m1+m2] (>= 0: position in alpha's boundary list, < 0: -(position in
+   beta's) - 1), a3/b3 [m3] (shared-edge positions in alpha/beta), Ie [m1+m2]
+   and Ii [m3] (global ids).  Returns the number of boxes in *n_boxes. */
+hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int sizes[4], int* pmap,
+                        int* a3, int* b3, int* Ie, int* Ii, int* n_boxes);
+
+/* ---- lifetime, errors --------------------------------------------------- */
+
+void hps_destroy(hps_op* op);
+const char* hps_last_error(void);
+const char* hps_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPS_H */

@@ -1,0 +1,341 @@
+"""MI355X composite spectral direct solver (Gillman & Martinsson, sections 2-5).
+
+Thin Python binding of ``libhps.so``: every function marshals arguments to the
+C entry point of the same name (declared in ``include/hps.h``).  All numerical
+work runs in the HIP kernels of the library; PyTorch is used only for device
+memory and streams.  Arrays may be NumPy arrays (host) or torch tensors; CUDA
+(ROCm) tensors are passed as device pointers, on the current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from ._lib import (HPS_EINVAL, HPS_ENOTCONV, HPS_ESINGULAR, HPS_FP64, HPS_MIXED_SPLIT32,
+                   HPS_SURROGATE, BuildOpts, HpsError, OpInfo, Problem, SolveInfo, SolveOpts,
+                   check, lib)
+
+__all__ = ["HpsError", "HPS_FP64", "HPS_MIXED_SPLIT32", "HPS_SURROGATE", "HPS_EINVAL",
+           "HPS_ESINGULAR", "HPS_ENOTCONV", "Operator", "cheb_nodes", "gauss_nodes_grid",
+           "boundary_ids", "leaf_dtn", "build_solution_operator", "build_batch", "solve_batch",
+           "leaf_tables", "plan_box", "version", "lib", "batched_solve", "batched_gemm"]
+
+
+def version() -> str:
+    return lib.hps_version().decode()
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _dev(x) -> bool:
+    return _is_torch(x) and x.is_cuda
+
+
+def _ptr(x):
+    """Pointer of a contiguous float64/int32 NumPy array or torch tensor."""
+    if _is_torch(x):
+        assert x.is_contiguous(), "tensor must be contiguous"
+        return C.c_void_p(x.data_ptr())
+    assert x.flags["C_CONTIGUOUS"], "array must be C-contiguous"
+    return x.ctypes.data_as(C.c_void_p)
+
+
+def _stream(x=None):
+    import torch
+    if x is not None and _dev(x):
+        return C.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)
+    if torch.cuda.is_available():
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(0)
+
+
+def _f64(x):
+    if _is_torch(x):
+        import torch
+        assert x.dtype == torch.float64, "float64 tensor required"
+        return x.contiguous()
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+# ---- discretization helpers (host) -----------------------------------------
+
+def cheb_nodes(box, nleaf, p: int) -> np.ndarray:
+    nx, ny = nleaf
+    xy = np.empty((nx * ny, p * p, 2))
+    b = (C.c_double * 4)(*box)
+    nl = (C.c_int * 2)(nx, ny)
+    check(lib.hps_cheb_nodes(b, nl, p, _ptr(xy)))
+    return xy
+
+
+def gauss_nodes_grid(box, nleaf, q: int) -> np.ndarray:
+    b = (C.c_double * 4)(*box)
+    nl = (C.c_int * 2)(*nleaf)
+    N = C.c_int()
+    check(lib.hps_gauss_nodes_grid(b, nl, q, None, C.byref(N)))
+    xy = np.empty((N.value, 2))
+    check(lib.hps_gauss_nodes_grid(b, nl, q, _ptr(xy), C.byref(N)))
+    return xy
+
+
+def boundary_ids(nleaf, q: int) -> np.ndarray:
+    nl = (C.c_int * 2)(*nleaf)
+    n = C.c_int()
+    check(lib.hps_boundary_ids(nl, q, None, C.byref(n)))
+    ids = np.empty(n.value, dtype=np.int32)
+    check(lib.hps_boundary_ids(nl, q, _ptr(ids), C.byref(n)))
+    return ids
+
+
+def leaf_tables(p: int, q: int, hx: float, hy: float) -> dict:
+    n, m = (p - 2) ** 2, 4 * q
+    out = dict(Dx=np.empty((p, p)), Dy=np.empty((p, p)), Dxx=np.empty((p, p)),
+               Dyy=np.empty((p, p)), G=np.empty((5, n, m)), P0=np.empty((m, m)),
+               P1=np.empty((m, n)), Ji=np.empty(n, dtype=np.int32))
+    check(lib.hps_leaf_tables(p, q, hx, hy, *[_ptr(out[k]) for k in
+                                              ("Dx", "Dy", "Dxx", "Dyy", "G", "P0", "P1", "Ji")]))
+    return out
+
+
+def plan_box(nleaf, q: int, box: int) -> dict:
+    nl = (C.c_int * 2)(*nleaf)
+    nb = C.c_int()
+    rec = np.empty(8, dtype=np.int32)
+    sizes = np.zeros(4, dtype=np.int32)
+    check(lib.hps_plan_box(nl, q, box, _ptr(rec), _ptr(sizes), None, None, None, None, None,
+                           C.byref(nb)))
+    me, m3 = int(sizes[0]), int(sizes[1])
+    arrs = dict(pmap=np.empty(me, np.int32), a3=np.empty(m3, np.int32), b3=np.empty(m3, np.int32),
+                Ie=np.empty(me, np.int32), Ii=np.empty(m3, np.int32))
+    if me:
+        check(lib.hps_plan_box(nl, q, box, _ptr(rec), _ptr(sizes), _ptr(arrs["pmap"]),
+                               _ptr(arrs["a3"]), _ptr(arrs["b3"]), _ptr(arrs["Ie"]),
+                               _ptr(arrs["Ii"]), C.byref(nb)))
+    return dict(rec=rec, sizes=sizes, n_boxes=nb.value, **arrs)
+
+
+# ---- leaf stage ----------------------------------------------------------------
+
+def leaf_dtn(coeffs, hx: float, hy: float, p: int, q: int, out=None):
+    """Leaf DtN maps (section 3.2) of a batch of equal leaves; device tensors only."""
+    import torch
+    coeffs = _f64(coeffs)
+    assert _dev(coeffs), "hps_leaf_dtn takes device tensors"
+    nl = coeffs.shape[0]
+    if out is None:
+        out = torch.empty((nl, 4 * q, 4 * q), dtype=torch.float64, device=coeffs.device)
+    check(lib.hps_leaf_dtn(_ptr(coeffs), nl, hx, hy, p, q, _ptr(out), _stream(coeffs)))
+    return out
+
+
+# ---- batched dense layer ---------------------------------------------------------
+
+def batched_solve(M, B, X=None):
+    """X_i = M_i^-1 B_i (LU with partial pivoting on the device); device tensors."""
+    import torch
+    M = _f64(M)
+    B = _f64(B)
+    assert _dev(M) and _dev(B)
+    nprob, n, m = B.shape
+    if X is None:
+        X = torch.empty_like(B)
+    check(lib.hps_batched_solve(_ptr(M), _ptr(B), n, m, nprob, _ptr(X), _stream(M)))
+    return X
+
+
+def batched_gemm(A, B, C, alpha: float = 1.0, split32: bool = False):
+    """C_i += alpha A_i B_i on the device (FP64 MFMA or the split-FP32 form)."""
+    A = _f64(A)
+    B = _f64(B)
+    assert _dev(A) and _dev(B) and _dev(C)
+    nprob, Mr, K = A.shape
+    Nc = B.shape[2]
+    check(lib.hps_batched_gemm(_ptr(A), _ptr(B), _ptr(C), Mr, Nc, K, nprob, alpha, int(split32),
+                               _stream(A)))
+    return C
+
+
+# ---- operator --------------------------------------------------------------------
+
+class Operator:
+    """Owner of an ``hps_op`` (solution operators in device memory)."""
+
+    def __init__(self, handle: C.c_void_p):
+        self._h = handle
+        info = OpInfo()
+        check(lib.hps_op_query(self._h, C.byref(info)))
+        self.nx, self.ny, self.p, self.q = info.nx, info.ny, info.p, info.q
+        self.N, self.n_bdry = info.N, info.n_bdry
+        self.n_boxes, self.n_levels = info.n_boxes, info.n_levels
+        self.mode = info.mode
+        self.box = tuple(info.box)
+        self.bytes_S, self.bytes_total, self.flops_build = info.bytes_S, info.bytes_total, info.flops_build
+
+    def __del__(self):
+        self.destroy()
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            lib.hps_destroy(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def n_tot(self) -> int:
+        """Total discretization points: Chebyshev grid points plus Gauss nodes (Table 1's N_tot)."""
+        return (self.nx * (self.p - 1) + 1) * (self.ny * (self.p - 1) + 1) + self.N
+
+    def gauss_nodes(self) -> np.ndarray:
+        xy = np.empty((self.N, 2))
+        N = C.c_int()
+        check(lib.hps_gauss_nodes(self._h, _ptr(xy), C.byref(N)))
+        return xy
+
+    def boundary_nodes(self) -> np.ndarray:
+        xy = np.empty((self.n_bdry, 2))
+        n = C.c_int()
+        check(lib.hps_boundary_nodes(self._h, _ptr(xy), C.byref(n)))
+        return xy
+
+    def solve(self, f, u=None, refine: bool = False, tol: float = 1e-12, max_iter: int = 10,
+              info: Optional[dict] = None):
+        """Algorithm 2: f [nrhs, n_bdry] -> u [nrhs, N]."""
+        f = _f64(f)
+        if f.ndim == 1:
+            f = f.reshape(1, -1)
+        nrhs = f.shape[0]
+        dev = _dev(f)
+        if u is None:
+            if dev:
+                import torch
+                u = torch.empty((nrhs, self.N), dtype=torch.float64, device=f.device)
+            else:
+                u = np.empty((nrhs, self.N))
+        so = SolveOpts(_stream(f) if dev else None, int(dev), int(refine), tol, max_iter)
+        si = SolveInfo()
+        check(lib.hps_solve(self._h, _ptr(f), nrhs, _ptr(u), C.byref(so), C.byref(si)))
+        if info is not None:
+            info.update(iters=si.iters, last_update_rel=si.last_update_rel,
+                        first_update_rel=si.first_update_rel,
+                        n_fallback_leaves=si.n_fallback_leaves)
+        return u
+
+    def root_dtn_apply(self, f, v=None):
+        f = _f64(f)
+        if f.ndim == 1:
+            f = f.reshape(1, -1)
+        dev = _dev(f)
+        if v is None:
+            if dev:
+                import torch
+                v = torch.empty_like(f)
+            else:
+                v = np.empty_like(f)
+        so = SolveOpts(_stream(f) if dev else None, int(dev), 0, 0.0, 0)
+        check(lib.hps_root_dtn_apply(self._h, _ptr(f), f.shape[0], _ptr(v), C.byref(so)))
+        return v
+
+    def interface_residual(self, u, r=None):
+        import torch
+        u = _f64(u)
+        assert _dev(u)
+        if r is None:
+            r = torch.empty_like(u)
+        check(lib.hps_interface_residual(self._h, _ptr(u), u.shape[0], _ptr(r), _stream(u)))
+        return r
+
+    def solve_with_sources(self, f, s, u=None):
+        import torch
+        f = _f64(f)
+        s = _f64(s)
+        assert _dev(f) and _dev(s)
+        if u is None:
+            u = torch.empty((f.shape[0], self.N), dtype=torch.float64, device=f.device)
+        check(lib.hps_solve_with_sources(self._h, _ptr(f), _ptr(s), f.shape[0], _ptr(u),
+                                         _stream(f)))
+        return u
+
+    def box_record(self, b: int) -> np.ndarray:
+        rec = np.empty(8, dtype=np.int32)
+        check(lib.hps_box(self._h, b, _ptr(rec)))
+        return rec
+
+    def export_S(self, b: int) -> np.ndarray:
+        r, c = C.c_int(), C.c_int()
+        check(lib.hps_export_S(self._h, b, None, C.byref(r), C.byref(c)))
+        S = np.empty((r.value, c.value))
+        check(lib.hps_export_S(self._h, b, _ptr(S), C.byref(r), C.byref(c)))
+        return S
+
+    def export_root_dtn(self) -> np.ndarray:
+        T = np.empty((self.n_bdry, self.n_bdry))
+        check(lib.hps_export_root_dtn(self._h, _ptr(T)))
+        return T
+
+    def export_leaf_dtn(self, leaf: int) -> np.ndarray:
+        m = 4 * self.q
+        T = np.empty((m, m))
+        check(lib.hps_export_leaf_dtn(self._h, leaf, _ptr(T)))
+        return T
+
+
+def _build_opts(mode, stream, device_ptrs, keep_factors, root_dtn):
+    return BuildOpts(mode, stream, int(device_ptrs), 1, int(keep_factors), int(root_dtn), 0.0,
+                     None, 0, 0.0)
+
+
+def build_solution_operator(coeffs, box, nleaf, p: int, q: int, mode: int = HPS_FP64,
+                            keep_factors: bool = False, root_dtn: bool = True) -> Operator:
+    """Algorithm 1.  coeffs [nx*ny, 6, p*p] (c11, c12, c22, c1, c2, c at Chebyshev nodes)."""
+    coeffs = _f64(coeffs)
+    dev = _dev(coeffs)
+    bo = _build_opts(mode, _stream(coeffs) if dev else None, dev, keep_factors, root_dtn)
+    h = C.c_void_p()
+    check(lib.hps_build_solution_operator(_ptr(coeffs), (C.c_double * 4)(*box),
+                                          (C.c_int * 2)(*nleaf), p, q, C.byref(bo), C.byref(h)))
+    return Operator(h)
+
+
+def build_batch(problems: Sequence[dict], mode: int = HPS_FP64, keep_factors: bool = False,
+                root_dtn: bool = True) -> List[Operator]:
+    """Heterogeneous batch; problems are dicts with coeffs (device), box, nleaf, p, q."""
+    arr = (Problem * len(problems))()
+    keep = []
+    for i, pr in enumerate(problems):
+        c = _f64(pr["coeffs"])
+        assert _dev(c), "hps_build_batch takes device coefficient tensors"
+        keep.append(c)
+        arr[i].coeffs = c.data_ptr()
+        arr[i].box = (C.c_double * 4)(*pr["box"])
+        arr[i].nleaf = (C.c_int * 2)(*pr["nleaf"])
+        arr[i].p = pr["p"]
+        arr[i].q = pr["q"]
+    bo = _build_opts(mode, _stream(keep[0]), 1, keep_factors, root_dtn)
+    hs = (C.c_void_p * len(problems))()
+    check(lib.hps_build_batch(arr, len(problems), C.byref(bo), hs))
+    return [Operator(C.c_void_p(h)) for h in hs]
+
+
+def solve_batch(ops: Sequence[Operator], fs, us=None):
+    """Solves every problem of a batch (device tensors)."""
+    import torch
+    n = len(ops)
+    fs = [_f64(f) for f in fs]
+    if us is None:
+        us = [torch.empty((f.shape[0], op.N), dtype=torch.float64, device=f.device)
+              for op, f in zip(ops, fs)]
+    hs = (C.c_void_p * n)(*[op.handle.value if isinstance(op.handle, C.c_void_p) else op.handle
+                            for op in ops])
+    fp = (C.c_void_p * n)(*[f.data_ptr() for f in fs])
+    up = (C.c_void_p * n)(*[u.data_ptr() for u in us])
+    nr = (C.c_int * n)(*[f.shape[0] for f in fs])
+    so = SolveOpts(_stream(fs[0]), 1, 0, 0.0, 0)
+    check(lib.hps_solve_batch(hs, n, fp, nr, up, C.byref(so)))
+    return us

@@ -1,0 +1,441 @@
+// C ABI of the solver (declared in include/hps.h).  Every entry point catches
+// library errors and turns them into a status plus a thread-local message.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dense.h"
+#include "solver.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+template <class F>
+hps_status guard(F&& f) {
+  try {
+    f();
+    return HPS_OK;
+  } catch (const hps::Error& e) {
+    g_err = e.what();
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return HPS_ENOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return HPS_EINVAL;
+  }
+}
+
+hps::BuildOptions to_build_options(const hps_build_opts* o) {
+  hps::BuildOptions b;
+  if (!o) return b;
+  b.mode = o->mode;
+  b.stream = (hipStream_t)o->stream;
+  b.device_ptrs = o->device_ptrs != 0;
+  b.keep_leaf = true;
+  b.keep_factors = o->keep_factors != 0;
+  b.root_dtn = o->compute_root_dtn != 0;
+  return b;
+}
+
+// Device staging of a caller array that may live on the host.
+struct Staged {
+  double* d = nullptr;
+  bool owned = false;
+  ~Staged() {
+    if (owned && d) (void)hipFree(d);
+  }
+};
+
+void stage_in(Staged& st, const double* p, size_t n, bool device, hipStream_t s) {
+  if (device) {
+    st.d = const_cast<double*>(p);
+    return;
+  }
+  HPS_HIP(hipMalloc((void**)&st.d, std::max<size_t>(n, 1) * sizeof(double)));
+  st.owned = true;
+  if (n) HPS_HIP(hipMemcpyAsync(st.d, p, n * sizeof(double), hipMemcpyHostToDevice, s));
+}
+
+void stage_out(const Staged& st, double* p, size_t n, bool device, hipStream_t s) {
+  if (!device && n)
+    HPS_HIP(hipMemcpyAsync(p, st.d, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  HPS_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hps_last_error(void) { return g_err.c_str(); }
+const char* hps_version(void) { return "hps-mi355x 0.1 (gfx950)"; }
+
+hps_status hps_cheb_nodes(const double box[4], const int nleaf[2], int p, double* xy) {
+  return guard([&] {
+    HPS_REQUIRE(box && nleaf && xy && p >= 2 && nleaf[0] >= 1 && nleaf[1] >= 1, "bad arguments");
+    std::vector<double> v;
+    hps::cheb_node_xy(nleaf[0], nleaf[1], p, box, v);
+    std::memcpy(xy, v.data(), v.size() * sizeof(double));
+  });
+}
+
+hps_status hps_gauss_nodes_grid(const double box[4], const int nleaf[2], int q, double* xy, int* N) {
+  return guard([&] {
+    HPS_REQUIRE(box && nleaf && q >= 1 && nleaf[0] >= 1 && nleaf[1] >= 1, "bad arguments");
+    hps::Tree t;
+    t.nx = nleaf[0];
+    t.ny = nleaf[1];
+    t.q = q;
+    t.nh = t.nx * (t.ny + 1);
+    t.N = q * (t.nx * (t.ny + 1) + (t.nx + 1) * t.ny);
+    if (N) *N = t.N;
+    if (xy) {
+      std::vector<double> v;
+      hps::gauss_node_xy(t, box, v);
+      std::memcpy(xy, v.data(), v.size() * sizeof(double));
+    }
+  });
+}
+
+hps_status hps_boundary_ids(const int nleaf[2], int q, int* ids, int* n_bdry) {
+  return guard([&] {
+    HPS_REQUIRE(nleaf && q >= 1 && nleaf[0] >= 1 && nleaf[1] >= 1, "bad arguments");
+    hps::Tree t;
+    t.nx = nleaf[0];
+    t.ny = nleaf[1];
+    t.q = q;
+    t.nh = t.nx * (t.ny + 1);
+    std::vector<int> v;
+    hps::box_boundary(t, 0, t.nx, 0, t.ny, v);
+    if (n_bdry) *n_bdry = (int)v.size();
+    if (ids) std::memcpy(ids, v.data(), v.size() * sizeof(int));
+  });
+}
+
+hps_status hps_leaf_dtn(const double* coeffs, int nleaf, double hx, double hy, int p, int q,
+                        double* T, void* stream) {
+  return guard([&] {
+    HPS_REQUIRE(coeffs && T && hx > 0 && hy > 0, "bad arguments");
+    hps::leaf_dtn_batch(coeffs, nleaf, hx, hy, p, q, T, (hipStream_t)stream);
+  });
+}
+
+hps_status hps_build_solution_operator(const double* coeffs, const double box[4],
+                                       const int nleaf[2], int p, int q,
+                                       const hps_build_opts* opts, hps_op** out) {
+  if (out) *out = nullptr;
+  return guard([&] {
+    HPS_REQUIRE(out != nullptr, "out is null");
+    HPS_REQUIRE(!opts || opts->mode == HPS_FP64 || opts->mode == HPS_MIXED_SPLIT32,
+                "mode not supported by this entry point");
+    hps::BuildOptions bo = to_build_options(opts);
+    auto op = hps::plan_operator(coeffs, box, nleaf, p, q, bo);
+    std::vector<hps_op*> v{op.get()};
+    hps::run_build(v, bo.stream);
+    *out = op.release();
+  });
+}
+
+hps_status hps_build_batch(const hps_problem* probs, int nprob, const hps_build_opts* opts,
+                           hps_op** out) {
+  return guard([&] {
+    HPS_REQUIRE(probs && out && nprob >= 1, "bad arguments");
+    for (int i = 0; i < nprob; ++i) out[i] = nullptr;
+    hps::BuildOptions bo = to_build_options(opts);
+    std::vector<std::unique_ptr<hps_op>> owned;
+    std::vector<hps_op*> v;
+    for (int i = 0; i < nprob; ++i) {
+      owned.push_back(hps::plan_operator(probs[i].coeffs, probs[i].box, probs[i].nleaf,
+                                         probs[i].p, probs[i].q, bo));
+      v.push_back(owned.back().get());
+    }
+    hps::run_build(v, bo.stream);
+    for (int i = 0; i < nprob; ++i) out[i] = owned[i].release();
+  });
+}
+
+hps_status hps_gauss_nodes(const hps_op* op, double* xy, int* N) {
+  return guard([&] {
+    HPS_REQUIRE(op, "null operator");
+    if (N) *N = op->tree.N;
+    if (xy) {
+      std::vector<double> v;
+      hps::gauss_node_xy(op->tree, op->box, v);
+      std::memcpy(xy, v.data(), v.size() * sizeof(double));
+    }
+  });
+}
+
+hps_status hps_boundary_nodes(const hps_op* op, double* xy, int* n_bdry) {
+  return guard([&] {
+    HPS_REQUIRE(op, "null operator");
+    if (n_bdry) *n_bdry = op->n_bdry;
+    if (xy) {
+      std::vector<double> v;
+      std::vector<int> ids;
+      hps::gauss_node_xy(op->tree, op->box, v);
+      hps::box_boundary(op->tree, 0, op->nx, 0, op->ny, ids);
+      for (size_t i = 0; i < ids.size(); ++i) {
+        xy[2 * i] = v[2 * (size_t)ids[i]];
+        xy[2 * i + 1] = v[2 * (size_t)ids[i] + 1];
+      }
+    }
+  });
+}
+
+hps_status hps_solve(hps_op* op, const double* f, int nrhs, double* u, const hps_solve_opts* opts,
+                     hps_solve_info* info) {
+  return guard([&] {
+    HPS_REQUIRE(op && f && u && nrhs >= 1, "bad arguments");
+    hipStream_t s = opts ? (hipStream_t)opts->stream : nullptr;
+    const bool dev = opts && opts->device_ptrs;
+    const size_t nf = (size_t)op->n_bdry * nrhs, nu = (size_t)op->tree.N * nrhs;
+    if (!dev)
+      for (size_t i = 0; i < nf; ++i) HPS_REQUIRE(std::isfinite(f[i]), "non-finite boundary data");
+    Staged F, U;
+    stage_in(F, f, nf, dev, s);
+    if (dev) {
+      U.d = u;
+    } else {
+      HPS_HIP(hipMalloc((void**)&U.d, nu * sizeof(double)));
+      U.owned = true;
+    }
+    if (info) std::memset(info, 0, sizeof(*info));
+    hps::solve_device(op, F.d, nrhs, U.d, s);
+    if (opts && opts->refine)
+      hps::refine_device(op, F.d, nrhs, U.d, opts->refine_tol > 0 ? opts->refine_tol : 1e-12,
+                         opts->max_iter > 0 ? opts->max_iter : 10, s, info);
+    if (info) info->n_fallback_leaves = op->n_fallback;
+    stage_out(U, u, nu, dev, s);
+  });
+}
+
+hps_status hps_solve_batch(hps_op* const* ops, int nprob, const double* const* f, const int* nrhs,
+                           double* const* u, const hps_solve_opts* opts) {
+  return guard([&] {
+    HPS_REQUIRE(ops && f && nrhs && u && nprob >= 1, "bad arguments");
+    HPS_REQUIRE(opts && opts->device_ptrs, "hps_solve_batch takes device pointers");
+    HPS_REQUIRE(!opts->refine, "refinement is per operator (hps_solve)");
+    hipStream_t s = (hipStream_t)opts->stream;
+    std::vector<hps_op*> v(ops, ops + nprob);
+    std::vector<const double*> fv(f, f + nprob);
+    std::vector<int> nv(nrhs, nrhs + nprob);
+    std::vector<double*> uv(u, u + nprob);
+    hps::solve_batch_device(v, fv, nv, uv, s);
+    HPS_HIP(hipStreamSynchronize(s));
+  });
+}
+
+hps_status hps_root_dtn_apply(const hps_op* op, const double* f, int nrhs, double* v,
+                              const hps_solve_opts* opts) {
+  return guard([&] {
+    HPS_REQUIRE(op && f && v && nrhs >= 1, "bad arguments");
+    hipStream_t s = opts ? (hipStream_t)opts->stream : nullptr;
+    const bool dev = opts && opts->device_ptrs;
+    const size_t n = (size_t)op->n_bdry * nrhs;
+    Staged F, V;
+    stage_in(F, f, n, dev, s);
+    if (dev) {
+      V.d = v;
+    } else {
+      HPS_HIP(hipMalloc((void**)&V.d, n * sizeof(double)));
+      V.owned = true;
+    }
+    hps::root_apply_device(op, F.d, nrhs, V.d, s);
+    stage_out(V, v, n, dev, s);
+  });
+}
+
+hps_status hps_interface_residual(const hps_op* op, const double* u, int nrhs, double* r,
+                                  void* stream) {
+  return guard([&] {
+    HPS_REQUIRE(op && u && r && nrhs >= 1, "bad arguments");
+    hps::residual_device(op, u, nrhs, r, (hipStream_t)stream);
+    HPS_HIP(hipStreamSynchronize((hipStream_t)stream));
+  });
+}
+
+hps_status hps_solve_with_sources(hps_op* op, const double* f, const double* s, int nrhs, double* u,
+                                  void* stream) {
+  return guard([&] {
+    HPS_REQUIRE(op && f && s && u && nrhs >= 1, "bad arguments");
+    hps::solve_with_sources_device(op, f, s, nrhs, u, (hipStream_t)stream);
+    HPS_HIP(hipStreamSynchronize((hipStream_t)stream));
+  });
+}
+
+hps_status hps_op_query(const hps_op* op, hps_op_info* info) {
+  return guard([&] {
+    HPS_REQUIRE(op && info, "bad arguments");
+    std::memset(info, 0, sizeof(*info));
+    info->nx = op->nx;
+    info->ny = op->ny;
+    info->p = op->p;
+    info->q = op->q;
+    info->N = op->tree.N;
+    info->n_bdry = op->n_bdry;
+    info->n_boxes = (int)op->tree.boxes.size();
+    info->n_levels = op->tree.depth + 1;
+    info->mode = op->mode;
+    info->n_fallback_leaves = op->n_fallback;
+    std::memcpy(info->box, op->box, sizeof(info->box));
+    info->bytes_S = op->bytes_S;
+    info->bytes_total = (int64_t)op->mem.bytes;
+    info->flops_build = op->flops;
+  });
+}
+
+hps_status hps_box(const hps_op* op, int box, int rec[8]) {
+  return guard([&] {
+    HPS_REQUIRE(op && rec && box >= 0 && box < (int)op->tree.boxes.size(), "bad arguments");
+    const hps::BoxRec& b = op->tree.boxes[box];
+    int v[8] = {b.i0, b.i1, b.j0, b.j1, b.level, b.parent, b.ca, b.cb};
+    std::memcpy(rec, v, sizeof(v));
+  });
+}
+
+hps_status hps_export_S(const hps_op* op, int box, double* S, int* rows, int* cols) {
+  return guard([&] {
+    HPS_REQUIRE(op && box >= 0 && box < (int)op->tree.boxes.size(), "bad arguments");
+    int lv = op->merge_level[box];
+    HPS_REQUIRE(lv >= 0, "box is a leaf");
+    const hps::MergeDesc& d = op->levels[lv].h[op->merge_index[box]];
+    if (rows) *rows = d.m3;
+    if (cols) *cols = d.me;
+    if (S)
+      HPS_HIP(hipMemcpy(S, d.S, (size_t)d.m3 * d.me * sizeof(double), hipMemcpyDeviceToHost));
+  });
+}
+
+hps_status hps_export_root_dtn(const hps_op* op, double* T) {
+  return guard([&] {
+    HPS_REQUIRE(op && T, "bad arguments");
+    HPS_REQUIRE(op->opt.root_dtn, "operator was built without the root DtN");
+    HPS_HIP(hipMemcpy(T, op->rootT, (size_t)op->n_bdry * op->n_bdry * sizeof(double),
+                      hipMemcpyDeviceToHost));
+  });
+}
+
+hps_status hps_export_leaf_dtn(const hps_op* op, int leaf, double* T) {
+  return guard([&] {
+    HPS_REQUIRE(op && T && leaf >= 0 && leaf < op->nx * op->ny, "bad arguments");
+    const size_t m = 4 * (size_t)op->q;
+    HPS_HIP(hipMemcpy(T, op->leafT + (size_t)leaf * m * m, m * m * sizeof(double),
+                      hipMemcpyDeviceToHost));
+  });
+}
+
+hps_status hps_batched_solve(const double* M, const double* B, int n, int m, int nprob, double* X,
+                             void* stream) {
+  return guard([&] {
+    HPS_REQUIRE(M && B && X && n >= 1 && m >= 1 && nprob >= 1, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    hps::dense_init();
+    hps::DeviceMem tmp;
+    const int ld = n + m;
+    double* W = tmp.alloc<double>((size_t)nprob * n * ld);
+    int* piv = tmp.alloc<int>((size_t)nprob * n);
+    int* st = tmp.alloc<int>(4);
+    HPS_HIP(hipMemsetAsync(st, 0, 4 * sizeof(int), s));
+    for (int i = 0; i < nprob; ++i) {
+      HPS_HIP(hipMemcpy2DAsync(W + (size_t)i * n * ld, ld * sizeof(double), M + (size_t)i * n * n,
+                               n * sizeof(double), n * sizeof(double), n, hipMemcpyDeviceToDevice,
+                               s));
+      HPS_HIP(hipMemcpy2DAsync(W + (size_t)i * n * ld + n, ld * sizeof(double),
+                               B + (size_t)i * n * m, m * sizeof(double), m * sizeof(double), n,
+                               hipMemcpyDeviceToDevice, s));
+    }
+    std::vector<hps::SolveDesc> hd(nprob);
+    for (int i = 0; i < nprob; ++i)
+      hd[i] = hps::SolveDesc{W + (size_t)i * n * ld, piv + (size_t)i * n, X + (size_t)i * n * m,
+                             n, m, ld, m, i, 0};
+    hps::SolveDesc* dd = tmp.upload(hd, s);
+    hps::batched_solve(dd, hd, st, s, 32);
+    int h[4];
+    HPS_HIP(hipMemcpyAsync(h, st, sizeof(h), hipMemcpyDeviceToHost, s));
+    HPS_HIP(hipStreamSynchronize(s));
+    if (h[0]) throw hps::Error(HPS_ESINGULAR, "zero or non-finite pivot in system " +
+                                                  std::to_string(h[1]));
+  });
+}
+
+hps_status hps_batched_gemm(const double* A, const double* B, double* C, int Mr, int Nc, int K,
+                            int nprob, double alpha, int split32, void* stream) {
+  return guard([&] {
+    HPS_REQUIRE(A && B && C && Mr >= 1 && Nc >= 1 && K >= 1 && nprob >= 1, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    hps::DeviceMem tmp;
+    std::vector<hps::GemmDesc> hd(nprob);
+    for (int i = 0; i < nprob; ++i)
+      hd[i] = hps::GemmDesc{A + (size_t)i * Mr * K, B + (size_t)i * K * Nc, C + (size_t)i * Mr * Nc,
+                            nullptr, Mr, Nc, K, K, Nc, Nc, 0, alpha};
+    hps::GemmDesc* dd = tmp.upload(hd, s);
+    hps::grouped_gemm(dd, hd, s, split32 != 0);
+    HPS_HIP(hipStreamSynchronize(s));
+  });
+}
+
+hps_status hps_leaf_tables(int p, int q, double hx, double hy, double* Dx, double* Dy, double* Dxx,
+                           double* Dyy, double* G, double* P0, double* P1, int* Ji) {
+  return guard([&] {
+    HPS_REQUIRE(p >= 4 && p <= 24 && q >= 1 && q <= p && hx > 0 && hy > 0, "bad arguments");
+    hps::LeafTables t = hps::make_leaf_tables(p, q, hx, hy);
+    auto put = [](double* dst, const std::vector<double>& v) {
+      if (dst) std::memcpy(dst, v.data(), v.size() * sizeof(double));
+    };
+    put(Dx, t.Dx);
+    put(Dy, t.Dy);
+    put(Dxx, t.Dxx);
+    put(Dyy, t.Dyy);
+    put(G, t.G);
+    put(P0, t.P0);
+    put(P1, t.P1);
+    if (Ji) std::memcpy(Ji, t.Ji.data(), t.Ji.size() * sizeof(int));
+  });
+}
+
+hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int sizes[4], int* pmap,
+                        int* a3, int* b3, int* Ie, int* Ii, int* n_boxes) {
+  return guard([&] {
+    HPS_REQUIRE(nleaf && nleaf[0] >= 1 && nleaf[1] >= 1 && q >= 1, "bad arguments");
+    hps::Tree t = hps::build_tree(nleaf[0], nleaf[1], q);
+    if (n_boxes) *n_boxes = (int)t.boxes.size();
+    if (box < 0) return;
+    HPS_REQUIRE(box < (int)t.boxes.size(), "box out of range");
+    const hps::BoxRec& b = t.boxes[box];
+    if (rec) {
+      int v[8] = {b.i0, b.i1, b.j0, b.j1, b.level, b.parent, b.ca, b.cb};
+      std::memcpy(rec, v, sizeof(v));
+    }
+    if (b.ca < 0) {
+      if (sizes) sizes[0] = sizes[1] = sizes[2] = sizes[3] = 0;
+      return;
+    }
+    hps::MergeMaps mm = hps::merge_maps(t, box);
+    if (sizes) {
+      sizes[0] = mm.me;
+      sizes[1] = mm.m3;
+      sizes[2] = mm.na;
+      sizes[3] = mm.nb;
+    }
+    auto put = [](int* dst, const std::vector<int>& v) {
+      if (dst) std::memcpy(dst, v.data(), v.size() * sizeof(int));
+    };
+    put(pmap, mm.pmap);
+    put(a3, mm.a3);
+    put(b3, mm.b3);
+    put(Ie, mm.Ie);
+    put(Ii, mm.Ii);
+  });
+}
+
+void hps_destroy(hps_op* op) {
+  if (!op) return;
+  (void)hipDeviceSynchronize();
+  delete op;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Shared definitions of the HIP library: error plumbing, device descriptors.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/hps.h"
+
+namespace hps {
+
+// Error carried from deep inside the library to the C ABI, where it becomes a
+// status code plus a thread-local message.  Exceptions never cross the ABI.
+struct Error : std::runtime_error {
+  hps_status status;
+  Error(hps_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define HPS_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw ::hps::Error(e_ == hipErrorOutOfMemory ? HPS_ENOMEM : HPS_EDEVICE,          \
+                         std::string(#call) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+#define HPS_REQUIRE(cond, msg)                                                          \
+  do {                                                                                  \
+    if (!(cond)) throw ::hps::Error(HPS_EINVAL, msg);                                   \
+  } while (0)
+
+// One dense system of the batched solver: the augmented row-major matrix
+// W = [M | B] (n rows, n + m columns used, leading dimension ld) is factored in
+// place (LU with partial pivoting of M, forward elimination applied to B) and
+// X = M^-1 B is written to X (n rows, leading dimension ldx).
+struct SolveDesc {
+  double* W;
+  int* piv;        // n pivot rows (absolute row index chosen at each column)
+  double* X;
+  int n, m, ld, ldx;
+  int tag;         // caller's id (box or leaf), reported on singular pivots
+  int pad;
+};
+
+// C (M x N, ldc) = C0 + alpha * A (M x K, lda) * B (K x N, ldb), all row-major
+// FP64, where C0 is the matrix at C0 (leading dimension ldc0) when C0 is not
+// null and the old contents of C otherwise.
+struct GemmDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  const double* C0;
+  int M, N, K;
+  int lda, ldb, ldc, ldc0;
+  double alpha;
+};
+
+// One tile of a grouped GEMM launch: problem index and tile coordinates.
+struct TileRef {
+  int prob, tm, tn, pad;
+};
+
+// One merge of two sibling boxes (section 4).  alpha = west/south child,
+// beta = east/north child.  Maps are child-local boundary positions.
+struct MergeDesc {
+  const double* Ta;   // alpha's DtN, na x na
+  const double* Tb;   // beta's DtN, nb x nb
+  double* Tp;         // parent DtN, me x me (me = m1 + m2)
+  double* W;          // augmented [M | B], m3 x (m3 + me), ld = m3 + me
+  double* S;          // solution operator, m3 x me
+  double* Q;          // [T13a; T23b] in parent order, me x m3
+  int* piv;           // m3 pivots (kept with W when factors are kept)
+  const int* pmap;    // me entries: >= 0 position in alpha, < 0: -(position in beta) - 1
+  const int* a3;      // m3 positions of the shared edge in alpha
+  const int* b3;      // m3 positions of the shared edge in beta
+  const int* Ie;      // me global ids (parent boundary, S,E,N,W)
+  const int* Ii;      // m3 global ids (shared edge)
+  int na, nb, me, m3;
+  int box, pad;
+};
+
+}  // namespace hps

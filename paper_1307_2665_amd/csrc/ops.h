@@ -1,0 +1,41 @@
+// Problem-specific kernels (leaf assembly, merge gather, downward and upward
+// passes, interface residual) -- host entry points.
+#pragma once
+
+#include <cstddef>
+
+#include "common.h"
+
+namespace hps {
+
+// Device copies of the coefficient-independent leaf tables (see LeafTables).
+struct LeafDev {
+  const double* Dx;
+  const double* Dy;
+  const double* Dxx;
+  const double* Dyy;
+  const double* G;   // 5 x n x m
+  int p, n, m, pad;
+};
+
+void leaf_assemble(const double* const* cptr, const LeafDev& tab, int count, double* W,
+                   hipStream_t s);
+void merge_gather(const MergeDesc* d_desc, int nmerge, size_t max_elems, hipStream_t s);
+void downward(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, double* u, int N,
+              int nrhs, const double* zbase, const long long* zoff, hipStream_t s);
+void set_boundary(const double* f, const int* gamma, int nb, double* u, int N, int nrhs,
+                  hipStream_t s);
+void interface_residual(const double* leafT, const double* u, int N, int nrhs, int nx, int ny,
+                        int q, double* vbuf, double* r, hipStream_t s);
+void upward_level(const MergeDesc* d_desc, int nmerge, int m3_max, const double* s, int N, int nb,
+                  const double* hchild, const long long* ha_off, const long long* hb_off,
+                  double* hpar, const long long* hp_off, double* zbuf, const long long* z_off,
+                  int nrhs, hipStream_t st);
+void axpy(double* y, const double* x, double a, size_t n, hipStream_t s);
+void absmax_partial(const double* x, size_t n, double* out, int blocks, hipStream_t s);
+void matvec(const double* A, int rows, int cols, const double* x, int nrhs, double* y,
+            hipStream_t s);
+void nonfinite(const double* x, size_t n, int* flag, hipStream_t s);
+void ops_init();
+
+}  // namespace hps

@@ -1,0 +1,465 @@
+// Problem-specific kernels: leaf assembly (section 3), merge gather
+// (section 4), downward pass (Algorithm 2), interface residual and the
+// upward source pass used by iterative refinement.
+#include "ops.h"
+
+#include <algorithm>
+
+namespace hps {
+
+// ---------------------------------------------------------------------------
+// Leaf assembly (section 3.1): for every leaf build the augmented system
+// W = [A_ii | R], R = A_ie L1, with n = (p-2)^2 rows and ld = n + 4q.
+// A_ii[k][k'] with k = (a, b), k' = (a', b') interior:
+//   -c11 Dxx[a][a'] d_bb' - 2 c12 Dx[a][a'] Dy[b][b'] - c22 Dyy[b][b'] d_aa'
+//   + c1 Dx[a][a'] d_bb' + c2 Dy[b][b'] d_aa' + c d_kk'
+// R[k][:] = -c11 G11[k] - 2 c12 G12[k] - c22 G22[k] + c1 G1[k] + c2 G2[k].
+// ---------------------------------------------------------------------------
+constexpr int PMAX = 24;
+
+__global__ void __launch_bounds__(256) k_leaf_assemble(const double* const* __restrict__ cptr,
+                                                       const LeafDev tab,
+                                                       double* __restrict__ W) {
+  __shared__ double Dx[PMAX * PMAX], Dy[PMAX * PMAX], Dxx[PMAX * PMAX], Dyy[PMAX * PMAX];
+  __shared__ double cf[6][(PMAX - 2) * (PMAX - 2)];
+  const int p = tab.p, n = tab.n, m = tab.m, pi = p - 2;
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    Dx[e] = tab.Dx[e];
+    Dy[e] = tab.Dy[e];
+    Dxx[e] = tab.Dxx[e];
+    Dyy[e] = tab.Dyy[e];
+  }
+  const double* cl = cptr[blockIdx.x];
+  for (int e = threadIdx.x; e < 6 * n; e += blockDim.x) {
+    int f = e / n, k = e % n;
+    int a = 1 + k % pi, b = 1 + k / pi;
+    cf[f][k] = cl[(size_t)f * p * p + a + p * b];
+  }
+  __syncthreads();
+  const int ld = n + m;
+  double* Wl = W + (size_t)blockIdx.x * n * ld;
+  for (int e = threadIdx.x; e < n * ld; e += blockDim.x) {
+    const int k = e / ld, col = e % ld;
+    const double c11 = cf[0][k], c12 = cf[1][k], c22 = cf[2][k];
+    const double c1 = cf[3][k], c2 = cf[4][k];
+    double v;
+    if (col < n) {
+      const int a = 1 + k % pi, b = 1 + k / pi;
+      const int a2 = 1 + col % pi, b2 = 1 + col / pi;
+      const double dx = Dx[a * p + a2], dy = Dy[b * p + b2];
+      v = -2.0 * c12 * dx * dy;
+      if (b == b2) v += -c11 * Dxx[a * p + a2] + c1 * dx;
+      if (a == a2) v += -c22 * Dyy[b * p + b2] + c2 * dy;
+      if (col == k) v += cf[5][k];
+    } else {
+      const int c = col - n;
+      const size_t o = (size_t)k * m + c, s = (size_t)n * m;
+      v = -c11 * tab.G[o] - 2.0 * c12 * tab.G[s + o] - c22 * tab.G[2 * s + o] +
+          c1 * tab.G[3 * s + o] + c2 * tab.G[4 * s + o];
+    }
+    Wl[e] = v;
+  }
+}
+
+void leaf_assemble(const double* const* cptr, const LeafDev& tab, int count, double* W,
+                   hipStream_t s) {
+  HPS_REQUIRE(tab.p <= PMAX, "p too large");
+  hipLaunchKernelGGL(k_leaf_assemble, dim3(count), dim3(256), 0, s, cptr, tab, W);
+}
+
+// ---------------------------------------------------------------------------
+// Merge gather (section 4, eq:premerge blocks): for each merge build
+//   W = [T33a - T33b | -T31a, T32b] (m3 x (m3 + me), columns of B in parent order),
+//   Q = [T13a; T23b] (me x m3, rows in parent order),
+//   Tp = diag(T11a, T22b) in parent order (me x me).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_merge_gather(const MergeDesc* __restrict__ descs) {
+  const MergeDesc d = descs[blockIdx.y];
+  const int m3 = d.m3, me = d.me, ldw = m3 + me;
+  const size_t nW = (size_t)m3 * ldw, nQ = (size_t)me * m3, nT = (size_t)me * me;
+  const size_t tot = nW + nQ + nT;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    if (e < nW) {
+      int i = (int)(e / ldw), j = (int)(e % ldw);
+      int ra = d.a3[i], rb = d.b3[i];
+      double v;
+      if (j < m3) {
+        v = d.Ta[(size_t)ra * d.na + d.a3[j]] - d.Tb[(size_t)rb * d.nb + d.b3[j]];
+      } else {
+        int pm = d.pmap[j - m3];
+        v = (pm >= 0) ? -d.Ta[(size_t)ra * d.na + pm] : d.Tb[(size_t)rb * d.nb + (-pm - 1)];
+      }
+      d.W[e] = v;
+    } else if (e < nW + nQ) {
+      size_t f = e - nW;
+      int r = (int)(f / m3), i = (int)(f % m3);
+      int pm = d.pmap[r];
+      d.Q[f] = (pm >= 0) ? d.Ta[(size_t)pm * d.na + d.a3[i]]
+                         : d.Tb[(size_t)(-pm - 1) * d.nb + d.b3[i]];
+    } else {
+      size_t f = e - nW - nQ;
+      int r = (int)(f / me), c = (int)(f % me);
+      int pr = d.pmap[r], pc = d.pmap[c];
+      double v = 0.0;
+      if (pr >= 0 && pc >= 0)
+        v = d.Ta[(size_t)pr * d.na + pc];
+      else if (pr < 0 && pc < 0)
+        v = d.Tb[(size_t)(-pr - 1) * d.nb + (-pc - 1)];
+      d.Tp[f] = v;
+    }
+  }
+}
+
+void merge_gather(const MergeDesc* d_desc, int nmerge, size_t max_elems, hipStream_t s) {
+  int bx = (int)std::min<size_t>((max_elems + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_merge_gather, dim3(bx, nmerge), dim3(256), 0, s, d_desc);
+}
+
+// ---------------------------------------------------------------------------
+// Downward pass (Algorithm 2, line 3): u(I_i) = S u(I_e) (+ z) for every merge
+// of one level.  u is [nrhs][N].  A workgroup owns DROWS rows of one S; the
+// gathered boundary values of up to RC right-hand sides sit in LDS.
+// ---------------------------------------------------------------------------
+constexpr int DROWS = 16;
+
+__global__ void __launch_bounds__(256) k_downward(const MergeDesc* __restrict__ descs,
+                                                  double* __restrict__ u, int N, int nrhs, int rc) {
+  extern __shared__ double ue[];
+  const MergeDesc d = descs[blockIdx.y];
+  const int r0 = blockIdx.x * DROWS;
+  if (r0 >= d.m3) return;
+  const int me = d.me;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int rb = 0; rb < nrhs; rb += rc) {
+    const int nr = min(rc, nrhs - rb);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * me; e += blockDim.x) {
+      int k = e / me, c = e % me;
+      ue[e] = u[(size_t)(rb + k) * N + d.Ie[c]];
+    }
+    __syncthreads();
+    for (int rr = wid; rr < DROWS; rr += 4) {
+      const int r = r0 + rr;
+      if (r >= d.m3) break;
+      const double* Srow = d.S + (size_t)r * me;
+      for (int k = 0; k < nr; ++k) {
+        double acc = 0.0;
+        for (int c = lane; c < me; c += 64) acc += Srow[c] * ue[k * me + c];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) u[(size_t)(rb + k) * N + d.Ii[r]] = acc;
+      }
+    }
+  }
+}
+
+// Interface-term variant: z of merge i is [nrhs][m3] at zbase + zoff[i] * nrhs.
+__global__ void __launch_bounds__(256) k_downward_z(const MergeDesc* __restrict__ descs,
+                                                    double* __restrict__ u, int N, int nrhs, int rc,
+                                                    const double* __restrict__ zbase,
+                                                    const long long* __restrict__ zoff) {
+  extern __shared__ double ue[];
+  const MergeDesc d = descs[blockIdx.y];
+  const int r0 = blockIdx.x * DROWS;
+  if (r0 >= d.m3) return;
+  const int me = d.me;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const double* z = zbase + zoff[blockIdx.y] * nrhs;
+  for (int rb = 0; rb < nrhs; rb += rc) {
+    const int nr = min(rc, nrhs - rb);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * me; e += blockDim.x) {
+      int k = e / me, c = e % me;
+      ue[e] = u[(size_t)(rb + k) * N + d.Ie[c]];
+    }
+    __syncthreads();
+    for (int rr = wid; rr < DROWS; rr += 4) {
+      const int r = r0 + rr;
+      if (r >= d.m3) break;
+      const double* Srow = d.S + (size_t)r * me;
+      for (int k = 0; k < nr; ++k) {
+        double acc = 0.0;
+        for (int c = lane; c < me; c += 64) acc += Srow[c] * ue[k * me + c];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) u[(size_t)(rb + k) * N + d.Ii[r]] = acc + z[(size_t)(rb + k) * d.m3 + r];
+      }
+    }
+  }
+}
+
+int downward_rhs_chunk(int me_max, int nrhs) {
+  int rc = std::max(1, 8192 / std::max(1, me_max));
+  return std::min(rc, std::max(1, nrhs));
+}
+
+void downward(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, double* u, int N,
+              int nrhs, const double* zbase, const long long* zoff, hipStream_t s) {
+  HPS_REQUIRE((size_t)me_max * sizeof(double) <= 96 * 1024,
+              "downward pass: box boundary too long for the LDS-staged kernel");
+  const int rc = downward_rhs_chunk(me_max, nrhs);
+  size_t shm = (size_t)rc * me_max * sizeof(double);
+  dim3 grid((m3_max + DROWS - 1) / DROWS, nmerge);
+  if (zbase)
+    hipLaunchKernelGGL(k_downward_z, grid, dim3(256), shm, s, d_desc, u, N, nrhs, rc, zbase, zoff);
+  else
+    hipLaunchKernelGGL(k_downward, grid, dim3(256), shm, s, d_desc, u, N, nrhs, rc);
+}
+
+// Boundary data into u: u[r][gamma[i]] = f[r][i].
+__global__ void k_set_boundary(const double* __restrict__ f, const int* __restrict__ gamma,
+                               int nb, double* __restrict__ u, int N, int nrhs) {
+  size_t tot = (size_t)nb * nrhs;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    int r = (int)(e / nb), i = (int)(e % nb);
+    u[(size_t)r * N + gamma[i]] = f[e];
+  }
+}
+
+void set_boundary(const double* f, const int* gamma, int nb, double* u, int N, int nrhs,
+                  hipStream_t s) {
+  size_t tot = (size_t)nb * nrhs;
+  int blocks = (int)std::min<size_t>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_set_boundary, dim3(std::max(blocks, 1)), dim3(256), 0, s, f, gamma, nb, u,
+                     N, nrhs);
+}
+
+// ---------------------------------------------------------------------------
+// Interface residual: v_leaf = T_leaf u(I_e^leaf) for every leaf, then the
+// jump v_alpha - v_beta at every interior Gauss node (0 on the boundary).
+// ---------------------------------------------------------------------------
+__device__ inline int leaf_bdry_id(int i, int j, int nx, int nh, int q, int k) {
+  int side = k / q, t = k % q;
+  switch (side) {
+    case 0: return (j * nx + i) * q + t;                  // S: hedge (i, j)
+    case 1: return (nh + j * (nx + 1) + i + 1) * q + t;   // E: vedge (i+1, j)
+    case 2: return ((j + 1) * nx + i) * q + t;            // N: hedge (i, j+1)
+    default: return (nh + j * (nx + 1) + i) * q + t;      // W: vedge (i, j)
+  }
+}
+
+__global__ void __launch_bounds__(256) k_leaf_flux(const double* __restrict__ T,
+                                                   const double* __restrict__ u, int N, int nrhs,
+                                                   int nx, int ny, int q,
+                                                   double* __restrict__ v) {
+  __shared__ double ue[8][96];
+  const int leaf = blockIdx.x;
+  const int i = leaf % nx, j = leaf / nx;
+  const int m = 4 * q, nh = nx * (ny + 1);
+  const double* Tl = T + (size_t)leaf * m * m;
+  for (int rb = 0; rb < nrhs; rb += 8) {
+    const int nr = min(8, nrhs - rb);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * m; e += blockDim.x) {
+      int k = e / m, c = e % m;
+      ue[k][c] = u[(size_t)(rb + k) * N + leaf_bdry_id(i, j, nx, nh, q, c)];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * m; e += blockDim.x) {
+      int k = e / m, r = e % m;
+      double acc = 0.0;
+      for (int c = 0; c < m; ++c) acc += Tl[(size_t)r * m + c] * ue[k][c];
+      v[((size_t)(rb + k) * nx * ny + leaf) * m + r] = acc;
+    }
+  }
+}
+
+__global__ void k_jump(const double* __restrict__ v, int nx, int ny, int q, int nrhs,
+                       double* __restrict__ r, int N) {
+  const int nh = nx * (ny + 1), m = 4 * q;
+  const size_t nl = (size_t)nx * ny;
+  size_t tot = (size_t)N * nrhs;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    int rh = (int)(e / N), g = (int)(e % N);
+    int edge = g / q, k = g % q;
+    double val = 0.0;
+    const double* vr = v + (size_t)rh * nl * m;
+    if (edge < nh) {
+      int i = edge % nx, j = edge / nx;
+      if (j > 0 && j < ny)  // alpha = south leaf (its N side), beta = north leaf (its S side)
+        val = vr[((size_t)(i + nx * (j - 1))) * m + 2 * q + k] - vr[((size_t)(i + nx * j)) * m + k];
+    } else {
+      int ve = edge - nh;
+      int i = ve % (nx + 1), j = ve / (nx + 1);
+      if (i > 0 && i < nx)  // alpha = west leaf (its E side), beta = east leaf (its W side)
+        val = vr[((size_t)(i - 1 + nx * j)) * m + q + k] - vr[((size_t)(i + nx * j)) * m + 3 * q + k];
+    }
+    r[e] = val;
+  }
+}
+
+void interface_residual(const double* leafT, const double* u, int N, int nrhs, int nx, int ny,
+                        int q, double* vbuf, double* r, hipStream_t s) {
+  HPS_REQUIRE(4 * q <= 96, "q too large for the residual kernel");
+  hipLaunchKernelGGL(k_leaf_flux, dim3(nx * ny), dim3(256), 0, s, leafT, u, N, nrhs, nx, ny, q,
+                     vbuf);
+  size_t tot = (size_t)N * nrhs;
+  int blocks = (int)std::min<size_t>((tot + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_jump, dim3(blocks), dim3(256), 0, s, vbuf, nx, ny, q, nrhs, r, N);
+}
+
+// ---------------------------------------------------------------------------
+// Upward source pass for one level (derived from the third block row of
+// eq:premerge with a source):  z = M^-1 (s3 - h3a + h3b),
+// h_parent = [h1a ; h2b] (parent order) + Q z.
+// M^-1 is applied with the kept LU factors: row interchanges and the unit
+// lower factor panel by panel (the left columns were never swapped after their
+// panel), then the upper factor.  One workgroup per (merge, right-hand side).
+// LU is stored in W[0:m3, 0:m3] with leading dimension ldw = m3 + me.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_upward(const MergeDesc* __restrict__ descs,
+                                                const double* __restrict__ s, int N, int nb,
+                                                const double* __restrict__ hchild,
+                                                const long long* __restrict__ ha_off,
+                                                const long long* __restrict__ hb_off,
+                                                double* __restrict__ hpar,
+                                                const long long* __restrict__ hp_off,
+                                                double* __restrict__ zbuf,
+                                                const long long* __restrict__ z_off,
+                                                int nrhs) {
+  extern __shared__ double zs[];
+  const int mi = blockIdx.x, rh = blockIdx.y;
+  const MergeDesc d = descs[mi];
+  const int m3 = d.m3, me = d.me, ldw = m3 + me;
+  // Offsets are per-box unit offsets; each box holds [nrhs][boundary size].
+  const double* ha = hchild ? hchild + ha_off[mi] * nrhs + (size_t)rh * d.na : nullptr;
+  const double* hb = hchild ? hchild + hb_off[mi] * nrhs + (size_t)rh * d.nb : nullptr;
+  for (int i = threadIdx.x; i < m3; i += blockDim.x) {
+    double v = s[(size_t)rh * N + d.Ii[i]];
+    if (ha) v += -ha[d.a3[i]] + hb[d.b3[i]];
+    zs[i] = v;
+  }
+  __syncthreads();
+  // Forward: interleaved row swaps and unit-lower elimination, panel by panel.
+  for (int k0 = 0; k0 < m3; k0 += nb) {
+    const int kb = min(nb, m3 - k0);
+    if (threadIdx.x == 0)
+      for (int j = 0; j < kb; ++j) {
+        int r2 = d.piv[k0 + j];
+        if (r2 != k0 + j) {
+          double t = zs[k0 + j];
+          zs[k0 + j] = zs[r2];
+          zs[r2] = t;
+        }
+      }
+    __syncthreads();
+    for (int j = 0; j < kb; ++j) {
+      const double zj = zs[k0 + j];
+      for (int r = k0 + j + 1 + threadIdx.x; r < m3; r += blockDim.x)
+        zs[r] -= d.W[(size_t)r * ldw + k0 + j] * zj;
+      __syncthreads();
+    }
+  }
+  // Backward with the upper factor.
+  for (int c = m3 - 1; c >= 0; --c) {
+    if (threadIdx.x == 0) zs[c] = zs[c] / d.W[(size_t)c * ldw + c];
+    __syncthreads();
+    const double zc = zs[c];
+    for (int r = threadIdx.x; r < c; r += blockDim.x) zs[r] -= d.W[(size_t)r * ldw + c] * zc;
+    __syncthreads();
+  }
+  double* z = zbuf + z_off[mi] * nrhs + (size_t)rh * m3;
+  for (int i = threadIdx.x; i < m3; i += blockDim.x) z[i] = zs[i];
+  // Parent particular flux h = [h1a; h2b] + Q z.
+  if (hpar) {
+    double* hp = hpar + hp_off[mi] * nrhs + (size_t)rh * me;
+    for (int r = threadIdx.x; r < me; r += blockDim.x) {
+      int pm = d.pmap[r];
+      double v = 0.0;
+      if (ha) v = (pm >= 0) ? ha[pm] : hb[-pm - 1];
+      const double* Qr = d.Q + (size_t)r * m3;
+      for (int i = 0; i < m3; ++i) v += Qr[i] * zs[i];
+      hp[r] = v;
+    }
+  }
+}
+
+void upward_level(const MergeDesc* d_desc, int nmerge, int m3_max, const double* s, int N, int nb,
+                  const double* hchild, const long long* ha_off, const long long* hb_off,
+                  double* hpar, const long long* hp_off, double* zbuf, const long long* z_off,
+                  int nrhs, hipStream_t st) {
+  size_t shm = (size_t)m3_max * sizeof(double);
+  hipLaunchKernelGGL(k_upward, dim3(nmerge, nrhs), dim3(256), shm, st, d_desc, s, N, nb, hchild,
+                     ha_off, hb_off, hpar, hp_off, zbuf, z_off, nrhs);
+}
+
+// ---------------------------------------------------------------------------
+// Small elementwise helpers.
+// ---------------------------------------------------------------------------
+__global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, size_t n) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    y[e] += a * x[e];
+}
+
+void axpy(double* y, const double* x, double a, size_t n, hipStream_t s) {
+  int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_axpy, dim3(std::max(blocks, 1)), dim3(256), 0, s, y, x, a, n);
+}
+
+// max |x| per block into out[block]; host finishes.  Used for refinement norms.
+__global__ void k_absmax(const double* __restrict__ x, size_t n, double* __restrict__ out) {
+  __shared__ double sm[4];
+  double m = 0.0;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    m = fmax(m, fabs(x[e]));
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = fmax(fmax(sm[0], sm[1]), fmax(sm[2], sm[3]));
+}
+
+void absmax_partial(const double* x, size_t n, double* out, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_absmax, dim3(blocks), dim3(256), 0, s, x, n, out);
+}
+
+// y[r][i] = sum_j A[i][j] x[r][j]; one wave per (row, right-hand side).
+__global__ void __launch_bounds__(256) k_matvec(const double* __restrict__ A, int rows, int cols,
+                                                const double* __restrict__ x, int nrhs,
+                                                double* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const long long w = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= (long long)rows * nrhs) return;
+  const int i = (int)(w % rows), r = (int)(w / rows);
+  const double* Ar = A + (size_t)i * cols;
+  const double* xr = x + (size_t)r * cols;
+  double acc = 0.0;
+  for (int j = lane; j < cols; j += 64) acc += Ar[j] * xr[j];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) y[(size_t)r * rows + i] = acc;
+}
+
+void matvec(const double* A, int rows, int cols, const double* x, int nrhs, double* y,
+            hipStream_t s) {
+  long long waves = (long long)rows * nrhs;
+  hipLaunchKernelGGL(k_matvec, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, A, rows, cols,
+                     x, nrhs, y);
+}
+
+// flag[0] = 1 if any entry is NaN or infinite.
+__global__ void k_nonfinite(const double* __restrict__ x, size_t n, int* flag) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+       e += (size_t)gridDim.x * blockDim.x)
+    if (!isfinite(x[e])) flag[0] = 1;
+}
+
+void nonfinite(const double* x, size_t n, int* flag, hipStream_t s) {
+  int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_nonfinite, dim3(std::max(blocks, 1)), dim3(256), 0, s, x, n, flag);
+}
+
+void ops_init() {
+  static bool done = false;
+  if (done) return;
+  HPS_HIP(hipFuncSetAttribute((const void*)k_downward, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              96 * 1024));
+  HPS_HIP(hipFuncSetAttribute((const void*)k_downward_z,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
+  HPS_HIP(hipFuncSetAttribute((const void*)k_upward, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              96 * 1024));
+  done = true;
+}
+
+}  // namespace hps

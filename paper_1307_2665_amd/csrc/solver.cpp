@@ -1,0 +1,515 @@
+// Build (Algorithm 1) and solve (Algorithm 2) drivers of the MI355X solver.
+//
+// Memory plan of one operator (all FP64 in HBM, row-major):
+//   leafT   [nleaf][4q][4q]      leaf DtNs (section 3), kept for refinement;
+//   arena0/1                    DtNs of the boxes at even/odd depth: the
+//                               children of a merge live in the other arena,
+//                               so only two levels of T are ever alive
+//                               (Algorithm 1 deletes children's T);
+//   S       per merge m3 x me    solution operators (eq:U_parent), kept;
+//   W, Q, piv                    per merge augmented system [M | B] (its
+//                               left block ends up holding LU(M)), Q = [T13a;
+//                               T23b] and pivots: kept per merge when the
+//                               upward pass is wanted, else one level of
+//                               scratch reused by every level.
+#include "solver.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+#include "dense.h"
+#include "ops.h"
+
+namespace hps {
+
+DeviceMem::~DeviceMem() {
+  for (void* p : ptrs) (void)hipFree(p);
+}
+
+void* DeviceMem::raw(size_t b) {
+  void* p = nullptr;
+  HPS_HIP(hipMalloc(&p, b));
+  ptrs.push_back(p);
+  bytes += b;
+  return p;
+}
+
+static void init_runtime() {
+  dense_init();
+  ops_init();
+}
+
+static inline int bdry_size(const BoxRec& b, int q) { return 2 * q * ((b.i1 - b.i0) + (b.j1 - b.j0)); }
+
+std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4], const int nleaf[2],
+                                      int p, int q, const BuildOptions& o) {
+  HPS_REQUIRE(coeffs != nullptr && box != nullptr && nleaf != nullptr, "null argument");
+  HPS_REQUIRE(p >= 4 && p <= 24, "p must be in [4, 24]");
+  HPS_REQUIRE(q >= 1 && q <= p, "q must satisfy 1 <= q <= p (q > p makes the merges singular)");
+  HPS_REQUIRE(nleaf[0] >= 1 && nleaf[1] >= 1, "nleaf must be >= 1");
+  HPS_REQUIRE(std::isfinite(box[0]) && std::isfinite(box[1]) && std::isfinite(box[2]) &&
+                  std::isfinite(box[3]) && box[1] > box[0] && box[3] > box[2],
+              "degenerate box");
+  init_runtime();
+  hipStream_t s = o.stream;
+  auto op = std::make_unique<hps_op>();
+  op->nx = nleaf[0];
+  op->ny = nleaf[1];
+  op->p = p;
+  op->q = q;
+  op->mode = o.mode;
+  std::memcpy(op->box, box, sizeof(op->box));
+  op->opt = o;
+  if (o.mode == HPS_MIXED_SPLIT32) {
+    op->opt.keep_factors = true;
+    op->opt.keep_leaf = true;
+  }
+  const int nx = op->nx, ny = op->ny, m = 4 * q;
+  const size_t nl = (size_t)nx * ny;
+  op->tree = build_tree(nx, ny, q);
+  const Tree& t = op->tree;
+  const double hx = (box[1] - box[0]) / nx, hy = (box[3] - box[2]) / ny;
+  op->lt = make_leaf_tables(p, q, hx, hy);
+  const LeafTables& lt = op->lt;
+
+  const size_t ncoef = nl * 6 * p * p;
+  if (o.device_ptrs) {
+    op->coeffs = coeffs;
+  } else {
+    for (size_t i = 0; i < ncoef; ++i)
+      HPS_REQUIRE(std::isfinite(coeffs[i]), "non-finite coefficient");
+    double* d = op->mem.alloc<double>(ncoef);
+    HPS_HIP(hipMemcpyAsync(d, coeffs, ncoef * sizeof(double), hipMemcpyHostToDevice, s));
+    op->coeffs = d;
+  }
+  op->dDx = op->mem.upload(lt.Dx, s);
+  op->dDy = op->mem.upload(lt.Dy, s);
+  op->dDxx = op->mem.upload(lt.Dxx, s);
+  op->dDyy = op->mem.upload(lt.Dyy, s);
+  op->dG = op->mem.upload(lt.G, s);
+  op->dP0 = op->mem.upload(lt.P0, s);
+  op->dP1 = op->mem.upload(lt.P1, s);
+  op->leafT = op->mem.alloc<double>(nl * m * m);
+
+  std::vector<int> ids;
+  box_boundary(t, 0, nx, 0, ny, ids);
+  op->n_bdry = (int)ids.size();
+  op->gamma = op->mem.upload(ids, s);
+
+  // ---- merges: maps, sizes, offsets --------------------------------------
+  const int nbox = (int)t.boxes.size();
+  std::vector<MergeMaps> mm(nbox);
+  std::vector<size_t> pool_off(nbox, 0);
+  std::vector<int> pool;
+  std::vector<long long> Toff(nbox, 0);
+  std::vector<long long> lvlT(t.depth + 1, 0);
+  for (int d = 0; d <= t.depth; ++d)
+    for (int b : t.parents_at_level[d]) {
+      mm[b] = merge_maps(t, b);
+      pool_off[b] = pool.size();
+      pool.insert(pool.end(), mm[b].pmap.begin(), mm[b].pmap.end());
+      pool.insert(pool.end(), mm[b].a3.begin(), mm[b].a3.end());
+      pool.insert(pool.end(), mm[b].b3.begin(), mm[b].b3.end());
+      pool.insert(pool.end(), mm[b].Ie.begin(), mm[b].Ie.end());
+      pool.insert(pool.end(), mm[b].Ii.begin(), mm[b].Ii.end());
+      Toff[b] = lvlT[d];
+      lvlT[d] += (long long)mm[b].me * mm[b].me;
+    }
+  int* dpool = op->mem.upload(pool, s);
+
+  const bool keep = op->opt.keep_factors;
+  long long totS = 0, totW = 0, totQ = 0, totP = 0;
+  long long maxW = 0, maxQ = 0, maxP = 0;
+  for (int d = 0; d <= t.depth; ++d) {
+    long long lw = 0, lq = 0, lp = 0;
+    for (int b : t.parents_at_level[d]) {
+      const MergeMaps& g = mm[b];
+      totS += (long long)g.m3 * g.me;
+      lw += (long long)g.m3 * (g.m3 + g.me);
+      lq += (long long)g.me * g.m3;
+      lp += g.m3;
+    }
+    totW += lw;
+    totQ += lq;
+    totP += lp;
+    maxW = std::max(maxW, lw);
+    maxQ = std::max(maxQ, lq);
+    maxP = std::max(maxP, lp);
+  }
+  op->S = op->mem.alloc<double>(totS);
+  op->bytes_S = totS * (long long)sizeof(double);
+  op->Wk = op->mem.alloc<double>(keep ? totW : maxW);
+  op->Q = op->mem.alloc<double>(keep ? totQ : maxQ);
+  op->piv = op->mem.alloc<int>(keep ? totP : maxP);
+  long long ar[2] = {0, 0};
+  for (int d = 0; d <= t.depth; ++d) ar[d % 2] = std::max(ar[d % 2], lvlT[d]);
+  op->arena[0] = op->mem.alloc<double>(ar[0]);
+  op->arena[1] = op->mem.alloc<double>(ar[1]);
+
+  op->box_hoff.assign(nbox, 0);
+  long long hu = 0;
+  for (int b = 0; b < nbox; ++b) {
+    op->box_hoff[b] = hu;
+    hu += bdry_size(t.boxes[b], q);
+  }
+  op->h_units = hu;
+
+  // ---- descriptors ---------------------------------------------------------
+  op->levels.assign(t.depth + 1, LevelPlan());
+  op->merge_level.assign(nbox, -1);
+  op->merge_index.assign(nbox, -1);
+  long long oS = 0, oW = 0, oQ = 0, oP = 0, oz = 0;
+  const int n_int = (p - 2) * (p - 2);
+  long long flops = (long long)nl * ((2LL * n_int * n_int * n_int) / 3 + 2LL * n_int * n_int * m +
+                                     2LL * m * m * n_int);
+  for (int d = 0; d <= t.depth; ++d) {
+    LevelPlan& L = op->levels[d];
+    if (!keep) oW = oQ = oP = 0;
+    for (int b : t.parents_at_level[d]) {
+      const BoxRec& B = t.boxes[b];
+      const MergeMaps& g = mm[b];
+      MergeDesc md{};
+      auto child_T = [&](int c) -> const double* {
+        const BoxRec& C = t.boxes[c];
+        if (C.ca < 0) return op->leafT + (size_t)(C.i0 + nx * C.j0) * m * m;
+        return op->arena[(d + 1) % 2] + Toff[c];
+      };
+      md.Ta = child_T(B.ca);
+      md.Tb = child_T(B.cb);
+      md.Tp = op->arena[d % 2] + Toff[b];
+      md.W = op->Wk + oW;
+      md.S = op->S + oS;
+      md.Q = op->Q + oQ;
+      md.piv = op->piv + oP;
+      const int* base = dpool + pool_off[b];
+      md.pmap = base;
+      md.a3 = base + g.me;
+      md.b3 = base + g.me + g.m3;
+      md.Ie = base + g.me + 2 * g.m3;
+      md.Ii = base + 2 * g.me + 2 * g.m3;
+      md.na = g.na;
+      md.nb = g.nb;
+      md.me = g.me;
+      md.m3 = g.m3;
+      md.box = b;
+      op->merge_level[b] = d;
+      op->merge_index[b] = (int)L.h.size();
+      L.h.push_back(md);
+      SolveDesc sd{md.W, md.piv, md.S, g.m3, g.me, g.m3 + g.me, g.me, b, 0};
+      L.hs.push_back(sd);
+      if (b != 0 || op->opt.root_dtn) {
+        GemmDesc gd{md.Q, md.S, md.Tp, nullptr, g.me, g.me, g.m3, g.m3, g.me, g.me, 0, 1.0};
+        L.hg.push_back(gd);
+      }
+      L.ha.push_back(op->box_hoff[B.ca]);
+      L.hb.push_back(op->box_hoff[B.cb]);
+      L.hp.push_back(op->box_hoff[b]);
+      L.zo.push_back(oz);
+      L.m3_max = std::max(L.m3_max, g.m3);
+      L.me_max = std::max(L.me_max, g.me);
+      L.gather_max = std::max(L.gather_max, (size_t)g.m3 * (g.m3 + g.me) + (size_t)g.me * g.m3 +
+                                                (size_t)g.me * g.me);
+      oS += (long long)g.m3 * g.me;
+      oW += (long long)g.m3 * (g.m3 + g.me);
+      oQ += (long long)g.me * g.m3;
+      oP += g.m3;
+      oz += g.m3;
+      flops += (2LL * g.m3 * g.m3 * g.m3) / 3 + 2LL * g.m3 * g.m3 * g.me;
+      if (b != 0 || op->opt.root_dtn) flops += 2LL * g.me * g.me * g.m3;
+    }
+    if (!L.h.empty()) {
+      L.d = op->mem.upload(L.h, s);
+      L.ds = op->mem.upload(L.hs, s);
+      L.dg = op->mem.upload(L.hg, s);
+      L.dha = op->mem.upload(L.ha, s);
+      L.dhb = op->mem.upload(L.hb, s);
+      L.dhp = op->mem.upload(L.hp, s);
+      L.dzo = op->mem.upload(L.zo, s);
+    }
+  }
+  op->z_units = oz;
+  op->flops = flops;
+  op->rootT = (t.boxes[0].ca >= 0) ? op->arena[0] : op->leafT;
+  HPS_HIP(hipStreamSynchronize(s));  // host vectors above must outlive their copies
+  return op;
+}
+
+// ---------------------------------------------------------------------------
+// Leaf stage (section 3): all leaves of equal (p, q, h) share launches.
+// ---------------------------------------------------------------------------
+struct LeafJob {
+  hps_op* op;
+  int leaf;
+};
+
+static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hipStream_t s,
+                           std::vector<std::vector<char>>& keep_alive, int* dstatus, int panel) {
+  hps_op* op0 = jobs[0].op;
+  const int p = op0->p, q = op0->q, n = (p - 2) * (p - 2), m = 4 * q, ld = n + m;
+  LeafDev tab{op0->dDx, op0->dDy, op0->dDxx, op0->dDyy, op0->dG, p, n, m, 0};
+  const size_t per = (size_t)n * ld * sizeof(double) + (size_t)n * sizeof(int);
+  const size_t budget = (size_t)2 << 30;
+  const int total = (int)jobs.size();
+  const int CH = (int)std::max<size_t>(1, std::min<size_t>(total, budget / per));
+  double* Wslab = tmp.alloc<double>((size_t)CH * n * ld);
+  int* pslab = tmp.alloc<int>((size_t)CH * n);
+  const double** dcp = tmp.alloc<const double*>(CH);
+  SolveDesc* dsd = tmp.alloc<SolveDesc>(CH);
+  GemmDesc* dgd = tmp.alloc<GemmDesc>(CH);
+  for (int c0 = 0; c0 < total; c0 += CH) {
+    const int cnt = std::min(CH, total - c0);
+    std::vector<const double*> cp(cnt);
+    std::vector<SolveDesc> sd(cnt);
+    std::vector<GemmDesc> gd(cnt);
+    for (int i = 0; i < cnt; ++i) {
+      const LeafJob& j = jobs[c0 + i];
+      cp[i] = j.op->coeffs + (size_t)j.leaf * 6 * p * p;
+      double* W = Wslab + (size_t)i * n * ld;
+      sd[i] = SolveDesc{W, pslab + (size_t)i * n, W + n, n, m, ld, ld, -(j.leaf + 1), 0};
+      gd[i] = GemmDesc{j.op->dP1, W + n, j.op->leafT + (size_t)j.leaf * m * m, j.op->dP0,
+                       m, m, n, n, ld, m, m, -1.0};
+    }
+    HPS_HIP(hipMemcpyAsync(dcp, cp.data(), cnt * sizeof(void*), hipMemcpyHostToDevice, s));
+    HPS_HIP(hipMemcpyAsync(dsd, sd.data(), cnt * sizeof(SolveDesc), hipMemcpyHostToDevice, s));
+    HPS_HIP(hipMemcpyAsync(dgd, gd.data(), cnt * sizeof(GemmDesc), hipMemcpyHostToDevice, s));
+    leaf_assemble(dcp, tab, cnt, Wslab, s);
+    batched_solve(dsd, sd, dstatus, s, panel);
+    grouped_gemm(dgd, gd, s, false);
+    HPS_HIP(hipStreamSynchronize(s));  // host descriptor vectors are reused next chunk
+  }
+  (void)keep_alive;
+}
+
+void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
+  DeviceMem tmp;
+  std::vector<std::vector<char>> keep_alive;
+  int* dstatus = tmp.alloc<int>(4);
+  HPS_HIP(hipMemsetAsync(dstatus, 0, 4 * sizeof(int), s));
+  for (hps_op* op : ops)
+    if (op->opt.device_ptrs)
+      nonfinite(op->coeffs, (size_t)op->nx * op->ny * 6 * op->p * op->p, dstatus + 2, s);
+
+  // Leaf groups keyed by (p, q, hx, hy).
+  std::map<std::tuple<int, int, double, double>, std::vector<LeafJob>> groups;
+  for (hps_op* op : ops) {
+    auto key = std::make_tuple(op->p, op->q, op->lt.hx, op->lt.hy);
+    auto& v = groups[key];
+    for (int l = 0; l < op->nx * op->ny; ++l) v.push_back(LeafJob{op, l});
+  }
+  const int panel = ops.empty() ? 32 : ops[0]->opt.panel;
+  for (auto& kv : groups) run_leaf_group(kv.second, tmp, s, keep_alive, dstatus, panel);
+
+  // Merges, deepest level first; all operators' merges at one depth together.
+  int maxd = 0;
+  for (hps_op* op : ops) maxd = std::max(maxd, (int)op->levels.size() - 1);
+  const bool split = !ops.empty() && ops[0]->mode == HPS_MIXED_SPLIT32;
+  for (int d = maxd; d >= 0; --d) {
+    std::vector<MergeDesc> hm;
+    std::vector<SolveDesc> hs;
+    std::vector<GemmDesc> hg;
+    size_t gmax = 0;
+    const LevelPlan* only = nullptr;
+    int contributors = 0;
+    for (hps_op* op : ops) {
+      if (d >= (int)op->levels.size() || op->levels[d].h.empty()) continue;
+      const LevelPlan& L = op->levels[d];
+      hm.insert(hm.end(), L.h.begin(), L.h.end());
+      hs.insert(hs.end(), L.hs.begin(), L.hs.end());
+      hg.insert(hg.end(), L.hg.begin(), L.hg.end());
+      gmax = std::max(gmax, L.gather_max);
+      only = &L;
+      ++contributors;
+    }
+    if (hm.empty()) continue;
+    const MergeDesc* dm;
+    const SolveDesc* dsd;
+    const GemmDesc* dgd;
+    if (contributors == 1) {
+      dm = only->d;
+      dsd = only->ds;
+      dgd = only->dg;
+    } else {
+      MergeDesc* a = tmp.upload(hm, s);
+      SolveDesc* b = tmp.upload(hs, s);
+      GemmDesc* c = tmp.upload(hg, s);
+      HPS_HIP(hipStreamSynchronize(s));
+      dm = a;
+      dsd = b;
+      dgd = c;
+    }
+    merge_gather(dm, (int)hm.size(), gmax, s);
+    batched_solve(dsd, hs, dstatus, s, panel);
+    grouped_gemm(dgd, hg, s, split);
+  }
+  int st[4];
+  HPS_HIP(hipMemcpyAsync(st, dstatus, sizeof(st), hipMemcpyDeviceToHost, s));
+  HPS_HIP(hipStreamSynchronize(s));
+  if (st[2]) throw Error(HPS_EINVAL, "non-finite coefficient");
+  if (st[0]) {
+    std::string where = st[1] < 0 ? "leaf " + std::to_string(-st[1] - 1)
+                                  : "merge of box " + std::to_string(st[1]);
+    throw Error(HPS_ESINGULAR, "zero or non-finite pivot in " + where);
+  }
+}
+
+void leaf_dtn_batch(const double* coeffs, int nleaf, double hx, double hy, int p, int q, double* T,
+                    hipStream_t s) {
+  HPS_REQUIRE(p >= 4 && p <= 24 && q >= 1 && q <= p && nleaf >= 1, "bad leaf batch arguments");
+  init_runtime();
+  hps_op op;
+  op.p = p;
+  op.q = q;
+  op.lt = make_leaf_tables(p, q, hx, hy);
+  op.coeffs = coeffs;
+  op.leafT = T;
+  op.dDx = op.mem.upload(op.lt.Dx, s);
+  op.dDy = op.mem.upload(op.lt.Dy, s);
+  op.dDxx = op.mem.upload(op.lt.Dxx, s);
+  op.dDyy = op.mem.upload(op.lt.Dyy, s);
+  op.dG = op.mem.upload(op.lt.G, s);
+  op.dP0 = op.mem.upload(op.lt.P0, s);
+  op.dP1 = op.mem.upload(op.lt.P1, s);
+  std::vector<LeafJob> jobs(nleaf);
+  for (int i = 0; i < nleaf; ++i) jobs[i] = LeafJob{&op, i};
+  DeviceMem tmp;
+  std::vector<std::vector<char>> ka;
+  int* dstatus = tmp.alloc<int>(4);
+  HPS_HIP(hipMemsetAsync(dstatus, 0, 4 * sizeof(int), s));
+  run_leaf_group(jobs, tmp, s, ka, dstatus, 32);
+  int st[4];
+  HPS_HIP(hipMemcpyAsync(st, dstatus, sizeof(st), hipMemcpyDeviceToHost, s));
+  HPS_HIP(hipStreamSynchronize(s));
+  if (st[0]) throw Error(HPS_ESINGULAR, "zero pivot in leaf " + std::to_string(-st[1] - 1));
+}
+
+// ---------------------------------------------------------------------------
+// Solve (Algorithm 2) and the refinement pieces.
+// ---------------------------------------------------------------------------
+static void downward_all(hps_op* op, double* u, int nrhs, const double* z, hipStream_t s) {
+  const int N = op->tree.N;
+  for (size_t d = 0; d < op->levels.size(); ++d) {
+    const LevelPlan& L = op->levels[d];
+    if (L.h.empty()) continue;
+    downward(L.d, (int)L.h.size(), L.m3_max, L.me_max, u, N, nrhs, z, z ? L.dzo : nullptr, s);
+  }
+}
+
+void solve_device(hps_op* op, const double* f, int nrhs, double* u, hipStream_t s) {
+  set_boundary(f, op->gamma, op->n_bdry, u, op->tree.N, nrhs, s);
+  downward_all(op, u, nrhs, nullptr, s);
+}
+
+void solve_batch_device(const std::vector<hps_op*>& ops, const std::vector<const double*>& f,
+                        const std::vector<int>& nrhs, const std::vector<double*>& u,
+                        hipStream_t s) {
+  for (size_t i = 0; i < ops.size(); ++i) solve_device(ops[i], f[i], nrhs[i], u[i], s);
+}
+
+double absmax_device(const double* x, size_t n, hipStream_t s) {
+  const int blocks = 256;
+  double* part = nullptr;
+  HPS_HIP(hipMallocAsync((void**)&part, blocks * sizeof(double), s));
+  absmax_partial(x, n, part, blocks, s);
+  double h[blocks];
+  HPS_HIP(hipMemcpyAsync(h, part, sizeof(h), hipMemcpyDeviceToHost, s));
+  HPS_HIP(hipFreeAsync(part, s));
+  HPS_HIP(hipStreamSynchronize(s));
+  double m = 0.0;
+  for (int i = 0; i < blocks; ++i) m = std::max(m, h[i]);
+  return m;
+}
+
+void residual_device(const hps_op* op, const double* u, int nrhs, double* r, hipStream_t s) {
+  HPS_REQUIRE(op->opt.keep_leaf, "operator was built without keep_leaf_ops");
+  const int nl = op->nx * op->ny, m = 4 * op->q;
+  double* v = nullptr;
+  HPS_HIP(hipMallocAsync((void**)&v, (size_t)nrhs * nl * m * sizeof(double), s));
+  interface_residual(op->leafT, u, op->tree.N, nrhs, op->nx, op->ny, op->q, v, r, s);
+  HPS_HIP(hipFreeAsync(v, s));
+}
+
+// Upward pass for sources src ([nrhs][N]): fills z ([nrhs] per merge).
+static void upward_all(hps_op* op, const double* src, int nrhs, double* h, double* z,
+                       hipStream_t s) {
+  HPS_REQUIRE(op->opt.keep_factors, "operator was built without keep_factors");
+  HPS_HIP(hipMemsetAsync(h, 0, (size_t)op->h_units * nrhs * sizeof(double), s));
+  for (int d = (int)op->levels.size() - 1; d >= 0; --d) {
+    const LevelPlan& L = op->levels[d];
+    if (L.h.empty()) continue;
+    upward_level(L.d, (int)L.h.size(), L.m3_max, src, op->tree.N, op->opt.panel, h, L.dha, L.dhb,
+                 h, L.dhp, z, L.dzo, nrhs, s);
+  }
+}
+
+void solve_with_sources_device(hps_op* op, const double* f, const double* src, int nrhs, double* u,
+                               hipStream_t s) {
+  double *h = nullptr, *z = nullptr;
+  HPS_HIP(hipMallocAsync((void**)&h, (size_t)op->h_units * nrhs * sizeof(double), s));
+  HPS_HIP(hipMallocAsync((void**)&z, (size_t)std::max<long long>(1, op->z_units) * nrhs *
+                                         sizeof(double), s));
+  upward_all(op, src, nrhs, h, z, s);
+  set_boundary(f, op->gamma, op->n_bdry, u, op->tree.N, nrhs, s);
+  downward_all(op, u, nrhs, z, s);
+  HPS_HIP(hipFreeAsync(h, s));
+  HPS_HIP(hipFreeAsync(z, s));
+}
+
+void refine_device(hps_op* op, const double* f, int nrhs, double* u, double tol, int max_iter,
+                   hipStream_t s, hps_solve_info* info) {
+  HPS_REQUIRE(op->opt.keep_factors && op->opt.keep_leaf,
+              "refinement needs keep_leaf_ops and keep_factors");
+  const int N = op->tree.N;
+  const size_t nu = (size_t)N * nrhs;
+  double *r = nullptr, *du = nullptr, *h = nullptr, *z = nullptr, *zero = nullptr;
+  HPS_HIP(hipMallocAsync((void**)&r, nu * sizeof(double), s));
+  HPS_HIP(hipMallocAsync((void**)&du, nu * sizeof(double), s));
+  HPS_HIP(hipMallocAsync((void**)&h, (size_t)op->h_units * nrhs * sizeof(double), s));
+  HPS_HIP(hipMallocAsync((void**)&z, (size_t)std::max<long long>(1, op->z_units) * nrhs *
+                                         sizeof(double), s));
+  HPS_HIP(hipMallocAsync((void**)&zero, (size_t)op->n_bdry * nrhs * sizeof(double), s));
+  HPS_HIP(hipMemsetAsync(zero, 0, (size_t)op->n_bdry * nrhs * sizeof(double), s));
+  (void)f;
+  int it = 0;
+  double last = 0.0, first = -1.0;
+  bool conv = false;
+  const double umax = std::max(absmax_device(u, nu, s), 1e-300);
+  while (it < max_iter) {
+    residual_device(op, u, nrhs, r, s);
+    // Correction with jump(delta) = -r: by linearity delta = -(solution for sources r).
+    upward_all(op, r, nrhs, h, z, s);
+    set_boundary(zero, op->gamma, op->n_bdry, du, N, nrhs, s);
+    downward_all(op, du, nrhs, z, s);
+    axpy(u, du, -1.0, nu, s);
+    ++it;
+    last = absmax_device(du, nu, s) / umax;
+    if (first < 0) first = last;
+    if (last <= tol) {
+      conv = true;
+      break;
+    }
+  }
+  HPS_HIP(hipFreeAsync(r, s));
+  HPS_HIP(hipFreeAsync(du, s));
+  HPS_HIP(hipFreeAsync(h, s));
+  HPS_HIP(hipFreeAsync(z, s));
+  HPS_HIP(hipFreeAsync(zero, s));
+  HPS_HIP(hipStreamSynchronize(s));
+  if (info) {
+    info->iters = it;
+    info->last_update_rel = last;
+    info->first_update_rel = first < 0 ? 0.0 : first;
+  }
+  if (!conv)
+    throw Error(HPS_ENOTCONV, "refinement did not reach tolerance in " + std::to_string(max_iter) +
+                                  " sweeps (last relative update " + std::to_string(last) + ")");
+}
+
+void root_apply_device(const hps_op* op, const double* f, int nrhs, double* v, hipStream_t s) {
+  HPS_REQUIRE(op->opt.root_dtn, "operator was built without the root DtN");
+  matvec(op->rootT, op->n_bdry, op->n_bdry, f, nrhs, v, s);
+}
+
+}  // namespace hps

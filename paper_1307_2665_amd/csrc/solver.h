@@ -1,0 +1,112 @@
+// Operator object and the build/solve drivers behind the C ABI.
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "common.h"
+#include "plan.h"
+
+namespace hps {
+
+// Owner of device allocations; frees them on destruction.
+struct DeviceMem {
+  std::vector<void*> ptrs;
+  DeviceMem() = default;
+  DeviceMem(const DeviceMem&) = delete;
+  DeviceMem& operator=(const DeviceMem&) = delete;
+  ~DeviceMem();
+  void* raw(size_t bytes);
+  template <class T>
+  T* alloc(size_t n) {
+    return (T*)raw(std::max<size_t>(n, 1) * sizeof(T));
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v, hipStream_t s) {
+    T* d = alloc<T>(v.size());
+    if (!v.empty()) HPS_HIP(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return d;
+  }
+  size_t bytes = 0;
+};
+
+// Merges of one tree depth of one operator (or of a batch when concatenated).
+struct LevelPlan {
+  std::vector<MergeDesc> h;
+  std::vector<SolveDesc> hs;
+  std::vector<GemmDesc> hg;                 // Schur products T^tau += Q S
+  std::vector<long long> ha, hb, hp, zo;    // unit offsets for the upward pass
+  MergeDesc* d = nullptr;
+  SolveDesc* ds = nullptr;
+  GemmDesc* dg = nullptr;
+  long long *dha = nullptr, *dhb = nullptr, *dhp = nullptr, *dzo = nullptr;
+  int m3_max = 0, me_max = 0;
+  size_t gather_max = 0;
+};
+
+struct BuildOptions {
+  int mode = HPS_FP64;
+  hipStream_t stream = nullptr;
+  bool device_ptrs = false;
+  bool keep_leaf = true;
+  bool keep_factors = false;
+  bool root_dtn = true;
+  int panel = 32;
+};
+
+}  // namespace hps
+
+struct hps_op {
+  int nx = 0, ny = 0, p = 0, q = 0, mode = HPS_FP64;
+  double box[4] = {0, 0, 0, 0};
+  hps::Tree tree;
+  hps::LeafTables lt;
+  hps::DeviceMem mem;
+  hps::BuildOptions opt;
+  const double* coeffs = nullptr;   // device coefficients used by the build
+  double* leafT = nullptr;          // [nleaf][4q][4q]
+  double* S = nullptr;
+  double* Wk = nullptr;             // augmented systems (kept factors) or level scratch
+  double* Q = nullptr;
+  int* piv = nullptr;
+  int* gamma = nullptr;             // boundary ids in S,E,N,W order
+  double* arena[2] = {nullptr, nullptr};
+  double* rootT = nullptr;
+  int n_bdry = 0;
+  std::vector<hps::LevelPlan> levels;       // indexed by depth
+  std::vector<int> merge_level, merge_index;  // per box: level and index of its merge, or -1
+  std::vector<long long> box_hoff;          // unit offset of each box's particular flux
+  long long h_units = 0, z_units = 0;       // totals (per right-hand side)
+  long long bytes_S = 0, flops = 0;
+  int n_fallback = 0;
+  // device tables of the leaf stage
+  double *dDx = nullptr, *dDy = nullptr, *dDxx = nullptr, *dDyy = nullptr, *dG = nullptr,
+         *dP0 = nullptr, *dP1 = nullptr;
+};
+
+namespace hps {
+
+// Validates, plans and allocates one operator (no kernel launches except uploads).
+std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4], const int nleaf[2],
+                                      int p, int q, const BuildOptions& o);
+// Runs the build of a batch of planned operators: leaf stage grouped by leaf
+// shape, merges grouped by depth.
+void run_build(const std::vector<hps_op*>& ops, hipStream_t s);
+// Leaf DtNs of nleaf equal leaves (device in, device out).
+void leaf_dtn_batch(const double* coeffs, int nleaf, double hx, double hy, int p, int q, double* T,
+                    hipStream_t s);
+// Algorithm 2 (+ optional interface terms).  u, f device pointers.
+void solve_device(hps_op* op, const double* f, int nrhs, double* u, hipStream_t s);
+void solve_batch_device(const std::vector<hps_op*>& ops, const std::vector<const double*>& f,
+                        const std::vector<int>& nrhs, const std::vector<double*>& u,
+                        hipStream_t s);
+// Refinement sweeps; returns the number of sweeps and the update sizes.
+void refine_device(hps_op* op, const double* f, int nrhs, double* u, double tol, int max_iter,
+                   hipStream_t s, hps_solve_info* info);
+void residual_device(const hps_op* op, const double* u, int nrhs, double* r, hipStream_t s);
+void solve_with_sources_device(hps_op* op, const double* f, const double* src, int nrhs, double* u,
+                               hipStream_t s);
+void root_apply_device(const hps_op* op, const double* f, int nrhs, double* v, hipStream_t s);
+double absmax_device(const double* x, size_t n, hipStream_t s);
+
+}  // namespace hps

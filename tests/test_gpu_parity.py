@@ -1,0 +1,260 @@
+"""GPU parity of the HIP path against the CPU oracle (FP64 path: 1e-10).
+
+Every comparison is element by element on the same seeded inputs; errors are
+max-abs differences relative to the max-abs entry of the oracle's result
+(per matrix for operators, per right-hand side for solutions).
+"""
+import numpy as np
+import pytest
+
+import hps_inputs as hi
+from oracle import brute, hps
+
+from .helpers import library_inputs, oracle_problem, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def H(gpu):
+    import paper_1307_2665_amd as H
+    return H
+
+
+def _t(x, dev):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+
+# ---------------------------------------------------------------------------
+# Batched dense layer.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("Mr,Nc,K,nb", [(64, 64, 16, 1), (70, 130, 37, 3), (5, 3, 200, 2),
+                                        (257, 65, 64, 1)])
+def test_gemm_f64(H, gpu, Mr, Nc, K, nb):
+    say(f"gemm_f64 {Mr}x{Nc}x{K} batch {nb}")
+    rng = np.random.default_rng(Mr * 7 + Nc)
+    A, B, C0 = rng.standard_normal((nb, Mr, K)), rng.standard_normal((nb, K, Nc)), rng.standard_normal((nb, Mr, Nc))
+    C = _t(C0, gpu)
+    H.batched_gemm(_t(A, gpu), _t(B, gpu), C, alpha=-0.5)
+    ref = C0 - 0.5 * A @ B
+    assert rel_err(C.cpu().numpy(), ref) < 1e-14
+
+
+def test_gemm_split32_accuracy(H, gpu):
+    say("gemm_split32 300x200x448")
+    rng = np.random.default_rng(5)
+    A, B = rng.standard_normal((1, 300, 448)), rng.standard_normal((1, 448, 200))
+    C = _t(np.zeros((1, 300, 200)), gpu)
+    H.batched_gemm(_t(A, gpu), _t(B, gpu), C, split32=True)
+    ref = A @ B
+    err = rel_err(C.cpu().numpy(), ref)
+    # hi/lo splitting removes the input rounding; the FP32 accumulation of each
+    # 16-deep slab leaves an error of a few units of 2^-24 (~6e-8).
+    assert err < 5e-7
+
+
+@pytest.mark.parametrize("n,m,nb", [(5, 3, 2), (33, 40, 3), (70, 17, 2), (130, 9, 1), (196, 56, 2)])
+def test_batched_solve_with_pivoting(H, gpu, n, m, nb):
+    say(f"batched_solve n={n} m={m} batch {nb}")
+    rng = np.random.default_rng(n + m)
+    M = rng.standard_normal((nb, n, n))
+    M[:, np.arange(n), np.arange(n)] = 0.0          # forces row interchanges
+    B = rng.standard_normal((nb, n, m))
+    X = H.batched_solve(_t(M, gpu), _t(B, gpu)).cpu().numpy()
+    ref = np.linalg.solve(M, B)
+    assert rel_err(X, ref) < 1e-10
+
+
+def test_batched_solve_reports_singular(H, gpu):
+    say("batched_solve singular")
+    M = np.zeros((2, 8, 8))
+    M[0] = np.eye(8)
+    B = np.ones((2, 8, 3))
+    with pytest.raises(H.HpsError) as e:
+        H.batched_solve(_t(M, gpu), _t(B, gpu))
+    assert e.value.status == H.HPS_ESINGULAR
+
+
+# ---------------------------------------------------------------------------
+# Leaf stage (section 3).
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("p,q", [(16, 14), (12, 10), (20, 18), (21, 21), (6, 4)])
+def test_leaf_dtn_parity(H, gpu, p, q):
+    say(f"leaf_dtn p={p} q={q}")
+    rng = np.random.default_rng(p * 31 + q)
+    nl = 7
+    hx, hy = 1.0 / 64, 1.0 / 32
+    C = np.zeros((nl, 6, p * p))
+    C[:, 0] = 1.0 + 0.4 * rng.random((nl, p * p))
+    C[:, 1] = 0.2 * rng.standard_normal((nl, p * p))
+    C[:, 2] = 1.0 + 0.4 * rng.random((nl, p * p))
+    C[:, 3] = 10.0 * rng.standard_normal((nl, p * p))
+    C[:, 4] = 10.0 * rng.standard_normal((nl, p * p))
+    C[:, 5] = -40.0 * rng.random((nl, p * p))
+    T = H.leaf_dtn(_t(C, gpu), hx, hy, p, q).cpu().numpy()
+    mats = hps.leaf_matrices(p, q, hx, hy)
+    for i in range(nl):
+        ref = hps.leaf_dtn(C[i], p, q, hx, hy, mats).T
+        assert rel_err(T[i], ref) < TOL, (i, rel_err(T[i], ref))
+
+
+# ---------------------------------------------------------------------------
+# Build and solve (Algorithms 1, 2).
+# ---------------------------------------------------------------------------
+
+def _compare_operator(H, op_g, op_o, check_S=True):
+    if check_S:
+        for t, mo in op_o.merges.items():
+            S = op_g.export_S(t)
+            assert S.shape == mo.S.shape
+            e = rel_err(S, mo.S)
+            assert e < TOL, (t, e)
+    e = rel_err(op_g.export_root_dtn(), op_o.rootT)
+    assert e < TOL, ("root T", e)
+
+
+def test_config1_laplace(H, gpu):
+    """4x4 leaves, p=16, q=14, u = log|x - (1.5, 1.5)|."""
+    say("config1 build")
+    pr = hi.laplace_log()
+    op_o, C_o, f_o, grid = oracle_problem(pr)
+    C, f = library_inputs(pr)
+    op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q)
+    _compare_operator(H, op, op_o)
+    for lf in range(16):
+        t = hps.find_leaf(op_o, lf % 4, lf // 4)
+        assert rel_err(op.export_leaf_dtn(lf), op_o.leafT[t]) < TOL
+    say("config1 solve")
+    u = op.solve(_t(f, gpu)).cpu().numpy()
+    u_o = hps.solve(op_o, f_o)
+    assert rel_err(u, u_o) < TOL
+    ex = pr.exact(*grid.node_xy().T)
+    assert np.max(np.abs(u[0] - ex)) < 1e-11
+    # host-pointer path gives the same numbers
+    u2 = op.solve(f)
+    assert np.max(np.abs(u2 - u)) == 0.0
+
+
+@pytest.mark.parametrize("nleaf", [(3, 5), (7, 2), (1, 1), (2, 1)])
+def test_rectangles_and_uneven_trees(H, gpu, nleaf):
+    say(f"manufactured build nleaf={nleaf}")
+    pr = hi.manufactured_variable(nleaf=nleaf, p=10, q=8)
+    pr.box = (0.0, 1.5, -0.5, 0.5)
+    op_o, C_o, f_o, grid = oracle_problem(pr)
+    C, f = library_inputs(pr)
+    op = H.build_solution_operator(_t(C, gpu), pr.box, nleaf, pr.p, pr.q)
+    _compare_operator(H, op, op_o)
+    u = op.solve(_t(f, gpu)).cpu().numpy()
+    assert rel_err(u, hps.solve(op_o, f_o)) < TOL
+    assert np.max(np.abs(u[0] - pr.exact(*grid.node_xy().T))) < 1e-10
+
+
+def test_convdiff_16x16_multi_rhs(H, gpu):
+    say("convdiff 16x16 p16 q14, 3 rhs")
+    pr = hi.convdiff(nleaf=(16, 16), p=16, q=14, nrhs=3)
+    op_o, C_o, f_o, grid = oracle_problem(pr)
+    C, f = library_inputs(pr)
+    op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q)
+    _compare_operator(H, op, op_o)
+    u = op.solve(_t(f, gpu)).cpu().numpy()
+    u_o = hps.solve(op_o, f_o)
+    for k in range(3):
+        assert rel_err(u[k], u_o[k]) < TOL
+    v = op.root_dtn_apply(_t(f, gpu)).cpu().numpy()
+    assert rel_err(v, f_o @ op_o.rootT.T) < TOL
+
+
+def test_helmholtz_bump_small(H, gpu):
+    say("helmholtz bump 16x16")
+    pr = hi.helmholtz_bump(nleaf=(16, 16), nrhs=2)
+    op_o, C_o, f_o, grid = oracle_problem(pr)
+    C, f = library_inputs(pr)
+    op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q)
+    _compare_operator(H, op, op_o, check_S=False)
+    u = op.solve(_t(f, gpu)).cpu().numpy()
+    u_o = hps.solve(op_o, f_o)
+    for k in range(2):
+        assert rel_err(u[k], u_o[k]) < TOL
+
+
+def test_interface_residual_and_sources(H, gpu):
+    say("residual + sources 5x4")
+    pr = hi.convdiff(nleaf=(5, 4), p=10, q=8)
+    op_o, C_o, f_o, grid = oracle_problem(pr)
+    C, f = library_inputs(pr)
+    op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q, keep_factors=True)
+    rng = np.random.default_rng(1)
+    u = rng.standard_normal((2, op.N))
+    r = op.interface_residual(_t(u, gpu)).cpu().numpy()
+    r_o = hps.interface_residual(op_o, u)
+    assert rel_err(r, r_o) < TOL
+    s = rng.standard_normal((2, op.N))
+    s[:, op_o.boxes[0].Ie] = 0.0
+    ug = op.solve_with_sources(_t(f_o[:1].repeat(2, 0), gpu), _t(s, gpu)).cpu().numpy()
+    z = hps.upward(op_o, s)
+    uo = hps.solve(op_o, f_o[:1].repeat(2, 0), z=z)
+    assert rel_err(ug, uo) < TOL
+
+
+def test_invalid_inputs(H, gpu):
+    say("invalid inputs")
+    p, q = 8, 6
+    C = np.zeros((4, 6, p * p))
+    C[:, 0] = C[:, 2] = 1.0
+    C[2, 5, 10] = np.nan
+    with pytest.raises(H.HpsError) as e:
+        H.build_solution_operator(_t(C, gpu), (0, 1, 0, 1), (2, 2), p, q)
+    assert e.value.status == H.HPS_EINVAL
+    with pytest.raises(H.HpsError) as e:
+        H.build_solution_operator(_t(np.zeros((4, 6, p * p)), gpu), (0, 1, 0, 1), (2, 2), p, q)
+    assert e.value.status == H.HPS_ESINGULAR
+    with pytest.raises(H.HpsError) as e:
+        H.build_solution_operator(_t(C, gpu), (0, 1, 0, 1), (2, 2), p, p + 1)
+    assert e.value.status == H.HPS_EINVAL
+
+
+def test_config2_full_size_sampled(H, gpu):
+    """64x64, p=16, q=14 (the benchmark workload): sampled leaf DtNs against the
+    oracle, and the oracle's flux-matching equations at every edge of sampled
+    leaves evaluated on the GPU solution."""
+    say("config2 full size build")
+    pr = hi.convdiff()
+    C, f = library_inputs(pr)
+    op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q)
+    u = op.solve(_t(f, gpu)).cpu().numpy()[0]
+    grid = hps.Grid(pr.box, 64, 64, pr.q)
+    Co = pr.coeffs_at(grid.cheb_xy(pr.p))
+    mats = hps.leaf_matrices(pr.p, pr.q, grid.hx, grid.hy)
+    rng = np.random.default_rng(2)
+    sample = rng.choice(64 * 64, size=24, replace=False)
+    say("config2 sampled leaves")
+    Tcache = {}
+
+    def leafT(i, j):
+        k = i + 64 * j
+        if k not in Tcache:
+            Tcache[k] = hps.leaf_dtn(Co[k], pr.p, pr.q, grid.hx, grid.hy, mats).T
+        return Tcache[k]
+
+    q = pr.q
+    for k in sample:
+        i, j = int(k % 64), int(k // 64)
+        Tg = op.export_leaf_dtn(int(k))
+        assert rel_err(Tg, leafT(i, j)) < TOL
+        # flux matching across this leaf's east and north edges (oracle T's, GPU u)
+        vk = leafT(i, j) @ u[grid.boundary(i, i + 1, j, j + 1)]
+        scale = np.max(np.abs(leafT(i, j))) * np.max(np.abs(u))
+        if i + 1 < 64:
+            ve = leafT(i + 1, j) @ u[grid.boundary(i + 1, i + 2, j, j + 1)]
+            assert np.max(np.abs(vk[q:2 * q] - ve[3 * q:])) < 1e-10 * scale
+        if j + 1 < 64:
+            vn = leafT(i, j + 1) @ u[grid.boundary(i, i + 1, j + 1, j + 2)]
+            assert np.max(np.abs(vk[2 * q:3 * q] - vn[:q])) < 1e-10 * scale
+    # boundary data is reproduced exactly
+    ids = H.boundary_ids((64, 64), q)
+    assert np.max(np.abs(u[ids] - f[0])) == 0.0
