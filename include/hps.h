@@ -245,6 +245,29 @@ hps_status hps_leaf_tables(int p, int q, double hx, double hy, double* Dx, doubl
 hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int sizes[4], int* pmap,
                         int* a3, int* b3, int* Ie, int* Ii, int* n_boxes);
 
+/* ---- tuning knobs -------------------------------------------------------- */
+
+/* Sets a kernel-selection knob for later launches in this process:
+   "leaf_variant": register layout of the fused leaf solve (-1 automatic,
+   0: 16x16 threads, 1: 16x64 threads, 2: 16x32 threads). */
+hps_status hps_tune_set(const char* knob, int value);
+
+/* ---- launch timing (HIP events on the launch stream) --------------------- */
+
+/* Kernel classes: 0 leaf assembly, 1 LU panel, 2 row swaps + block-row solve,
+   3 LU trailing update, 4 back substitution, 5 FP64 GEMM (Schur products and
+   leaf T = P0 - P1 Z), 6 split-FP32 Schur GEMM, 7 merge gather, 8 downward
+   pass, 9 interface residual, 10 upward pass.  Bit c of mask enables class c;
+   every later launch of an enabled class records a start and stop event on
+   its stream together with its algorithmic FLOPs and bytes.  Costs one event
+   pair per launch while enabled. */
+hps_status hps_prof_enable(unsigned mask);
+/* Drops all records (waits for their events first). */
+hps_status hps_prof_reset(void);
+/* Totals over the recorded launches of a class: summed event time in ms,
+   number of launches, algorithmic FLOPs and bytes.  Waits for the events. */
+hps_status hps_prof_query(int cls, double* ms, long long* launches, double* flops, double* bytes);
+
 /* ---- lifetime, errors --------------------------------------------------- */
 
 void hps_destroy(hps_op* op);

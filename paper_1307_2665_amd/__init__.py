@@ -159,6 +159,35 @@ def batched_gemm(A, B, C, alpha: float = 1.0, split32: bool = False):
     return C
 
 
+def tune_set(knob: str, value: int) -> None:
+    check(lib.hps_tune_set(knob.encode(), int(value)))
+
+
+# ---- launch timing -----------------------------------------------------------------
+
+PROF_CLASSES = {"leaf_assemble": 0, "lu_panel": 1, "swap_trsm": 2, "lu_update": 3,
+                "back_subst": 4, "gemm": 5, "gemm_split32": 6, "merge_gather": 7,
+                "downward": 8, "residual": 9, "upward": 10, "leaf_lu": 11}
+
+
+def prof_enable(classes) -> None:
+    mask = 0
+    for c in classes:
+        mask |= 1 << (PROF_CLASSES[c] if isinstance(c, str) else int(c))
+    check(lib.hps_prof_enable(mask))
+
+
+def prof_reset() -> None:
+    check(lib.hps_prof_reset())
+
+
+def prof_query(cls) -> dict:
+    ms, n, fl, by = C.c_double(), C.c_longlong(), C.c_double(), C.c_double()
+    c = PROF_CLASSES[cls] if isinstance(cls, str) else int(cls)
+    check(lib.hps_prof_query(c, C.byref(ms), C.byref(n), C.byref(fl), C.byref(by)))
+    return dict(ms=ms.value, launches=n.value, flops=fl.value, bytes=by.value)
+
+
 # ---- operator --------------------------------------------------------------------
 
 class Operator:

@@ -80,6 +80,11 @@ SIGNATURES = {
     "hps_batched_solve": [P, P, I, I, I, P, P],
     "hps_batched_gemm": [P, P, P, I, I, I, I, D, I, P],
     "hps_plan_box": [P, I, I, P, P, P, P, P, P, P, IP],
+    "hps_tune_set": [C.c_char_p, I],
+    "hps_prof_enable": [C.c_uint],
+    "hps_prof_reset": [],
+    "hps_prof_query": [I, C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.POINTER(C.c_double),
+                       C.POINTER(C.c_double)],
 }
 VOID_FUNCS = {"hps_destroy": [P]}
 STR_FUNCS = {"hps_last_error": [], "hps_version": []}

@@ -17,13 +17,15 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhps.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["plan.cpp", "solver.cpp", "api.cpp", "dense.hip", "ops.hip"]
+SOURCES = ["plan.cpp", "solver.cpp", "api.cpp", "prof.cpp", "dense.hip", "ops.hip", "leaf.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ARCH = os.environ.get("HPS_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           # no packed FP32 instructions in device code
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # register-resident kernels rely on full unrolling of their slot loops
+          "-mllvm", "-pragma-unroll-threshold=1000000",
           "-I", os.path.join(HERE, "..", "include")]
 
 

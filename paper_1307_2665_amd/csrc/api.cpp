@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "dense.h"
+#include "leaf.h"
 #include "solver.h"
 
 namespace {
@@ -306,7 +307,8 @@ hps_status hps_export_S(const hps_op* op, int box, double* S, int* rows, int* co
     if (rows) *rows = d.m3;
     if (cols) *cols = d.me;
     if (S)
-      HPS_HIP(hipMemcpy(S, d.S, (size_t)d.m3 * d.me * sizeof(double), hipMemcpyDeviceToHost));
+      HPS_HIP(hipMemcpy2D(S, d.me * sizeof(double), d.S, d.ldw * sizeof(double),
+                          d.me * sizeof(double), d.m3, hipMemcpyDeviceToHost));
   });
 }
 
@@ -332,6 +334,7 @@ hps_status hps_batched_solve(const double* M, const double* B, int n, int m, int
                              void* stream) {
   return guard([&] {
     HPS_REQUIRE(M && B && X && n >= 1 && m >= 1 && nprob >= 1, "bad arguments");
+    HPS_REQUIRE(n <= hps::max_solve_rows(), "n too large");
     hipStream_t s = (hipStream_t)stream;
     hps::dense_init();
     hps::DeviceMem tmp;
@@ -350,10 +353,14 @@ hps_status hps_batched_solve(const double* M, const double* B, int n, int m, int
     }
     std::vector<hps::SolveDesc> hd(nprob);
     for (int i = 0; i < nprob; ++i)
-      hd[i] = hps::SolveDesc{W + (size_t)i * n * ld, piv + (size_t)i * n, X + (size_t)i * n * m,
-                             n, m, ld, m, i, 0};
+      hd[i] = hps::SolveDesc{W + (size_t)i * n * ld, piv + (size_t)i * n,
+                             W + (size_t)i * n * ld + n, n, m, ld, ld, i, 0};
     hps::SolveDesc* dd = tmp.upload(hd, s);
     hps::batched_solve(dd, hd, st, s, 32);
+    for (int i = 0; i < nprob; ++i)
+      HPS_HIP(hipMemcpy2DAsync(X + (size_t)i * n * m, m * sizeof(double),
+                               W + (size_t)i * n * ld + n, ld * sizeof(double), m * sizeof(double),
+                               n, hipMemcpyDeviceToDevice, s));
     int h[4];
     HPS_HIP(hipMemcpyAsync(h, st, sizeof(h), hipMemcpyDeviceToHost, s));
     HPS_HIP(hipStreamSynchronize(s));
@@ -375,6 +382,17 @@ hps_status hps_batched_gemm(const double* A, const double* B, double* C, int Mr,
     hps::GemmDesc* dd = tmp.upload(hd, s);
     hps::grouped_gemm(dd, hd, s, split32 != 0);
     HPS_HIP(hipStreamSynchronize(s));
+  });
+}
+
+hps_status hps_tune_set(const char* knob, int value) {
+  return guard([&] {
+    HPS_REQUIRE(knob != nullptr, "null knob");
+    std::string k(knob);
+    if (k == "leaf_variant")
+      hps::leaf_lu_set_variant(value);
+    else
+      throw hps::Error(HPS_EINVAL, "unknown knob " + k);
   });
 }
 

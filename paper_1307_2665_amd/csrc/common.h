@@ -68,17 +68,19 @@ struct MergeDesc {
   const double* Ta;   // alpha's DtN, na x na
   const double* Tb;   // beta's DtN, nb x nb
   double* Tp;         // parent DtN, me x me (me = m1 + m2)
-  double* W;          // augmented [M | B], m3 x (m3 + me), ld = m3 + me
-  double* S;          // solution operator, m3 x me
+  double* W;          // augmented [M | B (| I)], m3 x ldw; after the solve
+                      // [* | S (| M^-1)]
+  double* S;          // solution operator, m3 x me, leading dimension ldw (inside W)
   double* Q;          // [T13a; T23b] in parent order, me x m3
-  int* piv;           // m3 pivots (kept with W when factors are kept)
+  int* piv;           // m3 pivots
   const int* pmap;    // me entries: >= 0 position in alpha, < 0: -(position in beta) - 1
   const int* a3;      // m3 positions of the shared edge in alpha
   const int* b3;      // m3 positions of the shared edge in beta
   const int* Ie;      // me global ids (parent boundary, S,E,N,W)
   const int* Ii;      // m3 global ids (shared edge)
   int na, nb, me, m3;
-  int box, pad;
+  int box, ldw;       // ldw = m3 + me (+ m3 when M^-1 is kept)
+  int inv, pad;       // inv = 1: W carries the identity block, giving M^-1 at W + m3 + me
 };
 
 }  // namespace hps

@@ -7,10 +7,10 @@
 
 namespace hps {
 
-// Solves every system of the batch in place: LU with partial pivoting of M,
-// forward elimination of B during the factorization, then back substitution
-// into X.  Panel width nb (<= 32).  d_status[0] becomes 1 (and d_status[1]
-// the tag) if a pivot is exactly zero or not finite.
+// Solves every system of the batch in place by block Gauss-Jordan elimination
+// with partial pivoting: afterwards W[:, n:n+m] holds X = M^-1 B (X must be
+// W + n with ldx = ld).  d_status[0] becomes 1 (and d_status[1] the tag) if a
+// pivot is exactly zero or not finite.  n <= max_solve_rows().
 void batched_solve(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc, int* d_status,
                    hipStream_t stream, int nb);
 
@@ -19,5 +19,6 @@ void grouped_gemm(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, h
                   bool split32);
 
 void dense_init();
+int max_solve_rows();
 
 }  // namespace hps

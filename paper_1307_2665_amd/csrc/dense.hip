@@ -7,6 +7,7 @@
 // (section 4: S = (T33a - T33b)^-1 [-T31a | T32b]); the Schur products carry
 // eq:merge and the leaf's T = P0 - P1 Z.
 #include "dense.h"
+#include "prof.h"
 
 #include <algorithm>
 #include <vector>
@@ -51,125 +52,214 @@ __device__ inline void block_argmax(double v, int idx, double* sv, int* si, doub
 }
 
 // ---------------------------------------------------------------------------
-// Panel factorization: columns [k0, k0+kb) of rows [k0, n), partial pivoting.
-// One workgroup per problem.  The panel is staged in LDS when it fits.
-// Only panel columns are swapped here; ipiv records the pivot row per column.
+// Block Gauss-Jordan elimination of the augmented systems W = [M | B].
+//
+// For each panel of kb columns starting at k0:
+//   1. k_gj_panel: LU with partial pivoting of W[k0:n, k0:k0+kb] in registers
+//      (one workgroup per system, rows spread over the threads).  It writes
+//      L11\U11 into the pivot block rows and, for the rows below, the
+//      original panel values in their new (pivoted) order; ipiv records the
+//      pivot row chosen for each column.
+//   2. k_gj_swap_trsm: applies the interchanges to every later column and
+//      turns the pivot block rows into R = U11^-1 L11^-1 A12 (one thread per
+//      column).
+//   3. k_gj_update: every row outside the pivot block gets
+//      A[i, k0+kb:] -= A[i, k0:k0+kb] R (FP64 MFMA tiles), which eliminates
+//      the panel columns from the rows above and below alike.
+// After the last panel the right-hand-side columns hold X = M^-1 B in natural
+// row order, so no back substitution is needed; the extra cost over LU is
+// n^3/3 flops, small next to the n^2 m of the right-hand sides.
 // ---------------------------------------------------------------------------
-constexpr int PANEL_LDS = 8192;  // doubles (64 KB)
 
-__device__ void panel_factor(double* P, int st, int rows, int kb, int* ipiv_out, int k0,
-                             int tag, int* status) {
-  __shared__ double sv[16];
-  __shared__ int si[16];
-  for (int j = 0; j < kb; ++j) {
-    double best = -1.0;
-    int bidx = -1;
-    for (int r = j + (int)threadIdx.x; r < rows; r += blockDim.x) {
-      double v = fabs(P[(size_t)r * st + j]);
-      if (v > best || (v != v)) { best = (v != v) ? INFINITY : v; bidx = r; }
-    }
-    double bv;
-    int pr;
-    block_argmax(best, bidx, sv, si, bv, pr);
-    if (pr < 0) pr = j;
-    if (pr != j) {
-      for (int c = threadIdx.x; c < kb; c += blockDim.x) {
-        double a = P[(size_t)j * st + c];
-        P[(size_t)j * st + c] = P[(size_t)pr * st + c];
-        P[(size_t)pr * st + c] = a;
-      }
-    }
-    __syncthreads();
-    const double piv = P[(size_t)j * st + j];
-    if (threadIdx.x == 0) {
-      ipiv_out[j] = k0 + pr;
-      if (!(piv != 0.0) || piv != piv) {
-        if (atomicCAS(status, 0, 1) == 0) status[1] = tag;
-      }
-    }
-    const double inv = (piv != 0.0) ? 1.0 / piv : 0.0;
-    for (int r = j + 1 + (int)threadIdx.x; r < rows; r += blockDim.x) {
-      double l = P[(size_t)r * st + j] * inv;
-      P[(size_t)r * st + j] = l;
-      for (int c = j + 1; c < kb; ++c) P[(size_t)r * st + c] -= l * P[(size_t)j * st + c];
-    }
-    __syncthreads();
-  }
-}
-
-__global__ void __launch_bounds__(256) k_lu_panel(const SolveDesc* __restrict__ descs, int k0,
-                                                  int nb, int* status) {
-  __shared__ double sp[PANEL_LDS];
+template <int NT, int R, int KB>
+__global__ void __launch_bounds__(NT) k_gj_panel(const SolveDesc* __restrict__ descs, int k0,
+                                                 int* status) {
+  constexpr int NW = NT / 64;
+  __shared__ double sv[2][NW];
+  __shared__ int si[2][NW];
+  __shared__ double rb[2][2][KB];  // [parity][0: pivot row, 1: row j][column]
+  __shared__ int ro[2][2];
   const SolveDesc d = descs[blockIdx.x];
   if (k0 >= d.n) return;
-  const int kb = min(nb, d.n - k0);
-  const int rows = d.n - k0;
-  double* G = d.W + (size_t)k0 * d.ld + k0;
-  if (rows * kb <= PANEL_LDS) {
-    for (int e = threadIdx.x; e < rows * kb; e += blockDim.x) {
-      int r = e / kb, c = e % kb;
-      sp[e] = G[(size_t)r * d.ld + c];
+  const int kb = min(KB, d.n - k0), rows = d.n - k0;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  double* P = d.W + (size_t)k0 * d.ld + k0;
+  const size_t ld = d.ld;
+  double w[R][KB];
+  int org[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int r = tid + NT * q;
+    org[q] = r;
+#pragma unroll
+    for (int c = 0; c < KB; ++c) w[q][c] = (r < rows && c < kb) ? P[(size_t)r * ld + c] : 0.0;
+  }
+  // Constant trip count (the loop holds barriers, so it must unroll fully);
+  // columns past kb are skipped uniformly.
+#pragma unroll
+  for (int j = 0; j < KB; ++j) {
+    if (j >= kb) continue;
+    const int buf = j & 1;
+    double best = -1.0;
+    int bi = -1;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int r = tid + NT * q;
+      const double v = w[q][j];
+      const double av = (v != v) ? INFINITY : fabs(v);
+      if (r >= j && r < rows && av > best) {
+        best = av;
+        bi = r;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (argmax_better(best, bi, ob, oi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      sv[buf][wid] = best;
+      si[buf][wid] = bi;
     }
     __syncthreads();
-    panel_factor(sp, kb, rows, kb, d.piv + k0, k0, d.tag, status);
-    for (int e = threadIdx.x; e < rows * kb; e += blockDim.x) {
-      int r = e / kb, c = e % kb;
-      G[(size_t)r * d.ld + c] = sp[e];
+    best = sv[buf][0];
+    bi = si[buf][0];
+#pragma unroll
+    for (int v = 1; v < NW; ++v)
+      if (argmax_better(best, bi, sv[buf][v], si[buf][v])) {
+        best = sv[buf][v];
+        bi = si[buf][v];
+      }
+    const int pr = __builtin_amdgcn_readfirstlane(bi < 0 ? j : bi);
+    const int qp = pr / NT, tp = pr % NT;
+    if (tid == j) {
+#pragma unroll
+      for (int c = 0; c < KB; ++c) rb[buf][1][c] = w[0][c];
+      ro[buf][1] = org[0];
     }
-  } else {
-    panel_factor(G, d.ld, rows, kb, d.piv + k0, k0, d.tag, status);
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      if (q == qp) {
+        if (tid == tp) {
+#pragma unroll
+          for (int c = 0; c < KB; ++c) rb[buf][0][c] = w[q][c];
+          ro[buf][0] = org[q];
+        }
+      }
+    __syncthreads();
+    if (pr != j) {
+      if (tid == j) {
+#pragma unroll
+        for (int c = 0; c < KB; ++c) w[0][c] = rb[buf][0][c];
+        org[0] = ro[buf][0];
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q)
+        if (q == qp) {
+          if (tid == tp) {
+#pragma unroll
+            for (int c = 0; c < KB; ++c) w[q][c] = rb[buf][1][c];
+            org[q] = ro[buf][1];
+          }
+        }
+    }
+    const double piv = rb[buf][0][j];
+    if (tid == 0) {
+      d.piv[k0 + j] = k0 + pr;
+      if (!(piv != 0.0) || piv != piv)
+        if (atomicCAS(status, 0, 1) == 0) status[1] = d.tag;
+    }
+    const double inv = (piv != 0.0 && piv == piv) ? 1.0 / piv : 0.0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int r = tid + NT * q;
+      if (r > j && r < rows) {
+        const double l = w[q][j] * inv;
+        w[q][j] = l;
+#pragma unroll
+        for (int c = j + 1; c < KB; ++c) w[q][c] -= l * rb[buf][0][c];
+      }
+    }
+  }
+  // Rows below the pivot block get their original values (in pivoted order);
+  // read them all before anything is written back.
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int r = tid + NT * q;
+    if (r >= kb && r < rows) {
+      const int src = org[q];
+#pragma unroll
+      for (int c = 0; c < KB; ++c) w[q][c] = (c < kb) ? P[(size_t)src * ld + c] : 0.0;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int r = tid + NT * q;
+    if (r < rows) {
+#pragma unroll
+      for (int c = 0; c < KB; ++c)
+        if (c < kb) P[(size_t)r * ld + c] = w[q][c];
+    }
   }
 }
 
-// ---------------------------------------------------------------------------
-// Apply the panel's row interchanges to columns [k0+kb, n+m) and solve
-// L11 X = W[k0:k0+kb, cols] (unit lower) in place.  One thread per column.
-// ---------------------------------------------------------------------------
-constexpr int MAXNB = 32;
-
-__global__ void __launch_bounds__(256) k_swap_trsm(const SolveDesc* __restrict__ descs, int k0,
-                                                   int nb) {
-  __shared__ double L[MAXNB * MAXNB];
-  __shared__ int pv[MAXNB];
+template <int KB>
+__global__ void __launch_bounds__(256) k_gj_swap_trsm(const SolveDesc* __restrict__ descs, int k0) {
+  __shared__ double LU[KB][KB + 1];
+  __shared__ int pv[KB];
   const SolveDesc d = descs[blockIdx.y];
   if (k0 >= d.n) return;
-  const int kb = min(nb, d.n - k0);
+  const int kb = min(KB, d.n - k0);
   const int c0 = k0 + kb;
   const int ncol = d.n + d.m - c0;
   if ((int)(blockIdx.x * blockDim.x) >= ncol) return;
+  const size_t ld = d.ld;
   for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
     int r = e / kb, c = e % kb;
-    L[e] = d.W[(size_t)(k0 + r) * d.ld + k0 + c];
+    LU[r][c] = d.W[(size_t)(k0 + r) * ld + k0 + c];
   }
   for (int e = threadIdx.x; e < kb; e += blockDim.x) pv[e] = d.piv[k0 + e];
   __syncthreads();
   const int col = c0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= d.n + d.m) return;
   double* W = d.W;
-  const size_t ld = d.ld;
   for (int j = 0; j < kb; ++j) {
-    int r2 = pv[j];
+    const int r2 = pv[j];
     if (r2 != k0 + j) {
       double a = W[(size_t)(k0 + j) * ld + col];
       W[(size_t)(k0 + j) * ld + col] = W[(size_t)r2 * ld + col];
       W[(size_t)r2 * ld + col] = a;
     }
   }
-  double x[MAXNB];
+  double x[KB];
 #pragma unroll
-  for (int j = 0; j < MAXNB; ++j)
-    if (j < kb) x[j] = W[(size_t)(k0 + j) * ld + col];
+  for (int j = 0; j < KB; ++j) x[j] = (j < kb) ? W[(size_t)(k0 + j) * ld + col] : 0.0;
 #pragma unroll
-  for (int j = 0; j < MAXNB; ++j) {
+  for (int j = 1; j < KB; ++j) {
+    double s = x[j];
+#pragma unroll
+    for (int i = 0; i < j; ++i) s -= LU[j][i] * x[i];
+    x[j] = s;
+  }
+#pragma unroll
+  for (int j = KB - 1; j >= 0; --j) {
     if (j < kb) {
       double s = x[j];
 #pragma unroll
-      for (int i = 0; i < MAXNB; ++i)
-        if (i < j) s -= L[j * kb + i] * x[i];
-      x[j] = s;
-      W[(size_t)(k0 + j) * ld + col] = s;
+      for (int i = j + 1; i < KB; ++i)
+        if (i < kb) s -= LU[j][i] * x[i];
+      x[j] = s / LU[j][j];
     }
   }
+#pragma unroll
+  for (int j = 0; j < KB; ++j)
+    if (j < kb) W[(size_t)(k0 + j) * ld + col] = x[j];
 }
 
 // ---------------------------------------------------------------------------
@@ -240,21 +330,31 @@ __device__ inline void gemm_tile_f64(const double* __restrict__ A, int lda,
       }
 }
 
-// Trailing update of the blocked LU: W[k0+kb:n, k0+kb:n+m] -= L21 * U12.
-__global__ void __launch_bounds__(256) k_lu_update(const SolveDesc* __restrict__ descs, int k0,
+// Gauss-Jordan update: rows outside the pivot block [k0, k0+kb) get
+// A[i, k0+kb:] -= A[i, k0:k0+kb] R.  Row tiles 0 .. ta-1 cover rows [0, k0),
+// the rest cover rows [k0+kb, n).
+__global__ void __launch_bounds__(256) k_gj_update(const SolveDesc* __restrict__ descs, int k0,
                                                    int nb) {
   __shared__ double As[TBK][TBM + 1];
   __shared__ double Bs[TBK][TBN + 1];
   const SolveDesc d = descs[blockIdx.z];
   if (k0 >= d.n) return;
   const int kb = min(nb, d.n - k0);
-  const int r0 = k0 + kb;
-  const int M = d.n - r0, N = d.n + d.m - r0;
-  if ((int)blockIdx.y * TBM >= M || (int)blockIdx.x * TBN >= N) return;
+  const int ta = (k0 + TBM - 1) / TBM;
+  int r0, M;
+  if ((int)blockIdx.y < ta) {
+    r0 = blockIdx.y * TBM;
+    M = min(TBM, k0 - r0);
+  } else {
+    r0 = k0 + kb + (blockIdx.y - ta) * TBM;
+    M = min(TBM, d.n - r0);
+  }
+  const int c0 = k0 + kb + blockIdx.x * TBN;
+  const int N = min(TBN, d.n + d.m - c0);
+  if (M <= 0 || N <= 0) return;
   const size_t ld = d.ld;
-  gemm_tile_f64(d.W + (size_t)r0 * ld + k0, d.ld, d.W + (size_t)k0 * ld + r0, d.ld,
-                d.W + (size_t)r0 * ld + r0, d.ld, nullptr, 0, M, N, kb, -1.0, blockIdx.y,
-                blockIdx.x, As, Bs);
+  gemm_tile_f64(d.W + (size_t)r0 * ld + k0, d.ld, d.W + (size_t)k0 * ld + c0, d.ld,
+                d.W + (size_t)r0 * ld + c0, d.ld, nullptr, 0, M, N, kb, -1.0, 0, 0, As, Bs);
 }
 
 // Grouped GEMM: one launch over problems, grid (tiles_n, tiles_m, nprob).
@@ -368,102 +468,72 @@ __global__ void __launch_bounds__(256) k_gemm_split32(const GemmDesc* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// Back substitution X = U^-1 Y on a column block of the right-hand sides,
-// blocked by BS rows from the bottom; the Y block lives in LDS.
-// ---------------------------------------------------------------------------
-constexpr int BS = 32;
-constexpr int BSUB_LDS = 16384;  // doubles (128 KB)
-
-__global__ void __launch_bounds__(256) k_back_subst(const SolveDesc* __restrict__ descs, int cw) {
-  extern __shared__ double smem[];
-  const SolveDesc d = descs[blockIdx.y];
-  const int c0 = blockIdx.x * cw;
-  if (c0 >= d.m) return;
-  const int w = min(cw, d.m - c0);
-  const int n = d.n, ldy = cw + 1;
-  double* Y = smem;                      // n x ldy
-  double* Ud = smem + (size_t)n * ldy;   // BS x (BS+1)
-  const size_t ld = d.ld;
-  for (int e = threadIdx.x; e < n * w; e += blockDim.x) {
-    int r = e / w, c = e % w;
-    Y[r * ldy + c] = d.W[(size_t)r * ld + n + c0 + c];
-  }
-  __syncthreads();
-  const int nblk = (n + BS - 1) / BS;
-  for (int b = nblk - 1; b >= 0; --b) {
-    const int k = b * BS, kend = min(n, k + BS), kw = kend - k;
-    for (int e = threadIdx.x; e < kw * kw; e += blockDim.x) {
-      int r = e / kw, c = e % kw;
-      Ud[r * (BS + 1) + c] = d.W[(size_t)(k + r) * ld + k + c];
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < w) {
-      const int c = threadIdx.x;
-      for (int r = kw - 1; r >= 0; --r) {
-        double s = Y[(k + r) * ldy + c];
-        for (int cc = r + 1; cc < kw; ++cc) s -= Ud[r * (BS + 1) + cc] * Y[(k + cc) * ldy + c];
-        Y[(k + r) * ldy + c] = s / Ud[r * (BS + 1) + r];
-      }
-    }
-    __syncthreads();
-    // Rows above the block: Y[r] -= U[r, k:kend] X[k:kend].
-    for (int r = threadIdx.x; r < k; r += blockDim.x) {
-      double u[BS];
-#pragma unroll
-      for (int i = 0; i < BS; ++i) u[i] = (i < kw) ? d.W[(size_t)r * ld + k + i] : 0.0;
-      for (int c = 0; c < w; ++c) {
-        double s = Y[r * ldy + c];
-#pragma unroll
-        for (int i = 0; i < BS; ++i)
-          if (i < kw) s -= u[i] * Y[(k + i) * ldy + c];
-        Y[r * ldy + c] = s;
-      }
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < n * w; e += blockDim.x) {
-    int r = e / w, c = e % w;
-    d.X[(size_t)r * d.ldx + c0 + c] = Y[r * ldy + c];
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Host drivers.
 // ---------------------------------------------------------------------------
 
-int back_subst_width(int n, int m) {
-  // Largest column block whose Y tile plus the diagonal block fits in LDS.
-  int cw = 64;
-  while (cw > 1 && (size_t)n * (cw + 1) + BS * (BS + 1) > (size_t)BSUB_LDS) cw >>= 1;
-  return std::max(1, std::min(cw, m));
+template <int KB>
+static void launch_panel(const SolveDesc* d_desc, int np, int k0, int rows, int* st,
+                         hipStream_t s) {
+  if (rows <= 256)
+    hipLaunchKernelGGL((k_gj_panel<256, 1, KB>), dim3(np), dim3(256), 0, s, d_desc, k0, st);
+  else if (rows <= 512)
+    hipLaunchKernelGGL((k_gj_panel<512, 1, KB>), dim3(np), dim3(512), 0, s, d_desc, k0, st);
+  else if (rows <= 1024)
+    hipLaunchKernelGGL((k_gj_panel<1024, 1, KB>), dim3(np), dim3(1024), 0, s, d_desc, k0, st);
+  else if (rows <= 2048)
+    hipLaunchKernelGGL((k_gj_panel<1024, 2, 16>), dim3(np), dim3(1024), 0, s, d_desc, k0, st);
+  else
+    hipLaunchKernelGGL((k_gj_panel<1024, 3, 16>), dim3(np), dim3(1024), 0, s, d_desc, k0, st);
 }
 
+int max_solve_rows() { return 3072; }
+
 void batched_solve(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc, int* d_status,
-                   hipStream_t stream, int nb) {
+                   hipStream_t stream, int /*nb_hint*/) {
   if (h_desc.empty()) return;
-  nb = std::min(nb, MAXNB);
-  int nmax = 0, wmax = 0, mmax = 0, nfor_cw = 0;
+  int nmax = 0, wmax = 0;
   for (auto& d : h_desc) {
     nmax = std::max(nmax, d.n);
     wmax = std::max(wmax, d.n + d.m);
-    mmax = std::max(mmax, d.m);
-    nfor_cw = std::max(nfor_cw, d.n);
   }
+  HPS_REQUIRE(nmax <= max_solve_rows(), "dense system too large for the register panel");
+  // Panels wider than 16 columns only while every row fits one register row per thread.
+  const int nb = nmax > 1024 ? 16 : 32;
   const int np = (int)h_desc.size();
   for (int k0 = 0; k0 < nmax; k0 += nb) {
-    hipLaunchKernelGGL(k_lu_panel, dim3(np), dim3(256), 0, stream, d_desc, k0, nb, d_status);
-    int rest = wmax - k0;
-    if (rest > 0) {
-      hipLaunchKernelGGL(k_swap_trsm, dim3((rest + 255) / 256, np), dim3(256), 0, stream, d_desc,
-                         k0, nb);
-      int mt = (nmax - k0 + TBM - 1) / TBM, nt = (rest + TBN - 1) / TBN;
-      hipLaunchKernelGGL(k_lu_update, dim3(nt, mt, np), dim3(256), 0, stream, d_desc, k0, nb);
+    double fp = 0, ft = 0, fu = 0;
+    for (auto& d : h_desc) {
+      if (k0 >= d.n) continue;
+      const double kb = std::min(nb, d.n - k0), rows = d.n - k0, rest = d.n + d.m - k0 - kb;
+      fp += rows * kb * kb;
+      ft += 2.0 * rest * kb * kb;
+      fu += 2.0 * (d.n - kb) * rest * kb;
+    }
+    const int rows = nmax - k0;
+    {
+      ProfScope ps(PROF_LU_PANEL, stream, fp, 0);
+      if (nb == 32)
+        launch_panel<32>(d_desc, np, k0, rows, d_status, stream);
+      else
+        launch_panel<16>(d_desc, np, k0, rows, d_status, stream);
+    }
+    const int rest = wmax - k0 - std::min(nb, rows);
+    if (rest <= 0) continue;
+    {
+      ProfScope ps(PROF_SWAP_TRSM, stream, ft, 0);
+      dim3 g((rest + 255) / 256, np);
+      if (nb == 32)
+        hipLaunchKernelGGL((k_gj_swap_trsm<32>), g, dim3(256), 0, stream, d_desc, k0);
+      else
+        hipLaunchKernelGGL((k_gj_swap_trsm<16>), g, dim3(256), 0, stream, d_desc, k0);
+    }
+    const int ty = (k0 + TBM - 1) / TBM + (std::max(0, nmax - k0 - nb) + TBM - 1) / TBM;
+    if (ty > 0) {
+      ProfScope ps(PROF_LU_UPDATE, stream, fu, 0);
+      hipLaunchKernelGGL(k_gj_update, dim3((rest + TBN - 1) / TBN, ty, np), dim3(256), 0, stream,
+                         d_desc, k0, nb);
     }
   }
-  const int cw = back_subst_width(nfor_cw, mmax);
-  size_t shm = ((size_t)nfor_cw * (cw + 1) + BS * (BS + 1)) * sizeof(double);
-  hipLaunchKernelGGL(k_back_subst, dim3((mmax + cw - 1) / cw, np), dim3(256), shm, stream, d_desc,
-                     cw);
 }
 
 void grouped_gemm(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, hipStream_t stream,
@@ -475,19 +545,18 @@ void grouped_gemm(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, h
     nmax = std::max(nmax, g.N);
   }
   dim3 grid((nmax + TBN - 1) / TBN, (mmax + TBM - 1) / TBM, (unsigned)h_desc.size());
+  double fl = 0, by = 0;
+  for (auto& g : h_desc) {
+    fl += 2.0 * g.M * g.N * g.K;
+    by += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + 2.0 * g.M * g.N);
+  }
+  ProfScope ps(split32 ? PROF_GEMM_SPLIT32 : PROF_GEMM, stream, fl, by);
   if (split32)
     hipLaunchKernelGGL(k_gemm_split32, grid, dim3(256), 0, stream, d_desc);
   else
     hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, stream, d_desc);
 }
 
-void dense_init() {
-  static bool done = false;
-  if (done) return;
-  HPS_HIP(hipFuncSetAttribute((const void*)k_back_subst,
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(BSUB_LDS + BS * (BS + 1)) * (int)sizeof(double)));
-  done = true;
-}
+void dense_init() {}
 
 }  // namespace hps

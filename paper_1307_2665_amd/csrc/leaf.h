@@ -1,0 +1,20 @@
+// Fused register-resident leaf solve (section 3.1) -- host entry points.
+#pragma once
+
+#include "common.h"
+#include "ops.h"
+
+namespace hps {
+
+// True when the augmented leaf system (n rows, n + m columns) fits a register variant.
+bool leaf_lu_fits(int n, int m);
+
+// Z[leaf] = A_ii^-1 R for count leaves (coefficients cptr[leaf]); Z is [count][n][m].
+// status[0] becomes 1 and status[1] = tag0 - leaf on a zero or non-finite pivot.
+// Register variant: 0 = 16x16 threads (p <= 12), 1 = 16x64 threads, 2 = 16x32 threads.
+void leaf_lu_set_variant(int v);
+
+void leaf_lu(const double* const* cptr, const LeafDev& tab, int count, double* Z, int* status,
+             int tag0, hipStream_t s);
+
+}  // namespace hps

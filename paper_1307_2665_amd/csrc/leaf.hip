@@ -1,0 +1,266 @@
+// Fused leaf solve (section 3.1, eq:leaf_solve): for one leaf per workgroup,
+// assemble the augmented system [A_ii | R] (R = A_ie L1) directly in
+// registers, run LU with partial pivoting on it (the elimination carries R
+// along) and back-substitute, leaving Z = A_ii^-1 R in global memory.  The
+// leaf DtN is then T = P0 - P1 Z (section 3.2), formed by the grouped GEMM.
+//
+// Register layout: a TR x TC thread grid (thread id = tr + TR * tc) owns the
+// matrix cyclically: row i = tr + TR * s (s < NR), column j = tc + TC * t
+// (t < NC), so each thread holds NR x NC doubles.  The TR threads owning a
+// column are TR consecutive lanes of one wave, so the pivot search of a column
+// is a shuffle reduction without barriers.  Step k of the elimination costs two
+// workgroup barriers: one to publish the pivot, one to publish the pivot row
+// and the multipliers (double-buffered in LDS).  The step loop is split as
+// k = TR * ks + kk with ks unrolled, so the row slot ks of the pivot row and
+// its column slot (TR * ks) / TC are compile-time register indices.
+#include "leaf.h"
+#include "prof.h"
+
+namespace hps {
+
+template <int TR, int TC, int NR, int NC>
+__global__ void __launch_bounds__(TR * TC) k_leaf_lu(const double* const* __restrict__ cptr,
+                                                     const LeafDev tab, double* __restrict__ Z,
+                                                     int* status, int tag0) {
+  static_assert(TC % TR == 0, "column tile must be a multiple of the row tile");
+  constexpr int NT = TR * TC;
+  __shared__ double sD[4][24 * 24];
+  __shared__ double sc[6][NR * TR];
+  __shared__ double RowK[2][NC * TC], RowP[2][NC * TC], Lb[2][NR * TR];
+  __shared__ double Ucol[2][NR * TR], Xr[2][NC * TC];
+  __shared__ double dinv[NR * TR];
+  __shared__ int pidx[2];
+  __shared__ double pval[2];
+
+  const int p = tab.p, n = tab.n, m = tab.m, pi = p - 2, w = n + m;
+  const int tid = threadIdx.x, tr = tid % TR, tc = tid / TR;
+  const double* cl = cptr[blockIdx.x];
+  for (int e = tid; e < p * p; e += NT) {
+    sD[0][e] = tab.Dx[e];
+    sD[1][e] = tab.Dy[e];
+    sD[2][e] = tab.Dxx[e];
+    sD[3][e] = tab.Dyy[e];
+  }
+  for (int e = tid; e < 6 * n; e += NT) {
+    int f = e / n, k = e % n;
+    sc[f][k] = cl[(size_t)f * p * p + (1 + k % pi) + p * (1 + k / pi)];
+  }
+  __syncthreads();
+
+  // ---- assembly (same formulas as the unfused path) ----
+  double a[NR][NC];
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    const int i = tr + TR * s;
+    const bool rv = i < n;
+    const int ia = rv ? 1 + i % pi : 1, ib = rv ? 1 + i / pi : 1;
+    const double c11 = rv ? sc[0][i] : 0, c12 = rv ? sc[1][i] : 0, c22 = rv ? sc[2][i] : 0;
+    const double c1 = rv ? sc[3][i] : 0, c2 = rv ? sc[4][i] : 0, c0 = rv ? sc[5][i] : 0;
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+      const int j = tc + TC * t;
+      double v = 0.0;
+      if (rv && j < n) {
+        const int ja = 1 + j % pi, jb = 1 + j / pi;
+        const double dx = sD[0][ia * p + ja], dy = sD[1][ib * p + jb];
+        v = -2.0 * c12 * dx * dy;
+        if (ib == jb) v += -c11 * sD[2][ia * p + ja] + c1 * dx;
+        if (ia == ja) v += -c22 * sD[3][ib * p + jb] + c2 * dy;
+        if (i == j) v += c0;
+      } else if (rv && j < w) {
+        const size_t o = (size_t)i * m + (j - n), st = (size_t)n * m;
+        v = -c11 * tab.G[o] - 2.0 * c12 * tab.G[st + o] - c22 * tab.G[2 * st + o] +
+            c1 * tab.G[3 * st + o] + c2 * tab.G[4 * st + o];
+      }
+      a[s][t] = v;
+    }
+  }
+
+  // ---- forward elimination with partial pivoting ----
+#pragma unroll
+  for (int ks = 0; ks < NR; ++ks) {
+      const int ts = (TR * ks) / TC;
+    for (int kk = 0; kk < TR; ++kk) {
+      const int k = TR * ks + kk;
+      if (k >= n) break;
+      const int buf = k & 1;
+      const int tck = (TR * ks) % TC + kk;
+      if (tc == tck) {
+        double best = -1.0, bval = 0.0;
+        int bidx = -1;
+#pragma unroll
+        for (int s = ks; s < NR; ++s) {
+          const int i = tr + TR * s;
+          const double v = a[s][ts];
+          const double av = (v != v) ? INFINITY : fabs(v);
+          if (i >= k && i < n && av > best) {
+            best = av;
+            bidx = i;
+            bval = v;
+          }
+        }
+#pragma unroll
+        for (int off = TR / 2; off > 0; off >>= 1) {
+          const double ob = __shfl_xor(best, off, TR);
+          const double ov = __shfl_xor(bval, off, TR);
+          const int oi = __shfl_xor(bidx, off, TR);
+          if (oi >= 0 && (bidx < 0 || ob > best || (ob == best && oi < bidx))) {
+            best = ob;
+            bval = ov;
+            bidx = oi;
+          }
+        }
+        if (tr == 0) {
+          pidx[buf] = bidx < 0 ? k : bidx;
+          pval[buf] = bval;
+        }
+      }
+      __syncthreads();
+      // The pivot row is the same for the whole workgroup: keep it in scalar
+      // registers so the slot selection below is a scalar branch.
+      const int pr = __builtin_amdgcn_readfirstlane(pidx[buf]);
+      const double piv = pval[buf];
+      const int trp = pr % TR, sp = pr / TR;
+      if (tr == kk) {
+#pragma unroll
+        for (int t = 0; t < NC; ++t) RowK[buf][tc + TC * t] = a[ks][t];
+      }
+#pragma unroll
+      for (int s = 0; s < NR; ++s)
+        if (s == sp) {
+          if (tr == trp) {
+#pragma unroll
+            for (int t = 0; t < NC; ++t) RowP[buf][tc + TC * t] = a[s][t];
+          }
+        }
+      const double inv = (piv != 0.0 && piv == piv) ? 1.0 / piv : 0.0;
+      if (tc == tck) {
+#pragma unroll
+        for (int s = ks; s < NR; ++s) {
+          const int i = tr + TR * s;
+          if (i > k && i < n && i != pr) Lb[buf][i] = a[s][ts] * inv;
+          if (i == k && pr != k) Lb[buf][pr] = a[s][ts] * inv;
+        }
+        if (tr == 0) dinv[k] = inv;
+      }
+      if (tid == 0 && (piv == 0.0 || piv != piv))
+        if (atomicCAS(status, 0, 1) == 0) status[1] = tag0 - (int)blockIdx.x;
+      __syncthreads();
+      if (pr != k) {
+        if (tr == kk) {
+#pragma unroll
+          for (int t = 0; t < NC; ++t) a[ks][t] = RowP[buf][tc + TC * t];
+        }
+#pragma unroll
+        for (int s = 0; s < NR; ++s)
+          if (s == sp) {
+            if (tr == trp) {
+#pragma unroll
+              for (int t = 0; t < NC; ++t) a[s][t] = RowK[buf][tc + TC * t];
+            }
+          }
+      }
+      double u[NC];
+#pragma unroll
+      for (int t = 0; t < NC; ++t) u[t] = (t >= ts) ? RowP[buf][tc + TC * t] : 0.0;
+#pragma unroll
+      for (int s = ks; s < NR; ++s) {
+        const int i = tr + TR * s;
+        const double l = (i > k && i < n) ? Lb[buf][i] : 0.0;
+#pragma unroll
+        for (int t = ts; t < NC; ++t) {
+          const int j = tc + TC * t;
+          if (t > ts || j > k) a[s][t] -= l * u[t];
+        }
+      }
+    }
+  }
+
+  // ---- back substitution on the right-hand-side columns ----
+  // Row k's RHS entries are final once rows > k are done; x_k = y_k / u_kk,
+  // then y_i -= u_ik x_k for i < k.
+  __syncthreads();
+#pragma unroll
+  for (int ks = NR - 1; ks >= 0; --ks) {
+    const int ts = (TR * ks) / TC;
+    for (int kk = TR - 1; kk >= 0; --kk) {
+      const int k = TR * ks + kk;
+      if (k >= n) continue;
+      const int buf = k & 1;
+      const int tck = (TR * ks) % TC + kk;
+      if (tr == kk) {
+        const double di = dinv[k];
+#pragma unroll
+        for (int t = 0; t < NC; ++t) {
+          const int j = tc + TC * t;
+          if (j >= n && j < w) {
+            a[ks][t] *= di;
+            Xr[buf][j - n] = a[ks][t];
+          }
+        }
+      }
+      if (tc == tck) {
+#pragma unroll
+        for (int s = 0; s <= ks; ++s) {
+          const int i = tr + TR * s;
+          if (i < k) Ucol[buf][i] = a[s][ts];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s <= ks; ++s) {
+        const int i = tr + TR * s;
+        if (i < k) {
+          const double uk = Ucol[buf][i];
+#pragma unroll
+          for (int t = 0; t < NC; ++t) {
+            const int j = tc + TC * t;
+            if (j >= n && j < w) a[s][t] -= uk * Xr[buf][j - n];
+          }
+        }
+      }
+    }
+  }
+
+  // ---- Z out: [n][m] per leaf ----
+  double* Zl = Z + (size_t)blockIdx.x * n * m;
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    const int i = tr + TR * s;
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+      const int j = tc + TC * t;
+      if (i < n && j >= n && j < w) Zl[(size_t)i * m + (j - n)] = a[s][t];
+    }
+  }
+}
+
+// Register variants: rows <= NR*TR, columns (n + m) <= NC*TC.
+bool leaf_lu_fits(int n, int m) {
+  return (n <= 13 * 16 && n + m <= 8 * 32) || (n <= 7 * 16 && n + m <= 9 * 16);
+}
+
+static int g_leaf_variant = -1;  // -1: default choice; else forced variant index
+
+void leaf_lu_set_variant(int v) { g_leaf_variant = v; }
+
+void leaf_lu(const double* const* cptr, const LeafDev& tab, int count, double* Z, int* status,
+             int tag0, hipStream_t s) {
+  const double n = tab.n, m = tab.m;
+  ProfScope ps(PROF_LEAF_LU, s, count * (2.0 * n * n * n / 3.0 + 2.0 * n * n * m), 0);
+  const bool small = tab.n <= 7 * 16 && tab.n + tab.m <= 9 * 16;
+  int v = g_leaf_variant >= 0 ? g_leaf_variant : (small ? 0 : 2);
+  if (v == 0 && !small) v = 1;
+  if (v == 0) {
+    hipLaunchKernelGGL((k_leaf_lu<16, 16, 7, 9>), dim3(count), dim3(256), 0, s, cptr, tab, Z,
+                       status, tag0);
+  } else if (v == 2) {
+    hipLaunchKernelGGL((k_leaf_lu<16, 32, 13, 8>), dim3(count), dim3(512), 0, s, cptr, tab, Z,
+                       status, tag0);
+  } else {
+    hipLaunchKernelGGL((k_leaf_lu<16, 64, 13, 4>), dim3(count), dim3(1024), 0, s, cptr, tab, Z,
+                       status, tag0);
+  }
+}
+
+}  // namespace hps

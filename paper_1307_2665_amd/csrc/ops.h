@@ -21,13 +21,15 @@ struct LeafDev {
 void leaf_assemble(const double* const* cptr, const LeafDev& tab, int count, double* W,
                    hipStream_t s);
 void merge_gather(const MergeDesc* d_desc, int nmerge, size_t max_elems, hipStream_t s);
+// s_bytes: bytes of all S of the level (the pass's algorithmic traffic per RHS chunk).
 void downward(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, double* u, int N,
-              int nrhs, const double* zbase, const long long* zoff, hipStream_t s);
+              int nrhs, const double* zbase, const long long* zoff, hipStream_t s,
+              double s_bytes);
 void set_boundary(const double* f, const int* gamma, int nb, double* u, int N, int nrhs,
                   hipStream_t s);
 void interface_residual(const double* leafT, const double* u, int N, int nrhs, int nx, int ny,
                         int q, double* vbuf, double* r, hipStream_t s);
-void upward_level(const MergeDesc* d_desc, int nmerge, int m3_max, const double* s, int N, int nb,
+void upward_level(const MergeDesc* d_desc, int nmerge, int m3_max, const double* s, int N,
                   const double* hchild, const long long* ha_off, const long long* hb_off,
                   double* hpar, const long long* hp_off, double* zbuf, const long long* z_off,
                   int nrhs, hipStream_t st);

@@ -2,6 +2,7 @@
 // (section 4), downward pass (Algorithm 2), interface residual and the
 // upward source pass used by iterative refinement.
 #include "ops.h"
+#include "prof.h"
 
 #include <algorithm>
 
@@ -64,6 +65,7 @@ __global__ void __launch_bounds__(256) k_leaf_assemble(const double* const* __re
 void leaf_assemble(const double* const* cptr, const LeafDev& tab, int count, double* W,
                    hipStream_t s) {
   HPS_REQUIRE(tab.p <= PMAX, "p too large");
+  ProfScope ps(PROF_LEAF_ASSEMBLE, s, 0, 8.0 * count * ((double)tab.n * (tab.n + tab.m) + 6.0 * tab.p * tab.p));
   hipLaunchKernelGGL(k_leaf_assemble, dim3(count), dim3(256), 0, s, cptr, tab, W);
 }
 
@@ -75,7 +77,7 @@ void leaf_assemble(const double* const* cptr, const LeafDev& tab, int count, dou
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_merge_gather(const MergeDesc* __restrict__ descs) {
   const MergeDesc d = descs[blockIdx.y];
-  const int m3 = d.m3, me = d.me, ldw = m3 + me;
+  const int m3 = d.m3, me = d.me, ldw = d.ldw;
   const size_t nW = (size_t)m3 * ldw, nQ = (size_t)me * m3, nT = (size_t)me * me;
   const size_t tot = nW + nQ + nT;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
@@ -86,9 +88,11 @@ __global__ void __launch_bounds__(256) k_merge_gather(const MergeDesc* __restric
       double v;
       if (j < m3) {
         v = d.Ta[(size_t)ra * d.na + d.a3[j]] - d.Tb[(size_t)rb * d.nb + d.b3[j]];
-      } else {
+      } else if (j < m3 + me) {
         int pm = d.pmap[j - m3];
         v = (pm >= 0) ? -d.Ta[(size_t)ra * d.na + pm] : d.Tb[(size_t)rb * d.nb + (-pm - 1)];
+      } else {
+        v = (j - m3 - me == i) ? 1.0 : 0.0;  // identity block -> M^-1
       }
       d.W[e] = v;
     } else if (e < nW + nQ) {
@@ -113,6 +117,7 @@ __global__ void __launch_bounds__(256) k_merge_gather(const MergeDesc* __restric
 
 void merge_gather(const MergeDesc* d_desc, int nmerge, size_t max_elems, hipStream_t s) {
   int bx = (int)std::min<size_t>((max_elems + 255) / 256, 4096);
+  ProfScope ps(PROF_MERGE_GATHER, s, 0, 16.0 * nmerge * (double)max_elems);
   hipLaunchKernelGGL(k_merge_gather, dim3(bx, nmerge), dim3(256), 0, s, d_desc);
 }
 
@@ -142,7 +147,7 @@ __global__ void __launch_bounds__(256) k_downward(const MergeDesc* __restrict__ 
     for (int rr = wid; rr < DROWS; rr += 4) {
       const int r = r0 + rr;
       if (r >= d.m3) break;
-      const double* Srow = d.S + (size_t)r * me;
+      const double* Srow = d.S + (size_t)r * d.ldw;
       for (int k = 0; k < nr; ++k) {
         double acc = 0.0;
         for (int c = lane; c < me; c += 64) acc += Srow[c] * ue[k * me + c];
@@ -176,7 +181,7 @@ __global__ void __launch_bounds__(256) k_downward_z(const MergeDesc* __restrict_
     for (int rr = wid; rr < DROWS; rr += 4) {
       const int r = r0 + rr;
       if (r >= d.m3) break;
-      const double* Srow = d.S + (size_t)r * me;
+      const double* Srow = d.S + (size_t)r * d.ldw;
       for (int k = 0; k < nr; ++k) {
         double acc = 0.0;
         for (int c = lane; c < me; c += 64) acc += Srow[c] * ue[k * me + c];
@@ -193,12 +198,14 @@ int downward_rhs_chunk(int me_max, int nrhs) {
 }
 
 void downward(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, double* u, int N,
-              int nrhs, const double* zbase, const long long* zoff, hipStream_t s) {
+              int nrhs, const double* zbase, const long long* zoff, hipStream_t s,
+              double s_bytes) {
   HPS_REQUIRE((size_t)me_max * sizeof(double) <= 96 * 1024,
               "downward pass: box boundary too long for the LDS-staged kernel");
   const int rc = downward_rhs_chunk(me_max, nrhs);
   size_t shm = (size_t)rc * me_max * sizeof(double);
   dim3 grid((m3_max + DROWS - 1) / DROWS, nmerge);
+  ProfScope ps(PROF_DOWNWARD, s, 2.0 * nrhs * s_bytes / 8.0, s_bytes);
   if (zbase)
     hipLaunchKernelGGL(k_downward_z, grid, dim3(256), shm, s, d_desc, u, N, nrhs, rc, zbase, zoff);
   else
@@ -292,6 +299,7 @@ __global__ void k_jump(const double* __restrict__ v, int nx, int ny, int q, int 
 void interface_residual(const double* leafT, const double* u, int N, int nrhs, int nx, int ny,
                         int q, double* vbuf, double* r, hipStream_t s) {
   HPS_REQUIRE(4 * q <= 96, "q too large for the residual kernel");
+  ProfScope ps(PROF_RESIDUAL, s, 2.0 * nrhs * nx * ny * 16.0 * q * q, 8.0 * nx * ny * 16.0 * q * q);
   hipLaunchKernelGGL(k_leaf_flux, dim3(nx * ny), dim3(256), 0, s, leafT, u, N, nrhs, nx, ny, q,
                      vbuf);
   size_t tot = (size_t)N * nrhs;
@@ -302,85 +310,63 @@ void interface_residual(const double* leafT, const double* u, int N, int nrhs, i
 // ---------------------------------------------------------------------------
 // Upward source pass for one level (derived from the third block row of
 // eq:premerge with a source):  z = M^-1 (s3 - h3a + h3b),
-// h_parent = [h1a ; h2b] (parent order) + Q z.
-// M^-1 is applied with the kept LU factors: row interchanges and the unit
-// lower factor panel by panel (the left columns were never swapped after their
-// panel), then the upper factor.  One workgroup per (merge, right-hand side).
-// LU is stored in W[0:m3, 0:m3] with leading dimension ldw = m3 + me.
+// h_parent = [h1a ; h2b] (parent order) + Q z.  M^-1 is the explicit inverse
+// left in W by the elimination of [M | B | I].  One workgroup per
+// (merge, right-hand side); a wave per row of M^-1 and of Q.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_upward(const MergeDesc* __restrict__ descs,
-                                                const double* __restrict__ s, int N, int nb,
+                                                const double* __restrict__ s, int N,
                                                 const double* __restrict__ hchild,
                                                 const long long* __restrict__ ha_off,
                                                 const long long* __restrict__ hb_off,
                                                 double* __restrict__ hpar,
                                                 const long long* __restrict__ hp_off,
                                                 double* __restrict__ zbuf,
-                                                const long long* __restrict__ z_off,
-                                                int nrhs) {
-  extern __shared__ double zs[];
+                                                const long long* __restrict__ z_off, int nrhs) {
+  extern __shared__ double sm[];
   const int mi = blockIdx.x, rh = blockIdx.y;
   const MergeDesc d = descs[mi];
-  const int m3 = d.m3, me = d.me, ldw = m3 + me;
+  const int m3 = d.m3, me = d.me;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double* rhs = sm;
+  double* zs = sm + m3;
   // Offsets are per-box unit offsets; each box holds [nrhs][boundary size].
-  const double* ha = hchild ? hchild + ha_off[mi] * nrhs + (size_t)rh * d.na : nullptr;
-  const double* hb = hchild ? hchild + hb_off[mi] * nrhs + (size_t)rh * d.nb : nullptr;
-  for (int i = threadIdx.x; i < m3; i += blockDim.x) {
-    double v = s[(size_t)rh * N + d.Ii[i]];
-    if (ha) v += -ha[d.a3[i]] + hb[d.b3[i]];
-    zs[i] = v;
+  const double* ha = hchild + ha_off[mi] * nrhs + (size_t)rh * d.na;
+  const double* hb = hchild + hb_off[mi] * nrhs + (size_t)rh * d.nb;
+  for (int i = threadIdx.x; i < m3; i += blockDim.x)
+    rhs[i] = s[(size_t)rh * N + d.Ii[i]] - ha[d.a3[i]] + hb[d.b3[i]];
+  __syncthreads();
+  const double* Minv = d.W + d.m3 + d.me;
+  for (int i = wid; i < m3; i += 4) {
+    const double* row = Minv + (size_t)i * d.ldw;
+    double acc = 0.0;
+    for (int j = lane; j < m3; j += 64) acc += row[j] * rhs[j];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) zs[i] = acc;
   }
   __syncthreads();
-  // Forward: interleaved row swaps and unit-lower elimination, panel by panel.
-  for (int k0 = 0; k0 < m3; k0 += nb) {
-    const int kb = min(nb, m3 - k0);
-    if (threadIdx.x == 0)
-      for (int j = 0; j < kb; ++j) {
-        int r2 = d.piv[k0 + j];
-        if (r2 != k0 + j) {
-          double t = zs[k0 + j];
-          zs[k0 + j] = zs[r2];
-          zs[r2] = t;
-        }
-      }
-    __syncthreads();
-    for (int j = 0; j < kb; ++j) {
-      const double zj = zs[k0 + j];
-      for (int r = k0 + j + 1 + threadIdx.x; r < m3; r += blockDim.x)
-        zs[r] -= d.W[(size_t)r * ldw + k0 + j] * zj;
-      __syncthreads();
-    }
-  }
-  // Backward with the upper factor.
-  for (int c = m3 - 1; c >= 0; --c) {
-    if (threadIdx.x == 0) zs[c] = zs[c] / d.W[(size_t)c * ldw + c];
-    __syncthreads();
-    const double zc = zs[c];
-    for (int r = threadIdx.x; r < c; r += blockDim.x) zs[r] -= d.W[(size_t)r * ldw + c] * zc;
-    __syncthreads();
-  }
   double* z = zbuf + z_off[mi] * nrhs + (size_t)rh * m3;
   for (int i = threadIdx.x; i < m3; i += blockDim.x) z[i] = zs[i];
-  // Parent particular flux h = [h1a; h2b] + Q z.
-  if (hpar) {
-    double* hp = hpar + hp_off[mi] * nrhs + (size_t)rh * me;
-    for (int r = threadIdx.x; r < me; r += blockDim.x) {
-      int pm = d.pmap[r];
-      double v = 0.0;
-      if (ha) v = (pm >= 0) ? ha[pm] : hb[-pm - 1];
-      const double* Qr = d.Q + (size_t)r * m3;
-      for (int i = 0; i < m3; ++i) v += Qr[i] * zs[i];
-      hp[r] = v;
+  double* hp = hpar + hp_off[mi] * nrhs + (size_t)rh * me;
+  for (int r = wid; r < me; r += 4) {
+    const double* Qr = d.Q + (size_t)r * m3;
+    double acc = 0.0;
+    for (int j = lane; j < m3; j += 64) acc += Qr[j] * zs[j];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) {
+      const int pm = d.pmap[r];
+      hp[r] = acc + ((pm >= 0) ? ha[pm] : hb[-pm - 1]);
     }
   }
 }
 
-void upward_level(const MergeDesc* d_desc, int nmerge, int m3_max, const double* s, int N, int nb,
+void upward_level(const MergeDesc* d_desc, int nmerge, int m3_max, const double* s, int N,
                   const double* hchild, const long long* ha_off, const long long* hb_off,
                   double* hpar, const long long* hp_off, double* zbuf, const long long* z_off,
                   int nrhs, hipStream_t st) {
-  size_t shm = (size_t)m3_max * sizeof(double);
-  hipLaunchKernelGGL(k_upward, dim3(nmerge, nrhs), dim3(256), shm, st, d_desc, s, N, nb, hchild,
+  size_t shm = 2 * (size_t)m3_max * sizeof(double);
+  ProfScope ps(PROF_UPWARD, st, 0, 0);
+  hipLaunchKernelGGL(k_upward, dim3(nmerge, nrhs), dim3(256), shm, st, d_desc, s, N, hchild,
                      ha_off, hb_off, hpar, hp_off, zbuf, z_off, nrhs);
 }
 

@@ -1,0 +1,40 @@
+// Launch-level timing of kernel classes with HIP events on the launch stream,
+// plus the algorithmic FLOPs and bytes of each timed launch.  Off unless a
+// class is enabled through hps_prof_enable.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace hps {
+
+enum ProfClass {
+  PROF_LEAF_ASSEMBLE = 0,
+  PROF_LU_PANEL = 1,
+  PROF_SWAP_TRSM = 2,
+  PROF_LU_UPDATE = 3,
+  PROF_BACK_SUBST = 4,
+  PROF_GEMM = 5,
+  PROF_GEMM_SPLIT32 = 6,
+  PROF_MERGE_GATHER = 7,
+  PROF_DOWNWARD = 8,
+  PROF_RESIDUAL = 9,
+  PROF_UPWARD = 10,
+  PROF_LEAF_LU = 11,
+  PROF_NCLASS = 16
+};
+
+bool prof_on(int cls);
+
+// Records a start event on construction and a stop event on destruction when
+// the class is enabled; flops/bytes are the launch's algorithmic work.
+class ProfScope {
+ public:
+  ProfScope(int cls, hipStream_t s, double flops, double bytes);
+  ~ProfScope();
+
+ private:
+  int rec_ = -1;
+  hipStream_t s_;
+};
+
+}  // namespace hps

@@ -21,6 +21,7 @@
 #include <tuple>
 
 #include "dense.h"
+#include "leaf.h"
 #include "ops.h"
 
 namespace hps {
@@ -120,30 +121,27 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
     }
   int* dpool = op->mem.upload(pool, s);
 
+  // W (augmented system, later S and M^-1) and pivots are kept for every merge;
+  // Q is kept only when the upward pass is wanted, else one level of scratch.
   const bool keep = op->opt.keep_factors;
-  long long totS = 0, totW = 0, totQ = 0, totP = 0;
-  long long maxW = 0, maxQ = 0, maxP = 0;
+  long long totW = 0, totQ = 0, totP = 0, maxQ = 0, totS = 0;
   for (int d = 0; d <= t.depth; ++d) {
-    long long lw = 0, lq = 0, lp = 0;
+    long long lq = 0;
     for (int b : t.parents_at_level[d]) {
       const MergeMaps& g = mm[b];
+      HPS_REQUIRE(g.m3 <= max_solve_rows(), "merge interface too long for the dense solver");
       totS += (long long)g.m3 * g.me;
-      lw += (long long)g.m3 * (g.m3 + g.me);
+      totW += (long long)g.m3 * (g.m3 + g.me + (keep ? g.m3 : 0));
       lq += (long long)g.me * g.m3;
-      lp += g.m3;
+      totP += g.m3;
     }
-    totW += lw;
     totQ += lq;
-    totP += lp;
-    maxW = std::max(maxW, lw);
     maxQ = std::max(maxQ, lq);
-    maxP = std::max(maxP, lp);
   }
-  op->S = op->mem.alloc<double>(totS);
   op->bytes_S = totS * (long long)sizeof(double);
-  op->Wk = op->mem.alloc<double>(keep ? totW : maxW);
+  op->Wk = op->mem.alloc<double>(totW);
   op->Q = op->mem.alloc<double>(keep ? totQ : maxQ);
-  op->piv = op->mem.alloc<int>(keep ? totP : maxP);
+  op->piv = op->mem.alloc<int>(totP);
   long long ar[2] = {0, 0};
   for (int d = 0; d <= t.depth; ++d) ar[d % 2] = std::max(ar[d % 2], lvlT[d]);
   op->arena[0] = op->mem.alloc<double>(ar[0]);
@@ -161,13 +159,13 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
   op->levels.assign(t.depth + 1, LevelPlan());
   op->merge_level.assign(nbox, -1);
   op->merge_index.assign(nbox, -1);
-  long long oS = 0, oW = 0, oQ = 0, oP = 0, oz = 0;
+  long long oW = 0, oQ = 0, oP = 0, oz = 0;
   const int n_int = (p - 2) * (p - 2);
   long long flops = (long long)nl * ((2LL * n_int * n_int * n_int) / 3 + 2LL * n_int * n_int * m +
                                      2LL * m * m * n_int);
   for (int d = 0; d <= t.depth; ++d) {
     LevelPlan& L = op->levels[d];
-    if (!keep) oW = oQ = oP = 0;
+    if (!keep) oQ = 0;
     for (int b : t.parents_at_level[d]) {
       const BoxRec& B = t.boxes[b];
       const MergeMaps& g = mm[b];
@@ -180,8 +178,11 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
       md.Ta = child_T(B.ca);
       md.Tb = child_T(B.cb);
       md.Tp = op->arena[d % 2] + Toff[b];
+      const int ldw = g.m3 + g.me + (keep ? g.m3 : 0);
       md.W = op->Wk + oW;
-      md.S = op->S + oS;
+      md.S = md.W + g.m3;
+      md.ldw = ldw;
+      md.inv = keep ? 1 : 0;
       md.Q = op->Q + oQ;
       md.piv = op->piv + oP;
       const int* base = dpool + pool_off[b];
@@ -198,10 +199,10 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
       op->merge_level[b] = d;
       op->merge_index[b] = (int)L.h.size();
       L.h.push_back(md);
-      SolveDesc sd{md.W, md.piv, md.S, g.m3, g.me, g.m3 + g.me, g.me, b, 0};
+      SolveDesc sd{md.W, md.piv, md.W + g.m3, g.m3, ldw - g.m3, ldw, ldw, b, 0};
       L.hs.push_back(sd);
       if (b != 0 || op->opt.root_dtn) {
-        GemmDesc gd{md.Q, md.S, md.Tp, nullptr, g.me, g.me, g.m3, g.m3, g.me, g.me, 0, 1.0};
+        GemmDesc gd{md.Q, md.S, md.Tp, nullptr, g.me, g.me, g.m3, g.m3, ldw, g.me, 0, 1.0};
         L.hg.push_back(gd);
       }
       L.ha.push_back(op->box_hoff[B.ca]);
@@ -212,8 +213,7 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
       L.me_max = std::max(L.me_max, g.me);
       L.gather_max = std::max(L.gather_max, (size_t)g.m3 * (g.m3 + g.me) + (size_t)g.me * g.m3 +
                                                 (size_t)g.me * g.me);
-      oS += (long long)g.m3 * g.me;
-      oW += (long long)g.m3 * (g.m3 + g.me);
+      oW += (long long)g.m3 * ldw;
       oQ += (long long)g.me * g.m3;
       oP += g.m3;
       oz += g.m3;
@@ -246,46 +246,57 @@ struct LeafJob {
 };
 
 static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hipStream_t s,
-                           std::vector<std::vector<char>>& keep_alive, int* dstatus, int panel) {
+                           int* dstatus, int panel) {
   hps_op* op0 = jobs[0].op;
   const int p = op0->p, q = op0->q, n = (p - 2) * (p - 2), m = 4 * q, ld = n + m;
   LeafDev tab{op0->dDx, op0->dDy, op0->dDxx, op0->dDyy, op0->dG, p, n, m, 0};
-  const size_t per = (size_t)n * ld * sizeof(double) + (size_t)n * sizeof(int);
+  const bool fused = leaf_lu_fits(n, m);
+  // Fused path: only Z (n x m) per leaf; generic path: the augmented system.
+  const size_t per = fused ? (size_t)n * m * sizeof(double)
+                           : (size_t)n * ld * sizeof(double) + (size_t)n * sizeof(int);
   const size_t budget = (size_t)2 << 30;
   const int total = (int)jobs.size();
   const int CH = (int)std::max<size_t>(1, std::min<size_t>(total, budget / per));
-  double* Wslab = tmp.alloc<double>((size_t)CH * n * ld);
-  int* pslab = tmp.alloc<int>((size_t)CH * n);
+  double* Wslab = tmp.alloc<double>(fused ? (size_t)CH * n * m : (size_t)CH * n * ld);
+  int* pslab = fused ? nullptr : tmp.alloc<int>((size_t)CH * n);
   const double** dcp = tmp.alloc<const double*>(CH);
-  SolveDesc* dsd = tmp.alloc<SolveDesc>(CH);
+  SolveDesc* dsd = fused ? nullptr : tmp.alloc<SolveDesc>(CH);
   GemmDesc* dgd = tmp.alloc<GemmDesc>(CH);
   for (int c0 = 0; c0 < total; c0 += CH) {
     const int cnt = std::min(CH, total - c0);
     std::vector<const double*> cp(cnt);
-    std::vector<SolveDesc> sd(cnt);
+    std::vector<SolveDesc> sd(fused ? 0 : cnt);
     std::vector<GemmDesc> gd(cnt);
     for (int i = 0; i < cnt; ++i) {
       const LeafJob& j = jobs[c0 + i];
       cp[i] = j.op->coeffs + (size_t)j.leaf * 6 * p * p;
-      double* W = Wslab + (size_t)i * n * ld;
-      sd[i] = SolveDesc{W, pslab + (size_t)i * n, W + n, n, m, ld, ld, -(j.leaf + 1), 0};
-      gd[i] = GemmDesc{j.op->dP1, W + n, j.op->leafT + (size_t)j.leaf * m * m, j.op->dP0,
-                       m, m, n, n, ld, m, m, -1.0};
+      if (fused) {
+        double* Zl = Wslab + (size_t)i * n * m;
+        gd[i] = GemmDesc{j.op->dP1, Zl, j.op->leafT + (size_t)j.leaf * m * m, j.op->dP0,
+                         m, m, n, n, m, m, m, -1.0};
+      } else {
+        double* W = Wslab + (size_t)i * n * ld;
+        sd[i] = SolveDesc{W, pslab + (size_t)i * n, W + n, n, m, ld, ld, -(j.leaf + 1), 0};
+        gd[i] = GemmDesc{j.op->dP1, W + n, j.op->leafT + (size_t)j.leaf * m * m, j.op->dP0,
+                         m, m, n, n, ld, m, m, -1.0};
+      }
     }
     HPS_HIP(hipMemcpyAsync(dcp, cp.data(), cnt * sizeof(void*), hipMemcpyHostToDevice, s));
-    HPS_HIP(hipMemcpyAsync(dsd, sd.data(), cnt * sizeof(SolveDesc), hipMemcpyHostToDevice, s));
     HPS_HIP(hipMemcpyAsync(dgd, gd.data(), cnt * sizeof(GemmDesc), hipMemcpyHostToDevice, s));
-    leaf_assemble(dcp, tab, cnt, Wslab, s);
-    batched_solve(dsd, sd, dstatus, s, panel);
+    if (fused) {
+      leaf_lu(dcp, tab, cnt, Wslab, dstatus, -(jobs[c0].leaf + 1), s);
+    } else {
+      HPS_HIP(hipMemcpyAsync(dsd, sd.data(), cnt * sizeof(SolveDesc), hipMemcpyHostToDevice, s));
+      leaf_assemble(dcp, tab, cnt, Wslab, s);
+      batched_solve(dsd, sd, dstatus, s, panel);
+    }
     grouped_gemm(dgd, gd, s, false);
     HPS_HIP(hipStreamSynchronize(s));  // host descriptor vectors are reused next chunk
   }
-  (void)keep_alive;
 }
 
 void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
   DeviceMem tmp;
-  std::vector<std::vector<char>> keep_alive;
   int* dstatus = tmp.alloc<int>(4);
   HPS_HIP(hipMemsetAsync(dstatus, 0, 4 * sizeof(int), s));
   for (hps_op* op : ops)
@@ -300,7 +311,7 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
     for (int l = 0; l < op->nx * op->ny; ++l) v.push_back(LeafJob{op, l});
   }
   const int panel = ops.empty() ? 32 : ops[0]->opt.panel;
-  for (auto& kv : groups) run_leaf_group(kv.second, tmp, s, keep_alive, dstatus, panel);
+  for (auto& kv : groups) run_leaf_group(kv.second, tmp, s, dstatus, panel);
 
   // Merges, deepest level first; all operators' merges at one depth together.
   int maxd = 0;
@@ -375,10 +386,9 @@ void leaf_dtn_batch(const double* coeffs, int nleaf, double hx, double hy, int p
   std::vector<LeafJob> jobs(nleaf);
   for (int i = 0; i < nleaf; ++i) jobs[i] = LeafJob{&op, i};
   DeviceMem tmp;
-  std::vector<std::vector<char>> ka;
   int* dstatus = tmp.alloc<int>(4);
   HPS_HIP(hipMemsetAsync(dstatus, 0, 4 * sizeof(int), s));
-  run_leaf_group(jobs, tmp, s, ka, dstatus, 32);
+  run_leaf_group(jobs, tmp, s, dstatus, 32);
   int st[4];
   HPS_HIP(hipMemcpyAsync(st, dstatus, sizeof(st), hipMemcpyDeviceToHost, s));
   HPS_HIP(hipStreamSynchronize(s));
@@ -393,7 +403,9 @@ static void downward_all(hps_op* op, double* u, int nrhs, const double* z, hipSt
   for (size_t d = 0; d < op->levels.size(); ++d) {
     const LevelPlan& L = op->levels[d];
     if (L.h.empty()) continue;
-    downward(L.d, (int)L.h.size(), L.m3_max, L.me_max, u, N, nrhs, z, z ? L.dzo : nullptr, s);
+    double sb = 0;
+    for (const MergeDesc& m : L.h) sb += 8.0 * m.m3 * m.me;
+    downward(L.d, (int)L.h.size(), L.m3_max, L.me_max, u, N, nrhs, z, z ? L.dzo : nullptr, s, sb);
   }
 }
 
@@ -439,8 +451,8 @@ static void upward_all(hps_op* op, const double* src, int nrhs, double* h, doubl
   for (int d = (int)op->levels.size() - 1; d >= 0; --d) {
     const LevelPlan& L = op->levels[d];
     if (L.h.empty()) continue;
-    upward_level(L.d, (int)L.h.size(), L.m3_max, src, op->tree.N, op->opt.panel, h, L.dha, L.dhb,
-                 h, L.dhp, z, L.dzo, nrhs, s);
+    upward_level(L.d, (int)L.h.size(), L.m3_max, src, op->tree.N, h, L.dha, L.dhb, h, L.dhp, z,
+                 L.dzo, nrhs, s);
   }
 }
 

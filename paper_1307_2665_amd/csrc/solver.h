@@ -65,8 +65,7 @@ struct hps_op {
   hps::BuildOptions opt;
   const double* coeffs = nullptr;   // device coefficients used by the build
   double* leafT = nullptr;          // [nleaf][4q][4q]
-  double* S = nullptr;
-  double* Wk = nullptr;             // augmented systems (kept factors) or level scratch
+  double* Wk = nullptr;             // augmented systems; S (and M^-1) live inside them
   double* Q = nullptr;
   int* piv = nullptr;
   int* gamma = nullptr;             // boundary ids in S,E,N,W order
