@@ -134,19 +134,24 @@ __global__ void __launch_bounds__(TR * TC) k_leaf_lu(const double* const* __rest
           }
         }
       const double inv = (piv != 0.0 && piv == piv) ? 1.0 / piv : 0.0;
+      // Multipliers of every row slot s >= ks (zero for rows <= k and padding
+      // rows), so the update below needs no row or column masks: rows <= k are
+      // left unchanged, and column k of the rows below becomes exactly 0.
       if (tc == tck) {
 #pragma unroll
         for (int s = ks; s < NR; ++s) {
           const int i = tr + TR * s;
-          if (i > k && i < n && i != pr) Lb[buf][i] = a[s][ts] * inv;
-          if (i == k && pr != k) Lb[buf][pr] = a[s][ts] * inv;
+          double l = (i > k && i < n && i != pr) ? a[s][ts] * inv : 0.0;
+          Lb[buf][i] = l;
         }
+        if (tr == kk && pr != k) Lb[buf][pr] = a[ks][ts] * inv;  // old row k moves to pr
         if (tr == 0) dinv[k] = inv;
       }
       if (tid == 0 && (piv == 0.0 || piv != piv))
         if (atomicCAS(status, 0, 1) == 0) status[1] = tag0 - (int)blockIdx.x;
       __syncthreads();
       if (pr != k) {
+        // Row k takes the pivot row, row pr takes the old row k.
         if (tr == kk) {
 #pragma unroll
           for (int t = 0; t < NC; ++t) a[ks][t] = RowP[buf][tc + TC * t];
@@ -160,18 +165,11 @@ __global__ void __launch_bounds__(TR * TC) k_leaf_lu(const double* const* __rest
             }
           }
       }
-      double u[NC];
 #pragma unroll
-      for (int t = 0; t < NC; ++t) u[t] = (t >= ts) ? RowP[buf][tc + TC * t] : 0.0;
+      for (int t = ts; t < NC; ++t) {
+        const double ut = RowP[buf][tc + TC * t];
 #pragma unroll
-      for (int s = ks; s < NR; ++s) {
-        const int i = tr + TR * s;
-        const double l = (i > k && i < n) ? Lb[buf][i] : 0.0;
-#pragma unroll
-        for (int t = ts; t < NC; ++t) {
-          const int j = tc + TC * t;
-          if (t > ts || j > k) a[s][t] -= l * u[t];
-        }
+        for (int s = ks; s < NR; ++s) a[s][t] = fma(-Lb[buf][tr + TR * s], ut, a[s][t]);
       }
     }
   }

@@ -29,10 +29,10 @@ void set_boundary(const double* f, const int* gamma, int nb, double* u, int N, i
                   hipStream_t s);
 void interface_residual(const double* leafT, const double* u, int N, int nrhs, int nx, int ny,
                         int q, double* vbuf, double* r, hipStream_t s);
-void upward_level(const MergeDesc* d_desc, int nmerge, int m3_max, const double* s, int N,
-                  const double* hchild, const long long* ha_off, const long long* hb_off,
-                  double* hpar, const long long* hp_off, double* zbuf, const long long* z_off,
-                  int nrhs, hipStream_t st);
+void upward_level(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, const double* s,
+                  int N, double* hbase, const long long* ha_off, const long long* hb_off,
+                  const long long* hp_off, double* zbuf, const long long* z_off, int nrhs,
+                  double flops, hipStream_t st);
 void axpy(double* y, const double* x, double a, size_t n, hipStream_t s);
 void absmax_partial(const double* x, size_t n, double* out, int blocks, hipStream_t s);
 void matvec(const double* A, int rows, int cols, const double* x, int nrhs, double* y,

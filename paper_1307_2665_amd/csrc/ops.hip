@@ -311,44 +311,66 @@ void interface_residual(const double* leafT, const double* u, int N, int nrhs, i
 // Upward source pass for one level (derived from the third block row of
 // eq:premerge with a source):  z = M^-1 (s3 - h3a + h3b),
 // h_parent = [h1a ; h2b] (parent order) + Q z.  M^-1 is the explicit inverse
-// left in W by the elimination of [M | B | I].  One workgroup per
-// (merge, right-hand side); a wave per row of M^-1 and of Q.
+// left in W by the elimination of [M | B | I].  Two row-parallel launches per
+// level: a workgroup owns UROWS rows of M^-1 (resp. of Q) of one merge and one
+// right-hand side, with the gathered vector in LDS.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_upward(const MergeDesc* __restrict__ descs,
-                                                const double* __restrict__ s, int N,
-                                                const double* __restrict__ hchild,
-                                                const long long* __restrict__ ha_off,
-                                                const long long* __restrict__ hb_off,
-                                                double* __restrict__ hpar,
-                                                const long long* __restrict__ hp_off,
-                                                double* __restrict__ zbuf,
-                                                const long long* __restrict__ z_off, int nrhs) {
-  extern __shared__ double sm[];
-  const int mi = blockIdx.x, rh = blockIdx.y;
+constexpr int UROWS = 16;
+
+__global__ void __launch_bounds__(256) k_upward_z(const MergeDesc* __restrict__ descs,
+                                                  const double* __restrict__ s, int N,
+                                                  const double* __restrict__ hbase,
+                                                  const long long* __restrict__ ha_off,
+                                                  const long long* __restrict__ hb_off,
+                                                  double* __restrict__ zbuf,
+                                                  const long long* __restrict__ z_off, int nrhs) {
+  extern __shared__ double rhs[];
+  const int mi = blockIdx.y, rh = blockIdx.z;
   const MergeDesc d = descs[mi];
-  const int m3 = d.m3, me = d.me;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  double* rhs = sm;
-  double* zs = sm + m3;
+  const int r0 = blockIdx.x * UROWS;
+  if (r0 >= d.m3) return;
+  const int m3 = d.m3, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   // Offsets are per-box unit offsets; each box holds [nrhs][boundary size].
-  const double* ha = hchild + ha_off[mi] * nrhs + (size_t)rh * d.na;
-  const double* hb = hchild + hb_off[mi] * nrhs + (size_t)rh * d.nb;
+  const double* ha = hbase + ha_off[mi] * nrhs + (size_t)rh * d.na;
+  const double* hb = hbase + hb_off[mi] * nrhs + (size_t)rh * d.nb;
   for (int i = threadIdx.x; i < m3; i += blockDim.x)
     rhs[i] = s[(size_t)rh * N + d.Ii[i]] - ha[d.a3[i]] + hb[d.b3[i]];
   __syncthreads();
   const double* Minv = d.W + d.m3 + d.me;
-  for (int i = wid; i < m3; i += 4) {
+  double* z = zbuf + z_off[mi] * nrhs + (size_t)rh * m3;
+  for (int rr = wid; rr < UROWS; rr += 4) {
+    const int i = r0 + rr;
+    if (i >= m3) break;
     const double* row = Minv + (size_t)i * d.ldw;
     double acc = 0.0;
     for (int j = lane; j < m3; j += 64) acc += row[j] * rhs[j];
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0) zs[i] = acc;
+    if (lane == 0) z[i] = acc;
   }
+}
+
+__global__ void __launch_bounds__(256) k_upward_h(const MergeDesc* __restrict__ descs,
+                                                  double* __restrict__ hbase,
+                                                  const long long* __restrict__ ha_off,
+                                                  const long long* __restrict__ hb_off,
+                                                  const long long* __restrict__ hp_off,
+                                                  const double* __restrict__ zbuf,
+                                                  const long long* __restrict__ z_off, int nrhs) {
+  extern __shared__ double zs[];
+  const int mi = blockIdx.y, rh = blockIdx.z;
+  const MergeDesc d = descs[mi];
+  const int r0 = blockIdx.x * UROWS;
+  if (r0 >= d.me) return;
+  const int m3 = d.m3, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const double* z = zbuf + z_off[mi] * nrhs + (size_t)rh * m3;
+  for (int i = threadIdx.x; i < m3; i += blockDim.x) zs[i] = z[i];
   __syncthreads();
-  double* z = zbuf + z_off[mi] * nrhs + (size_t)rh * m3;
-  for (int i = threadIdx.x; i < m3; i += blockDim.x) z[i] = zs[i];
-  double* hp = hpar + hp_off[mi] * nrhs + (size_t)rh * me;
-  for (int r = wid; r < me; r += 4) {
+  const double* ha = hbase + ha_off[mi] * nrhs + (size_t)rh * d.na;
+  const double* hb = hbase + hb_off[mi] * nrhs + (size_t)rh * d.nb;
+  double* hp = hbase + hp_off[mi] * nrhs + (size_t)rh * d.me;
+  for (int rr = wid; rr < UROWS; rr += 4) {
+    const int r = r0 + rr;
+    if (r >= d.me) break;
     const double* Qr = d.Q + (size_t)r * m3;
     double acc = 0.0;
     for (int j = lane; j < m3; j += 64) acc += Qr[j] * zs[j];
@@ -360,14 +382,17 @@ __global__ void __launch_bounds__(256) k_upward(const MergeDesc* __restrict__ de
   }
 }
 
-void upward_level(const MergeDesc* d_desc, int nmerge, int m3_max, const double* s, int N,
-                  const double* hchild, const long long* ha_off, const long long* hb_off,
-                  double* hpar, const long long* hp_off, double* zbuf, const long long* z_off,
-                  int nrhs, hipStream_t st) {
-  size_t shm = 2 * (size_t)m3_max * sizeof(double);
-  ProfScope ps(PROF_UPWARD, st, 0, 0);
-  hipLaunchKernelGGL(k_upward, dim3(nmerge, nrhs), dim3(256), shm, st, d_desc, s, N, hchild,
-                     ha_off, hb_off, hpar, hp_off, zbuf, z_off, nrhs);
+void upward_level(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, const double* s,
+                  int N, double* hbase, const long long* ha_off, const long long* hb_off,
+                  const long long* hp_off, double* zbuf, const long long* z_off, int nrhs,
+                  double flops, hipStream_t st) {
+  HPS_REQUIRE((size_t)m3_max * sizeof(double) <= 96 * 1024, "upward pass: interface too long");
+  ProfScope ps(PROF_UPWARD, st, flops, 8.0 * flops / 2.0);
+  const size_t shm = (size_t)m3_max * sizeof(double);
+  hipLaunchKernelGGL(k_upward_z, dim3((m3_max + UROWS - 1) / UROWS, nmerge, nrhs), dim3(256), shm,
+                     st, d_desc, s, N, hbase, ha_off, hb_off, zbuf, z_off, nrhs);
+  hipLaunchKernelGGL(k_upward_h, dim3((me_max + UROWS - 1) / UROWS, nmerge, nrhs), dim3(256), shm,
+                     st, d_desc, hbase, ha_off, hb_off, hp_off, zbuf, z_off, nrhs);
 }
 
 // ---------------------------------------------------------------------------
@@ -443,7 +468,9 @@ void ops_init() {
                               96 * 1024));
   HPS_HIP(hipFuncSetAttribute((const void*)k_downward_z,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
-  HPS_HIP(hipFuncSetAttribute((const void*)k_upward, hipFuncAttributeMaxDynamicSharedMemorySize,
+  HPS_HIP(hipFuncSetAttribute((const void*)k_upward_z, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              96 * 1024));
+  HPS_HIP(hipFuncSetAttribute((const void*)k_upward_h, hipFuncAttributeMaxDynamicSharedMemorySize,
                               96 * 1024));
   done = true;
 }

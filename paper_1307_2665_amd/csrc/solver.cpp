@@ -451,8 +451,10 @@ static void upward_all(hps_op* op, const double* src, int nrhs, double* h, doubl
   for (int d = (int)op->levels.size() - 1; d >= 0; --d) {
     const LevelPlan& L = op->levels[d];
     if (L.h.empty()) continue;
-    upward_level(L.d, (int)L.h.size(), L.m3_max, src, op->tree.N, h, L.dha, L.dhb, h, L.dhp, z,
-                 L.dzo, nrhs, s);
+    double fl = 0;
+    for (const MergeDesc& m : L.h) fl += 2.0 * nrhs * ((double)m.m3 * m.m3 + (double)m.me * m.m3);
+    upward_level(L.d, (int)L.h.size(), L.m3_max, L.me_max, src, op->tree.N, h, L.dha, L.dhb,
+                 L.dhp, z, L.dzo, nrhs, fl, s);
   }
 }
 
