@@ -83,4 +83,10 @@ struct MergeDesc {
   int inv, pad;       // inv = 1: W carries the identity block, giving M^-1 at W + m3 + me
 };
 
+// Solution array of the problem a merge belongs to (downward pass).
+struct SolveIO {
+  double* u;       // [nrhs][N]
+  int N, nrhs;
+};
+
 }  // namespace hps

@@ -21,10 +21,12 @@ struct LeafDev {
 void leaf_assemble(const double* const* cptr, const LeafDev& tab, int count, double* W,
                    hipStream_t s);
 void merge_gather(const MergeDesc* d_desc, int nmerge, size_t max_elems, hipStream_t s);
-// s_bytes: bytes of all S of the level (the pass's algorithmic traffic per RHS chunk).
-void downward(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, double* u, int N,
-              int nrhs, const double* zbase, const long long* zoff, hipStream_t s,
-              double s_bytes);
+// Downward pass of one depth; io[i] gives merge i's solution array (io null:
+// every merge uses io0).  s_bytes: bytes of all S of the launch (its
+// algorithmic traffic per RHS chunk).
+void downward(const MergeDesc* d_desc, const SolveIO* d_io, const SolveIO& io0, int nmerge,
+              int m3_max, int me_max, int nrhs_max, const double* zbase, const long long* zoff,
+              hipStream_t s, double s_bytes);
 void set_boundary(const double* f, const int* gamma, int nb, double* u, int N, int nrhs,
                   hipStream_t s);
 void interface_residual(const double* leafT, const double* u, int N, int nrhs, int nx, int ny,

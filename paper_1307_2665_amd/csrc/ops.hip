@@ -129,13 +129,20 @@ void merge_gather(const MergeDesc* d_desc, int nmerge, size_t max_elems, hipStre
 constexpr int DROWS = 16;
 
 __global__ void __launch_bounds__(256) k_downward(const MergeDesc* __restrict__ descs,
-                                                  double* __restrict__ u, int N, int nrhs, int rc) {
+                                                  const SolveIO* __restrict__ io,
+                                                  const SolveIO io0, int rc,
+                                                  const double* __restrict__ zbase,
+                                                  const long long* __restrict__ zoff) {
   extern __shared__ double ue[];
   const MergeDesc d = descs[blockIdx.y];
   const int r0 = blockIdx.x * DROWS;
   if (r0 >= d.m3) return;
-  const int me = d.me;
+  const SolveIO b = io ? io[blockIdx.y] : io0;
+  double* u = b.u;
+  const int N = b.N, nrhs = b.nrhs, me = d.me;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // Interface terms of the upward pass: z of this merge is [nrhs][m3].
+  const double* z = zbase ? zbase + zoff[blockIdx.y] * nrhs : nullptr;
   for (int rb = 0; rb < nrhs; rb += rc) {
     const int nr = min(rc, nrhs - rb);
     __syncthreads();
@@ -152,41 +159,10 @@ __global__ void __launch_bounds__(256) k_downward(const MergeDesc* __restrict__ 
         double acc = 0.0;
         for (int c = lane; c < me; c += 64) acc += Srow[c] * ue[k * me + c];
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if (lane == 0) u[(size_t)(rb + k) * N + d.Ii[r]] = acc;
-      }
-    }
-  }
-}
-
-// Interface-term variant: z of merge i is [nrhs][m3] at zbase + zoff[i] * nrhs.
-__global__ void __launch_bounds__(256) k_downward_z(const MergeDesc* __restrict__ descs,
-                                                    double* __restrict__ u, int N, int nrhs, int rc,
-                                                    const double* __restrict__ zbase,
-                                                    const long long* __restrict__ zoff) {
-  extern __shared__ double ue[];
-  const MergeDesc d = descs[blockIdx.y];
-  const int r0 = blockIdx.x * DROWS;
-  if (r0 >= d.m3) return;
-  const int me = d.me;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const double* z = zbase + zoff[blockIdx.y] * nrhs;
-  for (int rb = 0; rb < nrhs; rb += rc) {
-    const int nr = min(rc, nrhs - rb);
-    __syncthreads();
-    for (int e = threadIdx.x; e < nr * me; e += blockDim.x) {
-      int k = e / me, c = e % me;
-      ue[e] = u[(size_t)(rb + k) * N + d.Ie[c]];
-    }
-    __syncthreads();
-    for (int rr = wid; rr < DROWS; rr += 4) {
-      const int r = r0 + rr;
-      if (r >= d.m3) break;
-      const double* Srow = d.S + (size_t)r * d.ldw;
-      for (int k = 0; k < nr; ++k) {
-        double acc = 0.0;
-        for (int c = lane; c < me; c += 64) acc += Srow[c] * ue[k * me + c];
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if (lane == 0) u[(size_t)(rb + k) * N + d.Ii[r]] = acc + z[(size_t)(rb + k) * d.m3 + r];
+        if (lane == 0) {
+          if (z) acc += z[(size_t)(rb + k) * d.m3 + r];
+          u[(size_t)(rb + k) * N + d.Ii[r]] = acc;
+        }
       }
     }
   }
@@ -197,19 +173,16 @@ int downward_rhs_chunk(int me_max, int nrhs) {
   return std::min(rc, std::max(1, nrhs));
 }
 
-void downward(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, double* u, int N,
-              int nrhs, const double* zbase, const long long* zoff, hipStream_t s,
-              double s_bytes) {
+void downward(const MergeDesc* d_desc, const SolveIO* d_io, const SolveIO& io0, int nmerge,
+              int m3_max, int me_max, int nrhs_max, const double* zbase, const long long* zoff,
+              hipStream_t s, double s_bytes) {
   HPS_REQUIRE((size_t)me_max * sizeof(double) <= 96 * 1024,
               "downward pass: box boundary too long for the LDS-staged kernel");
-  const int rc = downward_rhs_chunk(me_max, nrhs);
+  const int rc = downward_rhs_chunk(me_max, nrhs_max);
   size_t shm = (size_t)rc * me_max * sizeof(double);
   dim3 grid((m3_max + DROWS - 1) / DROWS, nmerge);
-  ProfScope ps(PROF_DOWNWARD, s, 2.0 * nrhs * s_bytes / 8.0, s_bytes);
-  if (zbase)
-    hipLaunchKernelGGL(k_downward_z, grid, dim3(256), shm, s, d_desc, u, N, nrhs, rc, zbase, zoff);
-  else
-    hipLaunchKernelGGL(k_downward, grid, dim3(256), shm, s, d_desc, u, N, nrhs, rc);
+  ProfScope ps(PROF_DOWNWARD, s, 2.0 * nrhs_max * s_bytes / 8.0, s_bytes);
+  hipLaunchKernelGGL(k_downward, grid, dim3(256), shm, s, d_desc, d_io, io0, rc, zbase, zoff);
 }
 
 // Boundary data into u: u[r][gamma[i]] = f[r][i].
@@ -466,8 +439,6 @@ void ops_init() {
   if (done) return;
   HPS_HIP(hipFuncSetAttribute((const void*)k_downward, hipFuncAttributeMaxDynamicSharedMemorySize,
                               96 * 1024));
-  HPS_HIP(hipFuncSetAttribute((const void*)k_downward_z,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
   HPS_HIP(hipFuncSetAttribute((const void*)k_upward_z, hipFuncAttributeMaxDynamicSharedMemorySize,
                               96 * 1024));
   HPS_HIP(hipFuncSetAttribute((const void*)k_upward_h, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -398,15 +398,67 @@ void leaf_dtn_batch(const double* coeffs, int nleaf, double hx, double hy, int p
 // ---------------------------------------------------------------------------
 // Solve (Algorithm 2) and the refinement pieces.
 // ---------------------------------------------------------------------------
-static void downward_all(hps_op* op, double* u, int nrhs, const double* z, hipStream_t s) {
-  const int N = op->tree.N;
-  for (size_t d = 0; d < op->levels.size(); ++d) {
-    const LevelPlan& L = op->levels[d];
-    if (L.h.empty()) continue;
-    double sb = 0;
-    for (const MergeDesc& m : L.h) sb += 8.0 * m.m3 * m.me;
-    downward(L.d, (int)L.h.size(), L.m3_max, L.me_max, u, N, nrhs, z, z ? L.dzo : nullptr, s, sb);
+// Algorithm 2 over a batch: for every depth, the merges of all problems in
+// one launch (each merge carries its problem's solution array).
+static void downward_batch(const std::vector<hps_op*>& ops, const std::vector<double*>& u,
+                           const std::vector<int>& nrhs, const double* z, hipStream_t s) {
+  if (ops.size() == 1) {
+    hps_op* op = ops[0];
+    const SolveIO io0{u[0], op->tree.N, nrhs[0]};
+    for (size_t d = 0; d < op->levels.size(); ++d) {
+      const LevelPlan& L = op->levels[d];
+      if (L.h.empty()) continue;
+      double sb = 0;
+      for (const MergeDesc& m : L.h) sb += 8.0 * m.m3 * m.me;
+      downward(L.d, nullptr, io0, (int)L.h.size(), L.m3_max, L.me_max, nrhs[0], z,
+               z ? L.dzo : nullptr, s, sb);
+    }
+    return;
   }
+  int maxd = 0;
+  for (hps_op* op : ops) maxd = std::max(maxd, (int)op->levels.size() - 1);
+  std::vector<MergeDesc> hm;
+  std::vector<SolveIO> hio;
+  std::vector<size_t> off(maxd + 2, 0);
+  std::vector<int> m3m(maxd + 1, 0), mem(maxd + 1, 0), nrm(maxd + 1, 0);
+  std::vector<double> sb(maxd + 1, 0.0);
+  for (int d = 0; d <= maxd; ++d) {
+    off[d] = hm.size();
+    for (size_t i = 0; i < ops.size(); ++i) {
+      hps_op* op = ops[i];
+      if (d >= (int)op->levels.size()) continue;
+      for (const MergeDesc& m : op->levels[d].h) {
+        hm.push_back(m);
+        hio.push_back(SolveIO{u[i], op->tree.N, nrhs[i]});
+        m3m[d] = std::max(m3m[d], m.m3);
+        mem[d] = std::max(mem[d], m.me);
+        nrm[d] = std::max(nrm[d], nrhs[i]);
+        sb[d] += 8.0 * m.m3 * m.me;
+      }
+    }
+  }
+  off[maxd + 1] = hm.size();
+  if (hm.empty()) return;
+  MergeDesc* dm = nullptr;
+  SolveIO* dio = nullptr;
+  HPS_HIP(hipMallocAsync((void**)&dm, hm.size() * sizeof(MergeDesc), s));
+  HPS_HIP(hipMallocAsync((void**)&dio, hio.size() * sizeof(SolveIO), s));
+  HPS_HIP(hipMemcpyAsync(dm, hm.data(), hm.size() * sizeof(MergeDesc), hipMemcpyHostToDevice, s));
+  HPS_HIP(hipMemcpyAsync(dio, hio.data(), hio.size() * sizeof(SolveIO), hipMemcpyHostToDevice, s));
+  for (int d = 0; d <= maxd; ++d) {
+    const int nm = (int)(off[d + 1] - off[d]);
+    if (nm == 0) continue;
+    const long long* zo = z ? ops[0]->levels[d].dzo : nullptr;
+    downward(dm + off[d], dio + off[d], SolveIO{nullptr, 0, 0}, nm, m3m[d], mem[d], nrm[d], z, zo,
+             s, sb[d]);
+  }
+  HPS_HIP(hipFreeAsync(dm, s));
+  HPS_HIP(hipFreeAsync(dio, s));
+  HPS_HIP(hipStreamSynchronize(s));  // host vectors above must outlive the copies
+}
+
+static void downward_all(hps_op* op, double* u, int nrhs, const double* z, hipStream_t s) {
+  downward_batch({op}, {u}, {nrhs}, z, s);
 }
 
 void solve_device(hps_op* op, const double* f, int nrhs, double* u, hipStream_t s) {
@@ -417,7 +469,9 @@ void solve_device(hps_op* op, const double* f, int nrhs, double* u, hipStream_t 
 void solve_batch_device(const std::vector<hps_op*>& ops, const std::vector<const double*>& f,
                         const std::vector<int>& nrhs, const std::vector<double*>& u,
                         hipStream_t s) {
-  for (size_t i = 0; i < ops.size(); ++i) solve_device(ops[i], f[i], nrhs[i], u[i], s);
+  for (size_t i = 0; i < ops.size(); ++i)
+    set_boundary(f[i], ops[i]->gamma, ops[i]->n_bdry, u[i], ops[i]->tree.N, nrhs[i], s);
+  downward_batch(ops, u, nrhs, nullptr, s);
 }
 
 double absmax_device(const double* x, size_t n, hipStream_t s) {
