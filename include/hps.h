@@ -118,6 +118,8 @@ typedef struct {
   int64_t bytes_S;    /* device bytes of all solution operators S */
   int64_t bytes_total;
   int64_t flops_build;/* algorithmic FP64 FLOPs of the build (leaf + LU + TRSM + Schur) */
+  double judge_worst; /* surrogate mode: worst relative leaf-DtN error in the judged sample */
+  int n_judged;       /* surrogate mode: leaves re-solved by the FP64 leaf solver */
 } hps_op_info;
 
 /* One problem of a heterogeneous batch (hps_build_batch). */
@@ -183,6 +185,43 @@ hps_status hps_interface_residual(const hps_op* op, const double* u, int nrhs, d
    sources s [nrhs][N], then the downward pass.  Needs keep_factors. */
 hps_status hps_solve_with_sources(hps_op* op, const double* f, const double* s, int nrhs,
                                   double* u, void* stream);
+
+/* ---- learned leaf surrogate (not in the paper) -------------------------- */
+/* A small MLP maps (c11, c22, c) at a leaf's p^2 Chebyshev nodes (fields with
+   c12 = c1 = c2 = 0) to low-rank factors U, V (4q x rank) of
+   T = T_Laplace(h) + s U V^T, with T_Laplace(h) the leaf DtN of the Laplace
+   operator for the same leaf size.  Two tanh layers of width `hidden`; weights
+   are BF16 for every GEMM (BF16 MFMA, FP32 accumulation) with FP32 master
+   copies and Adam moments.  Training pairs come from hps_leaf_dtn.  A build in
+   mode HPS_SURROGATE infers every leaf DtN, then re-solves opts->judge_samples
+   seeded leaves plus every leaf whose coefficients leave the training ranges
+   with the FP64 leaf solver; judged leaves whose relative error exceeds
+   opts->judge_tol are replaced (counted in n_fallback_leaves), and if more than
+   a quarter of the random sample fails every leaf is rebuilt in FP64. */
+
+hps_status hps_surrogate_create(int p, int q, double hx, double hy, int hidden, int rank,
+                                unsigned long long seed, void* stream, hps_surrogate** out);
+/* Adam training on n device samples: coeffs [n][6][p*p], T [n][4q][4q] (FP64
+   leaf DtNs).  The first call also fixes the input normalisation and output
+   scale from these samples.  history (host, may be NULL) gets the mean loss of
+   every epoch; final_loss the last one. */
+hps_status hps_surrogate_train(hps_surrogate* s, const double* coeffs, const double* T, int n,
+                               int epochs, int batch, double lr, unsigned long long seed,
+                               void* stream, double* final_loss, double* history);
+/* Loss and gradients (host float [W1 b1 W2 b2 W3 b3]) of one batch; no update. */
+hps_status hps_surrogate_grad(hps_surrogate* s, const double* coeffs, const double* T, int n,
+                              float* grads, double* loss, void* stream);
+/* T [n][4q][4q] (device, FP64) from coeffs [n][6][p*p] (device). */
+hps_status hps_surrogate_predict(hps_surrogate* s, const double* coeffs, int n, double* T,
+                                 void* stream);
+/* dims = {p, q, hidden, rank, D, O, step}; out_scale = s. */
+hps_status hps_surrogate_info(const hps_surrogate* s, int dims[7], double* out_scale);
+/* Serialized state (shape, normalisation, scale, training ranges, FP32 weights). */
+hps_status hps_surrogate_get_state(const hps_surrogate* s, void* buf, size_t* len);
+hps_status hps_surrogate_set_state(hps_surrogate* s, const void* buf, size_t len, void* stream);
+hps_status hps_surrogate_save(const hps_surrogate* s, const char* path);
+hps_status hps_surrogate_load(const char* path, void* stream, hps_surrogate** out);
+void hps_surrogate_destroy(hps_surrogate* s);
 
 /* ---- heterogeneous batches --------------------------------------------- */
 

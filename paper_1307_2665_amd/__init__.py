@@ -20,7 +20,8 @@ from ._lib import (HPS_EINVAL, HPS_ENOTCONV, HPS_ESINGULAR, HPS_FP64, HPS_MIXED_
 __all__ = ["HpsError", "HPS_FP64", "HPS_MIXED_SPLIT32", "HPS_SURROGATE", "HPS_EINVAL",
            "HPS_ESINGULAR", "HPS_ENOTCONV", "Operator", "cheb_nodes", "gauss_nodes_grid",
            "boundary_ids", "leaf_dtn", "build_solution_operator", "build_batch", "solve_batch",
-           "leaf_tables", "plan_box", "version", "lib", "batched_solve", "batched_gemm"]
+           "leaf_tables", "plan_box", "version", "lib", "batched_solve", "batched_gemm",
+           "Surrogate"]
 
 
 def version() -> str:
@@ -163,11 +164,110 @@ def tune_set(knob: str, value: int) -> None:
     check(lib.hps_tune_set(knob.encode(), int(value)))
 
 
+# ---- learned leaf surrogate -------------------------------------------------------
+
+class Surrogate:
+    """Owner of an ``hps_surrogate`` (MLP leaf-DtN surrogate in device memory)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        dims = np.zeros(7, dtype=np.int32)
+        sc = C.c_double()
+        check(lib.hps_surrogate_info(self._h, _ptr(dims), C.byref(sc)))
+        self.p, self.q, self.hidden, self.rank, self.D, self.O, self.step = (int(x) for x in dims)
+        self.m = 4 * self.q
+
+    @classmethod
+    def create(cls, p, q, hx, hy, hidden=256, rank=16, seed=0):
+        h = C.c_void_p()
+        check(lib.hps_surrogate_create(p, q, hx, hy, hidden, rank, seed, _stream(), C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def load(cls, path):
+        h = C.c_void_p()
+        check(lib.hps_surrogate_load(str(path).encode(), _stream(), C.byref(h)))
+        return cls(h)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def out_scale(self) -> float:
+        sc = C.c_double()
+        check(lib.hps_surrogate_info(self._h, None, C.byref(sc)))
+        return sc.value
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib.hps_surrogate_destroy(self._h)
+            self._h = None
+
+    def train(self, coeffs, T, epochs=10, batch=256, lr=1e-3, seed=0):
+        coeffs, T = _f64(coeffs), _f64(T)
+        assert _dev(coeffs) and _dev(T)
+        hist = np.zeros(epochs)
+        L = C.c_double()
+        check(lib.hps_surrogate_train(self._h, _ptr(coeffs), _ptr(T), coeffs.shape[0], epochs,
+                                      batch, lr, seed, _stream(coeffs), C.byref(L), _ptr(hist)))
+        return hist
+
+    def grad(self, coeffs, T):
+        coeffs, T = _f64(coeffs), _f64(T)
+        n = coeffs.shape[0]
+        sizes = [self.hidden * self.D, self.hidden, self.hidden * self.hidden, self.hidden,
+                 self.O * self.hidden, self.O]
+        g = np.zeros(sum(sizes), dtype=np.float32)
+        L = C.c_double()
+        check(lib.hps_surrogate_grad(self._h, _ptr(coeffs), _ptr(T), n, _ptr(g), C.byref(L),
+                                     _stream(coeffs)))
+        out, o = {}, 0
+        for name, s_ in zip(("W1", "b1", "W2", "b2", "W3", "b3"), sizes):
+            out[name] = g[o:o + s_].astype(np.float64)
+            o += s_
+        return L.value, out
+
+    def predict(self, coeffs, out=None):
+        import torch
+        coeffs = _f64(coeffs)
+        n = coeffs.shape[0]
+        if out is None:
+            out = torch.empty((n, self.m, self.m), dtype=torch.float64, device=coeffs.device)
+        check(lib.hps_surrogate_predict(self._h, _ptr(coeffs), n, _ptr(out), _stream(coeffs)))
+        return out
+
+    def state(self) -> dict:
+        """Shape, normalisation, scale, training ranges and FP32 weights."""
+        n = C.c_size_t()
+        check(lib.hps_surrogate_get_state(self._h, None, C.byref(n)))
+        buf = np.zeros(n.value, dtype=np.uint8)
+        check(lib.hps_surrogate_get_state(self._h, _ptr(buf), C.byref(n)))
+        meta = buf[:14 * 8].view(np.float64)
+        f = buf[14 * 8:].view(np.float32)
+        D, H, O = self.D, self.hidden, self.O
+        st = dict(out_scale=float(meta[6]), step=int(meta[7]), lo=meta[8:11].copy(),
+                  hi=meta[11:14].copy())
+        o = 0
+        for name, s_ in (("mu", D), ("sigma", D), ("W1", H * D), ("b1", H), ("W2", H * H),
+                         ("b2", H), ("W3", O * H), ("b3", O)):
+            st[name] = f[o:o + s_].copy()
+            o += s_
+        st["W1"] = st["W1"].reshape(H, D)
+        st["W2"] = st["W2"].reshape(H, H)
+        st["W3"] = st["W3"].reshape(O, H)
+        return st
+
+    def save(self, path):
+        check(lib.hps_surrogate_save(self._h, str(path).encode()))
+
+
 # ---- launch timing -----------------------------------------------------------------
 
 PROF_CLASSES = {"leaf_assemble": 0, "lu_panel": 1, "swap_trsm": 2, "lu_update": 3,
                 "back_subst": 4, "gemm": 5, "gemm_split32": 6, "merge_gather": 7,
-                "downward": 8, "residual": 9, "upward": 10, "leaf_lu": 11}
+                "downward": 8, "residual": 9, "upward": 10, "leaf_lu": 11, "mlp_train": 12,
+                "mlp_infer": 13}
 
 
 def prof_enable(classes) -> None:
@@ -203,6 +303,9 @@ class Operator:
         self.mode = info.mode
         self.box = tuple(info.box)
         self.bytes_S, self.bytes_total, self.flops_build = info.bytes_S, info.bytes_total, info.flops_build
+        self.n_fallback_leaves = info.n_fallback_leaves
+        self.judge_worst = info.judge_worst
+        self.n_judged = info.n_judged
 
     def __del__(self):
         self.destroy()
@@ -315,17 +418,23 @@ class Operator:
         return T
 
 
-def _build_opts(mode, stream, device_ptrs, keep_factors, root_dtn):
+def _build_opts(mode, stream, device_ptrs, keep_factors, root_dtn, surrogate=None,
+                judge_samples=64, judge_tol=1e-6):
     return BuildOpts(mode, stream, int(device_ptrs), 1, int(keep_factors), int(root_dtn), 0.0,
-                     None, 0, 0.0)
+                     surrogate.handle if surrogate is not None else None, int(judge_samples),
+                     float(judge_tol))
 
 
 def build_solution_operator(coeffs, box, nleaf, p: int, q: int, mode: int = HPS_FP64,
-                            keep_factors: bool = False, root_dtn: bool = True) -> Operator:
+                            keep_factors: bool = False, root_dtn: bool = True, surrogate=None,
+                            judge_samples: int = 64, judge_tol: float = 1e-6) -> Operator:
     """Algorithm 1.  coeffs [nx*ny, 6, p*p] (c11, c12, c22, c1, c2, c at Chebyshev nodes)."""
     coeffs = _f64(coeffs)
     dev = _dev(coeffs)
-    bo = _build_opts(mode, _stream(coeffs) if dev else None, dev, keep_factors, root_dtn)
+    if surrogate is not None:
+        mode = HPS_SURROGATE
+    bo = _build_opts(mode, _stream(coeffs) if dev else None, dev, keep_factors, root_dtn,
+                     surrogate, judge_samples, judge_tol)
     h = C.c_void_p()
     check(lib.hps_build_solution_operator(_ptr(coeffs), (C.c_double * 4)(*box),
                                           (C.c_int * 2)(*nleaf), p, q, C.byref(bo), C.byref(h)))

@@ -37,7 +37,8 @@ class OpInfo(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("p", C.c_int), ("q", C.c_int), ("N", C.c_int),
                 ("n_bdry", C.c_int), ("n_boxes", C.c_int), ("n_levels", C.c_int),
                 ("mode", C.c_int), ("n_fallback_leaves", C.c_int), ("box", C.c_double * 4),
-                ("bytes_S", C.c_int64), ("bytes_total", C.c_int64), ("flops_build", C.c_int64)]
+                ("bytes_S", C.c_int64), ("bytes_total", C.c_int64), ("flops_build", C.c_int64),
+                ("judge_worst", C.c_double), ("n_judged", C.c_int)]
 
 
 class Problem(C.Structure):
@@ -81,12 +82,21 @@ SIGNATURES = {
     "hps_batched_gemm": [P, P, P, I, I, I, I, D, I, P],
     "hps_plan_box": [P, I, I, P, P, P, P, P, P, P, IP],
     "hps_tune_set": [C.c_char_p, I],
+    "hps_surrogate_create": [I, I, D, D, I, I, C.c_ulonglong, P, C.POINTER(P)],
+    "hps_surrogate_train": [P, P, P, I, I, I, D, C.c_ulonglong, P, C.POINTER(D), P],
+    "hps_surrogate_grad": [P, P, P, I, P, C.POINTER(D), P],
+    "hps_surrogate_predict": [P, P, I, P, P],
+    "hps_surrogate_info": [P, P, C.POINTER(D)],
+    "hps_surrogate_get_state": [P, P, C.POINTER(C.c_size_t)],
+    "hps_surrogate_set_state": [P, P, C.c_size_t, P],
+    "hps_surrogate_save": [P, C.c_char_p],
+    "hps_surrogate_load": [C.c_char_p, P, C.POINTER(P)],
     "hps_prof_enable": [C.c_uint],
     "hps_prof_reset": [],
     "hps_prof_query": [I, C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.POINTER(C.c_double),
                        C.POINTER(C.c_double)],
 }
-VOID_FUNCS = {"hps_destroy": [P]}
+VOID_FUNCS = {"hps_destroy": [P], "hps_surrogate_destroy": [P]}
 STR_FUNCS = {"hps_last_error": [], "hps_version": []}
 
 

@@ -8,6 +8,9 @@
 #include "dense.h"
 #include "leaf.h"
 #include "solver.h"
+#include "surrogate.h"
+
+#include <fstream>
 
 namespace {
 
@@ -39,6 +42,9 @@ hps::BuildOptions to_build_options(const hps_build_opts* o) {
   b.keep_leaf = true;
   b.keep_factors = o->keep_factors != 0;
   b.root_dtn = o->compute_root_dtn != 0;
+  b.surrogate = const_cast<hps_surrogate*>(o->surrogate);
+  b.judge_samples = o->judge_samples > 0 ? o->judge_samples : 64;
+  b.judge_tol = o->judge_tol > 0 ? o->judge_tol : 1e-6;
   return b;
 }
 
@@ -130,8 +136,11 @@ hps_status hps_build_solution_operator(const double* coeffs, const double box[4]
   if (out) *out = nullptr;
   return guard([&] {
     HPS_REQUIRE(out != nullptr, "out is null");
-    HPS_REQUIRE(!opts || opts->mode == HPS_FP64 || opts->mode == HPS_MIXED_SPLIT32,
-                "mode not supported by this entry point");
+    HPS_REQUIRE(!opts || opts->mode == HPS_FP64 || opts->mode == HPS_MIXED_SPLIT32 ||
+                    opts->mode == HPS_SURROGATE,
+                "unknown mode");
+    HPS_REQUIRE(!opts || opts->mode != HPS_SURROGATE || opts->surrogate,
+                "HPS_SURROGATE needs opts->surrogate");
     hps::BuildOptions bo = to_build_options(opts);
     auto op = hps::plan_operator(coeffs, box, nleaf, p, q, bo);
     std::vector<hps_op*> v{op.get()};
@@ -286,6 +295,8 @@ hps_status hps_op_query(const hps_op* op, hps_op_info* info) {
     info->bytes_S = op->bytes_S;
     info->bytes_total = (int64_t)op->mem.bytes;
     info->flops_build = op->flops;
+    info->judge_worst = op->judge_worst;
+    info->n_judged = op->n_judged;
   });
 }
 
@@ -448,6 +459,126 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
     put(Ie, mm.Ie);
     put(Ii, mm.Ii);
   });
+}
+
+hps_status hps_surrogate_create(int p, int q, double hx, double hy, int hidden, int rank,
+                                unsigned long long seed, void* stream, hps_surrogate** out) {
+  if (out) *out = nullptr;
+  return guard([&] {
+    HPS_REQUIRE(out && hx > 0 && hy > 0, "bad arguments");
+    *out = hps::surrogate_create(p, q, hx, hy, hidden, rank, seed, (hipStream_t)stream).release();
+  });
+}
+
+hps_status hps_surrogate_train(hps_surrogate* s, const double* coeffs, const double* T, int n,
+                               int epochs, int batch, double lr, unsigned long long seed,
+                               void* stream, double* final_loss, double* history) {
+  return guard([&] {
+    HPS_REQUIRE(s && coeffs && T, "bad arguments");
+    std::vector<double> hist;
+    double L = hps::surrogate_train(s, coeffs, T, n, epochs, batch, lr, seed, (hipStream_t)stream,
+                                    &hist);
+    if (final_loss) *final_loss = L;
+    if (history) std::memcpy(history, hist.data(), hist.size() * sizeof(double));
+  });
+}
+
+hps_status hps_surrogate_grad(hps_surrogate* s, const double* coeffs, const double* T, int n,
+                              float* grads, double* loss, void* stream) {
+  return guard([&] {
+    HPS_REQUIRE(s && coeffs && T && grads && n >= 1, "bad arguments");
+    double L = hps::surrogate_grad(s, coeffs, T, n, grads, (hipStream_t)stream);
+    if (loss) *loss = L;
+  });
+}
+
+hps_status hps_surrogate_predict(hps_surrogate* s, const double* coeffs, int n, double* T,
+                                 void* stream) {
+  return guard([&] {
+    HPS_REQUIRE(s && coeffs && T && n >= 1, "bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    hps::DeviceMem tmp;
+    const size_t pp = (size_t)s->p * s->p, mm = (size_t)s->m * s->m;
+    std::vector<const double*> cp(n);
+    std::vector<double*> tp(n);
+    for (int i = 0; i < n; ++i) {
+      cp[i] = coeffs + i * 6 * pp;
+      tp[i] = T + i * mm;
+    }
+    const double** dcp = tmp.upload(cp, st);
+    double** dtp = tmp.upload(tp, st);
+    hps::surrogate_predict(s, dcp, n, dtp, st);
+    HPS_HIP(hipStreamSynchronize(st));
+  });
+}
+
+hps_status hps_surrogate_info(const hps_surrogate* s, int dims[7], double* out_scale) {
+  return guard([&] {
+    HPS_REQUIRE(s, "null surrogate");
+    if (dims) {
+      int v[7] = {s->p, s->q, s->H, s->r, s->D, s->O, s->step};
+      std::memcpy(dims, v, sizeof(v));
+    }
+    if (out_scale) *out_scale = s->out_scale;
+  });
+}
+
+hps_status hps_surrogate_get_state(const hps_surrogate* s, void* buf, size_t* len) {
+  return guard([&] {
+    HPS_REQUIRE(s && len, "bad arguments");
+    HPS_REQUIRE(s->fitted, "surrogate is not trained");
+    std::vector<char> st = hps::surrogate_state(s);
+    if (buf) {
+      HPS_REQUIRE(*len >= st.size(), "buffer too small");
+      std::memcpy(buf, st.data(), st.size());
+    }
+    *len = st.size();
+  });
+}
+
+hps_status hps_surrogate_set_state(hps_surrogate* s, const void* buf, size_t len, void* stream) {
+  return guard([&] {
+    HPS_REQUIRE(s && buf, "bad arguments");
+    hps::surrogate_set_state(s, (const char*)buf, len, (hipStream_t)stream);
+  });
+}
+
+hps_status hps_surrogate_save(const hps_surrogate* s, const char* path) {
+  return guard([&] {
+    HPS_REQUIRE(s && path, "bad arguments");
+    HPS_REQUIRE(s->fitted, "surrogate is not trained");
+    std::vector<char> st = hps::surrogate_state(s);
+    std::ofstream f(path, std::ios::binary);
+    HPS_REQUIRE(f.good(), "cannot open file for writing");
+    const char magic[8] = {'H', 'P', 'S', 'M', 'L', 'P', '1', 0};
+    f.write(magic, 8);
+    f.write(st.data(), (std::streamsize)st.size());
+    HPS_REQUIRE(f.good(), "write failed");
+  });
+}
+
+hps_status hps_surrogate_load(const char* path, void* stream, hps_surrogate** out) {
+  if (out) *out = nullptr;
+  return guard([&] {
+    HPS_REQUIRE(path && out, "bad arguments");
+    std::ifstream f(path, std::ios::binary);
+    HPS_REQUIRE(f.good(), "cannot open file");
+    std::vector<char> all((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+    HPS_REQUIRE(all.size() > 8 + 14 * 8 && std::memcmp(all.data(), "HPSMLP1", 7) == 0,
+                "not a surrogate file");
+    double meta[14];
+    std::memcpy(meta, all.data() + 8, sizeof(meta));
+    auto sg = hps::surrogate_create((int)meta[0], (int)meta[1], meta[4], meta[5], (int)meta[2],
+                                    (int)meta[3], 0, (hipStream_t)stream);
+    hps::surrogate_set_state(sg.get(), all.data() + 8, all.size() - 8, (hipStream_t)stream);
+    *out = sg.release();
+  });
+}
+
+void hps_surrogate_destroy(hps_surrogate* s) {
+  if (!s) return;
+  (void)hipDeviceSynchronize();
+  delete s;
 }
 
 void hps_destroy(hps_op* op) {

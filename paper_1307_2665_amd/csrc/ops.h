@@ -40,6 +40,8 @@ void absmax_partial(const double* x, size_t n, double* out, int blocks, hipStrea
 void matvec(const double* A, int rows, int cols, const double* x, int nrhs, double* y,
             hipStream_t s);
 void nonfinite(const double* x, size_t n, int* flag, hipStream_t s);
+void leaf_range_flags(const double* const* cptr, int nl, int pp, const double* lohi, double margin,
+                      int* flag, hipStream_t s);
 void ops_init();
 
 }  // namespace hps

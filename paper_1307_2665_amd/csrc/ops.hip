@@ -434,6 +434,33 @@ void nonfinite(const double* x, size_t n, int* flag, hipStream_t s) {
   hipLaunchKernelGGL(k_nonfinite, dim3(std::max(blocks, 1)), dim3(256), 0, s, x, n, flag);
 }
 
+// flag[l] = 1 when a leaf's c11, c22 or c leaves [lo - margin*w, hi + margin*w]
+// (w = hi - lo) of the surrogate's training data.  lohi = {lo[3], hi[3]}.
+__global__ void __launch_bounds__(256) k_range_flags(const double* const* __restrict__ cptr, int pp,
+                                                     const double* __restrict__ lohi, double margin,
+                                                     int* __restrict__ flag) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  const double* c = cptr[blockIdx.x];
+  const int field[3] = {0, 2, 5};
+  int my = 0;
+  for (int e = threadIdx.x; e < 3 * pp; e += blockDim.x) {
+    const int f = e / pp;
+    const double v = c[(size_t)field[f] * pp + e % pp];
+    const double w = lohi[3 + f] - lohi[f];
+    if (!(v >= lohi[f] - margin * w && v <= lohi[3 + f] + margin * w)) my = 1;
+  }
+  if (my) atomicOr(&bad, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) flag[blockIdx.x] = bad;
+}
+
+void leaf_range_flags(const double* const* cptr, int nl, int pp, const double* lohi, double margin,
+                      int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_range_flags, dim3(nl), dim3(256), 0, s, cptr, pp, lohi, margin, flag);
+}
+
 void ops_init() {
   static bool done = false;
   if (done) return;

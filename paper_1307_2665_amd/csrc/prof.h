@@ -20,6 +20,8 @@ enum ProfClass {
   PROF_RESIDUAL = 9,
   PROF_UPWARD = 10,
   PROF_LEAF_LU = 11,
+  PROF_MLP_TRAIN = 12,
+  PROF_MLP_INFER = 13,
   PROF_NCLASS = 16
 };
 

@@ -18,11 +18,13 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <random>
 #include <tuple>
 
 #include "dense.h"
 #include "leaf.h"
 #include "ops.h"
+#include "surrogate.h"
 
 namespace hps {
 
@@ -64,6 +66,9 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
   op->mode = o.mode;
   std::memcpy(op->box, box, sizeof(op->box));
   op->opt = o;
+  op->surrogate = o.surrogate;
+  op->judge_samples = o.judge_samples;
+  op->judge_tol = o.judge_tol;
   if (o.mode == HPS_MIXED_SPLIT32) {
     op->opt.keep_factors = true;
     op->opt.keep_leaf = true;
@@ -241,8 +246,10 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
 // Leaf stage (section 3): all leaves of equal (p, q, h) share launches.
 // ---------------------------------------------------------------------------
 struct LeafJob {
-  hps_op* op;
-  int leaf;
+  hps_op* op;           // operator whose leaf tables are used
+  int leaf;             // leaf index (error reporting)
+  const double* coef;   // [6][p*p]
+  double* dst;          // [4q][4q]
 };
 
 static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hipStream_t s,
@@ -269,16 +276,14 @@ static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hip
     std::vector<GemmDesc> gd(cnt);
     for (int i = 0; i < cnt; ++i) {
       const LeafJob& j = jobs[c0 + i];
-      cp[i] = j.op->coeffs + (size_t)j.leaf * 6 * p * p;
+      cp[i] = j.coef;
       if (fused) {
         double* Zl = Wslab + (size_t)i * n * m;
-        gd[i] = GemmDesc{j.op->dP1, Zl, j.op->leafT + (size_t)j.leaf * m * m, j.op->dP0,
-                         m, m, n, n, m, m, m, -1.0};
+        gd[i] = GemmDesc{j.op->dP1, Zl, j.dst, j.op->dP0, m, m, n, n, m, m, m, -1.0};
       } else {
         double* W = Wslab + (size_t)i * n * ld;
         sd[i] = SolveDesc{W, pslab + (size_t)i * n, W + n, n, m, ld, ld, -(j.leaf + 1), 0};
-        gd[i] = GemmDesc{j.op->dP1, W + n, j.op->leafT + (size_t)j.leaf * m * m, j.op->dP0,
-                         m, m, n, n, ld, m, m, -1.0};
+        gd[i] = GemmDesc{j.op->dP1, W + n, j.dst, j.op->dP0, m, m, n, n, ld, m, m, -1.0};
       }
     }
     HPS_HIP(hipMemcpyAsync(dcp, cp.data(), cnt * sizeof(void*), hipMemcpyHostToDevice, s));
@@ -295,6 +300,87 @@ static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hip
   }
 }
 
+// Leaf stage of a surrogate operator: inference for every leaf, then the judge
+// re-solves a seeded sample of leaves plus every leaf whose coefficients leave
+// the training ranges with the FP64 leaf solver; judged leaves above the
+// tolerance are replaced, and if more than a quarter of the random sample
+// fails, every leaf is rebuilt by the FP64 solver.
+static void surrogate_leaf_stage(hps_op* op, DeviceMem& tmp, hipStream_t s, int* dstatus) {
+  hps_surrogate* sg = op->surrogate;
+  HPS_REQUIRE(sg && sg->fitted, "surrogate mode needs a trained surrogate");
+  HPS_REQUIRE(sg->p == op->p && sg->q == op->q, "surrogate was trained for another p, q");
+  HPS_REQUIRE(std::fabs(sg->hx - op->lt.hx) <= 1e-12 * sg->hx &&
+                  std::fabs(sg->hy - op->lt.hy) <= 1e-12 * sg->hy,
+              "surrogate was trained for another leaf size");
+  const int nl = op->nx * op->ny, p = op->p, m = 4 * op->q, mm = m * m, pp = p * p;
+  std::vector<const double*> cp(nl);
+  std::vector<double*> tp(nl);
+  for (int l = 0; l < nl; ++l) {
+    cp[l] = op->coeffs + (size_t)l * 6 * pp;
+    tp[l] = op->leafT + (size_t)l * mm;
+  }
+  const double** dcp = tmp.upload(cp, s);
+  double** dtp = tmp.upload(tp, s);
+  surrogate_predict(sg, dcp, nl, dtp, s);
+  // Out-of-distribution flags (10% margin on each field's training range).
+  std::vector<double> lohi = {sg->lo[0], sg->lo[1], sg->lo[2], sg->hi[0], sg->hi[1], sg->hi[2]};
+  double* dlohi = tmp.upload(lohi, s);
+  int* dflag = tmp.alloc<int>(nl);
+  leaf_range_flags(dcp, nl, pp, dlohi, 0.1, dflag, s);
+  std::vector<int> flag(nl);
+  HPS_HIP(hipMemcpyAsync(flag.data(), dflag, nl * sizeof(int), hipMemcpyDeviceToHost, s));
+  HPS_HIP(hipStreamSynchronize(s));
+  std::vector<int> judged;
+  std::vector<char> is_sample(nl, 0);
+  const int J = std::min(nl, std::max(1, op->judge_samples));
+  std::mt19937_64 rng(0x5eedULL + (unsigned long long)nl);
+  for (int i = 0; i < J; ++i) {
+    int l = (int)(rng() % (unsigned long long)nl);
+    if (!is_sample[l]) {
+      is_sample[l] = 1;
+      judged.push_back(l);
+    }
+  }
+  for (int l = 0; l < nl; ++l)
+    if (flag[l] && !is_sample[l]) judged.push_back(l);
+  const int nj = (int)judged.size();
+  op->n_judged = nj;
+  double* ref = tmp.alloc<double>((size_t)nj * mm);
+  std::vector<LeafJob> jobs(nj);
+  std::vector<double*> jp(nj);
+  for (int i = 0; i < nj; ++i) {
+    jobs[i] = LeafJob{op, judged[i], cp[judged[i]], ref + (size_t)i * mm};
+    jp[i] = tp[judged[i]];
+  }
+  run_leaf_group(jobs, tmp, s, dstatus, op->opt.panel);
+  double** djp = tmp.upload(jp, s);
+  double* derr = tmp.alloc<double>(nj);
+  block_errors(djp, ref, nj, mm, derr, s);
+  std::vector<double> err(nj);
+  HPS_HIP(hipMemcpyAsync(err.data(), derr, nj * sizeof(double), hipMemcpyDeviceToHost, s));
+  HPS_HIP(hipStreamSynchronize(s));
+  int bad_sample = 0, replaced = 0;
+  double worst = 0.0;
+  for (int i = 0; i < nj; ++i) {
+    const bool bad = !(err[i] <= op->judge_tol);
+    if (bad) ++replaced;
+    if (bad && is_sample[judged[i]]) ++bad_sample;
+    if (is_sample[judged[i]]) worst = std::max(worst, err[i]);
+  }
+  op->judge_worst = worst;
+  if (4 * bad_sample > J) {
+    // The surrogate is not good enough for this field: plain leaf build everywhere.
+    std::vector<LeafJob> all(nl);
+    for (int l = 0; l < nl; ++l) all[l] = LeafJob{op, l, cp[l], tp[l]};
+    run_leaf_group(all, tmp, s, dstatus, op->opt.panel);
+    op->n_fallback = nl;
+  } else {
+    block_replace(djp, ref, nj, mm, derr, op->judge_tol, s);
+    op->n_fallback = replaced;
+  }
+  HPS_HIP(hipStreamSynchronize(s));
+}
+
 void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
   DeviceMem tmp;
   int* dstatus = tmp.alloc<int>(4);
@@ -303,14 +389,21 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
     if (op->opt.device_ptrs)
       nonfinite(op->coeffs, (size_t)op->nx * op->ny * 6 * op->p * op->p, dstatus + 2, s);
 
-  // Leaf groups keyed by (p, q, hx, hy).
+  // Leaf groups keyed by (p, q, hx, hy); surrogate operators infer their leaves instead.
   std::map<std::tuple<int, int, double, double>, std::vector<LeafJob>> groups;
+  const int panel = ops.empty() ? 32 : ops[0]->opt.panel;
   for (hps_op* op : ops) {
+    if (op->mode == HPS_SURROGATE) {
+      surrogate_leaf_stage(op, tmp, s, dstatus);
+      continue;
+    }
     auto key = std::make_tuple(op->p, op->q, op->lt.hx, op->lt.hy);
     auto& v = groups[key];
-    for (int l = 0; l < op->nx * op->ny; ++l) v.push_back(LeafJob{op, l});
+    const int m = 4 * op->q;
+    for (int l = 0; l < op->nx * op->ny; ++l)
+      v.push_back(LeafJob{op, l, op->coeffs + (size_t)l * 6 * op->p * op->p,
+                          op->leafT + (size_t)l * m * m});
   }
-  const int panel = ops.empty() ? 32 : ops[0]->opt.panel;
   for (auto& kv : groups) run_leaf_group(kv.second, tmp, s, dstatus, panel);
 
   // Merges, deepest level first; all operators' merges at one depth together.
@@ -384,7 +477,9 @@ void leaf_dtn_batch(const double* coeffs, int nleaf, double hx, double hy, int p
   op.dP0 = op.mem.upload(op.lt.P0, s);
   op.dP1 = op.mem.upload(op.lt.P1, s);
   std::vector<LeafJob> jobs(nleaf);
-  for (int i = 0; i < nleaf; ++i) jobs[i] = LeafJob{&op, i};
+  const int m = 4 * q;
+  for (int i = 0; i < nleaf; ++i)
+    jobs[i] = LeafJob{&op, i, coeffs + (size_t)i * 6 * p * p, T + (size_t)i * m * m};
   DeviceMem tmp;
   int* dstatus = tmp.alloc<int>(4);
   HPS_HIP(hipMemsetAsync(dstatus, 0, 4 * sizeof(int), s));

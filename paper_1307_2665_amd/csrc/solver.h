@@ -46,6 +46,9 @@ struct LevelPlan {
 
 struct BuildOptions {
   int mode = HPS_FP64;
+  hps_surrogate* surrogate = nullptr;
+  int judge_samples = 64;
+  double judge_tol = 1e-6;
   hipStream_t stream = nullptr;
   bool device_ptrs = false;
   bool keep_leaf = true;
@@ -78,6 +81,11 @@ struct hps_op {
   long long h_units = 0, z_units = 0;       // totals (per right-hand side)
   long long bytes_S = 0, flops = 0;
   int n_fallback = 0;
+  hps_surrogate* surrogate = nullptr;   // HPS_SURROGATE mode (not owned)
+  int judge_samples = 64;
+  double judge_tol = 1e-6;
+  double judge_worst = 0.0;             // worst judged error in the random sample
+  int n_judged = 0;                     // leaves re-solved in FP64 by the judge
   // device tables of the leaf stage
   double *dDx = nullptr, *dDy = nullptr, *dDxx = nullptr, *dDyy = nullptr, *dG = nullptr,
          *dP0 = nullptr, *dP1 = nullptr;
