@@ -270,6 +270,20 @@ PROF_CLASSES = {"leaf_assemble": 0, "lu_panel": 1, "swap_trsm": 2, "lu_update": 
                 "mlp_infer": 13}
 
 
+def mem_trim() -> int:
+    """Frees the device blocks the library keeps cached for reuse; returns the bytes freed."""
+    f = C.c_size_t()
+    check(lib.hps_mem_trim(C.byref(f)))
+    return f.value
+
+
+def mem_stats() -> dict:
+    """Bytes of device memory the library holds cached (free) and in use."""
+    a, b = C.c_size_t(), C.c_size_t()
+    check(lib.hps_mem_stats(C.byref(a), C.byref(b)))
+    return dict(cached=a.value, in_use=b.value)
+
+
 def prof_enable(classes) -> None:
     mask = 0
     for c in classes:

@@ -91,6 +91,8 @@ SIGNATURES = {
     "hps_surrogate_set_state": [P, P, C.c_size_t, P],
     "hps_surrogate_save": [P, C.c_char_p],
     "hps_surrogate_load": [C.c_char_p, P, C.POINTER(P)],
+    "hps_mem_trim": [C.POINTER(C.c_size_t)],
+    "hps_mem_stats": [C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)],
     "hps_prof_enable": [C.c_uint],
     "hps_prof_reset": [],
     "hps_prof_query": [I, C.POINTER(C.c_double), C.POINTER(C.c_longlong), C.POINTER(C.c_double),

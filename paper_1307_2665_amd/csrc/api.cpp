@@ -53,7 +53,7 @@ struct Staged {
   double* d = nullptr;
   bool owned = false;
   ~Staged() {
-    if (owned && d) (void)hipFree(d);
+    if (owned && d) hps::pool_release(d);
   }
 };
 
@@ -62,7 +62,7 @@ void stage_in(Staged& st, const double* p, size_t n, bool device, hipStream_t s)
     st.d = const_cast<double*>(p);
     return;
   }
-  HPS_HIP(hipMalloc((void**)&st.d, std::max<size_t>(n, 1) * sizeof(double)));
+  st.d = (double*)hps::pool_alloc(std::max<size_t>(n, 1) * sizeof(double));
   st.owned = true;
   if (n) HPS_HIP(hipMemcpyAsync(st.d, p, n * sizeof(double), hipMemcpyHostToDevice, s));
 }
@@ -76,6 +76,17 @@ void stage_out(const Staged& st, double* p, size_t n, bool device, hipStream_t s
 }  // namespace
 
 extern "C" {
+
+hps_status hps_mem_trim(size_t* freed) {
+  return guard([&] {
+    const size_t f = hps::pool_trim();
+    if (freed) *freed = f;
+  });
+}
+
+hps_status hps_mem_stats(size_t* cached, size_t* in_use) {
+  return guard([&] { hps::pool_stats(cached, in_use); });
+}
 
 const char* hps_last_error(void) { return g_err.c_str(); }
 const char* hps_version(void) { return "hps-mi355x 0.1 (gfx950)"; }
@@ -170,10 +181,10 @@ hps_status hps_build_batch(const hps_problem* probs, int nprob, const hps_build_
 hps_status hps_gauss_nodes(const hps_op* op, double* xy, int* N) {
   return guard([&] {
     HPS_REQUIRE(op, "null operator");
-    if (N) *N = op->tree.N;
+    if (N) *N = op->tree().N;
     if (xy) {
       std::vector<double> v;
-      hps::gauss_node_xy(op->tree, op->box, v);
+      hps::gauss_node_xy(op->tree(), op->box, v);
       std::memcpy(xy, v.data(), v.size() * sizeof(double));
     }
   });
@@ -186,8 +197,8 @@ hps_status hps_boundary_nodes(const hps_op* op, double* xy, int* n_bdry) {
     if (xy) {
       std::vector<double> v;
       std::vector<int> ids;
-      hps::gauss_node_xy(op->tree, op->box, v);
-      hps::box_boundary(op->tree, 0, op->nx, 0, op->ny, ids);
+      hps::gauss_node_xy(op->tree(), op->box, v);
+      hps::box_boundary(op->tree(), 0, op->nx, 0, op->ny, ids);
       for (size_t i = 0; i < ids.size(); ++i) {
         xy[2 * i] = v[2 * (size_t)ids[i]];
         xy[2 * i + 1] = v[2 * (size_t)ids[i] + 1];
@@ -202,7 +213,7 @@ hps_status hps_solve(hps_op* op, const double* f, int nrhs, double* u, const hps
     HPS_REQUIRE(op && f && u && nrhs >= 1, "bad arguments");
     hipStream_t s = opts ? (hipStream_t)opts->stream : nullptr;
     const bool dev = opts && opts->device_ptrs;
-    const size_t nf = (size_t)op->n_bdry * nrhs, nu = (size_t)op->tree.N * nrhs;
+    const size_t nf = (size_t)op->n_bdry * nrhs, nu = (size_t)op->tree().N * nrhs;
     if (!dev)
       for (size_t i = 0; i < nf; ++i) HPS_REQUIRE(std::isfinite(f[i]), "non-finite boundary data");
     Staged F, U;
@@ -210,7 +221,7 @@ hps_status hps_solve(hps_op* op, const double* f, int nrhs, double* u, const hps
     if (dev) {
       U.d = u;
     } else {
-      HPS_HIP(hipMalloc((void**)&U.d, nu * sizeof(double)));
+      U.d = (double*)hps::pool_alloc(nu * sizeof(double));
       U.owned = true;
     }
     if (info) std::memset(info, 0, sizeof(*info));
@@ -251,7 +262,7 @@ hps_status hps_root_dtn_apply(const hps_op* op, const double* f, int nrhs, doubl
     if (dev) {
       V.d = v;
     } else {
-      HPS_HIP(hipMalloc((void**)&V.d, n * sizeof(double)));
+      V.d = (double*)hps::pool_alloc(n * sizeof(double));
       V.owned = true;
     }
     hps::root_apply_device(op, F.d, nrhs, V.d, s);
@@ -285,10 +296,10 @@ hps_status hps_op_query(const hps_op* op, hps_op_info* info) {
     info->ny = op->ny;
     info->p = op->p;
     info->q = op->q;
-    info->N = op->tree.N;
+    info->N = op->tree().N;
     info->n_bdry = op->n_bdry;
-    info->n_boxes = (int)op->tree.boxes.size();
-    info->n_levels = op->tree.depth + 1;
+    info->n_boxes = (int)op->tree().boxes.size();
+    info->n_levels = op->tree().depth + 1;
     info->mode = op->mode;
     info->n_fallback_leaves = op->n_fallback;
     std::memcpy(info->box, op->box, sizeof(info->box));
@@ -302,8 +313,8 @@ hps_status hps_op_query(const hps_op* op, hps_op_info* info) {
 
 hps_status hps_box(const hps_op* op, int box, int rec[8]) {
   return guard([&] {
-    HPS_REQUIRE(op && rec && box >= 0 && box < (int)op->tree.boxes.size(), "bad arguments");
-    const hps::BoxRec& b = op->tree.boxes[box];
+    HPS_REQUIRE(op && rec && box >= 0 && box < (int)op->tree().boxes.size(), "bad arguments");
+    const hps::BoxRec& b = op->tree().boxes[box];
     int v[8] = {b.i0, b.i1, b.j0, b.j1, b.level, b.parent, b.ca, b.cb};
     std::memcpy(rec, v, sizeof(v));
   });
@@ -311,7 +322,7 @@ hps_status hps_box(const hps_op* op, int box, int rec[8]) {
 
 hps_status hps_export_S(const hps_op* op, int box, double* S, int* rows, int* cols) {
   return guard([&] {
-    HPS_REQUIRE(op && box >= 0 && box < (int)op->tree.boxes.size(), "bad arguments");
+    HPS_REQUIRE(op && box >= 0 && box < (int)op->tree().boxes.size(), "bad arguments");
     int lv = op->merge_level[box];
     HPS_REQUIRE(lv >= 0, "box is a leaf");
     const hps::MergeDesc& d = op->levels[lv].h[op->merge_index[box]];

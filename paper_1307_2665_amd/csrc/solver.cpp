@@ -17,7 +17,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
+#include <mutex>
 #include <random>
 #include <tuple>
 
@@ -29,12 +31,11 @@
 namespace hps {
 
 DeviceMem::~DeviceMem() {
-  for (void* p : ptrs) (void)hipFree(p);
+  for (void* p : ptrs) pool_release(p);
 }
 
 void* DeviceMem::raw(size_t b) {
-  void* p = nullptr;
-  HPS_HIP(hipMalloc(&p, b));
+  void* p = pool_alloc(b);
   ptrs.push_back(p);
   bytes += b;
   return p;
@@ -46,6 +47,128 @@ static void init_runtime() {
 }
 
 static inline int bdry_size(const BoxRec& b, int q) { return 2 * q * ((b.i1 - b.i0) + (b.j1 - b.j0)); }
+
+// ---------------------------------------------------------------------------
+// Plans: everything a build needs that depends only on the shape of the
+// problem (section 2 tree, section 4 index maps, section 3.2 leaf tables).
+// They are computed once per shape and device and shared by every operator
+// of that shape, so repeated builds (coefficient sweeps) skip the host work.
+// ---------------------------------------------------------------------------
+namespace {
+
+template <class P>
+struct PlanCache {
+  std::mutex mu;
+  std::map<std::vector<long long>, std::pair<unsigned long long, std::shared_ptr<const P>>> items;
+  unsigned long long tick = 0;
+  static constexpr size_t kMax = 16;
+  std::shared_ptr<const P> get(const std::vector<long long>& key,
+                               const std::function<std::shared_ptr<P>()>& make) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      auto it = items.find(key);
+      if (it != items.end()) {
+        it->second.first = ++tick;
+        return it->second.second;
+      }
+    }
+    std::shared_ptr<const P> p = make();
+    std::lock_guard<std::mutex> lk(mu);
+    if (items.size() >= kMax) {  // evict the least recently used plan
+      auto old = items.begin();
+      for (auto it = items.begin(); it != items.end(); ++it)
+        if (it->second.first < old->second.first) old = it;
+      items.erase(old);
+    }
+    items[key] = {++tick, p};
+    return p;
+  }
+};
+
+long long bits(double x) {
+  long long b;
+  std::memcpy(&b, &x, sizeof(b));
+  return b;
+}
+
+int current_device() {
+  int d = 0;
+  HPS_HIP(hipGetDevice(&d));
+  return d;
+}
+
+}  // namespace
+
+std::shared_ptr<const LeafPlan> leaf_plan(int p, int q, double hx, double hy, hipStream_t s) {
+  static PlanCache<LeafPlan> cache;
+  const std::vector<long long> key{current_device(), p, q, bits(hx), bits(hy)};
+  return cache.get(key, [&] {
+    auto lp = std::make_shared<LeafPlan>();
+    lp->lt = make_leaf_tables(p, q, hx, hy);
+    const LeafTables& lt = lp->lt;
+    lp->dDx = lp->mem.upload(lt.Dx, s);
+    lp->dDy = lp->mem.upload(lt.Dy, s);
+    lp->dDxx = lp->mem.upload(lt.Dxx, s);
+    lp->dDyy = lp->mem.upload(lt.Dyy, s);
+    lp->dG = lp->mem.upload(lt.G, s);
+    lp->dP0 = lp->mem.upload(lt.P0, s);
+    lp->dP1 = lp->mem.upload(lt.P1, s);
+    HPS_HIP(hipStreamSynchronize(s));  // the tables are read from other streams later
+    return lp;
+  });
+}
+
+static std::shared_ptr<const TreePlan> tree_plan(int nx, int ny, int p, int q, double hx, double hy,
+                                                 bool keep, hipStream_t s) {
+  static PlanCache<TreePlan> cache;
+  const std::vector<long long> key{current_device(), nx, ny, p, q, bits(hx), bits(hy), keep};
+  return cache.get(key, [&] {
+    auto tp = std::make_shared<TreePlan>();
+    tp->leaf = leaf_plan(p, q, hx, hy, s);
+    tp->tree = build_tree(nx, ny, q);
+    const Tree& t = tp->tree;
+    std::vector<int> ids;
+    box_boundary(t, 0, nx, 0, ny, ids);
+    tp->n_bdry = (int)ids.size();
+    const int nbox = (int)t.boxes.size();
+    std::vector<int> pool;
+    tp->levels.assign(t.depth + 1, {});
+    std::vector<long long> lvlT(t.depth + 1, 0);
+    for (int d = 0; d <= t.depth; ++d)
+      for (int b : t.parents_at_level[d]) {
+        const MergeMaps g = merge_maps(t, b);
+        HPS_REQUIRE(g.m3 <= max_solve_rows(), "merge interface too long for the dense solver");
+        MergeRec r{};
+        r.box = b;
+        r.pool_off = pool.size();
+        r.na = g.na;
+        r.nb = g.nb;
+        r.me = g.me;
+        r.m3 = g.m3;
+        r.Toff = lvlT[d];
+        lvlT[d] += (long long)g.me * g.me;
+        for (const auto* v : {&g.pmap, &g.a3, &g.b3, &g.Ie, &g.Ii}) pool.insert(pool.end(), v->begin(), v->end());
+        tp->levels[d].push_back(r);
+      }
+    tp->ar[0] = tp->ar[1] = 0;
+    for (int d = 0; d <= t.depth; ++d) tp->ar[d % 2] = std::max(tp->ar[d % 2], lvlT[d]);
+    tp->box_hoff.assign(nbox, 0);
+    long long hu = 0;
+    for (int b = 0; b < nbox; ++b) {
+      tp->box_hoff[b] = hu;
+      hu += bdry_size(t.boxes[b], q);
+    }
+    tp->h_units = hu;
+    // Pool of index maps followed by the boundary ids of the root.
+    tp->pool_host = std::move(pool);
+    tp->gamma_off = tp->pool_host.size();
+    tp->pool_host.insert(tp->pool_host.end(), ids.begin(), ids.end());
+    tp->dpool = tp->mem.upload(tp->pool_host, s);
+    tp->gamma = tp->dpool + tp->gamma_off;
+    HPS_HIP(hipStreamSynchronize(s));
+    return tp;
+  });
+}
 
 std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4], const int nleaf[2],
                                       int p, int q, const BuildOptions& o) {
@@ -75,11 +198,14 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
   }
   const int nx = op->nx, ny = op->ny, m = 4 * q;
   const size_t nl = (size_t)nx * ny;
-  op->tree = build_tree(nx, ny, q);
-  const Tree& t = op->tree;
   const double hx = (box[1] - box[0]) / nx, hy = (box[3] - box[2]) / ny;
-  op->lt = make_leaf_tables(p, q, hx, hy);
-  const LeafTables& lt = op->lt;
+  const bool keep = op->opt.keep_factors;
+  op->plan = tree_plan(nx, ny, p, q, hx, hy, keep, s);
+  const TreePlan& P = *op->plan;
+  const Tree& t = P.tree;
+  op->n_bdry = P.n_bdry;
+  op->gamma = P.gamma;
+  op->h_units = P.h_units;
 
   const size_t ncoef = nl * 6 * p * p;
   if (o.device_ptrs) {
@@ -91,54 +217,18 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
     HPS_HIP(hipMemcpyAsync(d, coeffs, ncoef * sizeof(double), hipMemcpyHostToDevice, s));
     op->coeffs = d;
   }
-  op->dDx = op->mem.upload(lt.Dx, s);
-  op->dDy = op->mem.upload(lt.Dy, s);
-  op->dDxx = op->mem.upload(lt.Dxx, s);
-  op->dDyy = op->mem.upload(lt.Dyy, s);
-  op->dG = op->mem.upload(lt.G, s);
-  op->dP0 = op->mem.upload(lt.P0, s);
-  op->dP1 = op->mem.upload(lt.P1, s);
   op->leafT = op->mem.alloc<double>(nl * m * m);
-
-  std::vector<int> ids;
-  box_boundary(t, 0, nx, 0, ny, ids);
-  op->n_bdry = (int)ids.size();
-  op->gamma = op->mem.upload(ids, s);
-
-  // ---- merges: maps, sizes, offsets --------------------------------------
-  const int nbox = (int)t.boxes.size();
-  std::vector<MergeMaps> mm(nbox);
-  std::vector<size_t> pool_off(nbox, 0);
-  std::vector<int> pool;
-  std::vector<long long> Toff(nbox, 0);
-  std::vector<long long> lvlT(t.depth + 1, 0);
-  for (int d = 0; d <= t.depth; ++d)
-    for (int b : t.parents_at_level[d]) {
-      mm[b] = merge_maps(t, b);
-      pool_off[b] = pool.size();
-      pool.insert(pool.end(), mm[b].pmap.begin(), mm[b].pmap.end());
-      pool.insert(pool.end(), mm[b].a3.begin(), mm[b].a3.end());
-      pool.insert(pool.end(), mm[b].b3.begin(), mm[b].b3.end());
-      pool.insert(pool.end(), mm[b].Ie.begin(), mm[b].Ie.end());
-      pool.insert(pool.end(), mm[b].Ii.begin(), mm[b].Ii.end());
-      Toff[b] = lvlT[d];
-      lvlT[d] += (long long)mm[b].me * mm[b].me;
-    }
-  int* dpool = op->mem.upload(pool, s);
 
   // W (augmented system, later S and M^-1) and pivots are kept for every merge;
   // Q is kept only when the upward pass is wanted, else one level of scratch.
-  const bool keep = op->opt.keep_factors;
   long long totW = 0, totQ = 0, totP = 0, maxQ = 0, totS = 0;
-  for (int d = 0; d <= t.depth; ++d) {
+  for (const auto& lv : P.levels) {
     long long lq = 0;
-    for (int b : t.parents_at_level[d]) {
-      const MergeMaps& g = mm[b];
-      HPS_REQUIRE(g.m3 <= max_solve_rows(), "merge interface too long for the dense solver");
-      totS += (long long)g.m3 * g.me;
-      totW += (long long)g.m3 * (g.m3 + g.me + (keep ? g.m3 : 0));
-      lq += (long long)g.me * g.m3;
-      totP += g.m3;
+    for (const MergeRec& r : lv) {
+      totS += (long long)r.m3 * r.me;
+      totW += (long long)r.m3 * (r.m3 + r.me + (keep ? r.m3 : 0));
+      lq += (long long)r.me * r.m3;
+      totP += r.m3;
     }
     totQ += lq;
     maxQ = std::max(maxQ, lq);
@@ -147,23 +237,13 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
   op->Wk = op->mem.alloc<double>(totW);
   op->Q = op->mem.alloc<double>(keep ? totQ : maxQ);
   op->piv = op->mem.alloc<int>(totP);
-  long long ar[2] = {0, 0};
-  for (int d = 0; d <= t.depth; ++d) ar[d % 2] = std::max(ar[d % 2], lvlT[d]);
-  op->arena[0] = op->mem.alloc<double>(ar[0]);
-  op->arena[1] = op->mem.alloc<double>(ar[1]);
-
-  op->box_hoff.assign(nbox, 0);
-  long long hu = 0;
-  for (int b = 0; b < nbox; ++b) {
-    op->box_hoff[b] = hu;
-    hu += bdry_size(t.boxes[b], q);
-  }
-  op->h_units = hu;
+  op->arena[0] = op->mem.alloc<double>(P.ar[0]);
+  op->arena[1] = op->mem.alloc<double>(P.ar[1]);
 
   // ---- descriptors ---------------------------------------------------------
   op->levels.assign(t.depth + 1, LevelPlan());
-  op->merge_level.assign(nbox, -1);
-  op->merge_index.assign(nbox, -1);
+  op->merge_level.assign(t.boxes.size(), -1);
+  op->merge_index.assign(t.boxes.size(), -1);
   long long oW = 0, oQ = 0, oP = 0, oz = 0;
   const int n_int = (p - 2) * (p - 2);
   long long flops = (long long)nl * ((2LL * n_int * n_int * n_int) / 3 + 2LL * n_int * n_int * m +
@@ -171,74 +251,107 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
   for (int d = 0; d <= t.depth; ++d) {
     LevelPlan& L = op->levels[d];
     if (!keep) oQ = 0;
-    for (int b : t.parents_at_level[d]) {
+    for (const MergeRec& r : P.levels[d]) {
+      const int b = r.box;
       const BoxRec& B = t.boxes[b];
-      const MergeMaps& g = mm[b];
       MergeDesc md{};
-      auto child_T = [&](int c) -> const double* {
-        const BoxRec& C = t.boxes[c];
-        if (C.ca < 0) return op->leafT + (size_t)(C.i0 + nx * C.j0) * m * m;
-        return op->arena[(d + 1) % 2] + Toff[c];
-      };
-      md.Ta = child_T(B.ca);
-      md.Tb = child_T(B.cb);
-      md.Tp = op->arena[d % 2] + Toff[b];
-      const int ldw = g.m3 + g.me + (keep ? g.m3 : 0);
+      // Ta, Tb are set below, once every parent DtN has its place.
+      md.Tp = op->arena[d % 2] + r.Toff;
+      const int ldw = r.m3 + r.me + (keep ? r.m3 : 0);
       md.W = op->Wk + oW;
-      md.S = md.W + g.m3;
+      md.S = md.W + r.m3;
       md.ldw = ldw;
       md.inv = keep ? 1 : 0;
       md.Q = op->Q + oQ;
       md.piv = op->piv + oP;
-      const int* base = dpool + pool_off[b];
+      const int* base = P.dpool + r.pool_off;
       md.pmap = base;
-      md.a3 = base + g.me;
-      md.b3 = base + g.me + g.m3;
-      md.Ie = base + g.me + 2 * g.m3;
-      md.Ii = base + 2 * g.me + 2 * g.m3;
-      md.na = g.na;
-      md.nb = g.nb;
-      md.me = g.me;
-      md.m3 = g.m3;
+      md.a3 = base + r.me;
+      md.b3 = base + r.me + r.m3;
+      md.Ie = base + r.me + 2 * r.m3;
+      md.Ii = base + 2 * r.me + 2 * r.m3;
+      md.na = r.na;
+      md.nb = r.nb;
+      md.me = r.me;
+      md.m3 = r.m3;
       md.box = b;
       op->merge_level[b] = d;
       op->merge_index[b] = (int)L.h.size();
       L.h.push_back(md);
-      SolveDesc sd{md.W, md.piv, md.W + g.m3, g.m3, ldw - g.m3, ldw, ldw, b, 0};
+      SolveDesc sd{md.W, md.piv, md.W + r.m3, r.m3, ldw - r.m3, ldw, ldw, b, 0};
       L.hs.push_back(sd);
       if (b != 0 || op->opt.root_dtn) {
-        GemmDesc gd{md.Q, md.S, md.Tp, nullptr, g.me, g.me, g.m3, g.m3, ldw, g.me, 0, 1.0};
+        GemmDesc gd{md.Q, md.S, md.Tp, nullptr, r.me, r.me, r.m3, r.m3, ldw, r.me, 0, 1.0};
         L.hg.push_back(gd);
       }
-      L.ha.push_back(op->box_hoff[B.ca]);
-      L.hb.push_back(op->box_hoff[B.cb]);
-      L.hp.push_back(op->box_hoff[b]);
+      L.ha.push_back(P.box_hoff[B.ca]);
+      L.hb.push_back(P.box_hoff[B.cb]);
+      L.hp.push_back(P.box_hoff[b]);
       L.zo.push_back(oz);
-      L.m3_max = std::max(L.m3_max, g.m3);
-      L.me_max = std::max(L.me_max, g.me);
-      L.gather_max = std::max(L.gather_max, (size_t)g.m3 * (g.m3 + g.me) + (size_t)g.me * g.m3 +
-                                                (size_t)g.me * g.me);
-      oW += (long long)g.m3 * ldw;
-      oQ += (long long)g.me * g.m3;
-      oP += g.m3;
-      oz += g.m3;
-      flops += (2LL * g.m3 * g.m3 * g.m3) / 3 + 2LL * g.m3 * g.m3 * g.me;
-      if (b != 0 || op->opt.root_dtn) flops += 2LL * g.me * g.me * g.m3;
-    }
-    if (!L.h.empty()) {
-      L.d = op->mem.upload(L.h, s);
-      L.ds = op->mem.upload(L.hs, s);
-      L.dg = op->mem.upload(L.hg, s);
-      L.dha = op->mem.upload(L.ha, s);
-      L.dhb = op->mem.upload(L.hb, s);
-      L.dhp = op->mem.upload(L.hp, s);
-      L.dzo = op->mem.upload(L.zo, s);
+      L.m3_max = std::max(L.m3_max, r.m3);
+      L.me_max = std::max(L.me_max, r.me);
+      L.gather_max = std::max(L.gather_max, (size_t)r.m3 * (r.m3 + r.me) + (size_t)r.me * r.m3 +
+                                                (size_t)r.me * r.me);
+      oW += (long long)r.m3 * ldw;
+      oQ += (long long)r.me * r.m3;
+      oP += r.m3;
+      oz += r.m3;
+      flops += (2LL * r.m3 * r.m3 * r.m3) / 3 + 2LL * r.m3 * r.m3 * r.me;
+      if (b != 0 || op->opt.root_dtn) flops += 2LL * r.me * r.me * r.m3;
     }
   }
+  // Children's DtNs: leaves in leafT, inner boxes in the arena of their depth.
+  for (int d = 0; d <= t.depth; ++d)
+    for (MergeDesc& md : op->levels[d].h) {
+      const BoxRec& B = t.boxes[md.box];
+      auto child_T = [&](int c) -> const double* {
+        const BoxRec& C = t.boxes[c];
+        if (C.ca < 0) return op->leafT + (size_t)(C.i0 + nx * C.j0) * m * m;
+        return op->levels[C.level].h[op->merge_index[c]].Tp;
+      };
+      md.Ta = child_T(B.ca);
+      md.Tb = child_T(B.cb);
+    }
   op->z_units = oz;
   op->flops = flops;
   op->rootT = (t.boxes[0].ca >= 0) ? op->arena[0] : op->leafT;
-  HPS_HIP(hipStreamSynchronize(s));  // host vectors above must outlive their copies
+
+  // One upload of every level's descriptors from a staging buffer the
+  // operator keeps (so no wait is needed here).
+  size_t total = 0;
+  auto reserve = [&](size_t bytes) {
+    const size_t o = total;
+    total += (bytes + 255) & ~size_t(255);
+    return o;
+  };
+  struct Off { size_t h, hs, hg, ha, hb, hp, zo; };
+  std::vector<Off> offs(op->levels.size());
+  for (size_t d = 0; d < op->levels.size(); ++d) {
+    const LevelPlan& L = op->levels[d];
+    if (L.h.empty()) continue;
+    offs[d] = Off{reserve(L.h.size() * sizeof(MergeDesc)), reserve(L.hs.size() * sizeof(SolveDesc)),
+                  reserve(L.hg.size() * sizeof(GemmDesc)), reserve(L.ha.size() * 8),
+                  reserve(L.hb.size() * 8), reserve(L.hp.size() * 8), reserve(L.zo.size() * 8)};
+  }
+  op->staging.assign(total, 0);
+  char* dbase = (char*)op->mem.raw(std::max<size_t>(total, 1));
+  for (size_t d = 0; d < op->levels.size(); ++d) {
+    LevelPlan& L = op->levels[d];
+    if (L.h.empty()) continue;
+    const Off& f = offs[d];
+    auto put = [&](size_t off, const void* src, size_t n) {
+      if (n) std::memcpy(op->staging.data() + off, src, n);
+      return dbase + off;
+    };
+    L.d = (MergeDesc*)put(f.h, L.h.data(), L.h.size() * sizeof(MergeDesc));
+    L.ds = (SolveDesc*)put(f.hs, L.hs.data(), L.hs.size() * sizeof(SolveDesc));
+    L.dg = (GemmDesc*)put(f.hg, L.hg.data(), L.hg.size() * sizeof(GemmDesc));
+    L.dha = (long long*)put(f.ha, L.ha.data(), L.ha.size() * 8);
+    L.dhb = (long long*)put(f.hb, L.hb.data(), L.hb.size() * 8);
+    L.dhp = (long long*)put(f.hp, L.hp.data(), L.hp.size() * 8);
+    L.dzo = (long long*)put(f.zo, L.zo.data(), L.zo.size() * 8);
+  }
+  if (total) HPS_HIP(hipMemcpyAsync(dbase, op->staging.data(), total, hipMemcpyHostToDevice, s));
   return op;
 }
 
@@ -246,7 +359,7 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
 // Leaf stage (section 3): all leaves of equal (p, q, h) share launches.
 // ---------------------------------------------------------------------------
 struct LeafJob {
-  hps_op* op;           // operator whose leaf tables are used
+  const LeafPlan* lp;   // leaf tables of the job's shape
   int leaf;             // leaf index (error reporting)
   const double* coef;   // [6][p*p]
   double* dst;          // [4q][4q]
@@ -254,9 +367,9 @@ struct LeafJob {
 
 static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hipStream_t s,
                            int* dstatus, int panel) {
-  hps_op* op0 = jobs[0].op;
-  const int p = op0->p, q = op0->q, n = (p - 2) * (p - 2), m = 4 * q, ld = n + m;
-  LeafDev tab{op0->dDx, op0->dDy, op0->dDxx, op0->dDyy, op0->dG, p, n, m, 0};
+  const LeafPlan& L0 = *jobs[0].lp;
+  const int p = L0.lt.p, q = L0.lt.q, n = (p - 2) * (p - 2), m = 4 * q, ld = n + m;
+  LeafDev tab{L0.dDx, L0.dDy, L0.dDxx, L0.dDyy, L0.dG, p, n, m, 0};
   const bool fused = leaf_lu_fits(n, m);
   // Fused path: only Z (n x m) per leaf; generic path: the augmented system.
   const size_t per = fused ? (size_t)n * m * sizeof(double)
@@ -279,11 +392,11 @@ static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hip
       cp[i] = j.coef;
       if (fused) {
         double* Zl = Wslab + (size_t)i * n * m;
-        gd[i] = GemmDesc{j.op->dP1, Zl, j.dst, j.op->dP0, m, m, n, n, m, m, m, -1.0};
+        gd[i] = GemmDesc{j.lp->dP1, Zl, j.dst, j.lp->dP0, m, m, n, n, m, m, m, -1.0};
       } else {
         double* W = Wslab + (size_t)i * n * ld;
         sd[i] = SolveDesc{W, pslab + (size_t)i * n, W + n, n, m, ld, ld, -(j.leaf + 1), 0};
-        gd[i] = GemmDesc{j.op->dP1, W + n, j.dst, j.op->dP0, m, m, n, n, ld, m, m, -1.0};
+        gd[i] = GemmDesc{j.lp->dP1, W + n, j.dst, j.lp->dP0, m, m, n, n, ld, m, m, -1.0};
       }
     }
     HPS_HIP(hipMemcpyAsync(dcp, cp.data(), cnt * sizeof(void*), hipMemcpyHostToDevice, s));
@@ -309,8 +422,8 @@ static void surrogate_leaf_stage(hps_op* op, DeviceMem& tmp, hipStream_t s, int*
   hps_surrogate* sg = op->surrogate;
   HPS_REQUIRE(sg && sg->fitted, "surrogate mode needs a trained surrogate");
   HPS_REQUIRE(sg->p == op->p && sg->q == op->q, "surrogate was trained for another p, q");
-  HPS_REQUIRE(std::fabs(sg->hx - op->lt.hx) <= 1e-12 * sg->hx &&
-                  std::fabs(sg->hy - op->lt.hy) <= 1e-12 * sg->hy,
+  HPS_REQUIRE(std::fabs(sg->hx - op->leaf().lt.hx) <= 1e-12 * sg->hx &&
+                  std::fabs(sg->hy - op->leaf().lt.hy) <= 1e-12 * sg->hy,
               "surrogate was trained for another leaf size");
   const int nl = op->nx * op->ny, p = op->p, m = 4 * op->q, mm = m * m, pp = p * p;
   std::vector<const double*> cp(nl);
@@ -349,7 +462,7 @@ static void surrogate_leaf_stage(hps_op* op, DeviceMem& tmp, hipStream_t s, int*
   std::vector<LeafJob> jobs(nj);
   std::vector<double*> jp(nj);
   for (int i = 0; i < nj; ++i) {
-    jobs[i] = LeafJob{op, judged[i], cp[judged[i]], ref + (size_t)i * mm};
+    jobs[i] = LeafJob{&op->leaf(), judged[i], cp[judged[i]], ref + (size_t)i * mm};
     jp[i] = tp[judged[i]];
   }
   run_leaf_group(jobs, tmp, s, dstatus, op->opt.panel);
@@ -371,7 +484,7 @@ static void surrogate_leaf_stage(hps_op* op, DeviceMem& tmp, hipStream_t s, int*
   if (4 * bad_sample > J) {
     // The surrogate is not good enough for this field: plain leaf build everywhere.
     std::vector<LeafJob> all(nl);
-    for (int l = 0; l < nl; ++l) all[l] = LeafJob{op, l, cp[l], tp[l]};
+    for (int l = 0; l < nl; ++l) all[l] = LeafJob{&op->leaf(), l, cp[l], tp[l]};
     run_leaf_group(all, tmp, s, dstatus, op->opt.panel);
     op->n_fallback = nl;
   } else {
@@ -397,11 +510,11 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
       surrogate_leaf_stage(op, tmp, s, dstatus);
       continue;
     }
-    auto key = std::make_tuple(op->p, op->q, op->lt.hx, op->lt.hy);
+    auto key = std::make_tuple(op->p, op->q, op->leaf().lt.hx, op->leaf().lt.hy);
     auto& v = groups[key];
     const int m = 4 * op->q;
     for (int l = 0; l < op->nx * op->ny; ++l)
-      v.push_back(LeafJob{op, l, op->coeffs + (size_t)l * 6 * op->p * op->p,
+      v.push_back(LeafJob{&op->leaf(), l, op->coeffs + (size_t)l * 6 * op->p * op->p,
                           op->leafT + (size_t)l * m * m});
   }
   for (auto& kv : groups) run_leaf_group(kv.second, tmp, s, dstatus, panel);
@@ -463,23 +576,11 @@ void leaf_dtn_batch(const double* coeffs, int nleaf, double hx, double hy, int p
                     hipStream_t s) {
   HPS_REQUIRE(p >= 4 && p <= 24 && q >= 1 && q <= p && nleaf >= 1, "bad leaf batch arguments");
   init_runtime();
-  hps_op op;
-  op.p = p;
-  op.q = q;
-  op.lt = make_leaf_tables(p, q, hx, hy);
-  op.coeffs = coeffs;
-  op.leafT = T;
-  op.dDx = op.mem.upload(op.lt.Dx, s);
-  op.dDy = op.mem.upload(op.lt.Dy, s);
-  op.dDxx = op.mem.upload(op.lt.Dxx, s);
-  op.dDyy = op.mem.upload(op.lt.Dyy, s);
-  op.dG = op.mem.upload(op.lt.G, s);
-  op.dP0 = op.mem.upload(op.lt.P0, s);
-  op.dP1 = op.mem.upload(op.lt.P1, s);
+  std::shared_ptr<const LeafPlan> lp = leaf_plan(p, q, hx, hy, s);
   std::vector<LeafJob> jobs(nleaf);
   const int m = 4 * q;
   for (int i = 0; i < nleaf; ++i)
-    jobs[i] = LeafJob{&op, i, coeffs + (size_t)i * 6 * p * p, T + (size_t)i * m * m};
+    jobs[i] = LeafJob{lp.get(), i, coeffs + (size_t)i * 6 * p * p, T + (size_t)i * m * m};
   DeviceMem tmp;
   int* dstatus = tmp.alloc<int>(4);
   HPS_HIP(hipMemsetAsync(dstatus, 0, 4 * sizeof(int), s));
@@ -499,7 +600,7 @@ static void downward_batch(const std::vector<hps_op*>& ops, const std::vector<do
                            const std::vector<int>& nrhs, const double* z, hipStream_t s) {
   if (ops.size() == 1) {
     hps_op* op = ops[0];
-    const SolveIO io0{u[0], op->tree.N, nrhs[0]};
+    const SolveIO io0{u[0], op->tree().N, nrhs[0]};
     for (size_t d = 0; d < op->levels.size(); ++d) {
       const LevelPlan& L = op->levels[d];
       if (L.h.empty()) continue;
@@ -524,7 +625,7 @@ static void downward_batch(const std::vector<hps_op*>& ops, const std::vector<do
       if (d >= (int)op->levels.size()) continue;
       for (const MergeDesc& m : op->levels[d].h) {
         hm.push_back(m);
-        hio.push_back(SolveIO{u[i], op->tree.N, nrhs[i]});
+        hio.push_back(SolveIO{u[i], op->tree().N, nrhs[i]});
         m3m[d] = std::max(m3m[d], m.m3);
         mem[d] = std::max(mem[d], m.me);
         nrm[d] = std::max(nrm[d], nrhs[i]);
@@ -557,7 +658,7 @@ static void downward_all(hps_op* op, double* u, int nrhs, const double* z, hipSt
 }
 
 void solve_device(hps_op* op, const double* f, int nrhs, double* u, hipStream_t s) {
-  set_boundary(f, op->gamma, op->n_bdry, u, op->tree.N, nrhs, s);
+  set_boundary(f, op->gamma, op->n_bdry, u, op->tree().N, nrhs, s);
   downward_all(op, u, nrhs, nullptr, s);
 }
 
@@ -565,7 +666,7 @@ void solve_batch_device(const std::vector<hps_op*>& ops, const std::vector<const
                         const std::vector<int>& nrhs, const std::vector<double*>& u,
                         hipStream_t s) {
   for (size_t i = 0; i < ops.size(); ++i)
-    set_boundary(f[i], ops[i]->gamma, ops[i]->n_bdry, u[i], ops[i]->tree.N, nrhs[i], s);
+    set_boundary(f[i], ops[i]->gamma, ops[i]->n_bdry, u[i], ops[i]->tree().N, nrhs[i], s);
   downward_batch(ops, u, nrhs, nullptr, s);
 }
 
@@ -588,7 +689,7 @@ void residual_device(const hps_op* op, const double* u, int nrhs, double* r, hip
   const int nl = op->nx * op->ny, m = 4 * op->q;
   double* v = nullptr;
   HPS_HIP(hipMallocAsync((void**)&v, (size_t)nrhs * nl * m * sizeof(double), s));
-  interface_residual(op->leafT, u, op->tree.N, nrhs, op->nx, op->ny, op->q, v, r, s);
+  interface_residual(op->leafT, u, op->tree().N, nrhs, op->nx, op->ny, op->q, v, r, s);
   HPS_HIP(hipFreeAsync(v, s));
 }
 
@@ -602,7 +703,7 @@ static void upward_all(hps_op* op, const double* src, int nrhs, double* h, doubl
     if (L.h.empty()) continue;
     double fl = 0;
     for (const MergeDesc& m : L.h) fl += 2.0 * nrhs * ((double)m.m3 * m.m3 + (double)m.me * m.m3);
-    upward_level(L.d, (int)L.h.size(), L.m3_max, L.me_max, src, op->tree.N, h, L.dha, L.dhb,
+    upward_level(L.d, (int)L.h.size(), L.m3_max, L.me_max, src, op->tree().N, h, L.dha, L.dhb,
                  L.dhp, z, L.dzo, nrhs, fl, s);
   }
 }
@@ -614,7 +715,7 @@ void solve_with_sources_device(hps_op* op, const double* f, const double* src, i
   HPS_HIP(hipMallocAsync((void**)&z, (size_t)std::max<long long>(1, op->z_units) * nrhs *
                                          sizeof(double), s));
   upward_all(op, src, nrhs, h, z, s);
-  set_boundary(f, op->gamma, op->n_bdry, u, op->tree.N, nrhs, s);
+  set_boundary(f, op->gamma, op->n_bdry, u, op->tree().N, nrhs, s);
   downward_all(op, u, nrhs, z, s);
   HPS_HIP(hipFreeAsync(h, s));
   HPS_HIP(hipFreeAsync(z, s));
@@ -624,7 +725,7 @@ void refine_device(hps_op* op, const double* f, int nrhs, double* u, double tol,
                    hipStream_t s, hps_solve_info* info) {
   HPS_REQUIRE(op->opt.keep_factors && op->opt.keep_leaf,
               "refinement needs keep_leaf_ops and keep_factors");
-  const int N = op->tree.N;
+  const int N = op->tree().N;
   const size_t nu = (size_t)N * nrhs;
   double *r = nullptr, *du = nullptr, *h = nullptr, *z = nullptr, *zero = nullptr;
   HPS_HIP(hipMallocAsync((void**)&r, nu * sizeof(double), s));

@@ -6,10 +6,12 @@
 
 #include "common.h"
 #include "plan.h"
+#include "pool.h"
 
 namespace hps {
 
-// Owner of device allocations; frees them on destruction.
+// Owner of device allocations (from the device memory cache); returns them on
+// destruction.
 struct DeviceMem {
   std::vector<void*> ptrs;
   DeviceMem() = default;
@@ -44,6 +46,42 @@ struct LevelPlan {
   size_t gather_max = 0;
 };
 
+// Shape-only data of the leaf stage for one (p, q, hx, hy): host tables and
+// their device copies.
+struct LeafPlan {
+  LeafTables lt;
+  DeviceMem mem;
+  double *dDx = nullptr, *dDy = nullptr, *dDxx = nullptr, *dDyy = nullptr, *dG = nullptr,
+         *dP0 = nullptr, *dP1 = nullptr;
+};
+std::shared_ptr<const LeafPlan> leaf_plan(int p, int q, double hx, double hy, hipStream_t s);
+
+// One merge of a tree plan: its box, where its index maps start in the map
+// pool, its sizes and where its parent DtN goes in its depth's arena.
+struct MergeRec {
+  int box;
+  size_t pool_off;
+  int na, nb, me, m3;
+  long long Toff;
+};
+
+// Shape-only data of a whole operator: tree, merge maps (host and device),
+// root boundary ids and arena sizes.
+struct TreePlan {
+  std::shared_ptr<const LeafPlan> leaf;
+  Tree tree;
+  int n_bdry = 0;
+  std::vector<std::vector<MergeRec>> levels;   // by depth
+  std::vector<int> pool_host;                  // pmap, a3, b3, Ie, Ii per merge, then gamma
+  size_t gamma_off = 0;
+  DeviceMem mem;
+  int* dpool = nullptr;
+  int* gamma = nullptr;
+  long long ar[2] = {0, 0};
+  std::vector<long long> box_hoff;
+  long long h_units = 0;
+};
+
 struct BuildOptions {
   int mode = HPS_FP64;
   hps_surrogate* surrogate = nullptr;
@@ -62,9 +100,9 @@ struct BuildOptions {
 struct hps_op {
   int nx = 0, ny = 0, p = 0, q = 0, mode = HPS_FP64;
   double box[4] = {0, 0, 0, 0};
-  hps::Tree tree;
-  hps::LeafTables lt;
+  std::shared_ptr<const hps::TreePlan> plan;   // shared by every operator of this shape
   hps::DeviceMem mem;
+  std::vector<char> staging;        // host image of the device descriptors
   hps::BuildOptions opt;
   const double* coeffs = nullptr;   // device coefficients used by the build
   double* leafT = nullptr;          // [nleaf][4q][4q]
@@ -86,9 +124,8 @@ struct hps_op {
   double judge_tol = 1e-6;
   double judge_worst = 0.0;             // worst judged error in the random sample
   int n_judged = 0;                     // leaves re-solved in FP64 by the judge
-  // device tables of the leaf stage
-  double *dDx = nullptr, *dDy = nullptr, *dDxx = nullptr, *dDyy = nullptr, *dG = nullptr,
-         *dP0 = nullptr, *dP1 = nullptr;
+  const hps::Tree& tree() const { return plan->tree; }
+  const hps::LeafPlan& leaf() const { return *plan->leaf; }
 };
 
 namespace hps {
