@@ -55,12 +55,12 @@ __device__ inline void block_argmax(double v, int idx, double* sv, int* si, doub
 // Block Gauss-Jordan elimination of the augmented systems W = [M | B].
 //
 // For each panel of kb columns starting at k0:
-//   1. k_gj_panel: LU with partial pivoting of W[k0:n, k0:k0+kb] in registers
-//      (one workgroup per system, rows spread over the threads).  It writes
-//      L11\U11 into the pivot block rows and, for the rows below, the
-//      original panel values in their new (pivoted) order; ipiv records the
-//      pivot row chosen for each column.
-//   2. k_gj_swap_trsm: applies the interchanges to every later column and
+//   1. k_gj_panel: LU with partial pivoting of W[k0:n, k0:k0+kb] in
+//      registers (one workgroup per system, rows spread over the lanes, one
+//      barrier per column).  piv[k0 + j] = row that moves to position k0 + j.
+//      It writes L11\U11 into the pivot block rows and, for the positions
+//      vacated below, the original panel values of the rows that move there.
+//   2. k_gj_swap_trsm: applies the same row moves to every later column and
 //      turns the pivot block rows into R = U11^-1 L11^-1 A12 (one thread per
 //      column).
 //   3. k_gj_update: every row outside the pivot block gets
@@ -69,150 +69,180 @@ __device__ inline void block_argmax(double v, int idx, double* sv, int* si, doub
 // After the last panel the right-hand-side columns hold X = M^-1 B in natural
 // row order, so no back substitution is needed; the extra cost over LU is
 // n^3/3 flops, small next to the n^2 m of the right-hand sides.
+//
+// Row moves of a step: row pi[j] goes to position k0 + j; the rows at
+// positions k0..k0+kb-1 that were not chosen (D, ascending) go to the
+// positions of the chosen rows lying below the block (V, in pivot order).
 // ---------------------------------------------------------------------------
 
-template <int NT, int R, int KB>
-__global__ void __launch_bounds__(NT) k_gj_panel(const SolveDesc* __restrict__ descs, int k0,
-                                                 int* status) {
-  constexpr int NW = NT / 64;
-  __shared__ double sv[2][NW];
-  __shared__ int si[2][NW];
-  __shared__ double rb[2][2][KB];  // [parity][0: pivot row, 1: row j][column]
-  __shared__ int ro[2][2];
+// Search key of a pivot candidate: |v| rounded to float (NaN as +inf) with
+// the low 12 bits replaced by 4095 - slot, so one unsigned max finds both
+// the largest magnitude (to 2^-11 relative) and where it lives.  0 = none.
+__device__ inline unsigned pivot_key(double v, int slot) {
+  const unsigned u = (v != v) ? 0x7F800000u : __float_as_uint((float)fabs(v));
+  return (u & ~4095u) | (unsigned)(4095 - slot);
+}
+
+// Wave-wide unsigned max: DPP within each row of 16 lanes (quad swaps, then
+// row rotations by 4 and 8), then the four row results through readlane.
+__device__ inline unsigned wave_max_u32(unsigned k) {
+  k = max(k, (unsigned)__builtin_amdgcn_mov_dpp((int)k, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  k = max(k, (unsigned)__builtin_amdgcn_mov_dpp((int)k, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  k = max(k, (unsigned)__builtin_amdgcn_mov_dpp((int)k, 0x124, 0xF, 0xF, false));  // row_ror:4
+  k = max(k, (unsigned)__builtin_amdgcn_mov_dpp((int)k, 0x128, 0xF, 0xF, false));  // row_ror:8
+  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)k, 0);
+  const unsigned b = (unsigned)__builtin_amdgcn_readlane((int)k, 16);
+  const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)k, 32);
+  const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)k, 48);
+  return max(max(a, b), max(c, d));
+}
+
+// Row moves of a step from the chosen rows pi[0..kb) (run by one wave).
+__device__ inline void perm_lists(const int* pi, int kb, int k0, int* sD, int* sV, int* nd) {
+  const int lane = threadIdx.x & 63;
+  bool chosen = false;
+  const int myp = lane < kb ? pi[lane] : -1;
+  for (int j = 0; j < kb; ++j) chosen |= (pi[j] == k0 + lane);
+  const bool isd = lane < kb && !chosen, isv = lane < kb && myp >= k0 + kb;
+  const unsigned long long md = __ballot(isd), mv = __ballot(isv);
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  if (isd) sD[__popcll(md & below)] = k0 + lane;
+  if (isv) sV[__popcll(mv & below)] = myp;
+  if (lane == 0) *nd = __popcll(md);
+}
+
+constexpr int TP_MAXW = 8;  // waves of the panel workgroup (two per SIMD: 256 VGPRs each)
+
+// Panel LU with partial pivoting, one workgroup barrier per column.  Local
+// row i (absolute k0 + i) lives in wave i / (64 R), slot (i / 64) % R, lane
+// i % 64; x holds its panel values.  For each column every wave finds its
+// best candidate with DPP and its owner lane publishes that row before the
+// barrier; after it every thread picks the workgroup's winner from the
+// published keys and eliminates with the winner's row.  Buffers alternate
+// between columns, so a single barrier per column suffices.
+template <int R, int KB>
+__global__ void __launch_bounds__(64 * TP_MAXW) k_gj_panel(const SolveDesc* __restrict__ descs,
+                                                          int k0, int* status) {
+  __shared__ unsigned sKey[2][TP_MAXW];
+  __shared__ double sRow[2][TP_MAXW][KB];
+  __shared__ double sLU[KB][KB + 1];
+  __shared__ double sKeep[KB][KB + 1];
+  __shared__ int sPi[KB], sD[KB], sV[KB], sNd, sBad, sNs;
   const SolveDesc d = descs[blockIdx.x];
   if (k0 >= d.n) return;
   const int kb = min(KB, d.n - k0), rows = d.n - k0;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  double* P = d.W + (size_t)k0 * d.ld + k0;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const size_t ld = d.ld;
-  double w[R][KB];
-  int org[R];
+  double* P = d.W + (size_t)k0 * ld + k0;
+  double x[R][KB];
+  bool live[R];
 #pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int r = tid + NT * q;
-    org[q] = r;
+  for (int r = 0; r < R; ++r) {
+    const int lr = wid * 64 * R + r * 64 + lane;
+    live[r] = lr < rows;
 #pragma unroll
-    for (int c = 0; c < KB; ++c) w[q][c] = (r < rows && c < kb) ? P[(size_t)r * ld + c] : 0.0;
+    for (int c = 0; c < KB; ++c) x[r][c] = (live[r] && c < kb) ? P[(size_t)lr * ld + c] : 0.0;
   }
-  // Constant trip count (the loop holds barriers, so it must unroll fully);
-  // columns past kb are skipped uniformly.
+  if (threadIdx.x == 0) {
+    sBad = 0;
+    sNs = 0;
+  }
+  int ns = 0;
+  bool stop = false;
+  // Constant trip count (columns past kb, or past the last candidate, are
+  // skipped uniformly) so the loop unrolls and x stays in registers.
 #pragma unroll
-  for (int j = 0; j < KB; ++j) {
-    if (j >= kb) continue;
-    const int buf = j & 1;
-    double best = -1.0;
-    int bi = -1;
+  for (int c = 0; c < KB; ++c) {
+    if (c >= kb || stop) continue;
+    const int buf = c & 1;
+    unsigned key = 0;
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int r = tid + NT * q;
-      const double v = w[q][j];
-      const double av = (v != v) ? INFINITY : fabs(v);
-      if (r >= j && r < rows && av > best) {
-        best = av;
-        bi = r;
-      }
-    }
+    for (int r = 0; r < R; ++r)
+      if (live[r]) key = max(key, pivot_key(x[r][c], wid * 64 * R + r * 64 + lane));
+    const unsigned wkey = wave_max_u32(key);
+    if (wkey != 0) {
+      const int slot = 4095 - (int)(wkey & 4095u);
+      const int wl = slot & 63, wr = (slot >> 6) % R;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ob = __shfl_xor(best, off);
-      const int oi = __shfl_xor(bi, off);
-      if (argmax_better(best, bi, ob, oi)) {
-        best = ob;
-        bi = oi;
-      }
-    }
-    if (lane == 0) {
-      sv[buf][wid] = best;
-      si[buf][wid] = bi;
-    }
-    __syncthreads();
-    best = sv[buf][0];
-    bi = si[buf][0];
+      for (int r = 0; r < R; ++r)
+        if (wr == r && lane == wl) {
 #pragma unroll
-    for (int v = 1; v < NW; ++v)
-      if (argmax_better(best, bi, sv[buf][v], si[buf][v])) {
-        best = sv[buf][v];
-        bi = si[buf][v];
-      }
-    const int pr = __builtin_amdgcn_readfirstlane(bi < 0 ? j : bi);
-    const int qp = pr / NT, tp = pr % NT;
-    if (tid == j) {
-#pragma unroll
-      for (int c = 0; c < KB; ++c) rb[buf][1][c] = w[0][c];
-      ro[buf][1] = org[0];
-    }
-#pragma unroll
-    for (int q = 0; q < R; ++q)
-      if (q == qp) {
-        if (tid == tp) {
-#pragma unroll
-          for (int c = 0; c < KB; ++c) rb[buf][0][c] = w[q][c];
-          ro[buf][0] = org[q];
-        }
-      }
-    __syncthreads();
-    if (pr != j) {
-      if (tid == j) {
-#pragma unroll
-        for (int c = 0; c < KB; ++c) w[0][c] = rb[buf][0][c];
-        org[0] = ro[buf][0];
-      }
-#pragma unroll
-      for (int q = 0; q < R; ++q)
-        if (q == qp) {
-          if (tid == tp) {
-#pragma unroll
-            for (int c = 0; c < KB; ++c) w[q][c] = rb[buf][1][c];
-            org[q] = ro[buf][1];
-          }
+          for (int c2 = 0; c2 < KB; ++c2)
+            if (c2 >= c) sRow[buf][wid][c2] = x[r][c2];
         }
     }
-    const double piv = rb[buf][0][j];
-    if (tid == 0) {
-      d.piv[k0 + j] = k0 + pr;
-      if (!(piv != 0.0) || piv != piv)
-        if (atomicCAS(status, 0, 1) == 0) status[1] = d.tag;
+    if (lane == 0) sKey[buf][wid] = wkey;
+    __syncthreads();
+    unsigned g = 0;
+    for (int w = 0; w < nw; ++w) g = max(g, sKey[buf][w]);
+    g = (unsigned)__builtin_amdgcn_readfirstlane((int)g);
+    if (g == 0) {
+      stop = true;
+      continue;
     }
-    const double inv = (piv != 0.0 && piv == piv) ? 1.0 / piv : 0.0;
+    const int gslot = 4095 - (int)(g & 4095u);
+    const int gw = gslot / (64 * R), gr = (gslot >> 6) % R, gl = gslot & 63;
+    const double* prow = sRow[buf][gw];
+    if (wid == gw) {
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int r = tid + NT * q;
-      if (r > j && r < rows) {
-        const double l = w[q][j] * inv;
-        w[q][j] = l;
+      for (int r = 0; r < R; ++r)
+        if (gr == r && lane == gl) {
+          live[r] = false;
 #pragma unroll
-        for (int c = j + 1; c < KB; ++c) w[q][c] -= l * rb[buf][0][c];
+          for (int c2 = 0; c2 < KB; ++c2) sLU[ns][c2] = x[r][c2];
+        }
+    }
+    if (threadIdx.x == 0) sPi[ns] = k0 + gslot;
+    ++ns;
+    const double piv = prow[c];
+    const bool ok = (piv != 0.0) && (piv == piv) && fabs(piv) != INFINITY;
+    if (!ok && threadIdx.x == 0) sBad = 1;
+    const double inv = ok ? 1.0 / piv : 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (live[r]) {
+        const double l = x[r][c] * inv;
+        x[r][c] = l;
+        // Runs over all KB columns (the test folds away once the column loop
+        // is unrolled), so it unrolls and x stays in registers.
+#pragma unroll
+        for (int c2 = 0; c2 < KB; ++c2)
+          if (c2 > c) x[r][c2] = fma(-l, prow[c2], x[r][c2]);
       }
-    }
   }
-  // Rows below the pivot block get their original values (in pivoted order);
-  // read them all before anything is written back.
+  if (threadIdx.x == 0) sNs = ns;
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int r = tid + NT * q;
-    if (r >= kb && r < rows) {
-      const int src = org[q];
-#pragma unroll
-      for (int c = 0; c < KB; ++c) w[q][c] = (c < kb) ? P[(size_t)src * ld + c] : 0.0;
-    }
+  if (wid == 0) {
+    // Fewer than kb pivots cannot happen (every live row has a nonzero key);
+    // should it, the identity keeps every later access in bounds and the
+    // status reports the system as singular.
+    const bool short_ = sNs < kb;
+    if (short_ && lane < kb) sPi[lane] = k0 + lane;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    perm_lists(sPi, kb, k0, sD, sV, &sNd);
+    if (lane < kb) d.piv[k0 + lane] = sPi[lane];
+    if (lane == 0 && (sBad || short_))
+      if (atomicCAS(status, 0, 1) == 0) status[1] = d.tag;
   }
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int r = tid + NT * q;
-    if (r < rows) {
-#pragma unroll
-      for (int c = 0; c < KB; ++c)
-        if (c < kb) P[(size_t)r * ld + c] = w[q][c];
-    }
-  }
+  // Original panel values of the displaced rows (they sit in the pivot block,
+  // which is overwritten next), then the block's new rows.
+  const int nd = sNd;
+  for (int e = threadIdx.x; e < nd * kb; e += blockDim.x)
+    sKeep[e / kb][e % kb] = P[(size_t)(sD[e / kb] - k0) * ld + e % kb];
+  __syncthreads();
+  for (int e = threadIdx.x; e < kb * kb; e += blockDim.x)
+    P[(size_t)(e / kb) * ld + e % kb] = sLU[e / kb][e % kb];
+  for (int e = threadIdx.x; e < nd * kb; e += blockDim.x)
+    P[(size_t)(sV[e / kb] - k0) * ld + e % kb] = sKeep[e / kb][e % kb];
 }
 
 template <int KB>
 __global__ void __launch_bounds__(256) k_gj_swap_trsm(const SolveDesc* __restrict__ descs, int k0) {
   __shared__ double LU[KB][KB + 1];
-  __shared__ int pv[KB];
+  __shared__ int pv[KB], sD[KB], sV[KB], sNd;
   const SolveDesc d = descs[blockIdx.y];
   if (k0 >= d.n) return;
   const int kb = min(KB, d.n - k0);
@@ -226,20 +256,21 @@ __global__ void __launch_bounds__(256) k_gj_swap_trsm(const SolveDesc* __restric
   }
   for (int e = threadIdx.x; e < kb; e += blockDim.x) pv[e] = d.piv[k0 + e];
   __syncthreads();
+  if (threadIdx.x < 64) perm_lists(pv, kb, k0, sD, sV, &sNd);
+  __syncthreads();
   const int col = c0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= d.n + d.m) return;
   double* W = d.W;
-  for (int j = 0; j < kb; ++j) {
-    const int r2 = pv[j];
-    if (r2 != k0 + j) {
-      double a = W[(size_t)(k0 + j) * ld + col];
-      W[(size_t)(k0 + j) * ld + col] = W[(size_t)r2 * ld + col];
-      W[(size_t)r2 * ld + col] = a;
-    }
-  }
-  double x[KB];
+  const int nd = sNd;
+  double x[KB], y[KB];
 #pragma unroll
-  for (int j = 0; j < KB; ++j) x[j] = (j < kb) ? W[(size_t)(k0 + j) * ld + col] : 0.0;
+  for (int j = 0; j < KB; ++j) {
+    x[j] = (j < kb) ? W[(size_t)pv[j] * ld + col] : 0.0;
+    y[j] = (j < nd) ? W[(size_t)sD[j] * ld + col] : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < KB; ++j)
+    if (j < nd) W[(size_t)sV[j] * ld + col] = y[j];
 #pragma unroll
   for (int j = 1; j < KB; ++j) {
     double s = x[j];
@@ -471,19 +502,20 @@ __global__ void __launch_bounds__(256) k_gemm_split32(const GemmDesc* __restrict
 // Host drivers.
 // ---------------------------------------------------------------------------
 
-template <int KB>
-static void launch_panel(const SolveDesc* d_desc, int np, int k0, int rows, int* st,
+// Panel launch: up to eight waves; two rows per lane for 32-wide panels
+// (x[2][32] fits the 256 VGPRs of a wave at two waves per SIMD), six rows per
+// lane for the 16-wide panels of systems beyond 1024 rows.
+static void launch_panel(const SolveDesc* d_desc, int np, int k0, int rows, int nb, int* st,
                          hipStream_t s) {
-  if (rows <= 256)
-    hipLaunchKernelGGL((k_gj_panel<256, 1, KB>), dim3(np), dim3(256), 0, s, d_desc, k0, st);
-  else if (rows <= 512)
-    hipLaunchKernelGGL((k_gj_panel<512, 1, KB>), dim3(np), dim3(512), 0, s, d_desc, k0, st);
-  else if (rows <= 1024)
-    hipLaunchKernelGGL((k_gj_panel<1024, 1, KB>), dim3(np), dim3(1024), 0, s, d_desc, k0, st);
-  else if (rows <= 2048)
-    hipLaunchKernelGGL((k_gj_panel<1024, 2, 16>), dim3(np), dim3(1024), 0, s, d_desc, k0, st);
-  else
-    hipLaunchKernelGGL((k_gj_panel<1024, 3, 16>), dim3(np), dim3(1024), 0, s, d_desc, k0, st);
+  if (nb == 32) {
+    HPS_REQUIRE(rows <= 64 * TP_MAXW * 2, "panel has too many rows");
+    const int nw = (rows + 127) / 128;
+    hipLaunchKernelGGL((k_gj_panel<2, 32>), dim3(np), dim3(64 * nw), 0, s, d_desc, k0, st);
+  } else {
+    HPS_REQUIRE(rows <= 64 * TP_MAXW * 6, "panel has too many rows");
+    const int nw = (rows + 383) / 384;
+    hipLaunchKernelGGL((k_gj_panel<6, 16>), dim3(np), dim3(64 * nw), 0, s, d_desc, k0, st);
+  }
 }
 
 int max_solve_rows() { return 3072; }
@@ -496,8 +528,7 @@ void batched_solve(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc
     nmax = std::max(nmax, d.n);
     wmax = std::max(wmax, d.n + d.m);
   }
-  HPS_REQUIRE(nmax <= max_solve_rows(), "dense system too large for the register panel");
-  // Panels wider than 16 columns only while every row fits one register row per thread.
+  HPS_REQUIRE(nmax <= max_solve_rows(), "dense system too large for the panel kernel");
   const int nb = nmax > 1024 ? 16 : 32;
   const int np = (int)h_desc.size();
   for (int k0 = 0; k0 < nmax; k0 += nb) {
@@ -512,10 +543,7 @@ void batched_solve(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc
     const int rows = nmax - k0;
     {
       ProfScope ps(PROF_LU_PANEL, stream, fp, 0);
-      if (nb == 32)
-        launch_panel<32>(d_desc, np, k0, rows, d_status, stream);
-      else
-        launch_panel<16>(d_desc, np, k0, rows, d_status, stream);
+      launch_panel(d_desc, np, k0, rows, nb, d_status, stream);
     }
     const int rest = wmax - k0 - std::min(nb, rows);
     if (rest <= 0) continue;

@@ -11,7 +11,8 @@ bool leaf_lu_fits(int n, int m);
 
 // Z[leaf] = A_ii^-1 R for count leaves (coefficients cptr[leaf]); Z is [count][n][m].
 // status[0] becomes 1 and status[1] = tag0 - leaf on a zero or non-finite pivot.
-// Register variant: 0 = 16x16 threads (p <= 12), 1 = 16x64 threads, 2 = 16x32 threads.
+// Kernel variant: 0-2 step-by-step LU (16x16 threads for p <= 12, 16x64, 16x32), 3-4
+// blocked Gauss-Jordan (16x16 threads, 9-column blocks; 16x32 threads, 8-column blocks).
 void leaf_lu_set_variant(int v);
 
 void leaf_lu(const double* const* cptr, const LeafDev& tab, int count, double* Z, int* status,

@@ -233,6 +233,198 @@ __global__ void __launch_bounds__(TR * TC) k_leaf_lu(const double* const* __rest
   }
 }
 
+// ---------------------------------------------------------------------------
+// Gauss-Jordan leaf solve with one workgroup barrier per column.  Same result
+// as k_leaf_lu (Z = A_ii^-1 R) without its back substitution.
+//
+// Register layout: thread (tr, tc) = (tid % 16, tid / 16) holds rows
+// i = tr + 16 s (s < NR) and the NC consecutive columns j = NC tc + t
+// (t < NC).  The 16 threads of one tc are one DPP row (16 lanes) of a wave,
+// so column k lives in a single DPP row and row i's values in the columns of
+// any tc live in that tc's DPP row.
+//
+// Column k (owner tc = k / NC): the owner lanes find the pivot row p with a
+// DPP max (rows stay in place; chosen rows are only marked) and publish the
+// multipliers l_i = a[i][k] / a[p][k] for every row i != p (l_p = 0) and
+// 1 / a[p][k]; after the barrier every thread fetches row p's values for its
+// own columns from lane p % 16 of its DPP row, row p's owner divides it by
+// the pivot, and every thread applies a[i][j] -= l_i a[p][j].  That
+// eliminates column k from every other row (above and below: Gauss-Jordan).  Threads
+// whose columns all precede k + 1 have nothing left to update.  After the
+// last column, row p_k holds row k of A_ii^-1 R in its right-hand-side
+// columns.
+// ---------------------------------------------------------------------------
+
+// |v| as float with the low 12 bits replaced by 4095 - slot (as in the panel
+// kernel of the dense solver): one unsigned max gives value and place.
+__device__ inline unsigned leaf_key(double v, int slot) {
+  const unsigned u = (v != v) ? 0x7F800000u : __float_as_uint((float)fabs(v));
+  return (u & ~4095u) | (unsigned)(4095 - slot);
+}
+
+// Max over the 16 lanes of a DPP row (all 16 must be active).
+__device__ inline unsigned row16_max(unsigned k) {
+  k = max(k, (unsigned)__builtin_amdgcn_mov_dpp((int)k, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  k = max(k, (unsigned)__builtin_amdgcn_mov_dpp((int)k, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  k = max(k, (unsigned)__builtin_amdgcn_mov_dpp((int)k, 0x124, 0xF, 0xF, false));  // row_ror:4
+  k = max(k, (unsigned)__builtin_amdgcn_mov_dpp((int)k, 0x128, 0xF, 0xF, false));  // row_ror:8
+  return k;
+}
+
+__device__ inline double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <int TC, int NR, int NC>
+__global__ void __launch_bounds__(16 * TC) k_leaf_gj(const double* const* __restrict__ cptr,
+                                                     const LeafDev tab, double* __restrict__ Z,
+                                                     int* status, int tag0) {
+  constexpr int TR = 16, NT = TR * TC, NROW = NR * TR;
+  __shared__ double sD[4][24 * 24];
+  __shared__ double sc[6][NROW];
+  __shared__ double sL[2][NROW];  // multipliers of the current column
+  __shared__ int sP[2];           // its pivot row
+  __shared__ double sR[2];        // 1 / pivot
+  __shared__ int sInv[NROW];      // row -> column whose pivot it is
+
+  const int p = tab.p, n = tab.n, m = tab.m, pi = p - 2, w = n + m;
+  const int tid = threadIdx.x, tr = tid % TR, tc = tid / TR;
+  const int lane = tid & 63, rowlane = lane & ~15;
+  const double* cl = cptr[blockIdx.x];
+  for (int e = tid; e < p * p; e += NT) {
+    sD[0][e] = tab.Dx[e];
+    sD[1][e] = tab.Dy[e];
+    sD[2][e] = tab.Dxx[e];
+    sD[3][e] = tab.Dyy[e];
+  }
+  for (int e = tid; e < 6 * n; e += NT) {
+    int f = e / n, k = e % n;
+    sc[f][k] = cl[(size_t)f * p * p + (1 + k % pi) + p * (1 + k / pi)];
+  }
+  __syncthreads();
+
+  // ---- assembly of [A_ii | R] (same formulas as k_leaf_lu) ----
+  double a[NR][NC];
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    const int i = tr + TR * s;
+    const bool rv = i < n;
+    const int ia = rv ? 1 + i % pi : 1, ib = rv ? 1 + i / pi : 1;
+    const double c11 = rv ? sc[0][i] : 0, c12 = rv ? sc[1][i] : 0, c22 = rv ? sc[2][i] : 0;
+    const double c1 = rv ? sc[3][i] : 0, c2 = rv ? sc[4][i] : 0, c0 = rv ? sc[5][i] : 0;
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+      const int j = NC * tc + t;
+      double v = 0.0;
+      if (rv && j < n) {
+        const int ja = 1 + j % pi, jb = 1 + j / pi;
+        const double dx = sD[0][ia * p + ja], dy = sD[1][ib * p + jb];
+        v = -2.0 * c12 * dx * dy;
+        if (ib == jb) v += -c11 * sD[2][ia * p + ja] + c1 * dx;
+        if (ia == ja) v += -c22 * sD[3][ib * p + jb] + c2 * dy;
+        if (i == j) v += c0;
+      } else if (rv && j < w) {
+        const size_t o = (size_t)i * m + (j - n), st = (size_t)n * m;
+        v = -c11 * tab.G[o] - 2.0 * c12 * tab.G[st + o] - c22 * tab.G[2 * st + o] +
+            c1 * tab.G[3 * st + o] + c2 * tab.G[4 * st + o];
+      }
+      a[s][t] = v;
+    }
+  }
+
+  // Rows already chosen as pivots (bit s: row tr + 16 s); padding rows count as chosen.
+  unsigned done = 0;
+#pragma unroll
+  for (int s = 0; s < NR; ++s)
+    if (tr + TR * s >= n) done |= 1u << s;
+
+  const int nblk = (n + NC - 1) / NC;
+  for (int kb = 0; kb < nblk; ++kb) {
+    // Constant trip count over the block's columns (t is a register index).
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+      const int k = NC * kb + t;
+      if (k >= n) continue;
+      const int buf = k & 1;
+      if (tc == kb) {
+        unsigned key = 0;
+#pragma unroll
+        for (int s = 0; s < NR; ++s)
+          if (!((done >> s) & 1u)) key = max(key, leaf_key(a[s][t], TR * s + tr));
+        key = row16_max(key);
+        const int slot = __builtin_amdgcn_readfirstlane(4095 - (int)(key & 4095u));
+        const int sp = slot / TR, trp = slot % TR;
+        const int src = __builtin_amdgcn_readfirstlane(rowlane) + trp;
+        double piv = 0.0;
+#pragma unroll
+        for (int s = 0; s < NR; ++s)
+          if (s == sp) piv = readlane_d(a[s][t], src);
+        const bool ok = (piv != 0.0) && (piv == piv) && fabs(piv) != INFINITY;
+        const double inv = ok ? 1.0 / piv : 0.0;
+#pragma unroll
+        for (int s = 0; s < NR; ++s) {
+          const int i = TR * s + tr;
+          sL[buf][i] = (i == slot) ? 0.0 : a[s][t] * inv;
+        }
+        if (tr == 0) {
+          sP[buf] = ok ? slot : -1 - slot;
+          sR[buf] = inv;
+          sInv[slot] = k;
+        }
+      }
+      __syncthreads();
+      int slot = sP[buf];
+      if (slot < 0) {
+        slot = -1 - slot;
+        if (tid == 0)
+          if (atomicCAS(status, 0, 1) == 0) status[1] = tag0 - (int)blockIdx.x;
+      }
+      slot = __builtin_amdgcn_readfirstlane(slot);
+      const int sp = slot / TR, trp = slot % TR;
+      if (tr == trp) done |= 1u << sp;
+      // Columns of this thread that are still to be updated: j > k.
+      if (NC * tc + NC - 1 > k) {
+        // Row p's values in my columns: lane trp of my DPP row, slot sp.
+        double prow[NC];
+        const double rinv = sR[buf];
+#pragma unroll
+        for (int s = 0; s < NR; ++s)
+          if (s == sp) {
+#pragma unroll
+            for (int t2 = 0; t2 < NC; ++t2) prow[t2] = __shfl(a[s][t2], rowlane + trp);
+            if (tr == trp) {
+#pragma unroll
+              for (int t2 = 0; t2 < NC; ++t2) a[s][t2] *= rinv;
+            }
+          }
+#pragma unroll
+        for (int s = 0; s < NR; ++s) {
+          const double lv = sL[buf][TR * s + tr];
+#pragma unroll
+          for (int t2 = 0; t2 < NC; ++t2) a[s][t2] = fma(-lv, prow[t2], a[s][t2]);
+        }
+      }
+    }
+  }
+
+  // ---- Z out: row p_k holds row k of A_ii^-1 R ----
+  double* Zl = Z + (size_t)blockIdx.x * n * m;
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    const int i = tr + TR * s;
+    if (i >= n) continue;
+    const int k = sInv[i];
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+      const int j = NC * tc + t;
+      if (j >= n && j < w) Zl[(size_t)k * m + (j - n)] = a[s][t];
+    }
+  }
+}
+
 // Register variants: rows <= NR*TR, columns (n + m) <= NC*TC.
 bool leaf_lu_fits(int n, int m) {
   return (n <= 13 * 16 && n + m <= 8 * 32) || (n <= 7 * 16 && n + m <= 9 * 16);
@@ -247,17 +439,30 @@ void leaf_lu(const double* const* cptr, const LeafDev& tab, int count, double* Z
   const double n = tab.n, m = tab.m;
   ProfScope ps(PROF_LEAF_LU, s, count * (2.0 * n * n * n / 3.0 + 2.0 * n * n * m), 0);
   const bool small = tab.n <= 7 * 16 && tab.n + tab.m <= 9 * 16;
-  int v = g_leaf_variant >= 0 ? g_leaf_variant : (small ? 0 : 2);
-  if (v == 0 && !small) v = 1;
-  if (v == 0) {
-    hipLaunchKernelGGL((k_leaf_lu<16, 16, 7, 9>), dim3(count), dim3(256), 0, s, cptr, tab, Z,
-                       status, tag0);
-  } else if (v == 2) {
-    hipLaunchKernelGGL((k_leaf_lu<16, 32, 13, 8>), dim3(count), dim3(512), 0, s, cptr, tab, Z,
-                       status, tag0);
-  } else {
-    hipLaunchKernelGGL((k_leaf_lu<16, 64, 13, 4>), dim3(count), dim3(1024), 0, s, cptr, tab, Z,
-                       status, tag0);
+  // Variants: 0-2 step-by-step LU (k_leaf_lu), 3-4 blocked Gauss-Jordan (k_leaf_gj).
+  int v = g_leaf_variant >= 0 ? g_leaf_variant : (small ? 3 : 4);
+  if ((v == 0 || v == 3) && !small) v = (v == 0) ? 1 : 4;
+  switch (v) {
+    case 0:
+      hipLaunchKernelGGL((k_leaf_lu<16, 16, 7, 9>), dim3(count), dim3(256), 0, s, cptr, tab, Z,
+                         status, tag0);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_leaf_lu<16, 64, 13, 4>), dim3(count), dim3(1024), 0, s, cptr, tab, Z,
+                         status, tag0);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_leaf_lu<16, 32, 13, 8>), dim3(count), dim3(512), 0, s, cptr, tab, Z,
+                         status, tag0);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_leaf_gj<16, 7, 9>), dim3(count), dim3(256), 0, s, cptr, tab, Z, status,
+                         tag0);
+      break;
+    default:
+      hipLaunchKernelGGL((k_leaf_gj<32, 13, 8>), dim3(count), dim3(512), 0, s, cptr, tab, Z,
+                         status, tag0);
+      break;
   }
 }
 

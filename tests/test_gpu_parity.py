@@ -57,7 +57,10 @@ def test_gemm_split32_accuracy(H, gpu):
     assert err < 5e-7
 
 
-@pytest.mark.parametrize("n,m,nb", [(5, 3, 2), (33, 40, 3), (70, 17, 2), (130, 9, 1), (196, 56, 2)])
+# Sizes cover one round of the pivot tournament (n <= 128), two rounds (448),
+# three rounds (900) and waves taking several round-1 chunks (1100, 2100).
+@pytest.mark.parametrize("n,m,nb", [(5, 3, 2), (33, 40, 3), (70, 17, 2), (130, 9, 1), (196, 56, 2),
+                                    (448, 30, 2), (900, 40, 1), (1100, 20, 1), (2100, 7, 1)])
 def test_batched_solve_with_pivoting(H, gpu, n, m, nb):
     say(f"batched_solve n={n} m={m} batch {nb}")
     rng = np.random.default_rng(n + m)
@@ -67,6 +70,21 @@ def test_batched_solve_with_pivoting(H, gpu, n, m, nb):
     X = H.batched_solve(_t(M, gpu), _t(B, gpu)).cpu().numpy()
     ref = np.linalg.solve(M, B)
     assert rel_err(X, ref) < 1e-10
+
+
+def test_batched_solve_deep_pivots(H, gpu):
+    """The top 300 x 300 block has rank one and the top rows are tiny, so every
+    pivot of the first panels must come from rows far below (other chunks of
+    the tournament)."""
+    say("batched_solve deep pivots n=600")
+    rng = np.random.default_rng(77)
+    n, m = 600, 12
+    M = rng.standard_normal((1, n, n))
+    M[0, :300, :300] = 1e-8 * np.outer(rng.standard_normal(300), rng.standard_normal(300))
+    B = rng.standard_normal((1, n, m))
+    X = H.batched_solve(_t(M, gpu), _t(B, gpu)).cpu().numpy()
+    ref = np.linalg.solve(M, B)
+    assert rel_err(X, ref) < 1e-9
 
 
 def test_batched_solve_reports_singular(H, gpu):
