@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-leaves", type=int, default=512)
     ap.add_argument("--kernels", action="store_true", help="print per-class kernel times")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (kernels use their built-in defaults)")
     return ap.parse_args()
 
 
@@ -118,6 +120,19 @@ def main():
     fd = torch.tensor(f, dtype=torch.float64, device=dev)
     mode = H.HPS_MIXED_SPLIT32 if args.mode == "mixed" else H.HPS_FP64
     n_tot = (nx * (pr.p - 1) + 1) * (ny * (pr.p - 1) + 1) + pr.q * (nx * (ny + 1) + (nx + 1) * ny)
+
+    # One-time autotuning for this shape (reported separately, not timed).
+    tune_s = None
+    if not args.no_tune:
+        tune_s = H.autotune([dict(nleaf=pr.nleaf, p=pr.p, q=pr.q, box=pr.box)],
+                            keep_factors=(mode == H.HPS_MIXED_SPLIT32))
+        import tempfile
+        with tempfile.TemporaryDirectory() as td:
+            H.tune_save(os.path.join(td, "t.json"))
+            tuned = json.load(open(os.path.join(td, "t.json")))["entries"]
+        log(f"autotune {tune_s:.2f} s: " + ", ".join(
+            f"{e['name']}{e['key']}->{e['variant']} ({e['default_ms']:.3f}->{e['ms']:.3f} ms)"
+            for e in tuned))
 
     def build():
         return H.build_solution_operator(Cd, pr.box, pr.nleaf, pr.p, pr.q, mode=mode)
@@ -207,6 +222,7 @@ def main():
         "build_unknowns_per_s": n_tot / (build_ms * 1e-3),
         "solves_per_s": 1.0 / (solve_ms * 1e-3),
         "residual_rel": res_rel,
+        "autotune_s": tune_s,
         "roofline": roof,
         "kernel_ms_first_step": {c: round(per[c]["ms"], 4) for c in classes if per[c]["launches"]},
     }

@@ -284,12 +284,36 @@ hps_status hps_leaf_tables(int p, int q, double hx, double hy, double* Dx, doubl
 hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int sizes[4], int* pmap,
                         int* a3, int* b3, int* Ie, int* Ii, int* n_boxes);
 
-/* ---- tuning knobs -------------------------------------------------------- */
+/* ---- tuning knobs and the autotuner --------------------------------------- */
 
-/* Sets a kernel-selection knob for later launches in this process:
-   "leaf_variant": register layout of the fused leaf solve (-1 automatic,
-   0: 16x16 threads, 1: 16x64 threads, 2: 16x32 threads). */
+/* Forces a kernel variant for later launches in this process (-1 returns the
+   choice to the tuning table, else the built-in default):
+   "leaf_variant": fused leaf solve, 0-2 step-by-step LU (16x16 threads for
+     p <= 12, 16x64, 16x32), 3-4 Gauss-Jordan (16x16 threads for p <= 12,
+     16x32 threads);
+   "gemm_variant": FP64 MFMA GEMM tile (0: 64x64x16 on 2x2 waves, 1: 32x32x16
+     on one wave, 2: 128x128x16, 3: 128x64x16, 4: 64x128x16, 5: 64x64x32);
+   "gj_variant": merge solver, 4 * (update tile, as gemm_variant) + TRSM block
+     (0: 256, 1: 128, 2: 64 threads).
+   Unknown knobs or values give HPS_EINVAL. */
 hps_status hps_tune_set(const char* knob, int value);
+
+/* Autotuner.  For every problem shape in probs (only nleaf, p, q and box are
+   read; coeffs may be NULL) it times every variant of the leaf kernel, of the
+   FP64 MFMA GEMM (per shape bucket: log2 of M, N, K and of the batch count) and
+   of the merge solver (per bucket of system rows, columns and count) on
+   synthetic data of those shapes, and records the fastest in the process's
+   tuning table, which later builds consult.  keep_factors selects the merge
+   shapes of operators built for refinement.  Buckets already in the table are
+   not re-timed.  *seconds (may be NULL) receives the time spent.  Work is
+   enqueued on stream (NULL = default) and waited for. */
+hps_status hps_autotune(const hps_problem* probs, int nprob, int keep_factors, void* stream,
+                        double* seconds);
+/* Writes the tuning table as JSON (format "hps-tune-1") / merges such a file
+   into the table (HPS_EINVAL on a malformed file) / empties the table. */
+hps_status hps_tune_save(const char* path);
+hps_status hps_tune_load(const char* path);
+hps_status hps_tune_reset(void);
 
 /* ---- launch timing (HIP events on the launch stream) --------------------- */
 

@@ -161,7 +161,37 @@ def batched_gemm(A, B, C, alpha: float = 1.0, split32: bool = False):
 
 
 def tune_set(knob: str, value: int) -> None:
+    """Forces a kernel variant ("leaf_variant", "gemm_variant", "gj_variant"); -1 clears."""
     check(lib.hps_tune_set(knob.encode(), int(value)))
+
+
+def autotune(shapes, keep_factors: bool = False, stream=None) -> float:
+    """Times every kernel variant for the builds of the given problem shapes
+    (dicts with nleaf, p, q and optionally box) and keeps the fastest per shape
+    bucket in this process's tuning table.  Returns the seconds spent."""
+    arr = (Problem * len(shapes))()
+    for i, sh in enumerate(shapes):
+        arr[i].coeffs = None
+        box = sh.get("box", (0.0, 1.0, 0.0, 1.0))
+        for k in range(4):
+            arr[i].box[k] = float(box[k])
+        arr[i].nleaf[0], arr[i].nleaf[1] = int(sh["nleaf"][0]), int(sh["nleaf"][1])
+        arr[i].p, arr[i].q = int(sh["p"]), int(sh["q"])
+    sec = C.c_double()
+    check(lib.hps_autotune(arr, len(shapes), int(bool(keep_factors)), _stream(stream), C.byref(sec)))
+    return sec.value
+
+
+def tune_save(path) -> None:
+    check(lib.hps_tune_save(str(path).encode()))
+
+
+def tune_load(path) -> None:
+    check(lib.hps_tune_load(str(path).encode()))
+
+
+def tune_reset() -> None:
+    check(lib.hps_tune_reset())
 
 
 # ---- learned leaf surrogate -------------------------------------------------------

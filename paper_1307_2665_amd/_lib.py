@@ -82,6 +82,10 @@ SIGNATURES = {
     "hps_batched_gemm": [P, P, P, I, I, I, I, D, I, P],
     "hps_plan_box": [P, I, I, P, P, P, P, P, P, P, IP],
     "hps_tune_set": [C.c_char_p, I],
+    "hps_autotune": [C.POINTER(Problem), I, I, P, C.POINTER(D)],
+    "hps_tune_save": [C.c_char_p],
+    "hps_tune_load": [C.c_char_p],
+    "hps_tune_reset": [],
     "hps_surrogate_create": [I, I, D, D, I, I, C.c_ulonglong, P, C.POINTER(P)],
     "hps_surrogate_train": [P, P, P, I, I, I, D, C.c_ulonglong, P, C.POINTER(D), P],
     "hps_surrogate_grad": [P, P, P, I, P, C.POINTER(D), P],

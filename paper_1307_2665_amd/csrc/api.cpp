@@ -9,8 +9,10 @@
 #include "leaf.h"
 #include "solver.h"
 #include "surrogate.h"
+#include "tune.h"
 
 #include <fstream>
+#include <sstream>
 
 namespace {
 
@@ -411,11 +413,63 @@ hps_status hps_tune_set(const char* knob, int value) {
   return guard([&] {
     HPS_REQUIRE(knob != nullptr, "null knob");
     std::string k(knob);
-    if (k == "leaf_variant")
+    if (k == "leaf_variant") {
+      HPS_REQUIRE(value >= -1 && value <= 4, "leaf_variant must be in [-1, 4]");
       hps::leaf_lu_set_variant(value);
-    else
+    } else if (k == "gemm_variant") {
+      HPS_REQUIRE(value >= -1 && value < hps::GEMM_VARIANTS, "gemm_variant out of range");
+      hps::tune_force(hps::TUNE_GEMM, value);
+    } else if (k == "gj_variant") {
+      HPS_REQUIRE(value >= -1 && value < 4 * hps::GEMM_VARIANTS && (value < 0 || value % 4 < 3),
+                  "gj_variant out of range");
+      hps::tune_force(hps::TUNE_GJ, value);
+    } else {
       throw hps::Error(HPS_EINVAL, "unknown knob " + k);
+    }
   });
+}
+
+hps_status hps_autotune(const hps_problem* probs, int nprob, int keep_factors, void* stream,
+                        double* seconds) {
+  return guard([&] {
+    HPS_REQUIRE(probs != nullptr && nprob >= 1, "bad arguments");
+    std::vector<hps::TuneShape> shapes;
+    for (int i = 0; i < nprob; ++i) {
+      const hps_problem& p = probs[i];
+      HPS_REQUIRE(p.nleaf[0] >= 1 && p.nleaf[1] >= 1 && p.box[1] > p.box[0] && p.box[3] > p.box[2],
+                  "bad problem shape");
+      shapes.push_back(hps::TuneShape{p.nleaf[0], p.nleaf[1], p.p, p.q,
+                                      (p.box[1] - p.box[0]) / p.nleaf[0],
+                                      (p.box[3] - p.box[2]) / p.nleaf[1], keep_factors != 0});
+    }
+    const double t = hps::autotune(shapes, (hipStream_t)stream);
+    if (seconds) *seconds = t;
+  });
+}
+
+hps_status hps_tune_save(const char* path) {
+  return guard([&] {
+    HPS_REQUIRE(path != nullptr, "null path");
+    std::ofstream f(path);
+    HPS_REQUIRE(f.good(), std::string("cannot write ") + path);
+    f << hps::tune_json();
+    HPS_REQUIRE(f.good(), std::string("write failed: ") + path);
+  });
+}
+
+hps_status hps_tune_load(const char* path) {
+  return guard([&] {
+    HPS_REQUIRE(path != nullptr, "null path");
+    std::ifstream f(path);
+    HPS_REQUIRE(f.good(), std::string("cannot read ") + path);
+    std::stringstream ss;
+    ss << f.rdbuf();
+    hps::tune_load_json(ss.str());
+  });
+}
+
+hps_status hps_tune_reset(void) {
+  return guard([&] { hps::tune_clear(); });
 }
 
 hps_status hps_leaf_tables(int p, int q, double hx, double hy, double* Dx, double* Dy, double* Dxx,

@@ -18,6 +18,14 @@ void batched_solve(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc
 void grouped_gemm(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, hipStream_t stream,
                   bool split32);
 
+// The same with explicit kernel variants (the autotuner times them):
+// gj_variant = update tile * 4 + TRSM block code (see tune.h), -1 = default;
+// variant = FP64 MFMA tile of gemm_tile (0..5), -1 = default.
+void batched_solve_v(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc, int* d_status,
+                     hipStream_t stream, int gj_variant);
+void grouped_gemm_v(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, hipStream_t stream,
+                    int variant, bool split32);
+
 void dense_init();
 int max_solve_rows();
 

@@ -8,6 +8,7 @@
 // eq:merge and the leaf's T = P0 - P1 Z.
 #include "dense.h"
 #include "prof.h"
+#include "tune.h"
 
 #include <algorithm>
 #include <vector>
@@ -294,68 +295,85 @@ __global__ void __launch_bounds__(256) k_gj_swap_trsm(const SolveDesc* __restric
 }
 
 // ---------------------------------------------------------------------------
-// FP64 MFMA tile: 64x64 output tile per 256-thread workgroup, 4 waves in a
-// 2x2 arrangement, each wave a 32x32 block = 2x2 MFMA 16x16x4 f64 blocks.
-// Lane layout of v_mfma_f64_16x16x4f64: A operand lane l holds A[l%16][l/16],
+// FP64 MFMA tiles.  A workgroup computes a BM x BN tile of C with WM x WN
+// waves; each wave owns a (BM/WM) x (BN/WN) block made of 16 x 16
+// v_mfma_f64_16x16x4f64 blocks.  A and B stream through LDS in BK-deep
+// slabs.  Lane layout of the instruction: A operand lane l holds A[l%16][l/16],
 // B operand B[l/16][l%16], result register r holds D[l/16 + 4r][l%16]
 // (the f32 16x16x4 form instead holds D[4*(l/16) + r][l%16]).
+// Variants (index = tuning value): 0: 64x64x16 on 2x2 waves (the default),
+// 1: 32x32x16 on one wave, 2: 128x128x16 on 2x2 waves, 3: 128x64x16 on 2x2,
+// 4: 64x128x16 on 2x2, 5: 64x64x32 on 2x2.
 // ---------------------------------------------------------------------------
-constexpr int TBM = 64, TBN = 64, TBK = 16;
+constexpr int TBM = 64, TBN = 64, TBK = 16;  // tile of the split-FP32 kernel
 
-__device__ inline void gemm_tile_f64(const double* __restrict__ A, int lda,
-                                     const double* __restrict__ B, int ldb, double* C, int ldc,
-                                     const double* C0, int ldc0, int M, int N, int K, double alpha,
-                                     int tm, int tn, double (*As)[TBM + 1],
-                                     double (*Bs)[TBN + 1]) {
+template <int BM, int BN, int BK, int WM, int WN>
+struct GemmTile {
+  static constexpr int NT = 64 * WM * WN;
+  static constexpr int FM = BM / WM / 16, FN = BN / WN / 16;
+  static constexpr int SMEM = BK * (BM + 1) + BK * (BN + 1);  // doubles
+  static_assert(FM >= 1 && FN >= 1 && BK % 4 == 0, "bad tile");
+  static_assert((BM * BK) % NT == 0 && (BK * BN) % NT == 0, "tile loads must divide evenly");
+};
+
+// C[row0.., col0..] (M x N valid) = C0 (or C) + alpha * A (M x K) * B (K x N);
+// A, B, C, C0 point at the matrices' origins (row-major, given leading dims).
+template <int BM, int BN, int BK, int WM, int WN>
+__device__ inline void gemm_tile(const double* __restrict__ A, int lda, const double* __restrict__ B,
+                                 int ldb, double* C, int ldc, const double* C0, int ldc0, int M,
+                                 int N, int K, double alpha, int row0, int col0, double* sm) {
+  using T = GemmTile<BM, BN, BK, WM, WN>;
+  double(*As)[BM + 1] = reinterpret_cast<double(*)[BM + 1]>(sm);
+  double(*Bs)[BN + 1] = reinterpret_cast<double(*)[BN + 1]>(sm + BK * (BM + 1));
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int wm = wid >> 1, wn = wid & 1;
-  const int row0 = tm * TBM, col0 = tn * TBN;
-  d4 acc[2][2];
+  const int wm = wid / WN, wn = wid % WN;
+  constexpr int WBM = BM / WM, WBN = BN / WN;
+  d4 acc[T::FM][T::FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < T::FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int kt = 0; kt < K; kt += TBK) {
+    for (int j = 0; j < T::FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int kt = 0; kt < K; kt += BK) {
 #pragma unroll
-    for (int e = 0; e < (TBM * TBK) / 256; ++e) {
-      int idx = tid + 256 * e;
-      int i = idx / TBK, k = idx % TBK;
-      int gr = row0 + i, gk = kt + k;
+    for (int e = 0; e < (BM * BK) / T::NT; ++e) {
+      const int idx = tid + T::NT * e;
+      const int i = idx / BK, k = idx % BK;
+      const int gr = row0 + i, gk = kt + k;
       As[k][i] = (gr < M && gk < K) ? A[(size_t)gr * lda + gk] : 0.0;
     }
 #pragma unroll
-    for (int e = 0; e < (TBK * TBN) / 256; ++e) {
-      int idx = tid + 256 * e;
-      int k = idx / TBN, j = idx % TBN;
-      int gk = kt + k, gc = col0 + j;
+    for (int e = 0; e < (BK * BN) / T::NT; ++e) {
+      const int idx = tid + T::NT * e;
+      const int k = idx / BN, j = idx % BN;
+      const int gk = kt + k, gc = col0 + j;
       Bs[k][j] = (gk < K && gc < N) ? B[(size_t)gk * ldb + gc] : 0.0;
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < TBK; kk += 4) {
-      double a[2], b[2];
+    for (int kk = 0; kk < BK; kk += 4) {
+      double a[T::FM], b[T::FN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[kk + (lane >> 4)][wm * 32 + i * 16 + (lane & 15)];
+      for (int i = 0; i < T::FM; ++i) a[i] = As[kk + (lane >> 4)][wm * WBM + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[kk + (lane >> 4)][wn * 32 + j * 16 + (lane & 15)];
+      for (int j = 0; j < T::FN; ++j) b[j] = Bs[kk + (lane >> 4)][wn * WBN + j * 16 + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < T::FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < T::FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < T::FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < T::FN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int gr = row0 + wm * 32 + i * 16 + (lane >> 4) + 4 * r;
-        int gc = col0 + wn * 32 + j * 16 + (lane & 15);
+        const int gr = row0 + wm * WBM + i * 16 + (lane >> 4) + 4 * r;
+        const int gc = col0 + wn * WBN + j * 16 + (lane & 15);
         if (gr < M && gc < N) {
-          double c0 = C0 ? C0[(size_t)gr * ldc0 + gc] : C[(size_t)gr * ldc + gc];
+          const double c0 = C0 ? C0[(size_t)gr * ldc0 + gc] : C[(size_t)gr * ldc + gc];
           C[(size_t)gr * ldc + gc] = c0 + alpha * acc[i][j][r];
         }
       }
@@ -364,38 +382,39 @@ __device__ inline void gemm_tile_f64(const double* __restrict__ A, int lda,
 // Gauss-Jordan update: rows outside the pivot block [k0, k0+kb) get
 // A[i, k0+kb:] -= A[i, k0:k0+kb] R.  Row tiles 0 .. ta-1 cover rows [0, k0),
 // the rest cover rows [k0+kb, n).
-__global__ void __launch_bounds__(256) k_gj_update(const SolveDesc* __restrict__ descs, int k0,
-                                                   int nb) {
-  __shared__ double As[TBK][TBM + 1];
-  __shared__ double Bs[TBK][TBN + 1];
+template <int BM, int BN, int BK, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN) k_gj_update(const SolveDesc* __restrict__ descs,
+                                                           int k0, int nb) {
+  __shared__ double sm[GemmTile<BM, BN, BK, WM, WN>::SMEM];
   const SolveDesc d = descs[blockIdx.z];
   if (k0 >= d.n) return;
   const int kb = min(nb, d.n - k0);
-  const int ta = (k0 + TBM - 1) / TBM;
+  const int ta = (k0 + BM - 1) / BM;
   int r0, M;
   if ((int)blockIdx.y < ta) {
-    r0 = blockIdx.y * TBM;
-    M = min(TBM, k0 - r0);
+    r0 = blockIdx.y * BM;
+    M = min(BM, k0 - r0);
   } else {
-    r0 = k0 + kb + (blockIdx.y - ta) * TBM;
-    M = min(TBM, d.n - r0);
+    r0 = k0 + kb + (blockIdx.y - ta) * BM;
+    M = min(BM, d.n - r0);
   }
-  const int c0 = k0 + kb + blockIdx.x * TBN;
-  const int N = min(TBN, d.n + d.m - c0);
+  const int c0 = k0 + kb + blockIdx.x * BN;
+  const int N = min(BN, d.n + d.m - c0);
   if (M <= 0 || N <= 0) return;
   const size_t ld = d.ld;
-  gemm_tile_f64(d.W + (size_t)r0 * ld + k0, d.ld, d.W + (size_t)k0 * ld + c0, d.ld,
-                d.W + (size_t)r0 * ld + c0, d.ld, nullptr, 0, M, N, kb, -1.0, 0, 0, As, Bs);
+  gemm_tile<BM, BN, BK, WM, WN>(d.W + (size_t)r0 * ld + k0, d.ld, d.W + (size_t)k0 * ld + c0,
+                                d.ld, d.W + (size_t)r0 * ld + c0, d.ld, nullptr, 0, M, N, kb, -1.0,
+                                0, 0, sm);
 }
 
 // Grouped GEMM: one launch over problems, grid (tiles_n, tiles_m, nprob).
-__global__ void __launch_bounds__(256) k_gemm(const GemmDesc* __restrict__ descs) {
-  __shared__ double As[TBK][TBM + 1];
-  __shared__ double Bs[TBK][TBN + 1];
+template <int BM, int BN, int BK, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN) k_gemm(const GemmDesc* __restrict__ descs) {
+  __shared__ double sm[GemmTile<BM, BN, BK, WM, WN>::SMEM];
   const GemmDesc g = descs[blockIdx.z];
-  if ((int)blockIdx.y * TBM >= g.M || (int)blockIdx.x * TBN >= g.N) return;
-  gemm_tile_f64(g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.C0, g.ldc0, g.M, g.N, g.K, g.alpha,
-                blockIdx.y, blockIdx.x, As, Bs);
+  if ((int)blockIdx.y * BM >= g.M || (int)blockIdx.x * BN >= g.N) return;
+  gemm_tile<BM, BN, BK, WM, WN>(g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.C0, g.ldc0, g.M, g.N, g.K,
+                                g.alpha, blockIdx.y * BM, blockIdx.x * BN, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -520,8 +539,30 @@ static void launch_panel(const SolveDesc* d_desc, int np, int k0, int rows, int 
 
 int max_solve_rows() { return 3072; }
 
-void batched_solve(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc, int* d_status,
-                   hipStream_t stream, int /*nb_hint*/) {
+// Launch of one Gauss-Jordan update with tile variant v.
+static void launch_update(int v, const SolveDesc* d_desc, int np, int k0, int nb, int nmax,
+                          int rest, hipStream_t s) {
+#define HPS_UPD(BM, BN, BK, WM, WN)                                                        \
+  {                                                                                         \
+    const int ty = (k0 + BM - 1) / BM + (std::max(0, nmax - k0 - nb) + BM - 1) / BM;       \
+    if (ty > 0)                                                                             \
+      hipLaunchKernelGGL((k_gj_update<BM, BN, BK, WM, WN>), dim3((rest + BN - 1) / BN, ty, np), \
+                         dim3(64 * WM * WN), 0, s, d_desc, k0, nb);                         \
+    return;                                                                                 \
+  }
+  switch (v) {
+    case 1: HPS_UPD(32, 32, 16, 1, 1)
+    case 2: HPS_UPD(128, 128, 16, 2, 2)
+    case 3: HPS_UPD(128, 64, 16, 2, 2)
+    case 4: HPS_UPD(64, 128, 16, 2, 2)
+    case 5: HPS_UPD(64, 64, 32, 2, 2)
+    default: HPS_UPD(64, 64, 16, 2, 2)
+  }
+#undef HPS_UPD
+}
+
+void batched_solve_v(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc, int* d_status,
+                     hipStream_t stream, int gj_variant) {
   if (h_desc.empty()) return;
   int nmax = 0, wmax = 0;
   for (auto& d : h_desc) {
@@ -531,6 +572,8 @@ void batched_solve(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc
   HPS_REQUIRE(nmax <= max_solve_rows(), "dense system too large for the panel kernel");
   const int nb = nmax > 1024 ? 16 : 32;
   const int np = (int)h_desc.size();
+  const int upd = gj_variant >= 0 ? gj_variant / 4 : 0;
+  const int tb = TRSM_BLOCKS[gj_variant >= 0 ? std::min(gj_variant % 4, 2) : 0];
   for (int k0 = 0; k0 < nmax; k0 += nb) {
     double fp = 0, ft = 0, fu = 0;
     for (auto& d : h_desc) {
@@ -549,40 +592,83 @@ void batched_solve(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc
     if (rest <= 0) continue;
     {
       ProfScope ps(PROF_SWAP_TRSM, stream, ft, 0);
-      dim3 g((rest + 255) / 256, np);
+      dim3 g((rest + tb - 1) / tb, np);
       if (nb == 32)
-        hipLaunchKernelGGL((k_gj_swap_trsm<32>), g, dim3(256), 0, stream, d_desc, k0);
+        hipLaunchKernelGGL((k_gj_swap_trsm<32>), g, dim3(tb), 0, stream, d_desc, k0);
       else
-        hipLaunchKernelGGL((k_gj_swap_trsm<16>), g, dim3(256), 0, stream, d_desc, k0);
+        hipLaunchKernelGGL((k_gj_swap_trsm<16>), g, dim3(tb), 0, stream, d_desc, k0);
     }
-    const int ty = (k0 + TBM - 1) / TBM + (std::max(0, nmax - k0 - nb) + TBM - 1) / TBM;
-    if (ty > 0) {
+    {
       ProfScope ps(PROF_LU_UPDATE, stream, fu, 0);
-      hipLaunchKernelGGL(k_gj_update, dim3((rest + TBN - 1) / TBN, ty, np), dim3(256), 0, stream,
-                         d_desc, k0, nb);
+      launch_update(upd, d_desc, np, k0, nb, nmax, rest, stream);
     }
   }
 }
 
-void grouped_gemm(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, hipStream_t stream,
-                  bool split32) {
+void batched_solve(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc, int* d_status,
+                   hipStream_t stream, int /*nb_hint*/) {
+  if (h_desc.empty()) return;
+  int nmax = 0, wmax = 0;
+  for (auto& d : h_desc) {
+    nmax = std::max(nmax, d.n);
+    wmax = std::max(wmax, d.n + d.m);
+  }
+  const int v = tune_get(TUNE_GJ, tune_lg(nmax), tune_lg(wmax), tune_lg((long long)h_desc.size()), 0);
+  batched_solve_v(d_desc, h_desc, d_status, stream, v);
+}
+
+void grouped_gemm_v(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, hipStream_t stream,
+                    int variant, bool split32) {
   if (h_desc.empty()) return;
   int mmax = 0, nmax = 0;
   for (auto& g : h_desc) {
     mmax = std::max(mmax, g.M);
     nmax = std::max(nmax, g.N);
   }
-  dim3 grid((nmax + TBN - 1) / TBN, (mmax + TBM - 1) / TBM, (unsigned)h_desc.size());
   double fl = 0, by = 0;
   for (auto& g : h_desc) {
     fl += 2.0 * g.M * g.N * g.K;
     by += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + 2.0 * g.M * g.N);
   }
+  const unsigned np = (unsigned)h_desc.size();
   ProfScope ps(split32 ? PROF_GEMM_SPLIT32 : PROF_GEMM, stream, fl, by);
-  if (split32)
+  if (split32) {
+    dim3 grid((nmax + TBN - 1) / TBN, (mmax + TBM - 1) / TBM, np);
     hipLaunchKernelGGL(k_gemm_split32, grid, dim3(256), 0, stream, d_desc);
-  else
-    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, stream, d_desc);
+    return;
+  }
+#define HPS_GEMM(BM, BN, BK, WM, WN)                                                            \
+  {                                                                                             \
+    hipLaunchKernelGGL((k_gemm<BM, BN, BK, WM, WN>), dim3((nmax + BN - 1) / BN, (mmax + BM - 1) / BM, np), \
+                       dim3(64 * WM * WN), 0, stream, d_desc);                                  \
+    return;                                                                                     \
+  }
+  switch (variant) {
+    case 1: HPS_GEMM(32, 32, 16, 1, 1)
+    case 2: HPS_GEMM(128, 128, 16, 2, 2)
+    case 3: HPS_GEMM(128, 64, 16, 2, 2)
+    case 4: HPS_GEMM(64, 128, 16, 2, 2)
+    case 5: HPS_GEMM(64, 64, 32, 2, 2)
+    default: HPS_GEMM(64, 64, 16, 2, 2)
+  }
+#undef HPS_GEMM
+}
+
+int gemm_bucket_variant(const std::vector<GemmDesc>& h_desc) {
+  int mmax = 0, nmax = 0, kmax = 0;
+  for (auto& g : h_desc) {
+    mmax = std::max(mmax, g.M);
+    nmax = std::max(nmax, g.N);
+    kmax = std::max(kmax, g.K);
+  }
+  return tune_get(TUNE_GEMM, tune_lg(mmax), tune_lg(nmax), tune_lg(kmax),
+                  tune_lg((long long)h_desc.size()));
+}
+
+void grouped_gemm(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, hipStream_t stream,
+                  bool split32) {
+  if (h_desc.empty()) return;
+  grouped_gemm_v(d_desc, h_desc, stream, split32 ? 0 : gemm_bucket_variant(h_desc), split32);
 }
 
 void dense_init() {}

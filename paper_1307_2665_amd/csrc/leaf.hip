@@ -15,6 +15,7 @@
 // its column slot (TR * ks) / TC are compile-time register indices.
 #include "leaf.h"
 #include "prof.h"
+#include "tune.h"
 
 namespace hps {
 
@@ -440,7 +441,8 @@ void leaf_lu(const double* const* cptr, const LeafDev& tab, int count, double* Z
   ProfScope ps(PROF_LEAF_LU, s, count * (2.0 * n * n * n / 3.0 + 2.0 * n * n * m), 0);
   const bool small = tab.n <= 7 * 16 && tab.n + tab.m <= 9 * 16;
   // Variants: 0-2 step-by-step LU (k_leaf_lu), 3-4 blocked Gauss-Jordan (k_leaf_gj).
-  int v = g_leaf_variant >= 0 ? g_leaf_variant : (small ? 3 : 4);
+  int v = g_leaf_variant >= 0 ? g_leaf_variant : tune_get(TUNE_LEAF, tab.n, tab.m, 0, 0);
+  if (v < 0) v = small ? 3 : 4;
   if ((v == 0 || v == 3) && !small) v = (v == 0) ? 1 : 4;
   switch (v) {
     case 0:

@@ -1,0 +1,328 @@
+// Kernel-variant table and autotuner (see tune.h).
+#include "tune.h"
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <random>
+#include <set>
+#include <sstream>
+
+#include "dense.h"
+#include "leaf.h"
+#include "plan.h"
+#include "solver.h"
+
+namespace hps {
+
+namespace {
+
+struct Entry {
+  int variant;
+  double ms, ms_default;
+};
+using Key = std::array<int, 5>;
+
+struct Table {
+  std::mutex mu;
+  std::map<Key, Entry> entries;
+  int forced[TUNE_NKNOBS] = {-1, -1, -1};
+};
+
+Table& table() {
+  static Table* t = new Table();
+  return *t;
+}
+
+const char* knob_name(int k) {
+  static const char* names[TUNE_NKNOBS] = {"leaf", "gemm", "gj"};
+  return (k >= 0 && k < TUNE_NKNOBS) ? names[k] : "?";
+}
+
+}  // namespace
+
+int tune_lg(long long x) {
+  int l = 0;
+  while ((1LL << l) < x) ++l;
+  return l;
+}
+
+int tune_get(int knob, int a, int b, int c, int d) {
+  Table& T = table();
+  std::lock_guard<std::mutex> lk(T.mu);
+  if (T.forced[knob] >= 0) return T.forced[knob];
+  auto it = T.entries.find(Key{knob, a, b, c, d});
+  return it == T.entries.end() ? -1 : it->second.variant;
+}
+
+void tune_force(int knob, int variant) {
+  Table& T = table();
+  std::lock_guard<std::mutex> lk(T.mu);
+  T.forced[knob] = variant;
+}
+
+void tune_put(int knob, int a, int b, int c, int d, int variant, double ms, double ms_default) {
+  Table& T = table();
+  std::lock_guard<std::mutex> lk(T.mu);
+  T.entries[Key{knob, a, b, c, d}] = Entry{variant, ms, ms_default};
+}
+
+void tune_clear() {
+  Table& T = table();
+  std::lock_guard<std::mutex> lk(T.mu);
+  T.entries.clear();
+}
+
+std::string tune_json() {
+  Table& T = table();
+  std::lock_guard<std::mutex> lk(T.mu);
+  std::ostringstream o;
+  o << "{\n  \"format\": \"hps-tune-1\",\n  \"entries\": [\n";
+  size_t i = 0;
+  for (auto& kv : T.entries) {
+    const Key& k = kv.first;
+    char buf[256];
+    std::snprintf(buf, sizeof(buf),
+                  "    {\"knob\": %d, \"name\": \"%s\", \"key\": [%d, %d, %d, %d], \"variant\": %d, "
+                  "\"ms\": %.6g, \"default_ms\": %.6g}%s\n",
+                  k[0], knob_name(k[0]), k[1], k[2], k[3], k[4], kv.second.variant, kv.second.ms,
+                  kv.second.ms_default, ++i < T.entries.size() ? "," : "");
+    o << buf;
+  }
+  o << "  ]\n}\n";
+  return o.str();
+}
+
+void tune_load_json(const std::string& text) {
+  HPS_REQUIRE(text.find("\"hps-tune-1\"") != std::string::npos, "not a tuning cache (format hps-tune-1)");
+  std::istringstream in(text);
+  std::string line;
+  std::vector<std::pair<Key, Entry>> got;
+  while (std::getline(in, line)) {
+    const size_t p = line.find("\"knob\":");
+    if (p == std::string::npos) continue;
+    int knob, a, b, c, d, v;
+    double ms, md;
+    char name[32];
+    const int n = std::sscanf(line.c_str() + p,
+                              "\"knob\": %d, \"name\": \"%31[^\"]\", \"key\": [%d, %d, %d, %d], "
+                              "\"variant\": %d, \"ms\": %lf, \"default_ms\": %lf",
+                              &knob, name, &a, &b, &c, &d, &v, &ms, &md);
+    HPS_REQUIRE(n == 9 && knob >= 0 && knob < TUNE_NKNOBS && v >= 0,
+                "malformed tuning cache entry: " + line);
+    got.push_back({Key{knob, a, b, c, d}, Entry{v, ms, md}});
+  }
+  Table& T = table();
+  std::lock_guard<std::mutex> lk(T.mu);
+  for (auto& e : got) T.entries[e.first] = e.second;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Timer {
+  hipEvent_t a, b;
+  hipStream_t s;
+  explicit Timer(hipStream_t st) : s(st) {
+    HPS_HIP(hipEventCreate(&a));
+    HPS_HIP(hipEventCreate(&b));
+  }
+  ~Timer() {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+  void start() { HPS_HIP(hipEventRecord(a, s)); }
+  double stop() {
+    HPS_HIP(hipEventRecord(b, s));
+    HPS_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    HPS_HIP(hipEventElapsedTime(&ms, a, b));
+    return ms;
+  }
+};
+
+template <class F>
+double best_of(Timer& t, int reps, F&& f) {
+  f();  // warm-up (first launch of a kernel loads its code)
+  double best = 1e300;
+  for (int r = 0; r < reps; ++r) {
+    t.start();
+    f();
+    best = std::min(best, t.stop());
+  }
+  return best;
+}
+
+std::vector<double> random_vec(size_t n, unsigned seed, double lo, double hi) {
+  std::mt19937_64 g(seed);
+  std::uniform_real_distribution<double> u(lo, hi);
+  std::vector<double> v(n);
+  for (auto& x : v) x = u(g);
+  return v;
+}
+
+struct GemmShape {
+  int M, N, K, count;
+};
+struct GjShape {
+  int n, w, count;
+};
+
+void tune_leaf(int p, int q, double hx, double hy, int nleaf, hipStream_t s, Timer& tm) {
+  const int n = (p - 2) * (p - 2), m = 4 * q;
+  if (!leaf_lu_fits(n, m)) return;
+  if (tune_get(TUNE_LEAF, n, m, 0, 0) >= 0) return;
+  const int L = std::min(nleaf, 2048), pp = p * p;
+  std::vector<double> c((size_t)L * 6 * pp, 0.0);
+  std::mt19937_64 g(11);
+  std::uniform_real_distribution<double> u(0.0, 1.0);
+  for (int l = 0; l < L; ++l)
+    for (int k = 0; k < pp; ++k) {
+      double* cl = c.data() + (size_t)l * 6 * pp;
+      cl[0 * pp + k] = 1.0 + 0.3 * u(g);
+      cl[2 * pp + k] = 1.0 + 0.3 * u(g);
+      cl[3 * pp + k] = 0.5 * u(g);
+      cl[4 * pp + k] = 0.5 * u(g);
+    }
+  DeviceMem mem;
+  double* dc = mem.upload(c, s);
+  std::vector<const double*> cp(L);
+  for (int l = 0; l < L; ++l) cp[l] = dc + (size_t)l * 6 * pp;
+  const double** dcp = mem.upload(cp, s);
+  double* Z = mem.alloc<double>((size_t)L * n * m);
+  int* st = mem.alloc<int>(4);
+  HPS_HIP(hipMemsetAsync(st, 0, 4 * sizeof(int), s));
+  std::shared_ptr<const LeafPlan> lp = leaf_plan(p, q, hx, hy, s);
+  LeafDev tab{lp->dDx, lp->dDy, lp->dDxx, lp->dDyy, lp->dG, p, n, m, 0};
+  const bool small = n <= 7 * 16 && n + m <= 9 * 16;
+  const std::vector<int> cand = small ? std::vector<int>{0, 3} : std::vector<int>{1, 2, 4};
+  const int dflt = small ? 3 : 4;
+  double best = 1e300, tdef = 0;
+  int bv = dflt;
+  for (int v : cand) {
+    leaf_lu_set_variant(v);
+    const double t = best_of(tm, 2, [&] { leaf_lu(dcp, tab, L, Z, st, 0, s); });
+    if (v == dflt) tdef = t;
+    if (t < best) {
+      best = t;
+      bv = v;
+    }
+  }
+  leaf_lu_set_variant(-1);
+  tune_put(TUNE_LEAF, n, m, 0, 0, bv, best, tdef);
+}
+
+void tune_gemm(const GemmShape& g, hipStream_t s, Timer& tm) {
+  const int a = tune_lg(g.M), b = tune_lg(g.N), c = tune_lg(g.K), d = tune_lg(g.count);
+  if (tune_get(TUNE_GEMM, a, b, c, d) >= 0) return;
+  DeviceMem mem;
+  const size_t sa = (size_t)g.M * g.K, sb = (size_t)g.K * g.N, sc = (size_t)g.M * g.N;
+  double* A = mem.upload(random_vec(sa * g.count, 1, -1, 1), s);
+  double* B = mem.upload(random_vec(sb * g.count, 2, -1, 1), s);
+  double* C = mem.alloc<double>(sc * g.count);
+  HPS_HIP(hipMemsetAsync(C, 0, sc * g.count * sizeof(double), s));
+  std::vector<GemmDesc> hd(g.count);
+  for (int i = 0; i < g.count; ++i)
+    hd[i] = GemmDesc{A + sa * i, B + sb * i, C + sc * i, nullptr, g.M, g.N, g.K, g.K, g.N, g.N, 0, 1.0};
+  GemmDesc* dd = mem.upload(hd, s);
+  double best = 1e300, tdef = 0;
+  int bv = 0;
+  for (int v = 0; v < GEMM_VARIANTS; ++v) {
+    const double t = best_of(tm, 3, [&] { grouped_gemm_v(dd, hd, s, v, false); });
+    if (v == 0) tdef = t;
+    if (t < best) {
+      best = t;
+      bv = v;
+    }
+  }
+  tune_put(TUNE_GEMM, a, b, c, d, bv, best, tdef);
+}
+
+void tune_gj(const GjShape& g, hipStream_t s, Timer& tm) {
+  const int a = tune_lg(g.n), b = tune_lg(g.w), c = tune_lg(g.count);
+  if (tune_get(TUNE_GJ, a, b, c, 0) >= 0) return;
+  DeviceMem mem;
+  const size_t per = (size_t)g.n * g.w;
+  std::vector<double> h = random_vec(per * g.count, 3, -1, 1);
+  for (int i = 0; i < g.count; ++i)
+    for (int r = 0; r < g.n; ++r) h[per * i + (size_t)r * g.w + r] += 2.0 * g.n;  // well conditioned
+  double* W0 = mem.upload(h, s);
+  double* W = mem.alloc<double>(per * g.count);
+  int* piv = mem.alloc<int>((size_t)g.n * g.count);
+  int* st = mem.alloc<int>(4);
+  HPS_HIP(hipMemsetAsync(st, 0, 4 * sizeof(int), s));
+  std::vector<SolveDesc> hd(g.count);
+  for (int i = 0; i < g.count; ++i)
+    hd[i] = SolveDesc{W + per * i, piv + (size_t)g.n * i, W + per * i + g.n, g.n, g.w - g.n, g.w, g.w, i, 0};
+  SolveDesc* dd = mem.upload(hd, s);
+  double best = 1e300, tdef = 0;
+  int bv = 0;
+  for (int upd = 0; upd < GEMM_VARIANTS; ++upd)
+    for (int tb = 0; tb < 3; ++tb) {
+      const int v = upd * 4 + tb;
+      // Each timed solve starts from the pristine systems (the copy is not timed).
+      auto run = [&] {
+        HPS_HIP(hipMemcpyAsync(W, W0, per * g.count * sizeof(double), hipMemcpyDeviceToDevice, s));
+        tm.start();
+        batched_solve_v(dd, hd, st, s, v);
+        return tm.stop();
+      };
+      run();
+      const double t = std::min(run(), run());
+      if (v == 0) tdef = t;
+      if (t < best) {
+        best = t;
+        bv = v;
+      }
+    }
+  tune_put(TUNE_GJ, a, b, c, 0, bv, best, tdef);
+}
+
+}  // namespace
+
+double autotune(const std::vector<TuneShape>& shapes, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  Timer tm(s);
+  std::vector<GemmShape> gemms;
+  std::vector<GjShape> gjs;
+  std::set<std::array<int, 4>> seen_g, seen_j;
+  for (const TuneShape& sh : shapes) {
+    HPS_REQUIRE(sh.nx >= 1 && sh.ny >= 1 && sh.p >= 4 && sh.p <= 24 && sh.q >= 1 && sh.q <= sh.p &&
+                    sh.hx > 0 && sh.hy > 0,
+                "bad shape for the autotuner");
+    tune_leaf(sh.p, sh.q, sh.hx, sh.hy, sh.nx * sh.ny, s, tm);
+    const int n = (sh.p - 2) * (sh.p - 2), m = 4 * sh.q;
+    // The leaf DtN product T = P0 - P1 Z.
+    GemmShape lt{m, m, n, sh.nx * sh.ny};
+    if (seen_g.insert({tune_lg(lt.M), tune_lg(lt.N), tune_lg(lt.K), tune_lg(lt.count)}).second)
+      gemms.push_back(lt);
+    const Tree t = build_tree(sh.nx, sh.ny, sh.q);
+    for (int d = 0; d <= t.depth; ++d) {
+      if (t.parents_at_level[d].empty()) continue;
+      int me = 0, m3 = 0;
+      for (int b : t.parents_at_level[d]) {
+        const MergeMaps g = merge_maps(t, b);
+        me = std::max(me, g.me);
+        m3 = std::max(m3, g.m3);
+      }
+      const int cnt = (int)t.parents_at_level[d].size();
+      GemmShape gs{me, me, m3, cnt};
+      if (seen_g.insert({tune_lg(me), tune_lg(me), tune_lg(m3), tune_lg(cnt)}).second)
+        gemms.push_back(gs);
+      GjShape js{m3, m3 + me + (sh.keep_factors ? m3 : 0), cnt};
+      if (seen_j.insert({tune_lg(js.n), tune_lg(js.w), tune_lg(cnt), 0}).second) gjs.push_back(js);
+    }
+  }
+  for (const GemmShape& g : gemms) tune_gemm(g, s, tm);
+  for (const GjShape& g : gjs) tune_gj(g, s, tm);
+  HPS_HIP(hipStreamSynchronize(s));
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace hps

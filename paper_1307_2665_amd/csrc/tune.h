@@ -1,0 +1,44 @@
+// Kernel-variant selection per shape bucket, and the autotuner that fills it.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace hps {
+
+enum TuneKnob {
+  TUNE_LEAF = 0,  // leaf kernel variant; key (n, m)
+  TUNE_GEMM = 1,  // FP64 MFMA tile variant; key (lg M, lg N, lg K, lg count)
+  TUNE_GJ = 2,    // Gauss-Jordan update tile * 4 + TRSM block code; key (lg n, lg n+m, lg count)
+  TUNE_NKNOBS = 3
+};
+
+constexpr int GEMM_VARIANTS = 6;   // tiles of gemm_tile (dense.hip)
+constexpr int TRSM_BLOCKS[3] = {256, 128, 64};
+
+// ceil(log2(x)) for x >= 1.
+int tune_lg(long long x);
+
+// Variant for a shape key: a forced value (hps_tune_set) first, then the
+// table, else -1 (callers fall back to their default).
+int tune_get(int knob, int a, int b, int c, int d);
+void tune_force(int knob, int variant);  // -1 removes the force
+void tune_put(int knob, int a, int b, int c, int d, int variant, double ms, double ms_default);
+void tune_clear();
+std::string tune_json();
+void tune_load_json(const std::string& text);
+
+// Shape of a problem to tune for (coefficients are not needed).
+struct TuneShape {
+  int nx, ny, p, q;
+  double hx, hy;
+  bool keep_factors;
+};
+// Times the variants of every kernel the builds of these shapes launch, on
+// synthetic data of the same shapes, and records the fastest per bucket.
+// Returns the seconds spent.
+double autotune(const std::vector<TuneShape>& shapes, hipStream_t s);
+
+}  // namespace hps

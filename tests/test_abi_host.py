@@ -136,3 +136,39 @@ def test_invalid_arguments_are_rejected_on_host():
         H.leaf_tables(3, 2, 0.1, 0.1)            # p < 4
     with pytest.raises(H.HpsError):
         H.plan_box((0, 3), 4, 0)                 # empty grid
+
+
+def test_tuning_cache_round_trip(tmp_path):
+    """The tuning table's JSON cache loads, saves back the same entries, and
+    malformed files or knob values are rejected (host code only)."""
+    import json
+    import paper_1307_2665_amd as H
+    H.tune_reset()
+    entries = [
+        {"knob": 1, "name": "gemm", "key": [6, 6, 4, 11], "variant": 2, "ms": 0.5, "default_ms": 0.75},
+        {"knob": 2, "name": "gj", "key": [10, 13, 0, 0], "variant": 9, "ms": 3.25, "default_ms": 4.5},
+        {"knob": 0, "name": "leaf", "key": [196, 56, 0, 0], "variant": 4, "ms": 6.0, "default_ms": 6.0},
+    ]
+    src = tmp_path / "in.json"
+    src.write_text('{\n  "format": "hps-tune-1",\n  "entries": [\n' +
+                   ",\n".join("    " + json.dumps(e) for e in entries) + "\n  ]\n}\n")
+    H.tune_load(src)
+    out = tmp_path / "out.json"
+    H.tune_save(out)
+    got = json.loads(out.read_text())
+    assert got["format"] == "hps-tune-1"
+    key = lambda e: (e["knob"], tuple(e["key"]))
+    assert sorted(((key(e), e["variant"]) for e in got["entries"])) == \
+        sorted(((key(e), e["variant"]) for e in entries))
+    H.tune_reset()
+    H.tune_save(out)
+    assert json.loads(out.read_text())["entries"] == []
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"entries": []}')
+    with pytest.raises(H.HpsError) as e:
+        H.tune_load(bad)
+    assert e.value.status == H.HPS_EINVAL
+    for knob, v in (("gemm_variant", 6), ("gj_variant", 3), ("leaf_variant", 5), ("nope", 0)):
+        with pytest.raises(H.HpsError) as e:
+            H.tune_set(knob, v)
+        assert e.value.status == H.HPS_EINVAL
