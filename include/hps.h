@@ -294,7 +294,9 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
    "gemm_variant": FP64 MFMA GEMM tile (0: 64x64x16 on 2x2 waves, 1: 32x32x16
      on one wave, 2: 128x128x16, 3: 128x64x16, 4: 64x128x16, 5: 64x64x32);
    "gj_variant": merge solver, 4 * (update tile, as gemm_variant) + TRSM block
-     (0: 256, 1: 128, 2: 64 threads).
+     (0: 256, 1: 128, 2: 64 threads);
+   "solve_graph": 1 (default) runs plain solves as a captured HIP graph per
+     operator and right-hand-side count, 0 launches kernel by kernel.
    Unknown knobs or values give HPS_EINVAL. */
 hps_status hps_tune_set(const char* knob, int value);
 

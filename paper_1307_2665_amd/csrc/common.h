@@ -83,10 +83,12 @@ struct MergeDesc {
   int inv, pad;       // inv = 1: W carries the identity block, giving M^-1 at W + m3 + me
 };
 
-// Solution array of the problem a merge belongs to (downward pass).
+// Solution array of the problem a merge belongs to (downward pass), and its
+// boundary data (used by the graph-captured solve, which reads both here).
 struct SolveIO {
   double* u;       // [nrhs][N]
   int N, nrhs;
+  const double* f = nullptr;  // [nrhs][n_bdry]
 };
 
 }  // namespace hps

@@ -24,11 +24,15 @@ void merge_gather(const MergeDesc* d_desc, int nmerge, size_t max_elems, hipStre
 // Downward pass of one depth; io[i] gives merge i's solution array (io null:
 // every merge uses io0).  s_bytes: bytes of all S of the launch (its
 // algorithmic traffic per RHS chunk).
+// d_io: per-merge SolveIO array, or (io_shared) one SolveIO for all merges;
+// null: io0 (passed by value) for all merges.
 void downward(const MergeDesc* d_desc, const SolveIO* d_io, const SolveIO& io0, int nmerge,
               int m3_max, int me_max, int nrhs_max, const double* zbase, const long long* zoff,
-              hipStream_t s, double s_bytes);
+              hipStream_t s, double s_bytes, bool io_shared = false);
 void set_boundary(const double* f, const int* gamma, int nb, double* u, int N, int nrhs,
                   hipStream_t s);
+// u[r][gamma[i]] = f[r][i] with f, u, N, nrhs read from *io on the device.
+void set_boundary_io(const SolveIO* io, const int* gamma, int nb, int nrhs, hipStream_t s);
 void interface_residual(const double* leafT, const double* u, int N, int nrhs, int nx, int ny,
                         int q, double* vbuf, double* r, hipStream_t s);
 void upward_level(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, const double* s,

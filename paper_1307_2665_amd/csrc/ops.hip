@@ -123,21 +123,24 @@ void merge_gather(const MergeDesc* d_desc, int nmerge, size_t max_elems, hipStre
 
 // ---------------------------------------------------------------------------
 // Downward pass (Algorithm 2, line 3): u(I_i) = S u(I_e) (+ z) for every merge
-// of one level.  u is [nrhs][N].  A workgroup owns DROWS rows of one S; the
-// gathered boundary values of up to RC right-hand sides sit in LDS.
+// of one level.  u is [nrhs][N].  A workgroup owns rpb rows of one S (the host
+// picks rpb so that a level launches enough workgroups to fill the chip); the
+// gathered boundary values of up to rc right-hand sides sit in LDS.  Each
+// wave streams one row of S at a time (64 consecutive doubles per load) and
+// applies it to four right-hand sides at once, so S is read once per four.
 // ---------------------------------------------------------------------------
-constexpr int DROWS = 16;
+constexpr int DRHS = 4;
 
 __global__ void __launch_bounds__(256) k_downward(const MergeDesc* __restrict__ descs,
                                                   const SolveIO* __restrict__ io,
-                                                  const SolveIO io0, int rc,
-                                                  const double* __restrict__ zbase,
+                                                  const SolveIO io0, int io_shared, int rc,
+                                                  int rpb, const double* __restrict__ zbase,
                                                   const long long* __restrict__ zoff) {
   extern __shared__ double ue[];
   const MergeDesc d = descs[blockIdx.y];
-  const int r0 = blockIdx.x * DROWS;
+  const int r0 = blockIdx.x * rpb;
   if (r0 >= d.m3) return;
-  const SolveIO b = io ? io[blockIdx.y] : io0;
+  const SolveIO b = io ? io[io_shared ? 0 : blockIdx.y] : io0;
   double* u = b.u;
   const int N = b.N, nrhs = b.nrhs, me = d.me;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -147,21 +150,35 @@ __global__ void __launch_bounds__(256) k_downward(const MergeDesc* __restrict__ 
     const int nr = min(rc, nrhs - rb);
     __syncthreads();
     for (int e = threadIdx.x; e < nr * me; e += blockDim.x) {
-      int k = e / me, c = e % me;
+      const int k = e / me, c = e % me;
       ue[e] = u[(size_t)(rb + k) * N + d.Ie[c]];
     }
     __syncthreads();
-    for (int rr = wid; rr < DROWS; rr += 4) {
+    for (int rr = wid; rr < rpb; rr += 4) {
       const int r = r0 + rr;
       if (r >= d.m3) break;
       const double* Srow = d.S + (size_t)r * d.ldw;
-      for (int k = 0; k < nr; ++k) {
-        double acc = 0.0;
-        for (int c = lane; c < me; c += 64) acc += Srow[c] * ue[k * me + c];
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if (lane == 0) {
-          if (z) acc += z[(size_t)(rb + k) * d.m3 + r];
-          u[(size_t)(rb + k) * N + d.Ii[r]] = acc;
+      for (int k0 = 0; k0 < nr; k0 += DRHS) {
+        double acc[DRHS];
+#pragma unroll
+        for (int j = 0; j < DRHS; ++j) acc[j] = 0.0;
+#pragma unroll 4
+        for (int c = lane; c < me; c += 64) {
+          const double sv = Srow[c];
+#pragma unroll
+          for (int j = 0; j < DRHS; ++j)
+            if (k0 + j < nr) acc[j] += sv * ue[(k0 + j) * me + c];
+        }
+#pragma unroll
+        for (int j = 0; j < DRHS; ++j) {
+          double v = acc[j];
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+          if (lane == 0 && k0 + j < nr) {
+            const int k = rb + k0 + j;
+            if (z) v += z[(size_t)k * d.m3 + r];
+            u[(size_t)k * N + d.Ii[r]] = v;
+          }
         }
       }
     }
@@ -175,14 +192,19 @@ int downward_rhs_chunk(int me_max, int nrhs) {
 
 void downward(const MergeDesc* d_desc, const SolveIO* d_io, const SolveIO& io0, int nmerge,
               int m3_max, int me_max, int nrhs_max, const double* zbase, const long long* zoff,
-              hipStream_t s, double s_bytes) {
+              hipStream_t s, double s_bytes, bool io_shared) {
   HPS_REQUIRE((size_t)me_max * sizeof(double) <= 96 * 1024,
               "downward pass: box boundary too long for the LDS-staged kernel");
   const int rc = downward_rhs_chunk(me_max, nrhs_max);
   size_t shm = (size_t)rc * me_max * sizeof(double);
-  dim3 grid((m3_max + DROWS - 1) / DROWS, nmerge);
+  // Rows per workgroup: 4 to 16, fewer when the level is small, so that a
+  // level has about 2048 workgroups where it can.
+  const long long rows = (long long)nmerge * m3_max;
+  const int rpb = (int)std::min<long long>(16, std::max<long long>(4, rows / 2048 / 4 * 4));
+  dim3 grid((m3_max + rpb - 1) / rpb, nmerge);
   ProfScope ps(PROF_DOWNWARD, s, 2.0 * nrhs_max * s_bytes / 8.0, s_bytes);
-  hipLaunchKernelGGL(k_downward, grid, dim3(256), shm, s, d_desc, d_io, io0, rc, zbase, zoff);
+  hipLaunchKernelGGL(k_downward, grid, dim3(256), shm, s, d_desc, d_io, io0, io_shared ? 1 : 0, rc,
+                     rpb, zbase, zoff);
 }
 
 // Boundary data into u: u[r][gamma[i]] = f[r][i].
@@ -194,6 +216,24 @@ __global__ void k_set_boundary(const double* __restrict__ f, const int* __restri
     int r = (int)(e / nb), i = (int)(e % nb);
     u[(size_t)r * N + gamma[i]] = f[e];
   }
+}
+
+// The same with f, u, N and nrhs read from a device-side SolveIO (graph replay).
+__global__ void k_set_boundary_io(const SolveIO* __restrict__ io, const int* __restrict__ gamma,
+                                  int nb) {
+  const SolveIO b = *io;
+  size_t tot = (size_t)nb * b.nrhs;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    int r = (int)(e / nb), i = (int)(e % nb);
+    b.u[(size_t)r * b.N + gamma[i]] = b.f[e];
+  }
+}
+
+void set_boundary_io(const SolveIO* io, const int* gamma, int nb, int nrhs, hipStream_t s) {
+  size_t tot = (size_t)nb * nrhs;
+  int blocks = (int)std::min<size_t>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_set_boundary_io, dim3(std::max(blocks, 1)), dim3(256), 0, s, io, gamma, nb);
 }
 
 void set_boundary(const double* f, const int* gamma, int nb, double* u, int N, int nrhs,

@@ -30,7 +30,12 @@ hipEvent_t take_event() {
 }
 }  // namespace
 
-bool prof_on(int cls) { return (g_mask >> cls) & 1u; }
+thread_local int t_paused = 0;
+
+bool prof_on(int cls) { return t_paused == 0 && ((g_mask >> cls) & 1u); }
+
+ProfPause::ProfPause() { ++t_paused; }
+ProfPause::~ProfPause() { --t_paused; }
 
 ProfScope::ProfScope(int cls, hipStream_t s, double flops, double bytes) : s_(s) {
   if (!prof_on(cls)) return;

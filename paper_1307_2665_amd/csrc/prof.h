@@ -27,6 +27,14 @@ enum ProfClass {
 
 bool prof_on(int cls);
 
+// While alive, this thread records no events (used around graph capture,
+// whose launches are timed as a whole when the graph is replayed).
+class ProfPause {
+ public:
+  ProfPause();
+  ~ProfPause();
+};
+
 // Records a start event on construction and a stop event on destruction when
 // the class is enabled; flops/bytes are the launch's algorithmic work.
 class ProfScope {

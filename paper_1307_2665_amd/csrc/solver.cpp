@@ -26,6 +26,7 @@
 #include "dense.h"
 #include "leaf.h"
 #include "ops.h"
+#include "prof.h"
 #include "surrogate.h"
 
 namespace hps {
@@ -40,6 +41,16 @@ void* DeviceMem::raw(size_t b) {
   bytes += b;
   return p;
 }
+
+}  // namespace hps
+
+hps_op::~hps_op() {
+  for (auto& kv : solve_graphs) (void)hipGraphExecDestroy(kv.second);
+  if (h_io) (void)hipHostFree(h_io);
+  if (capture_stream) (void)hipStreamDestroy(capture_stream);
+}
+
+namespace hps {
 
 static void init_runtime() {
   dense_init();
@@ -657,9 +668,62 @@ static void downward_all(hps_op* op, double* u, int nrhs, const double* z, hipSt
   downward_batch({op}, {u}, {nrhs}, z, s);
 }
 
+static bool g_solve_graph = true;
+
+void set_solve_graph(bool on) { g_solve_graph = on; }
+
+// Algorithm 2 as one graph per right-hand-side count: the boundary data go
+// into u, then one downward launch per level.  Captured once on a private
+// stream (kernels read f and u from op->d_io, so the graph's arguments never
+// change) and replayed on the caller's stream after d_io is refreshed.
 void solve_device(hps_op* op, const double* f, int nrhs, double* u, hipStream_t s) {
-  set_boundary(f, op->gamma, op->n_bdry, u, op->tree().N, nrhs, s);
-  downward_all(op, u, nrhs, nullptr, s);
+  // The first solve with a right-hand-side count runs launch by launch; the
+  // graph is captured on the second (an operator solved once does not pay
+  // for the capture).
+  const bool first = op->solve_counts[nrhs]++ == 0;
+  if (!g_solve_graph || first) {
+    set_boundary(f, op->gamma, op->n_bdry, u, op->tree().N, nrhs, s);
+    downward_all(op, u, nrhs, nullptr, s);
+    return;
+  }
+  if (!op->d_io) {
+    op->d_io = op->mem.alloc<SolveIO>(1);
+    HPS_HIP(hipHostMalloc((void**)&op->h_io, sizeof(SolveIO), hipHostMallocDefault));
+  }
+  auto it = op->solve_graphs.find(nrhs);
+  if (it == op->solve_graphs.end()) {
+    if (!op->capture_stream)
+      HPS_HIP(hipStreamCreateWithFlags(&op->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = op->capture_stream;
+    hipGraph_t g = nullptr;
+    {
+      ProfPause pause;  // no profiling events inside the capture
+      HPS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      set_boundary_io(op->d_io, op->gamma, op->n_bdry, nrhs, cs);
+      for (const LevelPlan& L : op->levels) {
+        if (L.h.empty()) continue;
+        double sb = 0;
+        for (const MergeDesc& m : L.h) sb += 8.0 * m.m3 * m.me;
+        downward(L.d, op->d_io, SolveIO{}, (int)L.h.size(), L.m3_max, L.me_max, nrhs, nullptr,
+                 nullptr, cs, sb, true);
+      }
+      HPS_HIP(hipStreamEndCapture(cs, &g));
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HPS_HIP(e);
+    it = op->solve_graphs.emplace(nrhs, ex).first;
+  }
+  // Every call waits for its stream before returning, so the staging buffer
+  // is free again here.
+  *op->h_io = SolveIO{u, op->tree().N, nrhs, f};
+  HPS_HIP(hipMemcpyAsync(op->d_io, op->h_io, sizeof(SolveIO), hipMemcpyHostToDevice, s));
+  double sb = 0;
+  for (const LevelPlan& L : op->levels)
+    for (const MergeDesc& m : L.h) sb += 8.0 * m.m3 * m.me;
+  ProfScope ps(PROF_DOWNWARD, s, 2.0 * nrhs * sb / 8.0, sb);
+  HPS_HIP(hipGraphLaunch(it->second, s));
 }
 
 void solve_batch_device(const std::vector<hps_op*>& ops, const std::vector<const double*>& f,

@@ -1,6 +1,7 @@
 // Operator object and the build/solve drivers behind the C ABI.
 #pragma once
 
+#include <map>
 #include <memory>
 #include <vector>
 
@@ -124,8 +125,20 @@ struct hps_op {
   double judge_tol = 1e-6;
   double judge_worst = 0.0;             // worst judged error in the random sample
   int n_judged = 0;                     // leaves re-solved in FP64 by the judge
+  // Graph-captured plain solves (Algorithm 2), one executable graph per
+  // right-hand-side count; f and u reach the kernels through d_io.
+  std::map<int, hipGraphExec_t> solve_graphs;
+  std::map<int, int> solve_counts;    // plain solves so far, per right-hand-side count
+  hps::SolveIO* d_io = nullptr;       // device copy of the current solve's f, u
+  hps::SolveIO* h_io = nullptr;       // pinned host staging of it
+  hipStream_t capture_stream = nullptr;
+
   const hps::Tree& tree() const { return plan->tree; }
   const hps::LeafPlan& leaf() const { return *plan->leaf; }
+  hps_op() = default;
+  hps_op(const hps_op&) = delete;
+  hps_op& operator=(const hps_op&) = delete;
+  ~hps_op();
 };
 
 namespace hps {
@@ -152,5 +165,7 @@ void solve_with_sources_device(hps_op* op, const double* f, const double* src, i
                                hipStream_t s);
 void root_apply_device(const hps_op* op, const double* f, int nrhs, double* v, hipStream_t s);
 double absmax_device(const double* x, size_t n, hipStream_t s);
+// Plain solves through captured graphs (default on); off = launch by launch.
+void set_solve_graph(bool on);
 
 }  // namespace hps

@@ -117,3 +117,29 @@ def test_autotune_then_build_matches_oracle(H, gpu, tmp_path):
     say(f"tuned build vs oracle: u {e:.2e}")
     assert e < 1e-10
     H.tune_reset()
+
+
+def test_graph_solve_replays_match_eager(H, gpu):
+    """The captured solve graph, replayed many times with different boundary
+    data, right-hand-side counts and output buffers, with eager work and
+    synchronisation in between, gives exactly the launch-by-launch result."""
+    import torch
+    pr = hi.helmholtz_bump(nleaf=(8, 8), p=12, q=10, nrhs=3)
+    C, f = library_inputs(pr)
+    op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q)
+    rng = np.random.default_rng(9)
+    for it in range(6):
+        nrhs = (1, 3, 2)[it % 3]
+        fr = _t(rng.standard_normal((nrhs, op.n_bdry)), gpu)
+        H.tune_set("solve_graph", 0)
+        ue = op.solve(fr).clone()
+        H.tune_set("solve_graph", 1)
+        junk = torch.randn(1000, device=gpu, dtype=torch.float64).sum()  # eager work between
+        torch.cuda.synchronize()
+        ug = op.solve(fr)
+        assert torch.equal(ug, ue), it
+    op_o, C_o, f_o, grid = oracle_problem(pr)
+    u_o = hps.solve(op_o, f_o)
+    ug = op.solve(_t(f, gpu)).cpu().numpy()
+    assert max(rel_err(ug[k], u_o[k]) for k in range(u_o.shape[0])) < 1e-10
+    del junk
