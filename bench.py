@@ -31,6 +31,25 @@ BOUND_OF = {"gemm": ("mfma", "mfma_f64"), "lu_update": ("mfma", "mfma_f64"),
             "downward": ("hbm", "hbm")}
 # FP64 vector ALU peak: 256 CUs x 2.4 GHz x 128 FLOP/clk (64 FMA/clk/CU).
 ALU_F64_PEAK = 78.6
+# HBM bytes per launch of the dominant kernel on this workload, from two
+# rocprofv3 counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a
+# copy of known size); valid only while the kernel's source is unchanged.
+TRAFFIC = {"leaf_lu": dict(source="paper_1307_2665_amd/csrc/leaf.hip", sha256_16="a78f1106cbb34c9e",
+                           bytes=444.2e6)}
+
+
+def measured_traffic(cls):
+    """Counter-derived bytes per launch for a kernel class, or None if its source changed."""
+    import hashlib
+    t = TRAFFIC.get(cls)
+    if t is None:
+        return None
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), t["source"])
+    try:
+        h = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return t["bytes"] if h == t["sha256_16"] else None
 
 
 def parse():
@@ -44,6 +63,9 @@ def parse():
     ap.add_argument("--kernels", action="store_true", help="print per-class kernel times")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (kernels use their built-in defaults)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the run, copy a MIB-MiB device buffer once (a plain copy kernel "
+                         "of known traffic, to calibrate FETCH_SIZE/WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -212,7 +234,7 @@ def main():
         achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=ALU_F64_PEAK, unit="TFLOP/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dominant)
     roof["kernel"] = dominant
     roof["launches_per_step"] = dom["launches"] / args.steps
     roof["avg_launch_ms"] = dom["ms"] / max(dom["launches"], 1)
@@ -252,6 +274,14 @@ def main():
                        f"all {nx * ny - 1} merges and one solve timed in full on tiled leaf DtNs"),
             "seconds": {"leaf_est": cb["t_leaf"], "merge": cb["t_merge"], "solve": cb["t_solve"]},
         }
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration} MiB read + written")
     print(json.dumps(line), flush=True)
 
 
