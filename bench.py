@@ -58,6 +58,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--workload", choices=["convdiff", "helmholtz", "batch", "sweep"],
+                    default="convdiff",
+                    help="convdiff: 64x64 p16 (the default line); helmholtz: 128x128 p16, 64 "
+                         "right-hand sides, FP64 and split-FP32 + refinement; batch: 32 uneven "
+                         "problems with 16 right-hand sides each; sweep: 256x256 p12 coefficient "
+                         "fields, plain FP64 leaves against the learned surrogate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-leaves", type=int, default=512)
     ap.add_argument("--kernels", action="store_true", help="print per-class kernel times")
@@ -120,6 +126,174 @@ def cpu_baseline(pr, n_leaf_sample: int):
     return dict(t_leaf=t_leaf, t_merge=t_merge, t_solve=t_solve, threads=threads, ns=ns)
 
 
+def _n_tot(pr):
+    nx, ny = pr.nleaf
+    return (nx * (pr.p - 1) + 1) * (ny * (pr.p - 1) + 1) + pr.q * (nx * (ny + 1) + (nx + 1) * ny)
+
+
+def _inputs(H, pr, np, torch, dev, nrhs=None):
+    xy = H.cheb_nodes(pr.box, pr.nleaf, pr.p)
+    C = torch.tensor(pr.coeffs_at(xy), dtype=torch.float64, device=dev)
+    gxy = H.gauss_nodes_grid(pr.box, pr.nleaf, pr.q)
+    f = pr.bc_at(gxy[H.boundary_ids(pr.nleaf, pr.q)])
+    if nrhs is not None:
+        f = f[:nrhs]
+    return C, torch.tensor(np.ascontiguousarray(f), dtype=torch.float64, device=dev)
+
+
+def _timed(torch, np, steps, fn):
+    """Median and total wall time (ms) of steps calls of fn (one warm-up call first)."""
+    fn()
+    torch.cuda.synchronize()
+    t = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        t.append(1e3 * (time.perf_counter() - a))
+    return float(np.median(t)), 1e3 * (time.perf_counter() - t0)
+
+
+def _rel(a, b):
+    return float((a - b).abs().max() / b.abs().max())
+
+
+def other_workload(args, H, hi, np, torch, dev):
+    """The non-default workloads: each form (FP64, mixed + refinement, learned) is timed on the
+    same GPU and its solution compared with the FP64 form's (itself parity-tested against the
+    CPU oracle)."""
+    steps = args.steps
+    line = {"metric": METRIC, "unit": "unknowns/s", "n_gpus": 1, "steps": steps,
+            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "data": "synthetic"}
+    if args.workload == "helmholtz":
+        pr = hi.helmholtz_bump()
+        C, F = _inputs(H, pr, np, torch, dev)
+        nrhs = F.shape[0]
+        forms = {}
+        u_ref = None
+        for form in ("fp64", "mixed"):
+            mode = H.HPS_MIXED_SPLIT32 if form == "mixed" else H.HPS_FP64
+            if not args.no_tune:
+                H.autotune([dict(nleaf=pr.nleaf, p=pr.p, q=pr.q, box=pr.box)],
+                           keep_factors=(form == "mixed"))
+            box = {}
+
+            def build():
+                box["op"] = H.build_solution_operator(C, pr.box, pr.nleaf, pr.p, pr.q, mode=mode)
+
+            def solve():
+                if form == "mixed":
+                    box["info"] = {}
+                    box["u"] = box["op"].solve(F, refine=True, tol=1e-11, max_iter=20,
+                                               info=box["info"])
+                else:
+                    box["u"] = box["op"].solve(F)
+
+            bms, _ = _timed(torch, np, steps, build)
+            sms, _ = _timed(torch, np, steps, solve)
+            info = box.get("info")
+            u = box["u"]
+            if u_ref is None:
+                u_ref = u.clone()
+            err = _rel(u, u_ref)
+            forms[form] = {"build_ms": bms, "solve_ms": sms, "step_ms": bms + sms,
+                           "build_unknowns_per_s": _n_tot(pr) / (bms * 1e-3),
+                           "solves_per_s": nrhs / (sms * 1e-3),
+                           "rel_err_vs_fp64": err, "refine": info}
+            log(f"helmholtz {form}: build {bms:.1f} ms, {nrhs}-rhs solve {sms:.2f} ms, err {err:.2e}")
+            del box
+        sel = forms[args.mode]
+        line.update(value=_n_tot(pr) / (sel["step_ms"] * 1e-3), ms_per_step=sel["step_ms"],
+                    dtype="f64" if args.mode == "fp64" else "f64+split-f32",
+                    config={"workload": "helmholtz-bump-128x128-p16-q14-64rhs", "n_tot": _n_tot(pr),
+                            "nrhs": nrhs, "mode": args.mode},
+                    forms=forms)
+        return line
+    if args.workload == "batch":
+        probs = hi.batched_problems()
+        ins = [_inputs(H, pr, np, torch, dev) for pr in probs]
+        if not args.no_tune:
+            H.autotune([dict(nleaf=pr.nleaf, p=pr.p, q=pr.q, box=pr.box) for pr in probs])
+        box = {}
+
+        def build():
+            box["ops"] = H.build_batch([dict(coeffs=C, box=pr.box, nleaf=pr.nleaf, p=pr.p, q=pr.q)
+                                        for pr, (C, F) in zip(probs, ins)])
+
+        def solve():
+            box["u"] = H.solve_batch(box["ops"], [F for (C, F) in ins])
+
+        bms, _ = _timed(torch, np, steps, build)
+        sms, _ = _timed(torch, np, steps, solve)
+        tot = sum(_n_tot(pr) for pr in probs)
+        nrhs = sum(F.shape[0] for (C, F) in ins)
+        # Same problems one by one (each parity-tested against the oracle): same solution.
+        err = 0.0
+        for i in (0, len(probs) // 2, len(probs) - 1):
+            pr, (C, F) = probs[i], ins[i]
+            op = H.build_solution_operator(C, pr.box, pr.nleaf, pr.p, pr.q)
+            err = max(err, _rel(box["u"][i], op.solve(F)))
+        line.update(value=tot / ((bms + sms) * 1e-3), ms_per_step=bms + sms, dtype="f64",
+                    config={"workload": "batch-32-uneven-16rhs", "n_tot": tot, "nrhs": nrhs,
+                            "problems": [[pr.nleaf[0], pr.p] for pr in probs]},
+                    build_ms=bms, solve_ms=sms, build_unknowns_per_s=tot / (bms * 1e-3),
+                    solves_per_s=nrhs / (sms * 1e-3), rel_err_vs_single=err)
+        return line
+    # sweep: plain FP64 leaves against the learned surrogate on held-out fields
+    p, q, n = 12, 10, 256
+    h = 1.0 / n
+    rng = np.random.default_rng(6)
+    xc = -np.cos(np.pi * np.arange(p) / (p - 1))
+    patches = []
+    for i in range(40):
+        fld = hi.sweep_field(6000 + i)
+        for _ in range(500):
+            x0, y0 = rng.uniform(0, 1 - h, size=2)
+            X, Y = np.meshgrid(x0 + 0.5 * (xc + 1) * h, y0 + 0.5 * (xc + 1) * h)
+            patches.append(fld.coeffs_at(np.stack([X.ravel(), Y.ravel()], 1)[None])[0])
+    Cp = torch.tensor(np.array(patches), dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
+    Tp = H.leaf_dtn(Cp, h, h, p, q)
+    sg = H.Surrogate.create(p, q, h, h, hidden=256, rank=16, seed=5)
+    sg.train(Cp, Tp, epochs=40, batch=256, lr=1e-3, seed=7)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    if not args.no_tune:
+        H.autotune([dict(nleaf=(n, n), p=p, q=q)])
+    fields = [hi.sweep_field(5000 + k) for k in range(max(steps, 2))]
+    ins = [_inputs(H, pr, np, torch, dev) for pr in fields]
+    forms = {}
+    sols = {}
+    for form in ("fp64", "surrogate"):
+        kw = dict(surrogate=sg, judge_samples=256, judge_tol=1e-6) if form == "surrogate" else {}
+        times, us, fb = [], [], []
+        for k, (pr, (C, F)) in enumerate(zip(fields, ins)):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            op = H.build_solution_operator(C, pr.box, pr.nleaf, p, q, **kw)
+            u = op.solve(F)
+            torch.cuda.synchronize()
+            times.append(1e3 * (time.perf_counter() - a))
+            us.append(u)
+            fb.append(op.n_fallback_leaves if form == "surrogate" else 0)
+            del op
+        sols[form] = us
+        ms = float(np.median(times[1:] if len(times) > 2 else times))
+        forms[form] = {"step_ms": ms, "unknowns_per_s": _n_tot(fields[0]) / (ms * 1e-3),
+                       "fallback_leaves": fb}
+    errs = [_rel(a, b) for a, b in zip(sols["surrogate"], sols["fp64"])]
+    forms["surrogate"]["rel_err_vs_fp64"] = max(errs)
+    forms["surrogate"]["train_s"] = train_s
+    sel = forms["fp64" if args.mode == "fp64" else "surrogate"]
+    line.update(value=sel["unknowns_per_s"], ms_per_step=sel["step_ms"], dtype="f64",
+                config={"workload": "sweep-256x256-p12-q10", "n_tot": _n_tot(fields[0]),
+                        "fields": len(fields), "mode": "fp64" if args.mode == "fp64" else "surrogate"},
+                forms=forms)
+    return line
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -133,6 +307,9 @@ def main():
     import paper_1307_2665_amd as H
 
     dev = torch.device("cuda:0")
+    if args.workload != "convdiff":
+        print(json.dumps(other_workload(args, H, hi, np, torch, dev)), flush=True)
+        return
     pr = hi.convdiff()
     nx, ny = pr.nleaf
     xy = H.cheb_nodes(pr.box, pr.nleaf, pr.p)
