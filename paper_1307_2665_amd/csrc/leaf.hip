@@ -244,23 +244,28 @@ __global__ void __launch_bounds__(TR * TC) k_leaf_lu(const double* const* __rest
 // so column k lives in a single DPP row and row i's values in the columns of
 // any tc live in that tc's DPP row.
 //
-// Column k (owner tc = k / NC): the owner lanes find the pivot row p with a
-// DPP max (rows stay in place; chosen rows are only marked) and publish the
-// multipliers l_i = a[i][k] / a[p][k] for every row i != p (l_p = 0) and
-// 1 / a[p][k]; after the barrier every thread fetches row p's values for its
-// own columns from lane p % 16 of its DPP row, row p's owner divides it by
-// the pivot, and every thread applies a[i][j] -= l_i a[p][j].  That
-// eliminates column k from every other row (above and below: Gauss-Jordan).  Threads
-// whose columns all precede k + 1 have nothing left to update.  After the
-// last column, row p_k holds row k of A_ii^-1 R in its right-hand-side
-// columns.
+// Column k (owner tc = k / NC): the owner lanes store the column a[., k]
+// to LDS and find the pivot row p with a DPP max (rows stay in place; chosen
+// rows are only marked); that and one barrier is all the serial work of a
+// column.  After the barrier every thread reads a[p][k], fetches row p's
+// values for its own columns from lane p % 16 of its DPP row and scales them
+// by 1 / a[p][k] (giving r_j = a[p][j] / a[p][k], row p's new values), and
+// applies a[i][j] -= a[i][k] r_j, which eliminates column k from every other
+// row (above and below: Gauss-Jordan); the lane holding row p then stores
+// r_j in it.  Threads whose columns all precede k + 1 have nothing left to
+// update.  After the last column, row p_k holds row k of A_ii^-1 R in its
+// right-hand-side columns.
 // ---------------------------------------------------------------------------
 
-// |v| as float with the low 12 bits replaced by 4095 - slot (as in the panel
-// kernel of the dense solver): one unsigned max gives value and place.
+// Search key of a pivot candidate: the high word of |v| (exponent and the
+// top 20 mantissa bits, an order-preserving image of |v|) with the low 8
+// bits replaced by 255 - slot, so one unsigned max gives the largest
+// magnitude (to 2^-12 relative) and its place.  NaN sorts above every
+// number and is then reported as a bad pivot.  Every slot gives a nonzero
+// key (slots are below 256 - 48).
 __device__ inline unsigned leaf_key(double v, int slot) {
-  const unsigned u = (v != v) ? 0x7F800000u : __float_as_uint((float)fabs(v));
-  return (u & ~4095u) | (unsigned)(4095 - slot);
+  const unsigned hi = (unsigned)(__double_as_longlong(v) >> 32) & 0x7FFFFFFFu;
+  return (hi & ~255u) | (unsigned)(255 - slot);
 }
 
 // Max over the 16 lanes of a DPP row (all 16 must be active).
@@ -272,23 +277,16 @@ __device__ inline unsigned row16_max(unsigned k) {
   return k;
 }
 
-__device__ inline double readlane_d(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
 template <int TC, int NR, int NC>
 __global__ void __launch_bounds__(16 * TC) k_leaf_gj(const double* const* __restrict__ cptr,
                                                      const LeafDev tab, double* __restrict__ Z,
                                                      int* status, int tag0) {
   constexpr int TR = 16, NT = TR * TC, NROW = NR * TR;
+  static_assert(NROW <= 208, "pivot keys hold slots below 208");
   __shared__ double sD[4][24 * 24];
   __shared__ double sc[6][NROW];
-  __shared__ double sL[2][NROW];  // multipliers of the current column
+  __shared__ double sA[2][NROW];  // the current column, a[., k]
   __shared__ int sP[2];           // its pivot row
-  __shared__ double sR[2];        // 1 / pivot
   __shared__ int sInv[NROW];      // row -> column whose pivot it is
 
   const int p = tab.p, n = tab.n, m = tab.m, pi = p - 2, w = n + m;
@@ -353,59 +351,50 @@ __global__ void __launch_bounds__(16 * TC) k_leaf_gj(const double* const* __rest
       if (tc == kb) {
         unsigned key = 0;
 #pragma unroll
-        for (int s = 0; s < NR; ++s)
-          if (!((done >> s) & 1u)) key = max(key, leaf_key(a[s][t], TR * s + tr));
-        key = row16_max(key);
-        const int slot = __builtin_amdgcn_readfirstlane(4095 - (int)(key & 4095u));
-        const int sp = slot / TR, trp = slot % TR;
-        const int src = __builtin_amdgcn_readfirstlane(rowlane) + trp;
-        double piv = 0.0;
-#pragma unroll
-        for (int s = 0; s < NR; ++s)
-          if (s == sp) piv = readlane_d(a[s][t], src);
-        const bool ok = (piv != 0.0) && (piv == piv) && fabs(piv) != INFINITY;
-        const double inv = ok ? 1.0 / piv : 0.0;
-#pragma unroll
         for (int s = 0; s < NR; ++s) {
-          const int i = TR * s + tr;
-          sL[buf][i] = (i == slot) ? 0.0 : a[s][t] * inv;
+          sA[buf][TR * s + tr] = a[s][t];
+          if (!((done >> s) & 1u)) key = max(key, leaf_key(a[s][t], TR * s + tr));
         }
+        key = row16_max(key);
         if (tr == 0) {
-          sP[buf] = ok ? slot : -1 - slot;
-          sR[buf] = inv;
+          const int slot = 255 - (int)(key & 255u);
+          sP[buf] = slot;
           sInv[slot] = k;
         }
       }
       __syncthreads();
-      int slot = sP[buf];
-      if (slot < 0) {
-        slot = -1 - slot;
-        if (tid == 0)
-          if (atomicCAS(status, 0, 1) == 0) status[1] = tag0 - (int)blockIdx.x;
-      }
-      slot = __builtin_amdgcn_readfirstlane(slot);
+      const int slot = __builtin_amdgcn_readfirstlane(sP[buf]);
       const int sp = slot / TR, trp = slot % TR;
       if (tr == trp) done |= 1u << sp;
+      const double piv = sA[buf][slot];
+      const bool ok = (piv != 0.0) && (piv == piv) && fabs(piv) != INFINITY;
+      if (!ok && tid == 0)
+        if (atomicCAS(status, 0, 1) == 0) status[1] = tag0 - (int)blockIdx.x;
       // Columns of this thread that are still to be updated: j > k.
       if (NC * tc + NC - 1 > k) {
-        // Row p's values in my columns: lane trp of my DPP row, slot sp.
+        const double inv = ok ? 1.0 / piv : 0.0;
+        // Row p's values in my columns (lane trp of my DPP row, slot sp),
+        // divided by the pivot.
         double prow[NC];
-        const double rinv = sR[buf];
 #pragma unroll
         for (int s = 0; s < NR; ++s)
           if (s == sp) {
 #pragma unroll
-            for (int t2 = 0; t2 < NC; ++t2) prow[t2] = __shfl(a[s][t2], rowlane + trp);
-            if (tr == trp) {
-#pragma unroll
-              for (int t2 = 0; t2 < NC; ++t2) a[s][t2] *= rinv;
-            }
+            for (int t2 = 0; t2 < NC; ++t2) prow[t2] = __shfl(a[s][t2], rowlane + trp) * inv;
           }
 #pragma unroll
         for (int s = 0; s < NR; ++s) {
-          const double lv = sL[buf][TR * s + tr];
+          const double lv = sA[buf][TR * s + tr];
 #pragma unroll
           for (int t2 = 0; t2 < NC; ++t2) a[s][t2] = fma(-lv, prow[t2], a[s][t2]);
+        }
+        if (tr == trp) {
+#pragma unroll
+          for (int s = 0; s < NR; ++s)
+            if (s == sp) {
+#pragma unroll
+              for (int t2 = 0; t2 < NC; ++t2) a[s][t2] = prow[t2];
+            }
         }
       }
     }
