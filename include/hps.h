@@ -296,7 +296,11 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
    "gj_variant": merge solver, 4 * (update tile, as gemm_variant) + TRSM block
      (0: 256, 1: 128, 2: 64 threads);
    "solve_graph": 1 (default) runs plain solves as a captured HIP graph per
-     operator and right-hand-side count, 0 launches kernel by kernel.
+     operator and right-hand-side count, 0 launches kernel by kernel;
+   "solve_mm_min_rhs": solves, source solves and refinement with at least
+     this many right-hand sides keep the solution node by node ([N][nrhs],
+     transposed on entry and exit) and run every pass as grouped FP64 MFMA
+     GEMMs (-1: the default, 16; 0: never).
    Unknown knobs or values give HPS_EINVAL. */
 hps_status hps_tune_set(const char* knob, int value);
 

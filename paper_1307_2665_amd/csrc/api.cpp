@@ -422,6 +422,9 @@ hps_status hps_tune_set(const char* knob, int value) {
     } else if (k == "solve_graph") {
       HPS_REQUIRE(value == 0 || value == 1, "solve_graph must be 0 or 1");
       hps::set_solve_graph(value != 0);
+    } else if (k == "solve_mm_min_rhs") {
+      HPS_REQUIRE(value >= -1, "solve_mm_min_rhs must be >= -1");
+      hps::set_solve_mm_min_rhs(value < 0 ? 16 : value);
     } else if (k == "gj_variant") {
       HPS_REQUIRE(value >= -1 && value < 4 * hps::GEMM_VARIANTS && (value < 0 || value % 4 < 3),
                   "gj_variant out of range");

@@ -1,0 +1,120 @@
+// FP64 MFMA GEMM tile shared by the dense solver (trailing updates, Schur
+// products) and the solution passes (downward pass and interface residual
+// for many right-hand sides).  Device code only; included by .hip files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace hps {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Row maps of the tile: row r of an operand lives at base + map(r) * ld.
+struct RowsIdentity {
+  __device__ int operator()(int r) const { return r; }
+};
+struct RowsIndexed {
+  const int* idx;
+  __device__ int operator()(int r) const { return idx[r]; }
+};
+
+// ---------------------------------------------------------------------------
+// FP64 MFMA tiles.  A workgroup computes a BM x BN tile of C with WM x WN
+// waves; each wave owns a (BM/WM) x (BN/WN) block made of 16 x 16
+// v_mfma_f64_16x16x4f64 blocks.  A and B stream through LDS in BK-deep
+// slabs.  Lane layout of the instruction: A operand lane l holds A[l%16][l/16],
+// B operand B[l/16][l%16], result register r holds D[l/16 + 4r][l%16]
+// (the f32 16x16x4 form instead holds D[4*(l/16) + r][l%16]).
+// Variants (index = tuning value): 0: 64x64x16 on 2x2 waves (the default),
+// 1: 32x32x16 on one wave, 2: 128x128x16 on 2x2 waves, 3: 128x64x16 on 2x2,
+// 4: 64x128x16 on 2x2, 5: 64x64x32 on 2x2.
+// ---------------------------------------------------------------------------
+
+template <int BM, int BN, int BK, int WM, int WN>
+struct GemmTile {
+  static constexpr int NT = 64 * WM * WN;
+  static constexpr int FM = BM / WM / 16, FN = BN / WN / 16;
+  static constexpr int SMEM = BK * (BM + 1) + BK * (BN + 1);  // doubles
+  static_assert(FM >= 1 && FN >= 1 && BK % 4 == 0, "bad tile");
+  static_assert((BM * BK) % NT == 0 && (BK * BN) % NT == 0, "tile loads must divide evenly");
+};
+
+// Tile (row0.., col0..) of C = C0 (or C) + alpha * A (M x K) * B (K x N),
+// row-major with the given leading dimensions, where B's row k lives at
+// B + brow(k) * ldb and C's row r at C + crow(r) * ldc (a gathered operand
+// and a scattered result; A and C0 rows are plain).  With C0 null the old C
+// is added when acc_c is set and nothing otherwise (C is then not read).
+template <int BM, int BN, int BK, int WM, int WN, class BRow, class CRow>
+__device__ inline void gemm_tile_map(const double* __restrict__ A, int lda,
+                                     const double* B, int ldb, BRow brow, double* C, int ldc,
+                                     CRow crow, const double* C0, int ldc0, int M, int N, int K,
+                                     double alpha, int row0, int col0, double* sm, bool acc_c) {
+  using T = GemmTile<BM, BN, BK, WM, WN>;
+  double(*As)[BM + 1] = reinterpret_cast<double(*)[BM + 1]>(sm);
+  double(*Bs)[BN + 1] = reinterpret_cast<double(*)[BN + 1]>(sm + BK * (BM + 1));
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid / WN, wn = wid % WN;
+  constexpr int WBM = BM / WM, WBN = BN / WN;
+  d4 acc[T::FM][T::FN];
+#pragma unroll
+  for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < T::FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int kt = 0; kt < K; kt += BK) {
+#pragma unroll
+    for (int e = 0; e < (BM * BK) / T::NT; ++e) {
+      const int idx = tid + T::NT * e;
+      const int i = idx / BK, k = idx % BK;
+      const int gr = row0 + i, gk = kt + k;
+      As[k][i] = (gr < M && gk < K) ? A[(size_t)gr * lda + gk] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < (BK * BN) / T::NT; ++e) {
+      const int idx = tid + T::NT * e;
+      const int k = idx / BN, j = idx % BN;
+      const int gk = kt + k, gc = col0 + j;
+      Bs[k][j] = (gk < K && gc < N) ? B[(size_t)brow(gk) * ldb + gc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double a[T::FM], b[T::FN];
+#pragma unroll
+      for (int i = 0; i < T::FM; ++i) a[i] = As[kk + (lane >> 4)][wm * WBM + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < T::FN; ++j) b[j] = Bs[kk + (lane >> 4)][wn * WBN + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < T::FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < T::FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = row0 + wm * WBM + i * 16 + (lane >> 4) + 4 * r;
+        const int gc = col0 + wn * WBN + j * 16 + (lane & 15);
+        if (gr < M && gc < N) {
+          double* cp = C + (size_t)crow(gr) * ldc + gc;
+          const double c0 = C0 ? C0[(size_t)gr * ldc0 + gc] : (acc_c ? *cp : 0.0);
+          *cp = c0 + alpha * acc[i][j][r];
+        }
+      }
+}
+
+// C[row0.., col0..] (M x N valid) = C0 (or C) + alpha * A (M x K) * B (K x N);
+// A, B, C, C0 point at the matrices' origins (row-major, given leading dims).
+template <int BM, int BN, int BK, int WM, int WN>
+__device__ inline void gemm_tile(const double* __restrict__ A, int lda, const double* __restrict__ B,
+                                 int ldb, double* C, int ldc, const double* C0, int ldc0, int M,
+                                 int N, int K, double alpha, int row0, int col0, double* sm) {
+  gemm_tile_map<BM, BN, BK, WM, WN>(A, lda, B, ldb, RowsIdentity{}, C, ldc, RowsIdentity{}, C0,
+                                    ldc0, M, N, K, alpha, row0, col0, sm, true);
+}
+
+}  // namespace hps

@@ -39,6 +39,24 @@ void upward_level(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, c
                   int N, double* hbase, const long long* ha_off, const long long* hb_off,
                   const long long* hp_off, double* zbuf, const long long* z_off, int nrhs,
                   double flops, hipStream_t st);
+// Node-major solution passes for many right-hand sides: arrays are
+// [nodes][nrhs].  Algorithm 2 for one depth (z: upward-pass terms, [m3][nrhs]
+// per merge, or null); d_io, when not null, gives merge i's array and count
+// (U and nrhs then give only the launch shape: U unused, nrhs the largest).
+void downward_mm(const MergeDesc* d_desc, int nmerge, int m3_max, double* U, int nrhs,
+                 const double* zbase, const long long* zoff, hipStream_t s, double s_bytes,
+                 const SolveIO* d_io = nullptr);
+void set_boundary_nm(const double* f, const int* gamma, int nb, int nrhs, double* U,
+                     hipStream_t s);
+// out[c][r] = in[r][c], in being R x C row-major.
+void transpose(const double* in, int R, int C, double* out, hipStream_t s);
+void interface_residual_nm(const double* leafT, const double* U, int N, int nrhs, int nx, int ny,
+                           int q, double* vbuf, double* r, hipStream_t s);
+// rbuf: scratch of the size of zbuf.
+void upward_level_nm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, const double* src,
+                     double* hbase, const long long* ha_off, const long long* hb_off,
+                     const long long* hp_off, double* rbuf, double* zbuf, const long long* z_off,
+                     int nrhs, double flops, hipStream_t st);
 void axpy(double* y, const double* x, double a, size_t n, hipStream_t s);
 void absmax_partial(const double* x, size_t n, double* out, int blocks, hipStream_t s);
 void matvec(const double* A, int rows, int cols, const double* x, int nrhs, double* y,

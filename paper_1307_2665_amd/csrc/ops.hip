@@ -1,6 +1,7 @@
 // Problem-specific kernels: leaf assembly (section 3), merge gather
 // (section 4), downward pass (Algorithm 2), interface residual and the
 // upward source pass used by iterative refinement.
+#include "mfma_tile.h"
 #include "ops.h"
 #include "prof.h"
 
@@ -499,6 +500,264 @@ __global__ void __launch_bounds__(256) k_range_flags(const double* const* __rest
 void leaf_range_flags(const double* const* cptr, int nl, int pp, const double* lohi, double margin,
                       int* flag, hipStream_t s) {
   hipLaunchKernelGGL(k_range_flags, dim3(nl), dim3(256), 0, s, cptr, pp, lohi, margin, flag);
+}
+
+// ---------------------------------------------------------------------------
+// Solution passes for many right-hand sides on node-major arrays: U is
+// [N][nrhs] (the nrhs values of one node are contiguous), so the boundary
+// values of a box are whole rows and every pass is a grouped FP64 MFMA GEMM
+// with gathered and scattered rows.  Per box the upward-pass arrays h are
+// [boundary size][nrhs] and z is [m3][nrhs].
+// ---------------------------------------------------------------------------
+#define HPS_MM_TILE(BN) 64, BN, 16, (BN == 16 ? 4 : 2), (BN == 16 ? 1 : 2)
+
+// Algorithm 2 for one depth: U[Ii[r]][:] = S[r][:] U[Ie[:]][:] (+ z[r][:]).
+template <int BM, int BN, int BK, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN) k_down_mm(const MergeDesc* __restrict__ descs,
+                                                         double* U, int nrhs,
+                                                         const double* __restrict__ zbase,
+                                                         const long long* __restrict__ zoff,
+                                                         const SolveIO* __restrict__ io) {
+  __shared__ double sm[GemmTile<BM, BN, BK, WM, WN>::SMEM];
+  const MergeDesc d = descs[blockIdx.z];
+  if (io) {
+    U = io[blockIdx.z].u;
+    nrhs = io[blockIdx.z].nrhs;
+  }
+  const int row0 = blockIdx.y * BM, col0 = blockIdx.x * BN;
+  if (row0 >= d.m3 || col0 >= nrhs) return;
+  const double* z = zbase ? zbase + zoff[blockIdx.z] * nrhs : nullptr;
+  gemm_tile_map<BM, BN, BK, WM, WN>(d.S, d.ldw, U, nrhs, RowsIndexed{d.Ie}, U, nrhs,
+                                    RowsIndexed{d.Ii}, z, nrhs, d.m3, nrhs, d.me, 1.0, row0, col0,
+                                    sm, false);
+}
+
+template <int BN>
+static void launch_down_mm(const MergeDesc* d_desc, int nmerge, int m3_max, double* U, int nrhs,
+                           const double* zbase, const long long* zoff, const SolveIO* io,
+                           hipStream_t s) {
+  dim3 grid((nrhs + BN - 1) / BN, (m3_max + 63) / 64, nmerge);
+  hipLaunchKernelGGL((k_down_mm<HPS_MM_TILE(BN)>), grid, dim3(256), 0, s, d_desc, U, nrhs, zbase,
+                     zoff, io);
+}
+
+void downward_mm(const MergeDesc* d_desc, int nmerge, int m3_max, double* U, int nrhs,
+                 const double* zbase, const long long* zoff, hipStream_t s, double s_bytes,
+                 const SolveIO* io) {
+  if (nmerge == 0) return;
+  HPS_REQUIRE(nmerge <= 65535, "downward pass: too many merges at one depth");
+  ProfScope ps(PROF_DOWNWARD, s, 2.0 * nrhs * s_bytes / 8.0, s_bytes);
+  if (nrhs > 32)
+    launch_down_mm<64>(d_desc, nmerge, m3_max, U, nrhs, zbase, zoff, io, s);
+  else if (nrhs > 16)
+    launch_down_mm<32>(d_desc, nmerge, m3_max, U, nrhs, zbase, zoff, io, s);
+  else
+    launch_down_mm<16>(d_desc, nmerge, m3_max, U, nrhs, zbase, zoff, io, s);
+}
+
+// Node-major boundary data: U[gamma[i]][r] = f[r][i].
+__global__ void k_set_boundary_nm(const double* __restrict__ f, const int* __restrict__ gamma,
+                                  int nb, int nrhs, double* __restrict__ U) {
+  const size_t tot = (size_t)nb * nrhs;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / nrhs), r = (int)(e % nrhs);
+    U[(size_t)gamma[i] * nrhs + r] = f[(size_t)r * nb + i];
+  }
+}
+
+void set_boundary_nm(const double* f, const int* gamma, int nb, int nrhs, double* U,
+                     hipStream_t s) {
+  const size_t tot = (size_t)nb * nrhs;
+  const int blocks = (int)std::min<size_t>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_set_boundary_nm, dim3(std::max(blocks, 1)), dim3(256), 0, s, f, gamma, nb,
+                     nrhs, U);
+}
+
+// out[c][r] = in[r][c] for an R x C row-major in (64 x 64 tiles through LDS).
+__global__ void __launch_bounds__(256) k_transpose(const double* __restrict__ in, int R, int C,
+                                                   double* __restrict__ out) {
+  __shared__ double t[64][65];
+  const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int i = ty; i < 64; i += 4) {
+    const int r = r0 + i, c = c0 + tx;
+    if (r < R && c < C) t[i][tx] = in[(size_t)r * C + c];
+  }
+  __syncthreads();
+  for (int i = ty; i < 64; i += 4) {
+    const int c = c0 + i, r = r0 + tx;
+    if (r < R && c < C) out[(size_t)c * R + r] = t[tx][i];
+  }
+}
+
+void transpose(const double* in, int R, int C, double* out, hipStream_t s) {
+  if (R == 0 || C == 0) return;
+  HPS_REQUIRE((R + 63) / 64 <= 65535, "transpose: too many row tiles");
+  dim3 grid((C + 63) / 64, (R + 63) / 64);
+  hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, s, in, R, C, out);
+}
+
+// Interface residual, node-major: v_leaf = T_leaf U(I_e^leaf) for every leaf
+// (one GEMM tile per leaf and column block), then the jump at every interior
+// Gauss node.
+struct LeafRows {
+  int i, j, nx, nh, q;
+  __device__ int operator()(int c) const { return leaf_bdry_id(i, j, nx, nh, q, c); }
+};
+
+template <int BM, int BN, int BK, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN) k_flux_mm(const double* __restrict__ T,
+                                                         const double* __restrict__ U, int nrhs,
+                                                         int nx, int ny, int q,
+                                                         double* __restrict__ v) {
+  __shared__ double sm[GemmTile<BM, BN, BK, WM, WN>::SMEM];
+  const int leaf = blockIdx.z, m = 4 * q;
+  const int row0 = blockIdx.y * BM, col0 = blockIdx.x * BN;
+  const LeafRows rows{leaf % nx, leaf / nx, nx, nx * (ny + 1), q};
+  gemm_tile_map<BM, BN, BK, WM, WN>(T + (size_t)leaf * m * m, m, U, nrhs, rows,
+                                    v + (size_t)leaf * m * nrhs, nrhs, RowsIdentity{}, nullptr, 0,
+                                    m, nrhs, m, 1.0, row0, col0, sm, false);
+}
+
+__global__ void k_jump_nm(const double* __restrict__ v, int nx, int ny, int q, int nrhs,
+                          double* __restrict__ r, int N) {
+  const int nh = nx * (ny + 1), m = 4 * q;
+  const size_t tot = (size_t)N * nrhs;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int g = (int)(e / nrhs), rh = (int)(e % nrhs);
+    const int edge = g / q, k = g % q;
+    double val = 0.0;
+    if (edge < nh) {
+      const int i = edge % nx, j = edge / nx;
+      if (j > 0 && j < ny)  // alpha = south leaf (its N side), beta = north leaf (its S side)
+        val = v[((size_t)(i + nx * (j - 1)) * m + 2 * q + k) * nrhs + rh] -
+              v[((size_t)(i + nx * j) * m + k) * nrhs + rh];
+    } else {
+      const int ve = edge - nh;
+      const int i = ve % (nx + 1), j = ve / (nx + 1);
+      if (i > 0 && i < nx)  // alpha = west leaf (its E side), beta = east leaf (its W side)
+        val = v[((size_t)(i - 1 + nx * j) * m + q + k) * nrhs + rh] -
+              v[((size_t)(i + nx * j) * m + 3 * q + k) * nrhs + rh];
+    }
+    r[e] = val;
+  }
+}
+
+void interface_residual_nm(const double* leafT, const double* U, int N, int nrhs, int nx, int ny,
+                           int q, double* vbuf, double* r, hipStream_t s) {
+  const int m = 4 * q;
+  HPS_REQUIRE(nx * ny <= 65535, "residual: too many leaves for one launch");
+  ProfScope ps(PROF_RESIDUAL, s, 2.0 * nrhs * nx * ny * (double)m * m, 8.0 * nx * ny * (double)m * m);
+  if (nrhs > 32) {
+    dim3 grid((nrhs + 63) / 64, (m + 63) / 64, nx * ny);
+    hipLaunchKernelGGL((k_flux_mm<HPS_MM_TILE(64)>), grid, dim3(256), 0, s, leafT, U, nrhs, nx, ny,
+                       q, vbuf);
+  } else if (nrhs > 16) {
+    dim3 grid((nrhs + 31) / 32, (m + 63) / 64, nx * ny);
+    hipLaunchKernelGGL((k_flux_mm<HPS_MM_TILE(32)>), grid, dim3(256), 0, s, leafT, U, nrhs, nx, ny,
+                       q, vbuf);
+  } else {
+    dim3 grid((nrhs + 15) / 16, (m + 63) / 64, nx * ny);
+    hipLaunchKernelGGL((k_flux_mm<HPS_MM_TILE(16)>), grid, dim3(256), 0, s, leafT, U, nrhs, nx, ny,
+                       q, vbuf);
+  }
+  const size_t tot = (size_t)N * nrhs;
+  const int blocks = (int)std::min<size_t>((tot + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_jump_nm, dim3(blocks), dim3(256), 0, s, vbuf, nx, ny, q, nrhs, r, N);
+}
+
+// Upward source pass for one depth, node-major (same equations as
+// k_upward_z / k_upward_h): rhs = s3 - h3a + h3b gathered per merge, then
+// z = M^-1 rhs and h_parent = [h1a ; h2b] + Q z as grouped GEMMs.
+__global__ void k_up_gather_nm(const MergeDesc* __restrict__ descs, const double* __restrict__ src,
+                               double* __restrict__ hbase,
+                               const long long* __restrict__ ha_off,
+                               const long long* __restrict__ hb_off,
+                               const long long* __restrict__ hp_off,
+                               const long long* __restrict__ z_off, int nrhs,
+                               double* __restrict__ rbuf) {
+  const MergeDesc d = descs[blockIdx.y];
+  const double* ha = hbase + ha_off[blockIdx.y] * nrhs;
+  const double* hb = hbase + hb_off[blockIdx.y] * nrhs;
+  double* hp = hbase + hp_off[blockIdx.y] * nrhs;
+  double* rr = rbuf + z_off[blockIdx.y] * nrhs;
+  const int n3 = d.m3 * nrhs, ne = d.me * nrhs;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n3 + ne; e += gridDim.x * blockDim.x) {
+    if (e < n3) {
+      const int i = e / nrhs, k = e % nrhs;
+      rr[e] = src[(size_t)d.Ii[i] * nrhs + k] - ha[(size_t)d.a3[i] * nrhs + k] +
+              hb[(size_t)d.b3[i] * nrhs + k];
+    } else {
+      const int e2 = e - n3, r = e2 / nrhs, k = e2 % nrhs;
+      const int pm = d.pmap[r];
+      hp[e2] = (pm >= 0) ? ha[(size_t)pm * nrhs + k] : hb[(size_t)(-pm - 1) * nrhs + k];
+    }
+  }
+}
+
+template <int BM, int BN, int BK, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN) k_up_z_mm(const MergeDesc* __restrict__ descs,
+                                                         const double* __restrict__ rbuf,
+                                                         double* __restrict__ zbuf,
+                                                         const long long* __restrict__ z_off,
+                                                         int nrhs) {
+  __shared__ double sm[GemmTile<BM, BN, BK, WM, WN>::SMEM];
+  const MergeDesc d = descs[blockIdx.z];
+  const int row0 = blockIdx.y * BM, col0 = blockIdx.x * BN;
+  if (row0 >= d.m3 || col0 >= nrhs) return;
+  const size_t o = z_off[blockIdx.z] * nrhs;
+  gemm_tile_map<BM, BN, BK, WM, WN>(d.W + d.m3 + d.me, d.ldw, rbuf + o, nrhs, RowsIdentity{},
+                                    zbuf + o, nrhs, RowsIdentity{}, nullptr, 0, d.m3, nrhs, d.m3,
+                                    1.0, row0, col0, sm, false);
+}
+
+template <int BM, int BN, int BK, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN) k_up_h_mm(const MergeDesc* __restrict__ descs,
+                                                         const double* __restrict__ zbuf,
+                                                         const long long* __restrict__ z_off,
+                                                         double* __restrict__ hbase,
+                                                         const long long* __restrict__ hp_off,
+                                                         int nrhs) {
+  __shared__ double sm[GemmTile<BM, BN, BK, WM, WN>::SMEM];
+  const MergeDesc d = descs[blockIdx.z];
+  const int row0 = blockIdx.y * BM, col0 = blockIdx.x * BN;
+  if (row0 >= d.me || col0 >= nrhs) return;
+  gemm_tile<BM, BN, BK, WM, WN>(d.Q, d.m3, zbuf + z_off[blockIdx.z] * nrhs, nrhs,
+                                hbase + hp_off[blockIdx.z] * nrhs, nrhs, nullptr, 0, d.me, nrhs,
+                                d.m3, 1.0, row0, col0, sm);
+}
+
+template <int BN>
+static void launch_up_mm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max,
+                         double* hbase, const long long* hp_off, double* rbuf, double* zbuf,
+                         const long long* z_off, int nrhs, hipStream_t st) {
+  dim3 gz((nrhs + BN - 1) / BN, (m3_max + 63) / 64, nmerge);
+  hipLaunchKernelGGL((k_up_z_mm<HPS_MM_TILE(BN)>), gz, dim3(256), 0, st, d_desc, rbuf, zbuf, z_off,
+                     nrhs);
+  dim3 gh((nrhs + BN - 1) / BN, (me_max + 63) / 64, nmerge);
+  hipLaunchKernelGGL((k_up_h_mm<HPS_MM_TILE(BN)>), gh, dim3(256), 0, st, d_desc, zbuf, z_off, hbase,
+                     hp_off, nrhs);
+}
+
+void upward_level_nm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, const double* src,
+                     double* hbase, const long long* ha_off, const long long* hb_off,
+                     const long long* hp_off, double* rbuf, double* zbuf, const long long* z_off,
+                     int nrhs, double flops, hipStream_t st) {
+  if (nmerge == 0) return;
+  HPS_REQUIRE(nmerge <= 65535, "upward pass: too many merges at one depth");
+  ProfScope ps(PROF_UPWARD, st, flops, 8.0 * flops / (2.0 * nrhs));
+  const int per = (m3_max + me_max) * nrhs;
+  const int bx = std::min(64, std::max(1, (per + 255) / 256));
+  hipLaunchKernelGGL(k_up_gather_nm, dim3(bx, nmerge), dim3(256), 0, st, d_desc, src, hbase, ha_off,
+                     hb_off, hp_off, z_off, nrhs, rbuf);
+  if (nrhs > 32)
+    launch_up_mm<64>(d_desc, nmerge, m3_max, me_max, hbase, hp_off, rbuf, zbuf, z_off, nrhs, st);
+  else if (nrhs > 16)
+    launch_up_mm<32>(d_desc, nmerge, m3_max, me_max, hbase, hp_off, rbuf, zbuf, z_off, nrhs, st);
+  else
+    launch_up_mm<16>(d_desc, nmerge, m3_max, me_max, hbase, hp_off, rbuf, zbuf, z_off, nrhs, st);
 }
 
 void ops_init() {

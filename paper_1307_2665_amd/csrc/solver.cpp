@@ -16,9 +16,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <random>
 #include <tuple>
@@ -668,6 +670,110 @@ static void downward_all(hps_op* op, double* u, int nrhs, const double* z, hipSt
   downward_batch({op}, {u}, {nrhs}, z, s);
 }
 
+// Right-hand-side count from which solves run on node-major arrays
+// ([nodes][nrhs]) with FP64 MFMA GEMMs: the factors are then read once per
+// 64 right-hand sides instead of once per four.  0: never.
+static int g_mm_min_rhs = 16;
+
+void set_solve_mm_min_rhs(int v) { g_mm_min_rhs = v; }
+
+static bool use_mm(int nrhs) { return g_mm_min_rhs > 0 && nrhs >= g_mm_min_rhs; }
+
+static double level_s_bytes(const LevelPlan& L) {
+  double sb = 0;
+  for (const MergeDesc& m : L.h) sb += 8.0 * m.m3 * m.me;
+  return sb;
+}
+
+// Algorithm 2 on node-major arrays U[i] ([N_i][nrhs_i]); for every depth the
+// merges of all operators in one launch.  z: upward-pass terms (one
+// operator only), node-major per merge.
+static void downward_batch_nm(const std::vector<hps_op*>& ops, const std::vector<double*>& U,
+                              const std::vector<int>& nrhs, const double* z, hipStream_t s) {
+  if (ops.size() == 1) {
+    hps_op* op = ops[0];
+    for (const LevelPlan& L : op->levels)
+      if (!L.h.empty())
+        downward_mm(L.d, (int)L.h.size(), L.m3_max, U[0], nrhs[0], z, z ? L.dzo : nullptr, s,
+                    level_s_bytes(L));
+    return;
+  }
+  HPS_REQUIRE(z == nullptr, "batched downward pass takes no source terms");
+  int maxd = 0;
+  for (hps_op* op : ops) maxd = std::max(maxd, (int)op->levels.size() - 1);
+  std::vector<MergeDesc> hm;
+  std::vector<SolveIO> hio;
+  std::vector<size_t> off(maxd + 2, 0);
+  std::vector<int> m3m(maxd + 1, 0), nrm(maxd + 1, 0);
+  std::vector<double> sb(maxd + 1, 0.0);
+  for (int d = 0; d <= maxd; ++d) {
+    off[d] = hm.size();
+    for (size_t i = 0; i < ops.size(); ++i) {
+      if (d >= (int)ops[i]->levels.size()) continue;
+      for (const MergeDesc& m : ops[i]->levels[d].h) {
+        hm.push_back(m);
+        hio.push_back(SolveIO{U[i], ops[i]->tree().N, nrhs[i]});
+        m3m[d] = std::max(m3m[d], m.m3);
+        nrm[d] = std::max(nrm[d], nrhs[i]);
+        sb[d] += 8.0 * m.m3 * m.me;
+      }
+    }
+  }
+  off[maxd + 1] = hm.size();
+  if (hm.empty()) return;
+  MergeDesc* dm = nullptr;
+  SolveIO* dio = nullptr;
+  HPS_HIP(hipMallocAsync((void**)&dm, hm.size() * sizeof(MergeDesc), s));
+  HPS_HIP(hipMallocAsync((void**)&dio, hio.size() * sizeof(SolveIO), s));
+  HPS_HIP(hipMemcpyAsync(dm, hm.data(), hm.size() * sizeof(MergeDesc), hipMemcpyHostToDevice, s));
+  HPS_HIP(hipMemcpyAsync(dio, hio.data(), hio.size() * sizeof(SolveIO), hipMemcpyHostToDevice, s));
+  for (int d = 0; d <= maxd; ++d) {
+    const int nm = (int)(off[d + 1] - off[d]);
+    if (nm > 0)
+      downward_mm(dm + off[d], nm, m3m[d], nullptr, nrm[d], nullptr, nullptr, s, sb[d],
+                  dio + off[d]);
+  }
+  HPS_HIP(hipFreeAsync(dm, s));
+  HPS_HIP(hipFreeAsync(dio, s));
+  HPS_HIP(hipStreamSynchronize(s));  // host vectors above must outlive the copies
+}
+
+// Upward pass for node-major sources src ([N][nrhs]): fills z ([m3][nrhs]
+// per merge); h and rb are scratch (h_units and z_units per right-hand side).
+static void upward_all_nm(hps_op* op, const double* src, int nrhs, double* h, double* z,
+                          double* rb, hipStream_t s) {
+  HPS_REQUIRE(op->opt.keep_factors, "operator was built without keep_factors");
+  HPS_HIP(hipMemsetAsync(h, 0, (size_t)op->h_units * nrhs * sizeof(double), s));
+  for (int d = (int)op->levels.size() - 1; d >= 0; --d) {
+    const LevelPlan& L = op->levels[d];
+    if (L.h.empty()) continue;
+    double fl = 0;
+    for (const MergeDesc& m : L.h) fl += 2.0 * nrhs * ((double)m.m3 * m.m3 + (double)m.me * m.m3);
+    upward_level_nm(L.d, (int)L.h.size(), L.m3_max, L.me_max, src, h, L.dha, L.dhb, L.dhp, rb, z,
+                    L.dzo, nrhs, fl, s);
+  }
+}
+
+// Device buffer freed on the stream at scope exit.
+struct AsyncBuf {
+  double* p = nullptr;
+  hipStream_t s;
+  AsyncBuf(size_t n, hipStream_t st) : s(st) {
+    HPS_HIP(hipMallocAsync((void**)&p, std::max<size_t>(n, 1) * sizeof(double), s));
+  }
+  ~AsyncBuf() { (void)hipFreeAsync(p, s); }
+  AsyncBuf(const AsyncBuf&) = delete;
+  AsyncBuf& operator=(const AsyncBuf&) = delete;
+};
+
+static void solve_mm(hps_op* op, const double* f, int nrhs, double* u, hipStream_t s) {
+  const int N = op->tree().N;
+  AsyncBuf U((size_t)N * nrhs, s);
+  set_boundary_nm(f, op->gamma, op->n_bdry, nrhs, U.p, s);
+  downward_batch_nm({op}, {U.p}, {nrhs}, nullptr, s);
+  transpose(U.p, N, nrhs, u, s);
+}
+
 static bool g_solve_graph = true;
 
 void set_solve_graph(bool on) { g_solve_graph = on; }
@@ -677,6 +783,10 @@ void set_solve_graph(bool on) { g_solve_graph = on; }
 // stream (kernels read f and u from op->d_io, so the graph's arguments never
 // change) and replayed on the caller's stream after d_io is refreshed.
 void solve_device(hps_op* op, const double* f, int nrhs, double* u, hipStream_t s) {
+  if (use_mm(nrhs)) {
+    solve_mm(op, f, nrhs, u, s);
+    return;
+  }
   // The first solve with a right-hand-side count runs launch by launch; the
   // graph is captured on the second (an operator solved once does not pay
   // for the capture).
@@ -729,6 +839,18 @@ void solve_device(hps_op* op, const double* f, int nrhs, double* u, hipStream_t 
 void solve_batch_device(const std::vector<hps_op*>& ops, const std::vector<const double*>& f,
                         const std::vector<int>& nrhs, const std::vector<double*>& u,
                         hipStream_t s) {
+  if (!ops.empty() && use_mm(*std::min_element(nrhs.begin(), nrhs.end()))) {
+    std::vector<std::unique_ptr<AsyncBuf>> bufs;
+    std::vector<double*> U;
+    for (size_t i = 0; i < ops.size(); ++i) {
+      bufs.emplace_back(new AsyncBuf((size_t)ops[i]->tree().N * nrhs[i], s));
+      U.push_back(bufs.back()->p);
+      set_boundary_nm(f[i], ops[i]->gamma, ops[i]->n_bdry, nrhs[i], U[i], s);
+    }
+    downward_batch_nm(ops, U, nrhs, nullptr, s);
+    for (size_t i = 0; i < ops.size(); ++i) transpose(U[i], ops[i]->tree().N, nrhs[i], u[i], s);
+    return;
+  }
   for (size_t i = 0; i < ops.size(); ++i)
     set_boundary(f[i], ops[i]->gamma, ops[i]->n_bdry, u[i], ops[i]->tree().N, nrhs[i], s);
   downward_batch(ops, u, nrhs, nullptr, s);
@@ -751,6 +873,14 @@ double absmax_device(const double* x, size_t n, hipStream_t s) {
 void residual_device(const hps_op* op, const double* u, int nrhs, double* r, hipStream_t s) {
   HPS_REQUIRE(op->opt.keep_leaf, "operator was built without keep_leaf_ops");
   const int nl = op->nx * op->ny, m = 4 * op->q;
+  if (use_mm(nrhs)) {
+    const int N = op->tree().N;
+    AsyncBuf U((size_t)N * nrhs, s), R((size_t)N * nrhs, s), v((size_t)nl * m * nrhs, s);
+    transpose(u, nrhs, N, U.p, s);
+    interface_residual_nm(op->leafT, U.p, N, nrhs, op->nx, op->ny, op->q, v.p, R.p, s);
+    transpose(R.p, N, nrhs, r, s);
+    return;
+  }
   double* v = nullptr;
   HPS_HIP(hipMallocAsync((void**)&v, (size_t)nrhs * nl * m * sizeof(double), s));
   interface_residual(op->leafT, u, op->tree().N, nrhs, op->nx, op->ny, op->q, v, r, s);
@@ -774,6 +904,18 @@ static void upward_all(hps_op* op, const double* src, int nrhs, double* h, doubl
 
 void solve_with_sources_device(hps_op* op, const double* f, const double* src, int nrhs, double* u,
                                hipStream_t s) {
+  if (use_mm(nrhs)) {
+    const int N = op->tree().N;
+    AsyncBuf S((size_t)N * nrhs, s), U((size_t)N * nrhs, s);
+    AsyncBuf h((size_t)op->h_units * nrhs, s), z((size_t)op->z_units * nrhs, s),
+        rb((size_t)op->z_units * nrhs, s);
+    transpose(src, nrhs, N, S.p, s);
+    upward_all_nm(op, S.p, nrhs, h.p, z.p, rb.p, s);
+    set_boundary_nm(f, op->gamma, op->n_bdry, nrhs, U.p, s);
+    downward_batch_nm({op}, {U.p}, {nrhs}, z.p, s);
+    transpose(U.p, N, nrhs, u, s);
+    return;
+  }
   double *h = nullptr, *z = nullptr;
   HPS_HIP(hipMallocAsync((void**)&h, (size_t)op->h_units * nrhs * sizeof(double), s));
   HPS_HIP(hipMallocAsync((void**)&z, (size_t)std::max<long long>(1, op->z_units) * nrhs *
@@ -785,12 +927,67 @@ void solve_with_sources_device(hps_op* op, const double* f, const double* src, i
   HPS_HIP(hipFreeAsync(z, s));
 }
 
+static void refine_report(hps_solve_info* info, int it, double first, double last, bool conv,
+                          int max_iter) {
+  if (info) {
+    info->iters = it;
+    info->last_update_rel = last;
+    info->first_update_rel = first < 0 ? 0.0 : first;
+  }
+  if (!conv) {
+    char buf[160];
+    snprintf(buf, sizeof(buf),
+             "refinement did not reach tolerance in %d sweeps (first relative update %.3e, "
+             "last %.3e)", max_iter, first, last);
+    throw Error(HPS_ENOTCONV, buf);
+  }
+}
+
+// Refinement on node-major arrays (same sweep as below): residual, upward
+// pass, correction by the downward pass, all as grouped MFMA GEMMs.
+static void refine_mm(hps_op* op, int nrhs, double* u, double tol, int max_iter, hipStream_t s,
+                      hps_solve_info* info) {
+  const int N = op->tree().N, nl = op->nx * op->ny, m = 4 * op->q;
+  const size_t nu = (size_t)N * nrhs;
+  AsyncBuf U(nu, s), r(nu, s), du(nu, s), v((size_t)nl * m * nrhs, s);
+  AsyncBuf h((size_t)op->h_units * nrhs, s), z((size_t)op->z_units * nrhs, s),
+      rb((size_t)op->z_units * nrhs, s), zero((size_t)op->n_bdry * nrhs, s);
+  HPS_HIP(hipMemsetAsync(zero.p, 0, (size_t)op->n_bdry * nrhs * sizeof(double), s));
+  transpose(u, nrhs, N, U.p, s);
+  int it = 0;
+  double last = 0.0, first = -1.0;
+  bool conv = false;
+  const double umax = std::max(absmax_device(U.p, nu, s), 1e-300);
+  while (it < max_iter) {
+    interface_residual_nm(op->leafT, U.p, N, nrhs, op->nx, op->ny, op->q, v.p, r.p, s);
+    // Correction with jump(delta) = -r: by linearity delta = -(solution for sources r).
+    upward_all_nm(op, r.p, nrhs, h.p, z.p, rb.p, s);
+    set_boundary_nm(zero.p, op->gamma, op->n_bdry, nrhs, du.p, s);
+    downward_batch_nm({op}, {du.p}, {nrhs}, z.p, s);
+    axpy(U.p, du.p, -1.0, nu, s);
+    ++it;
+    last = absmax_device(du.p, nu, s) / umax;
+    if (first < 0) first = last;
+    if (last <= tol) {
+      conv = true;
+      break;
+    }
+  }
+  transpose(U.p, N, nrhs, u, s);
+  HPS_HIP(hipStreamSynchronize(s));
+  refine_report(info, it, first, last, conv, max_iter);
+}
+
 void refine_device(hps_op* op, const double* f, int nrhs, double* u, double tol, int max_iter,
                    hipStream_t s, hps_solve_info* info) {
   HPS_REQUIRE(op->opt.keep_factors && op->opt.keep_leaf,
               "refinement needs keep_leaf_ops and keep_factors");
   const int N = op->tree().N;
   const size_t nu = (size_t)N * nrhs;
+  if (use_mm(nrhs)) {
+    refine_mm(op, nrhs, u, tol, max_iter, s, info);
+    return;
+  }
   double *r = nullptr, *du = nullptr, *h = nullptr, *z = nullptr, *zero = nullptr;
   HPS_HIP(hipMallocAsync((void**)&r, nu * sizeof(double), s));
   HPS_HIP(hipMallocAsync((void**)&du, nu * sizeof(double), s));
@@ -825,14 +1022,7 @@ void refine_device(hps_op* op, const double* f, int nrhs, double* u, double tol,
   HPS_HIP(hipFreeAsync(z, s));
   HPS_HIP(hipFreeAsync(zero, s));
   HPS_HIP(hipStreamSynchronize(s));
-  if (info) {
-    info->iters = it;
-    info->last_update_rel = last;
-    info->first_update_rel = first < 0 ? 0.0 : first;
-  }
-  if (!conv)
-    throw Error(HPS_ENOTCONV, "refinement did not reach tolerance in " + std::to_string(max_iter) +
-                                  " sweeps (last relative update " + std::to_string(last) + ")");
+  refine_report(info, it, first, last, conv, max_iter);
 }
 
 void root_apply_device(const hps_op* op, const double* f, int nrhs, double* v, hipStream_t s) {

@@ -167,5 +167,8 @@ void root_apply_device(const hps_op* op, const double* f, int nrhs, double* v, h
 double absmax_device(const double* x, size_t n, hipStream_t s);
 // Plain solves through captured graphs (default on); off = launch by launch.
 void set_solve_graph(bool on);
+// Solves, source solves and refinement with at least v right-hand sides run
+// on node-major arrays with MFMA GEMMs (default 16; 0: never).
+void set_solve_mm_min_rhs(int v);
 
 }  // namespace hps
