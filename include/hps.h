@@ -300,7 +300,10 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
    "solve_mm_min_rhs": solves, source solves and refinement with at least
      this many right-hand sides keep the solution node by node ([N][nrhs],
      transposed on entry and exit) and run every pass as grouped FP64 MFMA
-     GEMMs (-1: the default, 16; 0: never).
+     GEMMs (-1: the default, 16; 0: never);
+   "split_min_chunk": in those passes, depths with too few merges to fill
+     the GPU split each GEMM contraction into chunks of at least this length
+     (-1: the default, 256; else at least 16), summed in a fixed order.
    Unknown knobs or values give HPS_EINVAL. */
 hps_status hps_tune_set(const char* knob, int value);
 

@@ -7,6 +7,7 @@
 
 #include "dense.h"
 #include "leaf.h"
+#include "ops.h"
 #include "solver.h"
 #include "surrogate.h"
 #include "tune.h"
@@ -425,6 +426,9 @@ hps_status hps_tune_set(const char* knob, int value) {
     } else if (k == "solve_mm_min_rhs") {
       HPS_REQUIRE(value >= -1, "solve_mm_min_rhs must be >= -1");
       hps::set_solve_mm_min_rhs(value < 0 ? 16 : value);
+    } else if (k == "split_min_chunk") {
+      HPS_REQUIRE(value == -1 || value >= 16, "split_min_chunk must be -1 or >= 16");
+      hps::set_split_min_chunk(value < 0 ? 256 : value);
     } else if (k == "gj_variant") {
       HPS_REQUIRE(value >= -1 && value < 4 * hps::GEMM_VARIANTS && (value < 0 || value % 4 < 3),
                   "gj_variant out of range");

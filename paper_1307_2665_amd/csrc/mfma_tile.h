@@ -60,22 +60,43 @@ __device__ inline void gemm_tile_map(const double* __restrict__ A, int lda,
   for (int i = 0; i < T::FM; ++i)
 #pragma unroll
     for (int j = 0; j < T::FN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int kt = 0; kt < K; kt += BK) {
+  // The next slab's operands are loaded into registers while the current one
+  // is multiplied out of LDS (one slab of global loads always in flight);
+  // tiles whose accumulators leave no room for that load as they go.
+  constexpr int EA = (BM * BK) / T::NT, EB = (BK * BN) / T::NT;
+  constexpr bool PF = T::FM * T::FN <= 4;
+  double ra[EA], rb[EB];
+  auto load = [&](int kt) {
 #pragma unroll
-    for (int e = 0; e < (BM * BK) / T::NT; ++e) {
+    for (int e = 0; e < EA; ++e) {
       const int idx = tid + T::NT * e;
       const int i = idx / BK, k = idx % BK;
       const int gr = row0 + i, gk = kt + k;
-      As[k][i] = (gr < M && gk < K) ? A[(size_t)gr * lda + gk] : 0.0;
+      ra[e] = (gr < M && gk < K) ? A[(size_t)gr * lda + gk] : 0.0;
     }
 #pragma unroll
-    for (int e = 0; e < (BK * BN) / T::NT; ++e) {
+    for (int e = 0; e < EB; ++e) {
       const int idx = tid + T::NT * e;
       const int k = idx / BN, j = idx % BN;
       const int gk = kt + k, gc = col0 + j;
-      Bs[k][j] = (gk < K && gc < N) ? B[(size_t)brow(gk) * ldb + gc] : 0.0;
+      rb[e] = (gk < K && gc < N) ? B[(size_t)brow(gk) * ldb + gc] : 0.0;
+    }
+  };
+  if (PF && K > 0) load(0);
+  for (int kt = 0; kt < K; kt += BK) {
+    if (!PF) load(kt);
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + T::NT * e;
+      As[idx % BK][idx / BK] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + T::NT * e;
+      Bs[idx / BN][idx % BN] = rb[e];
     }
     __syncthreads();
+    if (PF && kt + BK < K) load(kt + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       double a[T::FM], b[T::FN];

@@ -43,11 +43,14 @@ void upward_level(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, c
 // [nodes][nrhs].  Algorithm 2 for one depth (z: upward-pass terms, [m3][nrhs]
 // per merge, or null); d_io, when not null, gives merge i's array and count
 // (U and nrhs then give only the launch shape: U unused, nrhs the largest).
-void downward_mm(const MergeDesc* d_desc, int nmerge, int m3_max, double* U, int nrhs,
+void downward_mm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, double* U, int nrhs,
                  const double* zbase, const long long* zoff, hipStream_t s, double s_bytes,
                  const SolveIO* d_io = nullptr);
 void set_boundary_nm(const double* f, const int* gamma, int nb, int nrhs, double* U,
                      hipStream_t s);
+// Depths with few merges split the GEMM contractions of these passes into
+// chunks of at least v (default 256, at least 16) summed in a fixed order.
+void set_split_min_chunk(int v);
 // out[c][r] = in[r][c], in being R x C row-major.
 void transpose(const double* in, int R, int C, double* out, hipStream_t s);
 void interface_residual_nm(const double* leafT, const double* U, int N, int nrhs, int nx, int ny,

@@ -512,47 +512,103 @@ void leaf_range_flags(const double* const* cptr, int nl, int pp, const double* l
 #define HPS_MM_TILE(BN) 64, BN, 16, (BN == 16 ? 4 : 2), (BN == 16 ? 1 : 2)
 
 // Algorithm 2 for one depth: U[Ii[r]][:] = S[r][:] U[Ie[:]][:] (+ z[r][:]).
+// Depths with few merges split the contraction over me into ks chunks
+// (grid z = merge * ks + chunk) whose partial products go to P
+// ([merge][ks][m3_max][nrhs]) and are summed in chunk order by
+// k_down_reduce, so that the few large S of the top levels are streamed by
+// enough workgroups to fill the chip.
 template <int BM, int BN, int BK, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN) k_down_mm(const MergeDesc* __restrict__ descs,
                                                          double* U, int nrhs,
                                                          const double* __restrict__ zbase,
                                                          const long long* __restrict__ zoff,
-                                                         const SolveIO* __restrict__ io) {
+                                                         const SolveIO* __restrict__ io, int ks,
+                                                         double* __restrict__ P, int m3_max) {
   __shared__ double sm[GemmTile<BM, BN, BK, WM, WN>::SMEM];
-  const MergeDesc d = descs[blockIdx.z];
+  const int mi = blockIdx.z / ks, kc = blockIdx.z % ks;
+  const MergeDesc d = descs[mi];
   if (io) {
-    U = io[blockIdx.z].u;
-    nrhs = io[blockIdx.z].nrhs;
+    U = io[mi].u;
+    nrhs = io[mi].nrhs;
   }
   const int row0 = blockIdx.y * BM, col0 = blockIdx.x * BN;
   if (row0 >= d.m3 || col0 >= nrhs) return;
-  const double* z = zbase ? zbase + zoff[blockIdx.z] * nrhs : nullptr;
-  gemm_tile_map<BM, BN, BK, WM, WN>(d.S, d.ldw, U, nrhs, RowsIndexed{d.Ie}, U, nrhs,
-                                    RowsIndexed{d.Ii}, z, nrhs, d.m3, nrhs, d.me, 1.0, row0, col0,
-                                    sm, false);
+  if (ks == 1) {
+    const double* z = zbase ? zbase + zoff[mi] * nrhs : nullptr;
+    gemm_tile_map<BM, BN, BK, WM, WN>(d.S, d.ldw, U, nrhs, RowsIndexed{d.Ie}, U, nrhs,
+                                      RowsIndexed{d.Ii}, z, nrhs, d.m3, nrhs, d.me, 1.0, row0,
+                                      col0, sm, false);
+    return;
+  }
+  const int kchunk = ((d.me + ks - 1) / ks + BK - 1) / BK * BK;
+  const int k0 = min(d.me, kc * kchunk), K = min(kchunk, d.me - k0);
+  gemm_tile_map<BM, BN, BK, WM, WN>(d.S + k0, d.ldw, U, nrhs, RowsIndexed{d.Ie + k0},
+                                    P + (size_t)blockIdx.z * m3_max * nrhs, nrhs, RowsIdentity{},
+                                    nullptr, 0, d.m3, nrhs, K, 1.0, row0, col0, sm, false);
+}
+
+__global__ void k_down_reduce(const MergeDesc* __restrict__ descs, double* __restrict__ U,
+                              int nrhs, const double* __restrict__ zbase,
+                              const long long* __restrict__ zoff, int ks,
+                              const double* __restrict__ P, int m3_max) {
+  const int mi = blockIdx.y;
+  const MergeDesc d = descs[mi];
+  const double* z = zbase ? zbase + zoff[mi] * nrhs : nullptr;
+  const double* Pm = P + (size_t)mi * ks * m3_max * nrhs;
+  const int tot = d.m3 * nrhs;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
+    const int r = e / nrhs, c = e % nrhs;
+    double v = z ? z[e] : 0.0;
+    for (int j = 0; j < ks; ++j) v += Pm[((size_t)j * m3_max + r) * nrhs + c];
+    U[(size_t)d.Ii[r] * nrhs + c] = v;
+  }
+}
+
+// Number of contraction chunks for a launch of `tiles` output tiles with
+// contraction length K: enough workgroups to fill the chip (about 1024),
+// chunks of at least g_split_min (256 by default).
+static int g_split_min = 256;
+
+void set_split_min_chunk(int v) { g_split_min = std::max(16, v); }
+
+static int split_chunks(long long tiles, int K) {
+  if (tiles >= 512) return 1;
+  const long long want = (1024 + tiles - 1) / tiles;
+  return (int)std::max<long long>(1, std::min<long long>(want, K / g_split_min));
 }
 
 template <int BN>
-static void launch_down_mm(const MergeDesc* d_desc, int nmerge, int m3_max, double* U, int nrhs,
-                           const double* zbase, const long long* zoff, const SolveIO* io,
-                           hipStream_t s) {
-  dim3 grid((nrhs + BN - 1) / BN, (m3_max + 63) / 64, nmerge);
+static void launch_down_mm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max,
+                           double* U, int nrhs, const double* zbase, const long long* zoff,
+                           const SolveIO* io, hipStream_t s) {
+  const long long tiles = (long long)((nrhs + BN - 1) / BN) * ((m3_max + 63) / 64) * nmerge;
+  const int ks = io ? 1 : split_chunks(tiles, me_max);
+  HPS_REQUIRE((long long)nmerge * ks <= 65535, "downward pass: too many merges at one depth");
+  double* P = nullptr;
+  if (ks > 1)
+    HPS_HIP(hipMallocAsync((void**)&P, (size_t)nmerge * ks * m3_max * nrhs * sizeof(double), s));
+  dim3 grid((nrhs + BN - 1) / BN, (m3_max + 63) / 64, nmerge * ks);
   hipLaunchKernelGGL((k_down_mm<HPS_MM_TILE(BN)>), grid, dim3(256), 0, s, d_desc, U, nrhs, zbase,
-                     zoff, io);
+                     zoff, io, ks, P, m3_max);
+  if (ks > 1) {
+    const int bx = std::max(1, std::min(64, (m3_max * nrhs + 255) / 256));
+    hipLaunchKernelGGL(k_down_reduce, dim3(bx, nmerge), dim3(256), 0, s, d_desc, U, nrhs, zbase,
+                       zoff, ks, P, m3_max);
+    HPS_HIP(hipFreeAsync(P, s));
+  }
 }
 
-void downward_mm(const MergeDesc* d_desc, int nmerge, int m3_max, double* U, int nrhs,
+void downward_mm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, double* U, int nrhs,
                  const double* zbase, const long long* zoff, hipStream_t s, double s_bytes,
                  const SolveIO* io) {
   if (nmerge == 0) return;
-  HPS_REQUIRE(nmerge <= 65535, "downward pass: too many merges at one depth");
   ProfScope ps(PROF_DOWNWARD, s, 2.0 * nrhs * s_bytes / 8.0, s_bytes);
   if (nrhs > 32)
-    launch_down_mm<64>(d_desc, nmerge, m3_max, U, nrhs, zbase, zoff, io, s);
+    launch_down_mm<64>(d_desc, nmerge, m3_max, me_max, U, nrhs, zbase, zoff, io, s);
   else if (nrhs > 16)
-    launch_down_mm<32>(d_desc, nmerge, m3_max, U, nrhs, zbase, zoff, io, s);
+    launch_down_mm<32>(d_desc, nmerge, m3_max, me_max, U, nrhs, zbase, zoff, io, s);
   else
-    launch_down_mm<16>(d_desc, nmerge, m3_max, U, nrhs, zbase, zoff, io, s);
+    launch_down_mm<16>(d_desc, nmerge, m3_max, me_max, U, nrhs, zbase, zoff, io, s);
 }
 
 // Node-major boundary data: U[gamma[i]][r] = f[r][i].
@@ -697,20 +753,28 @@ __global__ void k_up_gather_nm(const MergeDesc* __restrict__ descs, const double
   }
 }
 
+// z = M^-1 rhs (M^-1 at W + m3 + me) and h_parent += Q z for every merge of a
+// depth; with ks > 1 the contraction over m3 is split as in k_down_mm and the
+// partial products are summed in chunk order by k_up_reduce.
 template <int BM, int BN, int BK, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN) k_up_z_mm(const MergeDesc* __restrict__ descs,
                                                          const double* __restrict__ rbuf,
                                                          double* __restrict__ zbuf,
                                                          const long long* __restrict__ z_off,
-                                                         int nrhs) {
+                                                         int nrhs, int ks, double* __restrict__ P,
+                                                         int rows_max) {
   __shared__ double sm[GemmTile<BM, BN, BK, WM, WN>::SMEM];
-  const MergeDesc d = descs[blockIdx.z];
+  const int mi = blockIdx.z / ks, kc = blockIdx.z % ks;
+  const MergeDesc d = descs[mi];
   const int row0 = blockIdx.y * BM, col0 = blockIdx.x * BN;
   if (row0 >= d.m3 || col0 >= nrhs) return;
-  const size_t o = z_off[blockIdx.z] * nrhs;
-  gemm_tile_map<BM, BN, BK, WM, WN>(d.W + d.m3 + d.me, d.ldw, rbuf + o, nrhs, RowsIdentity{},
-                                    zbuf + o, nrhs, RowsIdentity{}, nullptr, 0, d.m3, nrhs, d.m3,
-                                    1.0, row0, col0, sm, false);
+  const size_t o = z_off[mi] * nrhs;
+  const int kchunk = ((d.m3 + ks - 1) / ks + BK - 1) / BK * BK;
+  const int k0 = min(d.m3, kc * kchunk), K = min(kchunk, d.m3 - k0);
+  double* C = ks == 1 ? zbuf + o : P + (size_t)blockIdx.z * rows_max * nrhs;
+  gemm_tile_map<BM, BN, BK, WM, WN>(d.W + d.m3 + d.me + k0, d.ldw, rbuf + o + (size_t)k0 * nrhs,
+                                    nrhs, RowsIdentity{}, C, nrhs, RowsIdentity{}, nullptr, 0,
+                                    d.m3, nrhs, K, 1.0, row0, col0, sm, false);
 }
 
 template <int BM, int BN, int BK, int WM, int WN>
@@ -719,26 +783,72 @@ __global__ void __launch_bounds__(64 * WM * WN) k_up_h_mm(const MergeDesc* __res
                                                          const long long* __restrict__ z_off,
                                                          double* __restrict__ hbase,
                                                          const long long* __restrict__ hp_off,
-                                                         int nrhs) {
+                                                         int nrhs, int ks, double* __restrict__ P,
+                                                         int rows_max) {
   __shared__ double sm[GemmTile<BM, BN, BK, WM, WN>::SMEM];
-  const MergeDesc d = descs[blockIdx.z];
+  const int mi = blockIdx.z / ks, kc = blockIdx.z % ks;
+  const MergeDesc d = descs[mi];
   const int row0 = blockIdx.y * BM, col0 = blockIdx.x * BN;
   if (row0 >= d.me || col0 >= nrhs) return;
-  gemm_tile<BM, BN, BK, WM, WN>(d.Q, d.m3, zbuf + z_off[blockIdx.z] * nrhs, nrhs,
-                                hbase + hp_off[blockIdx.z] * nrhs, nrhs, nullptr, 0, d.me, nrhs,
-                                d.m3, 1.0, row0, col0, sm);
+  const int kchunk = ((d.m3 + ks - 1) / ks + BK - 1) / BK * BK;
+  const int k0 = min(d.m3, kc * kchunk), K = min(kchunk, d.m3 - k0);
+  const double* B = zbuf + z_off[mi] * nrhs + (size_t)k0 * nrhs;
+  if (ks == 1)
+    gemm_tile<BM, BN, BK, WM, WN>(d.Q, d.m3, B, nrhs, hbase + hp_off[mi] * nrhs, nrhs, nullptr, 0,
+                                  d.me, nrhs, d.m3, 1.0, row0, col0, sm);
+  else
+    gemm_tile_map<BM, BN, BK, WM, WN>(d.Q + k0, d.m3, B, nrhs, RowsIdentity{},
+                                      P + (size_t)blockIdx.z * rows_max * nrhs, nrhs,
+                                      RowsIdentity{}, nullptr, 0, d.me, nrhs, K, 1.0, row0, col0,
+                                      sm, false);
+}
+
+// dst rows of merge mi (z: m3 rows, overwritten; h: me rows, added to) from
+// the ks partial products.
+__global__ void k_up_reduce(const MergeDesc* __restrict__ descs, double* __restrict__ base,
+                            const long long* __restrict__ off, int nrhs, int ks,
+                            const double* __restrict__ P, int rows_max, int to_h) {
+  const int mi = blockIdx.y;
+  const MergeDesc d = descs[mi];
+  const int rows = to_h ? d.me : d.m3;
+  double* dst = base + off[mi] * nrhs;
+  const double* Pm = P + (size_t)mi * ks * rows_max * nrhs;
+  const int tot = rows * nrhs;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
+    double v = to_h ? dst[e] : 0.0;
+    for (int j = 0; j < ks; ++j) v += Pm[(size_t)j * rows_max * nrhs + e];
+    dst[e] = v;
+  }
 }
 
 template <int BN>
 static void launch_up_mm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max,
                          double* hbase, const long long* hp_off, double* rbuf, double* zbuf,
                          const long long* z_off, int nrhs, hipStream_t st) {
-  dim3 gz((nrhs + BN - 1) / BN, (m3_max + 63) / 64, nmerge);
+  const int ct = (nrhs + BN - 1) / BN;
+  const int ksz = split_chunks((long long)ct * ((m3_max + 63) / 64) * nmerge, m3_max);
+  const int ksh = split_chunks((long long)ct * ((me_max + 63) / 64) * nmerge, m3_max);
+  HPS_REQUIRE((long long)nmerge * std::max(ksz, ksh) <= 65535,
+              "upward pass: too many merges at one depth");
+  double* P = nullptr;
+  const size_t pz = (size_t)nmerge * ksz * m3_max * nrhs, ph = (size_t)nmerge * ksh * me_max * nrhs;
+  if (ksz > 1 || ksh > 1)
+    HPS_HIP(hipMallocAsync((void**)&P, std::max(ksz > 1 ? pz : 0, ksh > 1 ? ph : 0) *
+                                           sizeof(double), st));
+  const int bx = std::max(1, std::min(64, ((m3_max + me_max) * nrhs + 255) / 256));
+  dim3 gz(ct, (m3_max + 63) / 64, nmerge * ksz);
   hipLaunchKernelGGL((k_up_z_mm<HPS_MM_TILE(BN)>), gz, dim3(256), 0, st, d_desc, rbuf, zbuf, z_off,
-                     nrhs);
-  dim3 gh((nrhs + BN - 1) / BN, (me_max + 63) / 64, nmerge);
+                     nrhs, ksz, P, m3_max);
+  if (ksz > 1)
+    hipLaunchKernelGGL(k_up_reduce, dim3(bx, nmerge), dim3(256), 0, st, d_desc, zbuf, z_off, nrhs,
+                       ksz, P, m3_max, 0);
+  dim3 gh(ct, (me_max + 63) / 64, nmerge * ksh);
   hipLaunchKernelGGL((k_up_h_mm<HPS_MM_TILE(BN)>), gh, dim3(256), 0, st, d_desc, zbuf, z_off, hbase,
-                     hp_off, nrhs);
+                     hp_off, nrhs, ksh, P, me_max);
+  if (ksh > 1)
+    hipLaunchKernelGGL(k_up_reduce, dim3(bx, nmerge), dim3(256), 0, st, d_desc, hbase, hp_off, nrhs,
+                       ksh, P, me_max, 1);
+  if (P) HPS_HIP(hipFreeAsync(P, st));
 }
 
 void upward_level_nm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, const double* src,
@@ -746,7 +856,6 @@ void upward_level_nm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max
                      const long long* hp_off, double* rbuf, double* zbuf, const long long* z_off,
                      int nrhs, double flops, hipStream_t st) {
   if (nmerge == 0) return;
-  HPS_REQUIRE(nmerge <= 65535, "upward pass: too many merges at one depth");
   ProfScope ps(PROF_UPWARD, st, flops, 8.0 * flops / (2.0 * nrhs));
   const int per = (m3_max + me_max) * nrhs;
   const int bx = std::min(64, std::max(1, (per + 255) / 256));

@@ -694,8 +694,8 @@ static void downward_batch_nm(const std::vector<hps_op*>& ops, const std::vector
     hps_op* op = ops[0];
     for (const LevelPlan& L : op->levels)
       if (!L.h.empty())
-        downward_mm(L.d, (int)L.h.size(), L.m3_max, U[0], nrhs[0], z, z ? L.dzo : nullptr, s,
-                    level_s_bytes(L));
+        downward_mm(L.d, (int)L.h.size(), L.m3_max, L.me_max, U[0], nrhs[0], z,
+                    z ? L.dzo : nullptr, s, level_s_bytes(L));
     return;
   }
   HPS_REQUIRE(z == nullptr, "batched downward pass takes no source terms");
@@ -704,7 +704,7 @@ static void downward_batch_nm(const std::vector<hps_op*>& ops, const std::vector
   std::vector<MergeDesc> hm;
   std::vector<SolveIO> hio;
   std::vector<size_t> off(maxd + 2, 0);
-  std::vector<int> m3m(maxd + 1, 0), nrm(maxd + 1, 0);
+  std::vector<int> m3m(maxd + 1, 0), mem(maxd + 1, 0), nrm(maxd + 1, 0);
   std::vector<double> sb(maxd + 1, 0.0);
   for (int d = 0; d <= maxd; ++d) {
     off[d] = hm.size();
@@ -714,6 +714,7 @@ static void downward_batch_nm(const std::vector<hps_op*>& ops, const std::vector
         hm.push_back(m);
         hio.push_back(SolveIO{U[i], ops[i]->tree().N, nrhs[i]});
         m3m[d] = std::max(m3m[d], m.m3);
+        mem[d] = std::max(mem[d], m.me);
         nrm[d] = std::max(nrm[d], nrhs[i]);
         sb[d] += 8.0 * m.m3 * m.me;
       }
@@ -730,7 +731,7 @@ static void downward_batch_nm(const std::vector<hps_op*>& ops, const std::vector
   for (int d = 0; d <= maxd; ++d) {
     const int nm = (int)(off[d + 1] - off[d]);
     if (nm > 0)
-      downward_mm(dm + off[d], nm, m3m[d], nullptr, nrm[d], nullptr, nullptr, s, sb[d],
+      downward_mm(dm + off[d], nm, m3m[d], mem[d], nullptr, nrm[d], nullptr, nullptr, s, sb[d],
                   dio + off[d]);
   }
   HPS_HIP(hipFreeAsync(dm, s));

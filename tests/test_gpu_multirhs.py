@@ -25,6 +25,7 @@ def H(gpu):
     import paper_1307_2665_amd as H
     yield H
     H.tune_set("solve_mm_min_rhs", -1)
+    H.tune_set("split_min_chunk", -1)
 
 
 def _t(x, dev):
@@ -132,3 +133,42 @@ def test_batch_many_rhs(H, gpu):
         say(f"  {pr.name} {pr.nleaf}: vs oracle {e:.2e}")
         assert e < TOL
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("chunk", [16, 48])
+def test_split_contractions(H, gpu, chunk):
+    """Depths with few merges split their contractions (over me downward, over
+    m3 upward) into chunks; forcing short chunks on a small problem exercises
+    every split launch: solve, source solve and refinement against the oracle
+    and against the unsplit passes."""
+    say(f"split contractions, chunks >= {chunk}")
+    pr = hi.helmholtz_bump(nleaf=(8, 8), p=12, q=10)
+    op_o, C_o, f_o, grid = oracle_problem(pr)
+    C, _ = library_inputs(pr)
+    op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q,
+                                   mode=H.HPS_MIXED_SPLIT32)
+    rng = np.random.default_rng(chunk)
+    nrhs = 40
+    f = rng.standard_normal((nrhs, op.n_bdry))
+    s = rng.standard_normal((nrhs, op.N))
+    s[:, op_o.boxes[0].Ie] = 0.0
+    fd, sd = _t(f, gpu), _t(s, gpu)
+
+    def run():
+        info = {}
+        u = op.solve(fd, refine=True, tol=1e-12, max_iter=20, info=info).cpu().numpy()
+        w = op.solve_with_sources(fd, sd).cpu().numpy()
+        return np.concatenate([u, w]), info["iters"]
+
+    res = {}
+    for c in (chunk, -1):
+        H.tune_set("split_min_chunk", c)
+        (a, it), (a2, _) = run(), run()
+        assert np.array_equal(a, a2)
+        res[c] = a
+    H.tune_set("split_min_chunk", -1)
+    u_o = hps.solve(op_o, f)
+    e = max(rel_err(res[chunk][k], u_o[k]) for k in range(nrhs))
+    d = rel_err(res[chunk], res[-1])
+    say(f"  refined solve vs oracle {e:.2e} ({it} sweeps); split vs unsplit {d:.2e}")
+    assert e < TOL and d < 1e-10
