@@ -344,10 +344,12 @@ hps_status hps_prof_query(int cls, double* ms, long long* launches, double* flop
 
 /* Device memory cache.  Operators, plans and temporaries take their device
    memory from a per-device cache that keeps released blocks for reuse, so
-   repeated builds of one shape do not call hipMalloc/hipFree.  hps_mem_trim
-   frees every cached block (blocks in use are untouched) and reports the bytes
-   freed; hps_mem_stats reports the bytes cached and in use.  Either pointer
-   may be NULL. */
+   repeated builds of one shape do not call hipMalloc/hipFree; the
+   stream-ordered scratch of solves is likewise kept in the device's default
+   memory pool.  hps_mem_trim frees every cached block (blocks in use are
+   untouched) and the pool's unused memory on the current device, and reports
+   the bytes freed from the cache; hps_mem_stats reports the bytes cached and
+   in use.  Either pointer may be NULL. */
 hps_status hps_mem_trim(size_t* freed);
 hps_status hps_mem_stats(size_t* cached, size_t* in_use);
 

@@ -83,6 +83,7 @@ extern "C" {
 hps_status hps_mem_trim(size_t* freed) {
   return guard([&] {
     const size_t f = hps::pool_trim();
+    hps::trim_async_pool();
     if (freed) *freed = f;
   });
 }

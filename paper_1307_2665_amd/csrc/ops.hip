@@ -345,10 +345,11 @@ __global__ void __launch_bounds__(256) k_upward_z(const MergeDesc* __restrict__ 
   if (r0 >= d.m3) return;
   const int m3 = d.m3, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   // Offsets are per-box unit offsets; each box holds [nrhs][boundary size].
-  const double* ha = hbase + ha_off[mi] * nrhs + (size_t)rh * d.na;
-  const double* hb = hbase + hb_off[mi] * nrhs + (size_t)rh * d.nb;
+  // Offset -1: the child is a leaf, whose h is zero.
+  const double* ha = ha_off[mi] < 0 ? nullptr : hbase + ha_off[mi] * nrhs + (size_t)rh * d.na;
+  const double* hb = hb_off[mi] < 0 ? nullptr : hbase + hb_off[mi] * nrhs + (size_t)rh * d.nb;
   for (int i = threadIdx.x; i < m3; i += blockDim.x)
-    rhs[i] = s[(size_t)rh * N + d.Ii[i]] - ha[d.a3[i]] + hb[d.b3[i]];
+    rhs[i] = s[(size_t)rh * N + d.Ii[i]] - (ha ? ha[d.a3[i]] : 0.0) + (hb ? hb[d.b3[i]] : 0.0);
   __syncthreads();
   const double* Minv = d.W + d.m3 + d.me;
   double* z = zbuf + z_off[mi] * nrhs + (size_t)rh * m3;
@@ -379,8 +380,8 @@ __global__ void __launch_bounds__(256) k_upward_h(const MergeDesc* __restrict__ 
   const double* z = zbuf + z_off[mi] * nrhs + (size_t)rh * m3;
   for (int i = threadIdx.x; i < m3; i += blockDim.x) zs[i] = z[i];
   __syncthreads();
-  const double* ha = hbase + ha_off[mi] * nrhs + (size_t)rh * d.na;
-  const double* hb = hbase + hb_off[mi] * nrhs + (size_t)rh * d.nb;
+  const double* ha = ha_off[mi] < 0 ? nullptr : hbase + ha_off[mi] * nrhs + (size_t)rh * d.na;
+  const double* hb = hb_off[mi] < 0 ? nullptr : hbase + hb_off[mi] * nrhs + (size_t)rh * d.nb;
   double* hp = hbase + hp_off[mi] * nrhs + (size_t)rh * d.me;
   for (int rr = wid; rr < UROWS; rr += 4) {
     const int r = r0 + rr;
@@ -391,7 +392,7 @@ __global__ void __launch_bounds__(256) k_upward_h(const MergeDesc* __restrict__ 
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if (lane == 0) {
       const int pm = d.pmap[r];
-      hp[r] = acc + ((pm >= 0) ? ha[pm] : hb[-pm - 1]);
+      hp[r] = acc + ((pm >= 0) ? (ha ? ha[pm] : 0.0) : (hb ? hb[-pm - 1] : 0.0));
     }
   }
 }
@@ -429,7 +430,7 @@ __global__ void k_absmax(const double* __restrict__ x, size_t n, double* __restr
   double m = 0.0;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
        e += (size_t)gridDim.x * blockDim.x)
-    m = fmax(m, fabs(x[e]));
+    m = x[e] != x[e] ? INFINITY : fmax(m, fabs(x[e]));  // NaN counts as infinite
   for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
   if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
   __syncthreads();
@@ -509,7 +510,21 @@ void leaf_range_flags(const double* const* cptr, int nl, int pp, const double* l
 // with gathered and scattered rows.  Per box the upward-pass arrays h are
 // [boundary size][nrhs] and z is [m3][nrhs].
 // ---------------------------------------------------------------------------
-#define HPS_MM_TILE(BN) 64, BN, 16, (BN == 16 ? 4 : 2), (BN == 16 ? 1 : 2)
+// Tiles of these passes: BM x BN outputs (BM = 16, 32 or 64 rows, so that
+// the short interfaces of the lowest depths do not run mostly padded tiles;
+// BN = 16, 32 or 64 right-hand sides), BK = 16, WM x WN waves.
+template <int BM, int BN>
+struct MmCfg {
+  static constexpr int WM = BM == 16 ? 1 : (BM == 32 ? 2 : (BN == 16 ? 4 : 2));
+  static constexpr int WN =
+      BM == 16 ? BN / 16 : (BM == 32 ? (BN == 64 ? 2 : 1) : (BN == 16 ? 1 : 2));
+  static constexpr int NT = 64 * WM * WN;
+};
+#define HPS_MMT(BM, BN) BM, BN, 16, MmCfg<BM, BN>::WM, MmCfg<BM, BN>::WN
+#define HPS_MM_TILE(BN) HPS_MMT(64, BN)
+
+// Row-tile height for a launch whose output blocks have at most rows rows.
+static int mm_rows(int rows) { return rows <= 16 ? 16 : (rows <= 32 ? 32 : 64); }
 
 // Algorithm 2 for one depth: U[Ii[r]][:] = S[r][:] U[Ie[:]][:] (+ z[r][:]).
 // Depths with few merges split the contraction over me into ks chunks
@@ -577,19 +592,19 @@ static int split_chunks(long long tiles, int K) {
   return (int)std::max<long long>(1, std::min<long long>(want, K / g_split_min));
 }
 
-template <int BN>
+template <int BM, int BN>
 static void launch_down_mm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max,
                            double* U, int nrhs, const double* zbase, const long long* zoff,
                            const SolveIO* io, hipStream_t s) {
-  const long long tiles = (long long)((nrhs + BN - 1) / BN) * ((m3_max + 63) / 64) * nmerge;
+  const long long tiles = (long long)((nrhs + BN - 1) / BN) * ((m3_max + BM - 1) / BM) * nmerge;
   const int ks = io ? 1 : split_chunks(tiles, me_max);
   HPS_REQUIRE((long long)nmerge * ks <= 65535, "downward pass: too many merges at one depth");
   double* P = nullptr;
   if (ks > 1)
     HPS_HIP(hipMallocAsync((void**)&P, (size_t)nmerge * ks * m3_max * nrhs * sizeof(double), s));
-  dim3 grid((nrhs + BN - 1) / BN, (m3_max + 63) / 64, nmerge * ks);
-  hipLaunchKernelGGL((k_down_mm<HPS_MM_TILE(BN)>), grid, dim3(256), 0, s, d_desc, U, nrhs, zbase,
-                     zoff, io, ks, P, m3_max);
+  dim3 grid((nrhs + BN - 1) / BN, (m3_max + BM - 1) / BM, nmerge * ks);
+  hipLaunchKernelGGL((k_down_mm<HPS_MMT(BM, BN)>), grid, dim3(MmCfg<BM, BN>::NT), 0, s, d_desc, U,
+                     nrhs, zbase, zoff, io, ks, P, m3_max);
   if (ks > 1) {
     const int bx = std::max(1, std::min(64, (m3_max * nrhs + 255) / 256));
     hipLaunchKernelGGL(k_down_reduce, dim3(bx, nmerge), dim3(256), 0, s, d_desc, U, nrhs, zbase,
@@ -598,17 +613,30 @@ static void launch_down_mm(const MergeDesc* d_desc, int nmerge, int m3_max, int 
   }
 }
 
+template <int BM>
+static void launch_down_mm_bn(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max,
+                              double* U, int nrhs, const double* zbase, const long long* zoff,
+                              const SolveIO* io, hipStream_t s) {
+  if (nrhs > 32)
+    launch_down_mm<BM, 64>(d_desc, nmerge, m3_max, me_max, U, nrhs, zbase, zoff, io, s);
+  else if (nrhs > 16)
+    launch_down_mm<BM, 32>(d_desc, nmerge, m3_max, me_max, U, nrhs, zbase, zoff, io, s);
+  else
+    launch_down_mm<BM, 16>(d_desc, nmerge, m3_max, me_max, U, nrhs, zbase, zoff, io, s);
+}
+
 void downward_mm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, double* U, int nrhs,
                  const double* zbase, const long long* zoff, hipStream_t s, double s_bytes,
                  const SolveIO* io) {
   if (nmerge == 0) return;
   ProfScope ps(PROF_DOWNWARD, s, 2.0 * nrhs * s_bytes / 8.0, s_bytes);
-  if (nrhs > 32)
-    launch_down_mm<64>(d_desc, nmerge, m3_max, me_max, U, nrhs, zbase, zoff, io, s);
-  else if (nrhs > 16)
-    launch_down_mm<32>(d_desc, nmerge, m3_max, me_max, U, nrhs, zbase, zoff, io, s);
+  const int bm = mm_rows(m3_max);
+  if (bm == 16)
+    launch_down_mm_bn<16>(d_desc, nmerge, m3_max, me_max, U, nrhs, zbase, zoff, io, s);
+  else if (bm == 32)
+    launch_down_mm_bn<32>(d_desc, nmerge, m3_max, me_max, U, nrhs, zbase, zoff, io, s);
   else
-    launch_down_mm<16>(d_desc, nmerge, m3_max, me_max, U, nrhs, zbase, zoff, io, s);
+    launch_down_mm_bn<64>(d_desc, nmerge, m3_max, me_max, U, nrhs, zbase, zoff, io, s);
 }
 
 // Node-major boundary data: U[gamma[i]][r] = f[r][i].
@@ -708,16 +736,16 @@ void interface_residual_nm(const double* leafT, const double* U, int N, int nrhs
   ProfScope ps(PROF_RESIDUAL, s, 2.0 * nrhs * nx * ny * (double)m * m, 8.0 * nx * ny * (double)m * m);
   if (nrhs > 32) {
     dim3 grid((nrhs + 63) / 64, (m + 63) / 64, nx * ny);
-    hipLaunchKernelGGL((k_flux_mm<HPS_MM_TILE(64)>), grid, dim3(256), 0, s, leafT, U, nrhs, nx, ny,
-                       q, vbuf);
+    hipLaunchKernelGGL((k_flux_mm<HPS_MM_TILE(64)>), grid, dim3(MmCfg<64, 64>::NT), 0, s, leafT,
+                       U, nrhs, nx, ny, q, vbuf);
   } else if (nrhs > 16) {
     dim3 grid((nrhs + 31) / 32, (m + 63) / 64, nx * ny);
-    hipLaunchKernelGGL((k_flux_mm<HPS_MM_TILE(32)>), grid, dim3(256), 0, s, leafT, U, nrhs, nx, ny,
-                       q, vbuf);
+    hipLaunchKernelGGL((k_flux_mm<HPS_MM_TILE(32)>), grid, dim3(MmCfg<64, 32>::NT), 0, s, leafT,
+                       U, nrhs, nx, ny, q, vbuf);
   } else {
     dim3 grid((nrhs + 15) / 16, (m + 63) / 64, nx * ny);
-    hipLaunchKernelGGL((k_flux_mm<HPS_MM_TILE(16)>), grid, dim3(256), 0, s, leafT, U, nrhs, nx, ny,
-                       q, vbuf);
+    hipLaunchKernelGGL((k_flux_mm<HPS_MM_TILE(16)>), grid, dim3(MmCfg<64, 16>::NT), 0, s, leafT,
+                       U, nrhs, nx, ny, q, vbuf);
   }
   const size_t tot = (size_t)N * nrhs;
   const int blocks = (int)std::min<size_t>((tot + 255) / 256, 8192);
@@ -727,28 +755,36 @@ void interface_residual_nm(const double* leafT, const double* U, int N, int nrhs
 // Upward source pass for one depth, node-major (same equations as
 // k_upward_z / k_upward_h): rhs = s3 - h3a + h3b gathered per merge, then
 // z = M^-1 rhs and h_parent = [h1a ; h2b] + Q z as grouped GEMMs.
-__global__ void k_up_gather_nm(const MergeDesc* __restrict__ descs, const double* __restrict__ src,
-                               double* __restrict__ hbase,
-                               const long long* __restrict__ ha_off,
-                               const long long* __restrict__ hb_off,
-                               const long long* __restrict__ hp_off,
-                               const long long* __restrict__ z_off, int nrhs,
-                               double* __restrict__ rbuf) {
-  const MergeDesc d = descs[blockIdx.y];
-  const double* ha = hbase + ha_off[blockIdx.y] * nrhs;
-  const double* hb = hbase + hb_off[blockIdx.y] * nrhs;
-  double* hp = hbase + hp_off[blockIdx.y] * nrhs;
-  double* rr = rbuf + z_off[blockIdx.y] * nrhs;
-  const int n3 = d.m3 * nrhs, ne = d.me * nrhs;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n3 + ne; e += gridDim.x * blockDim.x) {
-    if (e < n3) {
-      const int i = e / nrhs, k = e % nrhs;
-      rr[e] = src[(size_t)d.Ii[i] * nrhs + k] - ha[(size_t)d.a3[i] * nrhs + k] +
-              hb[(size_t)d.b3[i] * nrhs + k];
+// Rows of merge blockIdx.y: rhs[i][:] = src[Ii[i]][:] - ha[a3[i]][:] +
+// hb[b3[i]][:] and h_parent[r][:] = ha[pmap[r]][:] (or hb's row); thread
+// (x, y) of a (64, 4) block takes column x (+ 64 j) of rows y + 4 k.  A leaf
+// child (offset -1) contributes zero.
+__global__ void __launch_bounds__(256) k_up_gather_nm(const MergeDesc* __restrict__ descs,
+                                                      const double* __restrict__ src,
+                                                      double* __restrict__ hbase,
+                                                      const long long* __restrict__ ha_off,
+                                                      const long long* __restrict__ hb_off,
+                                                      const long long* __restrict__ hp_off,
+                                                      const long long* __restrict__ z_off,
+                                                      int nrhs, double* __restrict__ rbuf) {
+  const int mi = blockIdx.y;
+  const MergeDesc d = descs[mi];
+  const double* ha = ha_off[mi] < 0 ? nullptr : hbase + ha_off[mi] * nrhs;
+  const double* hb = hb_off[mi] < 0 ? nullptr : hbase + hb_off[mi] * nrhs;
+  double* hp = hbase + hp_off[mi] * nrhs;
+  double* rr = rbuf + z_off[mi] * nrhs;
+  for (int i = blockIdx.x * 4 + threadIdx.y; i < d.m3 + d.me; i += gridDim.x * 4) {
+    if (i < d.m3) {
+      const double* sr = src + (size_t)d.Ii[i] * nrhs;
+      const double* ar = ha ? ha + (size_t)d.a3[i] * nrhs : nullptr;
+      const double* br = hb ? hb + (size_t)d.b3[i] * nrhs : nullptr;
+      for (int k = threadIdx.x; k < nrhs; k += 64)
+        rr[(size_t)i * nrhs + k] = sr[k] - (ar ? ar[k] : 0.0) + (br ? br[k] : 0.0);
     } else {
-      const int e2 = e - n3, r = e2 / nrhs, k = e2 % nrhs;
-      const int pm = d.pmap[r];
-      hp[e2] = (pm >= 0) ? ha[(size_t)pm * nrhs + k] : hb[(size_t)(-pm - 1) * nrhs + k];
+      const int r = i - d.m3, pm = d.pmap[r];
+      const double* pr = pm >= 0 ? (ha ? ha + (size_t)pm * nrhs : nullptr)
+                                 : (hb ? hb + (size_t)(-pm - 1) * nrhs : nullptr);
+      for (int k = threadIdx.x; k < nrhs; k += 64) hp[(size_t)r * nrhs + k] = pr ? pr[k] : 0.0;
     }
   }
 }
@@ -821,12 +857,12 @@ __global__ void k_up_reduce(const MergeDesc* __restrict__ descs, double* __restr
   }
 }
 
-template <int BN>
+template <int BMZ, int BN>
 static void launch_up_mm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max,
                          double* hbase, const long long* hp_off, double* rbuf, double* zbuf,
                          const long long* z_off, int nrhs, hipStream_t st) {
   const int ct = (nrhs + BN - 1) / BN;
-  const int ksz = split_chunks((long long)ct * ((m3_max + 63) / 64) * nmerge, m3_max);
+  const int ksz = split_chunks((long long)ct * ((m3_max + BMZ - 1) / BMZ) * nmerge, m3_max);
   const int ksh = split_chunks((long long)ct * ((me_max + 63) / 64) * nmerge, m3_max);
   HPS_REQUIRE((long long)nmerge * std::max(ksz, ksh) <= 65535,
               "upward pass: too many merges at one depth");
@@ -836,19 +872,34 @@ static void launch_up_mm(const MergeDesc* d_desc, int nmerge, int m3_max, int me
     HPS_HIP(hipMallocAsync((void**)&P, std::max(ksz > 1 ? pz : 0, ksh > 1 ? ph : 0) *
                                            sizeof(double), st));
   const int bx = std::max(1, std::min(64, ((m3_max + me_max) * nrhs + 255) / 256));
-  dim3 gz(ct, (m3_max + 63) / 64, nmerge * ksz);
-  hipLaunchKernelGGL((k_up_z_mm<HPS_MM_TILE(BN)>), gz, dim3(256), 0, st, d_desc, rbuf, zbuf, z_off,
-                     nrhs, ksz, P, m3_max);
+  dim3 gz(ct, (m3_max + BMZ - 1) / BMZ, nmerge * ksz);
+  hipLaunchKernelGGL((k_up_z_mm<HPS_MMT(BMZ, BN)>), gz, dim3(MmCfg<BMZ, BN>::NT), 0, st, d_desc,
+                     rbuf, zbuf, z_off, nrhs, ksz, P, m3_max);
   if (ksz > 1)
     hipLaunchKernelGGL(k_up_reduce, dim3(bx, nmerge), dim3(256), 0, st, d_desc, zbuf, z_off, nrhs,
                        ksz, P, m3_max, 0);
   dim3 gh(ct, (me_max + 63) / 64, nmerge * ksh);
-  hipLaunchKernelGGL((k_up_h_mm<HPS_MM_TILE(BN)>), gh, dim3(256), 0, st, d_desc, zbuf, z_off, hbase,
-                     hp_off, nrhs, ksh, P, me_max);
+  hipLaunchKernelGGL((k_up_h_mm<HPS_MM_TILE(BN)>), gh, dim3(MmCfg<64, BN>::NT), 0, st, d_desc, zbuf,
+                     z_off, hbase, hp_off, nrhs, ksh, P, me_max);
   if (ksh > 1)
     hipLaunchKernelGGL(k_up_reduce, dim3(bx, nmerge), dim3(256), 0, st, d_desc, hbase, hp_off, nrhs,
                        ksh, P, me_max, 1);
   if (P) HPS_HIP(hipFreeAsync(P, st));
+}
+
+template <int BMZ>
+static void launch_up_mm_bn(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max,
+                            double* hbase, const long long* hp_off, double* rbuf, double* zbuf,
+                            const long long* z_off, int nrhs, hipStream_t st) {
+  if (nrhs > 32)
+    launch_up_mm<BMZ, 64>(d_desc, nmerge, m3_max, me_max, hbase, hp_off, rbuf, zbuf, z_off, nrhs,
+                          st);
+  else if (nrhs > 16)
+    launch_up_mm<BMZ, 32>(d_desc, nmerge, m3_max, me_max, hbase, hp_off, rbuf, zbuf, z_off, nrhs,
+                          st);
+  else
+    launch_up_mm<BMZ, 16>(d_desc, nmerge, m3_max, me_max, hbase, hp_off, rbuf, zbuf, z_off, nrhs,
+                          st);
 }
 
 void upward_level_nm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, const double* src,
@@ -857,16 +908,19 @@ void upward_level_nm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max
                      int nrhs, double flops, hipStream_t st) {
   if (nmerge == 0) return;
   ProfScope ps(PROF_UPWARD, st, flops, 8.0 * flops / (2.0 * nrhs));
-  const int per = (m3_max + me_max) * nrhs;
-  const int bx = std::min(64, std::max(1, (per + 255) / 256));
-  hipLaunchKernelGGL(k_up_gather_nm, dim3(bx, nmerge), dim3(256), 0, st, d_desc, src, hbase, ha_off,
-                     hb_off, hp_off, z_off, nrhs, rbuf);
-  if (nrhs > 32)
-    launch_up_mm<64>(d_desc, nmerge, m3_max, me_max, hbase, hp_off, rbuf, zbuf, z_off, nrhs, st);
-  else if (nrhs > 16)
-    launch_up_mm<32>(d_desc, nmerge, m3_max, me_max, hbase, hp_off, rbuf, zbuf, z_off, nrhs, st);
+  const int bx = std::min(64, std::max(1, (m3_max + me_max + 3) / 4));
+  hipLaunchKernelGGL(k_up_gather_nm, dim3(bx, nmerge), dim3(64, 4), 0, st, d_desc, src, hbase,
+                     ha_off, hb_off, hp_off, z_off, nrhs, rbuf);
+  const int bm = mm_rows(m3_max);
+  if (bm == 16)
+    launch_up_mm_bn<16>(d_desc, nmerge, m3_max, me_max, hbase, hp_off, rbuf, zbuf, z_off, nrhs,
+                        st);
+  else if (bm == 32)
+    launch_up_mm_bn<32>(d_desc, nmerge, m3_max, me_max, hbase, hp_off, rbuf, zbuf, z_off, nrhs,
+                        st);
   else
-    launch_up_mm<16>(d_desc, nmerge, m3_max, me_max, hbase, hp_off, rbuf, zbuf, z_off, nrhs, st);
+    launch_up_mm_bn<64>(d_desc, nmerge, m3_max, me_max, hbase, hp_off, rbuf, zbuf, z_off, nrhs,
+                        st);
 }
 
 void ops_init() {

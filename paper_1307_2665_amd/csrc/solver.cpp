@@ -23,6 +23,7 @@
 #include <memory>
 #include <mutex>
 #include <random>
+#include <set>
 #include <tuple>
 
 #include "dense.h"
@@ -54,9 +55,36 @@ hps_op::~hps_op() {
 
 namespace hps {
 
+// Stream-ordered scratch (hipMallocAsync) comes from the device's default
+// pool; by default that pool hands freed memory back at every
+// synchronization, so each solve would map its buffers afresh.  Keep it
+// cached instead (hps_mem_trim releases it).
+static void keep_async_pool() {
+  static std::mutex mu;
+  static std::set<int> done;
+  int dev = 0;
+  HPS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  if (done.count(dev)) return;
+  hipMemPool_t pool = nullptr;
+  HPS_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+  uint64_t keep = UINT64_MAX;
+  HPS_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+  done.insert(dev);
+}
+
+void trim_async_pool() {
+  int dev = 0;
+  HPS_HIP(hipGetDevice(&dev));
+  hipMemPool_t pool = nullptr;
+  HPS_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+  HPS_HIP(hipMemPoolTrimTo(pool, 0));
+}
+
 static void init_runtime() {
   dense_init();
   ops_init();
+  keep_async_pool();
 }
 
 static inline int bdry_size(const BoxRec& b, int q) { return 2 * q * ((b.i1 - b.i0) + (b.j1 - b.j0)); }
@@ -165,13 +193,16 @@ static std::shared_ptr<const TreePlan> tree_plan(int nx, int ny, int p, int q, d
       }
     tp->ar[0] = tp->ar[1] = 0;
     for (int d = 0; d <= t.depth; ++d) tp->ar[d % 2] = std::max(tp->ar[d % 2], lvlT[d]);
-    tp->box_hoff.assign(nbox, 0);
+    // Upward-pass storage h: only merged boxes have any (a leaf's h is zero,
+    // marked by offset -1), so the pass needs no clearing.
+    tp->box_hoff.assign(nbox, -1);
     long long hu = 0;
     for (int b = 0; b < nbox; ++b) {
+      if (t.boxes[b].ca < 0) continue;
       tp->box_hoff[b] = hu;
       hu += bdry_size(t.boxes[b], q);
     }
-    tp->h_units = hu;
+    tp->h_units = std::max(hu, 1LL);
     // Pool of index maps followed by the boundary ids of the root.
     tp->pool_host = std::move(pool);
     tp->gamma_off = tp->pool_host.size();
@@ -744,7 +775,6 @@ static void downward_batch_nm(const std::vector<hps_op*>& ops, const std::vector
 static void upward_all_nm(hps_op* op, const double* src, int nrhs, double* h, double* z,
                           double* rb, hipStream_t s) {
   HPS_REQUIRE(op->opt.keep_factors, "operator was built without keep_factors");
-  HPS_HIP(hipMemsetAsync(h, 0, (size_t)op->h_units * nrhs * sizeof(double), s));
   for (int d = (int)op->levels.size() - 1; d >= 0; --d) {
     const LevelPlan& L = op->levels[d];
     if (L.h.empty()) continue;
@@ -768,6 +798,7 @@ struct AsyncBuf {
 };
 
 static void solve_mm(hps_op* op, const double* f, int nrhs, double* u, hipStream_t s) {
+  keep_async_pool();
   const int N = op->tree().N;
   AsyncBuf U((size_t)N * nrhs, s);
   set_boundary_nm(f, op->gamma, op->n_bdry, nrhs, U.p, s);
@@ -858,7 +889,7 @@ void solve_batch_device(const std::vector<hps_op*>& ops, const std::vector<const
 }
 
 double absmax_device(const double* x, size_t n, hipStream_t s) {
-  const int blocks = 256;
+  const int blocks = 2048;
   double* part = nullptr;
   HPS_HIP(hipMallocAsync((void**)&part, blocks * sizeof(double), s));
   absmax_partial(x, n, part, blocks, s);
@@ -892,7 +923,6 @@ void residual_device(const hps_op* op, const double* u, int nrhs, double* r, hip
 static void upward_all(hps_op* op, const double* src, int nrhs, double* h, double* z,
                        hipStream_t s) {
   HPS_REQUIRE(op->opt.keep_factors, "operator was built without keep_factors");
-  HPS_HIP(hipMemsetAsync(h, 0, (size_t)op->h_units * nrhs * sizeof(double), s));
   for (int d = (int)op->levels.size() - 1; d >= 0; --d) {
     const LevelPlan& L = op->levels[d];
     if (L.h.empty()) continue;
@@ -948,6 +978,7 @@ static void refine_report(hps_solve_info* info, int it, double first, double las
 // pass, correction by the downward pass, all as grouped MFMA GEMMs.
 static void refine_mm(hps_op* op, int nrhs, double* u, double tol, int max_iter, hipStream_t s,
                       hps_solve_info* info) {
+  keep_async_pool();
   const int N = op->tree().N, nl = op->nx * op->ny, m = 4 * op->q;
   const size_t nu = (size_t)N * nrhs;
   AsyncBuf U(nu, s), r(nu, s), du(nu, s), v((size_t)nl * m * nrhs, s);
