@@ -41,14 +41,17 @@ struct GemmTile {
 
 // Tile (row0.., col0..) of C = C0 (or C) + alpha * A (M x K) * B (K x N),
 // row-major with the given leading dimensions, where B's row k lives at
-// B + brow(k) * ldb and C's row r at C + crow(r) * ldc (a gathered operand
-// and a scattered result; A and C0 rows are plain).  With C0 null the old C
-// is added when acc_c is set and nothing otherwise (C is then not read).
-template <int BM, int BN, int BK, int WM, int WN, class BRow, class CRow>
+// B + brow(k) * ldb, C's row r at C + crow(r) * ldc and C0's row r at
+// C0 + c0row(r) * ldc0 (gathered operands, a scattered result; a negative
+// c0row is a zero row; A rows are plain).  With C0 null the old C is added
+// when acc_c is set and nothing otherwise (C is then not read).
+template <int BM, int BN, int BK, int WM, int WN, class BRow, class CRow,
+          class C0Row = RowsIdentity>
 __device__ inline void gemm_tile_map(const double* __restrict__ A, int lda,
                                      const double* B, int ldb, BRow brow, double* C, int ldc,
                                      CRow crow, const double* C0, int ldc0, int M, int N, int K,
-                                     double alpha, int row0, int col0, double* sm, bool acc_c) {
+                                     double alpha, int row0, int col0, double* sm, bool acc_c,
+                                     C0Row c0row = C0Row{}) {
   using T = GemmTile<BM, BN, BK, WM, WN>;
   double(*As)[BM + 1] = reinterpret_cast<double(*)[BM + 1]>(sm);
   double(*Bs)[BN + 1] = reinterpret_cast<double(*)[BN + 1]>(sm + BK * (BM + 1));
@@ -122,7 +125,13 @@ __device__ inline void gemm_tile_map(const double* __restrict__ A, int lda,
         const int gc = col0 + wn * WBN + j * 16 + (lane & 15);
         if (gr < M && gc < N) {
           double* cp = C + (size_t)crow(gr) * ldc + gc;
-          const double c0 = C0 ? C0[(size_t)gr * ldc0 + gc] : (acc_c ? *cp : 0.0);
+          double c0 = 0.0;
+          if (C0) {
+            const int r0 = c0row(gr);
+            if (r0 >= 0) c0 = C0[(size_t)r0 * ldc0 + gc];
+          } else if (acc_c) {
+            c0 = *cp;
+          }
           *cp = c0 + alpha * acc[i][j][r];
         }
       }

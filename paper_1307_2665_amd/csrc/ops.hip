@@ -756,38 +756,41 @@ void interface_residual_nm(const double* leafT, const double* U, int N, int nrhs
 // k_upward_z / k_upward_h): rhs = s3 - h3a + h3b gathered per merge, then
 // z = M^-1 rhs and h_parent = [h1a ; h2b] + Q z as grouped GEMMs.
 // Rows of merge blockIdx.y: rhs[i][:] = src[Ii[i]][:] - ha[a3[i]][:] +
-// hb[b3[i]][:] and h_parent[r][:] = ha[pmap[r]][:] (or hb's row); thread
-// (x, y) of a (64, 4) block takes column x (+ 64 j) of rows y + 4 k.  A leaf
-// child (offset -1) contributes zero.
+// hb[b3[i]][:]; thread (x, y) of a (64, 4) block takes column x (+ 64 j) of
+// rows y + 4 k.  A leaf child (offset -1) contributes zero.
 __global__ void __launch_bounds__(256) k_up_gather_nm(const MergeDesc* __restrict__ descs,
                                                       const double* __restrict__ src,
-                                                      double* __restrict__ hbase,
+                                                      const double* __restrict__ hbase,
                                                       const long long* __restrict__ ha_off,
                                                       const long long* __restrict__ hb_off,
-                                                      const long long* __restrict__ hp_off,
                                                       const long long* __restrict__ z_off,
                                                       int nrhs, double* __restrict__ rbuf) {
   const int mi = blockIdx.y;
   const MergeDesc d = descs[mi];
   const double* ha = ha_off[mi] < 0 ? nullptr : hbase + ha_off[mi] * nrhs;
   const double* hb = hb_off[mi] < 0 ? nullptr : hbase + hb_off[mi] * nrhs;
-  double* hp = hbase + hp_off[mi] * nrhs;
   double* rr = rbuf + z_off[mi] * nrhs;
-  for (int i = blockIdx.x * 4 + threadIdx.y; i < d.m3 + d.me; i += gridDim.x * 4) {
-    if (i < d.m3) {
-      const double* sr = src + (size_t)d.Ii[i] * nrhs;
-      const double* ar = ha ? ha + (size_t)d.a3[i] * nrhs : nullptr;
-      const double* br = hb ? hb + (size_t)d.b3[i] * nrhs : nullptr;
-      for (int k = threadIdx.x; k < nrhs; k += 64)
-        rr[(size_t)i * nrhs + k] = sr[k] - (ar ? ar[k] : 0.0) + (br ? br[k] : 0.0);
-    } else {
-      const int r = i - d.m3, pm = d.pmap[r];
-      const double* pr = pm >= 0 ? (ha ? ha + (size_t)pm * nrhs : nullptr)
-                                 : (hb ? hb + (size_t)(-pm - 1) * nrhs : nullptr);
-      for (int k = threadIdx.x; k < nrhs; k += 64) hp[(size_t)r * nrhs + k] = pr ? pr[k] : 0.0;
-    }
+  for (int i = blockIdx.x * 4 + threadIdx.y; i < d.m3; i += gridDim.x * 4) {
+    const double* sr = src + (size_t)d.Ii[i] * nrhs;
+    const double* ar = ha ? ha + (size_t)d.a3[i] * nrhs : nullptr;
+    const double* br = hb ? hb + (size_t)d.b3[i] * nrhs : nullptr;
+    for (int k = threadIdx.x; k < nrhs; k += 64)
+      rr[(size_t)i * nrhs + k] = sr[k] - (ar ? ar[k] : 0.0) + (br ? br[k] : 0.0);
   }
 }
+
+// Row r of the pass-through [h1a ; h2b] of a parent, as a row of the h
+// array (rows of nrhs values): alpha's row pmap[r] or beta's row
+// -pmap[r] - 1; -1 (zero) for a leaf child.
+struct PassRows {
+  const int* pmap;
+  long long ha, hb;
+  __device__ int operator()(int r) const {
+    const int pm = pmap[r];
+    if (pm >= 0) return ha < 0 ? -1 : (int)(ha + pm);
+    return hb < 0 ? -1 : (int)(hb - pm - 1);
+  }
+};
 
 // z = M^-1 rhs (M^-1 at W + m3 + me) and h_parent += Q z for every merge of a
 // depth; with ks > 1 the contraction over m3 is split as in k_down_mm and the
@@ -818,6 +821,8 @@ __global__ void __launch_bounds__(64 * WM * WN) k_up_h_mm(const MergeDesc* __res
                                                          const double* __restrict__ zbuf,
                                                          const long long* __restrict__ z_off,
                                                          double* __restrict__ hbase,
+                                                         const long long* __restrict__ ha_off,
+                                                         const long long* __restrict__ hb_off,
                                                          const long long* __restrict__ hp_off,
                                                          int nrhs, int ks, double* __restrict__ P,
                                                          int rows_max) {
@@ -830,8 +835,10 @@ __global__ void __launch_bounds__(64 * WM * WN) k_up_h_mm(const MergeDesc* __res
   const int k0 = min(d.m3, kc * kchunk), K = min(kchunk, d.m3 - k0);
   const double* B = zbuf + z_off[mi] * nrhs + (size_t)k0 * nrhs;
   if (ks == 1)
-    gemm_tile<BM, BN, BK, WM, WN>(d.Q, d.m3, B, nrhs, hbase + hp_off[mi] * nrhs, nrhs, nullptr, 0,
-                                  d.me, nrhs, d.m3, 1.0, row0, col0, sm);
+    gemm_tile_map<BM, BN, BK, WM, WN>(d.Q, d.m3, B, nrhs, RowsIdentity{},
+                                      hbase + hp_off[mi] * nrhs, nrhs, RowsIdentity{}, hbase, nrhs,
+                                      d.me, nrhs, d.m3, 1.0, row0, col0, sm, false,
+                                      PassRows{d.pmap, ha_off[mi], hb_off[mi]});
   else
     gemm_tile_map<BM, BN, BK, WM, WN>(d.Q + k0, d.m3, B, nrhs, RowsIdentity{},
                                       P + (size_t)blockIdx.z * rows_max * nrhs, nrhs,
@@ -839,19 +846,26 @@ __global__ void __launch_bounds__(64 * WM * WN) k_up_h_mm(const MergeDesc* __res
                                       sm, false);
 }
 
-// dst rows of merge mi (z: m3 rows, overwritten; h: me rows, added to) from
-// the ks partial products.
+// dst rows of merge mi from the ks partial products: z (m3 rows) or, with
+// to_h, h_parent (me rows) with its pass-through rows added.
 __global__ void k_up_reduce(const MergeDesc* __restrict__ descs, double* __restrict__ base,
                             const long long* __restrict__ off, int nrhs, int ks,
-                            const double* __restrict__ P, int rows_max, int to_h) {
+                            const double* __restrict__ P, int rows_max, int to_h,
+                            const double* __restrict__ hbase, const long long* __restrict__ ha_off,
+                            const long long* __restrict__ hb_off) {
   const int mi = blockIdx.y;
   const MergeDesc d = descs[mi];
   const int rows = to_h ? d.me : d.m3;
   double* dst = base + off[mi] * nrhs;
   const double* Pm = P + (size_t)mi * ks * rows_max * nrhs;
+  const PassRows pass{d.pmap, to_h ? ha_off[mi] : -1, to_h ? hb_off[mi] : -1};
   const int tot = rows * nrhs;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
-    double v = to_h ? dst[e] : 0.0;
+    double v = 0.0;
+    if (to_h) {
+      const int pr = pass(e / nrhs);
+      if (pr >= 0) v = hbase[(size_t)pr * nrhs + e % nrhs];
+    }
     for (int j = 0; j < ks; ++j) v += Pm[(size_t)j * rows_max * nrhs + e];
     dst[e] = v;
   }
@@ -859,7 +873,8 @@ __global__ void k_up_reduce(const MergeDesc* __restrict__ descs, double* __restr
 
 template <int BMZ, int BN>
 static void launch_up_mm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max,
-                         double* hbase, const long long* hp_off, double* rbuf, double* zbuf,
+                         double* hbase, const long long* ha_off, const long long* hb_off,
+                         const long long* hp_off, double* rbuf, double* zbuf,
                          const long long* z_off, int nrhs, hipStream_t st) {
   const int ct = (nrhs + BN - 1) / BN;
   const int ksz = split_chunks((long long)ct * ((m3_max + BMZ - 1) / BMZ) * nmerge, m3_max);
@@ -877,29 +892,30 @@ static void launch_up_mm(const MergeDesc* d_desc, int nmerge, int m3_max, int me
                      rbuf, zbuf, z_off, nrhs, ksz, P, m3_max);
   if (ksz > 1)
     hipLaunchKernelGGL(k_up_reduce, dim3(bx, nmerge), dim3(256), 0, st, d_desc, zbuf, z_off, nrhs,
-                       ksz, P, m3_max, 0);
+                       ksz, P, m3_max, 0, hbase, ha_off, hb_off);
   dim3 gh(ct, (me_max + 63) / 64, nmerge * ksh);
   hipLaunchKernelGGL((k_up_h_mm<HPS_MM_TILE(BN)>), gh, dim3(MmCfg<64, BN>::NT), 0, st, d_desc, zbuf,
-                     z_off, hbase, hp_off, nrhs, ksh, P, me_max);
+                     z_off, hbase, ha_off, hb_off, hp_off, nrhs, ksh, P, me_max);
   if (ksh > 1)
     hipLaunchKernelGGL(k_up_reduce, dim3(bx, nmerge), dim3(256), 0, st, d_desc, hbase, hp_off, nrhs,
-                       ksh, P, me_max, 1);
+                       ksh, P, me_max, 1, hbase, ha_off, hb_off);
   if (P) HPS_HIP(hipFreeAsync(P, st));
 }
 
 template <int BMZ>
 static void launch_up_mm_bn(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max,
-                            double* hbase, const long long* hp_off, double* rbuf, double* zbuf,
+                            double* hbase, const long long* ha_off, const long long* hb_off,
+                            const long long* hp_off, double* rbuf, double* zbuf,
                             const long long* z_off, int nrhs, hipStream_t st) {
   if (nrhs > 32)
-    launch_up_mm<BMZ, 64>(d_desc, nmerge, m3_max, me_max, hbase, hp_off, rbuf, zbuf, z_off, nrhs,
-                          st);
+    launch_up_mm<BMZ, 64>(d_desc, nmerge, m3_max, me_max, hbase, ha_off, hb_off, hp_off, rbuf,
+                          zbuf, z_off, nrhs, st);
   else if (nrhs > 16)
-    launch_up_mm<BMZ, 32>(d_desc, nmerge, m3_max, me_max, hbase, hp_off, rbuf, zbuf, z_off, nrhs,
-                          st);
+    launch_up_mm<BMZ, 32>(d_desc, nmerge, m3_max, me_max, hbase, ha_off, hb_off, hp_off, rbuf,
+                          zbuf, z_off, nrhs, st);
   else
-    launch_up_mm<BMZ, 16>(d_desc, nmerge, m3_max, me_max, hbase, hp_off, rbuf, zbuf, z_off, nrhs,
-                          st);
+    launch_up_mm<BMZ, 16>(d_desc, nmerge, m3_max, me_max, hbase, ha_off, hb_off, hp_off, rbuf,
+                          zbuf, z_off, nrhs, st);
 }
 
 void upward_level_nm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, const double* src,
@@ -908,19 +924,19 @@ void upward_level_nm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max
                      int nrhs, double flops, hipStream_t st) {
   if (nmerge == 0) return;
   ProfScope ps(PROF_UPWARD, st, flops, 8.0 * flops / (2.0 * nrhs));
-  const int bx = std::min(64, std::max(1, (m3_max + me_max + 3) / 4));
+  const int bx = std::min(64, std::max(1, (m3_max + 3) / 4));
   hipLaunchKernelGGL(k_up_gather_nm, dim3(bx, nmerge), dim3(64, 4), 0, st, d_desc, src, hbase,
-                     ha_off, hb_off, hp_off, z_off, nrhs, rbuf);
+                     ha_off, hb_off, z_off, nrhs, rbuf);
   const int bm = mm_rows(m3_max);
   if (bm == 16)
-    launch_up_mm_bn<16>(d_desc, nmerge, m3_max, me_max, hbase, hp_off, rbuf, zbuf, z_off, nrhs,
-                        st);
+    launch_up_mm_bn<16>(d_desc, nmerge, m3_max, me_max, hbase, ha_off, hb_off, hp_off, rbuf,
+                        zbuf, z_off, nrhs, st);
   else if (bm == 32)
-    launch_up_mm_bn<32>(d_desc, nmerge, m3_max, me_max, hbase, hp_off, rbuf, zbuf, z_off, nrhs,
-                        st);
+    launch_up_mm_bn<32>(d_desc, nmerge, m3_max, me_max, hbase, ha_off, hb_off, hp_off, rbuf,
+                        zbuf, z_off, nrhs, st);
   else
-    launch_up_mm_bn<64>(d_desc, nmerge, m3_max, me_max, hbase, hp_off, rbuf, zbuf, z_off, nrhs,
-                        st);
+    launch_up_mm_bn<64>(d_desc, nmerge, m3_max, me_max, hbase, ha_off, hb_off, hp_off, rbuf,
+                        zbuf, z_off, nrhs, st);
 }
 
 void ops_init() {
