@@ -120,22 +120,17 @@ constexpr int TP_MAXW = 8;  // waves of the panel workgroup (two per SIMD: 256 V
 // best candidate with DPP and its owner lane publishes that row before the
 // barrier; after it every thread picks the workgroup's winner from the
 // published keys and eliminates with the winner's row.  Buffers alternate
-// between columns, so a single barrier per column suffices.
-//
-// The columns run in groups of G: the loop over groups is a runtime loop
-// (the kernel runs once per launch, so a fully unrolled column loop would be
-// fetched cold from memory instruction by instruction), and at the end of a
-// group x rotates left by G, so that column c0 + t of group c0 always sits at
-// register position t.  Position j then holds column (c0 + j) mod KB:
-// positions j >= KB - c0 hold the multipliers of the columns before the
-// group, which the elimination must leave alone (the pivot row is read with
-// those positions masked to zero).
-template <int R, int KB, int G>
+// between columns, so a single barrier per column suffices.  The column loop
+// is unrolled in full, so that every row update covers only the columns
+// still to the right (a compact loop over groups of columns, with the
+// register file rotated between groups, measured slower: it must run every
+// update over the whole panel width).
+template <int R, int KB>
 __global__ void __launch_bounds__(64 * TP_MAXW) k_gj_panel(const SolveDesc* __restrict__ descs,
                                                           int k0, int* status) {
-  static_assert(KB % G == 0 && KB % 2 == 0, "bad panel shape");
   __shared__ unsigned sKey[2][TP_MAXW];
-  __shared__ double2 sRow[2][TP_MAXW][KB / 2];
+  __shared__ double sInvP[2][TP_MAXW];  // 1 / each wave's candidate pivot
+  __shared__ double sRow[2][TP_MAXW][KB];
   __shared__ double sLU[KB][KB + 1];
   __shared__ double sKeep[KB][KB + 1];
   __shared__ int sPi[KB], sD[KB], sV[KB], sNd, sBad, sNs;
@@ -160,79 +155,85 @@ __global__ void __launch_bounds__(64 * TP_MAXW) k_gj_panel(const SolveDesc* __re
   }
   int ns = 0;
   bool stop = false;
-#pragma unroll 1
-  for (int c0 = 0; c0 < kb && !stop; c0 += G) {
-    const int lim = KB - c0;
+  // Step at which each of this lane's rows became a pivot row (-1: not yet).
+  // A pivot row is no longer updated, so at the end its registers hold its
+  // row of L \ U, which is then written out in one go.
+  int sel[R];
 #pragma unroll
-    for (int t = 0; t < G; ++t) {
-      const int c = c0 + t;
-      if (c >= kb || stop) continue;
-      const int buf = c & 1;
-      unsigned key = 0;
+  for (int r = 0; r < R; ++r) sel[r] = -1;
+  // Constant trip count (columns past kb, or past the last candidate, are
+  // skipped uniformly) so the loop unrolls and x stays in registers.
+#pragma unroll
+  for (int c = 0; c < KB; ++c) {
+    if (c >= kb || stop) continue;
+    const int buf = c & 1;
+    unsigned key = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (live[r]) key = max(key, pivot_key(x[r][c], wid * 64 * R + r * 64 + lane));
+    const unsigned wkey = wave_max_u32(key);
+    if (wkey != 0) {
+      const int slot = 4095 - (int)(wkey & 4095u);
+      const int wl = slot & 63, wr = (slot >> 6) % R;
+      double cand = 0.0;
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        if (live[r]) key = max(key, pivot_key(x[r][t], wid * 64 * R + r * 64 + lane));
-      const unsigned wkey = wave_max_u32(key);
-      if (wkey != 0) {
-        const int slot = 4095 - (int)(wkey & 4095u);
-        const int wl = slot & 63, wr = (slot >> 6) % R;
+        if (wr == r) {
+          if (lane == wl) {
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-          if (wr == r && lane == wl) {
-#pragma unroll
-            for (int j = 0; j < KB / 2; ++j) sRow[buf][wid][j] = double2{x[r][2 * j], x[r][2 * j + 1]};
+            for (int c2 = 0; c2 < KB; ++c2)
+              if (c2 >= c) sRow[buf][wid][c2] = x[r][c2];
           }
-      }
-      if (lane == 0) sKey[buf][wid] = wkey;
-      __syncthreads();
-      unsigned g = 0;
-      for (int w = 0; w < nw; ++w) g = max(g, sKey[buf][w]);
-      g = (unsigned)__builtin_amdgcn_readfirstlane((int)g);
-      if (g == 0) {
-        stop = true;
-        continue;
-      }
-      const int gslot = 4095 - (int)(g & 4095u);
-      const int gw = gslot / (64 * R), gr = (gslot >> 6) % R, gl = gslot & 63;
-      const double* prow = reinterpret_cast<const double*>(sRow[buf][gw]);
-      if (wid == gw) {
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-          if (gr == r && lane == gl) live[r] = false;
-      }
-      // The winner's row in natural column order: L part (multipliers of
-      // the earlier columns) and U part.
-      if (threadIdx.x < KB) sLU[ns][(c0 + threadIdx.x) % KB] = prow[threadIdx.x];
-      if (threadIdx.x == 0) sPi[ns] = k0 + gslot;
-      ++ns;
-      const double piv = prow[t];
-      const bool ok = (piv != 0.0) && (piv == piv) && fabs(piv) != INFINITY;
-      if (!ok && threadIdx.x == 0) sBad = 1;
-      const double inv = ok ? 1.0 / piv : 0.0;
-      double pj[KB];
-#pragma unroll
-      for (int j = t + 1; j < KB; ++j) pj[j] = (j < lim) ? prow[j] : 0.0;
+          cand = __shfl(x[r][c], wl);
+        }
+      // The candidate's reciprocal is formed before the barrier, off the
+      // critical path of the elimination that follows it.
+      if (lane == 0) sInvP[buf][wid] = 1.0 / cand;
+    }
+    if (lane == 0) sKey[buf][wid] = wkey;
+    __syncthreads();
+    unsigned g = 0;
+    for (int w = 0; w < nw; ++w) g = max(g, sKey[buf][w]);
+    g = (unsigned)__builtin_amdgcn_readfirstlane((int)g);
+    if (g == 0) {
+      stop = true;
+      continue;
+    }
+    const int gslot = 4095 - (int)(g & 4095u);
+    const int gw = gslot / (64 * R), gr = (gslot >> 6) % R, gl = gslot & 63;
+    const double* prow = sRow[buf][gw];
+    if (wid == gw) {
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        if (live[r]) {
-          const double l = x[r][t] * inv;
-          x[r][t] = l;
-#pragma unroll
-          for (int j = t + 1; j < KB; ++j) x[r][j] = fma(-l, pj[j], x[r][j]);
+        if (gr == r && lane == gl) {
+          live[r] = false;
+          sel[r] = ns;
         }
     }
-    // Rotate left by G: the group's columns (now multipliers) go to the tail.
+    if (threadIdx.x == 0) sPi[ns] = k0 + gslot;
+    ++ns;
+    const double piv = prow[c];
+    const bool ok = (piv != 0.0) && (piv == piv) && fabs(piv) != INFINITY;
+    if (!ok && threadIdx.x == 0) sBad = 1;
+    const double inv = ok ? sInvP[buf][gw] : 0.0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      double tmp[G];
+    for (int r = 0; r < R; ++r)
+      if (live[r]) {
+        const double l = x[r][c] * inv;
+        x[r][c] = l;
+        // Runs over all KB columns (the test folds away once the column loop
+        // is unrolled), so it unrolls and x stays in registers.
 #pragma unroll
-      for (int j = 0; j < G; ++j) tmp[j] = x[r][j];
-#pragma unroll
-      for (int j = 0; j + G < KB; ++j) x[r][j] = x[r][j + G];
-#pragma unroll
-      for (int j = 0; j < G; ++j) x[r][KB - G + j] = tmp[j];
-    }
+        for (int c2 = 0; c2 < KB; ++c2)
+          if (c2 > c) x[r][c2] = fma(-l, prow[c2], x[r][c2]);
+      }
   }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (sel[r] >= 0) {
+#pragma unroll
+      for (int c2 = 0; c2 < KB; ++c2) sLU[sel[r]][c2] = x[r][c2];
+    }
   if (threadIdx.x == 0) sNs = ns;
   __syncthreads();
   if (wid == 0) {
@@ -468,11 +469,11 @@ static void launch_panel(const SolveDesc* d_desc, int np, int k0, int rows, int 
   if (nb == 32) {
     HPS_REQUIRE(rows <= 64 * TP_MAXW * 2, "panel has too many rows");
     const int nw = (rows + 127) / 128;
-    hipLaunchKernelGGL((k_gj_panel<2, 32, 8>), dim3(np), dim3(64 * nw), 0, s, d_desc, k0, st);
+    hipLaunchKernelGGL((k_gj_panel<2, 32>), dim3(np), dim3(64 * nw), 0, s, d_desc, k0, st);
   } else {
     HPS_REQUIRE(rows <= 64 * TP_MAXW * 6, "panel has too many rows");
     const int nw = (rows + 383) / 384;
-    hipLaunchKernelGGL((k_gj_panel<6, 16, 8>), dim3(np), dim3(64 * nw), 0, s, d_desc, k0, st);
+    hipLaunchKernelGGL((k_gj_panel<6, 16>), dim3(np), dim3(64 * nw), 0, s, d_desc, k0, st);
   }
 }
 
