@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(64 * TP_MAXW) k_gj_panel(const SolveDesc* __re
   const SolveDesc d = descs[blockIdx.x];
   if (k0 >= d.n) return;
   const int kb = min(KB, d.n - k0), rows = d.n - k0;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const size_t ld = d.ld;
   double* P = d.W + (size_t)k0 * ld + k0;
   double x[R][KB];
@@ -153,6 +153,10 @@ __global__ void __launch_bounds__(64 * TP_MAXW) k_gj_panel(const SolveDesc* __re
     sBad = 0;
     sNs = 0;
   }
+  // Keys of absent waves read as 0 (no candidate), so that every thread can
+  // read all TP_MAXW keys at once.
+  if (threadIdx.x < 2 * TP_MAXW) sKey[threadIdx.x / TP_MAXW][threadIdx.x % TP_MAXW] = 0;
+  __syncthreads();
   int ns = 0;
   bool stop = false;
   // Step at which each of this lane's rows became a pivot row (-1: not yet).
@@ -193,7 +197,8 @@ __global__ void __launch_bounds__(64 * TP_MAXW) k_gj_panel(const SolveDesc* __re
     if (lane == 0) sKey[buf][wid] = wkey;
     __syncthreads();
     unsigned g = 0;
-    for (int w = 0; w < nw; ++w) g = max(g, sKey[buf][w]);
+#pragma unroll
+    for (int w = 0; w < TP_MAXW; ++w) g = max(g, sKey[buf][w]);
     g = (unsigned)__builtin_amdgcn_readfirstlane((int)g);
     if (g == 0) {
       stop = true;
