@@ -288,6 +288,7 @@ __global__ void __launch_bounds__(16 * TC) k_leaf_gj(const double* const* __rest
   __shared__ double sA[2][NROW];  // the current column, a[., k]
   __shared__ int sP[2];           // its pivot row
   __shared__ int sInv[NROW];      // row -> column whose pivot it is
+  __shared__ double sRowP[TC][NC];  // the pivot row's values, one line per DPP row
 
   const int p = tab.p, n = tab.n, m = tab.m, pi = p - 2, w = n + m;
   const int tid = threadIdx.x, tr = tid % TR, tc = tid / TR;
@@ -375,13 +376,21 @@ __global__ void __launch_bounds__(16 * TC) k_leaf_gj(const double* const* __rest
         const double inv = ok ? 1.0 / piv : 0.0;
         // Row p's values in my columns (lane trp of my DPP row, slot sp),
         // divided by the pivot.
+        // Lane trp of each DPP row stores row p's values of its columns to
+        // the row's LDS line, which the row's lanes read back: all within
+        // one wave, whose LDS operations complete in program order.
+        if (tr == trp) {
+#pragma unroll
+          for (int s = 0; s < NR; ++s)
+            if (s == sp) {
+#pragma unroll
+              for (int t2 = 0; t2 < NC; ++t2) sRowP[tc][t2] = a[s][t2];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
         double prow[NC];
 #pragma unroll
-        for (int s = 0; s < NR; ++s)
-          if (s == sp) {
-#pragma unroll
-            for (int t2 = 0; t2 < NC; ++t2) prow[t2] = __shfl(a[s][t2], rowlane + trp) * inv;
-          }
+        for (int t2 = 0; t2 < NC; ++t2) prow[t2] = sRowP[tc][t2] * inv;
 #pragma unroll
         for (int s = 0; s < NR; ++s) {
           const double lv = sA[buf][TR * s + tr];
