@@ -285,7 +285,12 @@ __global__ void __launch_bounds__(16 * TC) k_leaf_gj(const double* const* __rest
   static_assert(NROW <= 208, "pivot keys hold slots below 208");
   __shared__ double sD[4][24 * 24];
   __shared__ double sc[6][NROW];
-  __shared__ double sA[2][NROW];  // the current column, a[., k]
+  // The current column a[., k], stored by row slot: row tr + 16 s at
+  // sA[buf][tr][s], so that every lane reads its NR values as one
+  // contiguous run (rows padded to an odd count of doubles against bank
+  // conflicts).
+  constexpr int NRP = NR | 1;
+  __shared__ double sA[2][TR][NRP];
   __shared__ int sP[2];           // its pivot row
   __shared__ int sInv[NROW];      // row -> column whose pivot it is
   __shared__ double sRowP[TC][NC];  // the pivot row's values, one line per DPP row
@@ -353,7 +358,7 @@ __global__ void __launch_bounds__(16 * TC) k_leaf_gj(const double* const* __rest
         unsigned key = 0;
 #pragma unroll
         for (int s = 0; s < NR; ++s) {
-          sA[buf][TR * s + tr] = a[s][t];
+          sA[buf][tr][s] = a[s][t];
           if (!((done >> s) & 1u)) key = max(key, leaf_key(a[s][t], TR * s + tr));
         }
         key = row16_max(key);
@@ -367,7 +372,7 @@ __global__ void __launch_bounds__(16 * TC) k_leaf_gj(const double* const* __rest
       const int slot = __builtin_amdgcn_readfirstlane(sP[buf]);
       const int sp = slot / TR, trp = slot % TR;
       if (tr == trp) done |= 1u << sp;
-      const double piv = sA[buf][slot];
+      const double piv = sA[buf][slot % TR][slot / TR];
       const bool ok = (piv != 0.0) && (piv == piv) && fabs(piv) != INFINITY;
       if (!ok && tid == 0)
         if (atomicCAS(status, 0, 1) == 0) status[1] = tag0 - (int)blockIdx.x;
@@ -393,7 +398,7 @@ __global__ void __launch_bounds__(16 * TC) k_leaf_gj(const double* const* __rest
         for (int t2 = 0; t2 < NC; ++t2) prow[t2] = sRowP[tc][t2] * inv;
 #pragma unroll
         for (int s = 0; s < NR; ++s) {
-          const double lv = sA[buf][TR * s + tr];
+          const double lv = sA[buf][tr][s];
 #pragma unroll
           for (int t2 = 0; t2 < NC; ++t2) a[s][t2] = fma(-lv, prow[t2], a[s][t2]);
         }
