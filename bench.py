@@ -34,8 +34,8 @@ ALU_F64_PEAK = 78.6
 # HBM bytes per launch of the dominant kernel on this workload, from two
 # rocprofv3 counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a
 # copy of known size); valid only while the kernel's source is unchanged.
-TRAFFIC = {"leaf_lu": dict(source="paper_1307_2665_amd/csrc/leaf.hip", sha256_16="a78f1106cbb34c9e",
-                           bytes=444.2e6)}
+TRAFFIC = {"leaf_lu": dict(source="paper_1307_2665_amd/csrc/leaf.hip", sha256_16="29ac5aa2d2fa726d",
+                           bytes=430.2e6)}
 
 
 def measured_traffic(cls):
