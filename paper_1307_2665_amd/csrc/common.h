@@ -55,6 +55,14 @@ struct GemmDesc {
   int M, N, K;
   int lda, ldb, ldc, ldc0;
   double alpha;
+  // Merge Schur product (eq:merge): with pmap set, C0 is the parent's
+  // block-diagonal pass-through diag(T11a, T22b), read from the children's
+  // DtNs through the parent-order map pmap (>= 0: row/column of Ta, < 0:
+  // -(row/column of Tb) - 1); C0 and the old C are then not read.
+  const int* pmap = nullptr;
+  const double* Ta = nullptr;
+  const double* Tb = nullptr;
+  int na = 0, nb = 0;
 };
 
 // One tile of a grouped GEMM launch: problem index and tile coordinates.

@@ -361,14 +361,39 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gj_update(const SolveDesc* __r
                                 0, 0, sm);
 }
 
+// The parent's pass-through diag(T11a, T22b) at (r, c) in parent order.
+struct MergePass {
+  static constexpr bool active = true;
+  const int* pmap;
+  const double* Ta;
+  const double* Tb;
+  int na, nb;
+  __device__ double operator()(int r, int c) const {
+    const int pr = pmap[r], pc = pmap[c];
+    if (pr >= 0) return pc >= 0 ? Ta[(size_t)pr * na + pc] : 0.0;
+    return pc < 0 ? Tb[(size_t)(-pr - 1) * nb + (-pc - 1)] : 0.0;
+  }
+};
+
+__device__ inline MergePass merge_pass(const GemmDesc& g) {
+  return MergePass{g.pmap, g.Ta, g.Tb, g.na, g.nb};
+}
+
 // Grouped GEMM: one launch over problems, grid (tiles_n, tiles_m, nprob).
-template <int BM, int BN, int BK, int WM, int WN>
+// PASS: merge Schur products, C = diag(T11a, T22b) + alpha A B (descs with pmap).
+template <int BM, int BN, int BK, int WM, int WN, bool PASS>
 __global__ void __launch_bounds__(64 * WM * WN) k_gemm(const GemmDesc* __restrict__ descs) {
   __shared__ double sm[GemmTile<BM, BN, BK, WM, WN>::SMEM];
   const GemmDesc g = descs[blockIdx.z];
   if ((int)blockIdx.y * BM >= g.M || (int)blockIdx.x * BN >= g.N) return;
-  gemm_tile<BM, BN, BK, WM, WN>(g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.C0, g.ldc0, g.M, g.N, g.K,
-                                g.alpha, blockIdx.y * BM, blockIdx.x * BN, sm);
+  if constexpr (PASS)
+    gemm_tile_map<BM, BN, BK, WM, WN>(g.A, g.lda, g.B, g.ldb, RowsIdentity{}, g.C, g.ldc,
+                                      RowsIdentity{}, nullptr, 0, g.M, g.N, g.K, g.alpha,
+                                      blockIdx.y * BM, blockIdx.x * BN, sm, false, RowsIdentity{},
+                                      merge_pass(g));
+  else
+    gemm_tile<BM, BN, BK, WM, WN>(g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.C0, g.ldc0, g.M, g.N, g.K,
+                                  g.alpha, blockIdx.y * BM, blockIdx.x * BN, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -465,7 +490,8 @@ __global__ void __launch_bounds__(256) k_gemm_split32(const GemmDesc* __restrict
         int gr = row0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
         int gc = col0 + wn * 32 + j * 16 + (lane & 15);
         if (gr < g.M && gc < g.N) {
-          double c0 = g.C0 ? g.C0[(size_t)gr * g.ldc0 + gc] : g.C[(size_t)gr * g.ldc + gc];
+          double c0 = g.pmap ? merge_pass(g)(gr, gc)
+                             : (g.C0 ? g.C0[(size_t)gr * g.ldc0 + gc] : g.C[(size_t)gr * g.ldc + gc]);
           g.C[(size_t)gr * g.ldc + gc] = c0 + g.alpha * acc[i][j][r];
         }
       }
@@ -585,17 +611,29 @@ void grouped_gemm_v(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc,
     by += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + 2.0 * g.M * g.N);
   }
   const unsigned np = (unsigned)h_desc.size();
+  // Every descriptor of a launch is of one kind (merge Schur products or plain).
+  const bool pass = h_desc[0].pmap != nullptr;
+  for (auto& g : h_desc) {
+    HPS_REQUIRE((g.pmap != nullptr) == pass, "mixed GEMM descriptor kinds");
+    HPS_REQUIRE(!pass || (g.Ta != nullptr && g.Tb != nullptr && g.na > 0 && g.nb > 0),
+                "merge Schur product without its children's DtNs");
+  }
   ProfScope ps(split32 ? PROF_GEMM_SPLIT32 : PROF_GEMM, stream, fl, by);
   if (split32) {
     dim3 grid((nmax + TBN - 1) / TBN, (mmax + TBM - 1) / TBM, np);
     hipLaunchKernelGGL(k_gemm_split32, grid, dim3(256), 0, stream, d_desc);
     return;
   }
-#define HPS_GEMM(BM, BN, BK, WM, WN)                                                            \
-  {                                                                                             \
-    hipLaunchKernelGGL((k_gemm<BM, BN, BK, WM, WN>), dim3((nmax + BN - 1) / BN, (mmax + BM - 1) / BM, np), \
-                       dim3(64 * WM * WN), 0, stream, d_desc);                                  \
-    return;                                                                                     \
+#define HPS_GEMM(BM, BN, BK, WM, WN)                                                          \
+  {                                                                                           \
+    const dim3 grid((nmax + BN - 1) / BN, (mmax + BM - 1) / BM, np);                          \
+    if (pass)                                                                                 \
+      hipLaunchKernelGGL((k_gemm<BM, BN, BK, WM, WN, true>), grid, dim3(64 * WM * WN), 0,     \
+                         stream, d_desc);                                                     \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_gemm<BM, BN, BK, WM, WN, false>), grid, dim3(64 * WM * WN), 0,    \
+                         stream, d_desc);                                                     \
+    return;                                                                                   \
   }
   switch (variant) {
     case 1: HPS_GEMM(32, 32, 16, 1, 1)

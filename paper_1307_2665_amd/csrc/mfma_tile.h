@@ -18,6 +18,12 @@ struct RowsIndexed {
   __device__ int operator()(int r) const { return idx[r]; }
 };
 
+// C0 given element by element (active = true), replacing C0 and acc_c.
+struct NoC0Elem {
+  static constexpr bool active = false;
+  __device__ double operator()(int, int) const { return 0.0; }
+};
+
 // ---------------------------------------------------------------------------
 // FP64 MFMA tiles.  A workgroup computes a BM x BN tile of C with WM x WN
 // waves; each wave owns a (BM/WM) x (BN/WN) block made of 16 x 16
@@ -44,14 +50,15 @@ struct GemmTile {
 // B + brow(k) * ldb, C's row r at C + crow(r) * ldc and C0's row r at
 // C0 + c0row(r) * ldc0 (gathered operands, a scattered result; a negative
 // c0row is a zero row; A rows are plain).  With C0 null the old C is added
-// when acc_c is set and nothing otherwise (C is then not read).
+// when acc_c is set and nothing otherwise (C is then not read).  An active
+// c0elem gives C0 element by element instead.
 template <int BM, int BN, int BK, int WM, int WN, class BRow, class CRow,
-          class C0Row = RowsIdentity>
+          class C0Row = RowsIdentity, class C0Elem = NoC0Elem>
 __device__ inline void gemm_tile_map(const double* __restrict__ A, int lda,
                                      const double* B, int ldb, BRow brow, double* C, int ldc,
                                      CRow crow, const double* C0, int ldc0, int M, int N, int K,
                                      double alpha, int row0, int col0, double* sm, bool acc_c,
-                                     C0Row c0row = C0Row{}) {
+                                     C0Row c0row = C0Row{}, C0Elem c0elem = C0Elem{}) {
   using T = GemmTile<BM, BN, BK, WM, WN>;
   double(*As)[BM + 1] = reinterpret_cast<double(*)[BM + 1]>(sm);
   double(*Bs)[BN + 1] = reinterpret_cast<double(*)[BN + 1]>(sm + BK * (BM + 1));
@@ -126,7 +133,9 @@ __device__ inline void gemm_tile_map(const double* __restrict__ A, int lda,
         if (gr < M && gc < N) {
           double* cp = C + (size_t)crow(gr) * ldc + gc;
           double c0 = 0.0;
-          if (C0) {
+          if constexpr (C0Elem::active) {
+            c0 = c0elem(gr, gc);
+          } else if (C0) {
             const int r0 = c0row(gr);
             if (r0 >= 0) c0 = C0[(size_t)r0 * ldc0 + gc];
           } else if (acc_c) {

@@ -73,14 +73,15 @@ void leaf_assemble(const double* const* cptr, const LeafDev& tab, int count, dou
 // ---------------------------------------------------------------------------
 // Merge gather (section 4, eq:premerge blocks): for each merge build
 //   W = [T33a - T33b | -T31a, T32b] (m3 x (m3 + me), columns of B in parent order),
-//   Q = [T13a; T23b] (me x m3, rows in parent order),
-//   Tp = diag(T11a, T22b) in parent order (me x me).
+//   Q = [T13a; T23b] (me x m3, rows in parent order).
+// The parent's diag(T11a, T22b) is not formed: the Schur product reads it
+// from the children's DtNs as it writes T = diag(T11a, T22b) + Q S.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_merge_gather(const MergeDesc* __restrict__ descs) {
   const MergeDesc d = descs[blockIdx.y];
   const int m3 = d.m3, me = d.me, ldw = d.ldw;
-  const size_t nW = (size_t)m3 * ldw, nQ = (size_t)me * m3, nT = (size_t)me * me;
-  const size_t tot = nW + nQ + nT;
+  const size_t nW = (size_t)m3 * ldw, nQ = (size_t)me * m3;
+  const size_t tot = nW + nQ;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
        e += (size_t)gridDim.x * blockDim.x) {
     if (e < nW) {
@@ -96,22 +97,12 @@ __global__ void __launch_bounds__(256) k_merge_gather(const MergeDesc* __restric
         v = (j - m3 - me == i) ? 1.0 : 0.0;  // identity block -> M^-1
       }
       d.W[e] = v;
-    } else if (e < nW + nQ) {
+    } else {
       size_t f = e - nW;
       int r = (int)(f / m3), i = (int)(f % m3);
       int pm = d.pmap[r];
       d.Q[f] = (pm >= 0) ? d.Ta[(size_t)pm * d.na + d.a3[i]]
                          : d.Tb[(size_t)(-pm - 1) * d.nb + d.b3[i]];
-    } else {
-      size_t f = e - nW - nQ;
-      int r = (int)(f / me), c = (int)(f % me);
-      int pr = d.pmap[r], pc = d.pmap[c];
-      double v = 0.0;
-      if (pr >= 0 && pc >= 0)
-        v = d.Ta[(size_t)pr * d.na + pc];
-      else if (pr < 0 && pc < 0)
-        v = d.Tb[(size_t)(-pr - 1) * d.nb + (-pc - 1)];
-      d.Tp[f] = v;
     }
   }
 }

@@ -325,7 +325,8 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
       SolveDesc sd{md.W, md.piv, md.W + r.m3, r.m3, ldw - r.m3, ldw, ldw, b, 0};
       L.hs.push_back(sd);
       if (b != 0 || op->opt.root_dtn) {
-        GemmDesc gd{md.Q, md.S, md.Tp, nullptr, r.me, r.me, r.m3, r.m3, ldw, r.me, 0, 1.0};
+        GemmDesc gd{md.Q, md.S, md.Tp, nullptr, r.me, r.me, r.m3, r.m3, ldw, r.me, 0, 1.0,
+                    md.pmap, md.Ta, md.Tb, md.na, md.nb};
         L.hg.push_back(gd);
       }
       L.ha.push_back(P.box_hoff[B.ca]);
@@ -334,8 +335,7 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
       L.zo.push_back(oz);
       L.m3_max = std::max(L.m3_max, r.m3);
       L.me_max = std::max(L.me_max, r.me);
-      L.gather_max = std::max(L.gather_max, (size_t)r.m3 * (r.m3 + r.me) + (size_t)r.me * r.m3 +
-                                                (size_t)r.me * r.me);
+      L.gather_max = std::max(L.gather_max, (size_t)r.m3 * ldw + (size_t)r.me * r.m3);
       oW += (long long)r.m3 * ldw;
       oQ += (long long)r.me * r.m3;
       oP += r.m3;
@@ -345,8 +345,12 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
     }
   }
   // Children's DtNs: leaves in leafT, inner boxes in the arena of their depth.
-  for (int d = 0; d <= t.depth; ++d)
-    for (MergeDesc& md : op->levels[d].h) {
+  // The Schur products read them too (the parent's pass-through blocks): their
+  // descriptors follow the merges in order, one per merge that forms its T.
+  for (int d = 0; d <= t.depth; ++d) {
+    LevelPlan& L = op->levels[d];
+    size_t gi = 0;
+    for (MergeDesc& md : L.h) {
       const BoxRec& B = t.boxes[md.box];
       auto child_T = [&](int c) -> const double* {
         const BoxRec& C = t.boxes[c];
@@ -355,7 +359,15 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
       };
       md.Ta = child_T(B.ca);
       md.Tb = child_T(B.cb);
+      if (md.box != 0 || op->opt.root_dtn) {
+        HPS_REQUIRE(gi < L.hg.size() && L.hg[gi].C == md.Tp, "Schur descriptor out of step");
+        L.hg[gi].Ta = md.Ta;
+        L.hg[gi].Tb = md.Tb;
+        ++gi;
+      }
     }
+    HPS_REQUIRE(gi == L.hg.size(), "Schur descriptor count mismatch");
+  }
   op->z_units = oz;
   op->flops = flops;
   op->rootT = (t.boxes[0].ca >= 0) ? op->arena[0] : op->leafT;
