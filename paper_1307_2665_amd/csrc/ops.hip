@@ -118,8 +118,9 @@ void merge_gather(const MergeDesc* d_desc, int nmerge, size_t max_elems, hipStre
 // of one level.  u is [nrhs][N].  A workgroup owns rpb rows of one S (the host
 // picks rpb so that a level launches enough workgroups to fill the chip); the
 // gathered boundary values of up to rc right-hand sides sit in LDS.  Each
-// wave streams one row of S at a time (64 consecutive doubles per load) and
-// applies it to four right-hand sides at once, so S is read once per four.
+// wave streams one row of S at a time (64 consecutive doubles per load, 16
+// loads in flight) and applies it to four right-hand sides at once, so S is
+// read once per four.
 // ---------------------------------------------------------------------------
 constexpr int DRHS = 4;
 
@@ -154,8 +155,22 @@ __global__ void __launch_bounds__(256) k_downward(const MergeDesc* __restrict__ 
         double acc[DRHS];
 #pragma unroll
         for (int j = 0; j < DRHS; ++j) acc[j] = 0.0;
-#pragma unroll 4
-        for (int c = lane; c < me; c += 64) {
+        // Sixteen loads of the row in flight per lane before they are used
+        // (the top levels have few rows, so each wave must keep many bytes
+        // in flight to stream S at HBM speed).
+        constexpr int SU = 16;
+        int c = lane;
+        for (; c + (SU - 1) * 64 < me; c += SU * 64) {
+          double sv[SU];
+#pragma unroll
+          for (int q = 0; q < SU; ++q) sv[q] = Srow[c + 64 * q];
+#pragma unroll
+          for (int q = 0; q < SU; ++q)
+#pragma unroll
+            for (int j = 0; j < DRHS; ++j)
+              if (k0 + j < nr) acc[j] += sv[q] * ue[(k0 + j) * me + c + 64 * q];
+        }
+        for (; c < me; c += 64) {
           const double sv = Srow[c];
 #pragma unroll
           for (int j = 0; j < DRHS; ++j)
