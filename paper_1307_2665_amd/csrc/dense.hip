@@ -364,14 +364,14 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gj_update(const SolveDesc* __r
 // The parent's pass-through diag(T11a, T22b) at (r, c) in parent order.
 struct MergePass {
   static constexpr bool active = true;
-  const int* pmap;
-  const double* Ta;
-  const double* Tb;
+  const int* __restrict__ pmap;
+  const double* __restrict__ Ta;
+  const double* __restrict__ Tb;
   int na, nb;
   __device__ double operator()(int r, int c) const {
-    const int pr = pmap[r], pc = pmap[c];
-    if (pr >= 0) return pc >= 0 ? Ta[(size_t)pr * na + pc] : 0.0;
-    return pc < 0 ? Tb[(size_t)(-pr - 1) * nb + (-pc - 1)] : 0.0;
+    const int pr = __ldg(pmap + r), pc = __ldg(pmap + c);
+    if (pr >= 0) return pc >= 0 ? __ldg(Ta + (size_t)pr * na + pc) : 0.0;
+    return pc < 0 ? __ldg(Tb + (size_t)(-pr - 1) * nb + (-pc - 1)) : 0.0;
   }
 };
 
@@ -532,7 +532,7 @@ static void launch_update(int v, const SolveDesc* d_desc, int np, int k0, int nb
   }
   switch (v) {
     case 1: HPS_UPD(32, 32, 16, 1, 1)
-    case 2: HPS_UPD(128, 128, 16, 2, 2)
+    case 2: HPS_UPD(128, 128, 16, 4, 2)
     case 3: HPS_UPD(128, 64, 16, 2, 2)
     case 4: HPS_UPD(64, 128, 16, 2, 2)
     case 5: HPS_UPD(64, 64, 32, 2, 2)
@@ -637,7 +637,7 @@ void grouped_gemm_v(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc,
   }
   switch (variant) {
     case 1: HPS_GEMM(32, 32, 16, 1, 1)
-    case 2: HPS_GEMM(128, 128, 16, 2, 2)
+    case 2: HPS_GEMM(128, 128, 16, 4, 2)
     case 3: HPS_GEMM(128, 64, 16, 2, 2)
     case 4: HPS_GEMM(64, 128, 16, 2, 2)
     case 5: HPS_GEMM(64, 64, 32, 2, 2)

@@ -32,7 +32,7 @@ struct NoC0Elem {
 // B operand B[l/16][l%16], result register r holds D[l/16 + 4r][l%16]
 // (the f32 16x16x4 form instead holds D[4*(l/16) + r][l%16]).
 // Variants (index = tuning value): 0: 64x64x16 on 2x2 waves (the default),
-// 1: 32x32x16 on one wave, 2: 128x128x16 on 2x2 waves, 3: 128x64x16 on 2x2,
+// 1: 32x32x16 on one wave, 2: 128x128x16 on 4x2 waves, 3: 128x64x16 on 2x2,
 // 4: 64x128x16 on 2x2, 5: 64x64x32 on 2x2.
 // ---------------------------------------------------------------------------
 
@@ -74,7 +74,7 @@ __device__ inline void gemm_tile_map(const double* __restrict__ A, int lda,
   // is multiplied out of LDS (one slab of global loads always in flight);
   // tiles whose accumulators leave no room for that load as they go.
   constexpr int EA = (BM * BK) / T::NT, EB = (BK * BN) / T::NT;
-  constexpr bool PF = T::FM * T::FN <= 4;
+  constexpr bool PF = T::FM * T::FN <= 8;
   double ra[EA], rb[EB];
   auto load = [&](int kt) {
 #pragma unroll
