@@ -102,7 +102,7 @@ struct PlanCache {
   std::mutex mu;
   std::map<std::vector<long long>, std::pair<unsigned long long, std::shared_ptr<const P>>> items;
   unsigned long long tick = 0;
-  static constexpr size_t kMax = 16;
+  static constexpr size_t kMax = 64;  // a heterogeneous batch holds one plan per shape
   std::shared_ptr<const P> get(const std::vector<long long>& key,
                                const std::function<std::shared_ptr<P>()>& make) {
     {
