@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--workload", choices=["convdiff", "helmholtz", "batch", "sweep"],
+    ap.add_argument("--workload", choices=["convdiff", "helmholtz", "batch", "sweep", "post"],
                     default="convdiff",
                     help="convdiff: 64x64 p16 (the default line); helmholtz: 128x128 p16, 64 "
                          "right-hand sides, FP64 and split-FP32 + refinement; batch: 32 uneven "
@@ -79,17 +79,21 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        return os.cpu_count() or 1
+
+
 def cpu_baseline(pr, n_leaf_sample: int):
     """Times the CPU oracle: a sample of leaves (scaled to all leaves), then the
     full merge stage and the solve with the sampled leaf DtNs tiled over the
     grid (dense costs do not depend on the values)."""
     import numpy as np
     from oracle import hps
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+    threads = _blas_threads()
     import warnings
     warnings.simplefilter("ignore")
     nx, ny = pr.nleaf
@@ -211,6 +215,8 @@ def other_workload(args, H, hi, np, torch, dev):
                             "nrhs": nrhs, "mode": args.mode},
                     forms=forms)
         return line
+    if args.workload == "post":
+        return post_workload(args, H, hi, np, torch, dev, line)
     if args.workload == "batch":
         probs = hi.batched_problems()
         ins = [_inputs(H, pr, np, torch, dev) for pr in probs]
@@ -291,6 +297,66 @@ def other_workload(args, H, hi, np, torch, dev):
                 config={"workload": "sweep-256x256-p12-q10", "n_tot": _n_tot(fields[0]),
                         "fields": len(fields), "mode": "fp64" if args.mode == "fp64" else "surrogate"},
                 forms=forms)
+    return line
+
+
+def post_workload(args, H, hi, np, torch, dev, line):
+    """Section 5.3 on the convection-diffusion operator (64 x 64 leaves, p = 16, q = 14): the
+    solution on all 4096 leaf Chebyshev grids from the Gauss-node solution, for 1, 16 and 64
+    right-hand sides.  Timed with HIP events around each post-processing launch."""
+    pr = hi.convdiff()
+    nx, ny = pr.nleaf
+    C, _ = _inputs(H, pr, np, torch, dev)
+    op = H.build_solution_operator(C, pr.box, pr.nleaf, pr.p, pr.q, keep_leaf_solution=True)
+    nl, pp = nx * ny, pr.p * pr.p
+    rng = np.random.default_rng(9)
+    runs = {}
+    for nrhs in (1, 16, 64):
+        F = torch.tensor(rng.standard_normal((nrhs, op.n_bdry)), dtype=torch.float64, device=dev)
+        u = op.solve(F)
+        uc = op.postprocess(u)
+        torch.cuda.synchronize()
+        H.prof_enable(["postprocess"])
+        H.prof_reset()
+        for _ in range(args.steps):
+            op.postprocess(u, uc)
+        torch.cuda.synchronize()
+        d = H.prof_query("postprocess")
+        H.prof_enable([])
+        ms = d["ms"] / d["launches"]
+        runs[nrhs] = {"ms": ms, "values_per_s": nrhs * nl * pp / (ms * 1e-3),
+                      "GB_per_s": d["bytes"] / d["launches"] / (ms * 1e-3) / 1e9,
+                      "TFLOP_per_s": d["flops"] / d["launches"] / (ms * 1e-3) / 1e12,
+                      "bytes_per_launch": d["bytes"] / d["launches"]}
+        log(f"postprocess {nrhs} rhs: {ms * 1e3:.1f} us, {runs[nrhs]['GB_per_s']:.0f} GB/s")
+    one = runs[1]
+    roof = dict(bound="hbm", achieved=one["GB_per_s"], peak=PEAK["hbm"], unit="GB/s",
+                frac=one["GB_per_s"] / PEAK["hbm"], traffic=None, kernel="postprocess",
+                launches_per_step=1, avg_launch_ms=one["ms"])
+    line.update(metric="post-processed Chebyshev grid values/s (section 5.3)",
+                unit="grid values/s", value=one["values_per_s"], ms_per_step=one["ms"],
+                dtype="f64", config={"workload": "post-convdiff-64x64-p16-q14", "nrhs": 1,
+                                     "nleaf": [nx, ny], "p": pr.p, "q": pr.q},
+                roofline=roof, by_nrhs=runs)
+    if not args.no_cpu_baseline:
+        # The oracle's post-processing on every leaf of an 8 x 8 operator of the same
+        # p and q (the per-leaf work does not depend on the grid), scaled to 4096 leaves.
+        from oracle import hps
+        sub = hi.convdiff(nleaf=(8, 8))
+        grid = hps.Grid(sub.box, 8, 8, sub.q)
+        op_o = hps.build(sub.coeffs_at(grid.cheb_xy(sub.p)), sub.box, (8, 8), sub.p, sub.q)
+        uo = hps.solve(op_o, sub.bc_at(hps.gamma_xy(op_o)))
+        leaves = [t for t, b in enumerate(op_o.boxes) if b.is_leaf]
+        reps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < 5.0:
+            for t in leaves:
+                hps.leaf_cheb_values(op_o, uo, t)
+            reps += 1
+        per_leaf = (time.perf_counter() - t0) / (reps * len(leaves))
+        line["cpu_baseline"] = {"value": pp / per_leaf, "unit": "grid values/s",
+                                "cores": _blas_threads(), "kind": "oracle",
+                                "sample": f"{reps} passes over the 64 leaves of an 8x8 operator "
+                                          "(same p, q), per-leaf rate"}
     return line
 
 

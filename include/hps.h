@@ -89,6 +89,9 @@ typedef struct {
   const hps_surrogate* surrogate;  /* mode HPS_SURROGATE only */
   int judge_samples;               /* surrogate: number of leaves re-built in FP64 to judge it */
   double judge_tol;                /* surrogate: max rel. leaf-DtN error before fallback */
+  int keep_leaf_solution;          /* keep each leaf's Z = A_ii^-1 A_ie L1 ((p-2)^2 x 4q doubles
+                                      per leaf, stored transposed) for hps_postprocess; not in
+                                      surrogate mode */
 } hps_build_opts;
 
 typedef struct {
@@ -173,6 +176,19 @@ hps_status hps_solve(hps_op* op, const double* f, int nrhs, double* u,
 /* Root DtN apply: v = T^1 f, f [nrhs][n_bdry] -> v [nrhs][n_bdry] (Table 1's T_apply). */
 hps_status hps_root_dtn_apply(const hps_op* op, const double* f, int nrhs, double* v,
                               const hps_solve_opts* opts);
+
+/* Post-processing (section 5.3): the solution on every leaf's p x p Chebyshev
+   grid from u at the Gauss nodes (the output of hps_solve).  Grid-boundary
+   nodes interpolate the leaf's edge values (corner nodes average their two
+   edges); interior nodes apply the leaf solution operator -A_ii^-1 A_ie that
+   the build kept (Remark 3.2).  u [nrhs][N] -> uc [nrhs][nx*ny][p*p], node
+   (a, b) of leaf i + nx*j at uc[r][i + nx*j][a + p*b].  Needs an operator
+   built with keep_leaf_solution (HPS_EINVAL otherwise).  Uses opts->stream
+   and opts->device_ptrs (u and uc both host or both device); the refinement
+   fields are ignored.  Exact only for A u = 0 inside the leaves, which is
+   the problem hps_solve answers. */
+hps_status hps_postprocess(const hps_op* op, const double* u, int nrhs, double* uc,
+                           const hps_solve_opts* opts);
 
 /* ---- iterative-refinement building blocks (device pointers) ------------- */
 
@@ -304,7 +320,9 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
      GEMMs (-1: the default, 16; 0: never);
    "split_min_chunk": in those passes, depths with too few merges to fill
      the GPU split each GEMM contraction into chunks of at least this length
-     (-1: the default, 256; else at least 16), summed in a fixed order.
+     (-1: the default, 256; else at least 16), summed in a fixed order;
+   "post_rows": Chebyshev-grid rows per lane in hps_postprocess (1, 2 or 4;
+     -1: the default, 4 from 16 right-hand sides on, else 2).
    Unknown knobs or values give HPS_EINVAL. */
 hps_status hps_tune_set(const char* knob, int value);
 
@@ -330,10 +348,11 @@ hps_status hps_tune_reset(void);
 /* Kernel classes: 0 leaf assembly, 1 LU panel, 2 row swaps + block-row solve,
    3 LU trailing update, 4 back substitution, 5 FP64 GEMM (Schur products and
    leaf T = P0 - P1 Z), 6 split-FP32 Schur GEMM, 7 merge gather, 8 downward
-   pass, 9 interface residual, 10 upward pass.  Bit c of mask enables class c;
-   every later launch of an enabled class records a start and stop event on
-   its stream together with its algorithmic FLOPs and bytes.  Costs one event
-   pair per launch while enabled. */
+   pass, 9 interface residual, 10 upward pass, 11 fused leaf elimination,
+   12 surrogate training, 13 surrogate inference, 14 post-processing.  Bit c
+   of mask enables class c; every later launch of an enabled class records a
+   start and stop event on its stream together with its algorithmic FLOPs and
+   bytes.  Costs one event pair per launch while enabled. */
 hps_status hps_prof_enable(unsigned mask);
 /* Drops all records (waits for their events first). */
 hps_status hps_prof_reset(void);

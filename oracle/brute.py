@@ -35,8 +35,12 @@ def _side_sign(q):
     return np.concatenate([-np.ones(q), np.ones(q), np.ones(q), -np.ones(q)])
 
 
-def collocation_solve(coeffs, box, nleaf, p, q, f):
-    """Solve the full composite collocation system densely; returns u at all Gauss nodes."""
+def collocation_solve(coeffs, box, nleaf, p, q, f, with_interior=False):
+    """Solve the full composite collocation system densely; returns u at all Gauss nodes.
+
+    With with_interior=True also returns every leaf's interior Chebyshev values,
+    [nx*ny, (p-2)^2] in ascending node order, the unknowns w_i of the same
+    global system (section 5.3 recovers them leaf by leaf)."""
     nx, ny = nleaf
     grid = hps.Grid(box, nx, ny, q)
     gamma = grid.boundary(0, nx, 0, ny)
@@ -85,7 +89,10 @@ def collocation_solve(coeffs, box, nleaf, p, q, f):
                         K[r, col_of[gg]] += sgn[k] * H[k, kk]
     x = np.linalg.solve(K, rhs)
     u = ufix.copy()
-    u[interior] = x[:len(interior)]
+    ni_g = len(interior)
+    u[interior] = x[:ni_g]
+    if with_interior:
+        return u, x[ni_g:].reshape(nleafs, ni)
     return u
 
 

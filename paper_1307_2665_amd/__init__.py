@@ -297,7 +297,7 @@ class Surrogate:
 PROF_CLASSES = {"leaf_assemble": 0, "lu_panel": 1, "swap_trsm": 2, "lu_update": 3,
                 "back_subst": 4, "gemm": 5, "gemm_split32": 6, "merge_gather": 7,
                 "downward": 8, "residual": 9, "upward": 10, "leaf_lu": 11, "mlp_train": 12,
-                "mlp_infer": 13}
+                "mlp_infer": 13, "postprocess": 14}
 
 
 def mem_trim() -> int:
@@ -418,6 +418,24 @@ class Operator:
         check(lib.hps_root_dtn_apply(self._h, _ptr(f), f.shape[0], _ptr(v), C.byref(so)))
         return v
 
+    def postprocess(self, u, uc=None):
+        """Section 5.3: u [nrhs, N] at the Gauss nodes -> uc [nrhs, nx*ny, p*p] on every
+        leaf's Chebyshev grid (operator built with keep_leaf_solution=True)."""
+        u = _f64(u)
+        if u.ndim == 1:
+            u = u.reshape(1, -1)
+        dev = _dev(u)
+        shape = (u.shape[0], self.nx * self.ny, self.p * self.p)
+        if uc is None:
+            if dev:
+                import torch
+                uc = torch.empty(shape, dtype=torch.float64, device=u.device)
+            else:
+                uc = np.empty(shape)
+        so = SolveOpts(_stream(u) if dev else None, int(dev), 0, 0.0, 0)
+        check(lib.hps_postprocess(self._h, _ptr(u), u.shape[0], _ptr(uc), C.byref(so)))
+        return uc
+
     def interface_residual(self, u, r=None):
         import torch
         u = _f64(u)
@@ -463,22 +481,24 @@ class Operator:
 
 
 def _build_opts(mode, stream, device_ptrs, keep_factors, root_dtn, surrogate=None,
-                judge_samples=64, judge_tol=1e-6):
+                judge_samples=64, judge_tol=1e-6, keep_leaf_solution=False):
     return BuildOpts(mode, stream, int(device_ptrs), 1, int(keep_factors), int(root_dtn), 0.0,
                      surrogate.handle if surrogate is not None else None, int(judge_samples),
-                     float(judge_tol))
+                     float(judge_tol), int(keep_leaf_solution))
 
 
 def build_solution_operator(coeffs, box, nleaf, p: int, q: int, mode: int = HPS_FP64,
                             keep_factors: bool = False, root_dtn: bool = True, surrogate=None,
-                            judge_samples: int = 64, judge_tol: float = 1e-6) -> Operator:
-    """Algorithm 1.  coeffs [nx*ny, 6, p*p] (c11, c12, c22, c1, c2, c at Chebyshev nodes)."""
+                            judge_samples: int = 64, judge_tol: float = 1e-6,
+                            keep_leaf_solution: bool = False) -> Operator:
+    """Algorithm 1.  coeffs [nx*ny, 6, p*p] (c11, c12, c22, c1, c2, c at Chebyshev nodes).
+    keep_leaf_solution keeps every leaf's interior solution operator for postprocess()."""
     coeffs = _f64(coeffs)
     dev = _dev(coeffs)
     if surrogate is not None:
         mode = HPS_SURROGATE
     bo = _build_opts(mode, _stream(coeffs) if dev else None, dev, keep_factors, root_dtn,
-                     surrogate, judge_samples, judge_tol)
+                     surrogate, judge_samples, judge_tol, keep_leaf_solution)
     h = C.c_void_p()
     check(lib.hps_build_solution_operator(_ptr(coeffs), (C.c_double * 4)(*box),
                                           (C.c_int * 2)(*nleaf), p, q, C.byref(bo), C.byref(h)))
@@ -486,7 +506,7 @@ def build_solution_operator(coeffs, box, nleaf, p: int, q: int, mode: int = HPS_
 
 
 def build_batch(problems: Sequence[dict], mode: int = HPS_FP64, keep_factors: bool = False,
-                root_dtn: bool = True) -> List[Operator]:
+                root_dtn: bool = True, keep_leaf_solution: bool = False) -> List[Operator]:
     """Heterogeneous batch; problems are dicts with coeffs (device), box, nleaf, p, q."""
     arr = (Problem * len(problems))()
     keep = []
@@ -499,7 +519,8 @@ def build_batch(problems: Sequence[dict], mode: int = HPS_FP64, keep_factors: bo
         arr[i].nleaf = (C.c_int * 2)(*pr["nleaf"])
         arr[i].p = pr["p"]
         arr[i].q = pr["q"]
-    bo = _build_opts(mode, _stream(keep[0]), 1, keep_factors, root_dtn)
+    bo = _build_opts(mode, _stream(keep[0]), 1, keep_factors, root_dtn,
+                     keep_leaf_solution=keep_leaf_solution)
     hs = (C.c_void_p * len(problems))()
     check(lib.hps_build_batch(arr, len(problems), C.byref(bo), hs))
     return [Operator(C.c_void_p(h)) for h in hs]

@@ -20,7 +20,8 @@ class BuildOpts(C.Structure):
     _fields_ = [("mode", C.c_int), ("stream", C.c_void_p), ("device_ptrs", C.c_int),
                 ("keep_leaf_ops", C.c_int), ("keep_factors", C.c_int),
                 ("compute_root_dtn", C.c_int), ("pivot_tol", C.c_double),
-                ("surrogate", C.c_void_p), ("judge_samples", C.c_int), ("judge_tol", C.c_double)]
+                ("surrogate", C.c_void_p), ("judge_samples", C.c_int), ("judge_tol", C.c_double),
+                ("keep_leaf_solution", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -68,6 +69,7 @@ SIGNATURES = {
     "hps_boundary_nodes": [P, P, IP],
     "hps_solve": [P, P, I, P, C.POINTER(SolveOpts), C.POINTER(SolveInfo)],
     "hps_root_dtn_apply": [P, P, I, P, C.POINTER(SolveOpts)],
+    "hps_postprocess": [P, P, I, P, C.POINTER(SolveOpts)],
     "hps_interface_residual": [P, P, I, P, P],
     "hps_solve_with_sources": [P, P, P, I, P, P],
     "hps_build_batch": [C.POINTER(Problem), I, C.POINTER(BuildOpts), C.POINTER(P)],

@@ -44,6 +44,7 @@ hps::BuildOptions to_build_options(const hps_build_opts* o) {
   b.device_ptrs = o->device_ptrs != 0;
   b.keep_leaf = true;
   b.keep_factors = o->keep_factors != 0;
+  b.keep_leaf_solution = o->keep_leaf_solution != 0;
   b.root_dtn = o->compute_root_dtn != 0;
   b.surrogate = const_cast<hps_surrogate*>(o->surrogate);
   b.judge_samples = o->judge_samples > 0 ? o->judge_samples : 64;
@@ -274,6 +275,27 @@ hps_status hps_root_dtn_apply(const hps_op* op, const double* f, int nrhs, doubl
   });
 }
 
+hps_status hps_postprocess(const hps_op* op, const double* u, int nrhs, double* uc,
+                           const hps_solve_opts* opts) {
+  return guard([&] {
+    HPS_REQUIRE(op && u && uc && nrhs >= 1, "bad arguments");
+    hipStream_t s = opts ? (hipStream_t)opts->stream : nullptr;
+    const bool dev = opts && opts->device_ptrs;
+    const size_t nu = (size_t)op->tree().N * nrhs;
+    const size_t nc = (size_t)nrhs * op->nx * op->ny * op->p * op->p;
+    Staged U, V;
+    stage_in(U, u, nu, dev, s);
+    if (dev) {
+      V.d = uc;
+    } else {
+      V.d = (double*)hps::pool_alloc(nc * sizeof(double));
+      V.owned = true;
+    }
+    hps::postprocess_device(op, U.d, nrhs, V.d, s);
+    stage_out(V, uc, nc, dev, s);
+  });
+}
+
 hps_status hps_interface_residual(const hps_op* op, const double* u, int nrhs, double* r,
                                   void* stream) {
   return guard([&] {
@@ -430,6 +452,8 @@ hps_status hps_tune_set(const char* knob, int value) {
     } else if (k == "split_min_chunk") {
       HPS_REQUIRE(value == -1 || value >= 16, "split_min_chunk must be -1 or >= 16");
       hps::set_split_min_chunk(value < 0 ? 256 : value);
+    } else if (k == "post_rows") {
+      hps::set_post_rows(value);
     } else if (k == "gj_variant") {
       HPS_REQUIRE(value >= -1 && value < 4 * hps::GEMM_VARIANTS && (value < 0 || value % 4 < 3),
                   "gj_variant out of range");

@@ -35,6 +35,19 @@ void set_boundary(const double* f, const int* gamma, int nb, double* u, int N, i
 void set_boundary_io(const SolveIO* io, const int* gamma, int nb, int nrhs, hipStream_t s);
 void interface_residual(const double* leafT, const double* u, int N, int nrhs, int nx, int ny,
                         int q, double* vbuf, double* r, hipStream_t s);
+// Section 5.3 post-processing: every leaf's p x p Chebyshev grid values from u
+// at its 4q boundary Gauss nodes.  A leaf's rows are the (p-2)^2 rows of -Z
+// (Z = A_ii^-1 A_ie L1) for the interior nodes, then the 4(p-1) rows of L1
+// (the Gauss-to-Chebyshev edge interpolation) for the grid-boundary nodes;
+// post_node[rho] is the node row rho produces.  Both are given transposed:
+// Zt [nleaf][4q][(p-2)^2], L1t [4q][4(p-1)].  uc is [nrhs][nx*ny][p*p].
+void leaf_postprocess(const double* Zt, const double* L1t, const int* post_node, const double* u,
+                      int N, int nrhs, int nx, int ny, int p, int q, double* uc, hipStream_t s);
+// dst[i][c * rows + r] = src[i][r * lds + c] for r < rows, c < cols, i < count.
+void transpose_rows_batch(const double* const* src, double* const* dst, int count, int rows,
+                          int cols, int lds, hipStream_t s);
+// Rows per lane of the post-processing kernel: 1, 2, 4, or 0/-1 (by count).
+void set_post_rows(int r);
 void upward_level(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, const double* s,
                   int N, double* hbase, const long long* ha_off, const long long* hb_off,
                   const long long* hp_off, double* zbuf, const long long* z_off, int nrhs,

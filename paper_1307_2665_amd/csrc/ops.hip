@@ -328,6 +328,161 @@ void interface_residual(const double* leafT, const double* u, int N, int nrhs, i
 }
 
 // ---------------------------------------------------------------------------
+// Post-processing (section 5.3).  Row list of a leaf: the (p-2)^2 rows of -Z
+// (interior nodes), then the 4(p-1) rows of L1 (grid-boundary nodes);
+// post_node[rho] is the Chebyshev node that row rho produces.  Z and L1 are
+// stored transposed (column-major), so lanes that own consecutive rows read
+// consecutive addresses.  Workgroup (leaf, chunk of 64 R rows, group of
+// right-hand sides): lane l owns rows 64 r + l of the chunk and wave w the q
+// columns that act on side w's Gauss values, kept in registers.  A side's
+// Gauss values are q consecutive entries of u, the same for the whole wave,
+// so they are read as wave-uniform (scalar) loads and every multiply-add takes
+// them as a scalar operand; the four side sums meet in LDS in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int POST_QMAX = 24, POST_ROWS = 64, POST_RG = 48;
+
+// R rows per lane (64 R rows per workgroup): each wave-uniform value of u then
+// feeds R multiply-adds.  RC right-hand sides share one round of side sums.
+template <int Q, int R>
+__global__ void __launch_bounds__(256) k_leaf_post(const double* __restrict__ Zt,
+                                                   const double* __restrict__ L1t,
+                                                   const int* __restrict__ post_node,
+                                                   const double* __restrict__ u, int N, int nrhs,
+                                                   int nx, int ny, int p,
+                                                   double* __restrict__ uc) {
+  constexpr int q = Q, m = 4 * Q, RC = 12 / R, ROWS = POST_ROWS * R;
+  extern __shared__ double sbuf[];  // [min(RC, nrhs)][4][ROWS] side sums
+  const int leaf = blockIdx.x, i = leaf % nx, j = leaf / nx;
+  const int nh = nx * (ny + 1), pp = p * p, n = (p - 2) * (p - 2);
+  const int lane = threadIdx.x & 63;
+  const int side = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const size_t nl = (size_t)nx * ny;
+
+  // Column c of the leaf's Z^T (and of L1^T) is contiguous over rows, so
+  // every load below reads 64 consecutive doubles across the wave.
+  const int ne = pp - n;
+  double z[R][Q];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int row = blockIdx.y * ROWS + r * POST_ROWS + lane;
+    if (row < n) {
+      const double* src = Zt + (size_t)leaf * n * m + (size_t)side * q * n + row;
+#pragma unroll
+      for (int c = 0; c < Q; ++c) z[r][c] = -src[(size_t)c * n];
+    } else if (row < pp) {
+      const double* src = L1t + (size_t)side * q * ne + (row - n);
+#pragma unroll
+      for (int c = 0; c < Q; ++c) z[r][c] = src[c * ne];
+    } else {
+#pragma unroll
+      for (int c = 0; c < Q; ++c) z[r][c] = 0.0;
+    }
+  }
+
+  const int base = __builtin_amdgcn_readfirstlane(leaf_bdry_id(i, j, nx, nh, q, side * q));
+  const int g0 = blockIdx.z * POST_RG, g1 = min(g0 + POST_RG, nrhs);
+  for (int rb = g0; rb < g1; rb += RC) {
+    const int nr = min(RC, g1 - rb);
+    for (int k = 0; k < nr; ++k) {
+      const double* us = u + (size_t)(rb + k) * N + base;
+      double acc[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] = 0.0;
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        const double uv = us[c];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = fma(z[r][c], uv, acc[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) sbuf[(k * 4 + side) * ROWS + r * POST_ROWS + lane] = acc[r];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * ROWS; e += 256) {
+      const int k = e / ROWS, l = e % ROWS, row = blockIdx.y * ROWS + l;
+      if (row < pp) {
+        const double* ps = sbuf + k * 4 * ROWS + l;
+        uc[((size_t)(rb + k) * nl + leaf) * pp + post_node[row]] =
+            ((ps[0] + ps[ROWS]) + ps[2 * ROWS]) + ps[3 * ROWS];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+static int g_post_rows = 0;  // rows per lane: 0 = by right-hand-side count (2, or 4 from 16 on)
+void set_post_rows(int r) {
+  HPS_REQUIRE(r == -1 || r == 0 || r == 1 || r == 2 || r == 4, "post_rows must be 1, 2 or 4");
+  g_post_rows = r < 0 ? 0 : r;
+}
+
+template <int R>
+static void launch_post(const double* Zt, const double* L1t, const int* post_node, const double* u,
+                        int N, int nrhs, int nx, int ny, int p, int q, double* uc, hipStream_t s) {
+  const int rows = POST_ROWS * R, rc = 12 / R;
+  const dim3 grid(nx * ny, (p * p + rows - 1) / rows, (nrhs + POST_RG - 1) / POST_RG);
+  const size_t lds = sizeof(double) * std::min(rc, nrhs) * 4 * rows;
+  switch (q) {
+#define HPS_POST(QQ)                                                                            \
+  case QQ:                                                                                      \
+    hipLaunchKernelGGL((k_leaf_post<QQ, R>), grid, dim3(256), lds, s, Zt, L1t, post_node, u, N, \
+                       nrhs, nx, ny, p, uc);                                                    \
+    break;
+    HPS_POST(1) HPS_POST(2) HPS_POST(3) HPS_POST(4) HPS_POST(5) HPS_POST(6) HPS_POST(7)
+    HPS_POST(8) HPS_POST(9) HPS_POST(10) HPS_POST(11) HPS_POST(12) HPS_POST(13) HPS_POST(14)
+    HPS_POST(15) HPS_POST(16) HPS_POST(17) HPS_POST(18) HPS_POST(19) HPS_POST(20) HPS_POST(21)
+    HPS_POST(22) HPS_POST(23) HPS_POST(24)
+#undef HPS_POST
+    default:
+      HPS_REQUIRE(false, "q too large for the post-processing kernel");
+  }
+}
+
+void leaf_postprocess(const double* Zt, const double* L1t, const int* post_node, const double* u,
+                      int N, int nrhs, int nx, int ny, int p, int q, double* uc, hipStream_t s) {
+  HPS_REQUIRE(q >= 1 && q <= POST_QMAX, "q out of range for the post-processing kernel");
+  HPS_REQUIRE(nrhs >= 1 && (nrhs + POST_RG - 1) / POST_RG <= 65535, "bad right-hand-side count");
+  const double nl = (double)nx * ny, n = (double)(p - 2) * (p - 2), m = 4.0 * q;
+  ProfScope ps(PROF_POSTPROCESS, s, 2.0 * nrhs * nl * p * p * m,
+               8.0 * (nl * n * m + nrhs * nl * (m + (double)p * p)));
+  const int R = g_post_rows ? g_post_rows : (nrhs >= 16 ? 4 : 2);
+  if (R == 4)
+    launch_post<4>(Zt, L1t, post_node, u, N, nrhs, nx, ny, p, q, uc, s);
+  else if (R == 2)
+    launch_post<2>(Zt, L1t, post_node, u, N, nrhs, nx, ny, p, q, uc, s);
+  else
+    launch_post<1>(Zt, L1t, post_node, u, N, nrhs, nx, ny, p, q, uc, s);
+}
+
+// Batched transpose through LDS, 64 source rows per workgroup: loads run along
+// a source row, stores along a destination row.
+__global__ void __launch_bounds__(256) k_transpose_rows(const double* const* src,
+                                                        double* const* dst, int rows, int cols,
+                                                        int lds) {
+  extern __shared__ double tile[];  // [64][cols + 1]
+  const double* a = src[blockIdx.x];
+  double* b = dst[blockIdx.x];
+  const int r0 = blockIdx.y * 64, nr = min(64, rows - r0);
+  for (int e = threadIdx.x; e < nr * cols; e += 256) {
+    const int rl = e / cols, c = e - rl * cols;
+    tile[rl * (cols + 1) + c] = a[(size_t)(r0 + rl) * lds + c];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nr * cols; e += 256) {
+    const int c = e / nr, rl = e - c * nr;
+    b[(size_t)c * rows + r0 + rl] = tile[rl * (cols + 1) + c];
+  }
+}
+
+void transpose_rows_batch(const double* const* src, double* const* dst, int count, int rows,
+                          int cols, int lds, hipStream_t s) {
+  if (count <= 0 || rows <= 0) return;
+  HPS_REQUIRE(count <= 0x7fffffff && (rows + 63) / 64 <= 65535, "transpose too large");
+  hipLaunchKernelGGL(k_transpose_rows, dim3(count, (rows + 63) / 64), dim3(256),
+                     sizeof(double) * 64 * (cols + 1), s, src, dst, rows, cols, lds);
+}
+
+// ---------------------------------------------------------------------------
 // Upward source pass for one level (derived from the third block row of
 // eq:premerge with a source):  z = M^-1 (s3 - h3a + h3b),
 // h_parent = [h1a ; h2b] (parent order) + Q z.  M^-1 is the explicit inverse

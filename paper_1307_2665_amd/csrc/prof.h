@@ -22,6 +22,7 @@ enum ProfClass {
   PROF_LEAF_LU = 11,
   PROF_MLP_TRAIN = 12,
   PROF_MLP_INFER = 13,
+  PROF_POSTPROCESS = 14,
   PROF_NCLASS = 16
 };
 

@@ -154,6 +154,14 @@ std::shared_ptr<const LeafPlan> leaf_plan(int p, int q, double hx, double hy, hi
     lp->dG = lp->mem.upload(lt.G, s);
     lp->dP0 = lp->mem.upload(lt.P0, s);
     lp->dP1 = lp->mem.upload(lt.P1, s);
+    const int ne = (int)lt.Je.size(), m = 4 * q;
+    std::vector<double> L1t((size_t)m * ne);
+    for (int r = 0; r < ne; ++r)
+      for (int c = 0; c < m; ++c) L1t[(size_t)c * ne + r] = lt.L1[(size_t)r * m + c];
+    lp->dL1t = lp->mem.upload(L1t, s);
+    std::vector<int> post_node(lt.Ji);
+    post_node.insert(post_node.end(), lt.Je.begin(), lt.Je.end());
+    lp->dPostNode = lp->mem.upload(post_node, s);
     HPS_HIP(hipStreamSynchronize(s));  // the tables are read from other streams later
     return lp;
   });
@@ -262,6 +270,11 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
     op->coeffs = d;
   }
   op->leafT = op->mem.alloc<double>(nl * m * m);
+  if (o.keep_leaf_solution) {
+    HPS_REQUIRE(o.mode != HPS_SURROGATE,
+                "keep_leaf_solution needs the FP64 leaf build (not surrogate mode)");
+    op->leafZ = op->mem.alloc<double>(nl * (size_t)(p - 2) * (p - 2) * m);
+  }
 
   // W (augmented system, later S and M^-1) and pivots are kept for every merge;
   // Q is kept only when the upward pass is wanted, else one level of scratch.
@@ -419,6 +432,7 @@ struct LeafJob {
   int leaf;             // leaf index (error reporting)
   const double* coef;   // [6][p*p]
   double* dst;          // [4q][4q]
+  double* zdst = nullptr;  // [4q][(p-2)^2]: keeps Z^T, Z = A_ii^-1 A_ie L1, when not null
 };
 
 static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hipStream_t s,
@@ -438,6 +452,10 @@ static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hip
   const double** dcp = tmp.alloc<const double*>(CH);
   SolveDesc* dsd = fused ? nullptr : tmp.alloc<SolveDesc>(CH);
   GemmDesc* dgd = tmp.alloc<GemmDesc>(CH);
+  bool keepZ = false;
+  for (const LeafJob& j : jobs) keepZ = keepZ || j.zdst;
+  const double** dzs = keepZ ? tmp.alloc<const double*>(CH) : nullptr;
+  double** dzd = keepZ ? tmp.alloc<double*>(CH) : nullptr;
   for (int c0 = 0; c0 < total; c0 += CH) {
     const int cnt = std::min(CH, total - c0);
     std::vector<const double*> cp(cnt);
@@ -465,6 +483,21 @@ static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hip
       batched_solve(dsd, sd, dstatus, s, panel);
     }
     grouped_gemm(dgd, gd, s, false);
+    // Kept Z goes out transposed ([4q][(p-2)^2]) for the post-processing loads.
+    std::vector<const double*> zs;  // live until the chunk's synchronization below
+    std::vector<double*> zd;
+    if (keepZ) {
+      for (int i = 0; i < cnt; ++i)
+        if (jobs[c0 + i].zdst) {
+          zs.push_back(fused ? Wslab + (size_t)i * n * m : Wslab + (size_t)i * n * ld + n);
+          zd.push_back(jobs[c0 + i].zdst);
+        }
+      if (!zs.empty()) {
+        HPS_HIP(hipMemcpyAsync(dzs, zs.data(), zs.size() * sizeof(void*), hipMemcpyHostToDevice, s));
+        HPS_HIP(hipMemcpyAsync(dzd, zd.data(), zd.size() * sizeof(void*), hipMemcpyHostToDevice, s));
+        transpose_rows_batch(dzs, dzd, (int)zs.size(), n, m, fused ? m : ld, s);
+      }
+    }
     HPS_HIP(hipStreamSynchronize(s));  // host descriptor vectors are reused next chunk
   }
 }
@@ -571,7 +604,8 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
     const int m = 4 * op->q;
     for (int l = 0; l < op->nx * op->ny; ++l)
       v.push_back(LeafJob{&op->leaf(), l, op->coeffs + (size_t)l * 6 * op->p * op->p,
-                          op->leafT + (size_t)l * m * m});
+                          op->leafT + (size_t)l * m * m,
+                          op->leafZ ? op->leafZ + (size_t)l * op->leaf().lt.n * m : nullptr});
   }
   for (auto& kv : groups) run_leaf_group(kv.second, tmp, s, dstatus, panel);
 
@@ -1072,6 +1106,14 @@ void refine_device(hps_op* op, const double* f, int nrhs, double* u, double tol,
 void root_apply_device(const hps_op* op, const double* f, int nrhs, double* v, hipStream_t s) {
   HPS_REQUIRE(op->opt.root_dtn, "operator was built without the root DtN");
   matvec(op->rootT, op->n_bdry, op->n_bdry, f, nrhs, v, s);
+}
+
+// Section 5.3 with the leaf solution operators kept by the build (Remark 3.2).
+void postprocess_device(const hps_op* op, const double* u, int nrhs, double* uc, hipStream_t s) {
+  HPS_REQUIRE(op->leafZ, "operator was built without keep_leaf_solution");
+  const LeafPlan& L = op->leaf();
+  leaf_postprocess(op->leafZ, L.dL1t, L.dPostNode, u, op->tree().N, nrhs, op->nx, op->ny, op->p,
+                   op->q, uc, s);
 }
 
 }  // namespace hps

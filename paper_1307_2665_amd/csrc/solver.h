@@ -54,6 +54,11 @@ struct LeafPlan {
   DeviceMem mem;
   double *dDx = nullptr, *dDy = nullptr, *dDxx = nullptr, *dDyy = nullptr, *dG = nullptr,
          *dP0 = nullptr, *dP1 = nullptr;
+  // Post-processing (section 5.3): L1 transposed (4q x 4(p-1)) and the
+  // Chebyshev node of each post-processing row (interior nodes J_i, then
+  // boundary nodes J_e).
+  double* dL1t = nullptr;
+  int* dPostNode = nullptr;
 };
 std::shared_ptr<const LeafPlan> leaf_plan(int p, int q, double hx, double hy, hipStream_t s);
 
@@ -92,6 +97,7 @@ struct BuildOptions {
   bool device_ptrs = false;
   bool keep_leaf = true;
   bool keep_factors = false;
+  bool keep_leaf_solution = false;
   bool root_dtn = true;
   int panel = 32;
 };
@@ -107,6 +113,7 @@ struct hps_op {
   hps::BuildOptions opt;
   const double* coeffs = nullptr;   // device coefficients used by the build
   double* leafT = nullptr;          // [nleaf][4q][4q]
+  double* leafZ = nullptr;          // [nleaf][4q][(p-2)^2]: Z^T, Z = A_ii^-1 A_ie L1, or null
   double* Wk = nullptr;             // augmented systems; S (and M^-1) live inside them
   double* Q = nullptr;
   int* piv = nullptr;
@@ -164,6 +171,8 @@ void residual_device(const hps_op* op, const double* u, int nrhs, double* r, hip
 void solve_with_sources_device(hps_op* op, const double* f, const double* src, int nrhs, double* u,
                                hipStream_t s);
 void root_apply_device(const hps_op* op, const double* f, int nrhs, double* v, hipStream_t s);
+// Section 5.3: u at every leaf's Chebyshev nodes, uc [nrhs][nleaf][p*p].
+void postprocess_device(const hps_op* op, const double* u, int nrhs, double* uc, hipStream_t s);
 double absmax_device(const double* x, size_t n, hipStream_t s);
 // Plain solves through captured graphs (default on); off = launch by launch.
 void set_solve_graph(bool on);

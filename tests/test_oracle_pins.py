@@ -274,3 +274,38 @@ def test_refinement_fixes_a_perturbed_solution():
     bad[:, inner] += 1e-3 * rng.standard_normal(len(inner))
     fixed = bad + hps.refine_step(op, bad)
     assert np.max(np.abs(fixed - u)) < 1e-11
+
+
+# ---- section 5.3: post-processing on the leaf Chebyshev grids ----------------
+
+def test_postprocess_interior_equals_global_collocation():
+    """Interior grid values recovered leaf by leaf equal the interior unknowns
+    of the one global collocation system (brute force)."""
+    pr = hi.manufactured_variable(p=10, q=8, seed=5)
+    pr.bc = [hi.field_from_seed(78)]
+    nleaf = (3, 2)
+    op, C, grid = _problem_ops(pr, nleaf)
+    f = pr.bc_at(hps.gamma_xy(op))
+    u = hps.solve(op, f)[0]
+    ub, wb = brute.collocation_solve(C, pr.box, nleaf, pr.p, pr.q, f[0], with_interior=True)
+    ji = hps.leaf_matrices(pr.p, pr.q, grid.hx, grid.hy)["Ji"]
+    for j in range(nleaf[1]):
+        for i in range(nleaf[0]):
+            w = hps.leaf_cheb_values(op, u, hps.find_leaf(op, i, j))[0]
+            ref = wb[i + nleaf[0] * j]
+            assert np.max(np.abs(w[ji] - ref)) < 1e-11 * np.max(np.abs(ref))
+
+
+def test_postprocess_reproduces_manufactured_cubic():
+    """All six coefficients active: every leaf's Chebyshev grid (boundary,
+    corners and interior) carries the exact cubic solution."""
+    pr = hi.manufactured_variable(p=12, q=10)
+    nleaf = (4, 2)
+    op, _, grid = _problem_ops(pr, nleaf)
+    u = hps.solve(op, pr.bc_at(hps.gamma_xy(op)))[0]
+    xy = grid.cheb_xy(pr.p)
+    for j in range(nleaf[1]):
+        for i in range(nleaf[0]):
+            w = hps.leaf_cheb_values(op, u, hps.find_leaf(op, i, j))[0]
+            ex = pr.exact(*xy[i + nleaf[0] * j].T)
+            assert np.max(np.abs(w - ex)) < 1e-11 * np.max(np.abs(ex))
