@@ -303,7 +303,8 @@ def other_workload(args, H, hi, np, torch, dev):
 def post_workload(args, H, hi, np, torch, dev, line):
     """Section 5.3 on the convection-diffusion operator (64 x 64 leaves, p = 16, q = 14): the
     solution on all 4096 leaf Chebyshev grids from the Gauss-node solution, for 1, 16 and 64
-    right-hand sides.  Timed with HIP events around each post-processing launch."""
+    right-hand sides, timed with HIP events around each post-processing launch; then the root DtN
+    apply at one right-hand side."""
     pr = hi.convdiff()
     nx, ny = pr.nleaf
     C, _ = _inputs(H, pr, np, torch, dev)
@@ -329,6 +330,21 @@ def post_workload(args, H, hi, np, torch, dev, line):
                       "TFLOP_per_s": d["flops"] / d["launches"] / (ms * 1e-3) / 1e12,
                       "bytes_per_launch": d["bytes"] / d["launches"]}
         log(f"postprocess {nrhs} rhs: {ms * 1e3:.1f} us, {runs[nrhs]['GB_per_s']:.0f} GB/s")
+    # Root DtN apply (Table 1's T_apply): v = T^1 f at one right-hand side, events on the
+    # tensor's stream, which is the stream the library launches on.
+    f1 = torch.tensor(rng.standard_normal((1, op.n_bdry)), dtype=torch.float64, device=dev)
+    v = op.root_dtn_apply(f1)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        op.root_dtn_apply(f1, v)
+        b.record()
+    torch.cuda.synchronize()
+    t_apply = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    nb = op.n_bdry
+    log(f"root DtN apply ({nb} x {nb}): {t_apply * 1e3:.1f} us")
     one = runs[1]
     roof = dict(bound="hbm", achieved=one["GB_per_s"], peak=PEAK["hbm"], unit="GB/s",
                 frac=one["GB_per_s"] / PEAK["hbm"], traffic=None, kernel="postprocess",
@@ -337,7 +353,9 @@ def post_workload(args, H, hi, np, torch, dev, line):
                 unit="grid values/s", value=one["values_per_s"], ms_per_step=one["ms"],
                 dtype="f64", config={"workload": "post-convdiff-64x64-p16-q14", "nrhs": 1,
                                      "nleaf": [nx, ny], "p": pr.p, "q": pr.q},
-                roofline=roof, by_nrhs=runs)
+                roofline=roof, by_nrhs=runs,
+                root_dtn_apply={"ms": t_apply, "n_bdry": nb,
+                                "GB_per_s": 8.0 * nb * (nb + 2) / (t_apply * 1e-3) / 1e9})
     if not args.no_cpu_baseline:
         # The oracle's post-processing on every leaf of an 8 x 8 operator of the same
         # p and q (the per-leaf work does not depend on the grid), scaled to 4096 leaves.

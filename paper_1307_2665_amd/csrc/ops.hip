@@ -114,77 +114,116 @@ void merge_gather(const MergeDesc* d_desc, int nmerge, size_t max_elems, hipStre
 }
 
 // ---------------------------------------------------------------------------
-// Downward pass (Algorithm 2, line 3): u(I_i) = S u(I_e) (+ z) for every merge
-// of one level.  u is [nrhs][N].  A workgroup owns rpb rows of one S (the host
-// picks rpb so that a level launches enough workgroups to fill the chip); the
-// gathered boundary values of up to rc right-hand sides sit in LDS.  Each
-// wave streams one row of S at a time (64 consecutive doubles per load, 16
-// loads in flight) and applies it to four right-hand sides at once, so S is
-// read once per four.
+// Downward pass (Algorithm 2): u(I_i) = S u(I_e) (+ z) for every merge of one
+// level, u [nrhs][N].  Every wave first issues the loads of all the S entries
+// it will use (16 per lane at most), then gathers the matching entries of u
+// (lane l of a wave always owns columns l, l + 64, ... of its rows, so it
+// needs u at those columns only), so one level costs about two memory
+// latencies instead of one per row.  Two shapes:
+//  - whole rows (box boundary me <= 1024): wave w of a workgroup owns RPW
+//    consecutive rows, L = ceil(me/64) loads per lane and row;
+//  - split rows (me > 1024): the four waves of a workgroup take a quarter of
+//    one row each, in pieces of 1024 columns, and add their four sums in a
+//    fixed order through LDS.
+// Up to DRHS right-hand sides share each pass over the loaded rows.
 // ---------------------------------------------------------------------------
-constexpr int DRHS = 4;
+constexpr int DRHS = 4, DSU = 16;
 
+template <int L, bool SPLIT>
 __global__ void __launch_bounds__(256) k_downward(const MergeDesc* __restrict__ descs,
                                                   const SolveIO* __restrict__ io,
-                                                  const SolveIO io0, int io_shared, int rc,
-                                                  int rpb, const double* __restrict__ zbase,
+                                                  const SolveIO io0, int io_shared,
+                                                  const double* __restrict__ zbase,
                                                   const long long* __restrict__ zoff) {
-  extern __shared__ double ue[];
+  constexpr int RPW = SPLIT ? 1 : (DSU / L < 4 ? DSU / L : 4);
+  __shared__ double part[4][DRHS];
   const MergeDesc d = descs[blockIdx.y];
-  const int r0 = blockIdx.x * rpb;
-  if (r0 >= d.m3) return;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int rbase = SPLIT ? blockIdx.x : (blockIdx.x * 4 + wid) * RPW;
+  if (SPLIT ? rbase >= d.m3 : blockIdx.x * 4 * RPW >= d.m3) return;  // whole workgroup
   const SolveIO b = io ? io[io_shared ? 0 : blockIdx.y] : io0;
   double* u = b.u;
-  const int N = b.N, nrhs = b.nrhs, me = d.me;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  // Interface terms of the upward pass: z of this merge is [nrhs][m3].
+  const int N = b.N, nrhs = b.nrhs, me = d.me, m3 = d.m3;
   const double* z = zbase ? zbase + zoff[blockIdx.y] * nrhs : nullptr;
-  for (int rb = 0; rb < nrhs; rb += rc) {
-    const int nr = min(rc, nrhs - rb);
-    __syncthreads();
-    for (int e = threadIdx.x; e < nr * me; e += blockDim.x) {
-      const int k = e / me, c = e % me;
-      ue[e] = u[(size_t)(rb + k) * N + d.Ie[c]];
+  // Columns of this wave: [c0, c1).
+  const int seg = SPLIT ? ((me + 255) / 256) * 64 : me;
+  const int c0 = SPLIT ? wid * seg : 0, c1 = SPLIT ? min(me, c0 + seg) : me;
+
+  for (int rb = 0; rb < nrhs; rb += DRHS) {
+    const int nr = min(DRHS, nrhs - rb);
+    double acc[RPW][DRHS];
+#pragma unroll
+    for (int g = 0; g < RPW; ++g)
+#pragma unroll
+      for (int j = 0; j < DRHS; ++j) acc[g][j] = 0.0;
+    for (int cb = c0; cb < c1; cb += 64 * L) {
+      double sv[RPW][L];
+#pragma unroll
+      for (int g = 0; g < RPW; ++g) {
+        const int r = rbase + g;
+        const double* Srow = d.S + (size_t)r * d.ldw;
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+          const int c = cb + lane + 64 * l;
+          sv[g][l] = (r < m3 && c < c1) ? Srow[c] : 0.0;
+        }
+      }
+      int ie[L];
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        const int c = cb + lane + 64 * l;
+        ie[l] = c < c1 ? d.Ie[c] : -1;
+      }
+#pragma unroll
+      for (int j = 0; j < DRHS; ++j) {
+        if (j < nr) {
+          double uv[L];
+#pragma unroll
+          for (int l = 0; l < L; ++l) uv[l] = ie[l] >= 0 ? u[(size_t)(rb + j) * N + ie[l]] : 0.0;
+#pragma unroll
+          for (int g = 0; g < RPW; ++g)
+#pragma unroll
+            for (int l = 0; l < L; ++l) acc[g][j] = fma(sv[g][l], uv[l], acc[g][j]);
+        }
+      }
     }
-    __syncthreads();
-    for (int rr = wid; rr < rpb; rr += 4) {
-      const int r = r0 + rr;
-      if (r >= d.m3) break;
-      const double* Srow = d.S + (size_t)r * d.ldw;
-      for (int k0 = 0; k0 < nr; k0 += DRHS) {
-        double acc[DRHS];
 #pragma unroll
-        for (int j = 0; j < DRHS; ++j) acc[j] = 0.0;
-        // Sixteen loads of the row in flight per lane before they are used
-        // (the top levels have few rows, so each wave must keep many bytes
-        // in flight to stream S at HBM speed).
-        constexpr int SU = 16;
-        int c = lane;
-        for (; c + (SU - 1) * 64 < me; c += SU * 64) {
-          double sv[SU];
+    for (int g = 0; g < RPW; ++g)
 #pragma unroll
-          for (int q = 0; q < SU; ++q) sv[q] = Srow[c + 64 * q];
-#pragma unroll
-          for (int q = 0; q < SU; ++q)
-#pragma unroll
-            for (int j = 0; j < DRHS; ++j)
-              if (k0 + j < nr) acc[j] += sv[q] * ue[(k0 + j) * me + c + 64 * q];
-        }
-        for (; c < me; c += 64) {
-          const double sv = Srow[c];
-#pragma unroll
-          for (int j = 0; j < DRHS; ++j)
-            if (k0 + j < nr) acc[j] += sv * ue[(k0 + j) * me + c];
-        }
-#pragma unroll
-        for (int j = 0; j < DRHS; ++j) {
-          double v = acc[j];
+      for (int j = 0; j < DRHS; ++j) {
+        if (j < nr) {
+          double v = acc[g][j];
 #pragma unroll
           for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-          if (lane == 0 && k0 + j < nr) {
-            const int k = rb + k0 + j;
-            if (z) v += z[(size_t)k * d.m3 + r];
-            u[(size_t)k * N + d.Ii[r]] = v;
+          acc[g][j] = v;
+        }
+      }
+    if (SPLIT) {
+      if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < DRHS; ++j) part[wid][j] = acc[0][j];
+      }
+      __syncthreads();
+      if (threadIdx.x < nr) {
+        const int j = threadIdx.x, k = rb + j, r = rbase;
+        double v = ((part[0][j] + part[1][j]) + part[2][j]) + part[3][j];
+        if (z) v += z[(size_t)k * m3 + r];
+        u[(size_t)k * N + d.Ii[r]] = v;
+      }
+      __syncthreads();
+    } else if (lane == 0) {
+#pragma unroll
+      for (int g = 0; g < RPW; ++g) {
+        const int r = rbase + g;
+        if (r < m3) {
+#pragma unroll
+          for (int j = 0; j < DRHS; ++j) {
+            if (j < nr) {
+              const int k = rb + j;
+              double v = acc[g][j];
+              if (z) v += z[(size_t)k * m3 + r];
+              u[(size_t)k * N + d.Ii[r]] = v;
+            }
           }
         }
       }
@@ -192,26 +231,37 @@ __global__ void __launch_bounds__(256) k_downward(const MergeDesc* __restrict__ 
   }
 }
 
-int downward_rhs_chunk(int me_max, int nrhs) {
-  int rc = std::max(1, 8192 / std::max(1, me_max));
-  return std::min(rc, std::max(1, nrhs));
+template <int L>
+static void launch_down_rows(dim3 grid, hipStream_t s, const MergeDesc* d_desc,
+                             const SolveIO* d_io, const SolveIO& io0, bool io_shared,
+                             const double* zbase, const long long* zoff) {
+  hipLaunchKernelGGL((k_downward<L, false>), grid, dim3(256), 0, s, d_desc, d_io, io0,
+                     io_shared ? 1 : 0, zbase, zoff);
 }
 
 void downward(const MergeDesc* d_desc, const SolveIO* d_io, const SolveIO& io0, int nmerge,
               int m3_max, int me_max, int nrhs_max, const double* zbase, const long long* zoff,
               hipStream_t s, double s_bytes, bool io_shared) {
-  HPS_REQUIRE((size_t)me_max * sizeof(double) <= 96 * 1024,
-              "downward pass: box boundary too long for the LDS-staged kernel");
-  const int rc = downward_rhs_chunk(me_max, nrhs_max);
-  size_t shm = (size_t)rc * me_max * sizeof(double);
-  // Rows per workgroup: 4 to 16, fewer when the level is small, so that a
-  // level has about 2048 workgroups where it can.
-  const long long rows = (long long)nmerge * m3_max;
-  const int rpb = (int)std::min<long long>(16, std::max<long long>(4, rows / 2048 / 4 * 4));
-  dim3 grid((m3_max + rpb - 1) / rpb, nmerge);
   ProfScope ps(PROF_DOWNWARD, s, 2.0 * nrhs_max * s_bytes / 8.0, s_bytes);
-  hipLaunchKernelGGL(k_downward, grid, dim3(256), shm, s, d_desc, d_io, io0, io_shared ? 1 : 0, rc,
-                     rpb, zbase, zoff);
+  (void)nrhs_max;
+  if (me_max > 64 * DSU) {
+    hipLaunchKernelGGL((k_downward<DSU, true>), dim3(m3_max, nmerge), dim3(256), 0, s, d_desc,
+                       d_io, io0, io_shared ? 1 : 0, zbase, zoff);
+    return;
+  }
+  const int L = std::max(1, (me_max + 63) / 64);
+  const int rpw = std::min(4, DSU / L);
+  const dim3 grid((m3_max + 4 * rpw - 1) / (4 * rpw), nmerge);
+  switch (L) {
+#define HPS_DOWN(LL) \
+  case LL: launch_down_rows<LL>(grid, s, d_desc, d_io, io0, io_shared, zbase, zoff); break;
+    HPS_DOWN(1) HPS_DOWN(2) HPS_DOWN(3) HPS_DOWN(4) HPS_DOWN(5) HPS_DOWN(6) HPS_DOWN(7)
+    HPS_DOWN(8) HPS_DOWN(9) HPS_DOWN(10) HPS_DOWN(11) HPS_DOWN(12) HPS_DOWN(13) HPS_DOWN(14)
+    HPS_DOWN(15) HPS_DOWN(16)
+#undef HPS_DOWN
+    default:
+      HPS_REQUIRE(false, "downward pass: bad row length");
+  }
 }
 
 // Boundary data into u: u[r][gamma[i]] = f[r][i].
@@ -1103,8 +1153,6 @@ void upward_level_nm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max
 void ops_init() {
   static bool done = false;
   if (done) return;
-  HPS_HIP(hipFuncSetAttribute((const void*)k_downward, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              96 * 1024));
   HPS_HIP(hipFuncSetAttribute((const void*)k_upward_z, hipFuncAttributeMaxDynamicSharedMemorySize,
                               96 * 1024));
   HPS_HIP(hipFuncSetAttribute((const void*)k_upward_h, hipFuncAttributeMaxDynamicSharedMemorySize,
