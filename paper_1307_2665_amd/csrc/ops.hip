@@ -114,40 +114,148 @@ void merge_gather(const MergeDesc* d_desc, int nmerge, size_t max_elems, hipStre
 }
 
 // ---------------------------------------------------------------------------
-// Downward pass (Algorithm 2): u(I_i) = S u(I_e) (+ z) for every merge of one
-// level, u [nrhs][N].  Every wave first issues the loads of all the S entries
-// it will use (16 per lane at most), then gathers the matching entries of u
-// (lane l of a wave always owns columns l, l + 64, ... of its rows, so it
-// needs u at those columns only), so one level costs about two memory
-// latencies instead of one per row.  Two shapes:
-//  - whole rows (box boundary me <= 1024): wave w of a workgroup owns RPW
-//    consecutive rows, L = ceil(me/64) loads per lane and row;
-//  - split rows (me > 1024): the four waves of a workgroup take a quarter of
-//    one row each, in pieces of 1024 columns, and add their four sums in a
-//    fixed order through LDS.
-// Up to DRHS right-hand sides share each pass over the loaded rows.
+// Row-parallel passes of a level: for every merge, y_r = A_r . x (one row of a
+// stored matrix against a gathered vector, per right-hand side).  Every wave
+// first issues the loads of all the matrix entries it will use (16 per lane
+// at most), then gathers the matching vector entries (lane l of a wave always
+// owns columns l, l + 64, ... of its rows, so it needs the vector at those
+// columns only), so a level costs about two memory latencies instead of one
+// per row.  Two shapes:
+//  - whole rows (row length <= 1024): wave w of a workgroup owns RPW
+//    consecutive rows, L = ceil(length/64) loads per lane and row;
+//  - split rows (longer): the four waves of a workgroup take a quarter of one
+//    row each, in pieces of 1024 columns, and add their four sums in a fixed
+//    order through LDS.
+// Up to DRHS right-hand sides share each pass over the loaded rows.  The
+// operation (which matrix, which vector, where the result goes) is a small
+// functor:
+//  - RowDown, Algorithm 2: u(I_i) = S u(I_e) (+ z from the upward pass);
+//  - RowUpZ, the upward pass: z = M^-1 (s3 - h3a + h3b);
+//  - RowUpH, the upward pass: h_parent = [h1a ; h2b] (parent order) + Q z.
+// (The two upward steps follow from the third block row of eq:premerge with
+// a source term; M^-1 is the explicit inverse the elimination of [M | B | I]
+// leaves in W.)
 // ---------------------------------------------------------------------------
 constexpr int DRHS = 4, DSU = 16;
 
-template <int L, bool SPLIT>
-__global__ void __launch_bounds__(256) k_downward(const MergeDesc* __restrict__ descs,
-                                                  const SolveIO* __restrict__ io,
-                                                  const SolveIO io0, int io_shared,
-                                                  const double* __restrict__ zbase,
-                                                  const long long* __restrict__ zoff) {
+struct RowDown {
+  struct Args {
+    const MergeDesc* descs;
+    const SolveIO* io;
+    SolveIO io0;
+    int io_shared;
+    const double* zbase;
+    const long long* zoff;
+  };
+  MergeDesc d;
+  double* u;
+  int N, nrhs;
+  const double* z;
+  __device__ RowDown(const Args& a, int mi) : d(a.descs[mi]) {
+    const SolveIO b = a.io ? a.io[a.io_shared ? 0 : mi] : a.io0;
+    u = b.u;
+    N = b.N;
+    nrhs = b.nrhs;
+    z = a.zbase ? a.zbase + a.zoff[mi] * nrhs : nullptr;
+  }
+  __device__ int rows() const { return d.m3; }
+  __device__ int cols() const { return d.me; }
+  __device__ const double* row(int r) const { return d.S + (size_t)r * d.ldw; }
+  using Key = int;
+  __device__ Key key(int c) const { return d.Ie[c]; }
+  __device__ double vec(int k, Key g) const { return u[(size_t)k * N + g]; }
+  __device__ void out(int k, int r, double v) const {
+    if (z) v += z[(size_t)k * d.m3 + r];
+    u[(size_t)k * N + d.Ii[r]] = v;
+  }
+};
+
+struct RowUpZ {
+  struct Args {
+    const MergeDesc* descs;
+    const double* s;
+    int N, nrhs;
+    const double* hbase;
+    const long long* ha_off;
+    const long long* hb_off;
+    double* zbuf;
+    const long long* z_off;
+  };
+  MergeDesc d;
+  const double* s;
+  int N, nrhs;
+  const double* ha;  // [nrhs][na] or null (a leaf child: h = 0)
+  const double* hb;
+  double* z;         // [nrhs][m3]
+  __device__ RowUpZ(const Args& a, int mi) : d(a.descs[mi]), s(a.s), N(a.N), nrhs(a.nrhs) {
+    ha = a.ha_off[mi] < 0 ? nullptr : a.hbase + a.ha_off[mi] * nrhs;
+    hb = a.hb_off[mi] < 0 ? nullptr : a.hbase + a.hb_off[mi] * nrhs;
+    z = a.zbuf + a.z_off[mi] * nrhs;
+  }
+  __device__ int rows() const { return d.m3; }
+  __device__ int cols() const { return d.m3; }
+  __device__ const double* row(int r) const { return d.W + d.m3 + d.me + (size_t)r * d.ldw; }
+  struct Key {
+    int g, a, b;
+  };
+  __device__ Key key(int c) const { return Key{d.Ii[c], d.a3[c], d.b3[c]}; }
+  __device__ double vec(int k, Key e) const {
+    return s[(size_t)k * N + e.g] - (ha ? ha[(size_t)k * d.na + e.a] : 0.0) +
+           (hb ? hb[(size_t)k * d.nb + e.b] : 0.0);
+  }
+  __device__ void out(int k, int r, double v) const { z[(size_t)k * d.m3 + r] = v; }
+};
+
+struct RowUpH {
+  struct Args {
+    const MergeDesc* descs;
+    double* hbase;
+    const long long* ha_off;
+    const long long* hb_off;
+    const long long* hp_off;
+    const double* zbuf;
+    const long long* z_off;
+    int nrhs;
+  };
+  MergeDesc d;
+  int nrhs;
+  const double* ha;
+  const double* hb;
+  double* hp;       // [nrhs][me]
+  const double* z;  // [nrhs][m3]
+  __device__ RowUpH(const Args& a, int mi) : d(a.descs[mi]), nrhs(a.nrhs) {
+    ha = a.ha_off[mi] < 0 ? nullptr : a.hbase + a.ha_off[mi] * nrhs;
+    hb = a.hb_off[mi] < 0 ? nullptr : a.hbase + a.hb_off[mi] * nrhs;
+    hp = a.hbase + a.hp_off[mi] * nrhs;
+    z = a.zbuf + a.z_off[mi] * nrhs;
+  }
+  __device__ int rows() const { return d.me; }
+  __device__ int cols() const { return d.m3; }
+  __device__ const double* row(int r) const { return d.Q + (size_t)r * d.m3; }
+  using Key = int;
+  __device__ Key key(int c) const { return c; }
+  __device__ double vec(int k, Key c) const { return z[(size_t)k * d.m3 + c]; }
+  __device__ void out(int k, int r, double v) const {
+    const int pm = d.pmap[r];
+    v += (pm >= 0) ? (ha ? ha[(size_t)k * d.na + pm] : 0.0)
+                   : (hb ? hb[(size_t)k * d.nb + (-pm - 1)] : 0.0);
+    hp[(size_t)k * d.me + r] = v;
+  }
+};
+
+template <class Op, int L, bool SPLIT>
+__global__ void __launch_bounds__(256) k_rowdot(const typename Op::Args args) {
   constexpr int RPW = SPLIT ? 1 : (DSU / L < 4 ? DSU / L : 4);
   __shared__ double part[4][DRHS];
-  const MergeDesc d = descs[blockIdx.y];
+  const Op op(args, blockIdx.y);
+  const int nrows = op.rows(), ncols = op.cols();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int rbase = SPLIT ? blockIdx.x : (blockIdx.x * 4 + wid) * RPW;
-  if (SPLIT ? rbase >= d.m3 : blockIdx.x * 4 * RPW >= d.m3) return;  // whole workgroup
-  const SolveIO b = io ? io[io_shared ? 0 : blockIdx.y] : io0;
-  double* u = b.u;
-  const int N = b.N, nrhs = b.nrhs, me = d.me, m3 = d.m3;
-  const double* z = zbase ? zbase + zoff[blockIdx.y] * nrhs : nullptr;
+  if (SPLIT ? rbase >= nrows : blockIdx.x * 4 * RPW >= nrows) return;  // whole workgroup
+  const int nrhs = op.nrhs;
   // Columns of this wave: [c0, c1).
-  const int seg = SPLIT ? ((me + 255) / 256) * 64 : me;
-  const int c0 = SPLIT ? wid * seg : 0, c1 = SPLIT ? min(me, c0 + seg) : me;
+  const int seg = SPLIT ? ((ncols + 255) / 256) * 64 : ncols;
+  const int c0 = SPLIT ? wid * seg : 0, c1 = SPLIT ? min(ncols, c0 + seg) : ncols;
 
   for (int rb = 0; rb < nrhs; rb += DRHS) {
     const int nr = min(DRHS, nrhs - rb);
@@ -161,29 +269,31 @@ __global__ void __launch_bounds__(256) k_downward(const MergeDesc* __restrict__ 
 #pragma unroll
       for (int g = 0; g < RPW; ++g) {
         const int r = rbase + g;
-        const double* Srow = d.S + (size_t)r * d.ldw;
+        const double* Arow = op.row(r < nrows ? r : 0);
 #pragma unroll
         for (int l = 0; l < L; ++l) {
           const int c = cb + lane + 64 * l;
-          sv[g][l] = (r < m3 && c < c1) ? Srow[c] : 0.0;
+          sv[g][l] = (r < nrows && c < c1) ? Arow[c] : 0.0;
         }
       }
-      int ie[L];
+      typename Op::Key key[L];
+      bool live[L];
 #pragma unroll
       for (int l = 0; l < L; ++l) {
         const int c = cb + lane + 64 * l;
-        ie[l] = c < c1 ? d.Ie[c] : -1;
+        live[l] = c < c1;
+        key[l] = op.key(live[l] ? c : c0);
       }
 #pragma unroll
       for (int j = 0; j < DRHS; ++j) {
         if (j < nr) {
-          double uv[L];
+          double xv[L];
 #pragma unroll
-          for (int l = 0; l < L; ++l) uv[l] = ie[l] >= 0 ? u[(size_t)(rb + j) * N + ie[l]] : 0.0;
+          for (int l = 0; l < L; ++l) xv[l] = live[l] ? op.vec(rb + j, key[l]) : 0.0;
 #pragma unroll
           for (int g = 0; g < RPW; ++g)
 #pragma unroll
-            for (int l = 0; l < L; ++l) acc[g][j] = fma(sv[g][l], uv[l], acc[g][j]);
+            for (int l = 0; l < L; ++l) acc[g][j] = fma(sv[g][l], xv[l], acc[g][j]);
         }
       }
     }
@@ -205,63 +315,55 @@ __global__ void __launch_bounds__(256) k_downward(const MergeDesc* __restrict__ 
       }
       __syncthreads();
       if (threadIdx.x < nr) {
-        const int j = threadIdx.x, k = rb + j, r = rbase;
-        double v = ((part[0][j] + part[1][j]) + part[2][j]) + part[3][j];
-        if (z) v += z[(size_t)k * m3 + r];
-        u[(size_t)k * N + d.Ii[r]] = v;
+        const int j = threadIdx.x;
+        op.out(rb + j, rbase, ((part[0][j] + part[1][j]) + part[2][j]) + part[3][j]);
       }
       __syncthreads();
     } else if (lane == 0) {
 #pragma unroll
       for (int g = 0; g < RPW; ++g) {
         const int r = rbase + g;
-        if (r < m3) {
+        if (r < nrows) {
 #pragma unroll
-          for (int j = 0; j < DRHS; ++j) {
-            if (j < nr) {
-              const int k = rb + j;
-              double v = acc[g][j];
-              if (z) v += z[(size_t)k * m3 + r];
-              u[(size_t)k * N + d.Ii[r]] = v;
-            }
-          }
+          for (int j = 0; j < DRHS; ++j)
+            if (j < nr) op.out(rb + j, r, acc[g][j]);
         }
       }
     }
   }
 }
 
-template <int L>
-static void launch_down_rows(dim3 grid, hipStream_t s, const MergeDesc* d_desc,
-                             const SolveIO* d_io, const SolveIO& io0, bool io_shared,
-                             const double* zbase, const long long* zoff) {
-  hipLaunchKernelGGL((k_downward<L, false>), grid, dim3(256), 0, s, d_desc, d_io, io0,
-                     io_shared ? 1 : 0, zbase, zoff);
+// One launch of a row-parallel pass over nmerge merges whose longest rows
+// have len_max entries and whose row count is at most rows_max.
+template <class Op>
+static void launch_rowdot(const typename Op::Args& a, int nmerge, int rows_max, int len_max,
+                          hipStream_t s) {
+  if (nmerge <= 0 || rows_max <= 0) return;
+  if (len_max > 64 * DSU) {
+    hipLaunchKernelGGL((k_rowdot<Op, DSU, true>), dim3(rows_max, nmerge), dim3(256), 0, s, a);
+    return;
+  }
+  const int L = std::max(1, (len_max + 63) / 64);
+  const int rpw = std::min(4, DSU / L);
+  const dim3 grid((rows_max + 4 * rpw - 1) / (4 * rpw), nmerge);
+  switch (L) {
+#define HPS_ROWDOT(LL) \
+  case LL: hipLaunchKernelGGL((k_rowdot<Op, LL, false>), grid, dim3(256), 0, s, a); break;
+    HPS_ROWDOT(1) HPS_ROWDOT(2) HPS_ROWDOT(3) HPS_ROWDOT(4) HPS_ROWDOT(5) HPS_ROWDOT(6)
+    HPS_ROWDOT(7) HPS_ROWDOT(8) HPS_ROWDOT(9) HPS_ROWDOT(10) HPS_ROWDOT(11) HPS_ROWDOT(12)
+    HPS_ROWDOT(13) HPS_ROWDOT(14) HPS_ROWDOT(15) HPS_ROWDOT(16)
+#undef HPS_ROWDOT
+    default:
+      HPS_REQUIRE(false, "row pass: bad row length");
+  }
 }
 
 void downward(const MergeDesc* d_desc, const SolveIO* d_io, const SolveIO& io0, int nmerge,
               int m3_max, int me_max, int nrhs_max, const double* zbase, const long long* zoff,
               hipStream_t s, double s_bytes, bool io_shared) {
   ProfScope ps(PROF_DOWNWARD, s, 2.0 * nrhs_max * s_bytes / 8.0, s_bytes);
-  (void)nrhs_max;
-  if (me_max > 64 * DSU) {
-    hipLaunchKernelGGL((k_downward<DSU, true>), dim3(m3_max, nmerge), dim3(256), 0, s, d_desc,
-                       d_io, io0, io_shared ? 1 : 0, zbase, zoff);
-    return;
-  }
-  const int L = std::max(1, (me_max + 63) / 64);
-  const int rpw = std::min(4, DSU / L);
-  const dim3 grid((m3_max + 4 * rpw - 1) / (4 * rpw), nmerge);
-  switch (L) {
-#define HPS_DOWN(LL) \
-  case LL: launch_down_rows<LL>(grid, s, d_desc, d_io, io0, io_shared, zbase, zoff); break;
-    HPS_DOWN(1) HPS_DOWN(2) HPS_DOWN(3) HPS_DOWN(4) HPS_DOWN(5) HPS_DOWN(6) HPS_DOWN(7)
-    HPS_DOWN(8) HPS_DOWN(9) HPS_DOWN(10) HPS_DOWN(11) HPS_DOWN(12) HPS_DOWN(13) HPS_DOWN(14)
-    HPS_DOWN(15) HPS_DOWN(16)
-#undef HPS_DOWN
-    default:
-      HPS_REQUIRE(false, "downward pass: bad row length");
-  }
+  const RowDown::Args a{d_desc, d_io, io0, io_shared ? 1 : 0, zbase, zoff};
+  launch_rowdot<RowDown>(a, nmerge, m3_max, me_max, s);
 }
 
 // Boundary data into u: u[r][gamma[i]] = f[r][i].
@@ -533,92 +635,18 @@ void transpose_rows_batch(const double* const* src, double* const* dst, int coun
 }
 
 // ---------------------------------------------------------------------------
-// Upward source pass for one level (derived from the third block row of
-// eq:premerge with a source):  z = M^-1 (s3 - h3a + h3b),
-// h_parent = [h1a ; h2b] (parent order) + Q z.  M^-1 is the explicit inverse
-// left in W by the elimination of [M | B | I].  Two row-parallel launches per
-// level: a workgroup owns UROWS rows of M^-1 (resp. of Q) of one merge and one
-// right-hand side, with the gathered vector in LDS.
+// Upward source pass for one level: z = M^-1 (s3 - h3a + h3b), then
+// h_parent = [h1a ; h2b] + Q z (row passes RowUpZ and RowUpH above).
 // ---------------------------------------------------------------------------
-constexpr int UROWS = 16;
-
-__global__ void __launch_bounds__(256) k_upward_z(const MergeDesc* __restrict__ descs,
-                                                  const double* __restrict__ s, int N,
-                                                  const double* __restrict__ hbase,
-                                                  const long long* __restrict__ ha_off,
-                                                  const long long* __restrict__ hb_off,
-                                                  double* __restrict__ zbuf,
-                                                  const long long* __restrict__ z_off, int nrhs) {
-  extern __shared__ double rhs[];
-  const int mi = blockIdx.y, rh = blockIdx.z;
-  const MergeDesc d = descs[mi];
-  const int r0 = blockIdx.x * UROWS;
-  if (r0 >= d.m3) return;
-  const int m3 = d.m3, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  // Offsets are per-box unit offsets; each box holds [nrhs][boundary size].
-  // Offset -1: the child is a leaf, whose h is zero.
-  const double* ha = ha_off[mi] < 0 ? nullptr : hbase + ha_off[mi] * nrhs + (size_t)rh * d.na;
-  const double* hb = hb_off[mi] < 0 ? nullptr : hbase + hb_off[mi] * nrhs + (size_t)rh * d.nb;
-  for (int i = threadIdx.x; i < m3; i += blockDim.x)
-    rhs[i] = s[(size_t)rh * N + d.Ii[i]] - (ha ? ha[d.a3[i]] : 0.0) + (hb ? hb[d.b3[i]] : 0.0);
-  __syncthreads();
-  const double* Minv = d.W + d.m3 + d.me;
-  double* z = zbuf + z_off[mi] * nrhs + (size_t)rh * m3;
-  for (int rr = wid; rr < UROWS; rr += 4) {
-    const int i = r0 + rr;
-    if (i >= m3) break;
-    const double* row = Minv + (size_t)i * d.ldw;
-    double acc = 0.0;
-    for (int j = lane; j < m3; j += 64) acc += row[j] * rhs[j];
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0) z[i] = acc;
-  }
-}
-
-__global__ void __launch_bounds__(256) k_upward_h(const MergeDesc* __restrict__ descs,
-                                                  double* __restrict__ hbase,
-                                                  const long long* __restrict__ ha_off,
-                                                  const long long* __restrict__ hb_off,
-                                                  const long long* __restrict__ hp_off,
-                                                  const double* __restrict__ zbuf,
-                                                  const long long* __restrict__ z_off, int nrhs) {
-  extern __shared__ double zs[];
-  const int mi = blockIdx.y, rh = blockIdx.z;
-  const MergeDesc d = descs[mi];
-  const int r0 = blockIdx.x * UROWS;
-  if (r0 >= d.me) return;
-  const int m3 = d.m3, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const double* z = zbuf + z_off[mi] * nrhs + (size_t)rh * m3;
-  for (int i = threadIdx.x; i < m3; i += blockDim.x) zs[i] = z[i];
-  __syncthreads();
-  const double* ha = ha_off[mi] < 0 ? nullptr : hbase + ha_off[mi] * nrhs + (size_t)rh * d.na;
-  const double* hb = hb_off[mi] < 0 ? nullptr : hbase + hb_off[mi] * nrhs + (size_t)rh * d.nb;
-  double* hp = hbase + hp_off[mi] * nrhs + (size_t)rh * d.me;
-  for (int rr = wid; rr < UROWS; rr += 4) {
-    const int r = r0 + rr;
-    if (r >= d.me) break;
-    const double* Qr = d.Q + (size_t)r * m3;
-    double acc = 0.0;
-    for (int j = lane; j < m3; j += 64) acc += Qr[j] * zs[j];
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0) {
-      const int pm = d.pmap[r];
-      hp[r] = acc + ((pm >= 0) ? (ha ? ha[pm] : 0.0) : (hb ? hb[-pm - 1] : 0.0));
-    }
-  }
-}
-
 void upward_level(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, const double* s,
                   int N, double* hbase, const long long* ha_off, const long long* hb_off,
                   const long long* hp_off, double* zbuf, const long long* z_off, int nrhs,
                   double flops, hipStream_t st) {
-  HPS_REQUIRE((size_t)m3_max * sizeof(double) <= 96 * 1024, "upward pass: interface too long");
   ProfScope ps(PROF_UPWARD, st, flops, 8.0 * flops / 2.0);
-  const size_t shm = (size_t)m3_max * sizeof(double);
-  hipLaunchKernelGGL(k_upward_z, dim3((m3_max + UROWS - 1) / UROWS, nmerge, nrhs), dim3(256), shm,
-                     st, d_desc, s, N, hbase, ha_off, hb_off, zbuf, z_off, nrhs);
-  hipLaunchKernelGGL(k_upward_h, dim3((me_max + UROWS - 1) / UROWS, nmerge, nrhs), dim3(256), shm,
-                     st, d_desc, hbase, ha_off, hb_off, hp_off, zbuf, z_off, nrhs);
+  const RowUpZ::Args az{d_desc, s, N, nrhs, hbase, ha_off, hb_off, zbuf, z_off};
+  launch_rowdot<RowUpZ>(az, nmerge, m3_max, m3_max, st);
+  const RowUpH::Args ah{d_desc, hbase, ha_off, hb_off, hp_off, zbuf, z_off, nrhs};
+  launch_rowdot<RowUpH>(ah, nmerge, me_max, m3_max, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -963,8 +991,8 @@ void interface_residual_nm(const double* leafT, const double* U, int N, int nrhs
   hipLaunchKernelGGL(k_jump_nm, dim3(blocks), dim3(256), 0, s, vbuf, nx, ny, q, nrhs, r, N);
 }
 
-// Upward source pass for one depth, node-major (same equations as
-// k_upward_z / k_upward_h): rhs = s3 - h3a + h3b gathered per merge, then
+// Upward source pass for one depth, node-major (same equations as the row
+// passes RowUpZ / RowUpH): rhs = s3 - h3a + h3b gathered per merge, then
 // z = M^-1 rhs and h_parent = [h1a ; h2b] + Q z as grouped GEMMs.
 // Rows of merge blockIdx.y: rhs[i][:] = src[Ii[i]][:] - ha[a3[i]][:] +
 // hb[b3[i]][:]; thread (x, y) of a (64, 4) block takes column x (+ 64 j) of
@@ -1153,10 +1181,6 @@ void upward_level_nm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max
 void ops_init() {
   static bool done = false;
   if (done) return;
-  HPS_HIP(hipFuncSetAttribute((const void*)k_upward_z, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              96 * 1024));
-  HPS_HIP(hipFuncSetAttribute((const void*)k_upward_h, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              96 * 1024));
   done = true;
 }
 
