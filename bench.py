@@ -23,12 +23,17 @@ import sys
 import time
 
 METRIC = "operator build unknowns/s + solves/s at rel err ≤1e-10, FP64 vs mixed/learned"
-PEAK = {"mfma_f64": 78.6, "mfma_f32": 157.3, "hbm": 8000.0}   # TFLOP/s, TFLOP/s, GB/s
+PEAK = {"mfma_f64": 78.6, "mfma_f32": 157.3, "mfma_bf16": 2500.0,   # TFLOP/s (dense)
+        "hbm": 8000.0}                                                # GB/s
 BOUND_OF = {"gemm": ("mfma", "mfma_f64"), "lu_update": ("mfma", "mfma_f64"),
-            "gemm_split32": ("mfma", "mfma_f32"), "back_subst": ("alu", None),
-            "lu_panel": ("alu", None), "swap_trsm": ("alu", None),
+            "gemm_split32": ("mfma", "mfma_f32"), "gemm_bf16x6": ("mfma", "mfma_bf16"),
+            "back_subst": ("alu", None), "lu_panel": ("alu", None), "swap_trsm": ("alu", None),
             "leaf_assemble": ("hbm", "hbm"), "merge_gather": ("hbm", "hbm"),
             "downward": ("hbm", "hbm")}
+# Arithmetic of the Schur products per --mode, and the dtype string of the line.
+MODES = {"fp64": lambda H: H.HPS_FP64, "mixed": lambda H: H.HPS_MIXED_SPLIT32,
+         "bf16x6": lambda H: H.HPS_MIXED_BF16X6}
+DTYPE = {"fp64": "f64", "mixed": "f64+split-f32", "bf16x6": "f64+bf16x6"}
 # FP64 vector ALU peak: 256 CUs x 2.4 GHz x 128 FLOP/clk (64 FMA/clk/CU).
 ALU_F64_PEAK = 78.6
 # HBM bytes per launch of the dominant kernel on this workload, from two
@@ -57,7 +62,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--mode", choices=["fp64", "mixed", "bf16x6"], default="fp64",
+                    help="Schur products: FP64 MFMA, split-FP32 MFMA, or BF16 MFMA on three-slice\n"
+                         "splits (the last two with refinement against the FP64 leaf DtNs)")
     ap.add_argument("--workload", choices=["convdiff", "helmholtz", "batch", "sweep", "post"],
                     default="convdiff",
                     help="convdiff: 64x64 p16 (the default line); helmholtz: 128x128 p16, 64 "
@@ -177,18 +184,18 @@ def other_workload(args, H, hi, np, torch, dev):
         nrhs = F.shape[0]
         forms = {}
         u_ref = None
-        for form in ("fp64", "mixed"):
-            mode = H.HPS_MIXED_SPLIT32 if form == "mixed" else H.HPS_FP64
+        for form in ("fp64", "mixed", "bf16x6"):
+            mode = MODES[form](H)
             if not args.no_tune:
                 H.autotune([dict(nleaf=pr.nleaf, p=pr.p, q=pr.q, box=pr.box)],
-                           keep_factors=(form == "mixed"))
+                           keep_factors=(form != "fp64"))
             box = {}
 
             def build():
                 box["op"] = H.build_solution_operator(C, pr.box, pr.nleaf, pr.p, pr.q, mode=mode)
 
             def solve():
-                if form == "mixed":
+                if form != "fp64":
                     box["info"] = {}
                     box["u"] = box["op"].solve(F, refine=True, tol=1e-11, max_iter=20,
                                                info=box["info"])
@@ -210,7 +217,7 @@ def other_workload(args, H, hi, np, torch, dev):
             del box
         sel = forms[args.mode]
         line.update(value=_n_tot(pr) / (sel["step_ms"] * 1e-3), ms_per_step=sel["step_ms"],
-                    dtype="f64" if args.mode == "fp64" else "f64+split-f32",
+                    dtype=DTYPE[args.mode],
                     config={"workload": "helmholtz-bump-128x128-p16-q14-64rhs", "n_tot": _n_tot(pr),
                             "nrhs": nrhs, "mode": args.mode},
                     forms=forms)
@@ -401,14 +408,14 @@ def main():
     gxy = H.gauss_nodes_grid(pr.box, pr.nleaf, pr.q)
     f = pr.bc_at(gxy[H.boundary_ids(pr.nleaf, pr.q)])
     fd = torch.tensor(f, dtype=torch.float64, device=dev)
-    mode = H.HPS_MIXED_SPLIT32 if args.mode == "mixed" else H.HPS_FP64
+    mode = MODES[args.mode](H)
     n_tot = (nx * (pr.p - 1) + 1) * (ny * (pr.p - 1) + 1) + pr.q * (nx * (ny + 1) + (nx + 1) * ny)
 
     # One-time autotuning for this shape (reported separately, not timed).
     tune_s = None
     if not args.no_tune:
         tune_s = H.autotune([dict(nleaf=pr.nleaf, p=pr.p, q=pr.q, box=pr.box)],
-                            keep_factors=(mode == H.HPS_MIXED_SPLIT32))
+                            keep_factors=(mode != H.HPS_FP64))
         import tempfile
         with tempfile.TemporaryDirectory() as td:
             H.tune_save(os.path.join(td, "t.json"))
@@ -421,7 +428,7 @@ def main():
         return H.build_solution_operator(Cd, pr.box, pr.nleaf, pr.p, pr.q, mode=mode)
 
     def solve(op):
-        if mode == H.HPS_MIXED_SPLIT32:
+        if mode != H.HPS_FP64:
             return op.solve(fd, refine=True, tol=1e-11, max_iter=20)
         return op.solve(fd)
 
@@ -511,7 +518,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if mode == H.HPS_FP64 else "f64+split-f32",
+        "dtype": DTYPE[args.mode],
         "data": "synthetic",
         "config": {"workload": "convdiff-64x64-p16-q14-1rhs", "nleaf": [nx, ny], "p": pr.p,
                    "q": pr.q, "nrhs": 1, "n_tot": n_tot, "mode": args.mode},

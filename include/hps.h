@@ -75,14 +75,16 @@ typedef enum {
 typedef enum {
   HPS_FP64 = 0,           /* every step in FP64 */
   HPS_MIXED_SPLIT32 = 1,  /* Schur products on FP32 MFMA with hi/lo splits; LU and TRSM FP64 */
-  HPS_SURROGATE = 2       /* leaf DtNs from a trained surrogate, judged by the FP64 leaf build */
+  HPS_SURROGATE = 2,      /* leaf DtNs from a trained surrogate, judged by the FP64 leaf build */
+  HPS_MIXED_BF16X6 = 3    /* Schur products on BF16 MFMA from three-slice splits (six products);
+                             LU and TRSM FP64; refinement as in HPS_MIXED_SPLIT32 */
 } hps_mode;
 
 typedef struct {
   int mode;                        /* hps_mode */
   void* stream;                    /* hipStream_t */
   int device_ptrs;                 /* coeffs is a device pointer */
-  int keep_leaf_ops;               /* keep leaf DtNs (needed by refinement; forced on in mixed mode) */
+  int keep_leaf_ops;               /* keep leaf DtNs (needed by refinement; forced on in the mixed modes) */
   int keep_factors;                /* keep LU(M), pivots and Q = [T13a; T23b] per merge (upward pass) */
   int compute_root_dtn;            /* 1: form T^1 at the root (default), 0: skip its Schur product */
   double pivot_tol;                /* |pivot| <= pivot_tol * max|column| -> HPS_ESINGULAR; 0: exact 0 only */
@@ -277,10 +279,13 @@ hps_status hps_batched_solve(const double* M, const double* B, int n, int m, int
                              void* stream);
 
 /* C_i = C_i + alpha A_i B_i for nprob products, A [nprob][Mr][K], B [nprob][K][Nc],
-   C [nprob][Mr][Nc]; split32 = 1 uses the split-FP32 MFMA form of the Schur
-   products (three FP32 products of hi/lo halves, FP64 accumulation per slab). */
+   C [nprob][Mr][Nc].  prec selects the arithmetic of the Schur products:
+   0 FP64 MFMA; 1 split-FP32 MFMA (three FP32 products of hi/lo halves, FP64
+   accumulation per 16-deep slab); 2 BF16 MFMA on three-slice splits (six
+   BF16 products, FP64 accumulation per 32-deep slab).  Other values give
+   HPS_EINVAL. */
 hps_status hps_batched_gemm(const double* A, const double* B, double* C, int Mr, int Nc, int K,
-                            int nprob, double alpha, int split32, void* stream);
+                            int nprob, double alpha, int prec, void* stream);
 
 /* ---- host-side planner queries (no device work; used by CPU tests) ------ */
 
@@ -322,7 +327,10 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
      the GPU split each GEMM contraction into chunks of at least this length
      (-1: the default, 256; else at least 16), summed in a fixed order;
    "post_rows": Chebyshev-grid rows per lane in hps_postprocess (1, 2 or 4;
-     -1: the default, 4 from 16 right-hand sides on, else 2).
+     -1: the default, 4 from 16 right-hand sides on, else 2);
+   "bf16x6_min_k": in HPS_MIXED_BF16X6 builds, merge levels whose longest
+     contraction (interface length m3) is below this run their Schur
+     products in FP64 (-1: the default, 384; 0: BF16 on every level).
    Unknown knobs or values give HPS_EINVAL. */
 hps_status hps_tune_set(const char* knob, int value);
 
@@ -349,10 +357,11 @@ hps_status hps_tune_reset(void);
    3 LU trailing update, 4 back substitution, 5 FP64 GEMM (Schur products and
    leaf T = P0 - P1 Z), 6 split-FP32 Schur GEMM, 7 merge gather, 8 downward
    pass, 9 interface residual, 10 upward pass, 11 fused leaf elimination,
-   12 surrogate training, 13 surrogate inference, 14 post-processing.  Bit c
-   of mask enables class c; every later launch of an enabled class records a
-   start and stop event on its stream together with its algorithmic FLOPs and
-   bytes.  Costs one event pair per launch while enabled. */
+   12 surrogate training, 13 surrogate inference, 14 post-processing, 15
+   BF16 three-slice Schur GEMM.  Bit c of mask enables class c; every later
+   launch of an enabled class records a start and stop event on its stream
+   together with its algorithmic FLOPs and bytes.  Costs one event pair per
+   launch while enabled. */
 hps_status hps_prof_enable(unsigned mask);
 /* Drops all records (waits for their events first). */
 hps_status hps_prof_reset(void);

@@ -13,11 +13,12 @@ from typing import List, Optional, Sequence
 
 import numpy as np
 
-from ._lib import (HPS_EINVAL, HPS_ENOTCONV, HPS_ESINGULAR, HPS_FP64, HPS_MIXED_SPLIT32,
-                   HPS_SURROGATE, BuildOpts, HpsError, OpInfo, Problem, SolveInfo, SolveOpts,
+from ._lib import (HPS_EINVAL, HPS_ENOTCONV, HPS_ESINGULAR, HPS_FP64, HPS_MIXED_BF16X6,
+                   HPS_MIXED_SPLIT32, HPS_SURROGATE, BuildOpts, HpsError, OpInfo, Problem, SolveInfo, SolveOpts,
                    check, lib)
 
-__all__ = ["HpsError", "HPS_FP64", "HPS_MIXED_SPLIT32", "HPS_SURROGATE", "HPS_EINVAL",
+__all__ = ["HpsError", "HPS_FP64", "HPS_MIXED_SPLIT32", "HPS_MIXED_BF16X6", "HPS_SURROGATE",
+           "HPS_EINVAL",
            "HPS_ESINGULAR", "HPS_ENOTCONV", "Operator", "cheb_nodes", "gauss_nodes_grid",
            "boundary_ids", "leaf_dtn", "build_solution_operator", "build_batch", "solve_batch",
            "leaf_tables", "plan_box", "version", "lib", "batched_solve", "batched_gemm",
@@ -148,14 +149,17 @@ def batched_solve(M, B, X=None):
     return X
 
 
-def batched_gemm(A, B, C, alpha: float = 1.0, split32: bool = False):
-    """C_i += alpha A_i B_i on the device (FP64 MFMA or the split-FP32 form)."""
+def batched_gemm(A, B, C, alpha: float = 1.0, split32: bool = False, bf16x6: bool = False):
+    """C_i += alpha A_i B_i on the device: FP64 MFMA, the split-FP32 form, or BF16 MFMA on
+    three-slice splits."""
     A = _f64(A)
     B = _f64(B)
     assert _dev(A) and _dev(B) and _dev(C)
+    assert not (split32 and bf16x6)
     nprob, Mr, K = A.shape
     Nc = B.shape[2]
-    check(lib.hps_batched_gemm(_ptr(A), _ptr(B), _ptr(C), Mr, Nc, K, nprob, alpha, int(split32),
+    prec = 1 if split32 else (2 if bf16x6 else 0)
+    check(lib.hps_batched_gemm(_ptr(A), _ptr(B), _ptr(C), Mr, Nc, K, nprob, alpha, prec,
                                _stream(A)))
     return C
 
@@ -297,7 +301,7 @@ class Surrogate:
 PROF_CLASSES = {"leaf_assemble": 0, "lu_panel": 1, "swap_trsm": 2, "lu_update": 3,
                 "back_subst": 4, "gemm": 5, "gemm_split32": 6, "merge_gather": 7,
                 "downward": 8, "residual": 9, "upward": 10, "leaf_lu": 11, "mlp_train": 12,
-                "mlp_infer": 13, "postprocess": 14}
+                "mlp_infer": 13, "postprocess": 14, "gemm_bf16x6": 15}
 
 
 def mem_trim() -> int:

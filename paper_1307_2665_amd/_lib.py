@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("HPS_LIB", os.path.join(HERE, "libhps.so"))
 
 HPS_OK, HPS_EINVAL, HPS_ESINGULAR, HPS_ENOMEM, HPS_EDEVICE, HPS_ENOTCONV, HPS_ESURROGATE = range(7)
-HPS_FP64, HPS_MIXED_SPLIT32, HPS_SURROGATE = 0, 1, 2
+HPS_FP64, HPS_MIXED_SPLIT32, HPS_SURROGATE, HPS_MIXED_BF16X6 = 0, 1, 2, 3
 STATUS_NAMES = {0: "HPS_OK", 1: "HPS_EINVAL", 2: "HPS_ESINGULAR", 3: "HPS_ENOMEM",
                 4: "HPS_EDEVICE", 5: "HPS_ENOTCONV", 6: "HPS_ESURROGATE"}
 

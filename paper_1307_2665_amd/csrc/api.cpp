@@ -153,7 +153,7 @@ hps_status hps_build_solution_operator(const double* coeffs, const double box[4]
   return guard([&] {
     HPS_REQUIRE(out != nullptr, "out is null");
     HPS_REQUIRE(!opts || opts->mode == HPS_FP64 || opts->mode == HPS_MIXED_SPLIT32 ||
-                    opts->mode == HPS_SURROGATE,
+                    opts->mode == HPS_SURROGATE || opts->mode == HPS_MIXED_BF16X6,
                 "unknown mode");
     HPS_REQUIRE(!opts || opts->mode != HPS_SURROGATE || opts->surrogate,
                 "HPS_SURROGATE needs opts->surrogate");
@@ -170,6 +170,10 @@ hps_status hps_build_batch(const hps_problem* probs, int nprob, const hps_build_
   return guard([&] {
     HPS_REQUIRE(probs && out && nprob >= 1, "bad arguments");
     for (int i = 0; i < nprob; ++i) out[i] = nullptr;
+    HPS_REQUIRE(!opts || opts->mode == HPS_FP64 || opts->mode == HPS_MIXED_SPLIT32 ||
+                    opts->mode == HPS_MIXED_BF16X6 ||
+                    (opts->mode == HPS_SURROGATE && opts->surrogate),
+                "unknown mode, or HPS_SURROGATE without a surrogate");
     hps::BuildOptions bo = to_build_options(opts);
     std::vector<std::unique_ptr<hps_op>> owned;
     std::vector<hps_op*> v;
@@ -418,9 +422,10 @@ hps_status hps_batched_solve(const double* M, const double* B, int n, int m, int
 }
 
 hps_status hps_batched_gemm(const double* A, const double* B, double* C, int Mr, int Nc, int K,
-                            int nprob, double alpha, int split32, void* stream) {
+                            int nprob, double alpha, int prec, void* stream) {
   return guard([&] {
     HPS_REQUIRE(A && B && C && Mr >= 1 && Nc >= 1 && K >= 1 && nprob >= 1, "bad arguments");
+    HPS_REQUIRE(prec >= 0 && prec <= 2, "prec must be 0, 1 or 2");
     hipStream_t s = (hipStream_t)stream;
     hps::DeviceMem tmp;
     std::vector<hps::GemmDesc> hd(nprob);
@@ -428,7 +433,7 @@ hps_status hps_batched_gemm(const double* A, const double* B, double* C, int Mr,
       hd[i] = hps::GemmDesc{A + (size_t)i * Mr * K, B + (size_t)i * K * Nc, C + (size_t)i * Mr * Nc,
                             nullptr, Mr, Nc, K, K, Nc, Nc, 0, alpha};
     hps::GemmDesc* dd = tmp.upload(hd, s);
-    hps::grouped_gemm(dd, hd, s, split32 != 0);
+    hps::grouped_gemm(dd, hd, s, prec);
     HPS_HIP(hipStreamSynchronize(s));
   });
 }
@@ -452,6 +457,9 @@ hps_status hps_tune_set(const char* knob, int value) {
     } else if (k == "split_min_chunk") {
       HPS_REQUIRE(value == -1 || value >= 16, "split_min_chunk must be -1 or >= 16");
       hps::set_split_min_chunk(value < 0 ? 256 : value);
+    } else if (k == "bf16x6_min_k") {
+      HPS_REQUIRE(value >= -1, "bf16x6_min_k must be >= -1");
+      hps::set_bf16x6_min_k(value);
     } else if (k == "post_rows") {
       hps::set_post_rows(value);
     } else if (k == "gj_variant") {

@@ -14,9 +14,19 @@ namespace hps {
 void batched_solve(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc, int* d_status,
                    hipStream_t stream, int nb);
 
-// C += alpha A B for every descriptor, FP64 MFMA (or the split-FP32 form).
+// Arithmetic of a grouped GEMM: FP64 MFMA; FP32 MFMA on hi/lo splits of the
+// operands (three products); BF16 MFMA on three-slice splits (six products).
+enum GemmPrec { GEMM_F64 = 0, GEMM_SPLIT32 = 1, GEMM_BF16X6 = 2 };
+
+// Merge levels whose longest contraction is shorter than this run their
+// Schur products in FP64 even in the BF16 mode (slicing costs more than it
+// saves there); default 384.
+void set_bf16x6_min_k(int k);
+int bf16x6_min_k();
+
+// C = C0 + alpha A B for every descriptor, in the given arithmetic.
 void grouped_gemm(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, hipStream_t stream,
-                  bool split32);
+                  int prec);
 
 // The same with explicit kernel variants (the autotuner times them):
 // gj_variant = update tile * 4 + TRSM block code (see tune.h), -1 = default;
@@ -24,7 +34,7 @@ void grouped_gemm(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, h
 void batched_solve_v(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc, int* d_status,
                      hipStream_t stream, int gj_variant);
 void grouped_gemm_v(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, hipStream_t stream,
-                    int variant, bool split32);
+                    int variant, int prec);
 
 void dense_init();
 int max_solve_rows();

@@ -498,6 +498,251 @@ __global__ void __launch_bounds__(256) k_gemm_split32(const GemmDesc* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// Schur product on BF16 MFMA with three-slice splits.  Every FP64 operand
+// value is written as h + m + l with h = bf16(v), m = bf16(v - h),
+// l = bf16(v - h - m) (each remainder is exact in FP64); the product is
+// formed from the six slice products of order 2^-16 or larger,
+// hh + (hm + mh + hl + lh + mm).  BF16 products are exact in FP32; the two
+// groups are summed in FP32 over one 32-deep step (v_mfma 16x16x32) and then
+// added to FP64 accumulators, so the error is a few units of 2^-24 relative
+// to |A||B|, like the split-FP32 form, at BF16 matrix-core rates.
+//
+// k_split3 writes the slices of an operand once per launch, k contiguous,
+// rows and k zero-padded to multiples of 64 (B transposed on the way, through
+// an LDS tile), so the GEMM reads each MFMA fragment (eight consecutive k of
+// one row) with one 16-byte load and needs no bounds checks.  MFMA lane
+// layout: A lane l holds A[l%16][8(l/16)..+7], B holds B[8(l/16)..+7][l%16],
+// result register r holds D[4(l/16)+r][l%16].
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline unsigned short bf16_rne(float x) {
+  unsigned int u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);  // inf/nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ inline double bf16_val(unsigned short b) {
+  return (double)__uint_as_float(((unsigned int)b) << 16);
+}
+
+// Slices of one operand: dst[s][r][k], s < 3, r < rows_pad, k < kpad, of the
+// matrix element (r, k) = src[r * ld + k] (trans = 0) or src[k * ld + r]
+// (trans = 1), zero outside rows x k.
+struct SliceJob {
+  const double* src;
+  unsigned short* dst;
+  int rows, k, ld, trans;
+  int rows_pad, kpad;
+};
+
+__global__ void __launch_bounds__(256) k_split3(const SliceJob* __restrict__ jobs) {
+  __shared__ double t[64][65];
+  const SliceJob jb = jobs[blockIdx.z];
+  const int r0 = blockIdx.y * 64, k0 = blockIdx.x * 64;
+  if (r0 >= jb.rows_pad || k0 >= jb.kpad) return;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int a = e / 64, b = e % 64;  // b runs along memory
+    double v = 0.0;
+    if (jb.trans) {
+      const int k = k0 + a, r = r0 + b;
+      if (k < jb.k && r < jb.rows) v = jb.src[(size_t)k * jb.ld + r];
+      t[b][a] = v;
+    } else {
+      const int r = r0 + a, k = k0 + b;
+      if (k < jb.k && r < jb.rows) v = jb.src[(size_t)r * jb.ld + k];
+      t[a][b] = v;
+    }
+  }
+  __syncthreads();
+  const size_t per = (size_t)jb.rows_pad * jb.kpad;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int rl = e / 64, kl = e % 64;
+    const double v = t[rl][kl];
+    const unsigned short h = bf16_rne((float)v);
+    const double r1 = v - bf16_val(h);
+    const unsigned short m = bf16_rne((float)r1);
+    const unsigned short l = bf16_rne((float)(r1 - bf16_val(m)));
+    const size_t o = (size_t)(r0 + rl) * jb.kpad + k0 + kl;
+    jb.dst[o] = h;
+    jb.dst[per + o] = m;
+    jb.dst[2 * per + o] = l;
+  }
+}
+
+// Slices of one product's operands (from k_split3): A [3][mpad][kpad],
+// B^T [3][npad][kpad].
+struct SliceGemm {
+  const unsigned short* a;
+  const unsigned short* b;
+  int mpad, npad, kpad, pad;
+};
+
+// Workgroup tile 128 x 64 (four waves stacked along M, 32 x 64 each, 2 x 4
+// MFMA blocks), 32-deep steps.  The step's slices of A (128 rows) and B
+// (64 columns) are staged in LDS with 16-byte copies, double-buffered, so
+// each slice value is read from L2 once per workgroup; the small products
+// accumulate in FP32 over the whole contraction (they are 2^-8 of the
+// result), the hh products in FP32 over one step and then in FP64.
+constexpr int XBM = 128, XBN = 64, XPAD = 40;  // XPAD: LDS row pitch in BF16 (80 bytes)
+
+__global__ void __launch_bounds__(256) k_gemm_bf16x6(const GemmDesc* __restrict__ descs,
+                                                     const SliceGemm* __restrict__ slices) {
+  __shared__ __attribute__((aligned(16))) unsigned short sA[2][3][XBM][XPAD];
+  __shared__ __attribute__((aligned(16))) unsigned short sB[2][3][XBN][XPAD];
+  const GemmDesc g = descs[blockIdx.z];
+  const SliceGemm sg = slices[blockIdx.z];
+  const int tm = blockIdx.y, tn = blockIdx.x;
+  if (tm * XBM >= g.M || tn * XBN >= g.N) return;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int row0 = tm * XBM, col0 = tn * XBN, kq = 8 * (lane >> 4);
+  const size_t sa = (size_t)sg.mpad * sg.kpad, sb = (size_t)sg.npad * sg.kpad;
+  // Copy assignment: thread t moves 16 bytes (8 k values) of row t / 4,
+  // k offset 8 (t % 4), for A rows t/4 and t/4 + 64 and B row t/4, per slice.
+  const int cr = tid >> 2, ck = 8 * (tid & 3);
+  // Rows past mpad/npad (a tile hanging over the padded edge) read row 0.
+  const int ra0 = row0 + cr < sg.mpad ? row0 + cr : 0;
+  const int ra1 = row0 + cr + 64 < sg.mpad ? row0 + cr + 64 : 0;
+  const int rb0 = col0 + cr < sg.npad ? col0 + cr : 0;
+  const unsigned short* ga0 = sg.a + (size_t)ra0 * sg.kpad + ck;
+  const unsigned short* ga1 = sg.a + (size_t)ra1 * sg.kpad + ck;
+  const unsigned short* gb0 = sg.b + (size_t)rb0 * sg.kpad + ck;
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  u4 ra[3][2], rbv[3];
+  auto fetch = [&](int kt) {
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+      ra[sl][0] = *reinterpret_cast<const u4*>(ga0 + sl * sa + kt);
+      ra[sl][1] = *reinterpret_cast<const u4*>(ga1 + sl * sa + kt);
+      rbv[sl] = *reinterpret_cast<const u4*>(gb0 + sl * sb + kt);
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+      *reinterpret_cast<u4*>(&sA[buf][sl][cr][ck]) = ra[sl][0];
+      *reinterpret_cast<u4*>(&sA[buf][sl][cr + 64][ck]) = ra[sl][1];
+      *reinterpret_cast<u4*>(&sB[buf][sl][cr][ck]) = rbv[sl];
+    }
+  };
+  double acc[2][4][4];
+  f4 small[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      small[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
+    }
+  fetch(0);
+  stage(0);
+  __syncthreads();
+  int buf = 0;
+  for (int kt = 0; kt < sg.kpad; kt += 32) {
+    const bool more = kt + 32 < sg.kpad;
+    if (more) fetch(kt + 32);  // in flight during this step's products
+    bf16x8 a[3][2], b[3][4];
+#pragma unroll
+    for (int sl = 0; sl < 3; ++sl) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        a[sl][i] = *reinterpret_cast<const bf16x8*>(&sA[buf][sl][wid * 32 + i * 16 + (lane & 15)][kq]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        b[sl][j] = *reinterpret_cast<const bf16x8*>(&sB[buf][sl][j * 16 + (lane & 15)][kq]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        f4 big = f4{0.f, 0.f, 0.f, 0.f};
+        big = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], big, 0, 0, 0);
+        small[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], small[i][j], 0, 0, 0);
+        small[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], small[i][j], 0, 0, 0);
+        small[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], small[i][j], 0, 0, 0);
+        small[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], small[i][j], 0, 0, 0);
+        small[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], small[i][j], 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)big[r];
+      }
+    if (more) stage(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = row0 + wid * 32 + i * 16 + 4 * (lane >> 4) + r;
+        const int gc = col0 + j * 16 + (lane & 15);
+        if (gr < g.M && gc < g.N) {
+          const double c0 = g.pmap ? merge_pass(g)(gr, gc)
+                                   : (g.C0 ? g.C0[(size_t)gr * g.ldc0 + gc]
+                                           : g.C[(size_t)gr * g.ldc + gc]);
+          g.C[(size_t)gr * g.ldc + gc] =
+              c0 + g.alpha * (acc[i][j][r] + (double)small[i][j][r]);
+        }
+      }
+}
+
+static int g_bf16x6_min_k = 384;
+void set_bf16x6_min_k(int k) { g_bf16x6_min_k = k < 0 ? 384 : k; }
+int bf16x6_min_k() { return g_bf16x6_min_k; }
+
+// Slices for every product of a launch (stream-ordered scratch, released on
+// the stream after the products), then the products.
+static void gemm_bf16x6(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc,
+                        hipStream_t s) {
+  const int np = (int)h_desc.size();
+  auto up64 = [](int x) { return (x + 63) / 64 * 64; };
+  std::vector<SliceJob> jobs;
+  std::vector<SliceGemm> sl(np);
+  size_t total = 0;
+  int mmax = 0, nmax = 0, rmax = 0, kmax = 0;
+  for (const GemmDesc& g : h_desc) {
+    const int mp = up64(g.M), npd = up64(g.N), kp = up64(g.K);
+    total += (size_t)3 * ((size_t)mp + npd) * kp;
+    mmax = std::max(mmax, g.M);
+    nmax = std::max(nmax, g.N);
+    rmax = std::max(rmax, std::max(mp, npd));
+    kmax = std::max(kmax, kp);
+  }
+  unsigned short* buf = nullptr;
+  HPS_HIP(hipMallocAsync((void**)&buf, total * sizeof(unsigned short), s));
+  size_t off = 0;
+  for (int i = 0; i < np; ++i) {
+    const GemmDesc& g = h_desc[i];
+    const int mp = up64(g.M), npd = up64(g.N), kp = up64(g.K);
+    unsigned short* a = buf + off;
+    off += (size_t)3 * mp * kp;
+    unsigned short* b = buf + off;
+    off += (size_t)3 * npd * kp;
+    jobs.push_back(SliceJob{g.A, a, g.M, g.K, g.lda, 0, mp, kp});
+    jobs.push_back(SliceJob{g.B, b, g.N, g.K, g.ldb, 1, npd, kp});
+    sl[i] = SliceGemm{a, b, mp, npd, kp, 0};
+  }
+  SliceJob* djobs = nullptr;
+  SliceGemm* dsl = nullptr;
+  HPS_HIP(hipMallocAsync((void**)&djobs, jobs.size() * sizeof(SliceJob), s));
+  HPS_HIP(hipMallocAsync((void**)&dsl, sl.size() * sizeof(SliceGemm), s));
+  HPS_HIP(hipMemcpyAsync(djobs, jobs.data(), jobs.size() * sizeof(SliceJob),
+                         hipMemcpyHostToDevice, s));
+  HPS_HIP(hipMemcpyAsync(dsl, sl.data(), sl.size() * sizeof(SliceGemm), hipMemcpyHostToDevice, s));
+  HPS_REQUIRE(jobs.size() <= 65535, "too many products in one launch");
+  hipLaunchKernelGGL(k_split3, dim3(kmax / 64, rmax / 64, (unsigned)jobs.size()), dim3(256), 0, s,
+                     djobs);
+  hipLaunchKernelGGL(k_gemm_bf16x6, dim3((nmax + XBN - 1) / XBN, (mmax + XBM - 1) / XBM, np),
+                     dim3(256), 0, s, d_desc, dsl);
+  // The host vectors above were copied from pageable memory, so they may go.
+  HPS_HIP(hipFreeAsync(dsl, s));
+  HPS_HIP(hipFreeAsync(djobs, s));
+  HPS_HIP(hipFreeAsync(buf, s));
+}
+
+// ---------------------------------------------------------------------------
 // Host drivers.
 // ---------------------------------------------------------------------------
 
@@ -598,7 +843,7 @@ void batched_solve(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc
 }
 
 void grouped_gemm_v(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, hipStream_t stream,
-                    int variant, bool split32) {
+                    int variant, int prec) {
   if (h_desc.empty()) return;
   int mmax = 0, nmax = 0;
   for (auto& g : h_desc) {
@@ -618,10 +863,18 @@ void grouped_gemm_v(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc,
     HPS_REQUIRE(!pass || (g.Ta != nullptr && g.Tb != nullptr && g.na > 0 && g.nb > 0),
                 "merge Schur product without its children's DtNs");
   }
-  ProfScope ps(split32 ? PROF_GEMM_SPLIT32 : PROF_GEMM, stream, fl, by);
-  if (split32) {
+  HPS_REQUIRE(prec == GEMM_F64 || prec == GEMM_SPLIT32 || prec == GEMM_BF16X6,
+              "unknown GEMM arithmetic");
+  ProfScope ps(prec == GEMM_SPLIT32 ? PROF_GEMM_SPLIT32
+                                    : (prec == GEMM_BF16X6 ? PROF_GEMM_BF16X6 : PROF_GEMM),
+               stream, fl, by);
+  if (prec == GEMM_SPLIT32) {
     dim3 grid((nmax + TBN - 1) / TBN, (mmax + TBM - 1) / TBM, np);
     hipLaunchKernelGGL(k_gemm_split32, grid, dim3(256), 0, stream, d_desc);
+    return;
+  }
+  if (prec == GEMM_BF16X6) {
+    gemm_bf16x6(d_desc, h_desc, stream);
     return;
   }
 #define HPS_GEMM(BM, BN, BK, WM, WN)                                                          \
@@ -658,9 +911,9 @@ int gemm_bucket_variant(const std::vector<GemmDesc>& h_desc) {
 }
 
 void grouped_gemm(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, hipStream_t stream,
-                  bool split32) {
+                  int prec) {
   if (h_desc.empty()) return;
-  grouped_gemm_v(d_desc, h_desc, stream, split32 ? 0 : gemm_bucket_variant(h_desc), split32);
+  grouped_gemm_v(d_desc, h_desc, stream, prec != GEMM_F64 ? 0 : gemm_bucket_variant(h_desc), prec);
 }
 
 void dense_init() {}

@@ -23,6 +23,7 @@ enum ProfClass {
   PROF_MLP_TRAIN = 12,
   PROF_MLP_INFER = 13,
   PROF_POSTPROCESS = 14,
+  PROF_GEMM_BF16X6 = 15,
   PROF_NCLASS = 16
 };
 

@@ -244,7 +244,7 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
   op->surrogate = o.surrogate;
   op->judge_samples = o.judge_samples;
   op->judge_tol = o.judge_tol;
-  if (o.mode == HPS_MIXED_SPLIT32) {
+  if (o.mode == HPS_MIXED_SPLIT32 || o.mode == HPS_MIXED_BF16X6) {
     op->opt.keep_factors = true;
     op->opt.keep_leaf = true;
   }
@@ -482,7 +482,7 @@ static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hip
       leaf_assemble(dcp, tab, cnt, Wslab, s);
       batched_solve(dsd, sd, dstatus, s, panel);
     }
-    grouped_gemm(dgd, gd, s, false);
+    grouped_gemm(dgd, gd, s, GEMM_F64);
     // Kept Z goes out transposed ([4q][(p-2)^2]) for the post-processing loads.
     std::vector<const double*> zs;  // live until the chunk's synchronization below
     std::vector<double*> zd;
@@ -612,7 +612,10 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
   // Merges, deepest level first; all operators' merges at one depth together.
   int maxd = 0;
   for (hps_op* op : ops) maxd = std::max(maxd, (int)op->levels.size() - 1);
-  const bool split = !ops.empty() && ops[0]->mode == HPS_MIXED_SPLIT32;
+  // Arithmetic of the Schur products (one mode per batch).
+  const int prec = ops.empty() ? GEMM_F64
+                   : ops[0]->mode == HPS_MIXED_SPLIT32 ? GEMM_SPLIT32
+                   : ops[0]->mode == HPS_MIXED_BF16X6 ? GEMM_BF16X6 : GEMM_F64;
   for (int d = maxd; d >= 0; --d) {
     std::vector<MergeDesc> hm;
     std::vector<SolveDesc> hs;
@@ -649,7 +652,9 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
     }
     merge_gather(dm, (int)hm.size(), gmax, s);
     batched_solve(dsd, hs, dstatus, s, panel);
-    grouped_gemm(dgd, hg, s, split);
+    int kmax = 0;
+    for (const GemmDesc& g : hg) kmax = std::max(kmax, g.K);
+    grouped_gemm(dgd, hg, s, prec == GEMM_BF16X6 && kmax < bf16x6_min_k() ? GEMM_F64 : prec);
   }
   int st[4];
   HPS_HIP(hipMemcpyAsync(st, dstatus, sizeof(st), hipMemcpyDeviceToHost, s));

@@ -234,7 +234,7 @@ void tune_gemm(const GemmShape& g, hipStream_t s, Timer& tm) {
   double best = 1e300, tdef = 0;
   int bv = 0;
   for (int v = 0; v < GEMM_VARIANTS; ++v) {
-    const double t = best_of(tm, 3, [&] { grouped_gemm_v(dd, hd, s, v, false); });
+    const double t = best_of(tm, 3, [&] { grouped_gemm_v(dd, hd, s, v, GEMM_F64); });
     if (v == 0) tdef = t;
     if (t < best) {
       best = t;

@@ -1,10 +1,11 @@
-"""Split-FP32 Schur products + iterative refinement against the FP64 oracle.
+"""Mixed-precision Schur products + iterative refinement against the FP64 oracle.
 
-The mixed operator's merges form their Schur products on FP32 MFMA from hi/lo
-splits; LU and the block-row solves stay FP64.  Solves are refined with the
-interface residual of the FP64 leaf DtNs (the discrete system the FP64 path
-solves exactly) until the update is below 1e-12 relative; the result must
-match the FP64 oracle to 1e-10.
+The mixed operators' merges form their Schur products on FP32 MFMA from hi/lo
+splits (HPS_MIXED_SPLIT32) or on BF16 MFMA from three-slice splits
+(HPS_MIXED_BF16X6); LU and the block-row solves stay FP64.  Solves are
+refined with the interface residual of the FP64 leaf DtNs (the discrete
+system the FP64 path solves exactly) until the update is below 1e-12
+relative; the result must match the FP64 oracle to 1e-10.
 """
 import numpy as np
 import pytest
@@ -23,23 +24,38 @@ def H(gpu):
     return H
 
 
+_MODES = {"split32": lambda H: H.HPS_MIXED_SPLIT32, "bf16x6": lambda H: H.HPS_MIXED_BF16X6}
+
+
+def _build(H, gpu, pr, C, mode):
+    """Mixed operator; the BF16 mode runs its slice products on every merge level
+    (by default levels with short interfaces stay FP64)."""
+    try:
+        if mode == "bf16x6":
+            H.tune_set("bf16x6_min_k", 0)
+        return H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q,
+                                         mode=_MODES[mode](H))
+    finally:
+        H.tune_set("bf16x6_min_k", -1)
+
+
 def _t(x, dev):
     import torch
     return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
 
 
+@pytest.mark.parametrize("mode", ["split32", "bf16x6"])
 @pytest.mark.parametrize("maker,nleaf", [(hi.convdiff, (16, 16)), (hi.helmholtz_bump, (16, 16)),
                                          (hi.laplace_log, (4, 4))])
-def test_mixed_refined_matches_fp64_oracle(H, gpu, maker, nleaf):
+def test_mixed_refined_matches_fp64_oracle(H, gpu, maker, nleaf, mode):
     kw = dict(nleaf=nleaf)
     if maker is hi.helmholtz_bump:
         kw["nrhs"] = 3
     pr = maker(**kw)
-    say(f"mixed {pr.name} {nleaf}")
+    say(f"mixed ({mode}) {pr.name} {nleaf}")
     op_o, C_o, f_o, grid = oracle_problem(pr)
     C, f = library_inputs(pr)
-    op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q,
-                                   mode=H.HPS_MIXED_SPLIT32)
+    op = _build(H, gpu, pr, C, mode)
     u0 = op.solve(_t(f, gpu)).cpu().numpy()
     info = {}
     u = op.solve(_t(f, gpu), refine=True, tol=1e-12, max_iter=20, info=info).cpu().numpy()
@@ -53,12 +69,12 @@ def test_mixed_refined_matches_fp64_oracle(H, gpu, maker, nleaf):
     assert rel_err(op.export_root_dtn(), op_o.rootT) < 1e-4
 
 
-def test_refinement_reports_nonconvergence(H, gpu):
-    say("mixed nonconvergence")
+@pytest.mark.parametrize("mode", ["split32", "bf16x6"])
+def test_refinement_reports_nonconvergence(H, gpu, mode):
+    say(f"mixed ({mode}) nonconvergence")
     pr = hi.convdiff(nleaf=(8, 8))
     C, f = library_inputs(pr)
-    op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q,
-                                   mode=H.HPS_MIXED_SPLIT32)
+    op = _build(H, gpu, pr, C, mode)
     with pytest.raises(H.HpsError) as e:
         op.solve(_t(f, gpu), refine=True, tol=1e-30, max_iter=2)
     assert e.value.status == H.HPS_ENOTCONV

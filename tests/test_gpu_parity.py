@@ -57,6 +57,32 @@ def test_gemm_split32_accuracy(H, gpu):
     assert err < 5e-7
 
 
+def test_gemm_bf16x6_accuracy(H, gpu):
+    """BF16 MFMA on three-slice splits: the operand slices carry 24 bits, the six
+    products are exact in FP32 and summed in FP32 over 32-deep slabs, so the
+    error is a few units of 2^-24 like the split-FP32 form.  Ragged tiles in all
+    three dimensions; a transposed fragment or a dropped slice product fails."""
+    say("gemm_bf16x6 300x200x448 and 70x130x37 batch 3")
+    rng = np.random.default_rng(6)
+    for (Mr, Nc, K, nb) in [(300, 200, 448, 1), (70, 130, 37, 3)]:
+        A, B = rng.standard_normal((nb, Mr, K)), rng.standard_normal((nb, K, Nc))
+        C0 = rng.standard_normal((nb, Mr, Nc))
+        C = _t(C0, gpu)
+        H.batched_gemm(_t(A, gpu), _t(B, gpu), C, alpha=-0.5, bf16x6=True)
+        ref = C0 - 0.5 * A @ B
+        err = rel_err(C.cpu().numpy(), ref)
+        say(f"  {Mr}x{Nc}x{K}: rel err {err:.2e}")
+        assert err < 5e-7
+    # scale spread: values over 2^-40 .. 2^40 keep their relative accuracy
+    A = rng.standard_normal((1, 64, 64)) * np.exp2(rng.integers(-40, 40, (1, 64, 1)))
+    B = rng.standard_normal((1, 64, 64))
+    C = _t(np.zeros((1, 64, 64)), gpu)
+    H.batched_gemm(_t(A, gpu), _t(B, gpu), C, bf16x6=True)
+    ref = A @ B
+    rowerr = np.max(np.abs(C.cpu().numpy() - ref), axis=2) / np.max(np.abs(ref), axis=2)
+    assert rowerr.max() < 5e-7
+
+
 # Sizes cover one round of the pivot tournament (n <= 128), two rounds (448),
 # three rounds (900) and waves taking several round-1 chunks (1100, 2100).
 @pytest.mark.parametrize("n,m,nb", [(5, 3, 2), (33, 40, 3), (70, 17, 2), (130, 9, 1), (196, 56, 2),
