@@ -86,6 +86,7 @@ class Problem:
     q: int = 14
     bc: List[CoefFn] = dataclasses.field(default_factory=list)  # RHS functions
     exact: CoefFn | None = None        # closed-form solution if known
+    body: List[CoefFn] = dataclasses.field(default_factory=list)  # body loads g (A u = g)
 
     def coeffs_at(self, xy: np.ndarray) -> np.ndarray:
         """Evaluate the six fields at Chebyshev nodes.
@@ -99,6 +100,11 @@ class Problem:
         for c, fn in enumerate(self.coefs):
             out[:, c, :] = np.broadcast_to(fn(x, y), x.shape)
         return out
+
+    def body_at(self, xy: np.ndarray) -> np.ndarray:
+        """Body loads [nrhs, nleaf, p*p] at every leaf's Chebyshev nodes xy [nleaf, p*p, 2]."""
+        return np.stack([np.asarray(g(xy[..., 0], xy[..., 1]), dtype=np.float64)
+                         * np.ones(xy.shape[:2]) for g in self.body])
 
     def bc_at(self, xy: np.ndarray) -> np.ndarray:
         """Boundary data [nrhs, n_bdry] at boundary points xy [n_bdry, 2]."""
@@ -230,6 +236,36 @@ def manufactured_variable(nleaf=(2, 2), p=12, q=10, seed=11) -> Problem:
 
     return Problem("manufactured", [c11, c12, c22, c1, c2, c], nleaf=tuple(nleaf), p=p, q=q,
                    bc=[u], exact=u)
+
+
+def manufactured_body(nleaf=(3, 2), p=12, q=10, seed=12) -> Problem:
+    """Body load with a known solution: A u = g with all six coefficients
+    seeded smooth fields (c too) and u = 1 + x^3 - 2 x y^2 + x^2 y - 3 y^3;
+    g = A u in closed form.  u is a cubic, so the discrete solution is exact up
+    to rounding once p, q >= 4."""
+    rng = np.random.default_rng(seed)
+    f = [fourier_field(rng) for _ in range(6)]
+    c11 = lambda x, y: 1.0 + 0.3 * f[0](x, y)
+    c12 = lambda x, y: 0.2 * f[1](x, y)
+    c22 = lambda x, y: 1.0 + 0.3 * f[2](x, y)
+    c1 = lambda x, y: 2.0 * f[3](x, y)
+    c2 = lambda x, y: 2.0 * f[4](x, y)
+    c = lambda x, y: 1.0 + 0.5 * f[5](x, y)
+    u = lambda x, y: 1.0 + x ** 3 - 2.0 * x * y * y + x * x * y - 3.0 * y ** 3
+    ux = lambda x, y: 3.0 * x * x - 2.0 * y * y + 2.0 * x * y
+    uy = lambda x, y: -4.0 * x * y + x * x - 9.0 * y * y
+    uxx = lambda x, y: 6.0 * x + 2.0 * y
+    uxy = lambda x, y: -4.0 * y + 2.0 * x
+    uyy = lambda x, y: -4.0 * x - 18.0 * y
+
+    def g(x, y):
+        x = np.asarray(x)
+        y = np.asarray(y)
+        return (-c11(x, y) * uxx(x, y) - 2.0 * c12(x, y) * uxy(x, y) - c22(x, y) * uyy(x, y)
+                + c1(x, y) * ux(x, y) + c2(x, y) * uy(x, y) + c(x, y) * u(x, y))
+
+    return Problem("manufactured_body", [c11, c12, c22, c1, c2, c], nleaf=tuple(nleaf), p=p, q=q,
+                   bc=[u], exact=u, body=[g])
 
 
 def rhs_fields(seeds: Sequence[int]) -> List[FourierField]:

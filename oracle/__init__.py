@@ -8,8 +8,10 @@ Everything here is plain, slow, FP64 NumPy/SciPy written from the paper:
 
 * ``oracle.hps``   -- sections 2-5: nodes, leaf DtN (section 3), merge
   (section 4, eq:U_parent and eq:merge), Algorithms 1 and 2, post-processing
-  (section 5.3), and the interface-source extension used by iterative
-  refinement (derived from eq:premerge with a non-zero third block row).
+  (section 5.3), the interface-source extension used by iterative
+  refinement (derived from eq:premerge with a non-zero third block row), and
+  body loads A u = g (leaf particular solutions whose fluxes ride the same
+  recursion).
 * ``oracle.brute`` -- a brute-force global collocation solve (every leaf's
   interior collocation equations plus flux matching on every interior edge, in
   one dense system) and the dense interface system built from leaf DtNs; both

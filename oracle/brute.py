@@ -35,12 +35,14 @@ def _side_sign(q):
     return np.concatenate([-np.ones(q), np.ones(q), np.ones(q), -np.ones(q)])
 
 
-def collocation_solve(coeffs, box, nleaf, p, q, f, with_interior=False):
+def collocation_solve(coeffs, box, nleaf, p, q, f, with_interior=False, body=None):
     """Solve the full composite collocation system densely; returns u at all Gauss nodes.
 
     With with_interior=True also returns every leaf's interior Chebyshev values,
     [nx*ny, (p-2)^2] in ascending node order, the unknowns w_i of the same
-    global system (section 5.3 recovers them leaf by leaf)."""
+    global system (section 5.3 recovers them leaf by leaf).  body [nx*ny, p*p]
+    is a body load g (A u = g) at the Chebyshev nodes: it becomes the
+    right-hand side of the interior collocation rows."""
     nx, ny = nleaf
     grid = hps.Grid(box, nx, ny, q)
     gamma = grid.boundary(0, nx, 0, ny)
@@ -66,9 +68,11 @@ def collocation_solve(coeffs, box, nleaf, p, q, f, with_interior=False):
             Aii, Aie, Fe, Fi = _leaf_blocks(coeffs[lf], mats)
             Ie = grid.boundary(i, i + 1, j, j + 1)
             wcol = len(interior) + lf * ni
-            # Interior collocation rows: Aii w_i + Aie L1 u_d = 0.
+            # Interior collocation rows: Aii w_i + Aie L1 u_d = g_i (0 without a load).
             G = Aie @ mats["L1"]                      # acts on the 4q Gauss values
             K[row:row + ni, wcol:wcol + ni] = Aii
+            if body is not None:
+                rhs[row:row + ni] += np.asarray(body)[lf][mats["Ji"]]
             for k, g in enumerate(Ie):
                 if on_gamma[g]:
                     rhs[row:row + ni] -= G[:, k] * ufix[g]

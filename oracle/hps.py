@@ -451,14 +451,16 @@ def interface_residual(op: Operator, u: np.ndarray) -> np.ndarray:
     return r
 
 
-def upward(op: Operator, s: np.ndarray) -> Dict[int, np.ndarray]:
+def upward(op: Operator, s: np.ndarray,
+           h_leaf: Optional[Dict[int, np.ndarray]] = None) -> Dict[int, np.ndarray]:
     """Upward pass for interface sources s (jump v_alpha - v_beta = s).
 
     Third block row of eq:premerge with a source term and with particular
     fluxes h carried up from the children:
         (T33a - T33b) u3 = -T31a u1 + T32b u2 + s3 - h3a + h3b,
     so u3 = S u_e + z with z = M^-1 (s3 - h3a + h3b), and the parent's
-    particular flux is h = [h1a; h2b] + Q z.  Leaves have h = 0.
+    particular flux is h = [h1a; h2b] + Q z.  Leaves have h = 0, or the
+    fluxes h_leaf[t] [nrhs, 4q] of a body load's leaf particular solutions.
     """
     s = np.atleast_2d(s)
     nr = s.shape[0]
@@ -467,7 +469,8 @@ def upward(op: Operator, s: np.ndarray) -> Dict[int, np.ndarray]:
     for t in range(len(op.boxes) - 1, -1, -1):
         b = op.boxes[t]
         if b.is_leaf:
-            h[t] = np.zeros((nr, len(b.Ie)))
+            h[t] = (np.zeros((nr, len(b.Ie))) if h_leaf is None
+                    else np.atleast_2d(h_leaf[t]).copy())
             continue
         a, c = b.children
         mo = op.merges[t]
@@ -502,6 +505,61 @@ def leaf_cheb_values(op: Operator, u: np.ndarray, t: int) -> np.ndarray:
     w = np.zeros((ue.shape[0], p * p))
     w[:, mats["Je"]] = we
     w[:, mats["Ji"]] = we @ op.leafX[t].T
+    return w
+
+
+# ---------------------------------------------------------------------------
+# Body loads, A u = g (an extension; the paper treats A u = 0).  In every
+# leaf u = v + w: w solves the leaf's collocation equations with the load and
+# zero boundary values, v the homogeneous ones.  w adds its flux h = (L4 L3) w
+# to the leaf's DtN relation (flux = T v + h); the merges carry these fluxes
+# up with the interface-source recursion above (s = 0), and the downward pass
+# adds the resulting z.
+# ---------------------------------------------------------------------------
+
+def leaf_particular(coef: np.ndarray, g: np.ndarray, p: int, q: int, hx: float, hy: float,
+                    mats=None):
+    """Particular solution of one leaf: A_ii w_i = g_i, w = 0 on the leaf's
+    Chebyshev boundary.  g [nrhs, p*p] at the leaf's Chebyshev nodes (only the
+    interior ones are used).  Returns w_i [nrhs, (p-2)^2] and its flux
+    h = L4 L3 [w on J_i, 0 on J_e], [nrhs, 4q]."""
+    m = mats if mats is not None else leaf_matrices(p, q, hx, hy)
+    A = collocation_matrix(coef, m)
+    Ji = m["Ji"]
+    g = np.atleast_2d(g)
+    wi = np.linalg.solve(A[np.ix_(Ji, Ji)], g[:, Ji].T).T
+    w = np.zeros((g.shape[0], p * p))
+    w[:, Ji] = wi
+    h = w @ (m["L4"] @ m["L3"]).T
+    return wi, h
+
+
+def body_solve(op: Operator, coeffs: np.ndarray, f: np.ndarray, g: np.ndarray):
+    """A u = g in the domain, u = f on its boundary.  coeffs [nx*ny, 6, p*p]
+    (as for build), f [nrhs, n_bdry], g [nrhs, nx*ny, p*p] at every leaf's
+    Chebyshev nodes.  Returns u at the Gauss nodes [nrhs, N] and the leaf
+    particular solutions {leaf box: w_i [nrhs, (p-2)^2]}."""
+    g = np.asarray(g)
+    if g.ndim == 2:
+        g = g[None]
+    nx = op.grid.nx
+    mats = leaf_matrices(op.p, op.q, op.grid.hx, op.grid.hy)
+    h_leaf, wpart = {}, {}
+    for t, b in enumerate(op.boxes):
+        if b.is_leaf:
+            k = leaf_index_of(b, nx)
+            wpart[t], h_leaf[t] = leaf_particular(coeffs[k], g[:, k], op.p, op.q,
+                                                  op.grid.hx, op.grid.hy, mats)
+    z = upward(op, np.zeros((g.shape[0], op.grid.N)), h_leaf)
+    return solve(op, f, z=z), wpart
+
+
+def body_cheb_values(op: Operator, u: np.ndarray, t: int, wpart) -> np.ndarray:
+    """Leaf t's Chebyshev-grid values of a body-load solution: the homogeneous
+    part from the leaf's Gauss values (section 5.3) plus the particular part."""
+    w = leaf_cheb_values(op, u, t)
+    Ji = leaf_matrices(op.p, op.q, op.grid.hx, op.grid.hy)["Ji"]
+    w[:, Ji] += wpart[t]
     return w
 
 

@@ -309,3 +309,54 @@ def test_postprocess_reproduces_manufactured_cubic():
             w = hps.leaf_cheb_values(op, u, hps.find_leaf(op, i, j))[0]
             ex = pr.exact(*xy[i + nleaf[0] * j].T)
             assert np.max(np.abs(w - ex)) < 1e-11 * np.max(np.abs(ex))
+
+
+# ---- body loads, A u = g (extension; leaf particular solutions + upward pass) -
+
+def test_body_load_reproduces_manufactured_cubic():
+    """All six coefficients active and g = A u for a cubic u: the body-load
+    solve is exact at the Gauss nodes and on every leaf's Chebyshev grid."""
+    pr = hi.manufactured_body(p=12, q=10)
+    nleaf = (3, 2)
+    op, C, grid = _problem_ops(pr, nleaf)
+    g = pr.body_at(grid.cheb_xy(pr.p))
+    u, wpart = hps.body_solve(op, C, pr.bc_at(hps.gamma_xy(op)), g)
+    ex = pr.exact(*grid.node_xy().T)
+    assert np.max(np.abs(u[0] - ex)) < 1e-11 * np.max(np.abs(ex))
+    xy = grid.cheb_xy(pr.p)
+    for j in range(nleaf[1]):
+        for i in range(nleaf[0]):
+            w = hps.body_cheb_values(op, u, hps.find_leaf(op, i, j), wpart)[0]
+            exc = pr.exact(*xy[i + nleaf[0] * j].T)
+            assert np.max(np.abs(w - exc)) < 1e-11 * np.max(np.abs(exc))
+
+
+def test_body_load_equals_global_collocation():
+    """Random smooth load and boundary data (no closed form): the hierarchical
+    body-load solve equals the one global collocation system with the load on
+    its interior rows, at the Gauss nodes and at every interior node."""
+    pr = hi.manufactured_variable(p=10, q=8, seed=5)
+    pr.bc = [hi.field_from_seed(79)]
+    pr.body = [hi.field_from_seed(80)]
+    nleaf = (3, 3)
+    op, C, grid = _problem_ops(pr, nleaf)
+    f = pr.bc_at(hps.gamma_xy(op))
+    g = pr.body_at(grid.cheb_xy(pr.p))
+    u, wpart = hps.body_solve(op, C, f, g)
+    ub, wb = brute.collocation_solve(C, pr.box, nleaf, pr.p, pr.q, f[0], with_interior=True,
+                                     body=g[0])
+    assert np.max(np.abs(u[0] - ub)) < 1e-11 * np.max(np.abs(ub))
+    ji = hps.leaf_matrices(pr.p, pr.q, grid.hx, grid.hy)["Ji"]
+    for j in range(nleaf[1]):
+        for i in range(nleaf[0]):
+            w = hps.body_cheb_values(op, u, hps.find_leaf(op, i, j), wpart)[0]
+            ref = wb[i + nleaf[0] * j]
+            assert np.max(np.abs(w[ji] - ref)) < 1e-11 * np.max(np.abs(wb))
+
+
+def test_body_load_zero_is_the_plain_solve():
+    pr = hi.convdiff(nleaf=(4, 3), p=10, q=8)
+    op, C, grid = _problem_ops(pr, (4, 3))
+    f = np.random.default_rng(1).standard_normal((2, op.n_bdry))
+    u, _ = hps.body_solve(op, C, f, np.zeros((2, 12, pr.p * pr.p)))
+    assert np.max(np.abs(u - hps.solve(op, f))) < 1e-13 * np.max(np.abs(u))
