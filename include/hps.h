@@ -85,7 +85,8 @@ typedef struct {
   void* stream;                    /* hipStream_t */
   int device_ptrs;                 /* coeffs is a device pointer */
   int keep_leaf_ops;               /* keep leaf DtNs (needed by refinement; forced on in the mixed modes) */
-  int keep_factors;                /* keep LU(M), pivots and Q = [T13a; T23b] per merge (upward pass) */
+  int keep_factors;                /* keep LU(M), pivots and Q = [T13a; T23b] per merge (upward pass)
+                                      and a copy of the coefficients (body loads) */
   int compute_root_dtn;            /* 1: form T^1 at the root (default), 0: skip its Schur product */
   double pivot_tol;                /* |pivot| <= pivot_tol * max|column| -> HPS_ESINGULAR; 0: exact 0 only */
   const hps_surrogate* surrogate;  /* mode HPS_SURROGATE only */
@@ -191,6 +192,24 @@ hps_status hps_root_dtn_apply(const hps_op* op, const double* f, int nrhs, doubl
    the problem hps_solve answers. */
 hps_status hps_postprocess(const hps_op* op, const double* u, int nrhs, double* uc,
                            const hps_solve_opts* opts);
+
+/* Body loads: A u = g in the domain, u = f on its boundary (an extension of
+   eq:basic, whose right-hand side is zero).  In every leaf u = v + w: w solves
+   the leaf's interior collocation equations with the load and zero boundary
+   values (section 3.1's A_ii w_i = g_i), v the homogeneous ones; the flux of
+   w joins the leaf's DtN relation (flux = T v + L4 L3 w), these particular
+   fluxes ride the merges' interface-source recursion up the tree (third
+   block row of eq:premerge), and Algorithm 2 adds the resulting interface
+   terms.  f [nrhs][n_bdry]; g [nrhs][nx*ny][p*p] at every leaf's Chebyshev
+   nodes (only interior nodes are used); u [nrhs][N] at the Gauss nodes; uc
+   (may be NULL) [nrhs][nx*ny][p*p], the solution on every leaf grid.  Needs
+   an operator built with keep_factors (and keep_leaf_solution for uc),
+   HPS_EINVAL otherwise; HPS_ESINGULAR if a leaf's A_ii is singular.  Uses
+   opts->stream and opts->device_ptrs (f, g, u, uc all host or all device);
+   the refinement fields are ignored.  Exact up to rounding for the FP64
+   operator; a mixed-precision operator gives its unrefined accuracy. */
+hps_status hps_solve_body(hps_op* op, const double* f, const double* g, int nrhs, double* u,
+                          double* uc, const hps_solve_opts* opts);
 
 /* ---- iterative-refinement building blocks (device pointers) ------------- */
 

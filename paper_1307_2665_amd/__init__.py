@@ -440,6 +440,32 @@ class Operator:
         check(lib.hps_postprocess(self._h, _ptr(u), u.shape[0], _ptr(uc), C.byref(so)))
         return uc
 
+    def solve_body(self, f, g, grid: bool = False):
+        """A u = g, u = f on the boundary: f [nrhs, n_bdry], g [nrhs, nx*ny, p*p] at the
+        Chebyshev nodes.  Returns u [nrhs, N], and with grid=True also the solution on
+        every leaf grid [nrhs, nx*ny, p*p] (operator built with keep_factors, and
+        keep_leaf_solution for the grid)."""
+        f = _f64(f)
+        g = _f64(g)
+        if f.ndim == 1:
+            f = f.reshape(1, -1)
+        nrhs = f.shape[0]
+        shape = (nrhs, self.nx * self.ny, self.p * self.p)
+        assert tuple(g.shape) == shape, "g must be [nrhs, nx*ny, p*p]"
+        dev = _dev(f)
+        assert _dev(g) == dev
+        if dev:
+            import torch
+            u = torch.empty((nrhs, self.N), dtype=torch.float64, device=f.device)
+            uc = torch.empty(shape, dtype=torch.float64, device=f.device) if grid else None
+        else:
+            u = np.empty((nrhs, self.N))
+            uc = np.empty(shape) if grid else None
+        so = SolveOpts(_stream(f) if dev else None, int(dev), 0, 0.0, 0)
+        check(lib.hps_solve_body(self._h, _ptr(f), _ptr(g), nrhs, _ptr(u),
+                                 _ptr(uc) if grid else None, C.byref(so)))
+        return (u, uc) if grid else u
+
     def interface_residual(self, u, r=None):
         import torch
         u = _f64(u)

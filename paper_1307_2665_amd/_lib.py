@@ -70,6 +70,7 @@ SIGNATURES = {
     "hps_solve": [P, P, I, P, C.POINTER(SolveOpts), C.POINTER(SolveInfo)],
     "hps_root_dtn_apply": [P, P, I, P, C.POINTER(SolveOpts)],
     "hps_postprocess": [P, P, I, P, C.POINTER(SolveOpts)],
+    "hps_solve_body": [P, P, P, I, P, P, C.POINTER(SolveOpts)],
     "hps_interface_residual": [P, P, I, P, P],
     "hps_solve_with_sources": [P, P, P, I, P, P],
     "hps_build_batch": [C.POINTER(Problem), I, C.POINTER(BuildOpts), C.POINTER(P)],

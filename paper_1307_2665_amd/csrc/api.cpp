@@ -300,6 +300,37 @@ hps_status hps_postprocess(const hps_op* op, const double* u, int nrhs, double* 
   });
 }
 
+hps_status hps_solve_body(hps_op* op, const double* f, const double* g, int nrhs, double* u,
+                          double* uc, const hps_solve_opts* opts) {
+  return guard([&] {
+    HPS_REQUIRE(op && f && g && u && nrhs >= 1, "bad arguments");
+    hipStream_t s = opts ? (hipStream_t)opts->stream : nullptr;
+    const bool dev = opts && opts->device_ptrs;
+    const size_t nf = (size_t)op->n_bdry * nrhs, nu = (size_t)op->tree().N * nrhs;
+    const size_t ng = (size_t)nrhs * op->nx * op->ny * op->p * op->p;
+    if (!dev) {
+      for (size_t i = 0; i < nf; ++i) HPS_REQUIRE(std::isfinite(f[i]), "non-finite boundary data");
+      for (size_t i = 0; i < ng; ++i) HPS_REQUIRE(std::isfinite(g[i]), "non-finite body load");
+    }
+    Staged F, G, U, V;
+    stage_in(F, f, nf, dev, s);
+    stage_in(G, g, ng, dev, s);
+    auto out = [&](Staged& st, double* p, size_t n) {
+      if (dev) {
+        st.d = p;
+      } else {
+        st.d = (double*)hps::pool_alloc(std::max<size_t>(n, 1) * sizeof(double));
+        st.owned = true;
+      }
+    };
+    out(U, u, nu);
+    if (uc) out(V, uc, ng);
+    hps::body_solve_device(op, F.d, G.d, nrhs, U.d, uc ? V.d : nullptr, s);
+    stage_out(U, u, nu, dev, s);
+    if (uc) stage_out(V, uc, ng, dev, s);
+  });
+}
+
 hps_status hps_interface_residual(const hps_op* op, const double* u, int nrhs, double* r,
                                   void* stream) {
   return guard([&] {

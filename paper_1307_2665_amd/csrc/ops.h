@@ -20,6 +20,18 @@ struct LeafDev {
 
 void leaf_assemble(const double* const* cptr, const LeafDev& tab, int count, double* W,
                    hipStream_t s);
+// Body loads: W = [A_ii | G] per leaf (ld = n + nrhs), G[k][r] = body[r][leaf][node k]
+// with body [nrhs][nl][p*p] and leaf = leaf0 + position in the batch.
+void leaf_assemble_body(const double* const* cptr, const LeafDev& tab, int count, double* W,
+                        const double* body, int nrhs, int nl, int leaf0, hipStream_t s);
+// Fluxes P1 w_i of the particular solutions left in W + n by the solve, into
+// the upward pass's h buffer at unit offset hoff + leaf m; optionally w_i
+// itself into wpart [nrhs][nl][n].
+void body_flux(const double* W, int count, int n, int m, int ld, int nrhs, const double* P1,
+               double* hbuf, long long hoff, double* wpart, int nl, int leaf0, hipStream_t s);
+// uc [nrhs][nleaf][pp]: adds wpart [nrhs][nleaf][n] at the interior nodes post_node[0..n).
+void add_particular(double* uc, const double* wpart, const int* post_node, int n, int pp,
+                    int nleaf, int nrhs, hipStream_t s);
 void merge_gather(const MergeDesc* d_desc, int nmerge, size_t max_elems, hipStream_t s);
 // Downward pass of one depth; io[i] gives merge i's solution array (io null:
 // every merge uses io0).  s_bytes: bytes of all S of the launch (its
@@ -48,6 +60,8 @@ void transpose_rows_batch(const double* const* src, double* const* dst, int coun
                           int cols, int lds, hipStream_t s);
 // Rows per lane of the post-processing kernel: 1, 2, 4, or 0/-1 (by count).
 void set_post_rows(int r);
+// Upward source pass of one depth, per right-hand side (s, [nrhs][N], may be
+// null: no interface sources).
 void upward_level(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max, const double* s,
                   int N, double* hbase, const long long* ha_off, const long long* hb_off,
                   const long long* hp_off, double* zbuf, const long long* z_off, int nrhs,

@@ -16,12 +16,16 @@ namespace hps {
 //   -c11 Dxx[a][a'] d_bb' - 2 c12 Dx[a][a'] Dy[b][b'] - c22 Dyy[b][b'] d_aa'
 //   + c1 Dx[a][a'] d_bb' + c2 Dy[b][b'] d_aa' + c d_kk'
 // R[k][:] = -c11 G11[k] - 2 c12 G12[k] - c22 G22[k] + c1 G1[k] + c2 G2[k].
+// With a body load the system is W = [A_ii | G] instead (ld = n + nrhs): G
+// holds the load of every right-hand side at the leaf's interior nodes.
 // ---------------------------------------------------------------------------
 constexpr int PMAX = 24;
 
 __global__ void __launch_bounds__(256) k_leaf_assemble(const double* const* __restrict__ cptr,
                                                        const LeafDev tab,
-                                                       double* __restrict__ W) {
+                                                       double* __restrict__ W,
+                                                       const double* __restrict__ body, int nrhs,
+                                                       int nl, int leaf0) {
   __shared__ double Dx[PMAX * PMAX], Dy[PMAX * PMAX], Dxx[PMAX * PMAX], Dyy[PMAX * PMAX];
   __shared__ double cf[6][(PMAX - 2) * (PMAX - 2)];
   const int p = tab.p, n = tab.n, m = tab.m, pi = p - 2;
@@ -38,7 +42,7 @@ __global__ void __launch_bounds__(256) k_leaf_assemble(const double* const* __re
     cf[f][k] = cl[(size_t)f * p * p + a + p * b];
   }
   __syncthreads();
-  const int ld = n + m;
+  const int ld = body ? n + nrhs : n + m;
   double* Wl = W + (size_t)blockIdx.x * n * ld;
   for (int e = threadIdx.x; e < n * ld; e += blockDim.x) {
     const int k = e / ld, col = e % ld;
@@ -53,6 +57,9 @@ __global__ void __launch_bounds__(256) k_leaf_assemble(const double* const* __re
       if (b == b2) v += -c11 * Dxx[a * p + a2] + c1 * dx;
       if (a == a2) v += -c22 * Dyy[b * p + b2] + c2 * dy;
       if (col == k) v += cf[5][k];
+    } else if (body) {  // load of right-hand side col - n at interior node k
+      const int a = 1 + k % pi, b = 1 + k / pi;
+      v = body[((size_t)(col - n) * nl + leaf0 + blockIdx.x) * p * p + a + p * b];
     } else {
       const int c = col - n;
       const size_t o = (size_t)k * m + c, s = (size_t)n * m;
@@ -67,7 +74,67 @@ void leaf_assemble(const double* const* cptr, const LeafDev& tab, int count, dou
                    hipStream_t s) {
   HPS_REQUIRE(tab.p <= PMAX, "p too large");
   ProfScope ps(PROF_LEAF_ASSEMBLE, s, 0, 8.0 * count * ((double)tab.n * (tab.n + tab.m) + 6.0 * tab.p * tab.p));
-  hipLaunchKernelGGL(k_leaf_assemble, dim3(count), dim3(256), 0, s, cptr, tab, W);
+  hipLaunchKernelGGL(k_leaf_assemble, dim3(count), dim3(256), 0, s, cptr, tab, W, nullptr, 0, 0,
+                     0);
+}
+
+void leaf_assemble_body(const double* const* cptr, const LeafDev& tab, int count, double* W,
+                        const double* body, int nrhs, int nl, int leaf0, hipStream_t s) {
+  HPS_REQUIRE(tab.p <= PMAX, "p too large");
+  ProfScope ps(PROF_LEAF_ASSEMBLE, s, 0,
+               8.0 * count * ((double)tab.n * (tab.n + nrhs) + 6.0 * tab.p * tab.p));
+  hipLaunchKernelGGL(k_leaf_assemble, dim3(count), dim3(256), 0, s, cptr, tab, W, body, nrhs, nl,
+                     leaf0);
+}
+
+// Body loads: for leaves leaf0 .. leaf0 + count - 1, X = W + n (ld) holds the
+// particular solutions w_i of every right-hand side ([n][nrhs]).  Writes
+// their fluxes h = P1 w_i ([m][n] times [n][nrhs]) to
+// hbuf[(hoff + leaf m) nrhs + k m + r] (the upward pass's per-box layout) and,
+// when wpart is not null, w_i to wpart[k][leaf][i].
+__global__ void __launch_bounds__(256) k_body_flux(const double* __restrict__ W, int n, int m,
+                                                   int ld, int nrhs, const double* __restrict__ P1,
+                                                   double* __restrict__ hbuf, long long hoff,
+                                                   double* __restrict__ wpart, int nl, int leaf0) {
+  const int leaf = leaf0 + blockIdx.x;
+  const double* X = W + (size_t)blockIdx.x * n * ld + n;
+  for (int e = threadIdx.x; e < nrhs * m; e += blockDim.x) {
+    const int k = e / m, r = e % m;
+    double acc = 0.0;
+    for (int c = 0; c < n; ++c) acc = fma(P1[(size_t)r * n + c], X[(size_t)c * ld + k], acc);
+    hbuf[(size_t)(hoff + (long long)leaf * m) * nrhs + (size_t)k * m + r] = acc;
+  }
+  if (wpart)
+    for (int e = threadIdx.x; e < nrhs * n; e += blockDim.x) {
+      const int k = e / n, i = e % n;
+      wpart[((size_t)k * nl + leaf) * n + i] = X[(size_t)i * ld + k];
+    }
+}
+
+void body_flux(const double* W, int count, int n, int m, int ld, int nrhs, const double* P1,
+               double* hbuf, long long hoff, double* wpart, int nl, int leaf0, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_body_flux, dim3(count), dim3(256), 0, s, W, n, m, ld, nrhs, P1, hbuf, hoff,
+                     wpart, nl, leaf0);
+}
+
+// uc[k][leaf][post_node[i]] += wpart[k][leaf][i] for the n interior rows.
+__global__ void k_add_particular(double* __restrict__ uc, const double* __restrict__ wpart,
+                                 const int* __restrict__ post_node, int n, int pp, size_t count) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const size_t kl = e / n;
+    const int i = (int)(e % n);
+    uc[kl * pp + post_node[i]] += wpart[e];
+  }
+}
+
+void add_particular(double* uc, const double* wpart, const int* post_node, int n, int pp,
+                    int nleaf, int nrhs, hipStream_t s) {
+  const size_t count = (size_t)nrhs * nleaf * n;
+  const int blocks = (int)std::min<size_t>((count + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_add_particular, dim3(std::max(blocks, 1)), dim3(256), 0, s, uc, wpart,
+                     post_node, n, pp, count);
 }
 
 // ---------------------------------------------------------------------------
@@ -200,7 +267,7 @@ struct RowUpZ {
   };
   __device__ Key key(int c) const { return Key{d.Ii[c], d.a3[c], d.b3[c]}; }
   __device__ double vec(int k, Key e) const {
-    return s[(size_t)k * N + e.g] - (ha ? ha[(size_t)k * d.na + e.a] : 0.0) +
+    return (s ? s[(size_t)k * N + e.g] : 0.0) - (ha ? ha[(size_t)k * d.na + e.a] : 0.0) +
            (hb ? hb[(size_t)k * d.nb + e.b] : 0.0);
   }
   __device__ void out(int k, int r, double v) const { z[(size_t)k * d.m3 + r] = v; }

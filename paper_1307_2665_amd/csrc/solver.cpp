@@ -260,8 +260,14 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
   op->h_units = P.h_units;
 
   const size_t ncoef = nl * 6 * p * p;
-  if (o.device_ptrs) {
-    op->coeffs = coeffs;
+  if (o.device_ptrs && !op->opt.keep_factors) {
+    op->coeffs = coeffs;  // read by the build only
+  } else if (o.device_ptrs) {
+    // Body-load solves assemble the leaf systems again after the build, so
+    // the operator keeps its own copy (the caller's buffer may be gone).
+    double* d = op->mem.alloc<double>(ncoef);
+    HPS_HIP(hipMemcpyAsync(d, coeffs, ncoef * sizeof(double), hipMemcpyDeviceToDevice, s));
+    op->coeffs = d;
   } else {
     for (size_t i = 0; i < ncoef; ++i)
       HPS_REQUIRE(std::isfinite(coeffs[i]), "non-finite coefficient");
@@ -344,6 +350,12 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
       }
       L.ha.push_back(P.box_hoff[B.ca]);
       L.hb.push_back(P.box_hoff[B.cb]);
+      auto body_off = [&](int c) {
+        const BoxRec& C = t.boxes[c];
+        return C.ca < 0 ? P.h_units + (long long)(C.i0 + nx * C.j0) * m : P.box_hoff[c];
+      };
+      L.hab.push_back(body_off(B.ca));
+      L.hbb.push_back(body_off(B.cb));
       L.hp.push_back(P.box_hoff[b]);
       L.zo.push_back(oz);
       L.m3_max = std::max(L.m3_max, r.m3);
@@ -393,14 +405,15 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
     total += (bytes + 255) & ~size_t(255);
     return o;
   };
-  struct Off { size_t h, hs, hg, ha, hb, hp, zo; };
+  struct Off { size_t h, hs, hg, ha, hb, hp, zo, hab, hbb; };
   std::vector<Off> offs(op->levels.size());
   for (size_t d = 0; d < op->levels.size(); ++d) {
     const LevelPlan& L = op->levels[d];
     if (L.h.empty()) continue;
     offs[d] = Off{reserve(L.h.size() * sizeof(MergeDesc)), reserve(L.hs.size() * sizeof(SolveDesc)),
                   reserve(L.hg.size() * sizeof(GemmDesc)), reserve(L.ha.size() * 8),
-                  reserve(L.hb.size() * 8), reserve(L.hp.size() * 8), reserve(L.zo.size() * 8)};
+                  reserve(L.hb.size() * 8), reserve(L.hp.size() * 8), reserve(L.zo.size() * 8),
+                  reserve(L.hab.size() * 8), reserve(L.hbb.size() * 8)};
   }
   op->staging.assign(total, 0);
   char* dbase = (char*)op->mem.raw(std::max<size_t>(total, 1));
@@ -419,6 +432,8 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
     L.dhb = (long long*)put(f.hb, L.hb.data(), L.hb.size() * 8);
     L.dhp = (long long*)put(f.hp, L.hp.data(), L.hp.size() * 8);
     L.dzo = (long long*)put(f.zo, L.zo.data(), L.zo.size() * 8);
+    L.dhab = (long long*)put(f.hab, L.hab.data(), L.hab.size() * 8);
+    L.dhbb = (long long*)put(f.hbb, L.hbb.data(), L.hbb.size() * 8);
   }
   if (total) HPS_HIP(hipMemcpyAsync(dbase, op->staging.data(), total, hipMemcpyHostToDevice, s));
   return op;
@@ -1007,6 +1022,70 @@ void solve_with_sources_device(hps_op* op, const double* f, const double* src, i
   downward_all(op, u, nrhs, z, s);
   HPS_HIP(hipFreeAsync(h, s));
   HPS_HIP(hipFreeAsync(z, s));
+}
+
+// Body loads (A u = g).  Leaf particular solutions by the batched dense
+// solver on [A_ii | G] (G: the load of every right-hand side at the leaf's
+// interior nodes); their fluxes P1 w_i enter the upward pass as the leaves'
+// h (no interface sources); Algorithm 2 then adds the resulting z.  uc adds
+// w_i to the post-processed grids.  Runs on the per-right-hand-side passes.
+void body_solve_device(hps_op* op, const double* f, const double* g, int nrhs, double* u,
+                       double* uc, hipStream_t s) {
+  HPS_REQUIRE(op->opt.keep_factors, "body loads need an operator built with keep_factors");
+  HPS_REQUIRE(!uc || op->leafZ, "grid values need an operator built with keep_leaf_solution");
+  HPS_REQUIRE(nrhs >= 1, "bad right-hand-side count");
+  const LeafPlan& LP = op->leaf();
+  const int p = op->p, q = op->q, n = (p - 2) * (p - 2), m = 4 * q, nl = op->nx * op->ny;
+  const int ld = n + nrhs, N = op->tree().N;
+  HPS_REQUIRE(n <= max_solve_rows(), "leaf too large for the dense solver");
+  LeafDev tab{LP.dDx, LP.dDy, LP.dDxx, LP.dDyy, LP.dG, p, n, m, 0};
+  const size_t per = (size_t)n * ld * sizeof(double) + (size_t)n * sizeof(int);
+  const int CH = (int)std::max<size_t>(1, std::min<size_t>(nl, ((size_t)2 << 30) / per));
+  AsyncBuf W((size_t)CH * n * ld, s), piv(((size_t)CH * n + 1) / 2 + 1, s);
+  AsyncBuf h((size_t)(op->h_units + (long long)nl * m) * nrhs, s);
+  AsyncBuf z((size_t)std::max<long long>(1, op->z_units) * nrhs, s);
+  AsyncBuf wpart(uc ? (size_t)nrhs * nl * n : 1, s);
+  AsyncBuf desc(((size_t)CH * (sizeof(SolveDesc) + sizeof(void*)) + 7) / 8 + 4, s);
+  const double** dcp = (const double**)desc.p;
+  SolveDesc* dsd = (SolveDesc*)(dcp + CH);
+  int* dstatus = (int*)(dsd + CH);
+  HPS_HIP(hipMemsetAsync(dstatus, 0, 4 * sizeof(int), s));
+  for (int c0 = 0; c0 < nl; c0 += CH) {
+    const int cnt = std::min(CH, nl - c0);
+    std::vector<const double*> cp(cnt);
+    std::vector<SolveDesc> sd(cnt);
+    for (int i = 0; i < cnt; ++i) {
+      cp[i] = op->coeffs + (size_t)(c0 + i) * 6 * p * p;
+      double* Wl = W.p + (size_t)i * n * ld;
+      sd[i] = SolveDesc{Wl, (int*)piv.p + (size_t)i * n, Wl + n, n, nrhs, ld, ld, -(c0 + i + 1), 0};
+    }
+    HPS_HIP(hipMemcpyAsync(dcp, cp.data(), cnt * sizeof(void*), hipMemcpyHostToDevice, s));
+    HPS_HIP(hipMemcpyAsync(dsd, sd.data(), cnt * sizeof(SolveDesc), hipMemcpyHostToDevice, s));
+    leaf_assemble_body(dcp, tab, cnt, W.p, g, nrhs, nl, c0, s);
+    batched_solve(dsd, sd, dstatus, s, 32);
+    body_flux(W.p, cnt, n, m, ld, nrhs, LP.dP1, h.p, op->h_units, uc ? wpart.p : nullptr, nl, c0,
+              s);
+    HPS_HIP(hipStreamSynchronize(s));  // host descriptor vectors are reused next chunk
+  }
+  int st[4];
+  HPS_HIP(hipMemcpyAsync(st, dstatus, sizeof(st), hipMemcpyDeviceToHost, s));
+  HPS_HIP(hipStreamSynchronize(s));
+  if (st[0]) throw Error(HPS_ESINGULAR, "zero or non-finite pivot in the particular solve of leaf " +
+                                            std::to_string(-st[1] - 1));
+  for (int d = (int)op->levels.size() - 1; d >= 0; --d) {
+    const LevelPlan& L = op->levels[d];
+    if (L.h.empty()) continue;
+    double fl = 0;
+    for (const MergeDesc& md : L.h) fl += 2.0 * nrhs * ((double)md.m3 * md.m3 + (double)md.me * md.m3);
+    upward_level(L.d, (int)L.h.size(), L.m3_max, L.me_max, nullptr, N, h.p, L.dhab, L.dhbb, L.dhp,
+                 z.p, L.dzo, nrhs, fl, s);
+  }
+  set_boundary(f, op->gamma, op->n_bdry, u, N, nrhs, s);
+  downward_all(op, u, nrhs, z.p, s);
+  if (uc) {
+    postprocess_device(op, u, nrhs, uc, s);
+    add_particular(uc, wpart.p, LP.dPostNode, n, p * p, nl, nrhs, s);
+  }
 }
 
 static void refine_report(hps_solve_info* info, int it, double first, double last, bool conv,

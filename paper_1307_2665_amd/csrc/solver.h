@@ -39,10 +39,14 @@ struct LevelPlan {
   std::vector<SolveDesc> hs;
   std::vector<GemmDesc> hg;                 // Schur products T^tau += Q S
   std::vector<long long> ha, hb, hp, zo;    // unit offsets for the upward pass
+  // The same child offsets for body-load solves: a leaf child's particular
+  // flux sits at unit offset h_units + leaf * 4q (after the merged boxes).
+  std::vector<long long> hab, hbb;
   MergeDesc* d = nullptr;
   SolveDesc* ds = nullptr;
   GemmDesc* dg = nullptr;
   long long *dha = nullptr, *dhb = nullptr, *dhp = nullptr, *dzo = nullptr;
+  long long *dhab = nullptr, *dhbb = nullptr;
   int m3_max = 0, me_max = 0;
   size_t gather_max = 0;
 };
@@ -111,7 +115,8 @@ struct hps_op {
   hps::DeviceMem mem;
   std::vector<char> staging;        // host image of the device descriptors
   hps::BuildOptions opt;
-  const double* coeffs = nullptr;   // device coefficients used by the build
+  const double* coeffs = nullptr;   // device coefficients: an owned copy (host input or
+                                    // keep_factors), else the caller's, read by the build only
   double* leafT = nullptr;          // [nleaf][4q][4q]
   double* leafZ = nullptr;          // [nleaf][4q][(p-2)^2]: Z^T, Z = A_ii^-1 A_ie L1, or null
   double* Wk = nullptr;             // augmented systems; S (and M^-1) live inside them
@@ -173,6 +178,10 @@ void solve_with_sources_device(hps_op* op, const double* f, const double* src, i
 void root_apply_device(const hps_op* op, const double* f, int nrhs, double* v, hipStream_t s);
 // Section 5.3: u at every leaf's Chebyshev nodes, uc [nrhs][nleaf][p*p].
 void postprocess_device(const hps_op* op, const double* u, int nrhs, double* uc, hipStream_t s);
+// Body loads (A u = g): g [nrhs][nleaf][p*p] at the Chebyshev nodes; u [nrhs][N];
+// uc (or null) [nrhs][nleaf][p*p], the full solution on every leaf grid.
+void body_solve_device(hps_op* op, const double* f, const double* g, int nrhs, double* u,
+                       double* uc, hipStream_t s);
 double absmax_device(const double* x, size_t n, hipStream_t s);
 // Plain solves through captured graphs (default on); off = launch by launch.
 void set_solve_graph(bool on);

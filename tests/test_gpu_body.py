@@ -1,0 +1,167 @@
+"""Body loads A u = g through the C ABI against the CPU oracle.
+
+hps_solve_body solves every leaf's particular problem (A_ii w_i = g_i) with
+the batched dense solver, carries the particular fluxes up the merges with the
+interface-source recursion and runs Algorithm 2 with the resulting terms.
+Each case compares u at the Gauss nodes with the oracle's body_solve and the
+grid values with body_cheb_values (1e-10, relative max-norm per right-hand
+side).  Counts of right-hand sides leave ragged groups of the row passes.
+"""
+import numpy as np
+import pytest
+
+import hps_inputs as hi
+from oracle import hps
+
+from .helpers import library_inputs, oracle_problem, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def H(gpu):
+    import paper_1307_2665_amd as H
+    return H
+
+
+def _t(x, dev):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+
+def _oracle(pr, f, nrhs, seed):
+    """The oracle's solution, with the loads evaluated at the oracle's own nodes."""
+    op_o, C_o, _, grid = oracle_problem(pr, keep=True)
+    u, wpart = hps.body_solve(op_o, C_o, f, _loads(grid.cheb_xy(pr.p), nrhs, seed))
+    nx, ny = pr.nleaf
+    uc = np.zeros((u.shape[0], nx * ny, pr.p * pr.p))
+    for j in range(ny):
+        for i in range(nx):
+            uc[:, i + nx * j] = hps.body_cheb_values(op_o, u, hps.find_leaf(op_o, i, j), wpart)
+    return u, uc
+
+
+def _loads(xy, nrhs, seed):
+    """Seeded smooth loads at Chebyshev nodes xy [nleaf, p*p, 2]: [nrhs, nleaf, p*p]."""
+    fields = hi.rhs_fields(range(seed, seed + nrhs))
+    return np.stack([fl(xy[..., 0], xy[..., 1]) for fl in fields])
+
+
+def _check(name, a, ref):
+    e = max(rel_err(a[k], ref[k]) for k in range(ref.shape[0]))
+    say(f"  {name} vs oracle {e:.2e}")
+    assert e < TOL
+
+
+@pytest.mark.parametrize("maker,nleaf,p,q,nrhs", [
+    (hi.convdiff, (6, 5), 10, 8, 1),
+    (hi.helmholtz_bump, (4, 4), 12, 10, 3),
+    (hi.convdiff, (4, 3), 16, 14, 6),
+])
+def test_body_matches_oracle(H, gpu, maker, nleaf, p, q, nrhs):
+    say(f"body load {maker.__name__} {nleaf} p{p} q{q} nrhs {nrhs}")
+    pr = maker(nleaf=nleaf, p=p, q=q)
+    C, _ = library_inputs(pr)
+    op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, p, q, keep_factors=True,
+                                   keep_leaf_solution=True)
+    f = np.random.default_rng(nrhs).standard_normal((nrhs, op.n_bdry))
+    g = _loads(H.cheb_nodes(pr.box, pr.nleaf, pr.p), nrhs, 500)
+    u, uc = op.solve_body(_t(f, gpu), _t(g, gpu), grid=True)
+    u_o, uc_o = _oracle(pr, f, nrhs, 500)
+    _check("u", u.cpu().numpy(), u_o)
+    _check("grid", uc.cpu().numpy(), uc_o)
+
+
+def test_body_manufactured_cubic_host_pointers(H, gpu):
+    """Host arrays; g = A u for a cubic u with all six coefficients active: the
+    solution is exact at the Gauss nodes and on every grid."""
+    say("body load manufactured cubic 3x2 p12 q10 (host arrays)")
+    pr = hi.manufactured_body(nleaf=(3, 2), p=12, q=10)
+    C, f = library_inputs(pr)
+    op = H.build_solution_operator(C, pr.box, pr.nleaf, pr.p, pr.q, keep_factors=True,
+                                   keep_leaf_solution=True)
+    xy = H.cheb_nodes(pr.box, pr.nleaf, pr.p)
+    g = pr.body_at(xy)
+    u, uc = op.solve_body(f, g, grid=True)
+    gxy = H.gauss_nodes_grid(pr.box, pr.nleaf, pr.q)
+    e_u = rel_err(u[0], pr.exact(gxy[:, 0], gxy[:, 1]))
+    e_c = rel_err(uc[0], pr.exact(xy[..., 0], xy[..., 1]))
+    say(f"  vs exact: u {e_u:.2e}, grid {e_c:.2e}")
+    assert e_u < TOL and e_c < TOL
+
+
+def test_body_many_rhs_and_zero_load(H, gpu):
+    """18 right-hand sides (ragged groups of four); a zero load gives the plain solve."""
+    say("body load 18 rhs, convdiff 5x4 p10 q8; zero load")
+    pr = hi.convdiff(nleaf=(5, 4), p=10, q=8)
+    C, _ = library_inputs(pr)
+    op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q, keep_factors=True)
+    f = np.random.default_rng(18).standard_normal((18, op.n_bdry))
+    g = _loads(H.cheb_nodes(pr.box, pr.nleaf, pr.p), 18, 700)
+    u = op.solve_body(_t(f, gpu), _t(g, gpu)).cpu().numpy()
+    u_o, _ = _oracle(pr, f, 18, 700)
+    _check("u", u, u_o)
+    u0 = op.solve_body(_t(f[:2], gpu), _t(np.zeros_like(g[:2]), gpu)).cpu().numpy()
+    assert rel_err(u0, op.solve(_t(f[:2], gpu)).cpu().numpy()) < 1e-13
+
+
+def test_body_needs_kept_factors(H, gpu):
+    pr = hi.convdiff(nleaf=(2, 2), p=10, q=8)
+    C, f = library_inputs(pr)
+    g = np.zeros((1, 4, pr.p * pr.p))
+    op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q)
+    with pytest.raises(H.HpsError) as e:
+        op.solve_body(_t(f, gpu), _t(g, gpu))
+    assert e.value.status == H.HPS_EINVAL
+    op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q, keep_factors=True)
+    with pytest.raises(H.HpsError) as e:
+        op.solve_body(_t(f, gpu), _t(g, gpu), grid=True)
+    assert e.value.status == H.HPS_EINVAL
+
+
+def test_config2_full_size_body_sampled(H, gpu):
+    """64x64, p=16, q=14 with a smooth load: on sampled leaves the oracle's
+    flux of (T u_b + particular flux) matches across the east and north edges,
+    and the grid values equal the oracle's leaf map plus particular solution
+    applied to the same Gauss values."""
+    say("config2 full size body load")
+    pr = hi.convdiff()
+    C, f = library_inputs(pr)
+    op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q, keep_factors=True,
+                                   keep_leaf_solution=True)
+    g = _loads(H.cheb_nodes(pr.box, pr.nleaf, pr.p), 1, 900)
+    ud, ucd = op.solve_body(_t(f, gpu), _t(g, gpu), grid=True)
+    u, uc = ud.cpu().numpy()[0], ucd.cpu().numpy()[0]
+    grid = hps.Grid(pr.box, 64, 64, pr.q)
+    Co = pr.coeffs_at(grid.cheb_xy(pr.p))
+    go = _loads(grid.cheb_xy(pr.p), 1, 900)[0]
+    mats = hps.leaf_matrices(pr.p, pr.q, grid.hx, grid.hy)
+    q = pr.q
+    cache = {}
+
+    def leaf(i, j):
+        k = i + 64 * j
+        if k not in cache:
+            lo = hps.leaf_dtn(Co[k], pr.p, pr.q, grid.hx, grid.hy, mats)
+            wi, h = hps.leaf_particular(Co[k], go[k][None], pr.p, pr.q, grid.hx, grid.hy, mats)
+            ub = u[grid.boundary(i, i + 1, j, j + 1)]
+            cache[k] = (lo, wi[0], lo.T @ ub + h[0], ub)
+        return cache[k]
+
+    rng = np.random.default_rng(4)
+    worst_flux = worst_grid = 0.0
+    for i, j in rng.integers(0, 63, size=(16, 2)):
+        lo, wi, v, ub = leaf(i, j)
+        scale = np.max(np.abs(lo.T)) * np.max(np.abs(u))
+        worst_flux = max(worst_flux, np.max(np.abs(v[q:2 * q] - leaf(i + 1, j)[2][3 * q:])) / scale,
+                         np.max(np.abs(v[2 * q:3 * q] - leaf(i, j + 1)[2][:q])) / scale)
+        ref = np.zeros(pr.p * pr.p)
+        we = lo.L1 @ ub
+        ref[lo.Je] = we
+        ref[lo.Ji] = lo.X @ we + wi
+        worst_grid = max(worst_grid, rel_err(uc[i + 64 * j], ref))
+    say(f"  flux mismatch {worst_flux:.2e}, grid vs oracle leaf map {worst_grid:.2e}")
+    assert worst_flux < 1e-10 and worst_grid < TOL
+
