@@ -65,7 +65,8 @@ def parse():
     ap.add_argument("--mode", choices=["fp64", "mixed", "bf16x6"], default="fp64",
                     help="Schur products: FP64 MFMA, split-FP32 MFMA, or BF16 MFMA on three-slice\n"
                          "splits (the last two with refinement against the FP64 leaf DtNs)")
-    ap.add_argument("--workload", choices=["convdiff", "helmholtz", "batch", "sweep", "post"],
+    ap.add_argument("--workload", choices=["convdiff", "helmholtz", "batch", "sweep", "post",
+                                           "body"],
                     default="convdiff",
                     help="convdiff: 64x64 p16 (the default line); helmholtz: 128x128 p16, 64 "
                          "right-hand sides, FP64 and split-FP32 + refinement; batch: 32 uneven "
@@ -224,6 +225,8 @@ def other_workload(args, H, hi, np, torch, dev):
         return line
     if args.workload == "post":
         return post_workload(args, H, hi, np, torch, dev, line)
+    if args.workload == "body":
+        return body_workload(args, H, hi, np, torch, dev, line)
     if args.workload == "batch":
         probs = hi.batched_problems()
         ins = [_inputs(H, pr, np, torch, dev) for pr in probs]
@@ -382,6 +385,86 @@ def post_workload(args, H, hi, np, torch, dev, line):
                                 "cores": _blas_threads(), "kind": "oracle",
                                 "sample": f"{reps} passes over the 64 leaves of an 8x8 operator "
                                           "(same p, q), per-leaf rate"}
+    return line
+
+
+def body_workload(args, H, hi, np, torch, dev, line):
+    """Body loads A u = g on the convection-diffusion operator (64 x 64 leaves, p = 16,
+    q = 14, built once with keep_factors): one right-hand side f and one seeded smooth load
+    g per solve.  A step is one hps_solve_body call (leaf particular solves, upward pass,
+    Algorithm 2); the first step's kernel classes pick the dominant one for the roofline."""
+    pr = hi.convdiff()
+    nx, ny = pr.nleaf
+    C, F = _inputs(H, pr, np, torch, dev)
+    op = H.build_solution_operator(C, pr.box, pr.nleaf, pr.p, pr.q, keep_factors=True)
+    xy = H.cheb_nodes(pr.box, pr.nleaf, pr.p)
+    g = torch.tensor(hi.rhs_fields([900])[0](xy[..., 0], xy[..., 1])[None], dtype=torch.float64,
+                     device=dev)
+    classes = list(H.PROF_CLASSES)
+    H.prof_enable(classes)
+    H.prof_reset()
+    u = op.solve_body(F, g)
+    torch.cuda.synchronize()
+    per = {c: H.prof_query(c) for c in classes}
+    H.prof_enable([])
+    dominant = max((c for c in per if per[c]["launches"] > 0), key=lambda c: per[c]["ms"])
+    log("body solve kernel classes: " + ", ".join(
+        f"{c}={per[c]['ms']:.3f}ms/{per[c]['launches']}" for c in classes if per[c]["launches"]))
+    for _ in range(args.warmup):
+        op.solve_body(F, g)
+    H.prof_enable([dominant])
+    H.prof_reset()
+    torch.cuda.synchronize()
+    t = []
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        u = op.solve_body(F, g)
+        torch.cuda.synchronize()
+        t.append(1e3 * (time.perf_counter() - a))
+    dom = H.prof_query(dominant)
+    H.prof_enable([])
+    ms = float(np.median(t))
+    bound, peak_key = BOUND_OF.get(dominant, ("alu", None))
+    if bound == "hbm":
+        ach = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=ach, peak=PEAK["hbm"], unit="GB/s")
+    else:
+        ach = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
+        roof = dict(bound=bound, achieved=ach,
+                    peak=PEAK[peak_key] if peak_key else ALU_F64_PEAK, unit="TFLOP/s")
+    roof.update(frac=roof["achieved"] / roof["peak"], traffic=None, kernel=dominant,
+                launches_per_step=dom["launches"] / args.steps,
+                avg_launch_ms=dom["ms"] / max(dom["launches"], 1))
+    n_tot = _n_tot(pr)
+    line.update(metric="body-load solves/s (A u = g, section 3.1 leaf systems + upward pass)",
+                unit="solves/s", value=1e3 / ms, ms_per_step=ms, dtype="f64",
+                config={"workload": "body-convdiff-64x64-p16-q14-1rhs", "nleaf": [nx, ny],
+                        "p": pr.p, "q": pr.q, "nrhs": 1, "n_tot": n_tot},
+                roofline=roof,
+                kernel_ms_first_call={c: round(per[c]["ms"], 4) for c in classes
+                                      if per[c]["launches"]})
+    if not args.no_cpu_baseline:
+        # The oracle's body-load solve of a 16 x 16-leaf problem of the same p and q, per leaf
+        # (leaf particular solves dominate), scaled to 4096 leaves.
+        from oracle import hps
+        sub = hi.convdiff(nleaf=(16, 16))
+        grid = hps.Grid(sub.box, 16, 16, sub.q)
+        Cs = sub.coeffs_at(grid.cheb_xy(sub.p))
+        op_o = hps.build(Cs, sub.box, (16, 16), sub.p, sub.q)
+        xs = grid.cheb_xy(sub.p)
+        gs = hi.rhs_fields([900])[0](xs[..., 0], xs[..., 1])[None]
+        fs = sub.bc_at(hps.gamma_xy(op_o))
+        reps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < 10.0:
+            hps.body_solve(op_o, Cs, fs, gs)
+            reps += 1
+        t_sub = (time.perf_counter() - t0) / reps
+        t_full = t_sub * (nx * ny) / 256
+        line["cpu_baseline"] = {"value": 1.0 / t_full, "unit": "solves/s", "cores": _blas_threads(),
+                                "kind": "oracle",
+                                "sample": f"{reps} body-load solves of a 16x16-leaf problem (same "
+                                          "p, q), scaled x16 by leaf count"}
+    del u
     return line
 
 
