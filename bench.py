@@ -29,7 +29,8 @@ BOUND_OF = {"gemm": ("mfma", "mfma_f64"), "lu_update": ("mfma", "mfma_f64"),
             "gemm_split32": ("mfma", "mfma_f32"), "gemm_bf16x6": ("mfma", "mfma_bf16"),
             "back_subst": ("alu", None), "lu_panel": ("alu", None), "swap_trsm": ("alu", None),
             "leaf_assemble": ("hbm", "hbm"), "merge_gather": ("hbm", "hbm"),
-            "downward": ("hbm", "hbm")}
+            "downward": ("hbm", "hbm"), "upward": ("hbm", "hbm"), "residual": ("hbm", "hbm"),
+            "body_flux": ("hbm", "hbm"), "postprocess": ("hbm", "hbm")}
 # Arithmetic of the Schur products per --mode, and the dtype string of the line.
 MODES = {"fp64": lambda H: H.HPS_FP64, "mixed": lambda H: H.HPS_MIXED_SPLIT32,
          "bf16x6": lambda H: H.HPS_MIXED_BF16X6}
@@ -73,6 +74,9 @@ def parse():
                          "problems with 16 right-hand sides each; sweep: 256x256 p12 coefficient "
                          "fields, plain FP64 leaves against the learned surrogate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--body-refactor", action="store_true",
+                    help="body workload: refactor the leaf systems in every solve instead of\n"
+                         "keeping P1 A_ii^-1 from the build")
     ap.add_argument("--cpu-sample-leaves", type=int, default=512)
     ap.add_argument("--kernels", action="store_true", help="print per-class kernel times")
     ap.add_argument("--no-tune", action="store_true",
@@ -390,13 +394,15 @@ def post_workload(args, H, hi, np, torch, dev, line):
 
 def body_workload(args, H, hi, np, torch, dev, line):
     """Body loads A u = g on the convection-diffusion operator (64 x 64 leaves, p = 16,
-    q = 14, built once with keep_factors): one right-hand side f and one seeded smooth load
-    g per solve.  A step is one hps_solve_body call (leaf particular solves, upward pass,
+    q = 14, built once with keep_body_operator, i.e. P1 A_ii^-1 kept per leaf; with
+    --body-refactor only keep_factors, and every solve refactors the leaf systems): one
+    right-hand side f and one seeded smooth load g per solve.  A step is one hps_solve_body call (leaf particular solves, upward pass,
     Algorithm 2); the first step's kernel classes pick the dominant one for the roofline."""
     pr = hi.convdiff()
     nx, ny = pr.nleaf
     C, F = _inputs(H, pr, np, torch, dev)
-    op = H.build_solution_operator(C, pr.box, pr.nleaf, pr.p, pr.q, keep_factors=True)
+    op = H.build_solution_operator(C, pr.box, pr.nleaf, pr.p, pr.q, keep_factors=True,
+                                   keep_body_operator=not args.body_refactor)
     xy = H.cheb_nodes(pr.box, pr.nleaf, pr.p)
     g = torch.tensor(hi.rhs_fields([900])[0](xy[..., 0], xy[..., 1])[None], dtype=torch.float64,
                      device=dev)
@@ -439,7 +445,8 @@ def body_workload(args, H, hi, np, torch, dev, line):
     line.update(metric="body-load solves/s (A u = g, section 3.1 leaf systems + upward pass)",
                 unit="solves/s", value=1e3 / ms, ms_per_step=ms, dtype="f64",
                 config={"workload": "body-convdiff-64x64-p16-q14-1rhs", "nleaf": [nx, ny],
-                        "p": pr.p, "q": pr.q, "nrhs": 1, "n_tot": n_tot},
+                        "p": pr.p, "q": pr.q, "nrhs": 1, "n_tot": n_tot,
+                        "leaf_particular": "refactor" if args.body_refactor else "kept"},
                 roofline=roof,
                 kernel_ms_first_call={c: round(per[c]["ms"], 4) for c in classes
                                       if per[c]["launches"]})

@@ -95,6 +95,10 @@ typedef struct {
   int keep_leaf_solution;          /* keep each leaf's Z = A_ii^-1 A_ie L1 ((p-2)^2 x 4q doubles
                                       per leaf, stored transposed) for hps_postprocess; not in
                                       surrogate mode */
+  int keep_body_operator;          /* keep K = P1 A_ii^-1 per leaf ((p-2)^2 x 4q doubles, stored
+                                      transposed; P1: interior values to leaf flux), so that
+                                      hps_solve_body needs no leaf factorization; implies
+                                      keep_factors */
 } hps_build_opts;
 
 typedef struct {
@@ -377,10 +381,11 @@ hps_status hps_tune_reset(void);
    leaf T = P0 - P1 Z), 6 split-FP32 Schur GEMM, 7 merge gather, 8 downward
    pass, 9 interface residual, 10 upward pass, 11 fused leaf elimination,
    12 surrogate training, 13 surrogate inference, 14 post-processing, 15
-   BF16 three-slice Schur GEMM.  Bit c of mask enables class c; every later
-   launch of an enabled class records a start and stop event on its stream
-   together with its algorithmic FLOPs and bytes.  Costs one event pair per
-   launch while enabled. */
+   BF16 three-slice Schur GEMM, 16 body-load fluxes from the kept body
+   operator.  Bit c of mask enables class c; every later launch of an
+   enabled class records a start and stop event on its stream together with
+   its algorithmic FLOPs and bytes.  Costs one event pair per launch while
+   enabled. */
 hps_status hps_prof_enable(unsigned mask);
 /* Drops all records (waits for their events first). */
 hps_status hps_prof_reset(void);

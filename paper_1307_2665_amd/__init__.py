@@ -301,7 +301,8 @@ class Surrogate:
 PROF_CLASSES = {"leaf_assemble": 0, "lu_panel": 1, "swap_trsm": 2, "lu_update": 3,
                 "back_subst": 4, "gemm": 5, "gemm_split32": 6, "merge_gather": 7,
                 "downward": 8, "residual": 9, "upward": 10, "leaf_lu": 11, "mlp_train": 12,
-                "mlp_infer": 13, "postprocess": 14, "gemm_bf16x6": 15}
+                "mlp_infer": 13, "postprocess": 14, "gemm_bf16x6": 15,
+                "body_flux": 16}
 
 
 def mem_trim() -> int:
@@ -511,24 +512,28 @@ class Operator:
 
 
 def _build_opts(mode, stream, device_ptrs, keep_factors, root_dtn, surrogate=None,
-                judge_samples=64, judge_tol=1e-6, keep_leaf_solution=False):
+                judge_samples=64, judge_tol=1e-6, keep_leaf_solution=False,
+                keep_body_operator=False):
     return BuildOpts(mode, stream, int(device_ptrs), 1, int(keep_factors), int(root_dtn), 0.0,
                      surrogate.handle if surrogate is not None else None, int(judge_samples),
-                     float(judge_tol), int(keep_leaf_solution))
+                     float(judge_tol), int(keep_leaf_solution), int(keep_body_operator))
 
 
 def build_solution_operator(coeffs, box, nleaf, p: int, q: int, mode: int = HPS_FP64,
                             keep_factors: bool = False, root_dtn: bool = True, surrogate=None,
                             judge_samples: int = 64, judge_tol: float = 1e-6,
-                            keep_leaf_solution: bool = False) -> Operator:
+                            keep_leaf_solution: bool = False,
+                            keep_body_operator: bool = False) -> Operator:
     """Algorithm 1.  coeffs [nx*ny, 6, p*p] (c11, c12, c22, c1, c2, c at Chebyshev nodes).
-    keep_leaf_solution keeps every leaf's interior solution operator for postprocess()."""
+    keep_leaf_solution keeps every leaf's interior solution operator for postprocess();
+    keep_body_operator keeps P1 A_ii^-1 per leaf for fast solve_body()."""
     coeffs = _f64(coeffs)
     dev = _dev(coeffs)
     if surrogate is not None:
         mode = HPS_SURROGATE
     bo = _build_opts(mode, _stream(coeffs) if dev else None, dev, keep_factors, root_dtn,
-                     surrogate, judge_samples, judge_tol, keep_leaf_solution)
+                     surrogate, judge_samples, judge_tol, keep_leaf_solution,
+                     keep_body_operator)
     h = C.c_void_p()
     check(lib.hps_build_solution_operator(_ptr(coeffs), (C.c_double * 4)(*box),
                                           (C.c_int * 2)(*nleaf), p, q, C.byref(bo), C.byref(h)))

@@ -21,7 +21,7 @@ class BuildOpts(C.Structure):
                 ("keep_leaf_ops", C.c_int), ("keep_factors", C.c_int),
                 ("compute_root_dtn", C.c_int), ("pivot_tol", C.c_double),
                 ("surrogate", C.c_void_p), ("judge_samples", C.c_int), ("judge_tol", C.c_double),
-                ("keep_leaf_solution", C.c_int)]
+                ("keep_leaf_solution", C.c_int), ("keep_body_operator", C.c_int)]
 
 
 class SolveOpts(C.Structure):

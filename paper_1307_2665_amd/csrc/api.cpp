@@ -45,6 +45,7 @@ hps::BuildOptions to_build_options(const hps_build_opts* o) {
   b.keep_leaf = true;
   b.keep_factors = o->keep_factors != 0;
   b.keep_leaf_solution = o->keep_leaf_solution != 0;
+  b.keep_body = o->keep_body_operator != 0;
   b.root_dtn = o->compute_root_dtn != 0;
   b.surrogate = const_cast<hps_surrogate*>(o->surrogate);
   b.judge_samples = o->judge_samples > 0 ? o->judge_samples : 64;

@@ -29,6 +29,16 @@ void leaf_assemble_body(const double* const* cptr, const LeafDev& tab, int count
 // itself into wpart [nrhs][nl][n].
 void body_flux(const double* W, int count, int n, int m, int ld, int nrhs, const double* P1,
                double* hbuf, long long hoff, double* wpart, int nl, int leaf0, hipStream_t s);
+// Kept body operator: W = [A_ii^T | P1^T] per leaf (ld = n + m), P1 [m][n].
+void leaf_assemble_body_operator(const double* const* cptr, const LeafDev& tab, int count,
+                                 double* W, const double* P1, hipStream_t s);
+// Body-load fluxes with the kept operator: h = K g_i, Kt [nl][n][m] = K^T per
+// leaf, g [nrhs][nl][p*p]; h into the upward pass's buffer as body_flux does.
+void body_flux_kept(const double* Kt, const double* g, int nrhs, int n, int m, int p, int nl,
+                    double* hbuf, long long hoff, hipStream_t s);
+// dst[i][r * cols + c] = src[i][r * lds + c] for r < rows, c < cols, i < count.
+void copy_rows_batch(const double* const* src, double* const* dst, int count, int rows, int cols,
+                     int lds, hipStream_t s);
 // uc [nrhs][nleaf][pp]: adds wpart [nrhs][nleaf][n] at the interior nodes post_node[0..n).
 void add_particular(double* uc, const double* wpart, const int* post_node, int n, int pp,
                     int nleaf, int nrhs, hipStream_t s);

@@ -17,7 +17,9 @@ namespace hps {
 //   + c1 Dx[a][a'] d_bb' + c2 Dy[b][b'] d_aa' + c d_kk'
 // R[k][:] = -c11 G11[k] - 2 c12 G12[k] - c22 G22[k] + c1 G1[k] + c2 G2[k].
 // With a body load the system is W = [A_ii | G] instead (ld = n + nrhs): G
-// holds the load of every right-hand side at the leaf's interior nodes.
+// holds the load of every right-hand side at the leaf's interior nodes.  For
+// the kept body operator it is W = [A_ii^T | P1^T] (ld = n + m), whose
+// solution is (P1 A_ii^-1)^T.
 // ---------------------------------------------------------------------------
 constexpr int PMAX = 24;
 
@@ -25,7 +27,8 @@ __global__ void __launch_bounds__(256) k_leaf_assemble(const double* const* __re
                                                        const LeafDev tab,
                                                        double* __restrict__ W,
                                                        const double* __restrict__ body, int nrhs,
-                                                       int nl, int leaf0) {
+                                                       int nl, int leaf0,
+                                                       const double* __restrict__ P1) {
   __shared__ double Dx[PMAX * PMAX], Dy[PMAX * PMAX], Dxx[PMAX * PMAX], Dyy[PMAX * PMAX];
   __shared__ double cf[6][(PMAX - 2) * (PMAX - 2)];
   const int p = tab.p, n = tab.n, m = tab.m, pi = p - 2;
@@ -50,13 +53,17 @@ __global__ void __launch_bounds__(256) k_leaf_assemble(const double* const* __re
     const double c1 = cf[3][k], c2 = cf[4][k];
     double v;
     if (col < n) {
-      const int a = 1 + k % pi, b = 1 + k / pi;
-      const int a2 = 1 + col % pi, b2 = 1 + col / pi;
+      // A_ii[i][j] (row i carries the coefficients); transposed for the body operator.
+      const int i = P1 ? col : k, j = P1 ? k : col;
+      const int a = 1 + i % pi, b = 1 + i / pi;
+      const int a2 = 1 + j % pi, b2 = 1 + j / pi;
       const double dx = Dx[a * p + a2], dy = Dy[b * p + b2];
-      v = -2.0 * c12 * dx * dy;
-      if (b == b2) v += -c11 * Dxx[a * p + a2] + c1 * dx;
-      if (a == a2) v += -c22 * Dyy[b * p + b2] + c2 * dy;
-      if (col == k) v += cf[5][k];
+      v = -2.0 * cf[1][i] * dx * dy;
+      if (b == b2) v += -cf[0][i] * Dxx[a * p + a2] + cf[3][i] * dx;
+      if (a == a2) v += -cf[2][i] * Dyy[b * p + b2] + cf[4][i] * dy;
+      if (i == j) v += cf[5][i];
+    } else if (P1) {  // P1^T[k][col - n]
+      v = P1[(size_t)(col - n) * n + k];
     } else if (body) {  // load of right-hand side col - n at interior node k
       const int a = 1 + k % pi, b = 1 + k / pi;
       v = body[((size_t)(col - n) * nl + leaf0 + blockIdx.x) * p * p + a + p * b];
@@ -75,7 +82,16 @@ void leaf_assemble(const double* const* cptr, const LeafDev& tab, int count, dou
   HPS_REQUIRE(tab.p <= PMAX, "p too large");
   ProfScope ps(PROF_LEAF_ASSEMBLE, s, 0, 8.0 * count * ((double)tab.n * (tab.n + tab.m) + 6.0 * tab.p * tab.p));
   hipLaunchKernelGGL(k_leaf_assemble, dim3(count), dim3(256), 0, s, cptr, tab, W, nullptr, 0, 0,
-                     0);
+                     0, nullptr);
+}
+
+void leaf_assemble_body_operator(const double* const* cptr, const LeafDev& tab, int count,
+                                 double* W, const double* P1, hipStream_t s) {
+  HPS_REQUIRE(tab.p <= PMAX, "p too large");
+  ProfScope ps(PROF_LEAF_ASSEMBLE, s, 0,
+               8.0 * count * ((double)tab.n * (tab.n + tab.m) + 6.0 * tab.p * tab.p));
+  hipLaunchKernelGGL(k_leaf_assemble, dim3(count), dim3(256), 0, s, cptr, tab, W, nullptr, 0, 0,
+                     0, P1);
 }
 
 void leaf_assemble_body(const double* const* cptr, const LeafDev& tab, int count, double* W,
@@ -84,7 +100,7 @@ void leaf_assemble_body(const double* const* cptr, const LeafDev& tab, int count
   ProfScope ps(PROF_LEAF_ASSEMBLE, s, 0,
                8.0 * count * ((double)tab.n * (tab.n + nrhs) + 6.0 * tab.p * tab.p));
   hipLaunchKernelGGL(k_leaf_assemble, dim3(count), dim3(256), 0, s, cptr, tab, W, body, nrhs, nl,
-                     leaf0);
+                     leaf0, nullptr);
 }
 
 // Body loads: for leaves leaf0 .. leaf0 + count - 1, X = W + n (ld) holds the
@@ -116,6 +132,59 @@ void body_flux(const double* W, int count, int n, int m, int ld, int nrhs, const
   if (count <= 0) return;
   hipLaunchKernelGGL(k_body_flux, dim3(count), dim3(256), 0, s, W, n, m, ld, nrhs, P1, hbuf, hoff,
                      wpart, nl, leaf0);
+}
+
+// Body loads with the kept operator: h = K g_i for every leaf and right-hand
+// side, K^T = Kt [nl][n][m] (lanes along the flux rows read K^T row by row),
+// g [nrhs][nl][p*p] read at the interior nodes.
+__global__ void __launch_bounds__(256) k_body_flux_kept(const double* __restrict__ Kt,
+                                                        const double* __restrict__ g, int nrhs,
+                                                        int n, int m, int p, int nl,
+                                                        double* __restrict__ hbuf,
+                                                        long long hoff) {
+  extern __shared__ double gi[];  // [nrhs chunk][n]
+  const int leaf = blockIdx.x, pi = p - 2, pp = p * p;
+  const double* K = Kt + (size_t)leaf * n * m;
+  const int kc = max(1, min(nrhs, 4096 / n));
+  for (int k0 = 0; k0 < nrhs; k0 += kc) {
+    const int nk = min(kc, nrhs - k0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nk * n; e += blockDim.x) {
+      const int k = e / n, c = e % n;
+      gi[e] = g[((size_t)(k0 + k) * nl + leaf) * pp + (1 + c % pi) + p * (1 + c / pi)];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nk * m; e += blockDim.x) {
+      const int k = e / m, r = e % m;
+      double acc = 0.0;
+      for (int c = 0; c < n; ++c) acc = fma(K[(size_t)c * m + r], gi[k * n + c], acc);
+      hbuf[(size_t)(hoff + (long long)leaf * m) * nrhs + (size_t)(k0 + k) * m + r] = acc;
+    }
+  }
+}
+
+void body_flux_kept(const double* Kt, const double* g, int nrhs, int n, int m, int p, int nl,
+                    double* hbuf, long long hoff, hipStream_t s) {
+  const int kc = std::max(1, std::min(nrhs, 4096 / n));
+  const double cells = (double)nl * n * m;
+  ProfScope ps(PROF_BODY_FLUX, s, 2.0 * nrhs * cells,
+               8.0 * (cells + (double)nrhs * nl * (n + m)));
+  hipLaunchKernelGGL(k_body_flux_kept, dim3(nl), dim3(256), sizeof(double) * kc * n, s, Kt, g,
+                     nrhs, n, m, p, nl, hbuf, hoff);
+}
+
+__global__ void __launch_bounds__(256) k_copy_rows(const double* const* src, double* const* dst,
+                                                   int rows, int cols, int lds) {
+  const double* a = src[blockIdx.x];
+  double* b = dst[blockIdx.x];
+  for (int e = threadIdx.x; e < rows * cols; e += blockDim.x)
+    b[e] = a[(size_t)(e / cols) * lds + e % cols];
+}
+
+void copy_rows_batch(const double* const* src, double* const* dst, int count, int rows, int cols,
+                     int lds, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_copy_rows, dim3(count), dim3(256), 0, s, src, dst, rows, cols, lds);
 }
 
 // uc[k][leaf][post_node[i]] += wpart[k][leaf][i] for the n interior rows.

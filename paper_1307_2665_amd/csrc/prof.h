@@ -24,7 +24,8 @@ enum ProfClass {
   PROF_MLP_INFER = 13,
   PROF_POSTPROCESS = 14,
   PROF_GEMM_BF16X6 = 15,
-  PROF_NCLASS = 16
+  PROF_BODY_FLUX = 16,
+  PROF_NCLASS = 24
 };
 
 bool prof_on(int cls);

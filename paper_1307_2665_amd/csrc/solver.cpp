@@ -244,6 +244,7 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
   op->surrogate = o.surrogate;
   op->judge_samples = o.judge_samples;
   op->judge_tol = o.judge_tol;
+  if (o.keep_body) op->opt.keep_factors = true;
   if (o.mode == HPS_MIXED_SPLIT32 || o.mode == HPS_MIXED_BF16X6) {
     op->opt.keep_factors = true;
     op->opt.keep_leaf = true;
@@ -281,6 +282,7 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
                 "keep_leaf_solution needs the FP64 leaf build (not surrogate mode)");
     op->leafZ = op->mem.alloc<double>(nl * (size_t)(p - 2) * (p - 2) * m);
   }
+  if (o.keep_body) op->leafK = op->mem.alloc<double>(nl * (size_t)(p - 2) * (p - 2) * m);
 
   // W (augmented system, later S and M^-1) and pivots are kept for every merge;
   // Q is kept only when the upward pass is wanted, else one level of scratch.
@@ -517,6 +519,45 @@ static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hip
   }
 }
 
+// Kept body operator (keep_body_operator): K^T = A_ii^-T P1^T for every leaf
+// by the batched dense solver on [A_ii^T | P1^T], copied to op->leafK as
+// [n][m].  A body-load solve then needs h = K g per leaf only.
+static void body_operator_stage(hps_op* op, DeviceMem& tmp, hipStream_t s, int* dstatus) {
+  const LeafPlan& LP = op->leaf();
+  const int p = op->p, n = (p - 2) * (p - 2), m = 4 * op->q, nl = op->nx * op->ny, ld = n + m;
+  HPS_REQUIRE(n <= max_solve_rows(), "leaf too large for the dense solver");
+  LeafDev tab{LP.dDx, LP.dDy, LP.dDxx, LP.dDyy, LP.dG, p, n, m, 0};
+  const size_t per = (size_t)n * ld * sizeof(double) + (size_t)n * sizeof(int);
+  const int CH = (int)std::max<size_t>(1, std::min<size_t>(nl, ((size_t)2 << 30) / per));
+  double* Wslab = tmp.alloc<double>((size_t)CH * n * ld);
+  int* pslab = tmp.alloc<int>((size_t)CH * n);
+  const double** dcp = tmp.alloc<const double*>(CH);
+  SolveDesc* dsd = tmp.alloc<SolveDesc>(CH);
+  const double** dsrc = tmp.alloc<const double*>(CH);
+  double** ddst = tmp.alloc<double*>(CH);
+  for (int c0 = 0; c0 < nl; c0 += CH) {
+    const int cnt = std::min(CH, nl - c0);
+    std::vector<const double*> cp(cnt), src(cnt);
+    std::vector<double*> dst(cnt);
+    std::vector<SolveDesc> sd(cnt);
+    for (int i = 0; i < cnt; ++i) {
+      double* Wl = Wslab + (size_t)i * n * ld;
+      cp[i] = op->coeffs + (size_t)(c0 + i) * 6 * p * p;
+      sd[i] = SolveDesc{Wl, pslab + (size_t)i * n, Wl + n, n, m, ld, ld, -(c0 + i + 1), 0};
+      src[i] = Wl + n;
+      dst[i] = op->leafK + (size_t)(c0 + i) * n * m;
+    }
+    HPS_HIP(hipMemcpyAsync(dcp, cp.data(), cnt * sizeof(void*), hipMemcpyHostToDevice, s));
+    HPS_HIP(hipMemcpyAsync(dsd, sd.data(), cnt * sizeof(SolveDesc), hipMemcpyHostToDevice, s));
+    HPS_HIP(hipMemcpyAsync(dsrc, src.data(), cnt * sizeof(void*), hipMemcpyHostToDevice, s));
+    HPS_HIP(hipMemcpyAsync(ddst, dst.data(), cnt * sizeof(void*), hipMemcpyHostToDevice, s));
+    leaf_assemble_body_operator(dcp, tab, cnt, Wslab, LP.dP1, s);
+    batched_solve(dsd, sd, dstatus, s, 32);
+    copy_rows_batch(dsrc, ddst, cnt, n, m, ld, s);
+    HPS_HIP(hipStreamSynchronize(s));  // host descriptor vectors are reused next chunk
+  }
+}
+
 // Leaf stage of a surrogate operator: inference for every leaf, then the judge
 // re-solves a seeded sample of leaves plus every leaf whose coefficients leave
 // the training ranges with the FP64 leaf solver; judged leaves above the
@@ -623,6 +664,8 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
                           op->leafZ ? op->leafZ + (size_t)l * op->leaf().lt.n * m : nullptr});
   }
   for (auto& kv : groups) run_leaf_group(kv.second, tmp, s, dstatus, panel);
+  for (hps_op* op : ops)
+    if (op->leafK) body_operator_stage(op, tmp, s, dstatus);
 
   // Merges, deepest level first; all operators' merges at one depth together.
   int maxd = 0;
@@ -1024,27 +1067,26 @@ void solve_with_sources_device(hps_op* op, const double* f, const double* src, i
   HPS_HIP(hipFreeAsync(z, s));
 }
 
-// Body loads (A u = g).  Leaf particular solutions by the batched dense
-// solver on [A_ii | G] (G: the load of every right-hand side at the leaf's
-// interior nodes); their fluxes P1 w_i enter the upward pass as the leaves'
-// h (no interface sources); Algorithm 2 then adds the resulting z.  uc adds
-// w_i to the post-processed grids.  Runs on the per-right-hand-side passes.
-void body_solve_device(hps_op* op, const double* f, const double* g, int nrhs, double* u,
-                       double* uc, hipStream_t s) {
-  HPS_REQUIRE(op->opt.keep_factors, "body loads need an operator built with keep_factors");
-  HPS_REQUIRE(!uc || op->leafZ, "grid values need an operator built with keep_leaf_solution");
-  HPS_REQUIRE(nrhs >= 1, "bad right-hand-side count");
+// Body loads (A u = g).  The leaves' particular fluxes h = P1 A_ii^-1 g_i
+// either come from the kept body operator K = P1 A_ii^-1 (one batched
+// product) or from leaf particular solutions by the batched dense solver on
+// [A_ii | G] (G: the load of every right-hand side at the leaf's interior
+// nodes), which also give w_i for the grid values.  h enters the
+// per-right-hand-side upward pass as the leaves' h (no interface sources);
+// Algorithm 2 then adds the resulting z.  uc adds w_i to the post-processed
+// grids.
+
+// Particular solutions of every leaf: fluxes into h (unit offset h_units +
+// leaf m), and w_i into wpart [nrhs][nl][n] when wpart is not null.
+static void body_particular(hps_op* op, const double* g, int nrhs, double* h, double* wpart,
+                            hipStream_t s) {
   const LeafPlan& LP = op->leaf();
-  const int p = op->p, q = op->q, n = (p - 2) * (p - 2), m = 4 * q, nl = op->nx * op->ny;
-  const int ld = n + nrhs, N = op->tree().N;
-  HPS_REQUIRE(n <= max_solve_rows(), "leaf too large for the dense solver");
+  const int p = op->p, n = (p - 2) * (p - 2), m = 4 * op->q, nl = op->nx * op->ny;
+  const int ld = n + nrhs;
   LeafDev tab{LP.dDx, LP.dDy, LP.dDxx, LP.dDyy, LP.dG, p, n, m, 0};
   const size_t per = (size_t)n * ld * sizeof(double) + (size_t)n * sizeof(int);
   const int CH = (int)std::max<size_t>(1, std::min<size_t>(nl, ((size_t)2 << 30) / per));
   AsyncBuf W((size_t)CH * n * ld, s), piv(((size_t)CH * n + 1) / 2 + 1, s);
-  AsyncBuf h((size_t)(op->h_units + (long long)nl * m) * nrhs, s);
-  AsyncBuf z((size_t)std::max<long long>(1, op->z_units) * nrhs, s);
-  AsyncBuf wpart(uc ? (size_t)nrhs * nl * n : 1, s);
   AsyncBuf desc(((size_t)CH * (sizeof(SolveDesc) + sizeof(void*)) + 7) / 8 + 4, s);
   const double** dcp = (const double**)desc.p;
   SolveDesc* dsd = (SolveDesc*)(dcp + CH);
@@ -1063,8 +1105,7 @@ void body_solve_device(hps_op* op, const double* f, const double* g, int nrhs, d
     HPS_HIP(hipMemcpyAsync(dsd, sd.data(), cnt * sizeof(SolveDesc), hipMemcpyHostToDevice, s));
     leaf_assemble_body(dcp, tab, cnt, W.p, g, nrhs, nl, c0, s);
     batched_solve(dsd, sd, dstatus, s, 32);
-    body_flux(W.p, cnt, n, m, ld, nrhs, LP.dP1, h.p, op->h_units, uc ? wpart.p : nullptr, nl, c0,
-              s);
+    body_flux(W.p, cnt, n, m, ld, nrhs, LP.dP1, h, op->h_units, wpart, nl, c0, s);
     HPS_HIP(hipStreamSynchronize(s));  // host descriptor vectors are reused next chunk
   }
   int st[4];
@@ -1072,6 +1113,24 @@ void body_solve_device(hps_op* op, const double* f, const double* g, int nrhs, d
   HPS_HIP(hipStreamSynchronize(s));
   if (st[0]) throw Error(HPS_ESINGULAR, "zero or non-finite pivot in the particular solve of leaf " +
                                             std::to_string(-st[1] - 1));
+}
+
+void body_solve_device(hps_op* op, const double* f, const double* g, int nrhs, double* u,
+                       double* uc, hipStream_t s) {
+  HPS_REQUIRE(op->opt.keep_factors, "body loads need an operator built with keep_factors");
+  HPS_REQUIRE(!uc || op->leafZ, "grid values need an operator built with keep_leaf_solution");
+  HPS_REQUIRE(nrhs >= 1, "bad right-hand-side count");
+  const LeafPlan& LP = op->leaf();
+  const int p = op->p, n = (p - 2) * (p - 2), m = 4 * op->q, nl = op->nx * op->ny;
+  const int N = op->tree().N;
+  HPS_REQUIRE(n <= max_solve_rows(), "leaf too large for the dense solver");
+  AsyncBuf h((size_t)(op->h_units + (long long)nl * m) * nrhs, s);
+  AsyncBuf z((size_t)std::max<long long>(1, op->z_units) * nrhs, s);
+  AsyncBuf wpart(uc ? (size_t)nrhs * nl * n : 1, s);
+  if (op->leafK && !uc)
+    body_flux_kept(op->leafK, g, nrhs, n, m, p, nl, h.p, op->h_units, s);
+  else
+    body_particular(op, g, nrhs, h.p, uc ? wpart.p : nullptr, s);
   for (int d = (int)op->levels.size() - 1; d >= 0; --d) {
     const LevelPlan& L = op->levels[d];
     if (L.h.empty()) continue;

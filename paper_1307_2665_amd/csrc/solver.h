@@ -102,6 +102,7 @@ struct BuildOptions {
   bool keep_leaf = true;
   bool keep_factors = false;
   bool keep_leaf_solution = false;
+  bool keep_body = false;
   bool root_dtn = true;
   int panel = 32;
 };
@@ -119,6 +120,7 @@ struct hps_op {
                                     // keep_factors), else the caller's, read by the build only
   double* leafT = nullptr;          // [nleaf][4q][4q]
   double* leafZ = nullptr;          // [nleaf][4q][(p-2)^2]: Z^T, Z = A_ii^-1 A_ie L1, or null
+  double* leafK = nullptr;          // [nleaf][(p-2)^2][4q]: K^T, K = P1 A_ii^-1, or null
   double* Wk = nullptr;             // augmented systems; S (and M^-1) live inside them
   double* Q = nullptr;
   int* piv = nullptr;

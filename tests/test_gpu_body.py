@@ -1,8 +1,9 @@
 """Body loads A u = g through the C ABI against the CPU oracle.
 
 hps_solve_body solves every leaf's particular problem (A_ii w_i = g_i) with
-the batched dense solver, carries the particular fluxes up the merges with the
-interface-source recursion and runs Algorithm 2 with the resulting terms.
+the batched dense solver, or applies the kept K = P1 A_ii^-1, carries the
+particular fluxes up the merges with the interface-source recursion and runs
+Algorithm 2 with the resulting terms.
 Each case compares u at the Gauss nodes with the oracle's body_solve and the
 grid values with body_cheb_values (1e-10, relative max-norm per right-hand
 side).  Counts of right-hand sides leave ragged groups of the row passes.
@@ -105,6 +106,31 @@ def test_body_many_rhs_and_zero_load(H, gpu):
     _check("u", u, u_o)
     u0 = op.solve_body(_t(f[:2], gpu), _t(np.zeros_like(g[:2]), gpu)).cpu().numpy()
     assert rel_err(u0, op.solve(_t(f[:2], gpu)).cpu().numpy()) < 1e-13
+
+
+@pytest.mark.parametrize("maker,nleaf,p,q,nrhs", [
+    (hi.convdiff, (6, 5), 10, 8, 1),
+    (hi.helmholtz_bump, (4, 4), 12, 10, 5),
+    (hi.manufactured_variable, (3, 2), 21, 19, 2),
+])
+def test_body_kept_operator(H, gpu, maker, nleaf, p, q, nrhs):
+    """keep_body_operator: the particular fluxes come from K = P1 A_ii^-1 kept by
+    the build (one batched product per solve); u matches the oracle and the
+    refactoring path; asking for grid values still takes the refactoring path."""
+    say(f"body load, kept operator, {maker.__name__} {nleaf} p{p} q{q} nrhs {nrhs}")
+    pr = maker(nleaf=nleaf, p=p, q=q)
+    C, _ = library_inputs(pr)
+    op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, p, q, keep_body_operator=True,
+                                   keep_leaf_solution=True)
+    ref = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, p, q, keep_factors=True)
+    f = np.random.default_rng(nrhs + 40).standard_normal((nrhs, op.n_bdry))
+    g = _loads(H.cheb_nodes(pr.box, pr.nleaf, pr.p), nrhs, 600)
+    u = op.solve_body(_t(f, gpu), _t(g, gpu)).cpu().numpy()
+    u_o, uc_o = _oracle(pr, f, nrhs, 600)
+    _check("u", u, u_o)
+    assert rel_err(u, ref.solve_body(_t(f, gpu), _t(g, gpu)).cpu().numpy()) < 1e-12
+    _, uc = op.solve_body(_t(f, gpu), _t(g, gpu), grid=True)
+    _check("grid", uc.cpu().numpy(), uc_o)
 
 
 def test_body_needs_kept_factors(H, gpu):
