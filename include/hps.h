@@ -208,7 +208,10 @@ hps_status hps_postprocess(const hps_op* op, const double* u, int nrhs, double* 
    nodes (only interior nodes are used); u [nrhs][N] at the Gauss nodes; uc
    (may be NULL) [nrhs][nx*ny][p*p], the solution on every leaf grid.  Needs
    an operator built with keep_factors (and keep_leaf_solution for uc),
-   HPS_EINVAL otherwise; HPS_ESINGULAR if a leaf's A_ii is singular.  Uses
+   HPS_EINVAL otherwise; HPS_ESINGULAR if a leaf's A_ii is singular.  With
+   keep_body_operator and uc NULL the particular fluxes are one batched
+   product with the kept P1 A_ii^-1; otherwise every call eliminates
+   [A_ii | g] for all leaves (the particular solutions w_i are needed for uc).  Uses
    opts->stream and opts->device_ptrs (f, g, u, uc all host or all device);
    the refinement fields are ignored.  Exact up to rounding for the FP64
    operator; a mixed-precision operator gives its unrefined accuracy. */
