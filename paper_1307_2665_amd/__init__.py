@@ -541,7 +541,8 @@ def build_solution_operator(coeffs, box, nleaf, p: int, q: int, mode: int = HPS_
 
 
 def build_batch(problems: Sequence[dict], mode: int = HPS_FP64, keep_factors: bool = False,
-                root_dtn: bool = True, keep_leaf_solution: bool = False) -> List[Operator]:
+                root_dtn: bool = True, keep_leaf_solution: bool = False,
+                keep_body_operator: bool = False) -> List[Operator]:
     """Heterogeneous batch; problems are dicts with coeffs (device), box, nleaf, p, q."""
     arr = (Problem * len(problems))()
     keep = []
@@ -555,7 +556,8 @@ def build_batch(problems: Sequence[dict], mode: int = HPS_FP64, keep_factors: bo
         arr[i].p = pr["p"]
         arr[i].q = pr["q"]
     bo = _build_opts(mode, _stream(keep[0]), 1, keep_factors, root_dtn,
-                     keep_leaf_solution=keep_leaf_solution)
+                     keep_leaf_solution=keep_leaf_solution,
+                     keep_body_operator=keep_body_operator)
     hs = (C.c_void_p * len(problems))()
     check(lib.hps_build_batch(arr, len(problems), C.byref(bo), hs))
     return [Operator(C.c_void_p(h)) for h in hs]

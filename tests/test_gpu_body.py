@@ -133,6 +133,26 @@ def test_body_kept_operator(H, gpu, maker, nleaf, p, q, nrhs):
     _check("grid", uc.cpu().numpy(), uc_o)
 
 
+def test_body_batch_kept_operator(H, gpu):
+    """A heterogeneous batch built with keep_body_operator (one leaf launch and one
+    body-operator stage per operator; the caller's coefficient tensors are freed
+    before the solves): every operator's body solve matches the oracle."""
+    say("body load batch: 3 uneven problems, kept operators")
+    probs = [hi.convdiff(nleaf=(4, 3), p=10, q=8), hi.convdiff(nleaf=(5, 5), p=12, q=10),
+             hi.helmholtz_bump(nleaf=(3, 4), p=12, q=10)]
+    ops = H.build_batch([dict(coeffs=_t(library_inputs(pr)[0], gpu), box=pr.box, nleaf=pr.nleaf,
+                              p=pr.p, q=pr.q) for pr in probs], keep_body_operator=True)
+    import torch
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(9)
+    for pr, op, k in zip(probs, ops, (1, 3, 2)):
+        f = rng.standard_normal((k, op.n_bdry))
+        g = _loads(H.cheb_nodes(pr.box, pr.nleaf, pr.p), k, 800)
+        u = op.solve_body(_t(f, gpu), _t(g, gpu)).cpu().numpy()
+        u_o, _ = _oracle(pr, f, k, 800)
+        _check(f"{pr.name} {pr.nleaf} u", u, u_o)
+
+
 def test_body_needs_kept_factors(H, gpu):
     pr = hi.convdiff(nleaf=(2, 2), p=10, q=8)
     C, f = library_inputs(pr)
