@@ -135,42 +135,79 @@ void body_flux(const double* W, int count, int n, int m, int ld, int nrhs, const
 }
 
 // Body loads with the kept operator: h = K g_i for every leaf and right-hand
-// side, K^T = Kt [nl][n][m] (lanes along the flux rows read K^T row by row),
-// g [nrhs][nl][p*p] read at the interior nodes.
+// side, K^T = Kt [nl][n][m], g [nrhs][nl][p*p] read at the interior nodes.
+// One workgroup per leaf: wave w takes a quarter of the interior nodes c,
+// lane r the flux row r (64 rows per pass), so each step reads one row of
+// K^T (up to 64 consecutive doubles) across the wave, eight rows in flight
+// per lane; the four partial sums meet in LDS in a fixed order.  Up to BRC
+// right-hand sides share each pass over K.
+constexpr int BRC = 4;
+
 __global__ void __launch_bounds__(256) k_body_flux_kept(const double* __restrict__ Kt,
                                                         const double* __restrict__ g, int nrhs,
                                                         int n, int m, int p, int nl,
                                                         double* __restrict__ hbuf,
                                                         long long hoff) {
-  extern __shared__ double gi[];  // [nrhs chunk][n]
+  extern __shared__ double sh[];  // gi [BRC][n], then part [4][BRC][64]
+  double* gi = sh;
+  double* part = sh + BRC * n;
   const int leaf = blockIdx.x, pi = p - 2, pp = p * p;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const double* K = Kt + (size_t)leaf * n * m;
-  const int kc = max(1, min(nrhs, 4096 / n));
-  for (int k0 = 0; k0 < nrhs; k0 += kc) {
-    const int nk = min(kc, nrhs - k0);
+  const int q4 = (n + 3) / 4, c0 = wid * q4, c1 = min(n, c0 + q4);
+  for (int k0 = 0; k0 < nrhs; k0 += BRC) {
+    const int nk = min(BRC, nrhs - k0);
     __syncthreads();
     for (int e = threadIdx.x; e < nk * n; e += blockDim.x) {
       const int k = e / n, c = e % n;
       gi[e] = g[((size_t)(k0 + k) * nl + leaf) * pp + (1 + c % pi) + p * (1 + c / pi)];
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < nk * m; e += blockDim.x) {
-      const int k = e / m, r = e % m;
-      double acc = 0.0;
-      for (int c = 0; c < n; ++c) acc = fma(K[(size_t)c * m + r], gi[k * n + c], acc);
-      hbuf[(size_t)(hoff + (long long)leaf * m) * nrhs + (size_t)(k0 + k) * m + r] = acc;
+    for (int rb = 0; rb < m; rb += 64) {
+      __syncthreads();
+      const int r = rb + lane < m ? rb + lane : m - 1;
+      double acc[BRC];
+#pragma unroll
+      for (int k = 0; k < BRC; ++k) acc[k] = 0.0;
+      int c = c0;
+      for (; c + 8 <= c1; c += 8) {
+        double kv[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) kv[t] = K[(size_t)(c + t) * m + r];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+#pragma unroll
+          for (int k = 0; k < BRC; ++k)
+            if (k < nk) acc[k] = fma(kv[t], gi[k * n + c + t], acc[k]);
+      }
+      for (; c < c1; ++c) {
+        const double kv = K[(size_t)c * m + r];
+#pragma unroll
+        for (int k = 0; k < BRC; ++k)
+          if (k < nk) acc[k] = fma(kv, gi[k * n + c], acc[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < BRC; ++k) part[(wid * BRC + k) * 64 + lane] = acc[k];
+      __syncthreads();
+      const int mr = min(64, m - rb);
+      for (int e = threadIdx.x; e < nk * mr; e += blockDim.x) {
+        const int k = e / mr, rr = e % mr;
+        const double* ps = part + k * 64 + rr;
+        const double v = ((ps[0] + ps[BRC * 64]) + ps[2 * BRC * 64]) + ps[3 * BRC * 64];
+        const size_t o = (size_t)(hoff + (long long)leaf * m) * nrhs + (size_t)(k0 + k) * m;
+        hbuf[o + rb + rr] = v;
+      }
     }
   }
 }
 
 void body_flux_kept(const double* Kt, const double* g, int nrhs, int n, int m, int p, int nl,
                     double* hbuf, long long hoff, hipStream_t s) {
-  const int kc = std::max(1, std::min(nrhs, 4096 / n));
   const double cells = (double)nl * n * m;
   ProfScope ps(PROF_BODY_FLUX, s, 2.0 * nrhs * cells,
                8.0 * (cells + (double)nrhs * nl * (n + m)));
-  hipLaunchKernelGGL(k_body_flux_kept, dim3(nl), dim3(256), sizeof(double) * kc * n, s, Kt, g,
-                     nrhs, n, m, p, nl, hbuf, hoff);
+  const size_t lds = sizeof(double) * (BRC * n + 4 * BRC * 64);
+  hipLaunchKernelGGL(k_body_flux_kept, dim3(nl), dim3(256), lds, s, Kt, g, nrhs, n, m, p, nl,
+                     hbuf, hoff);
 }
 
 __global__ void __launch_bounds__(256) k_copy_rows(const double* const* src, double* const* dst,
