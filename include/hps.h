@@ -354,6 +354,10 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
      (-1: the default, 256; else at least 16), summed in a fixed order;
    "post_rows": Chebyshev-grid rows per lane in hps_postprocess (1, 2 or 4;
      -1: the default, 4 from 16 right-hand sides on, else 2);
+   "gj_lookahead": 1 lets the merge solver update the next panel's columns
+     first and the remaining columns on a second stream while the next panel
+     is factored; 0 (default, also -1) runs every step on the caller's stream
+     (faster on MI355X: the side stream's update delays the next panel);
    "bf16x6_min_k": in HPS_MIXED_BF16X6 builds, merge levels whose longest
      contraction (interface length m3) is below this run their Schur
      products in FP64 (-1: the default, 384; 0: BF16 on every level).

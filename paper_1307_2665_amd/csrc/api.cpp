@@ -489,6 +489,9 @@ hps_status hps_tune_set(const char* knob, int value) {
     } else if (k == "split_min_chunk") {
       HPS_REQUIRE(value == -1 || value >= 16, "split_min_chunk must be -1 or >= 16");
       hps::set_split_min_chunk(value < 0 ? 256 : value);
+    } else if (k == "gj_lookahead") {
+      HPS_REQUIRE(value >= -1 && value <= 1, "gj_lookahead must be -1, 0 or 1");
+      hps::set_gj_lookahead(value == 1);
     } else if (k == "bf16x6_min_k") {
       HPS_REQUIRE(value >= -1, "bf16x6_min_k must be >= -1");
       hps::set_bf16x6_min_k(value);

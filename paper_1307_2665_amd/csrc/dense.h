@@ -36,6 +36,11 @@ void batched_solve_v(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_de
 void grouped_gemm_v(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, hipStream_t stream,
                     int variant, int prec);
 
+// Look-ahead in the block Gauss-Jordan solver (default off): each step updates
+// the next panel's columns first, and the remaining columns on a side stream
+// while the next panel is factored.  Measured slower on config 2: the side
+// stream's update fills the CUs, and the next panel's lone workgroup waits.
+void set_gj_lookahead(bool on);
 void dense_init();
 int max_solve_rows();
 

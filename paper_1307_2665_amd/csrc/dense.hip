@@ -12,6 +12,8 @@
 #include "tune.h"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <vector>
 
 namespace hps {
@@ -338,7 +340,8 @@ constexpr int TBM = 64, TBN = 64, TBK = 16;  // tile of the split-FP32 kernel
 // the rest cover rows [k0+kb, n).
 template <int BM, int BN, int BK, int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN) k_gj_update(const SolveDesc* __restrict__ descs,
-                                                           int k0, int nb) {
+                                                           int k0, int nb, int coff_lo,
+                                                           int coff_hi) {
   __shared__ double sm[GemmTile<BM, BN, BK, WM, WN>::SMEM];
   const SolveDesc d = descs[blockIdx.z];
   if (k0 >= d.n) return;
@@ -352,8 +355,9 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gj_update(const SolveDesc* __r
     r0 = k0 + kb + (blockIdx.y - ta) * BM;
     M = min(BM, d.n - r0);
   }
-  const int c0 = k0 + kb + blockIdx.x * BN;
-  const int N = min(BN, d.n + d.m - c0);
+  // Columns k0 + kb + [coff_lo, coff_hi) of this system (clipped to its width).
+  const int c0 = k0 + kb + coff_lo + blockIdx.x * BN;
+  const int N = min(BN, min(d.n + d.m, k0 + kb + coff_hi) - c0);
   if (M <= 0 || N <= 0) return;
   const size_t ld = d.ld;
   gemm_tile<BM, BN, BK, WM, WN>(d.W + (size_t)r0 * ld + k0, d.ld, d.W + (size_t)k0 * ld + c0,
@@ -765,14 +769,17 @@ static void launch_panel(const SolveDesc* d_desc, int np, int k0, int rows, int 
 int max_solve_rows() { return 3072; }
 
 // Launch of one Gauss-Jordan update with tile variant v.
+// Updates columns k0 + kb + [coff_lo, coff_lo + ncols) of every system.
 static void launch_update(int v, const SolveDesc* d_desc, int np, int k0, int nb, int nmax,
-                          int rest, hipStream_t s) {
+                          int coff_lo, int ncols, hipStream_t s) {
+  if (ncols <= 0) return;
+  const int coff_hi = coff_lo + ncols;
 #define HPS_UPD(BM, BN, BK, WM, WN)                                                        \
   {                                                                                         \
     const int ty = (k0 + BM - 1) / BM + (std::max(0, nmax - k0 - nb) + BM - 1) / BM;       \
     if (ty > 0)                                                                             \
-      hipLaunchKernelGGL((k_gj_update<BM, BN, BK, WM, WN>), dim3((rest + BN - 1) / BN, ty, np), \
-                         dim3(64 * WM * WN), 0, s, d_desc, k0, nb);                         \
+      hipLaunchKernelGGL((k_gj_update<BM, BN, BK, WM, WN>), dim3((ncols + BN - 1) / BN, ty, np), \
+                         dim3(64 * WM * WN), 0, s, d_desc, k0, nb, coff_lo, coff_hi);       \
     return;                                                                                 \
   }
   switch (v) {
@@ -785,6 +792,28 @@ static void launch_update(int v, const SolveDesc* d_desc, int np, int k0, int nb
   }
 #undef HPS_UPD
 }
+
+// Side stream and events of the look-ahead, one set per device (default priority).
+struct LookAhead {
+  hipStream_t side = nullptr;
+  hipEvent_t ready = nullptr, done = nullptr;
+};
+static const LookAhead& look_ahead() {
+  static std::mutex mu;
+  static std::map<int, LookAhead> per_device;
+  int dev = 0;
+  HPS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  LookAhead& la = per_device[dev];
+  if (!la.side) {
+    HPS_HIP(hipStreamCreateWithFlags(&la.side, hipStreamNonBlocking));
+    HPS_HIP(hipEventCreateWithFlags(&la.ready, hipEventDisableTiming));
+    HPS_HIP(hipEventCreateWithFlags(&la.done, hipEventDisableTiming));
+  }
+  return la;
+}
+static bool g_gj_lookahead = false;
+void set_gj_lookahead(bool on) { g_gj_lookahead = on; }
 
 void batched_solve_v(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc, int* d_status,
                      hipStream_t stream, int gj_variant) {
@@ -799,6 +828,9 @@ void batched_solve_v(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_de
   const int np = (int)h_desc.size();
   const int upd = gj_variant >= 0 ? gj_variant / 4 : 0;
   const int tb = TRSM_BLOCKS[gj_variant >= 0 ? std::min(gj_variant % 4, 2) : 0];
+  const bool look = g_gj_lookahead && nmax > nb;
+  const LookAhead& la = look ? look_ahead() : LookAhead{};
+  bool pending = false;
   for (int k0 = 0; k0 < nmax; k0 += nb) {
     double fp = 0, ft = 0, fu = 0;
     for (auto& d : h_desc) {
@@ -815,6 +847,10 @@ void batched_solve_v(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_de
     }
     const int rest = wmax - k0 - std::min(nb, rows);
     if (rest <= 0) continue;
+    if (pending) {  // the previous step's side-stream update must finish before these row moves
+      HPS_HIP(hipStreamWaitEvent(stream, la.done, 0));
+      pending = false;
+    }
     {
       ProfScope ps(PROF_SWAP_TRSM, stream, ft, 0);
       dim3 g((rest + tb - 1) / tb, np);
@@ -823,11 +859,27 @@ void batched_solve_v(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_de
       else
         hipLaunchKernelGGL((k_gj_swap_trsm<16>), g, dim3(tb), 0, stream, d_desc, k0);
     }
+    if (!look) {
+      ProfScope ps(PROF_LU_UPDATE, stream, fu, 0);
+      launch_update(upd, d_desc, np, k0, nb, nmax, 0, rest, stream);
+      continue;
+    }
+    // Look-ahead: the next panel's columns are updated on the caller's
+    // stream, so the next panel can start while the side stream updates the
+    // remaining columns; the next step's row moves wait for that update.
     {
       ProfScope ps(PROF_LU_UPDATE, stream, fu, 0);
-      launch_update(upd, d_desc, np, k0, nb, nmax, rest, stream);
+      launch_update(upd, d_desc, np, k0, nb, nmax, 0, std::min(nb, rest), stream);
+      if (rest > nb) {
+        HPS_HIP(hipEventRecord(la.ready, stream));
+        HPS_HIP(hipStreamWaitEvent(la.side, la.ready, 0));
+        launch_update(upd, d_desc, np, k0, nb, nmax, nb, rest - nb, la.side);
+        HPS_HIP(hipEventRecord(la.done, la.side));
+        pending = true;
+      }
     }
   }
+  if (pending) HPS_HIP(hipStreamWaitEvent(stream, la.done, 0));
 }
 
 void batched_solve(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc, int* d_status,
