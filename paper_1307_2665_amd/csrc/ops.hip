@@ -384,6 +384,30 @@ struct RowUpH {
   }
 };
 
+// Dense y[k] = A x[k]: A [rows][cols] row-major, x [nrhs][cols], y [nrhs][rows]
+// (the root DtN apply).  One "merge" (blockIdx.y = 0).
+struct RowMat {
+  struct Args {
+    const double* A;
+    int rows, cols, nrhs;
+    const double* x;
+    double* y;
+  };
+  const double* A;
+  int nr, nc, nrhs;
+  const double* x;
+  double* y;
+  __device__ RowMat(const Args& a, int) : A(a.A), nr(a.rows), nc(a.cols), nrhs(a.nrhs), x(a.x),
+                                           y(a.y) {}
+  __device__ int rows() const { return nr; }
+  __device__ int cols() const { return nc; }
+  __device__ const double* row(int r) const { return A + (size_t)r * nc; }
+  using Key = int;
+  __device__ Key key(int c) const { return c; }
+  __device__ double vec(int k, Key c) const { return x[(size_t)k * nc + c]; }
+  __device__ void out(int k, int r, double v) const { y[(size_t)k * nr + r] = v; }
+};
+
 template <class Op, int L, bool SPLIT>
 __global__ void __launch_bounds__(256) k_rowdot(const typename Op::Args args) {
   constexpr int RPW = SPLIT ? 1 : (DSU / L < 4 ? DSU / L : 4);
@@ -954,27 +978,12 @@ void absmax_partial(const double* x, size_t n, double* out, int blocks, hipStrea
   hipLaunchKernelGGL(k_absmax, dim3(blocks), dim3(256), 0, s, x, n, out);
 }
 
-// y[r][i] = sum_j A[i][j] x[r][j]; one wave per (row, right-hand side).
-__global__ void __launch_bounds__(256) k_matvec(const double* __restrict__ A, int rows, int cols,
-                                                const double* __restrict__ x, int nrhs,
-                                                double* __restrict__ y) {
-  const int lane = threadIdx.x & 63;
-  const long long w = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (w >= (long long)rows * nrhs) return;
-  const int i = (int)(w % rows), r = (int)(w / rows);
-  const double* Ar = A + (size_t)i * cols;
-  const double* xr = x + (size_t)r * cols;
-  double acc = 0.0;
-  for (int j = lane; j < cols; j += 64) acc += Ar[j] * xr[j];
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if (lane == 0) y[(size_t)r * rows + i] = acc;
-}
-
+// y[r][i] = sum_j A[i][j] x[r][j] on the row-pass kernel (loads first, long rows
+// split over four waves, up to four right-hand sides per pass over A).
 void matvec(const double* A, int rows, int cols, const double* x, int nrhs, double* y,
             hipStream_t s) {
-  long long waves = (long long)rows * nrhs;
-  hipLaunchKernelGGL(k_matvec, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, A, rows, cols,
-                     x, nrhs, y);
+  const RowMat::Args a{A, rows, cols, nrhs, x, y};
+  launch_rowdot<RowMat>(a, 1, rows, cols, s);
 }
 
 // flag[0] = 1 if any entry is NaN or infinite.
