@@ -21,40 +21,6 @@ namespace hps {
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
-// Block-wide argmax of |v| (ties -> smallest index), 256 threads.
-// ---------------------------------------------------------------------------
-__device__ inline bool argmax_better(double v1, int i1, double v2, int i2) {
-  // True when (v2, i2) should replace (v1, i1): valid beats invalid, larger
-  // value wins, equal values go to the smaller row index.
-  if (i2 < 0) return false;
-  if (i1 < 0) return true;
-  return v2 > v1 || (v2 == v1 && i2 < i1);
-}
-
-__device__ inline void block_argmax(double v, int idx, double* sv, int* si, double& bv, int& bi) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int off = 32; off > 0; off >>= 1) {
-    double ov = __shfl_xor(v, off);
-    int oi = __shfl_xor(idx, off);
-    if (argmax_better(v, idx, ov, oi)) { v = ov; idx = oi; }
-  }
-  if (lane == 0) { sv[wid] = v; si[wid] = idx; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double b = sv[0];
-    int i = si[0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
-      if (argmax_better(b, i, sv[w], si[w])) { b = sv[w]; i = si[w]; }
-    sv[0] = b;
-    si[0] = i;
-  }
-  __syncthreads();
-  bv = sv[0];
-  bi = si[0];
-  __syncthreads();
-}
-
-// ---------------------------------------------------------------------------
 // Block Gauss-Jordan elimination of the augmented systems W = [M | B].
 //
 // For each panel of kb columns starting at k0:
@@ -100,18 +66,81 @@ __device__ inline unsigned wave_max_u32(unsigned k) {
   return max(max(a, b), max(c, d));
 }
 
-// Row moves of a step from the chosen rows pi[0..kb) (run by one wave).
-__device__ inline void perm_lists(const int* pi, int kb, int k0, int* sD, int* sV, int* nd) {
+// Orders a wave's LDS accesses: what one lane wrote before is visible to
+// every lane of the wave after it.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Row moves of a step from the chosen rows pi[0..kb) (run by one wave).  The
+// block positions taken by a chosen row are marked in flag[0..kb) (LDS), so
+// each lane learns whether its position was chosen in two LDS round trips.
+__device__ inline void perm_lists(const int* pi, int kb, int k0, int* flag, int* sD, int* sV,
+                                  int* nd) {
   const int lane = threadIdx.x & 63;
-  bool chosen = false;
   const int myp = lane < kb ? pi[lane] : -1;
-  for (int j = 0; j < kb; ++j) chosen |= (pi[j] == k0 + lane);
+  if (lane < kb) flag[lane] = 0;
+  wave_lds_sync();
+  if (myp >= k0 && myp < k0 + kb) flag[myp - k0] = 1;
+  wave_lds_sync();
+  const bool chosen = lane < kb && flag[lane] != 0;
   const bool isd = lane < kb && !chosen, isv = lane < kb && myp >= k0 + kb;
   const unsigned long long md = __ballot(isd), mv = __ballot(isv);
   const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   if (isd) sD[__popcll(md & below)] = k0 + lane;
   if (isv) sV[__popcll(mv & below)] = myp;
   if (lane == 0) *nd = __popcll(md);
+}
+
+// End of a panel step, after the pivot rows' L \ U sits in sLU and the
+// chosen rows in sPi[0..ns) (the caller has synchronised the workgroup):
+// records the pivots and the status, then moves the panel rows.
+template <int KB>
+__device__ inline void panel_tail(const SolveDesc& d, int k0, int kb, int ns, bool bad,
+                                  int* status, double (*sLU)[KB + 1], double (*sKeep)[KB + 1],
+                                  int* sPi, int* sD, int* sV, int* sFlag, int* sNd) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const size_t ld = d.ld;
+  double* P = d.W + (size_t)k0 * ld + k0;
+  if (wid == 0) {
+    // Fewer than kb pivots cannot happen (every live row has a nonzero key);
+    // should it, the identity keeps every later access in bounds and the
+    // status reports the system as singular.
+    const bool short_ = ns < kb;
+    if (short_ && lane < kb) sPi[lane] = k0 + lane;
+    wave_lds_sync();
+    perm_lists(sPi, kb, k0, sFlag, sD, sV, sNd);
+    if (lane < kb) d.piv[k0 + lane] = sPi[lane];
+    if (lane == 0 && (bad || short_))
+      if (atomicCAS(status, 0, 1) == 0) status[1] = d.tag;
+  }
+  __syncthreads();
+  // Original panel values of the displaced rows (they sit in the pivot block,
+  // which is overwritten next), then the block's new rows.
+  // The loops have a constant trip count (the workgroup has at least one
+  // wave), so every thread issues all its loads before the first wait.
+  constexpr int IT = KB * KB / 64;
+  const int nd = *sNd, nkeep = nd * kb, bd = blockDim.x;
+  double kv[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * bd;
+    kv[it] = e < nkeep ? P[(size_t)(sD[e / kb] - k0) * ld + e % kb] : 0.0;
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * bd;
+    if (e < nkeep) sKeep[e / kb][e % kb] = kv[it];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * bd;
+    if (e < kb * kb) P[(size_t)(e / kb) * ld + e % kb] = sLU[e / kb][e % kb];
+    if (e < nkeep) P[(size_t)(sV[e / kb] - k0) * ld + e % kb] = sKeep[e / kb][e % kb];
+  }
 }
 
 constexpr int TP_MAXW = 8;  // waves of the panel workgroup (two per SIMD: 256 VGPRs each)
@@ -135,7 +164,7 @@ __global__ void __launch_bounds__(64 * TP_MAXW) k_gj_panel(const SolveDesc* __re
   __shared__ double sRow[2][TP_MAXW][KB];
   __shared__ double sLU[KB][KB + 1];
   __shared__ double sKeep[KB][KB + 1];
-  __shared__ int sPi[KB], sD[KB], sV[KB], sNd, sBad, sNs;
+  __shared__ int sPi[KB], sD[KB], sV[KB], sFlag[KB], sNd, sBad, sNs;
   const SolveDesc d = descs[blockIdx.x];
   if (k0 >= d.n) return;
   const int kb = min(KB, d.n - k0), rows = d.n - k0;
@@ -243,31 +272,105 @@ __global__ void __launch_bounds__(64 * TP_MAXW) k_gj_panel(const SolveDesc* __re
     }
   if (threadIdx.x == 0) sNs = ns;
   __syncthreads();
-  if (wid == 0) {
-    // Fewer than kb pivots cannot happen (every live row has a nonzero key);
-    // should it, the identity keeps every later access in bounds and the
-    // status reports the system as singular.
-    const bool short_ = sNs < kb;
-    if (short_ && lane < kb) sPi[lane] = k0 + lane;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    perm_lists(sPi, kb, k0, sD, sV, &sNd);
-    if (lane < kb) d.piv[k0 + lane] = sPi[lane];
-    if (lane == 0 && (sBad || short_))
-      if (atomicCAS(status, 0, 1) == 0) status[1] = d.tag;
+  panel_tail<KB>(d, k0, kb, sNs, sBad != 0, status, sLU, sKeep, sPi, sD, sV, sFlag, &sNd);
+}
+
+// Broadcast of lane `src` (wave-uniform) of a double to the whole wave.
+__device__ inline double bcast_lane(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// One-wave variant of k_gj_panel<2, KB> for panels of at most 128 rows:
+// the same pivot keys, choices and arithmetic, but with no workgroup to
+// synchronise the pivot row is read straight out of the winning lane's
+// registers (readlane) instead of through LDS, so a column step holds no LDS
+// round trip and no barrier.
+template <int KB>
+__global__ void __launch_bounds__(64) k_gj_panel_w1(const SolveDesc* __restrict__ descs, int k0,
+                                                    int* status) {
+  constexpr int R = 2;
+  __shared__ double sLU[KB][KB + 1];
+  __shared__ double sKeep[KB][KB + 1];
+  __shared__ int sPi[KB], sD[KB], sV[KB], sFlag[KB], sNd;
+  const SolveDesc d = descs[blockIdx.x];
+  if (k0 >= d.n) return;
+  const int kb = min(KB, d.n - k0), rows = d.n - k0;
+  const int lane = threadIdx.x;
+  const size_t ld = d.ld;
+  const double* P = d.W + (size_t)k0 * ld + k0;
+  double x[R][KB];
+  bool live[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int lr = r * 64 + lane;
+    live[r] = lr < rows;
+#pragma unroll
+    for (int c = 0; c < KB; ++c) x[r][c] = (live[r] && c < kb) ? P[(size_t)lr * ld + c] : 0.0;
   }
+  int ns = 0;
+  bool stop = false, bad = false;
+  int sel[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) sel[r] = -1;
+#pragma unroll
+  for (int c = 0; c < KB; ++c) {
+    if (c >= kb || stop) continue;
+    unsigned key = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (live[r]) key = max(key, pivot_key(x[r][c], r * 64 + lane));
+    const unsigned g = wave_max_u32(key);
+    if (g == 0) {
+      stop = true;
+      continue;
+    }
+    const int gslot = 4095 - (int)(g & 4095u);
+    const int gr = gslot >> 6, gl = gslot & 63;
+    double prow[KB];
+    if (gr == 0) {
+#pragma unroll
+      for (int c2 = 0; c2 < KB; ++c2)
+        if (c2 >= c) prow[c2] = bcast_lane(x[0][c2], gl);
+    } else {
+#pragma unroll
+      for (int c2 = 0; c2 < KB; ++c2)
+        if (c2 >= c) prow[c2] = bcast_lane(x[1][c2], gl);
+    }
+    if (lane == gl) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (gr == r) {
+          live[r] = false;
+          sel[r] = ns;
+        }
+    }
+    if (lane == 0) sPi[ns] = k0 + gslot;
+    ++ns;
+    const double piv = prow[c];
+    const bool ok = (piv != 0.0) && (piv == piv) && fabs(piv) != INFINITY;
+    bad |= !ok;
+    const double inv = ok ? 1.0 / piv : 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (live[r]) {
+        const double l = x[r][c] * inv;
+        x[r][c] = l;
+#pragma unroll
+        for (int c2 = 0; c2 < KB; ++c2)
+          if (c2 > c) x[r][c2] = fma(-l, prow[c2], x[r][c2]);
+      }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (sel[r] >= 0) {
+#pragma unroll
+      for (int c2 = 0; c2 < KB; ++c2) sLU[sel[r]][c2] = x[r][c2];
+    }
   __syncthreads();
-  // Original panel values of the displaced rows (they sit in the pivot block,
-  // which is overwritten next), then the block's new rows.
-  const int nd = sNd;
-  for (int e = threadIdx.x; e < nd * kb; e += blockDim.x)
-    sKeep[e / kb][e % kb] = P[(size_t)(sD[e / kb] - k0) * ld + e % kb];
-  __syncthreads();
-  for (int e = threadIdx.x; e < kb * kb; e += blockDim.x)
-    P[(size_t)(e / kb) * ld + e % kb] = sLU[e / kb][e % kb];
-  for (int e = threadIdx.x; e < nd * kb; e += blockDim.x)
-    P[(size_t)(sV[e / kb] - k0) * ld + e % kb] = sKeep[e / kb][e % kb];
+  panel_tail<KB>(d, k0, kb, ns, bad, status, sLU, sKeep, sPi, sD, sV, sFlag, &sNd);
 }
 
 // One thread per column to the right of the pivot block: apply the step's
@@ -280,7 +383,7 @@ template <int KB>
 __global__ void __launch_bounds__(256) k_gj_swap_trsm(const SolveDesc* __restrict__ descs, int k0) {
   __shared__ double LU[KB][KB + 1];
   __shared__ double rdiag[KB];
-  __shared__ int pv[KB], sD[KB], sV[KB], sNd;
+  __shared__ int pv[KB], sD[KB], sV[KB], sFlag[KB], sNd;
   const SolveDesc d = descs[blockIdx.y];
   if (k0 >= d.n) return;
   const int kb = min(KB, d.n - k0);
@@ -289,17 +392,29 @@ __global__ void __launch_bounds__(256) k_gj_swap_trsm(const SolveDesc* __restric
   if ((int)(blockIdx.x * blockDim.x) >= ncol) return;
   const size_t ld = d.ld;
   // Entries past kb are zero, so that the full-width loops below add exact
-  // zeros for them.
-  for (int e = threadIdx.x; e < KB * KB; e += blockDim.x) {
-    const int r = e / KB, c = e % KB;
-    LU[r][c] = (r < kb && c < kb) ? d.W[(size_t)(k0 + r) * ld + k0 + c] : 0.0;
+  // zeros for them.  Constant trip counts (the workgroup has at least one
+  // wave): every thread issues all its loads before the first wait.
+  constexpr int IT = KB * KB / 64;
+  const int bd = blockDim.x, t = threadIdx.x;
+  double lv[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = t + it * bd, r = e / KB, c = e % KB;
+    lv[it] = (e < KB * KB && r < kb && c < kb) ? d.W[(size_t)(k0 + r) * ld + k0 + c] : 0.0;
   }
-  for (int e = threadIdx.x; e < KB; e += blockDim.x) {
-    if (e < kb) pv[e] = d.piv[k0 + e];
-    rdiag[e] = e < kb ? 1.0 / d.W[(size_t)(k0 + e) * ld + k0 + e] : 0.0;
+  const double dg = t < kb ? d.W[(size_t)(k0 + t) * ld + k0 + t] : 0.0;
+  const int pvt = t < kb ? d.piv[k0 + t] : 0;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = t + it * bd;
+    if (e < KB * KB) LU[e / KB][e % KB] = lv[it];
+  }
+  if (t < KB) {
+    if (t < kb) pv[t] = pvt;
+    rdiag[t] = t < kb ? 1.0 / dg : 0.0;
   }
   __syncthreads();
-  if (threadIdx.x < 64) perm_lists(pv, kb, k0, sD, sV, &sNd);
+  if (threadIdx.x < 64) perm_lists(pv, kb, k0, sFlag, sD, sV, &sNd);
   __syncthreads();
   const int col = c0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= d.n + d.m) return;
@@ -757,6 +872,10 @@ static void launch_panel(const SolveDesc* d_desc, int np, int k0, int rows, int 
                          hipStream_t s) {
   if (nb == 32) {
     HPS_REQUIRE(rows <= 64 * TP_MAXW * 2, "panel has too many rows");
+    if (rows <= 128) {
+      hipLaunchKernelGGL((k_gj_panel_w1<32>), dim3(np), dim3(64), 0, s, d_desc, k0, st);
+      return;
+    }
     const int nw = (rows + 127) / 128;
     hipLaunchKernelGGL((k_gj_panel<2, 32>), dim3(np), dim3(64 * nw), 0, s, d_desc, k0, st);
   } else {
