@@ -475,9 +475,11 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gj_update(const SolveDesc* __r
   const int N = min(BN, min(d.n + d.m, k0 + kb + coff_hi) - c0);
   if (M <= 0 || N <= 0) return;
   const size_t ld = d.ld;
-  gemm_tile<BM, BN, BK, WM, WN>(d.W + (size_t)r0 * ld + k0, d.ld, d.W + (size_t)k0 * ld + c0,
-                                d.ld, d.W + (size_t)r0 * ld + c0, d.ld, nullptr, 0, M, N, kb, -1.0,
-                                0, 0, sm);
+  // The old values of the tile are loaded with the first operands (the tile
+  // lies outside both the panel columns and the pivot-block rows).
+  gemm_tile_map<BM, BN, BK, WM, WN, RowsIdentity, RowsIdentity, RowsIdentity, NoC0Elem, true>(
+      d.W + (size_t)r0 * ld + k0, d.ld, d.W + (size_t)k0 * ld + c0, d.ld, RowsIdentity{},
+      d.W + (size_t)r0 * ld + c0, d.ld, RowsIdentity{}, nullptr, 0, M, N, kb, -1.0, 0, 0, sm, true);
 }
 
 // The parent's pass-through diag(T11a, T22b) at (r, c) in parent order.

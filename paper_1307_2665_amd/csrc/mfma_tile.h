@@ -51,9 +51,11 @@ struct GemmTile {
 // C0 + c0row(r) * ldc0 (gathered operands, a scattered result; a negative
 // c0row is a zero row; A rows are plain).  With C0 null the old C is added
 // when acc_c is set and nothing otherwise (C is then not read).  An active
-// c0elem gives C0 element by element instead.
+// c0elem gives C0 element by element instead.  PRE_C (with acc_c and no C0)
+// loads the old C before the first product instead of after the last, one
+// dependent round of global loads fewer; C must not overlap A or B.
 template <int BM, int BN, int BK, int WM, int WN, class BRow, class CRow,
-          class C0Row = RowsIdentity, class C0Elem = NoC0Elem>
+          class C0Row = RowsIdentity, class C0Elem = NoC0Elem, bool PRE_C = false>
 __device__ inline void gemm_tile_map(const double* __restrict__ A, int lda,
                                      const double* B, int ldb, BRow brow, double* C, int ldc,
                                      CRow crow, const double* C0, int ldc0, int M, int N, int K,
@@ -93,6 +95,19 @@ __device__ inline void gemm_tile_map(const double* __restrict__ A, int lda,
     }
   };
   if (PF && K > 0) load(0);
+  double pc[PRE_C ? T::FM : 1][PRE_C ? T::FN : 1][4];
+  if constexpr (PRE_C) {
+#pragma unroll
+    for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < T::FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gr = row0 + wm * WBM + i * 16 + (lane >> 4) + 4 * r;
+          const int gc = col0 + wn * WBN + j * 16 + (lane & 15);
+          pc[i][j][r] = (gr < M && gc < N) ? C[(size_t)crow(gr) * ldc + gc] : 0.0;
+        }
+  }
   for (int kt = 0; kt < K; kt += BK) {
     if (!PF) load(kt);
 #pragma unroll
@@ -138,6 +153,8 @@ __device__ inline void gemm_tile_map(const double* __restrict__ A, int lda,
           } else if (C0) {
             const int r0 = c0row(gr);
             if (r0 >= 0) c0 = C0[(size_t)r0 * ldc0 + gc];
+          } else if constexpr (PRE_C) {
+            c0 = pc[i][j][r];
           } else if (acc_c) {
             c0 = *cp;
           }
