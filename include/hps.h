@@ -309,7 +309,8 @@ hps_status hps_batched_solve(const double* M, const double* B, int n, int m, int
    0 FP64 MFMA; 1 split-FP32 MFMA (three FP32 products of hi/lo halves, FP64
    accumulation per 16-deep slab); 2 BF16 MFMA on three-slice splits (six
    BF16 products, FP64 accumulation per 32-deep slab).  Other values give
-   HPS_EINVAL. */
+   HPS_EINVAL.  C_i must not overlap A_j or B_j (tiles of C are written while
+   other tiles still read the operands). */
 hps_status hps_batched_gemm(const double* A, const double* B, double* C, int Mr, int Nc, int K,
                             int nprob, double alpha, int prec, void* stream);
 
