@@ -83,8 +83,9 @@ def test_gemm_bf16x6_accuracy(H, gpu):
     assert rowerr.max() < 5e-7
 
 
-# Sizes cover one round of the pivot tournament (n <= 128), two rounds (448),
-# three rounds (900) and waves taking several round-1 chunks (1100, 2100).
+# Sizes cover the one-wave panel (n <= 128: 5, 33, 70), the multi-wave
+# 32-wide panel (130 .. 900, two to eight waves) and the 16-wide panel with six
+# rows per lane (1100, 2100).
 @pytest.mark.parametrize("n,m,nb", [(5, 3, 2), (33, 40, 3), (70, 17, 2), (130, 9, 1), (196, 56, 2),
                                     (448, 30, 2), (900, 40, 1), (1100, 20, 1), (2100, 7, 1)])
 def test_batched_solve_with_pivoting(H, gpu, n, m, nb):
@@ -118,6 +119,19 @@ def test_batched_solve_reports_singular(H, gpu):
     M = np.zeros((2, 8, 8))
     M[0] = np.eye(8)
     B = np.ones((2, 8, 3))
+    with pytest.raises(H.HpsError) as e:
+        H.batched_solve(_t(M, gpu), _t(B, gpu))
+    assert e.value.status == H.HPS_ESINGULAR
+
+
+@pytest.mark.parametrize("n", [70, 300, 1100])
+def test_batched_solve_singular_last_pivot(H, gpu, n):
+    """A zero last pivot (the identity with its last diagonal entry zeroed) is
+    reported by every panel form: one-wave, multi-wave and 16-wide."""
+    say(f"batched_solve singular last pivot n={n}")
+    M = np.eye(n)[None].repeat(2, axis=0)
+    M[1, n - 1, n - 1] = 0.0
+    B = np.ones((2, n, 2))
     with pytest.raises(H.HpsError) as e:
         H.batched_solve(_t(M, gpu), _t(B, gpu))
     assert e.value.status == H.HPS_ESINGULAR
