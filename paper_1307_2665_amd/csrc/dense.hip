@@ -502,19 +502,20 @@ __device__ inline MergePass merge_pass(const GemmDesc& g) {
 
 // Grouped GEMM: one launch over problems, grid (tiles_n, tiles_m, nprob).
 // PASS: merge Schur products, C = diag(T11a, T22b) + alpha A B (descs with pmap).
-template <int BM, int BN, int BK, int WM, int WN, bool PASS>
+template <int BM, int BN, int BK, int WM, int WN, bool PASS, int DEPTH = 1>
 __global__ void __launch_bounds__(64 * WM * WN) k_gemm(const GemmDesc* __restrict__ descs) {
   __shared__ double sm[GemmTile<BM, BN, BK, WM, WN>::SMEM];
   const GemmDesc g = descs[blockIdx.z];
   if ((int)blockIdx.y * BM >= g.M || (int)blockIdx.x * BN >= g.N) return;
   if constexpr (PASS)
-    gemm_tile_map<BM, BN, BK, WM, WN>(g.A, g.lda, g.B, g.ldb, RowsIdentity{}, g.C, g.ldc,
-                                      RowsIdentity{}, nullptr, 0, g.M, g.N, g.K, g.alpha,
-                                      blockIdx.y * BM, blockIdx.x * BN, sm, false, RowsIdentity{},
-                                      merge_pass(g));
+    gemm_tile_map<BM, BN, BK, WM, WN, RowsIdentity, RowsIdentity, RowsIdentity, MergePass, false,
+                  DEPTH>(g.A, g.lda, g.B, g.ldb, RowsIdentity{}, g.C, g.ldc, RowsIdentity{},
+                         nullptr, 0, g.M, g.N, g.K, g.alpha, blockIdx.y * BM, blockIdx.x * BN, sm,
+                         false, RowsIdentity{}, merge_pass(g));
   else
-    gemm_tile<BM, BN, BK, WM, WN>(g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.C0, g.ldc0, g.M, g.N, g.K,
-                                  g.alpha, blockIdx.y * BM, blockIdx.x * BN, sm);
+    gemm_tile_map<BM, BN, BK, WM, WN, RowsIdentity, RowsIdentity, RowsIdentity, NoC0Elem, false,
+                  DEPTH>(g.A, g.lda, g.B, g.ldb, RowsIdentity{}, g.C, g.ldc, RowsIdentity{}, g.C0,
+                         g.ldc0, g.M, g.N, g.K, g.alpha, blockIdx.y * BM, blockIdx.x * BN, sm, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -1050,24 +1051,25 @@ void grouped_gemm_v(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc,
     gemm_bf16x6(d_desc, h_desc, stream);
     return;
   }
-#define HPS_GEMM(BM, BN, BK, WM, WN)                                                          \
+#define HPS_GEMM(BM, BN, BK, WM, WN, D)                                                       \
   {                                                                                           \
     const dim3 grid((nmax + BN - 1) / BN, (mmax + BM - 1) / BM, np);                          \
     if (pass)                                                                                 \
-      hipLaunchKernelGGL((k_gemm<BM, BN, BK, WM, WN, true>), grid, dim3(64 * WM * WN), 0,     \
+      hipLaunchKernelGGL((k_gemm<BM, BN, BK, WM, WN, true, D>), grid, dim3(64 * WM * WN), 0,  \
                          stream, d_desc);                                                     \
     else                                                                                      \
-      hipLaunchKernelGGL((k_gemm<BM, BN, BK, WM, WN, false>), grid, dim3(64 * WM * WN), 0,    \
+      hipLaunchKernelGGL((k_gemm<BM, BN, BK, WM, WN, false, D>), grid, dim3(64 * WM * WN), 0, \
                          stream, d_desc);                                                     \
     return;                                                                                   \
   }
   switch (variant) {
-    case 1: HPS_GEMM(32, 32, 16, 1, 1)
-    case 2: HPS_GEMM(128, 128, 16, 4, 2)
-    case 3: HPS_GEMM(128, 64, 16, 2, 2)
-    case 4: HPS_GEMM(64, 128, 16, 2, 2)
-    case 5: HPS_GEMM(64, 64, 32, 2, 2)
-    default: HPS_GEMM(64, 64, 16, 2, 2)
+    case 1: HPS_GEMM(32, 32, 16, 1, 1, 1)
+    case 2: HPS_GEMM(128, 128, 16, 4, 2, 1)
+    case 3: HPS_GEMM(128, 64, 16, 2, 2, 1)
+    case 4: HPS_GEMM(64, 128, 16, 2, 2, 1)
+    case 5: HPS_GEMM(64, 64, 32, 2, 2, 1)
+    case 6: HPS_GEMM(64, 64, 16, 2, 2, 3)
+    default: HPS_GEMM(64, 64, 16, 2, 2, 1)
   }
 #undef HPS_GEMM
 }

@@ -55,7 +55,7 @@ struct GemmTile {
 // loads the old C before the first product instead of after the last, one
 // dependent round of global loads fewer; C must not overlap A or B.
 template <int BM, int BN, int BK, int WM, int WN, class BRow, class CRow,
-          class C0Row = RowsIdentity, class C0Elem = NoC0Elem, bool PRE_C = false>
+          class C0Row = RowsIdentity, class C0Elem = NoC0Elem, bool PRE_C = false, int DEPTH = 1>
 __device__ inline void gemm_tile_map(const double* __restrict__ A, int lda,
                                      const double* B, int ldb, BRow brow, double* C, int ldc,
                                      CRow crow, const double* C0, int ldc0, int M, int N, int K,
@@ -94,7 +94,7 @@ __device__ inline void gemm_tile_map(const double* __restrict__ A, int lda,
       rb[e] = (gk < K && gc < N) ? B[(size_t)brow(gk) * ldb + gc] : 0.0;
     }
   };
-  if (PF && K > 0) load(0);
+  if (DEPTH == 1 && PF && K > 0) load(0);
   double pc[PRE_C ? T::FM : 1][PRE_C ? T::FN : 1][4];
   if constexpr (PRE_C) {
 #pragma unroll
@@ -108,34 +108,96 @@ __device__ inline void gemm_tile_map(const double* __restrict__ A, int lda,
           pc[i][j][r] = (gr < M && gc < N) ? C[(size_t)crow(gr) * ldc + gc] : 0.0;
         }
   }
-  for (int kt = 0; kt < K; kt += BK) {
-    if (!PF) load(kt);
+  if constexpr (DEPTH == 1) {
+    for (int kt = 0; kt < K; kt += BK) {
+      if (!PF) load(kt);
 #pragma unroll
-    for (int e = 0; e < EA; ++e) {
-      const int idx = tid + T::NT * e;
-      As[idx % BK][idx / BK] = ra[e];
+      for (int e = 0; e < EA; ++e) {
+        const int idx = tid + T::NT * e;
+        As[idx % BK][idx / BK] = ra[e];
+      }
+#pragma unroll
+      for (int e = 0; e < EB; ++e) {
+        const int idx = tid + T::NT * e;
+        Bs[idx / BN][idx % BN] = rb[e];
+      }
+      __syncthreads();
+      if (PF && kt + BK < K) load(kt + BK);
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        double a[T::FM], b[T::FN];
+#pragma unroll
+        for (int i = 0; i < T::FM; ++i) a[i] = As[kk + (lane >> 4)][wm * WBM + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < T::FN; ++j) b[j] = Bs[kk + (lane >> 4)][wn * WBN + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+          for (int j = 0; j < T::FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+      __syncthreads();
     }
+  } else {
+    // DEPTH slabs of global loads in flight: slab kt + DEPTH * BK is loaded
+    // into the registers slab kt has just left (the slot index is a constant
+    // of the unrolled inner loop).
+    double qa[DEPTH][EA], qb[DEPTH][EB];
+    auto load_slot = [&](int kt, double (&pa)[EA], double (&pb)[EB]) {
 #pragma unroll
-    for (int e = 0; e < EB; ++e) {
-      const int idx = tid + T::NT * e;
-      Bs[idx / BN][idx % BN] = rb[e];
+      for (int e = 0; e < EA; ++e) {
+        const int idx = tid + T::NT * e;
+        const int i = idx / BK, k = idx % BK;
+        const int gr = row0 + i, gk = kt + k;
+        pa[e] = (gr < M && gk < K) ? A[(size_t)gr * lda + gk] : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < EB; ++e) {
+        const int idx = tid + T::NT * e;
+        const int k = idx / BN, j = idx % BN;
+        const int gk = kt + k, gc = col0 + j;
+        pb[e] = (gk < K && gc < N) ? B[(size_t)brow(gk) * ldb + gc] : 0.0;
+      }
+    };
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d)
+      if (d * BK < K) load_slot(d * BK, qa[d], qb[d]);
+    for (int kt0 = 0; kt0 < K; kt0 += DEPTH * BK) {
+#pragma unroll
+      for (int d = 0; d < DEPTH; ++d) {
+        const int kt = kt0 + d * BK;
+        if (kt < K) {
+#pragma unroll
+          for (int e = 0; e < EA; ++e) {
+            const int idx = tid + T::NT * e;
+            As[idx % BK][idx / BK] = qa[d][e];
+          }
+#pragma unroll
+          for (int e = 0; e < EB; ++e) {
+            const int idx = tid + T::NT * e;
+            Bs[idx / BN][idx % BN] = qb[d][e];
+          }
+          __syncthreads();
+          if (kt + DEPTH * BK < K) load_slot(kt + DEPTH * BK, qa[d], qb[d]);
+#pragma unroll
+          for (int kk = 0; kk < BK; kk += 4) {
+            double a[T::FM], b[T::FN];
+#pragma unroll
+            for (int i = 0; i < T::FM; ++i)
+              a[i] = As[kk + (lane >> 4)][wm * WBM + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < T::FN; ++j)
+              b[j] = Bs[kk + (lane >> 4)][wn * WBN + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+              for (int j = 0; j < T::FN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+          }
+          __syncthreads();
+        }
+      }
     }
-    __syncthreads();
-    if (PF && kt + BK < K) load(kt + BK);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      double a[T::FM], b[T::FN];
-#pragma unroll
-      for (int i = 0; i < T::FM; ++i) a[i] = As[kk + (lane >> 4)][wm * WBM + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < T::FN; ++j) b[j] = Bs[kk + (lane >> 4)][wn * WBN + j * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < T::FM; ++i)
-#pragma unroll
-        for (int j = 0; j < T::FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < T::FM; ++i)

@@ -15,7 +15,7 @@ enum TuneKnob {
   TUNE_NKNOBS = 3
 };
 
-constexpr int GEMM_VARIANTS = 6;   // tiles of gemm_tile (dense.hip)
+constexpr int GEMM_VARIANTS = 7;   // tiles of gemm_tile (dense.hip)
 constexpr int TRSM_BLOCKS[3] = {256, 128, 64};
 
 // ceil(log2(x)) for x >= 1.

@@ -33,7 +33,7 @@ def _t(x, dev):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
 
 
-@pytest.mark.parametrize("variant", range(6))
+@pytest.mark.parametrize("variant", range(7))
 def test_gemm_variants(H, gpu, variant):
     say(f"gemm variant {variant}")
     H.tune_set("gemm_variant", variant)
