@@ -339,9 +339,10 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
    "leaf_variant": fused leaf solve, 0-2 step-by-step LU (16x16 threads for
      p <= 12, 16x64, 16x32), 3-4 Gauss-Jordan (16x16 threads for p <= 12,
      16x32 threads);
-   "gemm_variant": FP64 MFMA GEMM tile (0: 64x64x16 on 2x2 waves, 1: 32x32x16
-     on one wave, 2: 128x128x16 on eight waves, 3: 128x64x16, 4: 64x128x16,
-     5: 64x64x32, 6: 64x64x16 with three slabs of loads in flight);
+   "gemm_variant": FP64 MFMA GEMM tile (0: 64x64x16 on 2x2 waves with three
+     k-slabs of loads in flight, 1: 32x32x16 on one wave, 2: 128x128x16 on
+     eight waves, 3: 128x64x16, 4: 64x128x16, 5: 64x64x32, 6: 64x64x16 with
+     one slab in flight; 1-6 keep one slab in flight);
    "gj_variant": merge solver, 4 * (update tile, as gemm_variant) + TRSM block
      (0: 256, 1: 128, 2: 64 threads);
    "solve_graph": 1 (default) runs plain solves as a captured HIP graph per

@@ -1068,8 +1068,8 @@ void grouped_gemm_v(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc,
     case 3: HPS_GEMM(128, 64, 16, 2, 2, 1)
     case 4: HPS_GEMM(64, 128, 16, 2, 2, 1)
     case 5: HPS_GEMM(64, 64, 32, 2, 2, 1)
-    case 6: HPS_GEMM(64, 64, 16, 2, 2, 3)
-    default: HPS_GEMM(64, 64, 16, 2, 2, 1)
+    case 6: HPS_GEMM(64, 64, 16, 2, 2, 1)
+    default: HPS_GEMM(64, 64, 16, 2, 2, 3)
   }
 #undef HPS_GEMM
 }
