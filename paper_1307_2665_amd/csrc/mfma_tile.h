@@ -225,6 +225,20 @@ __device__ inline void gemm_tile_map(const double* __restrict__ A, int lda,
       }
 }
 
+// gemm_tile_map with DEPTH k-slabs of global loads in flight and the row
+// maps deduced from the arguments.
+template <int BM, int BN, int BK, int WM, int WN, int DEPTH, class BRow, class CRow,
+          class C0Row = RowsIdentity, class C0Elem = NoC0Elem>
+__device__ inline void gemm_tile_map_d(const double* __restrict__ A, int lda, const double* B,
+                                       int ldb, BRow brow, double* C, int ldc, CRow crow,
+                                       const double* C0, int ldc0, int M, int N, int K,
+                                       double alpha, int row0, int col0, double* sm, bool acc_c,
+                                       C0Row c0row = C0Row{}, C0Elem c0elem = C0Elem{}) {
+  gemm_tile_map<BM, BN, BK, WM, WN, BRow, CRow, C0Row, C0Elem, false, DEPTH>(
+      A, lda, B, ldb, brow, C, ldc, crow, C0, ldc0, M, N, K, alpha, row0, col0, sm, acc_c, c0row,
+      c0elem);
+}
+
 // C[row0.., col0..] (M x N valid) = C0 (or C) + alpha * A (M x K) * B (K x N);
 // A, B, C, C0 point at the matrices' origins (row-major, given leading dims).
 template <int BM, int BN, int BK, int WM, int WN>

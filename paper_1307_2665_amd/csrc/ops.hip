@@ -1072,14 +1072,14 @@ __global__ void __launch_bounds__(64 * WM * WN) k_down_mm(const MergeDesc* __res
   if (row0 >= d.m3 || col0 >= nrhs) return;
   if (ks == 1) {
     const double* z = zbase ? zbase + zoff[mi] * nrhs : nullptr;
-    gemm_tile_map<BM, BN, BK, WM, WN>(d.S, d.ldw, U, nrhs, RowsIndexed{d.Ie}, U, nrhs,
+    gemm_tile_map_d<BM, BN, BK, WM, WN, 3>(d.S, d.ldw, U, nrhs, RowsIndexed{d.Ie}, U, nrhs,
                                       RowsIndexed{d.Ii}, z, nrhs, d.m3, nrhs, d.me, 1.0, row0,
                                       col0, sm, false);
     return;
   }
   const int kchunk = ((d.me + ks - 1) / ks + BK - 1) / BK * BK;
   const int k0 = min(d.me, kc * kchunk), K = min(kchunk, d.me - k0);
-  gemm_tile_map<BM, BN, BK, WM, WN>(d.S + k0, d.ldw, U, nrhs, RowsIndexed{d.Ie + k0},
+  gemm_tile_map_d<BM, BN, BK, WM, WN, 3>(d.S + k0, d.ldw, U, nrhs, RowsIndexed{d.Ie + k0},
                                     P + (size_t)blockIdx.z * m3_max * nrhs, nrhs, RowsIdentity{},
                                     nullptr, 0, d.m3, nrhs, K, 1.0, row0, col0, sm, false);
 }
@@ -1221,7 +1221,7 @@ __global__ void __launch_bounds__(64 * WM * WN) k_flux_mm(const double* __restri
   const int leaf = blockIdx.z, m = 4 * q;
   const int row0 = blockIdx.y * BM, col0 = blockIdx.x * BN;
   const LeafRows rows{leaf % nx, leaf / nx, nx, nx * (ny + 1), q};
-  gemm_tile_map<BM, BN, BK, WM, WN>(T + (size_t)leaf * m * m, m, U, nrhs, rows,
+  gemm_tile_map_d<BM, BN, BK, WM, WN, 3>(T + (size_t)leaf * m * m, m, U, nrhs, rows,
                                     v + (size_t)leaf * m * nrhs, nrhs, RowsIdentity{}, nullptr, 0,
                                     m, nrhs, m, 1.0, row0, col0, sm, false);
 }
@@ -1333,7 +1333,7 @@ __global__ void __launch_bounds__(64 * WM * WN) k_up_z_mm(const MergeDesc* __res
   const int kchunk = ((d.m3 + ks - 1) / ks + BK - 1) / BK * BK;
   const int k0 = min(d.m3, kc * kchunk), K = min(kchunk, d.m3 - k0);
   double* C = ks == 1 ? zbuf + o : P + (size_t)blockIdx.z * rows_max * nrhs;
-  gemm_tile_map<BM, BN, BK, WM, WN>(d.W + d.m3 + d.me + k0, d.ldw, rbuf + o + (size_t)k0 * nrhs,
+  gemm_tile_map_d<BM, BN, BK, WM, WN, 3>(d.W + d.m3 + d.me + k0, d.ldw, rbuf + o + (size_t)k0 * nrhs,
                                     nrhs, RowsIdentity{}, C, nrhs, RowsIdentity{}, nullptr, 0,
                                     d.m3, nrhs, K, 1.0, row0, col0, sm, false);
 }
@@ -1357,12 +1357,12 @@ __global__ void __launch_bounds__(64 * WM * WN) k_up_h_mm(const MergeDesc* __res
   const int k0 = min(d.m3, kc * kchunk), K = min(kchunk, d.m3 - k0);
   const double* B = zbuf + z_off[mi] * nrhs + (size_t)k0 * nrhs;
   if (ks == 1)
-    gemm_tile_map<BM, BN, BK, WM, WN>(d.Q, d.m3, B, nrhs, RowsIdentity{},
+    gemm_tile_map_d<BM, BN, BK, WM, WN, 3>(d.Q, d.m3, B, nrhs, RowsIdentity{},
                                       hbase + hp_off[mi] * nrhs, nrhs, RowsIdentity{}, hbase, nrhs,
                                       d.me, nrhs, d.m3, 1.0, row0, col0, sm, false,
                                       PassRows{d.pmap, ha_off[mi], hb_off[mi]});
   else
-    gemm_tile_map<BM, BN, BK, WM, WN>(d.Q + k0, d.m3, B, nrhs, RowsIdentity{},
+    gemm_tile_map_d<BM, BN, BK, WM, WN, 3>(d.Q + k0, d.m3, B, nrhs, RowsIdentity{},
                                       P + (size_t)blockIdx.z * rows_max * nrhs, nrhs,
                                       RowsIdentity{}, nullptr, 0, d.me, nrhs, K, 1.0, row0, col0,
                                       sm, false);
