@@ -541,67 +541,90 @@ __global__ void __launch_bounds__(256) k_gemm_split32(const GemmDesc* __restrict
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
-  for (int kt = 0; kt < g.K; kt += TBK) {
+  // Three 16-deep slabs of operand loads in flight: slab kt + 3 TBK goes into
+  // the registers slab kt has just left (constant slot of the unrolled loop).
+  constexpr int DEPTH = 3, EA = (TBM * TBK) / 256, EB = (TBK * TBN) / 256;
+  double qa[DEPTH][EA], qb[DEPTH][EB];
+  auto load_slot = [&](int kt, double (&pa)[EA], double (&pb)[EB]) {
 #pragma unroll
-    for (int e = 0; e < (TBM * TBK) / 256; ++e) {
-      int idx = tid + 256 * e;
-      int i = idx / TBK, k = idx % TBK;
-      int gr = row0 + i, gk = kt + k;
-      double v = (gr < g.M && gk < g.K) ? g.A[(size_t)gr * g.lda + gk] : 0.0;
-      float h = (float)v;
-      Ah[k][i] = h;
-      Al[k][i] = (float)(v - (double)h);
+    for (int e = 0; e < EA; ++e) {
+      const int idx = tid + 256 * e, i = idx / TBK, k = idx % TBK;
+      const int gr = row0 + i, gk = kt + k;
+      pa[e] = (gr < g.M && gk < g.K) ? g.A[(size_t)gr * g.lda + gk] : 0.0;
     }
 #pragma unroll
-    for (int e = 0; e < (TBK * TBN) / 256; ++e) {
-      int idx = tid + 256 * e;
-      int k = idx / TBN, j = idx % TBN;
-      int gk = kt + k, gc = col0 + j;
-      double v = (gk < g.K && gc < g.N) ? g.B[(size_t)gk * g.ldb + gc] : 0.0;
-      float h = (float)v;
-      Bh[k][j] = h;
-      Bl[k][j] = (float)(v - (double)h);
+    for (int e = 0; e < EB; ++e) {
+      const int idx = tid + 256 * e, k = idx / TBN, j = idx % TBN;
+      const int gk = kt + k, gc = col0 + j;
+      pb[e] = (gk < g.K && gc < g.N) ? g.B[(size_t)gk * g.ldb + gc] : 0.0;
     }
-    __syncthreads();
-    f4 hh[2][2], cr[2][2];
+  };
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+  for (int d = 0; d < DEPTH; ++d)
+    if (d * TBK < g.K) load_slot(d * TBK, qa[d], qb[d]);
+  for (int kt0 = 0; kt0 < g.K; kt0 += DEPTH * TBK) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        hh[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-        cr[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int d = 0; d < DEPTH; ++d) {
+      const int kt = kt0 + d * TBK;
+      if (kt >= g.K) break;
+#pragma unroll
+      for (int e = 0; e < EA; ++e) {
+        const int idx = tid + 256 * e, i = idx / TBK, k = idx % TBK;
+        const double v = qa[d][e];
+        const float h = (float)v;
+        Ah[k][i] = h;
+        Al[k][i] = (float)(v - (double)h);
       }
 #pragma unroll
-    for (int kk = 0; kk < TBK; kk += 4) {
-      float ah[2], al[2], bh[2], bl[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        int c = wm * 32 + i * 16 + (lane & 15);
-        ah[i] = Ah[kk + (lane >> 4)][c];
-        al[i] = Al[kk + (lane >> 4)][c];
+      for (int e = 0; e < EB; ++e) {
+        const int idx = tid + 256 * e, k = idx / TBN, j = idx % TBN;
+        const double v = qb[d][e];
+        const float h = (float)v;
+        Bh[k][j] = h;
+        Bl[k][j] = (float)(v - (double)h);
       }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        int c = wn * 32 + j * 16 + (lane & 15);
-        bh[j] = Bh[kk + (lane >> 4)][c];
-        bl[j] = Bl[kk + (lane >> 4)][c];
-      }
+      __syncthreads();
+      if (kt + DEPTH * TBK < g.K) load_slot(kt + DEPTH * TBK, qa[d], qb[d]);
+      f4 hh[2][2], cr[2][2];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          hh[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[i], bh[j], hh[i][j], 0, 0, 0);
-          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[i], bl[j], cr[i][j], 0, 0, 0);
-          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(al[i], bh[j], cr[i][j], 0, 0, 0);
+          hh[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+          cr[i][j] = f4{0.f, 0.f, 0.f, 0.f};
         }
+#pragma unroll
+      for (int kk = 0; kk < TBK; kk += 4) {
+        float ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          int c = wm * 32 + i * 16 + (lane & 15);
+          ah[i] = Ah[kk + (lane >> 4)][c];
+          al[i] = Al[kk + (lane >> 4)][c];
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          int c = wn * 32 + j * 16 + (lane & 15);
+          bh[j] = Bh[kk + (lane >> 4)][c];
+          bl[j] = Bl[kk + (lane >> 4)][c];
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            hh[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[i], bh[j], hh[i][j], 0, 0, 0);
+            cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ah[i], bl[j], cr[i][j], 0, 0, 0);
+            cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(al[i], bh[j], cr[i][j], 0, 0, 0);
+          }
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)hh[i][j][r] + (double)cr[i][j][r];
+      __syncthreads();
     }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[i][j][r] += (double)hh[i][j][r] + (double)cr[i][j][r];
-    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
