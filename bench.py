@@ -192,8 +192,7 @@ def other_workload(args, H, hi, np, torch, dev):
         for form in ("fp64", "mixed", "bf16x6"):
             mode = MODES[form](H)
             if not args.no_tune:
-                H.autotune([dict(nleaf=pr.nleaf, p=pr.p, q=pr.q, box=pr.box)],
-                           keep_factors=(form != "fp64"))
+                H.autotune([dict(nleaf=pr.nleaf, p=pr.p, q=pr.q, box=pr.box)])
             box = {}
 
             def build():
@@ -504,8 +503,7 @@ def main():
     # One-time autotuning for this shape (reported separately, not timed).
     tune_s = None
     if not args.no_tune:
-        tune_s = H.autotune([dict(nleaf=pr.nleaf, p=pr.p, q=pr.q, box=pr.box)],
-                            keep_factors=(mode != H.HPS_FP64))
+        tune_s = H.autotune([dict(nleaf=pr.nleaf, p=pr.p, q=pr.q, box=pr.box)])
         import tempfile
         with tempfile.TemporaryDirectory() as td:
             H.tune_save(os.path.join(td, "t.json"))

@@ -64,7 +64,7 @@ typedef struct hps_surrogate hps_surrogate;
 
 typedef enum {
   HPS_OK = 0,
-  HPS_EINVAL = 1,      /* bad argument: sizes, q > p, p < 4, non-finite data, ... */
+  HPS_EINVAL = 1,      /* bad argument: sizes, q >= p, p < 4, non-finite data, ... */
   HPS_ESINGULAR = 2,   /* a pivot of a leaf or merge elimination fell below pivot_tol */
   HPS_ENOMEM = 3,      /* device allocation failed */
   HPS_EDEVICE = 4,     /* HIP runtime error (no device, launch failure) */
@@ -88,7 +88,11 @@ typedef struct {
   int keep_factors;                /* keep LU(M), pivots and Q = [T13a; T23b] per merge (upward pass)
                                       and a copy of the coefficients (body loads) */
   int compute_root_dtn;            /* 1: form T^1 at the root (default), 0: skip its Schur product */
-  double pivot_tol;                /* |pivot| <= pivot_tol * max|column| -> HPS_ESINGULAR; 0: exact 0 only */
+  double pivot_tol;                /* in [0, 1): a leaf whose elimination meets a pivot with
+                                      |pivot| <= pivot_tol * max|A_ii|, or a merge whose smallest
+                                      pivot is <= pivot_tol * max|T33a - T33b|, makes the build
+                                      fail with HPS_ESINGULAR naming the leaf or the merge's box
+                                      and depth; 0: only zero or non-finite pivots fail */
   const hps_surrogate* surrogate;  /* mode HPS_SURROGATE only */
   int judge_samples;               /* surrogate: number of leaves re-built in FP64 to judge it */
   double judge_tol;                /* surrogate: max rel. leaf-DtN error before fallback */
@@ -155,7 +159,8 @@ hps_status hps_boundary_ids(const int nleaf[2], int q, int* ids, int* n_bdry);
 /* ---- leaf stage (section 3) --------------------------------------------- */
 
 /* Leaf DtN maps of nleaf equal leaves of size hx-by-hy (section 3.2):
-   coeffs [nleaf][6][p*p] -> T [nleaf][4q][4q].  Both device pointers. */
+   coeffs [nleaf][6][p*p] -> T [nleaf][4q][4q].  Both device pointers.
+   Requires 4 <= p <= 24 and 1 <= q <= p - 1 (HPS_EINVAL otherwise). */
 hps_status hps_leaf_dtn(const double* coeffs, int nleaf, double hx, double hy, int p, int q,
                         double* T, void* stream);
 
@@ -163,7 +168,12 @@ hps_status hps_leaf_dtn(const double* coeffs, int nleaf, double hx, double hy, i
 
 /* Builds every S^tau and the root DtN T^1 for one problem.  coeffs as above;
    box = {x0, x1, y0, y1}; nleaf = {nx, ny}; requires 4 <= p <= 24 and
-   1 <= q <= p (with q > p the merge matrices are singular).  opts may be NULL. */
+   1 <= q <= p - 1, else HPS_EINVAL.  (Section 3.2 step 1 maps the 4q Gauss
+   values of a leaf onto its 4(p-1) boundary Chebyshev nodes, averaging the
+   two sides at each corner; for q >= p that map has a null space, and at
+   every interior cross point the four edges carry a mode +a, -a, +a, -a that
+   no leaf sees, so T33a - T33b is singular for every merge whose shared edge
+   passes a cross point.)  opts may be NULL. */
 hps_status hps_build_solution_operator(const double* coeffs, const double box[4],
                                        const int nleaf[2], int p, int q,
                                        const hps_build_opts* opts, hps_op** out);
@@ -286,8 +296,20 @@ hps_status hps_op_query(const hps_op* op, hps_op_info* info);
 /* Box record: {i0, i1, j0, j1, level, parent, child_alpha, child_beta} (children -1 for leaves). */
 hps_status hps_box(const hps_op* op, int box, int rec[8]);
 
-/* S^tau of a parent box (host copy): [m3][m1+m2], rows in I_i order, columns in I_e order. */
+/* S^tau = (T33a - T33b)^-1 [-T31a | T32b] of a parent box (host copy):
+   [m3][m1+m2], rows in I_i order, columns in I_e order.  The build forms it
+   as M^-1 B: Gauss-Jordan elimination with partial pivoting of [M | I], then
+   an FP64 MFMA product. */
 hps_status hps_export_S(const hps_op* op, int box, double* S, int* rows, int* cols);
+
+/* Conditioning of the merges (section 4; the interface systems
+   (T33a - T33b) u3 = ... that eq:U_parent solves): for every tree depth d < n
+   (n = *n_levels, the tree depth + 1), cond_est[d] is the largest over the
+   depth's merges of max|M| / min |pivot| of M = T33a - T33b, from the
+   elimination with partial pivoting; a lower estimate of cond(M) up to a
+   modest factor.  The deepest depth holds only leaves: 0.  cond_est may be
+   NULL (only *n_levels is returned). */
+hps_status hps_level_conditions(const hps_op* op, double* cond_est, int* n_levels);
 
 /* Root DtN T^1 (host copy), [n_bdry][n_bdry]. */
 hps_status hps_export_root_dtn(const hps_op* op, double* T);
@@ -320,7 +342,8 @@ hps_status hps_batched_gemm(const double* A, const double* B, double* C, int Mr,
    n = (p-2)^2, m = 4q: Dx, Dy, Dxx, Dyy [p][p]; G [5][n][m] (the images of L1
    under D1^2, D1 D2, D2^2, D1, D2 restricted to interior rows); P0 = L4 L3e L1
    [m][m]; P1 = L4 L3i [m][n]; Ji [n] interior node indices.  Any output may be
-   NULL. */
+   NULL.  Requires 4 <= p <= 24, 1 <= q <= p - 1, hx, hy > 0 (HPS_EINVAL
+   otherwise). */
 hps_status hps_leaf_tables(int p, int q, double hx, double hy, double* Dx, double* Dy, double* Dxx,
                            double* Dyy, double* G, double* P0, double* P1, int* Ji);
 
@@ -343,8 +366,10 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
      k-slabs of loads in flight, 1: 32x32x16 on one wave, 2: 128x128x16 on
      eight waves, 3: 128x64x16, 4: 64x128x16, 5: 64x64x32, 6: 64x64x16 with
      one slab in flight; 1-6 keep one slab in flight);
-   "gj_variant": merge solver, 4 * (update tile, as gemm_variant) + TRSM block
-     (0: 256, 1: 128, 2: 64 threads);
+   "gj_variant": merge solver, 4 * (update tile) + TRSM block (0: 256, 1: 128,
+     2: 64 threads); update tiles 0: 64x64x16 on 2x2 waves, 1: 32x32x16 on
+     one wave, 2: 128x128x16 on 4x2 waves, 3: 128x64x16, 4: 64x128x16,
+     5: 64x64x32 (one k-slab of loads in flight each);
    "solve_graph": 1 (default) runs plain solves as a captured HIP graph per
      operator and right-hand-side count, 0 launches kernel by kernel;
    "solve_mm_min_rhs": solves, source solves and refinement with at least
@@ -371,14 +396,13 @@ hps_status hps_tune_set(const char* knob, int value);
    FP64 MFMA GEMM (per shape bucket: log2 of M, N, K and of the batch count) and
    of the merge solver (per bucket of system rows, columns and count) on
    synthetic data of those shapes, and records the fastest in the process's
-   tuning table, which later builds consult.  keep_factors selects the merge
-   shapes of operators built for refinement.  Buckets already in the table are
+   tuning table, which later builds consult.  Buckets already in the table are
    not re-timed.  *seconds (may be NULL) receives the time spent.  Work is
    enqueued on stream (NULL = default) and waited for. */
-hps_status hps_autotune(const hps_problem* probs, int nprob, int keep_factors, void* stream,
-                        double* seconds);
-/* Writes the tuning table as JSON (format "hps-tune-1") / merges such a file
-   into the table (HPS_EINVAL on a malformed file) / empties the table. */
+hps_status hps_autotune(const hps_problem* probs, int nprob, void* stream, double* seconds);
+/* Writes the tuning table as JSON (format "hps-tune-2") / merges such a file
+   into the table (HPS_EINVAL on a malformed file or another format: the
+   variant numbers of older formats meant other kernels) / empties the table. */
 hps_status hps_tune_save(const char* path);
 hps_status hps_tune_load(const char* path);
 hps_status hps_tune_reset(void);

@@ -372,13 +372,24 @@ def leaf_index_of(box: Box, nx: int) -> int:
     return box.i0 + nx * box.j0
 
 
-def build(coeffs: np.ndarray, box, nleaf, p: int, q: int, x_first=True, keep=True) -> Operator:
+def build(coeffs: np.ndarray, box, nleaf, p: int, q: int, x_first=True, keep=True,
+          allow_singular=False) -> Operator:
     """Algorithm 1 (build stage).
 
     ``coeffs`` has shape [nx*ny, 6, p*p] (leaf i + nx*j, node a + p*b).
     Boxes are processed from the last index to the first, so every parent
     comes after its children.
+
+    q must be below p.  Step 1 of section 3.2 maps the 4q Gauss values of a
+    leaf onto its 4(p-1) boundary Chebyshev nodes, averaging the two sides at
+    each corner; for q >= p that map has a null space, and at an interior
+    cross point the four edges can carry a mode +a, -a, +a, -a that none of
+    the four leaves sees, so the merge systems are singular.  (The leaf DtN
+    itself is still well defined: ``leaf_dtn`` accepts q = p.)
+    ``allow_singular`` lets the pins build such an operator on purpose.
     """
+    if q >= p and not allow_singular:
+        raise ValueError(f"q = {q} must be below p = {p}: with q >= p the merges are singular")
     nx, ny = nleaf
     grid = Grid(box, nx, ny, q)
     boxes = build_tree(nx, ny, x_first=x_first)
@@ -420,6 +431,22 @@ def solve(op: Operator, f: np.ndarray, z: Optional[Dict[int, np.ndarray]] = None
             u3 = u3 + z[t]
         u[:, b.Ii] = u3
     return u
+
+
+def level_conditions(op: Operator) -> np.ndarray:
+    """Per tree depth, the largest max|M| / min |u_kk| over its merges, where
+    M = T33a - T33b and u_kk are the pivots of its LU factorization with partial
+    pivoting (LAPACK getrf).  A cheap lower-side estimate of cond(M); the
+    deepest depth (leaves only) gets 0."""
+    depth = max(b.level for b in op.boxes)
+    out = np.zeros(depth + 1)
+    for t, mo in op.merges.items():
+        lu, _ = sla.lu_factor(mo.M, check_finite=False)
+        pmin = np.min(np.abs(np.diag(lu)))
+        est = np.max(np.abs(mo.M)) / pmin if pmin > 0 else np.inf
+        d = op.boxes[t].level
+        out[d] = max(out[d], est)
+    return out
 
 
 def gamma_xy(op: Operator) -> np.ndarray:

@@ -169,7 +169,7 @@ def tune_set(knob: str, value: int) -> None:
     check(lib.hps_tune_set(knob.encode(), int(value)))
 
 
-def autotune(shapes, keep_factors: bool = False, stream=None) -> float:
+def autotune(shapes, stream=None) -> float:
     """Times every kernel variant for the builds of the given problem shapes
     (dicts with nleaf, p, q and optionally box) and keeps the fastest per shape
     bucket in this process's tuning table.  Returns the seconds spent."""
@@ -182,7 +182,7 @@ def autotune(shapes, keep_factors: bool = False, stream=None) -> float:
         arr[i].nleaf[0], arr[i].nleaf[1] = int(sh["nleaf"][0]), int(sh["nleaf"][1])
         arr[i].p, arr[i].q = int(sh["p"]), int(sh["q"])
     sec = C.c_double()
-    check(lib.hps_autotune(arr, len(shapes), int(bool(keep_factors)), _stream(stream), C.byref(sec)))
+    check(lib.hps_autotune(arr, len(shapes), _stream(stream), C.byref(sec)))
     return sec.value
 
 
@@ -499,6 +499,14 @@ class Operator:
         check(lib.hps_export_S(self._h, b, _ptr(S), C.byref(r), C.byref(c)))
         return S
 
+    def level_conditions(self) -> np.ndarray:
+        """Per tree depth: the largest max|M| / min |pivot| of its merge systems M."""
+        n = C.c_int()
+        check(lib.hps_level_conditions(self._h, None, C.byref(n)))
+        out = np.zeros(n.value)
+        check(lib.hps_level_conditions(self._h, _ptr(out), C.byref(n)))
+        return out
+
     def export_root_dtn(self) -> np.ndarray:
         T = np.empty((self.n_bdry, self.n_bdry))
         check(lib.hps_export_root_dtn(self._h, _ptr(T)))
@@ -513,8 +521,9 @@ class Operator:
 
 def _build_opts(mode, stream, device_ptrs, keep_factors, root_dtn, surrogate=None,
                 judge_samples=64, judge_tol=1e-6, keep_leaf_solution=False,
-                keep_body_operator=False):
-    return BuildOpts(mode, stream, int(device_ptrs), 1, int(keep_factors), int(root_dtn), 0.0,
+                keep_body_operator=False, pivot_tol=0.0):
+    return BuildOpts(mode, stream, int(device_ptrs), 1, int(keep_factors), int(root_dtn),
+                     float(pivot_tol),
                      surrogate.handle if surrogate is not None else None, int(judge_samples),
                      float(judge_tol), int(keep_leaf_solution), int(keep_body_operator))
 
@@ -523,17 +532,19 @@ def build_solution_operator(coeffs, box, nleaf, p: int, q: int, mode: int = HPS_
                             keep_factors: bool = False, root_dtn: bool = True, surrogate=None,
                             judge_samples: int = 64, judge_tol: float = 1e-6,
                             keep_leaf_solution: bool = False,
-                            keep_body_operator: bool = False) -> Operator:
+                            keep_body_operator: bool = False,
+                            pivot_tol: float = 0.0) -> Operator:
     """Algorithm 1.  coeffs [nx*ny, 6, p*p] (c11, c12, c22, c1, c2, c at Chebyshev nodes).
     keep_leaf_solution keeps every leaf's interior solution operator for postprocess();
-    keep_body_operator keeps P1 A_ii^-1 per leaf for fast solve_body()."""
+    keep_body_operator keeps P1 A_ii^-1 per leaf for fast solve_body(); pivot_tol > 0
+    rejects near-singular leaf and merge systems (HPS_ESINGULAR)."""
     coeffs = _f64(coeffs)
     dev = _dev(coeffs)
     if surrogate is not None:
         mode = HPS_SURROGATE
     bo = _build_opts(mode, _stream(coeffs) if dev else None, dev, keep_factors, root_dtn,
                      surrogate, judge_samples, judge_tol, keep_leaf_solution,
-                     keep_body_operator)
+                     keep_body_operator, pivot_tol)
     h = C.c_void_p()
     check(lib.hps_build_solution_operator(_ptr(coeffs), (C.c_double * 4)(*box),
                                           (C.c_int * 2)(*nleaf), p, q, C.byref(bo), C.byref(h)))
@@ -542,7 +553,7 @@ def build_solution_operator(coeffs, box, nleaf, p: int, q: int, mode: int = HPS_
 
 def build_batch(problems: Sequence[dict], mode: int = HPS_FP64, keep_factors: bool = False,
                 root_dtn: bool = True, keep_leaf_solution: bool = False,
-                keep_body_operator: bool = False) -> List[Operator]:
+                keep_body_operator: bool = False, pivot_tol: float = 0.0) -> List[Operator]:
     """Heterogeneous batch; problems are dicts with coeffs (device), box, nleaf, p, q."""
     arr = (Problem * len(problems))()
     keep = []
@@ -557,7 +568,7 @@ def build_batch(problems: Sequence[dict], mode: int = HPS_FP64, keep_factors: bo
         arr[i].q = pr["q"]
     bo = _build_opts(mode, _stream(keep[0]), 1, keep_factors, root_dtn,
                      keep_leaf_solution=keep_leaf_solution,
-                     keep_body_operator=keep_body_operator)
+                     keep_body_operator=keep_body_operator, pivot_tol=pivot_tol)
     hs = (C.c_void_p * len(problems))()
     check(lib.hps_build_batch(arr, len(problems), C.byref(bo), hs))
     return [Operator(C.c_void_p(h)) for h in hs]

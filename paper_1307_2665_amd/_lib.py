@@ -1,6 +1,9 @@
 """ctypes declarations of include/hps.h and the loader of libhps.so.
 
-There is no fallback: if the HIP library is missing the import raises.
+The library is opened on first use, so that importing the package (for
+instance to run ``python -m paper_1307_2665_amd.build_lib`` on a clean tree)
+does not need it.  There is no fallback: the first call into a missing
+library raises ImportError.
 """
 from __future__ import annotations
 
@@ -85,7 +88,8 @@ SIGNATURES = {
     "hps_batched_gemm": [P, P, P, I, I, I, I, D, I, P],
     "hps_plan_box": [P, I, I, P, P, P, P, P, P, P, IP],
     "hps_tune_set": [C.c_char_p, I],
-    "hps_autotune": [C.POINTER(Problem), I, I, P, C.POINTER(D)],
+    "hps_autotune": [C.POINTER(Problem), I, P, C.POINTER(D)],
+    "hps_level_conditions": [P, P, IP],
     "hps_tune_save": [C.c_char_p],
     "hps_tune_load": [C.c_char_p],
     "hps_tune_reset": [],
@@ -130,7 +134,23 @@ def load() -> C.CDLL:
     return lib
 
 
-lib = load()
+class _LazyLib:
+    """Stands in for the CDLL until the first attribute access opens it."""
+
+    def __init__(self):
+        self._cdll = None
+
+    def __getattr__(self, name):
+        if self._cdll is None:
+            self._cdll = load()
+        return getattr(self._cdll, name)
+
+    @property
+    def loaded(self) -> bool:
+        return self._cdll is not None
+
+
+lib = _LazyLib()
 
 
 def check(status: int) -> None:

@@ -50,6 +50,8 @@ hps::BuildOptions to_build_options(const hps_build_opts* o) {
   b.surrogate = const_cast<hps_surrogate*>(o->surrogate);
   b.judge_samples = o->judge_samples > 0 ? o->judge_samples : 64;
   b.judge_tol = o->judge_tol > 0 ? o->judge_tol : 1e-6;
+  HPS_REQUIRE(o->pivot_tol >= 0.0 && o->pivot_tol < 1.0, "pivot_tol must be in [0, 1)");
+  b.pivot_tol = o->pivot_tol;
   return b;
 }
 
@@ -391,8 +393,17 @@ hps_status hps_export_S(const hps_op* op, int box, double* S, int* rows, int* co
     if (rows) *rows = d.m3;
     if (cols) *cols = d.me;
     if (S)
-      HPS_HIP(hipMemcpy2D(S, d.me * sizeof(double), d.S, d.ldw * sizeof(double),
+      HPS_HIP(hipMemcpy2D(S, d.me * sizeof(double), d.S, d.lds * sizeof(double),
                           d.me * sizeof(double), d.m3, hipMemcpyDeviceToHost));
+  });
+}
+
+hps_status hps_level_conditions(const hps_op* op, double* cond_est, int* n_levels) {
+  return guard([&] {
+    HPS_REQUIRE(op && n_levels, "bad arguments");
+    *n_levels = (int)op->level_cond.size();
+    if (cond_est)
+      for (size_t d = 0; d < op->level_cond.size(); ++d) cond_est[d] = op->level_cond[d];
   });
 }
 
@@ -498,7 +509,7 @@ hps_status hps_tune_set(const char* knob, int value) {
     } else if (k == "post_rows") {
       hps::set_post_rows(value);
     } else if (k == "gj_variant") {
-      HPS_REQUIRE(value >= -1 && value < 4 * hps::GEMM_VARIANTS && (value < 0 || value % 4 < 3),
+      HPS_REQUIRE(value >= -1 && value < 4 * hps::UPDATE_VARIANTS && (value < 0 || value % 4 < 3),
                   "gj_variant out of range");
       hps::tune_force(hps::TUNE_GJ, value);
     } else {
@@ -507,8 +518,7 @@ hps_status hps_tune_set(const char* knob, int value) {
   });
 }
 
-hps_status hps_autotune(const hps_problem* probs, int nprob, int keep_factors, void* stream,
-                        double* seconds) {
+hps_status hps_autotune(const hps_problem* probs, int nprob, void* stream, double* seconds) {
   return guard([&] {
     HPS_REQUIRE(probs != nullptr && nprob >= 1, "bad arguments");
     std::vector<hps::TuneShape> shapes;
@@ -518,7 +528,7 @@ hps_status hps_autotune(const hps_problem* probs, int nprob, int keep_factors, v
                   "bad problem shape");
       shapes.push_back(hps::TuneShape{p.nleaf[0], p.nleaf[1], p.p, p.q,
                                       (p.box[1] - p.box[0]) / p.nleaf[0],
-                                      (p.box[3] - p.box[2]) / p.nleaf[1], keep_factors != 0});
+                                      (p.box[3] - p.box[2]) / p.nleaf[1]});
     }
     const double t = hps::autotune(shapes, (hipStream_t)stream);
     if (seconds) *seconds = t;
@@ -553,7 +563,8 @@ hps_status hps_tune_reset(void) {
 hps_status hps_leaf_tables(int p, int q, double hx, double hy, double* Dx, double* Dy, double* Dxx,
                            double* Dyy, double* G, double* P0, double* P1, int* Ji) {
   return guard([&] {
-    HPS_REQUIRE(p >= 4 && p <= 24 && q >= 1 && q <= p && hx > 0 && hy > 0, "bad arguments");
+    HPS_REQUIRE(p >= 4 && p <= 24 && q >= 1 && q < p && hx > 0 && hy > 0,
+                "bad arguments (need 4 <= p <= 24, 1 <= q <= p - 1, hx, hy > 0)");
     hps::LeafTables t = hps::make_leaf_tables(p, q, hx, hy);
     auto put = [](double* dst, const std::vector<double>& v) {
       if (dst) std::memcpy(dst, v.data(), v.size() * sizeof(double));

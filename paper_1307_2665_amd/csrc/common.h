@@ -42,7 +42,22 @@ struct SolveDesc {
   int n, m, ld, ldx;
   int tag;         // caller's id (box or leaf), reported on singular pivots
   int pad;
+  // Pivot statistics of this system, or null: pstat[0] = max|M| and
+  // pstat[1] = min |pivot|, both as the bit patterns of non-negative doubles
+  // (which order like the integers), kept with atomicMax / atomicMin.
+  unsigned long long* pstat = nullptr;
 };
+
+// Bit pattern of |x| for the pivot statistics (NaN counts as +inf).
+__host__ __device__ inline unsigned long long abs_bits(double x) {
+  if (x != x) return 0x7FF0000000000000ull;
+  union {
+    double d;
+    unsigned long long u;
+  } c;
+  c.d = x < 0 ? -x : x;
+  return c.u;
+}
 
 // C (M x N, ldc) = C0 + alpha * A (M x K, lda) * B (K x N, ldb), all row-major
 // FP64, where C0 is the matrix at C0 (leading dimension ldc0) when C0 is not
@@ -63,6 +78,8 @@ struct GemmDesc {
   const double* Ta = nullptr;
   const double* Tb = nullptr;
   int na = 0, nb = 0;
+  // 1: C = alpha A B (the old C is neither read nor kept); 0: as above.
+  int overwrite = 0;
 };
 
 // One tile of a grouped GEMM launch: problem index and tile coordinates.
@@ -76,9 +93,10 @@ struct MergeDesc {
   const double* Ta;   // alpha's DtN, na x na
   const double* Tb;   // beta's DtN, nb x nb
   double* Tp;         // parent DtN, me x me (me = m1 + m2)
-  double* W;          // augmented [M | B (| I)], m3 x ldw; after the solve
-                      // [* | S (| M^-1)]
-  double* S;          // solution operator, m3 x me, leading dimension ldw (inside W)
+  double* W;          // merge system [M | I], m3 x ldw (ldw = 2 m3), M = T33a - T33b;
+                      // after the elimination W + m3 holds M^-1 (leading dimension ldw)
+  double* B;          // gathered right-hand sides [-T31a | T32b], m3 x me (leading dimension me)
+  double* S;          // solution operator S = M^-1 B (eq:U_parent), m3 x me, leading dimension lds
   double* Q;          // [T13a; T23b] in parent order, me x m3
   int* piv;           // m3 pivots
   const int* pmap;    // me entries: >= 0 position in alpha, < 0: -(position in beta) - 1
@@ -87,8 +105,9 @@ struct MergeDesc {
   const int* Ie;      // me global ids (parent boundary, S,E,N,W)
   const int* Ii;      // m3 global ids (shared edge)
   int na, nb, me, m3;
-  int box, ldw;       // ldw = m3 + me (+ m3 when M^-1 is kept)
-  int inv, pad;       // inv = 1: W carries the identity block, giving M^-1 at W + m3 + me
+  int box, ldw;       // ldw = 2 m3
+  int lds, pad;       // lds = me
+  unsigned long long* pstat = nullptr;  // the merge system's pivot statistics (SolveDesc)
 };
 
 // Solution array of the problem a merge belongs to (downward pass), and its

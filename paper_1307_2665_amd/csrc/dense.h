@@ -41,6 +41,15 @@ void grouped_gemm_v(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc,
 // while the next panel is factored.  Measured slower on config 2: the side
 // stream's update fills the CUs, and the next panel's lone workgroup waits.
 void set_gj_lookahead(bool on);
+
+// Pivot statistics of the systems (SolveDesc::pstat): pstat_init clears count
+// pairs (max|M| = 0, min |pivot| = none); system_absmax records max|M| of the
+// n x n block of every system with statistics before it is eliminated (nmax:
+// the largest n); after the elimination pivot_check sets status[0] = 1 and
+// status[1] = the tag of a system whose smallest pivot is <= tol max|M|.
+void pstat_init(unsigned long long* pstat, size_t count, hipStream_t s);
+void system_absmax(const SolveDesc* d_desc, int count, int nmax, hipStream_t s);
+void pivot_check(const SolveDesc* d_desc, int count, double tol, int* status, hipStream_t s);
 void dense_init();
 int max_solve_rows();
 

@@ -190,6 +190,7 @@ __global__ void __launch_bounds__(64 * TP_MAXW) k_gj_panel(const SolveDesc* __re
   __syncthreads();
   int ns = 0;
   bool stop = false;
+  double minp = INFINITY;  // smallest |pivot| of the panel (pivot statistics)
   // Step at which each of this lane's rows became a pivot row (-1: not yet).
   // A pivot row is no longer updated, so at the end its registers hold its
   // row of L \ U, which is then written out in one go.
@@ -251,6 +252,7 @@ __global__ void __launch_bounds__(64 * TP_MAXW) k_gj_panel(const SolveDesc* __re
     const double piv = prow[c], invp = sInvP[buf][gw];
     const bool ok = (piv != 0.0) && (piv == piv) && fabs(piv) != INFINITY;
     if (!ok && threadIdx.x == 0) sBad = 1;
+    minp = fmin(minp, fabs(piv));
     const double inv = ok ? invp : 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -270,7 +272,10 @@ __global__ void __launch_bounds__(64 * TP_MAXW) k_gj_panel(const SolveDesc* __re
 #pragma unroll
       for (int c2 = 0; c2 < KB; ++c2) sLU[sel[r]][c2] = x[r][c2];
     }
-  if (threadIdx.x == 0) sNs = ns;
+  if (threadIdx.x == 0) {
+    sNs = ns;
+    if (d.pstat && ns > 0) atomicMin(d.pstat + 1, abs_bits(minp));
+  }
   __syncthreads();
   panel_tail<KB>(d, k0, kb, sNs, sBad != 0, status, sLU, sKeep, sPi, sD, sV, sFlag, &sNd);
 }
@@ -312,6 +317,7 @@ __global__ void __launch_bounds__(64) k_gj_panel_w1(const SolveDesc* __restrict_
   }
   int ns = 0;
   bool stop = false, bad = false;
+  double minp = INFINITY;  // smallest |pivot| of the panel (pivot statistics)
   int sel[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) sel[r] = -1;
@@ -352,6 +358,7 @@ __global__ void __launch_bounds__(64) k_gj_panel_w1(const SolveDesc* __restrict_
     const double piv = prow[c];
     const bool ok = (piv != 0.0) && (piv == piv) && fabs(piv) != INFINITY;
     bad |= !ok;
+    minp = fmin(minp, fabs(piv));
     const double inv = ok ? 1.0 / piv : 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -369,6 +376,7 @@ __global__ void __launch_bounds__(64) k_gj_panel_w1(const SolveDesc* __restrict_
 #pragma unroll
       for (int c2 = 0; c2 < KB; ++c2) sLU[sel[r]][c2] = x[r][c2];
     }
+  if (lane == 0 && d.pstat && ns > 0) atomicMin(d.pstat + 1, abs_bits(minp));
   __syncthreads();
   panel_tail<KB>(d, k0, kb, ns, bad, status, sLU, sKeep, sPi, sD, sV, sFlag, &sNd);
 }
@@ -515,7 +523,8 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm(const GemmDesc* __restric
   else
     gemm_tile_map<BM, BN, BK, WM, WN, RowsIdentity, RowsIdentity, RowsIdentity, NoC0Elem, false,
                   DEPTH>(g.A, g.lda, g.B, g.ldb, RowsIdentity{}, g.C, g.ldc, RowsIdentity{}, g.C0,
-                         g.ldc0, g.M, g.N, g.K, g.alpha, blockIdx.y * BM, blockIdx.x * BN, sm, true);
+                         g.ldc0, g.M, g.N, g.K, g.alpha, blockIdx.y * BM, blockIdx.x * BN, sm,
+                         g.overwrite == 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -636,7 +645,8 @@ __global__ void __launch_bounds__(256) k_gemm_split32(const GemmDesc* __restrict
         int gc = col0 + wn * 32 + j * 16 + (lane & 15);
         if (gr < g.M && gc < g.N) {
           double c0 = g.pmap ? merge_pass(g)(gr, gc)
-                             : (g.C0 ? g.C0[(size_t)gr * g.ldc0 + gc] : g.C[(size_t)gr * g.ldc + gc]);
+                      : g.C0 ? g.C0[(size_t)gr * g.ldc0 + gc]
+                      : g.overwrite ? 0.0 : g.C[(size_t)gr * g.ldc + gc];
           g.C[(size_t)gr * g.ldc + gc] = c0 + g.alpha * acc[i][j][r];
         }
       }
@@ -825,8 +835,8 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x6(const GemmDesc* __restrict_
         const int gc = col0 + j * 16 + (lane & 15);
         if (gr < g.M && gc < g.N) {
           const double c0 = g.pmap ? merge_pass(g)(gr, gc)
-                                   : (g.C0 ? g.C0[(size_t)gr * g.ldc0 + gc]
-                                           : g.C[(size_t)gr * g.ldc + gc]);
+                            : g.C0 ? g.C0[(size_t)gr * g.ldc0 + gc]
+                            : g.overwrite ? 0.0 : g.C[(size_t)gr * g.ldc + gc];
           g.C[(size_t)gr * g.ldc + gc] =
               c0 + g.alpha * (acc[i][j][r] + (double)small[i][j][r]);
         }
@@ -927,6 +937,7 @@ static void launch_update(int v, const SolveDesc* d_desc, int np, int k0, int nb
                          dim3(64 * WM * WN), 0, s, d_desc, k0, nb, coff_lo, coff_hi);       \
     return;                                                                                 \
   }
+  // Tile variants as listed at UPDATE_VARIANTS (tune.h).
   switch (v) {
     case 1: HPS_UPD(32, 32, 16, 1, 1)
     case 2: HPS_UPD(128, 128, 16, 4, 2)
@@ -1112,6 +1123,68 @@ void grouped_gemm(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, h
                   int prec) {
   if (h_desc.empty()) return;
   grouped_gemm_v(d_desc, h_desc, stream, prec != GEMM_F64 ? 0 : gemm_bucket_variant(h_desc), prec);
+}
+
+// ---------------------------------------------------------------------------
+// Pivot statistics: max|M| of a system before its elimination, the smallest
+// pivot magnitude after it, and the relative pivot test |pivot| <= tol max|M|.
+// ---------------------------------------------------------------------------
+__global__ void k_pstat_init(unsigned long long* __restrict__ pstat, size_t count) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * blockDim.x) {
+    pstat[2 * i] = 0ull;
+    pstat[2 * i + 1] = ~0ull;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_sys_absmax(const SolveDesc* __restrict__ descs) {
+  const SolveDesc d = descs[blockIdx.y];
+  if (!d.pstat) return;
+  const size_t tot = (size_t)d.n * d.n;
+  double amax = 0.0;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
+       e += (size_t)gridDim.x * blockDim.x)
+    amax = fmax(amax, fabs(d.W[(e / d.n) * d.ld + e % d.n]));
+  __shared__ double red[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (m > 0.0) atomicMax(d.pstat, abs_bits(m));
+  }
+}
+
+__global__ void k_pivot_check(const SolveDesc* __restrict__ descs, int count, double tol,
+                              int* status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const SolveDesc d = descs[i];
+  if (!d.pstat) return;
+  const double amax = __longlong_as_double((long long)d.pstat[0]);
+  const unsigned long long pb = d.pstat[1];
+  const double pmin = pb >= 0x7FF0000000000000ull ? INFINITY : __longlong_as_double((long long)pb);
+  if (pmin <= tol * amax)
+    if (atomicCAS(status, 0, 1) == 0) status[1] = d.tag;
+}
+
+void pstat_init(unsigned long long* pstat, size_t count, hipStream_t s) {
+  if (count == 0) return;
+  const int blocks = (int)std::min<size_t>((count + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_pstat_init, dim3(blocks), dim3(256), 0, s, pstat, count);
+}
+
+void system_absmax(const SolveDesc* d_desc, int count, int nmax, hipStream_t s) {
+  if (count == 0) return;
+  const int bx = (int)std::min<size_t>(((size_t)nmax * nmax + 255) / 256, 64);
+  hipLaunchKernelGGL(k_sys_absmax, dim3(bx, count), dim3(256), 0, s, d_desc);
+}
+
+void pivot_check(const SolveDesc* d_desc, int count, double tol, int* status, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_pivot_check, dim3((count + 255) / 256), dim3(256), 0, s, d_desc, count, tol,
+                     status);
 }
 
 void dense_init() {}

@@ -10,12 +10,13 @@ namespace hps {
 bool leaf_lu_fits(int n, int m);
 
 // Z[leaf] = A_ii^-1 R for count leaves (coefficients cptr[leaf]); Z is [count][n][m].
-// status[0] becomes 1 and status[1] = tag0 - leaf on a zero or non-finite pivot.
+// status[0] becomes 1 and status[1] = tag0 - leaf on a zero or non-finite pivot,
+// or (tol > 0) on a pivot with |pivot| <= tol max|A_ii|.
 // Kernel variant: 0-2 step-by-step LU (16x16 threads for p <= 12, 16x64, 16x32), 3-4
 // blocked Gauss-Jordan (16x16 threads, 9-column blocks; 16x32 threads, 8-column blocks).
 void leaf_lu_set_variant(int v);
 
 void leaf_lu(const double* const* cptr, const LeafDev& tab, int count, double* Z, int* status,
-             int tag0, hipStream_t s);
+             int tag0, hipStream_t s, double tol = 0.0);
 
 }  // namespace hps

@@ -19,10 +19,25 @@
 
 namespace hps {
 
+// Pivot threshold of a leaf system: tol * max|A_ii| over the workgroup (every
+// thread passes its largest magnitude; all threads get the threshold), or 0
+// when tol is 0 (then only exactly zero pivots are rejected).
+__device__ inline double leaf_pivot_threshold(double mine, double tol, double* red) {
+  if (!(tol > 0.0)) return 0.0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mine = fmax(mine, __shfl_xor(mine, off));
+  const int nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mine;
+  __syncthreads();
+  double m = 0.0;
+  for (int w = 0; w < nw; ++w) m = fmax(m, red[w]);
+  return tol * m;
+}
+
 template <int TR, int TC, int NR, int NC>
 __global__ void __launch_bounds__(TR * TC) k_leaf_lu(const double* const* __restrict__ cptr,
                                                      const LeafDev tab, double* __restrict__ Z,
-                                                     int* status, int tag0) {
+                                                     int* status, int tag0, double tol) {
   static_assert(TC % TR == 0, "column tile must be a multiple of the row tile");
   constexpr int NT = TR * TC;
   __shared__ double sD[4][24 * 24];
@@ -76,6 +91,14 @@ __global__ void __launch_bounds__(TR * TC) k_leaf_lu(const double* const* __rest
       a[s][t] = v;
     }
   }
+  __shared__ double sRed[16];
+  double mine = 0.0;
+#pragma unroll
+  for (int s = 0; s < NR; ++s)
+#pragma unroll
+    for (int t = 0; t < NC; ++t)
+      if (tr + TR * s < n && tc + TC * t < n) mine = fmax(mine, fabs(a[s][t]));
+  const double thr = leaf_pivot_threshold(mine, tol, sRed);
 
   // ---- forward elimination with partial pivoting ----
 #pragma unroll
@@ -148,7 +171,7 @@ __global__ void __launch_bounds__(TR * TC) k_leaf_lu(const double* const* __rest
         if (tr == kk && pr != k) Lb[buf][pr] = a[ks][ts] * inv;  // old row k moves to pr
         if (tr == 0) dinv[k] = inv;
       }
-      if (tid == 0 && (piv == 0.0 || piv != piv))
+      if (tid == 0 && (piv == 0.0 || piv != piv || fabs(piv) <= thr))
         if (atomicCAS(status, 0, 1) == 0) status[1] = tag0 - (int)blockIdx.x;
       __syncthreads();
       if (pr != k) {
@@ -280,7 +303,7 @@ __device__ inline unsigned row16_max(unsigned k) {
 template <int TC, int NR, int NC>
 __global__ void __launch_bounds__(16 * TC) k_leaf_gj(const double* const* __restrict__ cptr,
                                                      const LeafDev tab, double* __restrict__ Z,
-                                                     int* status, int tag0) {
+                                                     int* status, int tag0, double tol) {
   constexpr int TR = 16, NT = TR * TC, NROW = NR * TR;
   static_assert(NROW <= 208, "pivot keys hold slots below 208");
   __shared__ double sD[4][24 * 24];
@@ -340,6 +363,15 @@ __global__ void __launch_bounds__(16 * TC) k_leaf_gj(const double* const* __rest
     }
   }
 
+  __shared__ double sRed[16];
+  double mine = 0.0;
+#pragma unroll
+  for (int s = 0; s < NR; ++s)
+#pragma unroll
+    for (int t = 0; t < NC; ++t)
+      if (tr + TR * s < n && NC * tc + t < n) mine = fmax(mine, fabs(a[s][t]));
+  const double thr = leaf_pivot_threshold(mine, tol, sRed);
+
   // Rows already chosen as pivots (bit s: row tr + 16 s); padding rows count as chosen.
   unsigned done = 0;
 #pragma unroll
@@ -373,7 +405,7 @@ __global__ void __launch_bounds__(16 * TC) k_leaf_gj(const double* const* __rest
       const int sp = slot / TR, trp = slot % TR;
       if (tr == trp) done |= 1u << sp;
       const double piv = sA[buf][slot % TR][slot / TR];
-      const bool ok = (piv != 0.0) && (piv == piv) && fabs(piv) != INFINITY;
+      const bool ok = (piv != 0.0) && (piv == piv) && fabs(piv) != INFINITY && fabs(piv) > thr;
       if (!ok && tid == 0)
         if (atomicCAS(status, 0, 1) == 0) status[1] = tag0 - (int)blockIdx.x;
       // Columns of this thread that are still to be updated: j > k.
@@ -439,7 +471,7 @@ static int g_leaf_variant = -1;  // -1: default choice; else forced variant inde
 void leaf_lu_set_variant(int v) { g_leaf_variant = v; }
 
 void leaf_lu(const double* const* cptr, const LeafDev& tab, int count, double* Z, int* status,
-             int tag0, hipStream_t s) {
+             int tag0, hipStream_t s, double tol) {
   const double n = tab.n, m = tab.m;
   ProfScope ps(PROF_LEAF_LU, s, count * (2.0 * n * n * n / 3.0 + 2.0 * n * n * m), 0);
   const bool small = tab.n <= 7 * 16 && tab.n + tab.m <= 9 * 16;
@@ -450,23 +482,23 @@ void leaf_lu(const double* const* cptr, const LeafDev& tab, int count, double* Z
   switch (v) {
     case 0:
       hipLaunchKernelGGL((k_leaf_lu<16, 16, 7, 9>), dim3(count), dim3(256), 0, s, cptr, tab, Z,
-                         status, tag0);
+                         status, tag0, tol);
       break;
     case 1:
       hipLaunchKernelGGL((k_leaf_lu<16, 64, 13, 4>), dim3(count), dim3(1024), 0, s, cptr, tab, Z,
-                         status, tag0);
+                         status, tag0, tol);
       break;
     case 2:
       hipLaunchKernelGGL((k_leaf_lu<16, 32, 13, 8>), dim3(count), dim3(512), 0, s, cptr, tab, Z,
-                         status, tag0);
+                         status, tag0, tol);
       break;
     case 3:
       hipLaunchKernelGGL((k_leaf_gj<16, 7, 9>), dim3(count), dim3(256), 0, s, cptr, tab, Z, status,
-                         tag0);
+                         tag0, tol);
       break;
     default:
       hipLaunchKernelGGL((k_leaf_gj<32, 13, 8>), dim3(count), dim3(512), 0, s, cptr, tab, Z,
-                         status, tag0);
+                         status, tag0, tol);
       break;
   }
 }

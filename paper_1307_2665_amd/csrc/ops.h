@@ -42,6 +42,8 @@ void copy_rows_batch(const double* const* src, double* const* dst, int count, in
 // uc [nrhs][nleaf][pp]: adds wpart [nrhs][nleaf][n] at the interior nodes post_node[0..n).
 void add_particular(double* uc, const double* wpart, const int* post_node, int n, int pp,
                     int nleaf, int nrhs, hipStream_t s);
+// W = [M | I], B and Q of every merge (max_elems: the largest merge's element
+// count of the three), and max|M| into each merge's pivot statistics.
 void merge_gather(const MergeDesc* d_desc, int nmerge, size_t max_elems, hipStream_t s);
 // Downward pass of one depth; io[i] gives merge i's solution array (io null:
 // every merge uses io0).  s_bytes: bytes of all S of the launch (its

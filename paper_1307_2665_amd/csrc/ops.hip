@@ -245,37 +245,54 @@ void add_particular(double* uc, const double* wpart, const int* post_node, int n
 
 // ---------------------------------------------------------------------------
 // Merge gather (section 4, eq:premerge blocks): for each merge build
-//   W = [T33a - T33b | -T31a, T32b] (m3 x (m3 + me), columns of B in parent order),
-//   Q = [T13a; T23b] (me x m3, rows in parent order).
-// The parent's diag(T11a, T22b) is not formed: the Schur product reads it
-// from the children's DtNs as it writes T = diag(T11a, T22b) + Q S.
+//   W = [T33a - T33b | I] (m3 x 2 m3), whose elimination leaves M^-1,
+//   B = [-T31a, T32b]     (m3 x me, columns in parent order),
+//   Q = [T13a; T23b]      (me x m3, rows in parent order),
+// and record max|M| in the merge's pivot statistics.  The parent's
+// diag(T11a, T22b) is not formed: the Schur product reads it from the
+// children's DtNs as it writes T = diag(T11a, T22b) + Q S.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_merge_gather(const MergeDesc* __restrict__ descs) {
   const MergeDesc d = descs[blockIdx.y];
   const int m3 = d.m3, me = d.me, ldw = d.ldw;
-  const size_t nW = (size_t)m3 * ldw, nQ = (size_t)me * m3;
-  const size_t tot = nW + nQ;
+  const size_t nW = (size_t)m3 * ldw, nB = (size_t)m3 * me, nQ = (size_t)me * m3;
+  const size_t tot = nW + nB + nQ;
+  double amax = 0.0;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
        e += (size_t)gridDim.x * blockDim.x) {
     if (e < nW) {
-      int i = (int)(e / ldw), j = (int)(e % ldw);
-      int ra = d.a3[i], rb = d.b3[i];
+      const int i = (int)(e / ldw), j = (int)(e % ldw);
       double v;
       if (j < m3) {
-        v = d.Ta[(size_t)ra * d.na + d.a3[j]] - d.Tb[(size_t)rb * d.nb + d.b3[j]];
-      } else if (j < m3 + me) {
-        int pm = d.pmap[j - m3];
-        v = (pm >= 0) ? -d.Ta[(size_t)ra * d.na + pm] : d.Tb[(size_t)rb * d.nb + (-pm - 1)];
+        v = d.Ta[(size_t)d.a3[i] * d.na + d.a3[j]] - d.Tb[(size_t)d.b3[i] * d.nb + d.b3[j]];
+        amax = fmax(amax, fabs(v));
       } else {
-        v = (j - m3 - me == i) ? 1.0 : 0.0;  // identity block -> M^-1
+        v = (j - m3 == i) ? 1.0 : 0.0;
       }
       d.W[e] = v;
+    } else if (e < nW + nB) {
+      const size_t f = e - nW;
+      const int i = (int)(f / me), j = (int)(f % me);
+      const int pm = d.pmap[j];
+      d.B[f] = (pm >= 0) ? -d.Ta[(size_t)d.a3[i] * d.na + pm]
+                         : d.Tb[(size_t)d.b3[i] * d.nb + (-pm - 1)];
     } else {
-      size_t f = e - nW;
-      int r = (int)(f / m3), i = (int)(f % m3);
-      int pm = d.pmap[r];
+      const size_t f = e - nW - nB;
+      const int r = (int)(f / m3), i = (int)(f % m3);
+      const int pm = d.pmap[r];
       d.Q[f] = (pm >= 0) ? d.Ta[(size_t)pm * d.na + d.a3[i]]
                          : d.Tb[(size_t)(-pm - 1) * d.nb + d.b3[i]];
+    }
+  }
+  if (d.pstat) {
+    __shared__ double red[4];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+      if (m > 0.0) atomicMax(d.pstat, abs_bits(m));
     }
   }
 }
@@ -335,7 +352,7 @@ struct RowUpZ {
   }
   __device__ int rows() const { return d.m3; }
   __device__ int cols() const { return d.m3; }
-  __device__ const double* row(int r) const { return d.W + d.m3 + d.me + (size_t)r * d.ldw; }
+  __device__ const double* row(int r) const { return d.W + d.m3 + (size_t)r * d.ldw; }
   struct Key {
     int g, a, b;
   };
@@ -561,7 +578,7 @@ __global__ void __launch_bounds__(256) k_downward(const MergeDesc* __restrict__ 
 #pragma unroll
       for (int g = 0; g < RPW; ++g) {
         const int r = rbase + g;
-        const double* Srow = d.S + (size_t)r * d.ldw;
+        const double* Srow = d.S + (size_t)r * d.lds;
 #pragma unroll
         for (int l = 0; l < L; ++l) {
           const int c = cb + lane + 64 * l;
@@ -1072,14 +1089,14 @@ __global__ void __launch_bounds__(64 * WM * WN) k_down_mm(const MergeDesc* __res
   if (row0 >= d.m3 || col0 >= nrhs) return;
   if (ks == 1) {
     const double* z = zbase ? zbase + zoff[mi] * nrhs : nullptr;
-    gemm_tile_map_d<BM, BN, BK, WM, WN, 3>(d.S, d.ldw, U, nrhs, RowsIndexed{d.Ie}, U, nrhs,
+    gemm_tile_map_d<BM, BN, BK, WM, WN, 3>(d.S, d.lds, U, nrhs, RowsIndexed{d.Ie}, U, nrhs,
                                       RowsIndexed{d.Ii}, z, nrhs, d.m3, nrhs, d.me, 1.0, row0,
                                       col0, sm, false);
     return;
   }
   const int kchunk = ((d.me + ks - 1) / ks + BK - 1) / BK * BK;
   const int k0 = min(d.me, kc * kchunk), K = min(kchunk, d.me - k0);
-  gemm_tile_map_d<BM, BN, BK, WM, WN, 3>(d.S + k0, d.ldw, U, nrhs, RowsIndexed{d.Ie + k0},
+  gemm_tile_map_d<BM, BN, BK, WM, WN, 3>(d.S + k0, d.lds, U, nrhs, RowsIndexed{d.Ie + k0},
                                     P + (size_t)blockIdx.z * m3_max * nrhs, nrhs, RowsIdentity{},
                                     nullptr, 0, d.m3, nrhs, K, 1.0, row0, col0, sm, false);
 }
@@ -1333,7 +1350,7 @@ __global__ void __launch_bounds__(64 * WM * WN) k_up_z_mm(const MergeDesc* __res
   const int kchunk = ((d.m3 + ks - 1) / ks + BK - 1) / BK * BK;
   const int k0 = min(d.m3, kc * kchunk), K = min(kchunk, d.m3 - k0);
   double* C = ks == 1 ? zbuf + o : P + (size_t)blockIdx.z * rows_max * nrhs;
-  gemm_tile_map_d<BM, BN, BK, WM, WN, 3>(d.W + d.m3 + d.me + k0, d.ldw, rbuf + o + (size_t)k0 * nrhs,
+  gemm_tile_map_d<BM, BN, BK, WM, WN, 3>(d.W + d.m3 + k0, d.ldw, rbuf + o + (size_t)k0 * nrhs,
                                     nrhs, RowsIdentity{}, C, nrhs, RowsIdentity{}, nullptr, 0,
                                     d.m3, nrhs, K, 1.0, row0, col0, sm, false);
 }

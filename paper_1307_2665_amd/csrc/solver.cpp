@@ -226,7 +226,9 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
                                       int p, int q, const BuildOptions& o) {
   HPS_REQUIRE(coeffs != nullptr && box != nullptr && nleaf != nullptr, "null argument");
   HPS_REQUIRE(p >= 4 && p <= 24, "p must be in [4, 24]");
-  HPS_REQUIRE(q >= 1 && q <= p, "q must satisfy 1 <= q <= p (q > p makes the merges singular)");
+  HPS_REQUIRE(q >= 1 && q < p,
+              "q must satisfy 1 <= q <= p - 1 (with q >= p the corner averaging of L1 leaves a "
+              "null mode at every interior cross point, so the merges are singular)");
   HPS_REQUIRE(nleaf[0] >= 1 && nleaf[1] >= 1, "nleaf must be >= 1");
   HPS_REQUIRE(std::isfinite(box[0]) && std::isfinite(box[1]) && std::isfinite(box[2]) &&
                   std::isfinite(box[3]) && box[1] > box[0] && box[3] > box[2],
@@ -284,24 +286,37 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
   }
   if (o.keep_body) op->leafK = op->mem.alloc<double>(nl * (size_t)(p - 2) * (p - 2) * m);
 
-  // W (augmented system, later S and M^-1) and pivots are kept for every merge;
-  // Q is kept only when the upward pass is wanted, else one level of scratch.
-  long long totW = 0, totQ = 0, totP = 0, maxQ = 0, totS = 0;
+  // Per merge: the system W = [M | I] (whose elimination leaves M^-1), the
+  // gathered right-hand sides B = [-T31a | T32b] and Q = [T13a; T23b].  S =
+  // M^-1 B and the pivots are kept for every merge.  W and Q are kept too when
+  // the upward pass is wanted (keep_factors); otherwise they, like B always,
+  // live in one level of scratch that every level reuses.
+  long long totW = 0, totQ = 0, totP = 0, totS = 0, maxW = 0, maxQ = 0, maxB = 0;
+  size_t nmerges = 0;
   for (const auto& lv : P.levels) {
-    long long lq = 0;
+    long long lw = 0, lq = 0, lb = 0;
     for (const MergeRec& r : lv) {
       totS += (long long)r.m3 * r.me;
-      totW += (long long)r.m3 * (r.m3 + r.me + (keep ? r.m3 : 0));
+      lw += 2LL * r.m3 * r.m3;
       lq += (long long)r.me * r.m3;
+      lb += (long long)r.m3 * r.me;
       totP += r.m3;
+      ++nmerges;
     }
+    totW += lw;
     totQ += lq;
+    maxW = std::max(maxW, lw);
     maxQ = std::max(maxQ, lq);
+    maxB = std::max(maxB, lb);
   }
   op->bytes_S = totS * (long long)sizeof(double);
-  op->Wk = op->mem.alloc<double>(totW);
+  op->Sk = op->mem.alloc<double>(totS);
+  op->Wk = op->mem.alloc<double>(keep ? totW : maxW);
   op->Q = op->mem.alloc<double>(keep ? totQ : maxQ);
+  op->Bk = op->mem.alloc<double>(maxB);
   op->piv = op->mem.alloc<int>(totP);
+  op->n_merges = nmerges;
+  op->pstat = op->mem.alloc<unsigned long long>(2 * std::max<size_t>(nmerges, 1));
   op->arena[0] = op->mem.alloc<double>(P.ar[0]);
   op->arena[1] = op->mem.alloc<double>(P.ar[1]);
 
@@ -309,26 +324,29 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
   op->levels.assign(t.depth + 1, LevelPlan());
   op->merge_level.assign(t.boxes.size(), -1);
   op->merge_index.assign(t.boxes.size(), -1);
-  long long oW = 0, oQ = 0, oP = 0, oz = 0;
+  long long oW = 0, oQ = 0, oP = 0, oz = 0, oS = 0, oB = 0;
+  size_t mi = 0;
   const int n_int = (p - 2) * (p - 2);
   long long flops = (long long)nl * ((2LL * n_int * n_int * n_int) / 3 + 2LL * n_int * n_int * m +
                                      2LL * m * m * n_int);
   for (int d = 0; d <= t.depth; ++d) {
     LevelPlan& L = op->levels[d];
-    if (!keep) oQ = 0;
+    if (!keep) oW = oQ = 0;
+    oB = 0;
     for (const MergeRec& r : P.levels[d]) {
       const int b = r.box;
       const BoxRec& B = t.boxes[b];
       MergeDesc md{};
       // Ta, Tb are set below, once every parent DtN has its place.
       md.Tp = op->arena[d % 2] + r.Toff;
-      const int ldw = r.m3 + r.me + (keep ? r.m3 : 0);
       md.W = op->Wk + oW;
-      md.S = md.W + r.m3;
-      md.ldw = ldw;
-      md.inv = keep ? 1 : 0;
+      md.ldw = 2 * r.m3;
+      md.B = op->Bk + oB;
+      md.S = op->Sk + oS;
+      md.lds = r.me;
       md.Q = op->Q + oQ;
       md.piv = op->piv + oP;
+      md.pstat = op->pstat + 2 * mi;
       const int* base = P.dpool + r.pool_off;
       md.pmap = base;
       md.a3 = base + r.me;
@@ -343,10 +361,14 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
       op->merge_level[b] = d;
       op->merge_index[b] = (int)L.h.size();
       L.h.push_back(md);
-      SolveDesc sd{md.W, md.piv, md.W + r.m3, r.m3, ldw - r.m3, ldw, ldw, b, 0};
+      SolveDesc sd{md.W, md.piv, md.W + r.m3, r.m3, r.m3, md.ldw, md.ldw, b, 0, md.pstat};
       L.hs.push_back(sd);
+      // S = M^-1 B (FP64 in every mode).
+      GemmDesc sg{md.W + r.m3, md.B, md.S, nullptr, r.m3, r.me, r.m3, md.ldw, r.me, r.me, 0, 1.0};
+      sg.overwrite = 1;
+      L.hsg.push_back(sg);
       if (b != 0 || op->opt.root_dtn) {
-        GemmDesc gd{md.Q, md.S, md.Tp, nullptr, r.me, r.me, r.m3, r.m3, ldw, r.me, 0, 1.0,
+        GemmDesc gd{md.Q, md.S, md.Tp, nullptr, r.me, r.me, r.m3, r.m3, r.me, r.me, 0, 1.0,
                     md.pmap, md.Ta, md.Tb, md.na, md.nb};
         L.hg.push_back(gd);
       }
@@ -362,11 +384,15 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
       L.zo.push_back(oz);
       L.m3_max = std::max(L.m3_max, r.m3);
       L.me_max = std::max(L.me_max, r.me);
-      L.gather_max = std::max(L.gather_max, (size_t)r.m3 * ldw + (size_t)r.me * r.m3);
-      oW += (long long)r.m3 * ldw;
+      L.gather_max =
+          std::max(L.gather_max, (size_t)r.m3 * md.ldw + 2 * (size_t)r.me * r.m3);
+      oW += 2LL * r.m3 * r.m3;
       oQ += (long long)r.me * r.m3;
+      oB += (long long)r.m3 * r.me;
+      oS += (long long)r.m3 * r.me;
       oP += r.m3;
       oz += r.m3;
+      ++mi;
       flops += (2LL * r.m3 * r.m3 * r.m3) / 3 + 2LL * r.m3 * r.m3 * r.me;
       if (b != 0 || op->opt.root_dtn) flops += 2LL * r.me * r.me * r.m3;
     }
@@ -407,13 +433,14 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
     total += (bytes + 255) & ~size_t(255);
     return o;
   };
-  struct Off { size_t h, hs, hg, ha, hb, hp, zo, hab, hbb; };
+  struct Off { size_t h, hs, hg, hsg, ha, hb, hp, zo, hab, hbb; };
   std::vector<Off> offs(op->levels.size());
   for (size_t d = 0; d < op->levels.size(); ++d) {
     const LevelPlan& L = op->levels[d];
     if (L.h.empty()) continue;
     offs[d] = Off{reserve(L.h.size() * sizeof(MergeDesc)), reserve(L.hs.size() * sizeof(SolveDesc)),
-                  reserve(L.hg.size() * sizeof(GemmDesc)), reserve(L.ha.size() * 8),
+                  reserve(L.hg.size() * sizeof(GemmDesc)), reserve(L.hsg.size() * sizeof(GemmDesc)),
+                  reserve(L.ha.size() * 8),
                   reserve(L.hb.size() * 8), reserve(L.hp.size() * 8), reserve(L.zo.size() * 8),
                   reserve(L.hab.size() * 8), reserve(L.hbb.size() * 8)};
   }
@@ -430,6 +457,7 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
     L.d = (MergeDesc*)put(f.h, L.h.data(), L.h.size() * sizeof(MergeDesc));
     L.ds = (SolveDesc*)put(f.hs, L.hs.data(), L.hs.size() * sizeof(SolveDesc));
     L.dg = (GemmDesc*)put(f.hg, L.hg.data(), L.hg.size() * sizeof(GemmDesc));
+    L.dsg = (GemmDesc*)put(f.hsg, L.hsg.data(), L.hsg.size() * sizeof(GemmDesc));
     L.dha = (long long*)put(f.ha, L.ha.data(), L.ha.size() * 8);
     L.dhb = (long long*)put(f.hb, L.hb.data(), L.hb.size() * 8);
     L.dhp = (long long*)put(f.hp, L.hp.data(), L.hp.size() * 8);
@@ -453,7 +481,7 @@ struct LeafJob {
 };
 
 static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hipStream_t s,
-                           int* dstatus, int panel) {
+                           int* dstatus, int panel, double tol = 0.0) {
   const LeafPlan& L0 = *jobs[0].lp;
   const int p = L0.lt.p, q = L0.lt.q, n = (p - 2) * (p - 2), m = 4 * q, ld = n + m;
   LeafDev tab{L0.dDx, L0.dDy, L0.dDxx, L0.dDyy, L0.dG, p, n, m, 0};
@@ -473,6 +501,9 @@ static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hip
   for (const LeafJob& j : jobs) keepZ = keepZ || j.zdst;
   const double** dzs = keepZ ? tmp.alloc<const double*>(CH) : nullptr;
   double** dzd = keepZ ? tmp.alloc<double*>(CH) : nullptr;
+  // Pivot statistics of the generic path's systems (relative pivot test).
+  unsigned long long* dps = (!fused && tol > 0.0) ? tmp.alloc<unsigned long long>(2 * (size_t)CH)
+                                                  : nullptr;
   for (int c0 = 0; c0 < total; c0 += CH) {
     const int cnt = std::min(CH, total - c0);
     std::vector<const double*> cp(cnt);
@@ -486,18 +517,24 @@ static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hip
         gd[i] = GemmDesc{j.lp->dP1, Zl, j.dst, j.lp->dP0, m, m, n, n, m, m, m, -1.0};
       } else {
         double* W = Wslab + (size_t)i * n * ld;
-        sd[i] = SolveDesc{W, pslab + (size_t)i * n, W + n, n, m, ld, ld, -(j.leaf + 1), 0};
+        sd[i] = SolveDesc{W, pslab + (size_t)i * n, W + n, n, m, ld, ld, -(j.leaf + 1), 0,
+                          dps ? dps + 2 * (size_t)i : nullptr};
         gd[i] = GemmDesc{j.lp->dP1, W + n, j.dst, j.lp->dP0, m, m, n, n, ld, m, m, -1.0};
       }
     }
     HPS_HIP(hipMemcpyAsync(dcp, cp.data(), cnt * sizeof(void*), hipMemcpyHostToDevice, s));
     HPS_HIP(hipMemcpyAsync(dgd, gd.data(), cnt * sizeof(GemmDesc), hipMemcpyHostToDevice, s));
     if (fused) {
-      leaf_lu(dcp, tab, cnt, Wslab, dstatus, -(jobs[c0].leaf + 1), s);
+      leaf_lu(dcp, tab, cnt, Wslab, dstatus, -(jobs[c0].leaf + 1), s, tol);
     } else {
       HPS_HIP(hipMemcpyAsync(dsd, sd.data(), cnt * sizeof(SolveDesc), hipMemcpyHostToDevice, s));
       leaf_assemble(dcp, tab, cnt, Wslab, s);
+      if (dps) {
+        pstat_init(dps, cnt, s);
+        system_absmax(dsd, cnt, n, s);
+      }
       batched_solve(dsd, sd, dstatus, s, panel);
+      if (dps) pivot_check(dsd, cnt, tol, dstatus, s);
     }
     grouped_gemm(dgd, gd, s, GEMM_F64);
     // Kept Z goes out transposed ([4q][(p-2)^2]) for the post-processing loads.
@@ -610,7 +647,7 @@ static void surrogate_leaf_stage(hps_op* op, DeviceMem& tmp, hipStream_t s, int*
     jobs[i] = LeafJob{&op->leaf(), judged[i], cp[judged[i]], ref + (size_t)i * mm};
     jp[i] = tp[judged[i]];
   }
-  run_leaf_group(jobs, tmp, s, dstatus, op->opt.panel);
+  run_leaf_group(jobs, tmp, s, dstatus, op->opt.panel, op->opt.pivot_tol);
   double** djp = tmp.upload(jp, s);
   double* derr = tmp.alloc<double>(nj);
   block_errors(djp, ref, nj, mm, derr, s);
@@ -630,7 +667,7 @@ static void surrogate_leaf_stage(hps_op* op, DeviceMem& tmp, hipStream_t s, int*
     // The surrogate is not good enough for this field: plain leaf build everywhere.
     std::vector<LeafJob> all(nl);
     for (int l = 0; l < nl; ++l) all[l] = LeafJob{&op->leaf(), l, cp[l], tp[l]};
-    run_leaf_group(all, tmp, s, dstatus, op->opt.panel);
+    run_leaf_group(all, tmp, s, dstatus, op->opt.panel, op->opt.pivot_tol);
     op->n_fallback = nl;
   } else {
     block_replace(djp, ref, nj, mm, derr, op->judge_tol, s);
@@ -650,6 +687,8 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
   // Leaf groups keyed by (p, q, hx, hy); surrogate operators infer their leaves instead.
   std::map<std::tuple<int, int, double, double>, std::vector<LeafJob>> groups;
   const int panel = ops.empty() ? 32 : ops[0]->opt.panel;
+  const double tol = ops.empty() ? 0.0 : ops[0]->opt.pivot_tol;  // one value per batch
+  for (hps_op* op : ops) pstat_init(op->pstat, op->n_merges, s);
   for (hps_op* op : ops) {
     if (op->mode == HPS_SURROGATE) {
       surrogate_leaf_stage(op, tmp, s, dstatus);
@@ -663,7 +702,7 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
                           op->leafT + (size_t)l * m * m,
                           op->leafZ ? op->leafZ + (size_t)l * op->leaf().lt.n * m : nullptr});
   }
-  for (auto& kv : groups) run_leaf_group(kv.second, tmp, s, dstatus, panel);
+  for (auto& kv : groups) run_leaf_group(kv.second, tmp, s, dstatus, panel, tol);
   for (hps_op* op : ops)
     if (op->leafK) body_operator_stage(op, tmp, s, dstatus);
 
@@ -677,7 +716,7 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
   for (int d = maxd; d >= 0; --d) {
     std::vector<MergeDesc> hm;
     std::vector<SolveDesc> hs;
-    std::vector<GemmDesc> hg;
+    std::vector<GemmDesc> hg, hsg;
     size_t gmax = 0;
     const LevelPlan* only = nullptr;
     int contributors = 0;
@@ -687,6 +726,7 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
       hm.insert(hm.end(), L.h.begin(), L.h.end());
       hs.insert(hs.end(), L.hs.begin(), L.hs.end());
       hg.insert(hg.end(), L.hg.begin(), L.hg.end());
+      hsg.insert(hsg.end(), L.hsg.begin(), L.hsg.end());
       gmax = std::max(gmax, L.gather_max);
       only = &L;
       ++contributors;
@@ -694,40 +734,78 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
     if (hm.empty()) continue;
     const MergeDesc* dm;
     const SolveDesc* dsd;
-    const GemmDesc* dgd;
+    const GemmDesc *dgd, *dsg;
     if (contributors == 1) {
       dm = only->d;
       dsd = only->ds;
       dgd = only->dg;
+      dsg = only->dsg;
     } else {
       MergeDesc* a = tmp.upload(hm, s);
       SolveDesc* b = tmp.upload(hs, s);
       GemmDesc* c = tmp.upload(hg, s);
+      GemmDesc* e = tmp.upload(hsg, s);
       HPS_HIP(hipStreamSynchronize(s));
       dm = a;
       dsd = b;
       dgd = c;
+      dsg = e;
     }
     merge_gather(dm, (int)hm.size(), gmax, s);
     batched_solve(dsd, hs, dstatus, s, panel);
+    grouped_gemm(dsg, hsg, s, GEMM_F64);
     int kmax = 0;
     for (const GemmDesc& g : hg) kmax = std::max(kmax, g.K);
     grouped_gemm(dgd, hg, s, prec == GEMM_BF16X6 && kmax < bf16x6_min_k() ? GEMM_F64 : prec);
   }
   int st[4];
   HPS_HIP(hipMemcpyAsync(st, dstatus, sizeof(st), hipMemcpyDeviceToHost, s));
+  // Pivot statistics of every merge: the per-depth condition estimates and
+  // the relative pivot test.
+  std::vector<std::vector<unsigned long long>> ps(ops.size());
+  for (size_t i = 0; i < ops.size(); ++i) {
+    ps[i].resize(2 * ops[i]->n_merges);
+    if (!ps[i].empty())
+      HPS_HIP(hipMemcpyAsync(ps[i].data(), ops[i]->pstat, ps[i].size() * 8, hipMemcpyDeviceToHost, s));
+  }
   HPS_HIP(hipStreamSynchronize(s));
   if (st[2]) throw Error(HPS_EINVAL, "non-finite coefficient");
   if (st[0]) {
     std::string where = st[1] < 0 ? "leaf " + std::to_string(-st[1] - 1)
                                   : "merge of box " + std::to_string(st[1]);
-    throw Error(HPS_ESINGULAR, "zero or non-finite pivot in " + where);
+    throw Error(HPS_ESINGULAR, tol > 0.0 && st[1] < 0
+                                   ? "pivot below pivot_tol * max|A_ii| in " + where
+                                   : "zero or non-finite pivot in " + where);
+  }
+  for (size_t i = 0; i < ops.size(); ++i) {
+    hps_op* op = ops[i];
+    op->level_cond.assign(op->levels.size(), 0.0);
+    size_t k = 0;
+    for (size_t d = 0; d < op->levels.size(); ++d)
+      for (const MergeDesc& md : op->levels[d].h) {
+        double amax, pmin;
+        std::memcpy(&amax, &ps[i][2 * k], 8);
+        const unsigned long long pb = ps[i][2 * k + 1];
+        if (pb >= 0x7FF0000000000000ull) pmin = INFINITY;
+        else std::memcpy(&pmin, &pb, 8);
+        ++k;
+        const double est = pmin > 0.0 ? amax / pmin : INFINITY;
+        op->level_cond[d] = std::max(op->level_cond[d], est);
+        if (tol > 0.0 && !(pmin > tol * amax)) {
+          char buf[200];
+          std::snprintf(buf, sizeof(buf),
+                        "merge of box %d (depth %d): min |pivot| %.3e <= pivot_tol * max|M| = %.3e",
+                        md.box, (int)d, pmin, tol * amax);
+          throw Error(HPS_ESINGULAR, buf);
+        }
+      }
   }
 }
 
 void leaf_dtn_batch(const double* coeffs, int nleaf, double hx, double hy, int p, int q, double* T,
                     hipStream_t s) {
-  HPS_REQUIRE(p >= 4 && p <= 24 && q >= 1 && q <= p && nleaf >= 1, "bad leaf batch arguments");
+  HPS_REQUIRE(p >= 4 && p <= 24 && q >= 1 && q < p && nleaf >= 1,
+              "bad leaf batch arguments (need 4 <= p <= 24, 1 <= q <= p - 1, nleaf >= 1)");
   init_runtime();
   std::shared_ptr<const LeafPlan> lp = leaf_plan(p, q, hx, hy, s);
   std::vector<LeafJob> jobs(nleaf);

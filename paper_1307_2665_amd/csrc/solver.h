@@ -37,7 +37,8 @@ struct DeviceMem {
 struct LevelPlan {
   std::vector<MergeDesc> h;
   std::vector<SolveDesc> hs;
-  std::vector<GemmDesc> hg;                 // Schur products T^tau += Q S
+  std::vector<GemmDesc> hg;                 // Schur products T^tau = diag + Q S
+  std::vector<GemmDesc> hsg;                // solution operators S = M^-1 B
   std::vector<long long> ha, hb, hp, zo;    // unit offsets for the upward pass
   // The same child offsets for body-load solves: a leaf child's particular
   // flux sits at unit offset h_units + leaf * 4q (after the merged boxes).
@@ -45,6 +46,7 @@ struct LevelPlan {
   MergeDesc* d = nullptr;
   SolveDesc* ds = nullptr;
   GemmDesc* dg = nullptr;
+  GemmDesc* dsg = nullptr;
   long long *dha = nullptr, *dhb = nullptr, *dhp = nullptr, *dzo = nullptr;
   long long *dhab = nullptr, *dhbb = nullptr;
   int m3_max = 0, me_max = 0;
@@ -105,6 +107,7 @@ struct BuildOptions {
   bool keep_body = false;
   bool root_dtn = true;
   int panel = 32;
+  double pivot_tol = 0.0;   // relative pivot test (0: exactly zero pivots only)
 };
 
 }  // namespace hps
@@ -121,9 +124,14 @@ struct hps_op {
   double* leafT = nullptr;          // [nleaf][4q][4q]
   double* leafZ = nullptr;          // [nleaf][4q][(p-2)^2]: Z^T, Z = A_ii^-1 A_ie L1, or null
   double* leafK = nullptr;          // [nleaf][(p-2)^2][4q]: K^T, K = P1 A_ii^-1, or null
-  double* Wk = nullptr;             // augmented systems; S (and M^-1) live inside them
+  double* Wk = nullptr;             // merge systems [M | I] (M^-1 after the elimination)
+  double* Bk = nullptr;             // gathered right-hand sides of one level (scratch)
+  double* Sk = nullptr;             // solution operators S = M^-1 B of every merge
   double* Q = nullptr;
   int* piv = nullptr;
+  size_t n_merges = 0;
+  unsigned long long* pstat = nullptr;  // per merge: max|M| and min |pivot| (bit patterns)
+  std::vector<double> level_cond;   // per depth: max over its merges of max|M| / min |pivot|
   int* gamma = nullptr;             // boundary ids in S,E,N,W order
   double* arena[2] = {nullptr, nullptr};
   double* rootT = nullptr;

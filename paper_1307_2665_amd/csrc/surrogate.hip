@@ -306,7 +306,7 @@ static void upload_f(float* d, const std::vector<double>& v, hipStream_t s) {
 
 std::unique_ptr<hps_surrogate> surrogate_create(int p, int q, double hx, double hy, int hidden,
                                                 int rank, unsigned long long seed, hipStream_t s) {
-  HPS_REQUIRE(p >= 4 && p <= 24 && q >= 1 && q <= p && hidden >= 8 && rank >= 1 && rank <= 4 * q,
+  HPS_REQUIRE(p >= 4 && p <= 24 && q >= 1 && q < p && hidden >= 8 && rank >= 1 && rank <= 4 * q,
               "bad surrogate shape");
   auto sg = std::make_unique<hps_surrogate>();
   sg->p = p;

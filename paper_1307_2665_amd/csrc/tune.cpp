@@ -81,7 +81,7 @@ std::string tune_json() {
   Table& T = table();
   std::lock_guard<std::mutex> lk(T.mu);
   std::ostringstream o;
-  o << "{\n  \"format\": \"hps-tune-1\",\n  \"entries\": [\n";
+  o << "{\n  \"format\": \"hps-tune-2\",\n  \"entries\": [\n";
   size_t i = 0;
   for (auto& kv : T.entries) {
     const Key& k = kv.first;
@@ -98,7 +98,7 @@ std::string tune_json() {
 }
 
 void tune_load_json(const std::string& text) {
-  HPS_REQUIRE(text.find("\"hps-tune-1\"") != std::string::npos, "not a tuning cache (format hps-tune-1)");
+  HPS_REQUIRE(text.find("\"hps-tune-2\"") != std::string::npos, "not a tuning cache (format hps-tune-2)");
   std::istringstream in(text);
   std::string line;
   std::vector<std::pair<Key, Entry>> got;
@@ -263,7 +263,7 @@ void tune_gj(const GjShape& g, hipStream_t s, Timer& tm) {
   SolveDesc* dd = mem.upload(hd, s);
   double best = 1e300, tdef = 0;
   int bv = 0;
-  for (int upd = 0; upd < GEMM_VARIANTS; ++upd)
+  for (int upd = 0; upd < UPDATE_VARIANTS; ++upd)
     for (int tb = 0; tb < 3; ++tb) {
       const int v = upd * 4 + tb;
       // Each timed solve starts from the pristine systems (the copy is not timed).
@@ -293,7 +293,7 @@ double autotune(const std::vector<TuneShape>& shapes, hipStream_t s) {
   std::vector<GjShape> gjs;
   std::set<std::array<int, 4>> seen_g, seen_j;
   for (const TuneShape& sh : shapes) {
-    HPS_REQUIRE(sh.nx >= 1 && sh.ny >= 1 && sh.p >= 4 && sh.p <= 24 && sh.q >= 1 && sh.q <= sh.p &&
+    HPS_REQUIRE(sh.nx >= 1 && sh.ny >= 1 && sh.p >= 4 && sh.p <= 24 && sh.q >= 1 && sh.q < sh.p &&
                     sh.hx > 0 && sh.hy > 0,
                 "bad shape for the autotuner");
     tune_leaf(sh.p, sh.q, sh.hx, sh.hy, sh.nx * sh.ny, s, tm);
@@ -312,10 +312,15 @@ double autotune(const std::vector<TuneShape>& shapes, hipStream_t s) {
         m3 = std::max(m3, g.m3);
       }
       const int cnt = (int)t.parents_at_level[d].size();
+      // Schur product T = diag + Q S and solution operator S = M^-1 B.
       GemmShape gs{me, me, m3, cnt};
       if (seen_g.insert({tune_lg(me), tune_lg(me), tune_lg(m3), tune_lg(cnt)}).second)
         gemms.push_back(gs);
-      GjShape js{m3, m3 + me + (sh.keep_factors ? m3 : 0), cnt};
+      GemmShape ss{m3, me, m3, cnt};
+      if (seen_g.insert({tune_lg(m3), tune_lg(me), tune_lg(m3), tune_lg(cnt)}).second)
+        gemms.push_back(ss);
+      // The merge system [M | I].
+      GjShape js{m3, 2 * m3, cnt};
       if (seen_j.insert({tune_lg(js.n), tune_lg(js.w), tune_lg(cnt), 0}).second) gjs.push_back(js);
     }
   }

@@ -15,7 +15,12 @@ enum TuneKnob {
   TUNE_NKNOBS = 3
 };
 
-constexpr int GEMM_VARIANTS = 7;   // tiles of gemm_tile (dense.hip)
+constexpr int GEMM_VARIANTS = 7;   // tiles of grouped_gemm_v (dense.hip)
+// Tiles of the Gauss-Jordan trailing update (launch_update in dense.hip):
+// 0: 64x64x16 on 2x2 waves, 1: 32x32x16 on one wave, 2: 128x128x16 on 4x2
+// waves, 3: 128x64x16, 4: 64x128x16, 5: 64x64x32; each loads its tile's old
+// values with the first operands and keeps one k-slab of loads in flight.
+constexpr int UPDATE_VARIANTS = 6;
 constexpr int TRSM_BLOCKS[3] = {256, 128, 64};
 
 // ceil(log2(x)) for x >= 1.
@@ -34,7 +39,6 @@ void tune_load_json(const std::string& text);
 struct TuneShape {
   int nx, ny, p, q;
   double hx, hy;
-  bool keep_factors;
 };
 // Times the variants of every kernel the builds of these shapes launch, on
 // synthetic data of the same shapes, and records the fastest per bucket.

@@ -52,7 +52,7 @@ def test_nodes_match_oracle(nleaf, q, p):
     assert np.array_equal(H.boundary_ids(nleaf, q), g.boundary(0, nleaf[0], 0, nleaf[1]))
 
 
-@pytest.mark.parametrize("p,q", [(16, 14), (12, 10), (21, 21), (20, 18), (5, 3)])
+@pytest.mark.parametrize("p,q", [(16, 14), (12, 10), (21, 20), (20, 18), (5, 3)])
 def test_leaf_tables_reproduce_oracle_dtn(p, q):
     """T = P0 - P1 A_ii^-1 R from the planner's tables equals the oracle's L4 L3 L2 L1."""
     import paper_1307_2665_amd as H
@@ -132,6 +132,9 @@ def test_invalid_arguments_are_rejected_on_host():
     with pytest.raises(H.HpsError) as e:
         H.leaf_tables(8, 10, 0.1, 0.1)           # q > p
     assert e.value.status == H.HPS_EINVAL
+    with pytest.raises(H.HpsError) as e:
+        H.leaf_tables(8, 8, 0.1, 0.1)            # q = p: singular merges
+    assert e.value.status == H.HPS_EINVAL
     with pytest.raises(H.HpsError):
         H.leaf_tables(3, 2, 0.1, 0.1)            # p < 4
     with pytest.raises(H.HpsError):
@@ -150,13 +153,13 @@ def test_tuning_cache_round_trip(tmp_path):
         {"knob": 0, "name": "leaf", "key": [196, 56, 0, 0], "variant": 4, "ms": 6.0, "default_ms": 6.0},
     ]
     src = tmp_path / "in.json"
-    src.write_text('{\n  "format": "hps-tune-1",\n  "entries": [\n' +
+    src.write_text('{\n  "format": "hps-tune-2",\n  "entries": [\n' +
                    ",\n".join("    " + json.dumps(e) for e in entries) + "\n  ]\n}\n")
     H.tune_load(src)
     out = tmp_path / "out.json"
     H.tune_save(out)
     got = json.loads(out.read_text())
-    assert got["format"] == "hps-tune-1"
+    assert got["format"] == "hps-tune-2"
     key = lambda e: (e["knob"], tuple(e["key"]))
     assert sorted(((key(e), e["variant"]) for e in got["entries"])) == \
         sorted(((key(e), e["variant"]) for e in entries))
@@ -172,3 +175,26 @@ def test_tuning_cache_round_trip(tmp_path):
         with pytest.raises(H.HpsError) as e:
             H.tune_set(knob, v)
         assert e.value.status == H.HPS_EINVAL
+
+
+@pytest.mark.parametrize("p,q", [(12, 12), (8, 8), (6, 9)])
+def test_build_refuses_q_not_below_p(p, q):
+    """The build validates 1 <= q <= p - 1 before any device work: with q >= p
+    every interior cross point carries a mode that no leaf sees (section 3.2,
+    step 1), so the merge systems are singular (pinned on the oracle)."""
+    import paper_1307_2665_amd as H
+    C = np.zeros((4, 6, p * p))
+    C[:, 0] = C[:, 2] = 1.0
+    with pytest.raises(H.HpsError) as e:
+        H.build_solution_operator(C, (0.0, 1.0, 0.0, 1.0), (2, 2), p, q)
+    assert e.value.status == H.HPS_EINVAL
+    assert "q" in str(e.value)
+
+
+def test_tuning_cache_of_older_format_is_refused(tmp_path):
+    import paper_1307_2665_amd as H
+    old = tmp_path / "old.json"
+    old.write_text('{"format": "hps-tune-1", "entries": []}')
+    with pytest.raises(H.HpsError) as e:
+        H.tune_load(old)
+    assert e.value.status == H.HPS_EINVAL

@@ -360,3 +360,89 @@ def test_body_load_zero_is_the_plain_solve():
     f = np.random.default_rng(1).standard_normal((2, op.n_bdry))
     u, _ = hps.body_solve(op, C, f, np.zeros((2, 12, pr.p * pr.p)))
     assert np.max(np.abs(u - hps.solve(op, f))) < 1e-13 * np.max(np.abs(u))
+
+
+# ---------------------------------------------------------------------------
+# Admissible (p, q): section 3.2 step 1 and the cross-point null modes.
+# ---------------------------------------------------------------------------
+
+def _cross_point_mode(grid, p):
+    """At the centre of a 2x2-leaf grid: on each of the four edges meeting
+    there, the Gauss values of the degree-(p-1) polynomial that is 1 at the
+    edge's Chebyshev node at the centre and 0 at its other p-1 Chebyshev
+    nodes; + on the two horizontal edges, - on the two vertical ones.  Every
+    leaf sees one edge of each sign at its corner there, so the corner average
+    of step 1 cancels and its boundary Chebyshev values all vanish."""
+    q = grid.q
+    xc = hps.cheb_points(p)
+    xg = hps.gauss_points(q)
+    ell_end = hps.lagrange_matrix(xc, xg)[:, -1]     # 1 at the node x = +1
+    ell_start = hps.lagrange_matrix(xc, xg)[:, 0]    # 1 at the node x = -1
+    v = np.zeros(grid.N)
+    v[grid.hedge(0, 1)] = ell_end        # west of the centre: its east end
+    v[grid.hedge(1, 1)] = ell_start      # east of the centre: its west end
+    v[grid.vedge(1, 0)] = -ell_end       # south of the centre: its north end
+    v[grid.vedge(1, 1)] = -ell_start     # north of the centre: its south end
+    return v
+
+
+def test_cross_point_mode_is_invisible_only_when_q_equals_p():
+    """With q = p the cross-point mode lies in the null space of all four leaf
+    DtNs and of the root merge system M = T33a - T33b; with q = p - 1 the same
+    construction is seen by every leaf."""
+    for p, q, singular in ((8, 8, True), (12, 12, True), (12, 11, False)):
+        pr = hi.laplace_log(nleaf=(2, 2), p=p, q=q)
+        grid = hps.Grid(pr.box, 2, 2, q)
+        op = hps.build(pr.coeffs_at(grid.cheb_xy(p)), pr.box, (2, 2), p, q, allow_singular=True)
+        v = _cross_point_mode(grid, p)
+        flux = max(np.max(np.abs(T @ v[op.boxes[t].Ie])) / np.max(np.abs(T))
+                   for t, T in op.leafT.items())
+        root = op.merges[0]
+        v3 = v[op.boxes[0].Ii]
+        mv = np.max(np.abs(root.M @ v3)) / (np.max(np.abs(root.M)) * np.max(np.abs(v3)))
+        cond = np.linalg.cond(root.M)
+        if singular:
+            assert flux < 1e-12 and mv < 1e-12 and cond > 1e12, (p, q, flux, mv, cond)
+        else:
+            assert flux > 1e-3 and mv > 1e-3 and cond < 1e3, (p, q, flux, mv, cond)
+
+
+@pytest.mark.parametrize("p", [8, 12, 16])
+def test_q_equal_p_ruins_the_gauss_solution(p):
+    """4x4 Laplace leaves, u = log|x - (1.5, 1.5)|: at q = p - 1 the merges are
+    well conditioned and the Gauss-node solution is accurate; at q = p the
+    solution is off by O(1) (the singular merges amplify rounding along the
+    cross-point modes).  The oracle refuses q >= p unless asked."""
+    def run(q):
+        pr = hi.laplace_log(nleaf=(4, 4), p=p, q=q)
+        grid = hps.Grid(pr.box, 4, 4, q)
+        op = hps.build(pr.coeffs_at(grid.cheb_xy(p)), pr.box, (4, 4), p, q, allow_singular=True)
+        u = hps.solve(op, pr.bc_at(hps.gamma_xy(op)))[0]
+        return np.max(np.abs(u - pr.exact(*grid.node_xy().T))), hps.level_conditions(op)
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        err_bad, cond_bad = run(p)
+    err_ok, cond_ok = run(p - 1)
+    assert err_ok < 1e-8 and err_bad > 1e-3, (err_ok, err_bad)
+    assert np.max(cond_ok) < 1e2 and np.max(cond_bad) > 1e12, (cond_ok, cond_bad)
+    with pytest.raises(ValueError):
+        pr = hi.laplace_log(nleaf=(2, 2), p=p, q=p)
+        hps.build(pr.coeffs_at(hps.Grid(pr.box, 2, 2, p).cheb_xy(p)), pr.box, (2, 2), p, p)
+
+
+def test_level_condition_estimate_brackets_cond2():
+    """max|M| / min |u_kk| (the per-depth estimate both sides report) stays
+    below cond_2(M) and within a factor 50 of it on a variable-coefficient
+    problem (p = 16, q = 14)."""
+    import scipy.linalg as sla
+    pr = hi.convdiff(nleaf=(4, 4), p=16, q=14)
+    op, _, _ = _problem_ops(pr, (4, 4))
+    est = hps.level_conditions(op)
+    for t, mo in op.merges.items():
+        lu, _ = sla.lu_factor(mo.M)
+        e = np.max(np.abs(mo.M)) / np.min(np.abs(np.diag(lu)))
+        c2 = np.linalg.cond(mo.M)
+        assert c2 / 50 < e <= c2 * (1 + 1e-12), (t, e, c2)
+        assert e <= est[op.boxes[t].level]
+    assert est[-1] == 0.0
