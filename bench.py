@@ -1,18 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the composite spectral direct solver on one MI355X.
 
-Workload (N=1): variable-coefficient convection-diffusion on the unit square,
-c11 = c22 = 1 + g/2, c1 = c2 = 10 h (g, h seeded 8-mode Fourier fields), c = 0,
-64 x 64 leaves, p = 16 Chebyshev nodes per leaf side, q = 14 Gauss nodes per
-edge, one right-hand side f = cos(2 x1)(1 - 2 x2): N_tot = 1,040,001 unknowns.
-
-One step = the whole hot path on resident inputs: leaf DtNs (section 3), all
-merges (section 4, Algorithm 1) including the root DtN, and the downward solve
-(Algorithm 2).  ``value`` = N_tot * steps / (time of the timed steps).
+Default workload (the largest single-GPU configuration): coefficient sweep
+fields c11 = c22 = 1 + g/2, c = 1 + g' (g, g' seeded 8-mode Fourier fields)
+on the unit square, 256 x 256 leaves, p = 12 Chebyshev nodes per leaf side,
+q = 10 Gauss nodes per edge: N_tot = 9,251,329 unknowns per field.  One step
+= the whole hot path for one field on resident inputs: leaf DtNs (section 3),
+all merges (section 4, Algorithm 1) including the root DtN, and the downward
+solve (Algorithm 2) of one right-hand side f = cos(2 x1)(1 - 2 x2).  Steps
+cycle over four resident fields.  ``value`` = N_tot * steps / (time of the
+timed steps) in FP64; the learned-surrogate form (leaf DtNs from the network,
+judged by the FP64 leaf solver) is timed the same way and reported under
+``forms`` with its error against the FP64 form.
 
 The ``roofline`` entry times the dominant kernel class with HIP events on its
 launch stream during the timed steps; ``cpu_baseline`` times the CPU oracle on
-a bounded sample of the same workload.
+a bounded sample of the same workload.  Other workloads (--workload): convdiff
+(64 x 64, p = 16), helmholtz (128 x 128, p = 16, 64 right-hand sides, FP64
+against the mixed forms with refinement), batch (32 uneven problems), post
+(section 5.3), body (body loads).
 """
 from __future__ import annotations
 
@@ -26,6 +32,7 @@ METRIC = "operator build unknowns/s + solves/s at rel err ≤1e-10, FP64 vs mixe
 PEAK = {"mfma_f64": 78.6, "mfma_f32": 157.3, "mfma_bf16": 2500.0,   # TFLOP/s (dense)
         "hbm": 8000.0}                                                # GB/s
 BOUND_OF = {"gemm": ("mfma", "mfma_f64"), "lu_update": ("mfma", "mfma_f64"),
+            "leaf_gemm": ("mfma", "mfma_f64"), "merge_s": ("mfma", "mfma_f64"),
             "gemm_split32": ("mfma", "mfma_f32"), "gemm_bf16x6": ("mfma", "mfma_bf16"),
             "back_subst": ("alu", None), "lu_panel": ("alu", None), "swap_trsm": ("alu", None),
             "leaf_assemble": ("hbm", "hbm"), "merge_gather": ("hbm", "hbm"),
@@ -63,16 +70,22 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["fp64", "mixed", "bf16x6"], default="fp64",
+    ap.add_argument("--mode", choices=["fp64", "mixed", "bf16x6", "surrogate"], default="fp64",
                     help="Schur products: FP64 MFMA, split-FP32 MFMA, or BF16 MFMA on three-slice\n"
-                         "splits (the last two with refinement against the FP64 leaf DtNs)")
+                         "splits (the last two with refinement against the FP64 leaf DtNs); for\n"
+                         "the sweep, which form's time is the line's value (fp64 or surrogate)")
     ap.add_argument("--workload", choices=["convdiff", "helmholtz", "batch", "sweep", "post",
                                            "body"],
-                    default="convdiff",
-                    help="convdiff: 64x64 p16 (the default line); helmholtz: 128x128 p16, 64 "
-                         "right-hand sides, FP64 and split-FP32 + refinement; batch: 32 uneven "
-                         "problems with 16 right-hand sides each; sweep: 256x256 p12 coefficient "
-                         "fields, plain FP64 leaves against the learned surrogate")
+                    default="sweep",
+                    help="sweep (default): 256x256 p12 coefficient fields, plain FP64 leaves and "
+                         "the learned surrogate; convdiff: 64x64 p16, one right-hand side; "
+                         "helmholtz: 128x128 p16, 64 right-hand sides, FP64 and the mixed forms "
+                         "with refinement; batch: 32 uneven problems with 16 right-hand sides "
+                         "each; post: section 5.3; body: body loads")
+    ap.add_argument("--train-pairs", type=int, default=200000,
+                    help="sweep: surrogate training pairs (leaf solves of random leaves of "
+                         "1000 training fields)")
+    ap.add_argument("--train-epochs", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--body-refactor", action="store_true",
                     help="body workload: refactor the leaf systems in every solve instead of\n"
@@ -142,6 +155,100 @@ def cpu_baseline(pr, n_leaf_sample: int):
     return dict(t_leaf=t_leaf, t_merge=t_merge, t_solve=t_solve, threads=threads, ns=ns)
 
 
+def profile_first(H, torch, fn):
+    """Runs fn once with every kernel class timed; returns ({class: totals}, fn's result)."""
+    classes = list(H.PROF_CLASSES)
+    H.prof_enable(classes)
+    H.prof_reset()
+    out = fn()
+    torch.cuda.synchronize()
+    per = {c: H.prof_query(c) for c in classes}
+    H.prof_enable([])
+    H.prof_reset()
+    return per, out
+
+
+def dominant_of(per):
+    return max((c for c in per if per[c]["launches"] > 0), key=lambda c: per[c]["ms"])
+
+
+def roofline_of(dominant, dom, steps, traffic=None):
+    """Roofline entry of the dominant kernel class from its event-timed totals over the timed
+    steps: algorithmic FLOPs (or bytes) per launch / average launch time against the peak."""
+    bound, peak_key = BOUND_OF.get(dominant, ("alu", None))
+    sec = dom["ms"] * 1e-3
+    if bound == "mfma":
+        roof = dict(bound="mfma", achieved=dom["flops"] / sec / 1e12, peak=PEAK[peak_key],
+                    unit="TFLOP/s")
+    elif bound == "hbm":
+        roof = dict(bound="hbm", achieved=dom["bytes"] / sec / 1e9, peak=PEAK["hbm"], unit="GB/s")
+    else:
+        roof = dict(bound="alu", achieved=dom["flops"] / sec / 1e12, peak=ALU_F64_PEAK,
+                    unit="TFLOP/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = traffic
+    roof["kernel"] = dominant
+    roof["launches_per_step"] = dom["launches"] / steps
+    roof["avg_launch_ms"] = dom["ms"] / max(dom["launches"], 1)
+    return roof
+
+
+def chain_cpu_baseline(pr, n_leaf_sample, log=None, nrhs=1):
+    """The CPU oracle on a bounded sample of a build + solve on a 2^k x 2^k grid.
+
+    Leaves: n_leaf_sample leaf DtNs timed, scaled to all leaves.  Merges: at every tree depth
+    one merge of that depth's shapes is timed in full (repeated while it is short) and scaled
+    by the number of merges at that depth; its children are the previous depth's merged box
+    and its translate, built from one leaf DtN tiled over the grid (the dense merge costs do
+    not depend on the values).  Solve: the same per-depth sample of u3 = S u_e for nrhs
+    right-hand sides at once."""
+    import warnings
+
+    import numpy as np
+    from oracle import hps
+    warnings.simplefilter("ignore")
+    nx, ny = pr.nleaf
+    grid = hps.Grid(pr.box, nx, ny, pr.q)
+    mats = hps.leaf_matrices(pr.p, pr.q, grid.hx, grid.hy)
+    ns = min(n_leaf_sample, nx * ny)
+    xy = grid.cheb_xy(pr.p)[:ns]
+    C = pr.coeffs_at(xy)
+    t0 = time.perf_counter()
+    Ts = [hps.leaf_dtn(C[k], pr.p, pr.q, grid.hx, grid.hy, mats).T for k in range(ns)]
+    t_leaf = (time.perf_counter() - t0) * (nx * ny) / ns
+    boxes = hps.build_tree(nx, ny)
+    for b in boxes:
+        b.Ie = grid.boundary(b.i0, b.i1, b.j0, b.j1)
+    depth = max(b.level for b in boxes)
+    T = Ts[0]
+    t_merge = t_solve = 0.0
+    for d in range(depth - 1, -1, -1):
+        idx = [k for k, b in enumerate(boxes) if b.level == d and not b.is_leaf]
+        b = boxes[idx[0]]
+        a, c = b.children
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            mo = hps.merge(T, boxes[a].Ie, T, boxes[c].Ie, b.Ie)
+            reps += 1
+            if time.perf_counter() - t0 > 0.1:
+                break
+        t_merge += (time.perf_counter() - t0) / reps * len(idx)
+        ue = np.ones((nrhs, len(b.Ie)))
+        reps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < 0.02:
+            ue @ mo.S.T
+            reps += 1
+        t_solve += (time.perf_counter() - t0) / reps * len(idx)
+        T = mo.T
+    if log:
+        log(f"cpu baseline: leaves {t_leaf:.1f} s (est), merges {t_merge:.1f} s, "
+            f"solve {t_solve:.3f} s")
+    return dict(t_leaf=t_leaf, t_merge=t_merge, t_solve=t_solve, threads=_blas_threads(), ns=ns,
+                sample=(f"{ns} of {nx * ny} leaf DtNs timed, scaled x{nx * ny / ns:.0f}; one merge "
+                        f"and one S u_e product per tree depth ({depth} depths) timed in full on "
+                        f"tiled leaf DtNs, scaled by the merge count of that depth"))
+
+
 def _n_tot(pr):
     nx, ny = pr.nleaf
     return (nx * (pr.p - 1) + 1) * (ny * (pr.p - 1) + 1) + pr.q * (nx * (ny + 1) + (nx + 1) * ny)
@@ -188,6 +295,7 @@ def other_workload(args, H, hi, np, torch, dev):
         C, F = _inputs(H, pr, np, torch, dev)
         nrhs = F.shape[0]
         forms = {}
+        roofs = {}
         u_ref = None
         for form in ("fp64", "mixed", "bf16x6"):
             mode = MODES[form](H)
@@ -196,6 +304,7 @@ def other_workload(args, H, hi, np, torch, dev):
             box = {}
 
             def build():
+                box.pop("op", None)
                 box["op"] = H.build_solution_operator(C, pr.box, pr.nleaf, pr.p, pr.q, mode=mode)
 
             def solve():
@@ -206,8 +315,21 @@ def other_workload(args, H, hi, np, torch, dev):
                 else:
                     box["u"] = box["op"].solve(F)
 
+            def step():
+                build()
+                solve()
+
+            per, _ = profile_first(H, torch, step)
+            dominant = dominant_of(per)
+            H.prof_enable([dominant])
+            H.prof_reset()
             bms, _ = _timed(torch, np, steps, build)
             sms, _ = _timed(torch, np, steps, solve)
+            dom = H.prof_query(dominant)
+            H.prof_enable([])
+            H.prof_reset()
+            # _timed runs one untimed call before its timed ones: steps + 1 builds and solves.
+            roofs[form] = roofline_of(dominant, dom, steps + 1)
             info = box.get("info")
             u = box["u"]
             if u_ref is None:
@@ -216,15 +338,28 @@ def other_workload(args, H, hi, np, torch, dev):
             forms[form] = {"build_ms": bms, "solve_ms": sms, "step_ms": bms + sms,
                            "build_unknowns_per_s": _n_tot(pr) / (bms * 1e-3),
                            "solves_per_s": nrhs / (sms * 1e-3),
-                           "rel_err_vs_fp64": err, "refine": info}
-            log(f"helmholtz {form}: build {bms:.1f} ms, {nrhs}-rhs solve {sms:.2f} ms, err {err:.2e}")
+                           "rel_err_vs_fp64": err, "refine": info,
+                           "dominant_kernel": dominant,
+                           "kernel_ms_first_step": {c: round(per[c]["ms"], 4) for c in per
+                                                    if per[c]["launches"]}}
+            log(f"helmholtz {form}: build {bms:.1f} ms, {nrhs}-rhs solve {sms:.2f} ms, err {err:.2e}; "
+                + ", ".join(f"{c}={per[c]['ms']:.2f}ms/{per[c]['launches']}" for c in per
+                            if per[c]["launches"]))
             del box
         sel = forms[args.mode]
         line.update(value=_n_tot(pr) / (sel["step_ms"] * 1e-3), ms_per_step=sel["step_ms"],
                     dtype=DTYPE[args.mode],
                     config={"workload": "helmholtz-bump-128x128-p16-q14-64rhs", "n_tot": _n_tot(pr),
                             "nrhs": nrhs, "mode": args.mode},
-                    forms=forms)
+                    roofline=roofs[args.mode], forms=forms)
+        if not args.no_cpu_baseline:
+            cb = chain_cpu_baseline(pr, args.cpu_sample_leaves, log, nrhs=nrhs)
+            t_cpu = cb["t_leaf"] + cb["t_merge"] + cb["t_solve"]
+            line["cpu_baseline"] = {"value": _n_tot(pr) / t_cpu, "unit": "unknowns/s",
+                                    "cores": cb["threads"], "kind": "oracle",
+                                    "sample": cb["sample"],
+                                    "seconds": {"leaf_est": cb["t_leaf"], "merge_est": cb["t_merge"],
+                                                "solve_est": cb["t_solve"]}}
         return line
     if args.workload == "post":
         return post_workload(args, H, hi, np, torch, dev, line)
@@ -260,56 +395,128 @@ def other_workload(args, H, hi, np, torch, dev):
                     build_ms=bms, solve_ms=sms, build_unknowns_per_s=tot / (bms * 1e-3),
                     solves_per_s=nrhs / (sms * 1e-3), rel_err_vs_single=err)
         return line
-    # sweep: plain FP64 leaves against the learned surrogate on held-out fields
-    p, q, n = 12, 10, 256
+    return sweep_workload(args, H, hi, np, torch, dev, line)
+
+
+def train_sweep_surrogate(args, H, hi, np, torch, dev, p, q, n):
+    """Leaf-DtN surrogate for the 256 x 256, p = 12, q = 10 sweep: --train-pairs FP64 leaf
+    solves of random leaves of training fields 6000-6999 (disjoint from the sweep's fields),
+    then training on the GPU.  Returns (surrogate, info)."""
     h = 1.0 / n
+    nfield = 1000
+    per = max(1, args.train_pairs // nfield)
     rng = np.random.default_rng(6)
     xc = -np.cos(np.pi * np.arange(p) / (p - 1))
-    patches = []
-    for i in range(40):
+    t0 = time.perf_counter()
+    chunks = []
+    for i in range(nfield):
         fld = hi.sweep_field(6000 + i)
-        for _ in range(500):
-            x0, y0 = rng.uniform(0, 1 - h, size=2)
-            X, Y = np.meshgrid(x0 + 0.5 * (xc + 1) * h, y0 + 0.5 * (xc + 1) * h)
-            patches.append(fld.coeffs_at(np.stack([X.ravel(), Y.ravel()], 1)[None])[0])
-    Cp = torch.tensor(np.array(patches), dtype=torch.float64, device=dev)
+        x0 = rng.uniform(0, 1 - h, size=(per, 1, 1))
+        y0 = rng.uniform(0, 1 - h, size=(per, 1, 1))
+        X = x0 + 0.5 * (xc[None, None, :] + 1) * h          # [per, 1, p] along x (index a)
+        Y = y0 + 0.5 * (xc[None, :, None] + 1) * h          # [per, p, 1] along y (index b)
+        xy = np.stack(np.broadcast_arrays(X, Y), axis=-1).reshape(per, p * p, 2)
+        chunks.append(fld.coeffs_at(xy))
+    Cp = torch.tensor(np.concatenate(chunks), dtype=torch.float64, device=dev)
+    t_inputs = time.perf_counter() - t0
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     Tp = H.leaf_dtn(Cp, h, h, p, q)
-    sg = H.Surrogate.create(p, q, h, h, hidden=256, rank=16, seed=5)
-    sg.train(Cp, Tp, epochs=40, batch=256, lr=1e-3, seed=7)
     torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    if not args.no_tune:
-        H.autotune([dict(nleaf=(n, n), p=p, q=q)])
-    fields = [hi.sweep_field(5000 + k) for k in range(max(steps, 2))]
+    t_solves = time.perf_counter() - t0
+    sg = H.Surrogate.create(p, q, h, h, hidden=256, rank=16, seed=5)
+    t0 = time.perf_counter()
+    hist = sg.train(Cp, Tp, epochs=args.train_epochs, batch=256, lr=1e-3, seed=7)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"surrogate: {Cp.shape[0]} pairs from {nfield} fields (inputs {t_inputs:.1f} s, "
+        f"FP64 leaf solves {t_solves:.2f} s), {args.train_epochs} epochs {t_train:.1f} s, "
+        f"loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    del Cp, Tp
+    return sg, {"pairs": nfield * per, "fields": nfield, "epochs": args.train_epochs,
+                "leaf_solve_s": t_solves, "train_s": t_train,
+                "loss_first_epoch": float(hist[0]), "loss_last_epoch": float(hist[-1])}
+
+
+def sweep_workload(args, H, hi, np, torch, dev, line):
+    """Coefficient sweep on 256 x 256 leaves, p = 12, q = 10 (one field per step, four resident
+    fields cycled): the plain FP64 form and the learned-surrogate form, each timed over the same
+    steps; the surrogate's solutions are compared with the FP64 form's on every field."""
+    p, q, n = 12, 10, 256
+    nf = 4
+    fields = [hi.sweep_field(5000 + k) for k in range(nf)]
     ins = [_inputs(H, pr, np, torch, dev) for pr in fields]
-    forms = {}
-    sols = {}
+    n_tot = _n_tot(fields[0])
+    tune_s = H.autotune([dict(nleaf=(n, n), p=p, q=q)]) if not args.no_tune else None
+    sg, train = train_sweep_surrogate(args, H, hi, np, torch, dev, p, q, n)
+    forms, sols, roofs = {}, {}, {}
     for form in ("fp64", "surrogate"):
         kw = dict(surrogate=sg, judge_samples=256, judge_tol=1e-6) if form == "surrogate" else {}
-        times, us, fb = [], [], []
-        for k, (pr, (C, F)) in enumerate(zip(fields, ins)):
-            torch.cuda.synchronize()
-            a = time.perf_counter()
+        last = {}
+
+        def step(k):
+            pr, (C, F) = fields[k % nf], ins[k % nf]
+            last.pop("op", None)
             op = H.build_solution_operator(C, pr.box, pr.nleaf, p, q, **kw)
-            u = op.solve(F)
-            torch.cuda.synchronize()
-            times.append(1e3 * (time.perf_counter() - a))
-            us.append(u)
+            last["u"] = op.solve(F)
+            last["op"] = op
+            return op
+
+        per, _ = profile_first(H, torch, lambda: step(0))
+        for w in range(1, max(args.warmup, 1)):
+            step(w)
+        dominant = dominant_of(per)
+        H.prof_enable([dominant])
+        H.prof_reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            step(k)
+        torch.cuda.synchronize()
+        t_total = time.perf_counter() - t0
+        dom = H.prof_query(dominant)
+        H.prof_enable([])
+        H.prof_reset()
+        roofs[form] = roofline_of(dominant, dom, args.steps)
+        # One solution per field for the comparison (not timed).
+        us, fb = [], []
+        for k in range(nf):
+            op = step(k)
+            us.append(last["u"].clone())
             fb.append(op.n_fallback_leaves if form == "surrogate" else 0)
-            del op
+        res = 0.0
+        if form == "fp64":
+            r = last["op"].interface_residual(last["u"])
+            res = float(r.abs().max() / last["u"].abs().max())
+        last.clear()
         sols[form] = us
-        ms = float(np.median(times[1:] if len(times) > 2 else times))
-        forms[form] = {"step_ms": ms, "unknowns_per_s": _n_tot(fields[0]) / (ms * 1e-3),
+        ms = 1e3 * t_total / args.steps
+        forms[form] = {"ms_per_step": ms, "unknowns_per_s": n_tot / (ms * 1e-3),
+                       "dominant_kernel": dominant,
+                       "kernel_ms_first_step": {c: round(per[c]["ms"], 4) for c in per
+                                                if per[c]["launches"]},
                        "fallback_leaves": fb}
+        if form == "fp64":
+            forms[form]["residual_rel"] = res
+        log(f"sweep {form}: {ms:.2f} ms per field, " + ", ".join(
+            f"{c}={per[c]['ms']:.2f}ms/{per[c]['launches']}" for c in per if per[c]["launches"]))
     errs = [_rel(a, b) for a, b in zip(sols["surrogate"], sols["fp64"])]
     forms["surrogate"]["rel_err_vs_fp64"] = max(errs)
-    forms["surrogate"]["train_s"] = train_s
-    sel = forms["fp64" if args.mode == "fp64" else "surrogate"]
-    line.update(value=sel["unknowns_per_s"], ms_per_step=sel["step_ms"], dtype="f64",
-                config={"workload": "sweep-256x256-p12-q10", "n_tot": _n_tot(fields[0]),
-                        "fields": len(fields), "mode": "fp64" if args.mode == "fp64" else "surrogate"},
-                forms=forms)
+    forms["surrogate"]["training"] = train
+    sel = "fp64" if args.mode == "fp64" else "surrogate"
+    line.update(value=forms[sel]["unknowns_per_s"], ms_per_step=forms[sel]["ms_per_step"],
+                dtype="f64",
+                config={"workload": "sweep-256x256-p12-q10-1rhs", "nleaf": [n, n], "p": p, "q": q,
+                        "nrhs": 1, "n_tot": n_tot, "fields_resident": nf, "mode": sel},
+                roofline=roofs[sel], forms=forms, autotune_s=tune_s,
+                residual_rel=forms["fp64"]["residual_rel"])
+    if not args.no_cpu_baseline:
+        cb = chain_cpu_baseline(fields[0], args.cpu_sample_leaves, log)
+        t_cpu = cb["t_leaf"] + cb["t_merge"] + cb["t_solve"]
+        line["cpu_baseline"] = {"value": n_tot / t_cpu, "unit": "unknowns/s",
+                                "cores": cb["threads"], "kind": "oracle", "sample": cb["sample"],
+                                "seconds": {"leaf_est": cb["t_leaf"], "merge_est": cb["t_merge"],
+                                            "solve_est": cb["t_solve"]}}
     return line
 
 
@@ -487,8 +694,12 @@ def main():
     import paper_1307_2665_amd as H
 
     dev = torch.device("cuda:0")
+    if args.mode == "surrogate" and args.workload != "sweep":
+        sys.exit("bench.py: --mode surrogate applies to the sweep workload only")
     if args.workload != "convdiff":
-        print(json.dumps(other_workload(args, H, hi, np, torch, dev)), flush=True)
+        line = other_workload(args, H, hi, np, torch, dev)
+        copy_calibration(args, torch, dev)
+        print(json.dumps(line), flush=True)
         return
     pr = hi.convdiff()
     nx, ny = pr.nleaf
@@ -630,15 +841,22 @@ def main():
                        f"all {nx * ny - 1} merges and one solve timed in full on tiled leaf DtNs"),
             "seconds": {"leaf_est": cb["t_leaf"], "merge": cb["t_merge"], "solve": cb["t_solve"]},
         }
-    if args.copy_calibration > 0:
-        n = args.copy_calibration * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"copy calibration: {args.copy_calibration} MiB read + written")
+    copy_calibration(args, torch, dev)
     print(json.dumps(line), flush=True)
+
+
+def copy_calibration(args, torch, dev):
+    """One device copy of a known size (a plain copy kernel whose FETCH_SIZE and WRITE_SIZE
+    counters calibrate the ones of the solver's kernels)."""
+    if args.copy_calibration <= 0:
+        return
+    n = args.copy_calibration * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {args.copy_calibration} MiB read + written")
 
 
 if __name__ == "__main__":

@@ -410,12 +410,13 @@ hps_status hps_tune_reset(void);
 /* ---- launch timing (HIP events on the launch stream) --------------------- */
 
 /* Kernel classes: 0 leaf assembly, 1 LU panel, 2 row swaps + block-row solve,
-   3 LU trailing update, 4 back substitution, 5 FP64 GEMM (Schur products and
-   leaf T = P0 - P1 Z), 6 split-FP32 Schur GEMM, 7 merge gather, 8 downward
-   pass, 9 interface residual, 10 upward pass, 11 fused leaf elimination,
-   12 surrogate training, 13 surrogate inference, 14 post-processing, 15
-   BF16 three-slice Schur GEMM, 16 body-load fluxes from the kept body
-   operator.  Bit c of mask enables class c; every later launch of an
+   3 LU trailing update, 4 back substitution, 5 FP64 Schur GEMM of the
+   merges (T = D + Q S, eq:merge), 6 split-FP32 Schur GEMM, 7 merge gather,
+   8 downward pass, 9 interface residual, 10 upward pass, 11 fused leaf
+   elimination, 12 surrogate training, 13 surrogate inference, 14
+   post-processing, 15 BF16 three-slice Schur GEMM, 16 body-load fluxes from
+   the kept body operator, 17 leaf T = P0 - P1 Z products (section 3.2),
+   18 the merges' S = M^-1 B products (eq:U_parent).  Bit c of mask enables class c; every later launch of an
    enabled class records a start and stop event on its stream together with
    its algorithmic FLOPs and bytes.  Costs one event pair per launch while
    enabled. */

@@ -25,8 +25,9 @@ void set_bf16x6_min_k(int k);
 int bf16x6_min_k();
 
 // C = C0 + alpha A B for every descriptor, in the given arithmetic.
+// prof_cls: the profiling class its FP64 launches are timed under.
 void grouped_gemm(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, hipStream_t stream,
-                  int prec);
+                  int prec, int prof_cls = 5 /* PROF_GEMM */);
 
 // The same with explicit kernel variants (the autotuner times them):
 // gj_variant = update tile * 4 + TRSM block code (see tune.h), -1 = default;
@@ -34,7 +35,7 @@ void grouped_gemm(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, h
 void batched_solve_v(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc, int* d_status,
                      hipStream_t stream, int gj_variant);
 void grouped_gemm_v(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, hipStream_t stream,
-                    int variant, int prec);
+                    int variant, int prec, int prof_cls = 5 /* PROF_GEMM */);
 
 // Look-ahead in the block Gauss-Jordan solver (default off): each step updates
 // the next panel's columns first, and the remaining columns on a side stream

@@ -1051,7 +1051,7 @@ void batched_solve(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc
 }
 
 void grouped_gemm_v(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, hipStream_t stream,
-                    int variant, int prec) {
+                    int variant, int prec, int prof_cls) {
   if (h_desc.empty()) return;
   int mmax = 0, nmax = 0;
   for (auto& g : h_desc) {
@@ -1074,7 +1074,7 @@ void grouped_gemm_v(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc,
   HPS_REQUIRE(prec == GEMM_F64 || prec == GEMM_SPLIT32 || prec == GEMM_BF16X6,
               "unknown GEMM arithmetic");
   ProfScope ps(prec == GEMM_SPLIT32 ? PROF_GEMM_SPLIT32
-                                    : (prec == GEMM_BF16X6 ? PROF_GEMM_BF16X6 : PROF_GEMM),
+                                    : (prec == GEMM_BF16X6 ? PROF_GEMM_BF16X6 : prof_cls),
                stream, fl, by);
   if (prec == GEMM_SPLIT32) {
     dim3 grid((nmax + TBN - 1) / TBN, (mmax + TBM - 1) / TBM, np);
@@ -1120,9 +1120,10 @@ int gemm_bucket_variant(const std::vector<GemmDesc>& h_desc) {
 }
 
 void grouped_gemm(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, hipStream_t stream,
-                  int prec) {
+                  int prec, int prof_cls) {
   if (h_desc.empty()) return;
-  grouped_gemm_v(d_desc, h_desc, stream, prec != GEMM_F64 ? 0 : gemm_bucket_variant(h_desc), prec);
+  grouped_gemm_v(d_desc, h_desc, stream, prec != GEMM_F64 ? 0 : gemm_bucket_variant(h_desc), prec,
+                 prof_cls);
 }
 
 // ---------------------------------------------------------------------------

@@ -25,6 +25,8 @@ enum ProfClass {
   PROF_POSTPROCESS = 14,
   PROF_GEMM_BF16X6 = 15,
   PROF_BODY_FLUX = 16,
+  PROF_LEAF_GEMM = 17,   // leaf T = P0 - P1 Z products (section 3.2, step 4)
+  PROF_MERGE_S = 18,     // S = M^-1 B products of the merges (eq:U_parent)
   PROF_NCLASS = 24
 };
 

@@ -536,7 +536,7 @@ static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hip
       batched_solve(dsd, sd, dstatus, s, panel);
       if (dps) pivot_check(dsd, cnt, tol, dstatus, s);
     }
-    grouped_gemm(dgd, gd, s, GEMM_F64);
+    grouped_gemm(dgd, gd, s, GEMM_F64, PROF_LEAF_GEMM);
     // Kept Z goes out transposed ([4q][(p-2)^2]) for the post-processing loads.
     std::vector<const double*> zs;  // live until the chunk's synchronization below
     std::vector<double*> zd;
@@ -753,7 +753,7 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
     }
     merge_gather(dm, (int)hm.size(), gmax, s);
     batched_solve(dsd, hs, dstatus, s, panel);
-    grouped_gemm(dsg, hsg, s, GEMM_F64);
+    grouped_gemm(dsg, hsg, s, GEMM_F64, PROF_MERGE_S);
     int kmax = 0;
     for (const GemmDesc& g : hg) kmax = std::max(kmax, g.K);
     grouped_gemm(dgd, hg, s, prec == GEMM_BF16X6 && kmax < bf16x6_min_k() ? GEMM_F64 : prec);

@@ -78,7 +78,7 @@ def test_gradients_match_fp64_oracle(H, gpu):
     for k in mlp.PARAM_NAMES:
         e = np.max(np.abs(G[k].reshape(Go[k].shape) - Go[k])) / np.max(np.abs(Go[k]))
         say(f"  d{k}: rel err {e:.2e}")
-        assert e < 3e-2, (k, e)
+        assert e < 5e-3, (k, e)
 
 
 def test_training_reduces_loss(H, gpu):
@@ -117,15 +117,28 @@ def test_surrogate_sweep_gain_and_error(H, gpu, trained, tmp_path):
     pr = hi.sweep_field(5000)
     C, f = library_inputs(pr)
     Cd, fd = _t(C, gpu), _t(f, gpu)
-    H.prof_enable(["leaf_lu", "gemm", "mlp_infer"])
-    H.prof_reset()
-    op_f = H.build_solution_operator(Cd, pr.box, pr.nleaf, pr.p, pr.q)
-    t_plain = H.prof_query("leaf_lu")["ms"] + H.prof_query("gemm")["ms"]
-    H.prof_reset()
-    op_s = H.build_solution_operator(Cd, pr.box, pr.nleaf, pr.p, pr.q, surrogate=trained,
-                                     judge_samples=256, judge_tol=1e-6)
-    t_sur = H.prof_query("mlp_infer")["ms"] + H.prof_query("leaf_lu")["ms"]
-    H.prof_enable([])
+    import time
+    leaf_classes = ["leaf_assemble", "leaf_lu", "leaf_gemm", "mlp_infer"]
+
+    def build(**kw):
+        """(operator, leaf-stage ms from HIP events, wall ms of the whole build)."""
+        torch.cuda.synchronize()
+        H.prof_enable(leaf_classes)
+        H.prof_reset()
+        t0 = time.perf_counter()
+        op = H.build_solution_operator(Cd, pr.box, pr.nleaf, pr.p, pr.q, **kw)
+        torch.cuda.synchronize()
+        wall = 1e3 * (time.perf_counter() - t0)
+        leaf = sum(H.prof_query(c)["ms"] for c in leaf_classes)
+        H.prof_enable([])
+        return op, leaf, wall
+
+    sk = dict(surrogate=trained, judge_samples=256, judge_tol=1e-6)
+    build()                                         # warm-up (plans, memory cache)
+    build(**sk)
+    op_f, t_plain, w_plain = build()
+    op_s, t_sur, w_sur = build(**sk)
+    say(f"build wall time: plain {w_plain:.1f} ms, surrogate {w_sur:.1f} ms")
     u_f = op_f.solve(fd).cpu().numpy()
     u_s = op_s.solve(fd).cpu().numpy()
     err = rel_err(u_s, u_f)
@@ -135,11 +148,13 @@ def test_surrogate_sweep_gain_and_error(H, gpu, trained, tmp_path):
     C0[:, 5] = 0.0
     op_0 = H.build_solution_operator(_t(C0, gpu), pr.box, pr.nleaf, pr.p, pr.q)
     err0 = rel_err(op_0.solve(fd).cpu().numpy(), u_f)
-    say(f"leaf stage: plain {t_plain:.2f} ms, surrogate {t_sur:.2f} ms; u rel err: "
+    say(f"leaf stage (assembly, elimination, T products, inference): plain {t_plain:.2f} ms, "
+        f"surrogate {t_sur:.2f} ms; u rel err: "
         f"surrogate {err:.2e}, T_Laplace-only {err0:.2e}; judged {op_s.n_judged} leaves, "
         f"worst {op_s.judge_worst:.2e}, fallback leaves {op_s.n_fallback_leaves}")
     assert op_s.n_judged == 256 and op_s.n_fallback_leaves == 0
-    assert t_sur < 0.25 * t_plain
+    assert t_sur < 0.5 * t_plain
+    assert w_sur < w_plain
     assert err < 1e-3 and err < 0.2 * err0
     # save / load round trip keeps predictions bit-identical
     path = tmp_path / "sur.bin"
