@@ -343,6 +343,15 @@ hps_status hps_interface_residual(const hps_op* op, const double* u, int nrhs, d
   });
 }
 
+hps_status hps_interface_residual_noalloc(const hps_op* op, const double* u, int nrhs, double* r,
+                                          void* stream) {
+  return guard([&] {
+    HPS_REQUIRE(op && u && r && nrhs >= 1, "bad arguments");
+    hps::residual_noalloc(op, u, nrhs, r, (hipStream_t)stream);
+    HPS_HIP(hipStreamSynchronize((hipStream_t)stream));
+  });
+}
+
 hps_status hps_solve_with_sources(hps_op* op, const double* f, const double* s, int nrhs, double* u,
                                   void* stream) {
   return guard([&] {
@@ -488,6 +497,9 @@ hps_status hps_tune_set(const char* knob, int value) {
     if (k == "leaf_variant") {
       HPS_REQUIRE(value >= -1 && value <= 4, "leaf_variant must be in [-1, 4]");
       hps::leaf_lu_set_variant(value);
+    } else if (k == "leaf_mfma") {
+      HPS_REQUIRE(value >= -1 && value <= 1, "leaf_mfma must be -1, 0 or 1");
+      hps::leaf_set_mfma(value != 0);
     } else if (k == "gemm_variant") {
       HPS_REQUIRE(value >= -1 && value < hps::GEMM_VARIANTS, "gemm_variant out of range");
       hps::tune_force(hps::TUNE_GEMM, value);

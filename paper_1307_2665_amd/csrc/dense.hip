@@ -8,6 +8,7 @@
 // eq:merge and the leaf's T = P0 - P1 Z.
 #include "dense.h"
 #include "mfma_tile.h"
+#include "wave_ops.h"
 #include "prof.h"
 #include "tune.h"
 
@@ -43,36 +44,6 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // positions k0..k0+kb-1 that were not chosen (D, ascending) go to the
 // positions of the chosen rows lying below the block (V, in pivot order).
 // ---------------------------------------------------------------------------
-
-// Search key of a pivot candidate: |v| rounded to float (NaN as +inf) with
-// the low 12 bits replaced by 4095 - slot, so one unsigned max finds both
-// the largest magnitude (to 2^-11 relative) and where it lives.  0 = none.
-__device__ inline unsigned pivot_key(double v, int slot) {
-  const unsigned u = (v != v) ? 0x7F800000u : __float_as_uint((float)fabs(v));
-  return (u & ~4095u) | (unsigned)(4095 - slot);
-}
-
-// Wave-wide unsigned max: DPP within each row of 16 lanes (quad swaps, then
-// row rotations by 4 and 8), then the four row results through readlane.
-__device__ inline unsigned wave_max_u32(unsigned k) {
-  k = max(k, (unsigned)__builtin_amdgcn_mov_dpp((int)k, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
-  k = max(k, (unsigned)__builtin_amdgcn_mov_dpp((int)k, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
-  k = max(k, (unsigned)__builtin_amdgcn_mov_dpp((int)k, 0x124, 0xF, 0xF, false));  // row_ror:4
-  k = max(k, (unsigned)__builtin_amdgcn_mov_dpp((int)k, 0x128, 0xF, 0xF, false));  // row_ror:8
-  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)k, 0);
-  const unsigned b = (unsigned)__builtin_amdgcn_readlane((int)k, 16);
-  const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)k, 32);
-  const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)k, 48);
-  return max(max(a, b), max(c, d));
-}
-
-// Orders a wave's LDS accesses: what one lane wrote before is visible to
-// every lane of the wave after it.
-__device__ inline void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Row moves of a step from the chosen rows pi[0..kb) (run by one wave).  The
 // block positions taken by a chosen row are marked in flag[0..kb) (LDS), so
@@ -278,14 +249,6 @@ __global__ void __launch_bounds__(64 * TP_MAXW) k_gj_panel(const SolveDesc* __re
   }
   __syncthreads();
   panel_tail<KB>(d, k0, kb, sNs, sBad != 0, status, sLU, sKeep, sPi, sD, sV, sFlag, &sNd);
-}
-
-// Broadcast of lane `src` (wave-uniform) of a double to the whole wave.
-__device__ inline double bcast_lane(double v, int src) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffll), src);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 // One-wave variant of k_gj_panel<2, KB> for panels of at most 128 rows:

@@ -16,6 +16,8 @@
 #include "leaf.h"
 #include "prof.h"
 #include "tune.h"
+#include "mfma_tile.h"
+#include "wave_ops.h"
 
 namespace hps {
 
@@ -461,12 +463,381 @@ __global__ void __launch_bounds__(16 * TC) k_leaf_gj(const double* const* __rest
   }
 }
 
+// ---------------------------------------------------------------------------
+// Leaf solve and DtN on FP64 MFMA (sections 3.1-3.2): blocked Gauss-Jordan on
+// W = [A_ii | R] (R = A_ie L1) with partial pivoting, rank-16 updates on
+// v_mfma_f64_16x16x4f64, and T = P0 - P1 Z formed before the leaf leaves the
+// CU (Z = A_ii^-1 R never goes to memory).
+//
+// W is padded to NR = 16 NTI rows and 16 (NTI + NTR) columns: padding rows and
+// columns of A_ii are identity, padding of R is zero.  Tile wave ti (< NTI)
+// holds row tile ti of W as NTI + NTR 16 x 16 MFMA accumulator tiles (lane l,
+// register r: row 16 ti + l/16 + 4r, column l%16 of the tile); wave NTI is the
+// panel wave.  Rows stay in place; a row chosen as a pivot is only marked.
+//
+// Step k eliminates the columns of block K = [16k, 16k + 16).  With P the 16
+// rows chosen as pivots and B = W[P, K], Gauss-Jordan takes W[P] to B^-1 W[P]
+// and every other row i to W[i] - W[i, K] B^-1 W[P]:
+//   1. the tile waves store their block-K tiles (the panel X) to LDS;
+//   2. the panel wave runs in-place Gauss-Jordan with partial pivoting on X
+//      (candidates: rows not chosen at an earlier step; every row is
+//      eliminated, earlier pivot rows included).  Column c of X ends up
+//      holding the multipliers of column c's step, so X becomes Z = E[:, P],
+//      the columns P of the step's elimination matrix E: Z[P] = B^-1 and
+//      Z[i] = -W[i, K] B^-1 elsewhere;
+//   3. each tile wave loads its rows of Z (in the MFMA A-operand layout),
+//      stages the chosen rows' values W[P, :] that it holds and sets those
+//      rows to zero;
+//   4. every tile (ti, tj) with tj past block K gets C += Z(ti) W[P, tj]
+//      (four MFMAs): the chosen rows become B^-1 W[P] from zero, with no
+//      cancellation between a row and its own update; block K itself is
+//      finished (it is not needed again).
+// After the last step row p of the R block holds row j of A_ii^-1 R, where p
+// is the pivot row of column j; the R block is staged in LDS in the order of
+// j, and T = P0 - P1 (A_ii^-1 R) is one more MFMA product.
+// Pivot search keys compare magnitudes rounded to float (ties to the lowest
+// row), so a pivot may differ from exact partial pivoting among candidates
+// within 2^-11 of each other; the results agree to rounding.
+// ---------------------------------------------------------------------------
+constexpr int LMF_XS = 17;  // LDS row stride of 16-wide blocks (odd: spreads banks)
+
+template <int NTI, int NTR>
+struct LeafMfmaShape {
+  static constexpr int NR = 16 * NTI;           // padded rows (and A_ii columns)
+  static constexpr int NTC = NTI + NTR;         // column tiles of W
+  static constexpr int NC = 16 * NTC;
+  static constexpr int NS = (NR + 63) / 64;     // row slots per lane of the panel wave
+  static constexpr int NW = NTI + 1;            // waves
+  static constexpr int LDR = 16 * NTR + 1;      // row stride of the staged R block
+  // LDS doubles: panel X, rows of Z, staged pivot rows (rows of W[P, :]);
+  // the R block reuses the same space at the end.
+  static constexpr int STEP = 2 * NR * LMF_XS + 16 * NC;
+  static constexpr int TAIL = NR * LDR;
+  static constexpr int BUF = STEP > TAIL ? STEP : TAIL;
+};
+
+template <int NTI, int NTR>
+__global__ void __launch_bounds__(64 * (NTI + 1), 4) k_leaf_mfma(
+    const double* const* __restrict__ cptr, const LeafDev tab, const double* __restrict__ P0,
+    const double* __restrict__ P1, double* const* __restrict__ tdst, int* status, int tag0,
+    double tol) {
+  using S = LeafMfmaShape<NTI, NTR>;
+  constexpr int NR = S::NR, NTC = S::NTC, NC = S::NC, NS = S::NS, XS = LMF_XS;
+  __shared__ double sD[4][256];
+  __shared__ double sc[6][NR];
+  __shared__ double sbuf[S::BUF];
+  __shared__ int sInv[NR];        // row -> column whose pivot it is
+  __shared__ int sIdx[NR];        // interior node j -> (1 + j % (p-2)) | (1 + j / (p-2)) << 8
+  __shared__ double sRed[S::NW];
+  double* sX = sbuf;                      // [NR][XS] panel block
+  double* sL = sbuf + NR * XS;            // [NR][XS] rows of Z (the step's multipliers)
+  double* sWP = sbuf + 2 * NR * XS;       // [16][NC] the chosen rows' values
+
+  const int p = tab.p, n = tab.n, m = tab.m, pi = p - 2;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool panel_wave = wid == NTI;
+  const int ti = wid;
+  const double* cl = cptr[blockIdx.x];
+  for (int e = tid; e < p * p; e += 64 * S::NW) {
+    sD[0][e] = tab.Dx[e];
+    sD[1][e] = tab.Dy[e];
+    sD[2][e] = tab.Dxx[e];
+    sD[3][e] = tab.Dyy[e];
+  }
+  for (int e = tid; e < 6 * NR; e += 64 * S::NW) {
+    const int f = e / NR, k = e % NR;
+    sc[f][k] = k < n ? cl[(size_t)f * p * p + (1 + k % pi) + p * (1 + k / pi)] : 0.0;
+  }
+  for (int e = tid; e < NR; e += 64 * S::NW) {
+    sInv[e] = 1 << 20;  // not chosen yet
+    sIdx[e] = e < n ? (1 + e % pi) | ((1 + e / pi) << 8) : 0;
+  }
+  __syncthreads();
+
+  // The panel wave and the tile waves run separate loops with the same
+  // sequence of workgroup barriers (three per step), so neither keeps the
+  // other's registers live.
+  if (panel_wave) {
+    __syncthreads();  // the tile waves' assembly (and their max|A_ii|)
+    double thr = 0.0;
+    if (tol > 0.0) {
+      double mx = 0.0;
+#pragma unroll
+      for (int w = 0; w < NTI; ++w) mx = fmax(mx, sRed[w]);
+      thr = uniform(tol * mx);
+    }
+    bool cand[NS];  // rows not chosen as a pivot yet
+#pragma unroll
+    for (int s = 0; s < NS; ++s) cand[s] = s * 64 + lane < NR;
+    bool bad = false;
+    for (int k = 0; k < NTI; ++k) {
+      __syncthreads();  // (1) the panel block is in LDS
+      double x[NS][16];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int row = s * 64 + lane;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) x[s][c] = row < NR ? sX[row * XS + c] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        unsigned key = 0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          if (cand[s]) key = max(key, pivot_key(x[s][c], s * 64 + lane));
+        const unsigned g = wave_max_u32(key);
+        // Every step leaves at least 16 candidates (NR - 16 k rows), so g != 0.
+        const int slot = 4095 - (int)(g & 4095u);
+        const int gs = slot >> 6, gl = slot & 63;
+        // The pivot row (all 16 columns: those left of c hold its multipliers
+        // of earlier columns, which Gauss-Jordan carries along) goes to scalar
+        // registers by readlane from lane gl of slot gs (gs is the same for the
+        // whole wave).
+        double prow[16];
+#pragma unroll
+        for (int c2 = 0; c2 < 16; ++c2) prow[c2] = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          if (gs == s) {
+#pragma unroll
+            for (int c2 = 0; c2 < 16; ++c2) prow[c2] = bcast_lane(x[s][c2], gl);
+            if (lane == gl) {
+              cand[s] = false;                  // chosen: no longer a candidate
+              sInv[s * 64 + lane] = 16 * k + c;
+            }
+          }
+        const double piv = prow[c];
+        const bool ok = g != 0 && piv != 0.0 && piv == piv && fabs(piv) != INFINITY &&
+                        fabs(piv) > thr;
+        bad |= !ok;
+        const double inv = uniform(ok ? 1.0 / piv : 0.0);
+        // In-place Gauss-Jordan step on column c: every row loses f times the
+        // scaled pivot row and column c takes the multipliers (-f / pivot);
+        // the pivot row is then overwritten with the scaled row (1 / pivot in
+        // column c).
+        double f[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) f[s] = x[s][c];
+#pragma unroll
+        for (int c2 = 0; c2 < 16; ++c2)
+          if (c2 != c) {
+            const double pr = prow[c2] * inv;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) x[s][c2] = fma(-f[s], pr, x[s][c2]);
+          }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) x[s][c] = -f[s] * inv;
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          if (gs == s) {
+            if (lane == gl) {
+#pragma unroll
+              for (int c2 = 0; c2 < 16; ++c2) x[s][c2] = c2 == c ? inv : prow[c2] * inv;
+            }
+          }
+      }
+      // Row i of the panel now holds row i of Z = E[:, P]: the update is
+      // W_new = W + Z W[P] with the chosen rows W[P] set to zero first.
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int row = s * 64 + lane;
+        if (row < NR) {
+#pragma unroll
+          for (int c2 = 0; c2 < 16; ++c2) sL[row * XS + c2] = x[s][c2];
+        }
+      }
+      __syncthreads();  // (2) factors out
+      __syncthreads();  // (3) the chosen rows' values are staged
+    }
+    if (bad && lane == 0)
+      if (atomicCAS(status, 0, 1) == 0) status[1] = tag0 - (int)blockIdx.x;
+    __syncthreads();  // before the tile waves reuse the step buffers for R
+  } else {
+    // ---- assembly of row tile ti of A_ii (formulas of k_leaf_lu); the R
+    // tiles are assembled during step 0's panel, when this wave waits ----
+    d4 acc[NTC];
+    double mine = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      // One row at a time: keeps the assembly's temporaries from piling up
+      // on top of the accumulator tiles.
+      __builtin_amdgcn_sched_barrier(0);
+      const int i = 16 * ti + (lane >> 4) + 4 * r;
+      const bool rv = i < n;
+      const int ii = sIdx[i], ia = ii & 255, ib = ii >> 8;
+      const double c11 = sc[0][i], c12 = sc[1][i], c22 = sc[2][i];
+      const double c1 = sc[3][i], c2 = sc[4][i], c0 = sc[5][i];
+#pragma unroll
+      for (int tj = 0; tj < NTI; ++tj) {
+        const int j = 16 * tj + (lane & 15);
+        double v = 0.0;
+        if (rv && j < n) {
+          const int jj = sIdx[j], ja = jj & 255, jb = jj >> 8;
+          const double dx = sD[0][ia * p + ja], dy = sD[1][ib * p + jb];
+          v = -2.0 * c12 * dx * dy;
+          if (ib == jb) v += -c11 * sD[2][ia * p + ja] + c1 * dx;
+          if (ia == ja) v += -c22 * sD[3][ib * p + jb] + c2 * dy;
+          if (i == j) v += c0;
+          mine = fmax(mine, fabs(v));
+        } else if (i == j) {
+          v = 1.0;  // padding: identity
+        }
+        acc[tj][r] = v;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mine = fmax(mine, __shfl_xor(mine, off));
+    if (lane == 0) sRed[wid] = mine;
+    __syncthreads();
+
+    for (int k = 0; k < NTI; ++k) {
+      // (1) the panel block to LDS
+#pragma unroll
+      for (int tj = 0; tj < NTI; ++tj)
+        if (tj == k) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            sX[(16 * ti + (lane >> 4) + 4 * r) * XS + (lane & 15)] = acc[tj][r];
+        }
+      __syncthreads();
+      if (k == 0) {
+        // R = A_ie L1 (five coefficient-free tables weighted by the row's
+        // coefficients), overlapping the first panel.
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          __builtin_amdgcn_sched_barrier(0);  // one row's loads in flight at a time
+          const int i = 16 * ti + (lane >> 4) + 4 * r;
+          const bool rv = i < n;
+          const double c11 = sc[0][i], c12 = sc[1][i], c22 = sc[2][i];
+          const double c1 = sc[3][i], c2 = sc[4][i];
+#pragma unroll
+          for (int tr = 0; tr < NTR; ++tr) {
+            const int jr = 16 * tr + (lane & 15);
+            double v = 0.0;
+            if (rv && jr < m) {
+              const size_t o = (size_t)i * m + jr, st = (size_t)n * m;
+              v = -c11 * tab.G[o] - 2.0 * c12 * tab.G[st + o] - c22 * tab.G[2 * st + o] +
+                  c1 * tab.G[3 * st + o] + c2 * tab.G[4 * st + o];
+            }
+            acc[NTI + tr][r] = v;
+          }
+        }
+      }
+      __syncthreads();  // (2) the panel wave's factors
+      // (3) this row tile's rows of Z (the A operands of the update) and the
+      // chosen rows' values held by this wave
+      double la[4];
+#pragma unroll
+      for (int st = 0; st < 4; ++st)
+        la[st] = sL[(16 * ti + (lane & 15)) * XS + 4 * st + (lane >> 4)];
+      int cr[4];  // column of this step whose pivot each of my rows is, or -1
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = sInv[16 * ti + (lane >> 4) + 4 * r] - 16 * k;
+        cr[r] = (c >= 0 && c < 16) ? c : -1;
+      }
+#pragma unroll
+      for (int tj = 0; tj < NTC; ++tj)
+        if (tj > k) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (cr[r] >= 0) {
+              sWP[cr[r] * NC + 16 * tj + (lane & 15)] = acc[tj][r];
+              acc[tj][r] = 0.0;  // the update then writes B^-1 W[P, :] into this row
+            }
+        }
+      __syncthreads();
+      // (4) rank-16 update of every tile right of block K
+#pragma unroll
+      for (int tj = 0; tj < NTC; ++tj)
+        if (tj > k) {
+#pragma unroll
+          for (int st = 0; st < 4; ++st) {
+            const double b = sWP[(4 * st + (lane >> 4)) * NC + 16 * tj + (lane & 15)];
+            acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(la[st], b, acc[tj], 0, 0, 0);
+          }
+          // Tile by tile: the next tile's operand loads are not hoisted above
+          // this one's products (they would not fit next to the accumulators).
+          __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    // The R block to LDS for T, row j of A_ii^-1 R (held by the pivot row
+    // of column j) at row j.
+    __syncthreads();  // every wave is done with the step buffers
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = sInv[16 * ti + (lane >> 4) + 4 * r];
+#pragma unroll
+      for (int tr = 0; tr < NTR; ++tr) sbuf[j * S::LDR + 16 * tr + (lane & 15)] = acc[NTI + tr][r];
+    }
+  }
+  __syncthreads();  // the R block is staged
+
+  // ---- T = P0 - P1' W_R ----
+  const double* sR = sbuf;  // [NR][LDR]
+  double* T = tdst[blockIdx.x];
+  for (int tt = wid; tt < NTR * NTR; tt += S::NW) {
+    const int ta = tt / NTR, tb = tt % NTR;
+    const int trow = 16 * ta + (lane & 15);
+    d4 t = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < NR / 4; ++ks) {
+      const int kk = 4 * ks + (lane >> 4);
+      const double a = (trow < m && kk < n) ? P1[(size_t)trow * n + kk] : 0.0;
+      const double b = sR[kk * S::LDR + 16 * tb + (lane & 15)];
+      t = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, t, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * ta + (lane >> 4) + 4 * r, col = 16 * tb + (lane & 15);
+      if (row < m && col < m) T[(size_t)row * m + col] = P0[(size_t)row * m + col] - t[r];
+    }
+  }
+}
+
+static bool g_leaf_mfma = true;
+static int g_leaf_variant = -1;  // -1: default choice; else forced leaf_lu variant index
+
+void leaf_set_mfma(bool on) { g_leaf_mfma = on; }
+
+bool leaf_mfma_fits(int n, int m) {
+  const int nti = (n + 15) / 16, ntr = (m + 15) / 16;
+  // A forced leaf_lu variant (leaf_variant knob) selects the older kernels.
+  return g_leaf_mfma && g_leaf_variant < 0 && ((nti == 7 && ntr == 3) || (nti == 4 && ntr == 2) ||
+                         (nti == 3 && ntr == 2) || (nti == 1 && ntr == 1) ||
+                         (nti == 2 && ntr == 2) || (nti == 5 && ntr == 2) ||
+                         (nti == 6 && ntr == 3));
+}
+
+void leaf_dtn_mfma(const double* const* cptr, const LeafDev& tab, const double* P0,
+                   const double* P1, double* const* tdst, int count, int* status, int tag0,
+                   hipStream_t s, double tol) {
+  const double n = tab.n, m = tab.m;
+  ProfScope ps(PROF_LEAF_LU, s, count * (2.0 * n * n * n / 3.0 + 2.0 * n * n * m + 2.0 * m * m * n),
+               8.0 * count * (6.0 * tab.p * tab.p + m * m));
+  const int nti = (tab.n + 15) / 16, ntr = (tab.m + 15) / 16;
+#define HPS_LMF(A, B)                                                                           \
+  if (nti == A && ntr == B) {                                                                   \
+    hipLaunchKernelGGL((k_leaf_mfma<A, B>), dim3(count), dim3(64 * (A + 1)), 0, s, cptr, tab, P0, \
+                       P1, tdst, status, tag0, tol);                                            \
+    return;                                                                                     \
+  }
+  HPS_LMF(7, 3)
+  HPS_LMF(4, 2)
+  HPS_LMF(3, 2)
+  HPS_LMF(1, 1)
+  HPS_LMF(2, 2)
+  HPS_LMF(5, 2)
+  HPS_LMF(6, 3)
+#undef HPS_LMF
+  HPS_REQUIRE(false, "leaf shape without an MFMA leaf kernel");
+}
+
 // Register variants: rows <= NR*TR, columns (n + m) <= NC*TC.
 bool leaf_lu_fits(int n, int m) {
   return (n <= 13 * 16 && n + m <= 8 * 32) || (n <= 7 * 16 && n + m <= 9 * 16);
 }
-
-static int g_leaf_variant = -1;  // -1: default choice; else forced variant index
 
 void leaf_lu_set_variant(int v) { g_leaf_variant = v; }
 

@@ -485,6 +485,25 @@ static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hip
   const LeafPlan& L0 = *jobs[0].lp;
   const int p = L0.lt.p, q = L0.lt.q, n = (p - 2) * (p - 2), m = 4 * q, ld = n + m;
   LeafDev tab{L0.dDx, L0.dDy, L0.dDxx, L0.dDyy, L0.dG, p, n, m, 0};
+  bool keepZ = false;
+  for (const LeafJob& j : jobs) keepZ = keepZ || j.zdst;
+  if (!keepZ && leaf_mfma_fits(n, m)) {
+    // MFMA leaf kernel: T straight from the coefficients, Z never stored.
+    const int total = (int)jobs.size();
+    std::vector<const double*> cp(total);
+    std::vector<double*> td(total);
+    for (int i = 0; i < total; ++i) {
+      cp[i] = jobs[i].coef;
+      td[i] = jobs[i].dst;
+    }
+    const double** dcp = tmp.alloc<const double*>(total);
+    double** dtd = tmp.alloc<double*>(total);
+    HPS_HIP(hipMemcpyAsync(dcp, cp.data(), total * sizeof(void*), hipMemcpyHostToDevice, s));
+    HPS_HIP(hipMemcpyAsync(dtd, td.data(), total * sizeof(void*), hipMemcpyHostToDevice, s));
+    leaf_dtn_mfma(dcp, tab, L0.dP0, L0.dP1, dtd, total, dstatus, -(jobs[0].leaf + 1), s, tol);
+    HPS_HIP(hipStreamSynchronize(s));  // the host pointer arrays are freed on return
+    return;
+  }
   const bool fused = leaf_lu_fits(n, m);
   // Fused path: only Z (n x m) per leaf; generic path: the augmented system.
   const size_t per = fused ? (size_t)n * m * sizeof(double)
@@ -497,8 +516,6 @@ static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hip
   const double** dcp = tmp.alloc<const double*>(CH);
   SolveDesc* dsd = fused ? nullptr : tmp.alloc<SolveDesc>(CH);
   GemmDesc* dgd = tmp.alloc<GemmDesc>(CH);
-  bool keepZ = false;
-  for (const LeafJob& j : jobs) keepZ = keepZ || j.zdst;
   const double** dzs = keepZ ? tmp.alloc<const double*>(CH) : nullptr;
   double** dzd = keepZ ? tmp.alloc<double*>(CH) : nullptr;
   // Pivot statistics of the generic path's systems (relative pivot test).

@@ -83,10 +83,11 @@ def test_well_conditioned_build_passes_pivot_test(H, gpu):
     assert np.max(np.abs(u - u_o)) / np.max(np.abs(u_o)) < 1e-10
 
 
-@pytest.mark.parametrize("p,q", [(16, 14), (21, 19), (10, 8)])
+@pytest.mark.parametrize("p,q", [(16, 14), (21, 19), (10, 8), (12, 10)])
 def test_singular_leaf_is_reported(H, gpu, p, q):
     """c = -lambda_1 of the leaf's interior collocation operator makes every A_ii
-    singular to rounding; p = 21 runs the unfused leaf path."""
+    singular to rounding; p = 21 runs the unfused leaf path, p = 10 and 12 the
+    MFMA leaf kernel."""
     h = 0.25
     m = hps.leaf_matrices(p, q, h, h)
     Ji = m["Ji"]

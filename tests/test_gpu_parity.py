@@ -141,7 +141,10 @@ def test_batched_solve_singular_last_pivot(H, gpu, n):
 # Leaf stage (section 3).
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("p,q", [(16, 14), (12, 10), (20, 18), (21, 20), (6, 4)])
+# p <= 12 (and q below p) take the MFMA leaf kernel; p = 16 the register
+# Gauss-Jordan kernel; p = 20 and 21 the unfused path.
+@pytest.mark.parametrize("p,q", [(16, 14), (12, 10), (20, 18), (21, 20), (6, 4), (7, 5), (8, 6),
+                                 (9, 7), (10, 8), (11, 9), (12, 11), (12, 6)])
 def test_leaf_dtn_parity(H, gpu, p, q):
     say(f"leaf_dtn p={p} q={q}")
     rng = np.random.default_rng(p * 31 + q)
@@ -156,9 +159,40 @@ def test_leaf_dtn_parity(H, gpu, p, q):
     C[:, 5] = -40.0 * rng.random((nl, p * p))
     T = H.leaf_dtn(_t(C, gpu), hx, hy, p, q).cpu().numpy()
     mats = hps.leaf_matrices(p, q, hx, hy)
+    worst = 0.0
     for i in range(nl):
         ref = hps.leaf_dtn(C[i], p, q, hx, hy, mats).T
+        worst = max(worst, rel_err(T[i], ref))
         assert rel_err(T[i], ref) < TOL, (i, rel_err(T[i], ref))
+    say(f"  worst rel err {worst:.2e}")
+
+
+@pytest.mark.parametrize("p,q", [(12, 10), (8, 6)])
+def test_leaf_mfma_matches_register_kernel(H, gpu, p, q):
+    """The MFMA leaf kernel against the register Gauss-Jordan kernel and the
+    separate T product (leaf_mfma off), on 300 leaves (several waves of
+    workgroups), a Helmholtz-like zeroth-order term and large convection."""
+    rng = np.random.default_rng(5 * p + q)
+    nl = 300
+    C = np.zeros((nl, 6, p * p))
+    C[:, 0] = 1.0 + 0.4 * rng.random((nl, p * p))
+    C[:, 2] = 1.0 + 0.4 * rng.random((nl, p * p))
+    C[:, 3] = 30.0 * rng.standard_normal((nl, p * p))
+    C[:, 4] = 30.0 * rng.standard_normal((nl, p * p))
+    C[:, 5] = -2000.0 * rng.random((nl, p * p))
+    Cd = _t(C, gpu)
+    T_m = H.leaf_dtn(Cd, 1.0 / 16, 1.0 / 16, p, q).cpu().numpy()
+    H.tune_set("leaf_mfma", 0)
+    try:
+        T_r = H.leaf_dtn(Cd, 1.0 / 16, 1.0 / 16, p, q).cpu().numpy()
+    finally:
+        H.tune_set("leaf_mfma", -1)
+    errs = [rel_err(T_m[i], T_r[i]) for i in range(nl)]
+    say(f"  MFMA vs register kernel: worst rel diff {max(errs):.2e}")
+    assert max(errs) < TOL
+    mats = hps.leaf_matrices(p, q, 1.0 / 16, 1.0 / 16)
+    for i in (0, 137, nl - 1):
+        assert rel_err(T_m[i], hps.leaf_dtn(C[i], p, q, 1.0 / 16, 1.0 / 16, mats).T) < TOL
 
 
 # ---------------------------------------------------------------------------
