@@ -235,6 +235,19 @@ hps_status hps_solve_body(hps_op* op, const double* f, const double* g, int nrhs
 hps_status hps_interface_residual(const hps_op* op, const double* u, int nrhs, double* r,
                                   void* stream);
 
+/* For callers that cannot allocate (code under graph capture, tight serving
+   loops): hps_interface_residual without any allocation.  The per-leaf flux
+   scratch (nrhs * nleaf * 4q doubles) comes from a fixed device array of
+   HPS_NOALLOC_SCRATCH_BYTES that each GPU holds for the life of the process;
+   calls that need more return HPS_EINVAL and launch nothing.  u and r are
+   device pointers ([nrhs][N]); the operator needs its leaf DtNs (every build
+   keeps them).  Waits for the stream before returning, like every call.
+   Every call on one GPU shares that GPU's array: calls that overlap on one
+   GPU (two streams, two threads) race and must be serialised by the caller. */
+#define HPS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+hps_status hps_interface_residual_noalloc(const hps_op* op, const double* u, int nrhs, double* r,
+                                          void* stream);
+
 /* Solution of "jump = s at interior nodes, u = f on Gamma": upward pass for the
    sources s [nrhs][N], then the downward pass.  Needs keep_factors. */
 hps_status hps_solve_with_sources(hps_op* op, const double* f, const double* s, int nrhs,

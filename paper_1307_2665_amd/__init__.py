@@ -476,6 +476,15 @@ class Operator:
         check(lib.hps_interface_residual(self._h, _ptr(u), u.shape[0], _ptr(r), _stream(u)))
         return r
 
+    def interface_residual_noalloc(self, u, r):
+        """hps_interface_residual_noalloc: the residual into a caller-given r, with no
+        allocation in the library (its scratch is a fixed per-device array)."""
+        u, r = _f64(u), _f64(r)
+        assert _dev(u) and _dev(r) and r.shape == u.shape
+        check(lib.hps_interface_residual_noalloc(self._h, _ptr(u), u.shape[0], _ptr(r),
+                                                 _stream(u)))
+        return r
+
     def solve_with_sources(self, f, s, u=None):
         import torch
         f = _f64(f)

@@ -183,6 +183,9 @@ void solve_batch_device(const std::vector<hps_op*>& ops, const std::vector<const
 void refine_device(hps_op* op, const double* f, int nrhs, double* u, double tol, int max_iter,
                    hipStream_t s, hps_solve_info* info);
 void residual_device(const hps_op* op, const double* u, int nrhs, double* r, hipStream_t s);
+// The same with the flux scratch in a fixed device array (no allocation);
+// throws HPS_EINVAL when nrhs * nleaf * 4q doubles exceed it.
+void residual_noalloc(const hps_op* op, const double* u, int nrhs, double* r, hipStream_t s);
 void solve_with_sources_device(hps_op* op, const double* f, const double* src, int nrhs, double* u,
                                hipStream_t s);
 void root_apply_device(const hps_op* op, const double* f, int nrhs, double* v, hipStream_t s);
