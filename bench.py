@@ -44,25 +44,30 @@ MODES = {"fp64": lambda H: H.HPS_FP64, "mixed": lambda H: H.HPS_MIXED_SPLIT32,
 DTYPE = {"fp64": "f64", "mixed": "f64+split-f32", "bf16x6": "f64+bf16x6"}
 # FP64 vector ALU peak: 256 CUs x 2.4 GHz x 128 FLOP/clk (64 FMA/clk/CU).
 ALU_F64_PEAK = 78.6
-# HBM bytes per launch of the dominant kernel on this workload, from two
-# rocprofv3 counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a
-# copy of known size); valid only while the kernel's source is unchanged.
-TRAFFIC = {"leaf_lu": dict(source="paper_1307_2665_amd/csrc/leaf.hip", sha256_16="29ac5aa2d2fa726d",
-                           bytes=430.2e6)}
+# HBM bytes per launch of a kernel class on the default workload, from two rocprofv3 counter runs
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a 256 MiB copy), valid only while every source
+# the kernel is built from is unchanged (profiles/gemm_schur_sweep_256x256_p12_counters.md).
+TRAFFIC = {"gemm": dict(sources={"paper_1307_2665_amd/csrc/dense.hip": "ce8c908d3a7704b5",
+                                 "paper_1307_2665_amd/csrc/mfma_tile.h": "3a9a0f4aa40c70ba"},
+                        bytes=6.419e9, workload="sweep-256x256-p12-q10-1rhs")}
 
 
-def measured_traffic(cls):
-    """Counter-derived bytes per launch for a kernel class, or None if its source changed."""
+def measured_traffic(cls, workload):
+    """Counter-derived bytes per launch for a kernel class on a workload, or None if a source
+    it is built from has changed since the counters were taken."""
     import hashlib
     t = TRAFFIC.get(cls)
-    if t is None:
+    if t is None or t["workload"] != workload:
         return None
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), t["source"])
-    try:
-        h = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
-    except OSError:
-        return None
-    return t["bytes"] if h == t["sha256_16"] else None
+    root = os.path.dirname(os.path.abspath(__file__))
+    for path, digest in t["sources"].items():
+        try:
+            h = hashlib.sha256(open(os.path.join(root, path), "rb").read()).hexdigest()[:16]
+        except OSError:
+            return None
+        if h != digest:
+            return None
+    return t["bytes"]
 
 
 def parse():
@@ -477,7 +482,8 @@ def sweep_workload(args, H, hi, np, torch, dev, line):
         dom = H.prof_query(dominant)
         H.prof_enable([])
         H.prof_reset()
-        roofs[form] = roofline_of(dominant, dom, args.steps)
+        roofs[form] = roofline_of(dominant, dom, args.steps,
+                                  measured_traffic(dominant, "sweep-256x256-p12-q10-1rhs"))
         # One solution per field for the comparison (not timed).
         us, fb = [], []
         for k in range(nf):
@@ -801,7 +807,7 @@ def main():
         achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=ALU_F64_PEAK, unit="TFLOP/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(dominant)
+    roof["traffic"] = measured_traffic(dominant, "convdiff-64x64-p16-q14-1rhs")
     roof["kernel"] = dominant
     roof["launches_per_step"] = dom["launches"] / args.steps
     roof["avg_launch_ms"] = dom["ms"] / max(dom["launches"], 1)
