@@ -105,6 +105,9 @@ def parse():
     return ap.parse_args()
 
 
+SHOW_KERNELS = False
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -170,6 +173,10 @@ def profile_first(H, torch, fn):
     per = {c: H.prof_query(c) for c in classes}
     H.prof_enable([])
     H.prof_reset()
+    if SHOW_KERNELS:
+        for c in sorted(per, key=lambda c: -per[c]["ms"]):
+            if per[c]["launches"]:
+                log(f"  {c:14s} {per[c]['ms']:9.3f} ms  {per[c]['launches']:6d} launches")
     return per, out
 
 
@@ -378,14 +385,26 @@ def other_workload(args, H, hi, np, torch, dev):
         box = {}
 
         def build():
+            box.pop("ops", None)
             box["ops"] = H.build_batch([dict(coeffs=C, box=pr.box, nleaf=pr.nleaf, p=pr.p, q=pr.q)
                                         for pr, (C, F) in zip(probs, ins)])
 
         def solve():
             box["u"] = H.solve_batch(box["ops"], [F for (C, F) in ins])
 
+        def step():
+            build()
+            solve()
+
+        per, _ = profile_first(H, torch, step)
+        dominant = dominant_of(per)
+        H.prof_enable([dominant])
+        H.prof_reset()
         bms, _ = _timed(torch, np, steps, build)
         sms, _ = _timed(torch, np, steps, solve)
+        dom = H.prof_query(dominant)
+        H.prof_enable([])
+        H.prof_reset()
         tot = sum(_n_tot(pr) for pr in probs)
         nrhs = sum(F.shape[0] for (C, F) in ins)
         # Same problems one by one (each parity-tested against the oracle): same solution.
@@ -394,11 +413,44 @@ def other_workload(args, H, hi, np, torch, dev):
             pr, (C, F) = probs[i], ins[i]
             op = H.build_solution_operator(C, pr.box, pr.nleaf, pr.p, pr.q)
             err = max(err, _rel(box["u"][i], op.solve(F)))
+        log("batch: " + ", ".join(f"{c}={per[c]['ms']:.2f}ms/{per[c]['launches']}" for c in per
+                                  if per[c]["launches"]))
         line.update(value=tot / ((bms + sms) * 1e-3), ms_per_step=bms + sms, dtype="f64",
                     config={"workload": "batch-32-uneven-16rhs", "n_tot": tot, "nrhs": nrhs,
                             "problems": [[pr.nleaf[0], pr.p] for pr in probs]},
                     build_ms=bms, solve_ms=sms, build_unknowns_per_s=tot / (bms * 1e-3),
-                    solves_per_s=nrhs / (sms * 1e-3), rel_err_vs_single=err)
+                    solves_per_s=nrhs / (sms * 1e-3), rel_err_vs_single=err,
+                    roofline=roofline_of(dominant, dom, steps + 1),
+                    kernel_ms_first_step={c: round(per[c]["ms"], 4) for c in per
+                                          if per[c]["launches"]})
+        if not args.no_cpu_baseline:
+            # The oracle on the smallest problems of the batch, in full (build and the 16-rhs
+            # solve), as a rate; larger problems cost more per unknown, so this rate is an upper
+            # bound for the whole batch.
+            import warnings
+            from oracle import hps
+            warnings.simplefilter("ignore")
+            order = sorted(range(len(probs)), key=lambda i: _n_tot(probs[i]))
+            done, n_done, t_cpu = [], 0, 0.0
+            for i in order:
+                pr = probs[i]
+                grid = hps.Grid(pr.box, pr.nleaf[0], pr.nleaf[1], pr.q)
+                Co = pr.coeffs_at(grid.cheb_xy(pr.p))
+                t0 = time.perf_counter()
+                op_o = hps.build(Co, pr.box, pr.nleaf, pr.p, pr.q, keep=False)
+                hps.solve(op_o, pr.bc_at(hps.gamma_xy(op_o)))
+                t_cpu += time.perf_counter() - t0
+                done.append(i)
+                n_done += _n_tot(pr)
+                if t_cpu > 15.0:
+                    break
+            line["cpu_baseline"] = {
+                "value": n_done / t_cpu, "unit": "unknowns/s", "cores": _blas_threads(),
+                "kind": "oracle",
+                "sample": f"problems {sorted(done)} of 32 (the smallest, {n_done} unknowns) built and "
+                          f"solved (16 rhs) in full; smaller problems cost less per unknown, so the "
+                          f"rate overstates the oracle on the whole batch",
+                "seconds": t_cpu}
         return line
     return sweep_workload(args, H, hi, np, torch, dev, line)
 
@@ -455,15 +507,21 @@ def sweep_workload(args, H, hi, np, torch, dev, line):
     tune_s = H.autotune([dict(nleaf=(n, n), p=p, q=q)]) if not args.no_tune else None
     sg, train = train_sweep_surrogate(args, H, hi, np, torch, dev, p, q, n)
     forms, sols, roofs = {}, {}, {}
-    for form in ("fp64", "surrogate"):
-        kw = dict(surrogate=sg, judge_samples=256, judge_tol=1e-6) if form == "surrogate" else {}
+    for form in ("fp64", "bf16x6", "surrogate"):
+        kw = (dict(surrogate=sg, judge_samples=256, judge_tol=1e-6) if form == "surrogate" else
+              dict(mode=H.HPS_MIXED_BF16X6) if form == "bf16x6" else {})
         last = {}
 
         def step(k):
             pr, (C, F) = fields[k % nf], ins[k % nf]
             last.pop("op", None)
             op = H.build_solution_operator(C, pr.box, pr.nleaf, p, q, **kw)
-            last["u"] = op.solve(F)
+            if form == "bf16x6":   # BF16 slice products, refined against the FP64 leaf DtNs
+                info = {}
+                last["u"] = op.solve(F, refine=True, tol=1e-11, max_iter=20, info=info)
+                last["info"] = info
+            else:
+                last["u"] = op.solve(F)
             last["op"] = op
             return op
 
@@ -494,7 +552,10 @@ def sweep_workload(args, H, hi, np, torch, dev, line):
         if form == "fp64":
             r = last["op"].interface_residual(last["u"])
             res = float(r.abs().max() / last["u"].abs().max())
+        info = last.get("info")
         last.clear()
+        if info is not None:
+            last["info"] = info
         sols[form] = us
         ms = 1e3 * t_total / args.steps
         forms[form] = {"ms_per_step": ms, "unknowns_per_s": n_tot / (ms * 1e-3),
@@ -504,14 +565,17 @@ def sweep_workload(args, H, hi, np, torch, dev, line):
                        "fallback_leaves": fb}
         if form == "fp64":
             forms[form]["residual_rel"] = res
+        if form == "bf16x6":
+            forms[form]["refine"] = last.get("info")
         log(f"sweep {form}: {ms:.2f} ms per field, " + ", ".join(
             f"{c}={per[c]['ms']:.2f}ms/{per[c]['launches']}" for c in per if per[c]["launches"]))
     errs = [_rel(a, b) for a, b in zip(sols["surrogate"], sols["fp64"])]
     forms["surrogate"]["rel_err_vs_fp64"] = max(errs)
+    forms["bf16x6"]["rel_err_vs_fp64"] = max(_rel(a, b) for a, b in zip(sols["bf16x6"], sols["fp64"]))
     forms["surrogate"]["training"] = train
-    sel = "fp64" if args.mode == "fp64" else "surrogate"
+    sel = args.mode if args.mode in forms else "fp64"
     line.update(value=forms[sel]["unknowns_per_s"], ms_per_step=forms[sel]["ms_per_step"],
-                dtype="f64",
+                dtype=DTYPE.get(sel, "f64"),
                 config={"workload": "sweep-256x256-p12-q10-1rhs", "nleaf": [n, n], "p": p, "q": q,
                         "nrhs": 1, "n_tot": n_tot, "fields_resident": nf, "mode": sel},
                 roofline=roofs[sel], forms=forms, autotune_s=tune_s,
@@ -688,7 +752,9 @@ def body_workload(args, H, hi, np, torch, dev, line):
 
 
 def main():
+    global SHOW_KERNELS
     args = parse()
+    SHOW_KERNELS = args.kernels
     if args.gpus != 1:
         print(f"bench.py: this benchmark runs on exactly one GPU (got --gpus {args.gpus}); the "
               "multi-GPU sharding is a design note, not a measured path.", file=sys.stderr)

@@ -400,9 +400,23 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
      (faster on MI355X: the side stream's update delays the next panel);
    "bf16x6_min_k": in HPS_MIXED_BF16X6 builds, merge levels whose longest
      contraction (interface length m3) is below this run their Schur
-     products in FP64 (-1: the default, 384; 0: BF16 on every level).
+     products in FP64 (-1: the default, 384; 0: BF16 on every level);
+   "leaf_mfma": 1 (default, also -1) runs leaves with (p-2)^2 <= 112 on the
+     MFMA leaf kernel (T formed in the kernel), 0 on leaf_variant's kernels;
+   "bgj_min_rows": merge levels whose largest system (M = T33a - T33b, m3
+     rows) has at least this many rows eliminate [M | I] by blocked
+     Gauss-Jordan with pivoting inside 64 x 64 diagonal blocks (-1: the
+     default, 256; 0: never), the others by partial pivoting;
+   "bgj_fallback_tol_exp": e; a level whose blocked elimination meets a
+     block pivot of at most 10^-e max|M| (or a zero or non-finite one) is
+     gathered again and eliminated with partial pivoting (-1: the default,
+     e = 6; 0 makes every level fall back).
    Unknown knobs or values give HPS_EINVAL. */
 hps_status hps_tune_set(const char* knob, int value);
+
+/* Number of merge levels, over all builds of this process, whose blocked
+   Gauss-Jordan elimination fell back to partial pivoting. */
+hps_status hps_bgj_fallbacks(long long* count);
 
 /* Autotuner.  For every problem shape in probs (only nleaf, p, q and box are
    read; coeffs may be NULL) it times every variant of the leaf kernel, of the

@@ -169,6 +169,14 @@ def tune_set(knob: str, value: int) -> None:
     check(lib.hps_tune_set(knob.encode(), int(value)))
 
 
+def bgj_fallbacks() -> int:
+    """Merge levels (all builds of this process) whose blocked Gauss-Jordan fell back to
+    partial pivoting."""
+    n = C.c_longlong()
+    check(lib.hps_bgj_fallbacks(C.byref(n)))
+    return n.value
+
+
 def autotune(shapes, stream=None) -> float:
     """Times every kernel variant for the builds of the given problem shapes
     (dicts with nleaf, p, q and optionally box) and keeps the fastest per shape

@@ -76,6 +76,7 @@ SIGNATURES = {
     "hps_solve_body": [P, P, P, I, P, P, C.POINTER(SolveOpts)],
     "hps_interface_residual": [P, P, I, P, P],
     "hps_interface_residual_noalloc": [P, P, I, P, P],
+    "hps_bgj_fallbacks": [C.POINTER(C.c_longlong)],
     "hps_solve_with_sources": [P, P, P, I, P, P],
     "hps_build_batch": [C.POINTER(Problem), I, C.POINTER(BuildOpts), C.POINTER(P)],
     "hps_solve_batch": [P, I, P, P, P, C.POINTER(SolveOpts)],

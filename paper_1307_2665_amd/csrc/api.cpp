@@ -490,6 +490,13 @@ hps_status hps_batched_gemm(const double* A, const double* B, double* C, int Mr,
   });
 }
 
+hps_status hps_bgj_fallbacks(long long* count) {
+  return guard([&] {
+    HPS_REQUIRE(count != nullptr, "null count");
+    *count = hps::bgj_fallbacks();
+  });
+}
+
 hps_status hps_tune_set(const char* knob, int value) {
   return guard([&] {
     HPS_REQUIRE(knob != nullptr, "null knob");
@@ -500,6 +507,12 @@ hps_status hps_tune_set(const char* knob, int value) {
     } else if (k == "leaf_mfma") {
       HPS_REQUIRE(value >= -1 && value <= 1, "leaf_mfma must be -1, 0 or 1");
       hps::leaf_set_mfma(value != 0);
+    } else if (k == "bgj_min_rows") {
+      HPS_REQUIRE(value >= -1, "bgj_min_rows must be >= -1");
+      hps::set_bgj(value < 0 ? 256 : value, -1.0);
+    } else if (k == "bgj_fallback_tol_exp") {
+      HPS_REQUIRE(value >= -1 && value <= 300, "bgj_fallback_tol_exp must be in [-1, 300]");
+      hps::set_bgj(-1, value < 0 ? 1e-6 : std::pow(10.0, -value));
     } else if (k == "gemm_variant") {
       HPS_REQUIRE(value >= -1 && value < hps::GEMM_VARIANTS, "gemm_variant out of range");
       hps::tune_force(hps::TUNE_GEMM, value);

@@ -52,6 +52,18 @@ void pstat_init(unsigned long long* pstat, size_t count, hipStream_t s);
 void system_absmax(const SolveDesc* d_desc, int count, int nmax, hipStream_t s);
 void pivot_check(const SolveDesc* d_desc, int count, double tol, int* status, hipStream_t s);
 void dense_init();
+
+// Blocked Gauss-Jordan with pivoting inside 64 x 64 diagonal blocks (see
+// dense.hip); binv: scratch of 64 x 64 doubles per system.  Raises
+// status[3] when a block pivot is not above fb_tol max|M|: the caller then
+// redoes the systems with batched_solve.  Used for systems of at least
+// bgj_min_rows() rows (set_bgj: -1 keeps a value).
+void batched_solve_bgj(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc, int* d_status,
+                       double* binv, hipStream_t stream);
+void set_bgj(int min_rows, double fb_tol);
+// Clears the smallest-pivot statistic of every system (before a redo).
+void pstat_reset_min(const SolveDesc* d_desc, int count, hipStream_t s);
+int bgj_min_rows();
 int max_solve_rows();
 
 }  // namespace hps

@@ -1001,6 +1001,176 @@ void batched_solve_v(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_de
   if (pending) HPS_HIP(hipStreamWaitEvent(stream, la.done, 0));
 }
 
+// ---------------------------------------------------------------------------
+// Blocked Gauss-Jordan with pivoting inside the diagonal block (large merge
+// systems).  Step k0 of W = [M | I] (n = m3 rows, kb = min(64, n - k0)):
+//   1. k_bgj_diag: B^-1 of the diagonal block B = W[K, K], K = [k0, k0 + kb),
+//      by in-place Gauss-Jordan with partial pivoting among the kb rows of
+//      the block (one wave per system, rows in registers, the pivot row
+//      broadcast by readlane);
+//   2. k_bgj_rows: the block's rows become B^-1 W[K, k0 + kb:] (FP64 MFMA);
+//   3. k_gj_update: every other row gets W[i, :] -= W[i, K] W_new[K, :].
+// No rows move, so the identity block ends up holding M^-1 in natural
+// order, as with the partial-pivoting path.  The serial part of a step is a
+// 64-column elimination of 64 rows, not of the whole remaining column, which
+// is what makes the top merges (thousands of rows) fast.  Stability rests on
+// the diagonal blocks: a block pivot below fb_tol max|M| (or a zero or
+// non-finite one) raises status[3], and the caller redoes the level with
+// partial pivoting.
+// ---------------------------------------------------------------------------
+constexpr int BGJ_NB = 64;
+
+__global__ void __launch_bounds__(64) k_bgj_diag(const SolveDesc* __restrict__ descs, int k0,
+                                                 double* __restrict__ binv, double fb_tol,
+                                                 int* status) {
+  __shared__ int sP[BGJ_NB], sPi[BGJ_NB];
+  const SolveDesc d = descs[blockIdx.x];
+  if (k0 >= d.n) return;
+  const int kb = min(BGJ_NB, d.n - k0);
+  const int lane = threadIdx.x;
+  const size_t ld = d.ld;
+  const double* Bk = d.W + (size_t)k0 * ld + k0;
+  // One wave: lane r holds row r of the block; padding (rows or columns >=
+  // kb) is the identity, which no real column can pick.
+  double x[BGJ_NB];
+#pragma unroll
+  for (int c = 0; c < BGJ_NB; ++c)
+    x[c] = (lane < kb && c < kb) ? Bk[(size_t)lane * ld + c] : (lane == c ? 1.0 : 0.0);
+  bool chosen = false, bad = false;
+  double minp = INFINITY;
+#pragma unroll
+  for (int c = 0; c < BGJ_NB; ++c) {
+    if (c >= kb) continue;  // wave-uniform
+    const unsigned key = chosen ? 0u : pivot_key(x[c], lane);
+    const unsigned g = wave_max_u32(key);
+    const int pr = 4095 - (int)(g & 4095u);
+    if (lane == 0) sP[c] = g != 0 ? pr : 0;
+    chosen |= lane == pr;
+    // The pivot row reaches every lane through readlane (pr is uniform).
+    const double piv = bcast_lane(x[c], pr);
+    const bool ok = g != 0 && piv != 0.0 && piv == piv && fabs(piv) != INFINITY;
+    bad |= !ok;
+    minp = fmin(minp, fabs(piv));
+    const double inv = ok ? 1.0 / piv : 0.0;
+    // In-place Gauss-Jordan step: the pivot row is scaled, every other row
+    // loses f times it, column c takes the multipliers.
+    const double f = x[c];
+    const bool me = lane == pr;
+#pragma unroll
+    for (int j = 0; j < BGJ_NB; ++j)
+      if (j != c) {
+        const double pj = bcast_lane(x[j], pr) * inv;
+        x[j] = me ? pj : fma(-f, pj, x[j]);
+      }
+    x[c] = me ? inv : -f * inv;
+  }
+  // Pivot statistics and the fall-back test (block pivots against max|M|);
+  // a zero or non-finite block pivot also falls back (the partial-pivoting
+  // path then decides whether M itself is singular).
+  if (lane == 0) {
+    if (d.pstat && !bad) atomicMin(d.pstat + 1, abs_bits(minp));
+    const double amax = d.pstat ? __longlong_as_double((long long)d.pstat[0]) : 0.0;
+    if (bad || !(minp > fb_tol * amax)) atomicExch(status + 3, 1);
+  }
+  sPi[lane] = 0;  // in range even for a failed block
+  wave_lds_sync();
+  if (lane < kb) sPi[sP[lane]] = lane;
+  wave_lds_sync();
+  // In-place Gauss-Jordan with marked (unmoved) pivot rows leaves X with
+  // B^-1[Pi[r]][P[c]] = X[r][c] (P: pivot row of each column, Pi its inverse).
+  double* Bi = binv + (size_t)blockIdx.x * BGJ_NB * BGJ_NB;
+  if (lane < kb) {
+    const int a = sPi[lane];
+#pragma unroll
+    for (int c = 0; c < BGJ_NB; ++c)
+      if (c < kb) Bi[(size_t)a * BGJ_NB + sP[c]] = x[c];
+  }
+}
+
+// Rows K of every system: W[K, k0 + kb + c] = B^-1 W[K, k0 + kb + c] for the
+// columns c of this tile (one 64-row tile covers all kb rows, so a tile reads
+// its own columns of W[K, :] before it overwrites them).
+__global__ void __launch_bounds__(256) k_bgj_rows(const SolveDesc* __restrict__ descs, int k0,
+                                                  const double* __restrict__ binv) {
+  __shared__ double sm[GemmTile<64, 64, 16, 2, 2>::SMEM];
+  const SolveDesc d = descs[blockIdx.z];
+  if (k0 >= d.n) return;
+  const int kb = min(BGJ_NB, d.n - k0);
+  // Columns k0 + kb .. n + k0 + kb - 1: the rest of M and the part of the
+  // identity block already touched (its later columns are still unit
+  // vectors that no step changes before its own).
+  const int ncols = min(d.n, d.n + d.m - k0 - kb);
+  if ((int)blockIdx.x * 64 >= ncols) return;
+  double* Wk = d.W + (size_t)k0 * d.ld + k0 + kb;
+  gemm_tile_map<64, 64, 16, 2, 2, RowsIdentity, RowsIdentity, RowsIdentity, NoC0Elem, false, 3>(
+      binv + (size_t)blockIdx.z * BGJ_NB * BGJ_NB, BGJ_NB, Wk, (int)d.ld, RowsIdentity{}, Wk,
+      (int)d.ld, RowsIdentity{}, nullptr, 0, kb, ncols, kb, 1.0, 0, blockIdx.x * 64, sm, false);
+}
+
+__global__ void k_pstat_reset_min(const SolveDesc* __restrict__ descs, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count && descs[i].pstat) descs[i].pstat[1] = ~0ull;
+}
+
+void pstat_reset_min(const SolveDesc* d_desc, int count, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_pstat_reset_min, dim3((count + 255) / 256), dim3(256), 0, s, d_desc, count);
+}
+
+static double g_bgj_fb_tol = 1e-6;
+static int g_bgj_min_rows = 256;
+
+void set_bgj(int min_rows, double fb_tol) {
+  if (min_rows >= 0) g_bgj_min_rows = min_rows;
+  if (fb_tol >= 0.0) g_bgj_fb_tol = fb_tol;
+}
+
+int bgj_min_rows() { return g_bgj_min_rows; }
+
+void batched_solve_bgj(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc, int* d_status,
+                       double* binv, hipStream_t stream) {
+  if (h_desc.empty()) return;
+  int nmax = 0, wmax = 0;
+  for (auto& d : h_desc) {
+    // Only the untouched columns of the identity block are skipped, so the
+    // right-hand block must be I (m == n).
+    HPS_REQUIRE(d.m == d.n, "blocked Gauss-Jordan needs W = [M | I]");
+    nmax = std::max(nmax, d.n);
+    wmax = std::max(wmax, d.n + d.m);
+  }
+  const int np = (int)h_desc.size();
+  const int upd = 0;
+  for (int k0 = 0; k0 < nmax; k0 += BGJ_NB) {
+    double fd = 0, fr = 0, fu = 0;
+    for (auto& d : h_desc) {
+      if (k0 >= d.n) continue;
+      const double kb = std::min(BGJ_NB, d.n - k0), rest = std::min<double>(d.n, d.n + d.m - k0 - kb);
+      fd += 2.0 * kb * kb * kb;
+      fr += 2.0 * kb * kb * rest;
+      fu += 2.0 * (d.n - kb) * rest * kb;
+    }
+    {
+      ProfScope ps(PROF_LU_PANEL, stream, fd, 0);
+      hipLaunchKernelGGL(k_bgj_diag, dim3(np), dim3(64), 0, stream, d_desc, k0, binv,
+                         g_bgj_fb_tol, d_status);
+    }
+    // Columns past the block: the rest of M and the touched part of the
+    // identity block, n columns in all (k_bgj_rows and the update clip them
+    // per system).
+    const int rest = std::min(nmax, wmax - k0 - std::min(BGJ_NB, nmax - k0));
+    if (rest <= 0) continue;
+    {
+      ProfScope ps(PROF_SWAP_TRSM, stream, fr, 0);
+      hipLaunchKernelGGL(k_bgj_rows, dim3((rest + 63) / 64, 1, np), dim3(256), 0, stream, d_desc,
+                         k0, (const double*)binv);
+    }
+    {
+      ProfScope ps(PROF_LU_UPDATE, stream, fu, 0);
+      launch_update(upd, d_desc, np, k0, BGJ_NB, nmax, 0, rest, stream);
+    }
+  }
+}
+
 void batched_solve(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc, int* d_status,
                    hipStream_t stream, int /*nb_hint*/) {
   if (h_desc.empty()) return;

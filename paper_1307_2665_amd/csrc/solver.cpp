@@ -15,6 +15,7 @@
 #include "solver.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -693,6 +694,11 @@ static void surrogate_leaf_stage(hps_op* op, DeviceMem& tmp, hipStream_t s, int*
   HPS_HIP(hipStreamSynchronize(s));
 }
 
+// Levels whose blocked Gauss-Jordan fell back to partial pivoting (all builds).
+static std::atomic<long long> g_bgj_fallbacks{0};
+
+long long bgj_fallbacks() { return g_bgj_fallbacks.load(); }
+
 void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
   DeviceMem tmp;
   int* dstatus = tmp.alloc<int>(4);
@@ -769,7 +775,27 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
       dsg = e;
     }
     merge_gather(dm, (int)hm.size(), gmax, s);
-    batched_solve(dsd, hs, dstatus, s, panel);
+    int nmax_level = 0;
+    for (const SolveDesc& sd : hs) nmax_level = std::max(nmax_level, sd.n);
+    bool solved = false;
+    if (bgj_min_rows() > 0 && nmax_level >= bgj_min_rows()) {
+      // Large systems: blocked Gauss-Jordan with pivoting inside 64 x 64
+      // diagonal blocks; should a block pivot be too small, the level is
+      // gathered again and solved with partial pivoting.
+      double* binv = tmp.alloc<double>(hs.size() * 64 * 64);
+      HPS_HIP(hipMemsetAsync(dstatus + 3, 0, sizeof(int), s));
+      batched_solve_bgj(dsd, hs, dstatus, binv, s);
+      int fb = 0;
+      HPS_HIP(hipMemcpyAsync(&fb, dstatus + 3, sizeof(int), hipMemcpyDeviceToHost, s));
+      HPS_HIP(hipStreamSynchronize(s));
+      solved = fb == 0;
+      if (!solved) {
+        g_bgj_fallbacks.fetch_add(1);
+        merge_gather(dm, (int)hm.size(), gmax, s);
+        pstat_reset_min(dsd, (int)hs.size(), s);
+      }
+    }
+    if (!solved) batched_solve(dsd, hs, dstatus, s, panel);
     grouped_gemm(dsg, hsg, s, GEMM_F64, PROF_MERGE_S);
     int kmax = 0;
     for (const GemmDesc& g : hg) kmax = std::max(kmax, g.K);

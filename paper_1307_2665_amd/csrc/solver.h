@@ -201,6 +201,9 @@ void set_solve_graph(bool on);
 // Solves, source solves and refinement with at least v right-hand sides run
 // on node-major arrays with MFMA GEMMs (default 16; 0: never).
 void set_solve_mm_min_rhs(int v);
+// Merge levels (over all builds so far) whose blocked Gauss-Jordan fell back
+// to partial pivoting.
+long long bgj_fallbacks();
 // Releases the stream-ordered scratch cached in the current device's pool.
 void trim_async_pool();
 

@@ -373,3 +373,54 @@ def test_gj_lookahead_matches_serial_steps(H, gpu):
     assert rel_err(out[1][0], np.linalg.solve(M, B)) < 1e-10
     for a, b in zip(out[1], out[0]):
         assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# Merge systems by blocked Gauss-Jordan (pivoting inside 64 x 64 diagonal
+# blocks) and its fall-back to partial pivoting.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("maker,nleaf", [
+    (lambda: hi.convdiff(nleaf=(16, 16), p=12, q=10), (16, 16)),
+    (lambda: hi.helmholtz_bump(kappa=25.0, nleaf=(8, 16), p=12, q=10, nrhs=3), (8, 16)),
+    (lambda: hi.manufactured_variable(nleaf=(12, 10), p=10, q=8), (12, 10)),
+])
+def test_blocked_gauss_jordan_merges_match_oracle(H, gpu, maker, nleaf):
+    """Every merge level on the blocked path (bgj_min_rows = 1): every merge's S, the root DtN
+    and u against the oracle at 1e-10 (ragged last blocks: m3 is not a multiple of 64)."""
+    pr = maker()
+    op_o, Co, fo, grid = oracle_problem(pr)
+    C, f = library_inputs(pr)
+    before = H.bgj_fallbacks()
+    H.tune_set("bgj_min_rows", 1)
+    try:
+        op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q)
+    finally:
+        H.tune_set("bgj_min_rows", -1)
+    assert H.bgj_fallbacks() == before
+    _compare_operator(H, op, op_o)
+    u = op.solve(_t(f, gpu)).cpu().numpy()
+    e = rel_err(u, hps.solve(op_o, fo))
+    say(f"  blocked Gauss-Jordan {pr.name} {nleaf}: u rel err {e:.2e}")
+    assert e < TOL
+
+
+def test_blocked_gauss_jordan_fallback(H, gpu):
+    """A fall-back threshold of max|M| sends every blocked level back to partial pivoting: the
+    counter moves and the operator still matches the oracle."""
+    pr = hi.convdiff(nleaf=(8, 8), p=12, q=10)
+    op_o, Co, fo, grid = oracle_problem(pr)
+    C, f = library_inputs(pr)
+    before = H.bgj_fallbacks()
+    H.tune_set("bgj_min_rows", 1)
+    H.tune_set("bgj_fallback_tol_exp", 0)
+    try:
+        op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q)
+    finally:
+        H.tune_set("bgj_min_rows", -1)
+        H.tune_set("bgj_fallback_tol_exp", -1)
+    fell = H.bgj_fallbacks() - before
+    say(f"  fallbacks: {fell}")
+    assert fell == len([d for d in range(20) if any(b.level == d and not b.is_leaf
+                                                     for b in op_o.boxes)])
+    _compare_operator(H, op, op_o)
