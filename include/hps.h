@@ -378,7 +378,8 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
    "gemm_variant": FP64 MFMA GEMM tile (0: 64x64x16 on 2x2 waves with three
      k-slabs of loads in flight, 1: 32x32x16 on one wave, 2: 128x128x16 on
      eight waves, 3: 128x64x16, 4: 64x128x16, 5: 64x64x32, 6: 64x64x16 with
-     one slab in flight; 1-6 keep one slab in flight);
+     one slab in flight; 1-6 keep one slab in flight; 7: 128x128x16 on 2x2
+     waves of 64x64, two LDS buffers, tiles in XCD-grouped order);
    "gj_variant": merge solver, 4 * (update tile) + TRSM block (0: 256, 1: 128,
      2: 64 threads); update tiles 0: 64x64x16 on 2x2 waves, 1: 32x32x16 on
      one wave, 2: 128x128x16 on 4x2 waves, 3: 128x64x16, 4: 64x128x16,
@@ -443,10 +444,12 @@ hps_status hps_tune_reset(void);
    elimination, 12 surrogate training, 13 surrogate inference, 14
    post-processing, 15 BF16 three-slice Schur GEMM, 16 body-load fluxes from
    the kept body operator, 17 leaf T = P0 - P1 Z products (section 3.2),
-   18 the merges' S = M^-1 B products (eq:U_parent).  Bit c of mask enables class c; every later launch of an
-   enabled class records a start and stop event on its stream together with
-   its algorithmic FLOPs and bytes.  Costs one event pair per launch while
-   enabled. */
+   18 the merges' S = M^-1 B products (eq:U_parent), 19-21 the blocked
+   Gauss-Jordan steps of large merge systems (diagonal-block inverses, block
+   rows, updates of the other rows).  Bit c of mask enables class c; every
+   later launch of an enabled class records a start and stop event on its
+   stream together with its algorithmic FLOPs and bytes.  Costs one event
+   pair per launch while enabled. */
 hps_status hps_prof_enable(unsigned mask);
 /* Drops all records (waits for their events first). */
 hps_status hps_prof_reset(void);

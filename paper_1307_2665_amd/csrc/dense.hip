@@ -461,9 +461,9 @@ struct MergePass {
   const double* __restrict__ Tb;
   int na, nb;
   __device__ double operator()(int r, int c) const {
-    const int pr = __ldg(pmap + r), pc = __ldg(pmap + c);
-    if (pr >= 0) return pc >= 0 ? __ldg(Ta + (size_t)pr * na + pc) : 0.0;
-    return pc < 0 ? __ldg(Tb + (size_t)(-pr - 1) * nb + (-pc - 1)) : 0.0;
+    const int pr = as_global(pmap)[r], pc = as_global(pmap)[c];
+    if (pr >= 0) return pc >= 0 ? as_global(Ta)[(size_t)pr * na + pc] : 0.0;
+    return pc < 0 ? as_global(Tb)[(size_t)(-pr - 1) * nb + (-pc - 1)] : 0.0;
   }
 };
 
@@ -488,6 +488,22 @@ __global__ void __launch_bounds__(64 * WM * WN) k_gemm(const GemmDesc* __restric
                   DEPTH>(g.A, g.lda, g.B, g.ldb, RowsIdentity{}, g.C, g.ldc, RowsIdentity{}, g.C0,
                          g.ldc0, g.M, g.N, g.K, g.alpha, blockIdx.y * BM, blockIdx.x * BN, sm,
                          g.overwrite == 0);
+}
+
+// The 128 x 128 tile (gemm128_tile), tiles in XCD-grouped order.
+template <int VEC, bool PASS>
+__global__ void __launch_bounds__(256, 2) k_gemm128(const GemmDesc* __restrict__ descs) {
+  __shared__ double sm[Gemm128::SMEM];
+  const GemmDesc g = descs[blockIdx.z];
+  int tx, ty;
+  gemm128_tile_order(gridDim.x, gridDim.y, blockIdx.x, blockIdx.y, tx, ty);
+  if (ty * Gemm128::BM >= g.M || tx * Gemm128::BN >= g.N) return;
+  if constexpr (PASS)
+    gemm128_tile<VEC>(g.A, g.lda, g.B, g.ldb, g.C, g.ldc, nullptr, 0, g.M, g.N, g.K, g.alpha,
+                      ty * Gemm128::BM, tx * Gemm128::BN, sm, false, merge_pass(g));
+  else
+    gemm128_tile<VEC>(g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.C0, g.ldc0, g.M, g.N, g.K, g.alpha,
+                      ty * Gemm128::BM, tx * Gemm128::BN, sm, g.overwrite == 0, NoC0Elem{});
 }
 
 // ---------------------------------------------------------------------------
@@ -1006,8 +1022,9 @@ void batched_solve_v(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_de
 // systems).  Step k0 of W = [M | I] (n = m3 rows, kb = min(64, n - k0)):
 //   1. k_bgj_diag: B^-1 of the diagonal block B = W[K, K], K = [k0, k0 + kb),
 //      by in-place Gauss-Jordan with partial pivoting among the kb rows of
-//      the block (one wave per system, rows in registers, the pivot row
-//      broadcast by readlane);
+//      the block (one workgroup per system: wave w holds 16 columns of every
+//      row, the pivot row reaches each wave by readlane, the multipliers
+//      through LDS; one barrier per column);
 //   2. k_bgj_rows: the block's rows become B^-1 W[K, k0 + kb:] (FP64 MFMA);
 //   3. k_gj_update: every other row gets W[i, :] -= W[i, K] W_new[K, :].
 // No rows move, so the identity block ends up holding M^-1 in natural
@@ -1020,70 +1037,95 @@ void batched_solve_v(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_de
 // ---------------------------------------------------------------------------
 constexpr int BGJ_NB = 64;
 
-__global__ void __launch_bounds__(64) k_bgj_diag(const SolveDesc* __restrict__ descs, int k0,
-                                                 double* __restrict__ binv, double fb_tol,
-                                                 int* status) {
+__global__ void __launch_bounds__(256) k_bgj_diag(const SolveDesc* __restrict__ descs, int k0,
+                                                  double* __restrict__ binv, double fb_tol,
+                                                  int* status) {
+  // Multipliers of the current column (double-buffered by column parity, so
+  // one barrier per column suffices), its pivot row and pivot.
+  __shared__ double sF[2][BGJ_NB];
+  __shared__ double sPiv[2];
+  __shared__ int sPr[2];
   __shared__ int sP[BGJ_NB], sPi[BGJ_NB];
   const SolveDesc d = descs[blockIdx.x];
   if (k0 >= d.n) return;
   const int kb = min(BGJ_NB, d.n - k0);
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const size_t ld = d.ld;
   const double* Bk = d.W + (size_t)k0 * ld + k0;
-  // One wave: lane r holds row r of the block; padding (rows or columns >=
-  // kb) is the identity, which no real column can pick.
-  double x[BGJ_NB];
+  // Wave w holds columns 16 w .. 16 w + 15 of row `lane`; padding (rows or
+  // columns >= kb) is the identity, which no real column can pick.
+  double x[16];
 #pragma unroll
-  for (int c = 0; c < BGJ_NB; ++c)
-    x[c] = (lane < kb && c < kb) ? Bk[(size_t)lane * ld + c] : (lane == c ? 1.0 : 0.0);
+  for (int j = 0; j < 16; ++j) {
+    const int c = 16 * wid + j;
+    x[j] = (lane < kb && c < kb) ? as_global(Bk)[(size_t)lane * ld + c] : (lane == c ? 1.0 : 0.0);
+  }
+  // Rows are scaled lazily: the true row is scale * x.  A pivot row keeps
+  // its values and takes scale = 1 / pivot; only unchosen rows (scale 1)
+  // are ever broadcast as pivot rows, so every update is one FMA per entry.
+  double scale = 1.0;
   bool chosen = false, bad = false;
   double minp = INFINITY;
+  for (int g = 0; g < (kb + 15) / 16; ++g) {
 #pragma unroll
-  for (int c = 0; c < BGJ_NB; ++c) {
-    if (c >= kb) continue;  // wave-uniform
-    const unsigned key = chosen ? 0u : pivot_key(x[c], lane);
-    const unsigned g = wave_max_u32(key);
-    const int pr = 4095 - (int)(g & 4095u);
-    if (lane == 0) sP[c] = g != 0 ? pr : 0;
-    chosen |= lane == pr;
-    // The pivot row reaches every lane through readlane (pr is uniform).
-    const double piv = bcast_lane(x[c], pr);
-    const bool ok = g != 0 && piv != 0.0 && piv == piv && fabs(piv) != INFINITY;
-    bad |= !ok;
-    minp = fmin(minp, fabs(piv));
-    const double inv = ok ? 1.0 / piv : 0.0;
-    // In-place Gauss-Jordan step: the pivot row is scaled, every other row
-    // loses f times it, column c takes the multipliers.
-    const double f = x[c];
-    const bool me = lane == pr;
-#pragma unroll
-    for (int j = 0; j < BGJ_NB; ++j)
-      if (j != c) {
-        const double pj = bcast_lane(x[j], pr) * inv;
-        x[j] = me ? pj : fma(-f, pj, x[j]);
+    for (int cc = 0; cc < 16; ++cc) {
+      const int c = 16 * g + cc;
+      if (c >= kb) continue;  // uniform
+      const int buf = c & 1;
+      if (wid == g) {
+        const unsigned key = chosen ? 0u : pivot_key(x[cc], lane);
+        const unsigned gk = wave_max_u32(key);
+        const int pr = 4095 - (int)(gk & 4095u);
+        sF[buf][lane] = x[cc];
+        if (lane == pr) sPiv[buf] = x[cc];
+        if (lane == 0) {
+          sPr[buf] = pr;
+          sP[c] = pr;
+        }
       }
-    x[c] = me ? inv : -f * inv;
+      __syncthreads();
+      const int pr = __builtin_amdgcn_readfirstlane(sPr[buf]);
+      const double piv = uniform(sPiv[buf]);
+      const double f = sF[buf][lane];
+      const bool ok = piv != 0.0 && piv == piv && fabs(piv) != INFINITY;
+      bad |= !ok;
+      minp = fmin(minp, fabs(piv));
+      const double inv = ok ? 1.0 / piv : 0.0;
+      const bool me = lane == pr;
+      const double gm = me ? 0.0 : -f * inv;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) x[j] = fma(gm, bcast_lane(x[j], pr), x[j]);
+      if (wid == g) x[cc] = me ? 1.0 : gm;
+      if (me) {
+        scale = inv;
+        chosen = true;
+      }
+    }
   }
+#pragma unroll
+  for (int j = 0; j < 16; ++j) x[j] *= scale;
   // Pivot statistics and the fall-back test (block pivots against max|M|);
   // a zero or non-finite block pivot also falls back (the partial-pivoting
   // path then decides whether M itself is singular).
-  if (lane == 0) {
+  if (threadIdx.x == 0) {
     if (d.pstat && !bad) atomicMin(d.pstat + 1, abs_bits(minp));
     const double amax = d.pstat ? __longlong_as_double((long long)d.pstat[0]) : 0.0;
     if (bad || !(minp > fb_tol * amax)) atomicExch(status + 3, 1);
   }
-  sPi[lane] = 0;  // in range even for a failed block
-  wave_lds_sync();
-  if (lane < kb) sPi[sP[lane]] = lane;
-  wave_lds_sync();
+  if (threadIdx.x < BGJ_NB) sPi[threadIdx.x] = 0;  // in range even for a failed block
+  __syncthreads();
+  if (threadIdx.x < kb) sPi[sP[threadIdx.x]] = threadIdx.x;
+  __syncthreads();
   // In-place Gauss-Jordan with marked (unmoved) pivot rows leaves X with
   // B^-1[Pi[r]][P[c]] = X[r][c] (P: pivot row of each column, Pi its inverse).
   double* Bi = binv + (size_t)blockIdx.x * BGJ_NB * BGJ_NB;
   if (lane < kb) {
     const int a = sPi[lane];
 #pragma unroll
-    for (int c = 0; c < BGJ_NB; ++c)
-      if (c < kb) Bi[(size_t)a * BGJ_NB + sP[c]] = x[c];
+    for (int j = 0; j < 16; ++j) {
+      const int c = 16 * wid + j;
+      if (c < kb) Bi[(size_t)a * BGJ_NB + sP[c]] = x[j];
+    }
   }
 }
 
@@ -1150,8 +1192,8 @@ void batched_solve_bgj(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_
       fu += 2.0 * (d.n - kb) * rest * kb;
     }
     {
-      ProfScope ps(PROF_LU_PANEL, stream, fd, 0);
-      hipLaunchKernelGGL(k_bgj_diag, dim3(np), dim3(64), 0, stream, d_desc, k0, binv,
+      ProfScope ps(PROF_BGJ_DIAG, stream, fd, 0);
+      hipLaunchKernelGGL(k_bgj_diag, dim3(np), dim3(256), 0, stream, d_desc, k0, binv,
                          g_bgj_fb_tol, d_status);
     }
     // Columns past the block: the rest of M and the touched part of the
@@ -1160,12 +1202,12 @@ void batched_solve_bgj(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_
     const int rest = std::min(nmax, wmax - k0 - std::min(BGJ_NB, nmax - k0));
     if (rest <= 0) continue;
     {
-      ProfScope ps(PROF_SWAP_TRSM, stream, fr, 0);
+      ProfScope ps(PROF_BGJ_ROWS, stream, fr, 0);
       hipLaunchKernelGGL(k_bgj_rows, dim3((rest + 63) / 64, 1, np), dim3(256), 0, stream, d_desc,
                          k0, (const double*)binv);
     }
     {
-      ProfScope ps(PROF_LU_UPDATE, stream, fu, 0);
+      ProfScope ps(PROF_BGJ_UPDATE, stream, fu, 0);
       launch_update(upd, d_desc, np, k0, BGJ_NB, nmax, 0, rest, stream);
     }
   }
@@ -1228,6 +1270,24 @@ void grouped_gemm_v(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc,
       hipLaunchKernelGGL((k_gemm<BM, BN, BK, WM, WN, false, D>), grid, dim3(64 * WM * WN), 0, \
                          stream, d_desc);                                                     \
     return;                                                                                   \
+  }
+  if (variant == 7) {
+    // Pairs of doubles when every operand row starts 16-byte aligned and no
+    // pair straddles the K or N edge.
+    bool v2 = true;
+    for (auto& g : h_desc)
+      v2 = v2 && g.lda % 2 == 0 && g.ldb % 2 == 0 && g.K % 2 == 0 && g.N % 2 == 0 &&
+           ((uintptr_t)g.A & 15) == 0 && ((uintptr_t)g.B & 15) == 0;
+    const dim3 grid((nmax + 127) / 128, (mmax + 127) / 128, np);
+    if (pass && v2)
+      hipLaunchKernelGGL((k_gemm128<2, true>), grid, dim3(256), 0, stream, d_desc);
+    else if (pass)
+      hipLaunchKernelGGL((k_gemm128<1, true>), grid, dim3(256), 0, stream, d_desc);
+    else if (v2)
+      hipLaunchKernelGGL((k_gemm128<2, false>), grid, dim3(256), 0, stream, d_desc);
+    else
+      hipLaunchKernelGGL((k_gemm128<1, false>), grid, dim3(256), 0, stream, d_desc);
+    return;
   }
   switch (variant) {
     case 1: HPS_GEMM(32, 32, 16, 1, 1, 1)

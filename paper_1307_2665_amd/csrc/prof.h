@@ -27,6 +27,9 @@ enum ProfClass {
   PROF_BODY_FLUX = 16,
   PROF_LEAF_GEMM = 17,   // leaf T = P0 - P1 Z products (section 3.2, step 4)
   PROF_MERGE_S = 18,     // S = M^-1 B products of the merges (eq:U_parent)
+  PROF_BGJ_DIAG = 19,    // blocked Gauss-Jordan: diagonal-block inverses
+  PROF_BGJ_ROWS = 20,    // blocked Gauss-Jordan: block rows times the inverse
+  PROF_BGJ_UPDATE = 21,  // blocked Gauss-Jordan: updates of the other rows
   PROF_NCLASS = 24
 };
 

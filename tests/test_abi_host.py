@@ -171,7 +171,7 @@ def test_tuning_cache_round_trip(tmp_path):
     with pytest.raises(H.HpsError) as e:
         H.tune_load(bad)
     assert e.value.status == H.HPS_EINVAL
-    for knob, v in (("gemm_variant", 7), ("gj_variant", 3), ("leaf_variant", 5), ("nope", 0)):
+    for knob, v in (("gemm_variant", 8), ("gj_variant", 3), ("leaf_variant", 5), ("nope", 0)):
         with pytest.raises(H.HpsError) as e:
             H.tune_set(knob, v)
         assert e.value.status == H.HPS_EINVAL

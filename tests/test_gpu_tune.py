@@ -33,12 +33,19 @@ def _t(x, dev):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
 
 
-@pytest.mark.parametrize("variant", range(7))
+# Shapes: odd leading dimensions (single-double loads of the 128 x 128 tile),
+# even ones with ragged K and N (pair loads with a single tail), and grids of
+# 8 x 8 and 9 x 16 tiles (the XCD-grouped tile order, with a partial group).
+GEMM_SHAPES = [(70, 130, 37, 3), (257, 65, 64, 1), (5, 3, 200, 2), (130, 300, 33, 1),
+               (300, 260, 96, 2), (140, 258, 50, 1), (1024, 1024, 48, 1), (1152, 2048, 32, 1)]
+
+
+@pytest.mark.parametrize("variant", range(8))
 def test_gemm_variants(H, gpu, variant):
     say(f"gemm variant {variant}")
     H.tune_set("gemm_variant", variant)
     try:
-        for Mr, Nc, K, nb in [(70, 130, 37, 3), (257, 65, 64, 1), (5, 3, 200, 2), (130, 300, 33, 1)]:
+        for Mr, Nc, K, nb in GEMM_SHAPES:
             rng = np.random.default_rng(Mr + 3 * Nc + K)
             A, B = rng.standard_normal((nb, Mr, K)), rng.standard_normal((nb, K, Nc))
             C0 = rng.standard_normal((nb, Mr, Nc))
@@ -117,6 +124,27 @@ def test_autotune_then_build_matches_oracle(H, gpu, tmp_path):
     say(f"tuned build vs oracle: u {e:.2e}")
     assert e < 1e-10
     H.tune_reset()
+
+
+@pytest.mark.parametrize("variant", [0, 7])
+@pytest.mark.parametrize("nleaf,p,q", [((8, 8), 12, 10), ((5, 3), 10, 7)])
+def test_build_with_gemm_variant_matches_oracle(H, gpu, variant, nleaf, p, q):
+    """Every merge's Schur product T = diag(T11a, T22b) + Q S on one forced
+    tile; q = 7 on 5 x 3 leaves gives odd interface lengths (single-double
+    operand loads)."""
+    pr = hi.convdiff(seed_g=31, seed_h=32, nleaf=nleaf, p=p, q=q)
+    C, f = library_inputs(pr)
+    H.tune_set("gemm_variant", variant)
+    try:
+        op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q)
+        u = op.solve(_t(f, gpu)).cpu().numpy()
+    finally:
+        H.tune_set("gemm_variant", -1)
+    op_o, C_o, f_o, grid = oracle_problem(pr)
+    u_o = hps.solve(op_o, f_o)
+    e = max(rel_err(u[k], u_o[k]) for k in range(u_o.shape[0]))
+    say(f"gemm variant {variant} {nleaf} p={p} q={q}: u {e:.2e}")
+    assert e < 1e-10
 
 
 def test_graph_solve_replays_match_eager(H, gpu):
