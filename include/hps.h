@@ -38,7 +38,8 @@
  * Memory: pointers are host pointers unless the options say device_ptrs = 1,
  * in which case they are device pointers on the current HIP device.  The
  * library never keeps a caller pointer after a call returns.  An hps_op owns
- * all of its device memory until hps_destroy.
+ * all of its device memory until hps_destroy; see hps_destroy for the
+ * buffers it then keeps for the next build of the same shape.
  *
  * Streams: all device work is enqueued on the given hipStream_t (NULL means
  * the default stream) and every call synchronizes that stream before it
@@ -393,6 +394,9 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
    "split_min_chunk": in those passes, depths with too few merges to fill
      the GPU split each GEMM contraction into chunks of at least this length
      (-1: the default, 256; else at least 16), summed in a fixed order;
+   "parked_ops": how many destroyed operators keep their device buffers and
+     descriptors for the next build of the same shape (0 frees at once; -1:
+     the default, 2);
    "post_rows": Chebyshev-grid rows per lane in hps_postprocess (1, 2 or 4;
      -1: the default, 4 from 16 right-hand sides on, else 2);
    "gj_lookahead": 1 lets the merge solver update the next panel's columns
@@ -463,13 +467,21 @@ hps_status hps_prof_query(int cls, double* ms, long long* launches, double* flop
    memory from a per-device cache that keeps released blocks for reuse, so
    repeated builds of one shape do not call hipMalloc/hipFree; the
    stream-ordered scratch of solves is likewise kept in the device's default
-   memory pool.  hps_mem_trim frees every cached block (blocks in use are
-   untouched) and the pool's unused memory on the current device, and reports
-   the bytes freed from the cache; hps_mem_stats reports the bytes cached and
-   in use.  Either pointer may be NULL. */
+   memory pool.  hps_mem_trim frees the parked operators (see hps_destroy),
+   every cached block (blocks in use are untouched) and the pool's unused
+   memory on the current device, and reports the bytes freed from the cache;
+   hps_mem_stats reports the bytes cached and in use (a parked operator's
+   buffers count as in use).  Either pointer may be NULL. */
 hps_status hps_mem_trim(size_t* freed);
 hps_status hps_mem_stats(size_t* cached, size_t* in_use);
 
+/* Waits for the device, then releases op.  Its device buffers and level
+   descriptors are parked for the next hps_build_solution_operator or
+   hps_build_batch of the same leaf grid, box, p, q, mode, device_ptrs and
+   kept data on the same device, which then only sets the coefficients and
+   per-build options instead of planning and uploading descriptors (knob
+   "parked_ops" bounds how many wait, most recent first; hps_mem_trim frees
+   them).  NULL is ignored. */
 void hps_destroy(hps_op* op);
 const char* hps_last_error(void);
 const char* hps_version(void);

@@ -315,7 +315,8 @@ PROF_CLASSES = {"leaf_assemble": 0, "lu_panel": 1, "swap_trsm": 2, "lu_update": 
 
 
 def mem_trim() -> int:
-    """Frees the device blocks the library keeps cached for reuse; returns the bytes freed."""
+    """Frees the parked operators (destroyed operators kept for the next build of their
+    shape) and the device blocks the library keeps cached for reuse; returns the bytes freed."""
     f = C.c_size_t()
     check(lib.hps_mem_trim(C.byref(f)))
     return f.value
@@ -366,7 +367,10 @@ class Operator:
         self.n_judged = info.n_judged
 
     def __del__(self):
-        self.destroy()
+        try:
+            self.destroy()
+        except (AttributeError, TypeError):
+            pass  # interpreter shutdown: the library binding may already be gone
 
     def destroy(self):
         if getattr(self, "_h", None):

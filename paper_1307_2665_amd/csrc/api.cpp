@@ -86,6 +86,8 @@ extern "C" {
 
 hps_status hps_mem_trim(size_t* freed) {
   return guard([&] {
+    (void)hipDeviceSynchronize();
+    hps::parked_clear();
     const size_t f = hps::pool_trim();
     hps::trim_async_pool();
     if (freed) *freed = f;
@@ -533,6 +535,9 @@ hps_status hps_tune_set(const char* knob, int value) {
       hps::set_bf16x6_min_k(value);
     } else if (k == "post_rows") {
       hps::set_post_rows(value);
+    } else if (k == "parked_ops") {
+      HPS_REQUIRE(value >= -1 && value <= 64, "parked_ops must be in [-1, 64]");
+      hps::set_parked_limit(value < 0 ? 2 : value);
     } else if (k == "gj_variant") {
       HPS_REQUIRE(value >= -1 && value < 4 * hps::UPDATE_VARIANTS && (value < 0 || value % 4 < 3),
                   "gj_variant out of range");
@@ -763,7 +768,10 @@ void hps_surrogate_destroy(hps_surrogate* s) {
 void hps_destroy(hps_op* op) {
   if (!op) return;
   (void)hipDeviceSynchronize();
-  delete op;
+  try {
+    hps::park_operator(op);
+  } catch (...) {
+  }
 }
 
 }  // extern "C"

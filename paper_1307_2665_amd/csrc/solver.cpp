@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <list>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -80,6 +81,84 @@ void trim_async_pool() {
   hipMemPool_t pool = nullptr;
   HPS_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
   HPS_HIP(hipMemPoolTrimTo(pool, 0));
+}
+
+// Parked operators: destroyed operators whose buffers and descriptors are
+// kept for the next build of the same key (most recent first).  Never freed
+// at process exit (the HIP runtime may be gone by then).
+namespace {
+struct ParkList {
+  std::mutex mu;
+  std::list<hps_op*> ops;
+  size_t limit = 2;
+};
+ParkList& parked() {
+  static ParkList* l = new ParkList;
+  return *l;
+}
+}  // namespace
+
+void park_operator(hps_op* op) {
+  if (!op) return;
+  ParkList& L = parked();
+  std::vector<hps_op*> drop;
+  {
+    std::lock_guard<std::mutex> lk(L.mu);
+    if (L.limit == 0 || op->park_key.empty()) {
+      drop.push_back(op);
+    } else {
+      // Graphs and per-build state go; buffers and descriptors stay.
+      for (auto& kv : op->solve_graphs) (void)hipGraphExecDestroy(kv.second);
+      op->solve_graphs.clear();
+      op->solve_counts.clear();
+      op->surrogate = nullptr;
+      if (op->coeffs != op->coeffs_own) op->coeffs = nullptr;
+      L.ops.push_front(op);
+      while (L.ops.size() > L.limit) {
+        drop.push_back(L.ops.back());
+        L.ops.pop_back();
+      }
+    }
+  }
+  for (hps_op* d : drop) delete d;
+}
+
+std::unique_ptr<hps_op> unpark_operator(const std::vector<long long>& key) {
+  ParkList& L = parked();
+  std::lock_guard<std::mutex> lk(L.mu);
+  for (auto it = L.ops.begin(); it != L.ops.end(); ++it)
+    if ((*it)->park_key == key) {
+      hps_op* op = *it;
+      L.ops.erase(it);
+      return std::unique_ptr<hps_op>(op);
+    }
+  return nullptr;
+}
+
+size_t parked_clear() {
+  ParkList& L = parked();
+  std::list<hps_op*> all;
+  {
+    std::lock_guard<std::mutex> lk(L.mu);
+    all.swap(L.ops);
+  }
+  size_t n = all.size();
+  for (hps_op* op : all) delete op;
+  return n;
+}
+
+void set_parked_limit(int n) {
+  ParkList& L = parked();
+  std::vector<hps_op*> drop;
+  {
+    std::lock_guard<std::mutex> lk(L.mu);
+    L.limit = (size_t)std::max(n, 0);
+    while (L.ops.size() > L.limit) {
+      drop.push_back(L.ops.back());
+      L.ops.pop_back();
+    }
+  }
+  for (hps_op* d : drop) delete d;
 }
 
 static void init_runtime() {
@@ -236,55 +315,78 @@ std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4],
               "degenerate box");
   init_runtime();
   hipStream_t s = o.stream;
+  HPS_REQUIRE(!o.keep_leaf_solution || o.mode != HPS_SURROGATE,
+              "keep_leaf_solution needs the FP64 leaf build (not surrogate mode)");
+  // Options as the operator keeps them: body loads and the mixed forms need
+  // the factors (upward pass, refinement) and the leaf operators.
+  BuildOptions eo = o;
+  if (o.keep_body) eo.keep_factors = true;
+  if (o.mode == HPS_MIXED_SPLIT32 || o.mode == HPS_MIXED_BF16X6) {
+    eo.keep_factors = true;
+    eo.keep_leaf = true;
+  }
+  const int nx = nleaf[0], ny = nleaf[1], m = 4 * q;
+  const size_t nl = (size_t)nx * ny;
+  const size_t ncoef = nl * 6 * p * p;
+  const bool keep = eo.keep_factors;
+  // Coefficients: the caller's device buffer when only the build reads them;
+  // otherwise an owned copy (body-load solves assemble the leaf systems again
+  // after the build, when the caller's buffer may be gone).
+  auto set_coeffs = [&](hps_op* op) {
+    if (o.device_ptrs && !keep) {
+      op->coeffs = coeffs;
+      return;
+    }
+    if (!o.device_ptrs)
+      for (size_t i = 0; i < ncoef; ++i)
+        HPS_REQUIRE(std::isfinite(coeffs[i]), "non-finite coefficient");
+    if (!op->coeffs_own) op->coeffs_own = op->mem.alloc<double>(ncoef);
+    HPS_HIP(hipMemcpyAsync(op->coeffs_own, coeffs, ncoef * sizeof(double),
+                           o.device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    op->coeffs = op->coeffs_own;
+  };
+  // An operator of the same shape and kept buffers, destroyed earlier, comes
+  // back with its device buffers and descriptors: only the per-build state
+  // is set again (coefficient sweeps skip the planning host work).
+  int dev = 0;
+  HPS_HIP(hipGetDevice(&dev));
+  std::vector<long long> key{dev, nx, ny, p, q, bits(box[0]), bits(box[1]), bits(box[2]),
+                             bits(box[3]), o.mode, o.device_ptrs, keep, eo.keep_leaf,
+                             o.keep_leaf_solution, o.keep_body, o.root_dtn};
+  if (std::unique_ptr<hps_op> op = unpark_operator(key)) {
+    op->opt = eo;
+    op->surrogate = o.surrogate;
+    op->judge_samples = o.judge_samples;
+    op->judge_tol = o.judge_tol;
+    op->judge_worst = 0.0;
+    op->n_judged = 0;
+    op->n_fallback = 0;
+    op->level_cond.clear();
+    set_coeffs(op.get());
+    return op;
+  }
   auto op = std::make_unique<hps_op>();
-  op->nx = nleaf[0];
-  op->ny = nleaf[1];
+  op->park_key = key;
+  op->nx = nx;
+  op->ny = ny;
   op->p = p;
   op->q = q;
   op->mode = o.mode;
   std::memcpy(op->box, box, sizeof(op->box));
-  op->opt = o;
+  op->opt = eo;
   op->surrogate = o.surrogate;
   op->judge_samples = o.judge_samples;
   op->judge_tol = o.judge_tol;
-  if (o.keep_body) op->opt.keep_factors = true;
-  if (o.mode == HPS_MIXED_SPLIT32 || o.mode == HPS_MIXED_BF16X6) {
-    op->opt.keep_factors = true;
-    op->opt.keep_leaf = true;
-  }
-  const int nx = op->nx, ny = op->ny, m = 4 * q;
-  const size_t nl = (size_t)nx * ny;
   const double hx = (box[1] - box[0]) / nx, hy = (box[3] - box[2]) / ny;
-  const bool keep = op->opt.keep_factors;
   op->plan = tree_plan(nx, ny, p, q, hx, hy, keep, s);
   const TreePlan& P = *op->plan;
   const Tree& t = P.tree;
   op->n_bdry = P.n_bdry;
   op->gamma = P.gamma;
   op->h_units = P.h_units;
-
-  const size_t ncoef = nl * 6 * p * p;
-  if (o.device_ptrs && !op->opt.keep_factors) {
-    op->coeffs = coeffs;  // read by the build only
-  } else if (o.device_ptrs) {
-    // Body-load solves assemble the leaf systems again after the build, so
-    // the operator keeps its own copy (the caller's buffer may be gone).
-    double* d = op->mem.alloc<double>(ncoef);
-    HPS_HIP(hipMemcpyAsync(d, coeffs, ncoef * sizeof(double), hipMemcpyDeviceToDevice, s));
-    op->coeffs = d;
-  } else {
-    for (size_t i = 0; i < ncoef; ++i)
-      HPS_REQUIRE(std::isfinite(coeffs[i]), "non-finite coefficient");
-    double* d = op->mem.alloc<double>(ncoef);
-    HPS_HIP(hipMemcpyAsync(d, coeffs, ncoef * sizeof(double), hipMemcpyHostToDevice, s));
-    op->coeffs = d;
-  }
+  set_coeffs(op.get());
   op->leafT = op->mem.alloc<double>(nl * m * m);
-  if (o.keep_leaf_solution) {
-    HPS_REQUIRE(o.mode != HPS_SURROGATE,
-                "keep_leaf_solution needs the FP64 leaf build (not surrogate mode)");
-    op->leafZ = op->mem.alloc<double>(nl * (size_t)(p - 2) * (p - 2) * m);
-  }
+  if (o.keep_leaf_solution) op->leafZ = op->mem.alloc<double>(nl * (size_t)(p - 2) * (p - 2) * m);
   if (o.keep_body) op->leafK = op->mem.alloc<double>(nl * (size_t)(p - 2) * (p - 2) * m);
 
   // Per merge: the system W = [M | I] (whose elimination leaves M^-1), the
@@ -737,43 +839,49 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
                    : ops[0]->mode == HPS_MIXED_SPLIT32 ? GEMM_SPLIT32
                    : ops[0]->mode == HPS_MIXED_BF16X6 ? GEMM_BF16X6 : GEMM_F64;
   for (int d = maxd; d >= 0; --d) {
-    std::vector<MergeDesc> hm;
-    std::vector<SolveDesc> hs;
-    std::vector<GemmDesc> hg, hsg;
     size_t gmax = 0;
-    const LevelPlan* only = nullptr;
-    int contributors = 0;
+    std::vector<const LevelPlan*> parts;
     for (hps_op* op : ops) {
       if (d >= (int)op->levels.size() || op->levels[d].h.empty()) continue;
       const LevelPlan& L = op->levels[d];
-      hm.insert(hm.end(), L.h.begin(), L.h.end());
-      hs.insert(hs.end(), L.hs.begin(), L.hs.end());
-      hg.insert(hg.end(), L.hg.begin(), L.hg.end());
-      hsg.insert(hsg.end(), L.hsg.begin(), L.hsg.end());
       gmax = std::max(gmax, L.gather_max);
-      only = &L;
-      ++contributors;
+      parts.push_back(&L);
     }
-    if (hm.empty()) continue;
+    if (parts.empty()) continue;
+    // One operator at this depth: its own host and device descriptors.  Several:
+    // the concatenation, uploaded for this level.
+    std::vector<MergeDesc> cm;
+    std::vector<SolveDesc> cs;
+    std::vector<GemmDesc> cg, csg;
     const MergeDesc* dm;
     const SolveDesc* dsd;
     const GemmDesc *dgd, *dsg;
-    if (contributors == 1) {
-      dm = only->d;
-      dsd = only->ds;
-      dgd = only->dg;
-      dsg = only->dsg;
+    if (parts.size() == 1) {
+      dm = parts[0]->d;
+      dsd = parts[0]->ds;
+      dgd = parts[0]->dg;
+      dsg = parts[0]->dsg;
     } else {
-      MergeDesc* a = tmp.upload(hm, s);
-      SolveDesc* b = tmp.upload(hs, s);
-      GemmDesc* c = tmp.upload(hg, s);
-      GemmDesc* e = tmp.upload(hsg, s);
+      for (const LevelPlan* L : parts) {
+        cm.insert(cm.end(), L->h.begin(), L->h.end());
+        cs.insert(cs.end(), L->hs.begin(), L->hs.end());
+        cg.insert(cg.end(), L->hg.begin(), L->hg.end());
+        csg.insert(csg.end(), L->hsg.begin(), L->hsg.end());
+      }
+      MergeDesc* a = tmp.upload(cm, s);
+      SolveDesc* b = tmp.upload(cs, s);
+      GemmDesc* c = tmp.upload(cg, s);
+      GemmDesc* e = tmp.upload(csg, s);
       HPS_HIP(hipStreamSynchronize(s));
       dm = a;
       dsd = b;
       dgd = c;
       dsg = e;
     }
+    const std::vector<MergeDesc>& hm = parts.size() == 1 ? parts[0]->h : cm;
+    const std::vector<SolveDesc>& hs = parts.size() == 1 ? parts[0]->hs : cs;
+    const std::vector<GemmDesc>& hg = parts.size() == 1 ? parts[0]->hg : cg;
+    const std::vector<GemmDesc>& hsg = parts.size() == 1 ? parts[0]->hsg : csg;
     merge_gather(dm, (int)hm.size(), gmax, s);
     int nmax_level = 0;
     for (const SolveDesc& sd : hs) nmax_level = std::max(nmax_level, sd.n);

@@ -121,6 +121,8 @@ struct hps_op {
   hps::BuildOptions opt;
   const double* coeffs = nullptr;   // device coefficients: an owned copy (host input or
                                     // keep_factors), else the caller's, read by the build only
+  double* coeffs_own = nullptr;     // the owned copy's buffer, once allocated
+  std::vector<long long> park_key;  // shape and kept buffers (parked-operator reuse)
   double* leafT = nullptr;          // [nleaf][4q][4q]
   double* leafZ = nullptr;          // [nleaf][4q][(p-2)^2]: Z^T, Z = A_ii^-1 A_ie L1, or null
   double* leafK = nullptr;          // [nleaf][(p-2)^2][4q]: K^T, K = P1 A_ii^-1, or null
@@ -165,7 +167,17 @@ struct hps_op {
 
 namespace hps {
 
-// Validates, plans and allocates one operator (no kernel launches except uploads).
+// Destroyed operators are parked: their device buffers and descriptors wait
+// for the next build of the same shape, options and device (at most
+// set_parked_limit of them, most recent first; parked_clear frees them all
+// and returns how many there were).
+void park_operator(hps_op* op);
+std::unique_ptr<hps_op> unpark_operator(const std::vector<long long>& key);
+size_t parked_clear();
+void set_parked_limit(int n);
+
+// Validates, plans and allocates one operator (no kernel launches except
+// uploads), or takes back a parked one of the same key.
 std::unique_ptr<hps_op> plan_operator(const double* coeffs, const double box[4], const int nleaf[2],
                                       int p, int q, const BuildOptions& o);
 // Runs the build of a batch of planned operators: leaf stage grouped by leaf

@@ -424,3 +424,46 @@ def test_blocked_gauss_jordan_fallback(H, gpu):
     assert fell == len([d for d in range(20) if any(b.level == d and not b.is_leaf
                                                      for b in op_o.boxes)])
     _compare_operator(H, op, op_o)
+
+
+# ---------------------------------------------------------------------------
+# Parked operators: a destroyed operator's buffers and descriptors serve the
+# next build of the same shape.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kw,host", [({}, False), ({"keep_factors": True}, False), ({}, True)])
+def test_parked_operator_rebuild_matches_fresh(H, gpu, kw, host):
+    """A build that takes back a parked operator (other coefficients before) gives bit for bit
+    what a fresh build gives, and matches the oracle; hps_mem_trim frees the parked ones."""
+    import torch
+    first = hi.convdiff(seed_g=41, seed_h=42, nleaf=(8, 8), p=12, q=10)
+    pr = hi.convdiff(seed_g=43, seed_h=44, nleaf=(8, 8), p=12, q=10)
+    C1, _ = library_inputs(first)
+    C, f = library_inputs(pr)
+    arg = (lambda c: np.ascontiguousarray(c)) if host else (lambda c: _t(c, gpu))
+    H.tune_set("parked_ops", 0)
+    try:
+        op = H.build_solution_operator(arg(C), pr.box, pr.nleaf, pr.p, pr.q, **kw)
+        u_fresh = op.solve(_t(f, gpu)).cpu().numpy()
+        op.destroy()
+        H.tune_set("parked_ops", 2)
+        op1 = H.build_solution_operator(arg(C1), first.box, first.nleaf, first.p, first.q, **kw)
+        op1.solve(_t(f, gpu))
+        op1.destroy()
+        torch.cuda.synchronize()
+        in_use_parked = H.mem_stats()["in_use"]
+        op = H.build_solution_operator(arg(C), pr.box, pr.nleaf, pr.p, pr.q, **kw)
+        u = op.solve(_t(f, gpu)).cpu().numpy()
+        if kw.get("keep_factors"):
+            ur = op.solve(_t(f, gpu), refine=True, tol=1e-12, max_iter=3).cpu().numpy()
+            assert rel_err(ur, u_fresh) < 1e-12
+        op.destroy()
+    finally:
+        H.tune_set("parked_ops", -1)
+    assert np.array_equal(u, u_fresh)
+    op_o, Co, fo, grid = oracle_problem(pr)
+    e = rel_err(u, hps.solve(op_o, fo))
+    say(f"  parked rebuild {kw} host={host}: u rel err {e:.2e}")
+    assert e < TOL
+    H.mem_trim()
+    assert H.mem_stats()["in_use"] < in_use_parked
