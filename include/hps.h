@@ -415,7 +415,11 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
    "bgj_fallback_tol_exp": e; a level whose blocked elimination meets a
      block pivot of at most 10^-e max|M| (or a zero or non-finite one) is
      gathered again and eliminated with partial pivoting (-1: the default,
-     e = 6; 0 makes every level fall back).
+     e = 6; 0 makes every level fall back);
+   "bgj_lookahead": 1 (default, also -1) updates the next diagonal block's
+     columns first and the other columns on a second stream (default
+     priority) while the next diagonal block is inverted; 0 runs each step's
+     update in one launch on the caller's stream.
    Unknown knobs or values give HPS_EINVAL. */
 hps_status hps_tune_set(const char* knob, int value);
 

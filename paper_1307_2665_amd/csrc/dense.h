@@ -61,6 +61,9 @@ void dense_init();
 void batched_solve_bgj(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc, int* d_status,
                        double* binv, hipStream_t stream);
 void set_bgj(int min_rows, double fb_tol);
+// On (default): each step's update of the columns past the next diagonal
+// block runs on a side stream beside the next diagonal-block kernel.
+void set_bgj_lookahead(bool on);
 // Clears the smallest-pivot statistic of every system (before a redo).
 void pstat_reset_min(const SolveDesc* d_desc, int count, hipStream_t s);
 int bgj_min_rows();

@@ -460,11 +460,13 @@ struct MergePass {
   const double* __restrict__ Ta;
   const double* __restrict__ Tb;
   int na, nb;
-  __device__ double operator()(int r, int c) const {
-    const int pr = as_global(pmap)[r], pc = as_global(pmap)[c];
+  __device__ int row(int r) const { return as_global(pmap)[r]; }
+  __device__ int col(int c) const { return as_global(pmap)[c]; }
+  __device__ double value(int pr, int pc) const {
     if (pr >= 0) return pc >= 0 ? as_global(Ta)[(size_t)pr * na + pc] : 0.0;
     return pc < 0 ? as_global(Tb)[(size_t)(-pr - 1) * nb + (-pc - 1)] : 0.0;
   }
+  __device__ double operator()(int r, int c) const { return value(row(r), col(c)); }
 };
 
 __device__ inline MergePass merge_pass(const GemmDesc& g) {
@@ -1161,6 +1163,8 @@ void pstat_reset_min(const SolveDesc* d_desc, int count, hipStream_t s) {
 
 static double g_bgj_fb_tol = 1e-6;
 static int g_bgj_min_rows = 256;
+static bool g_bgj_lookahead = true;
+void set_bgj_lookahead(bool on) { g_bgj_lookahead = on; }
 
 void set_bgj(int min_rows, double fb_tol) {
   if (min_rows >= 0) g_bgj_min_rows = min_rows;
@@ -1182,6 +1186,13 @@ void batched_solve_bgj(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_
   }
   const int np = (int)h_desc.size();
   const int upd = 0;
+  // Look-ahead: each step updates the next diagonal block's columns first,
+  // then the other columns on a side stream, so the next (latency-bound)
+  // diagonal-block kernel runs beside that update; the next block-row kernel
+  // waits for it.
+  const bool look = g_bgj_lookahead && nmax > BGJ_NB;
+  const LookAhead& la = look ? look_ahead() : LookAhead{};
+  bool pending = false;
   for (int k0 = 0; k0 < nmax; k0 += BGJ_NB) {
     double fd = 0, fr = 0, fu = 0;
     for (auto& d : h_desc) {
@@ -1201,6 +1212,10 @@ void batched_solve_bgj(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_
     // per system).
     const int rest = std::min(nmax, wmax - k0 - std::min(BGJ_NB, nmax - k0));
     if (rest <= 0) continue;
+    if (pending) {  // the previous step's side-stream update must finish first
+      HPS_HIP(hipStreamWaitEvent(stream, la.done, 0));
+      pending = false;
+    }
     {
       ProfScope ps(PROF_BGJ_ROWS, stream, fr, 0);
       hipLaunchKernelGGL(k_bgj_rows, dim3((rest + 63) / 64, 1, np), dim3(256), 0, stream, d_desc,
@@ -1208,9 +1223,19 @@ void batched_solve_bgj(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_
     }
     {
       ProfScope ps(PROF_BGJ_UPDATE, stream, fu, 0);
-      launch_update(upd, d_desc, np, k0, BGJ_NB, nmax, 0, rest, stream);
+      if (!look || rest <= BGJ_NB) {
+        launch_update(upd, d_desc, np, k0, BGJ_NB, nmax, 0, rest, stream);
+      } else {
+        launch_update(upd, d_desc, np, k0, BGJ_NB, nmax, 0, BGJ_NB, stream);
+        HPS_HIP(hipEventRecord(la.ready, stream));
+        HPS_HIP(hipStreamWaitEvent(la.side, la.ready, 0));
+        launch_update(upd, d_desc, np, k0, BGJ_NB, nmax, BGJ_NB, rest - BGJ_NB, la.side);
+        HPS_HIP(hipEventRecord(la.done, la.side));
+        pending = true;
+      }
     }
   }
+  if (pending) HPS_HIP(hipStreamWaitEvent(stream, la.done, 0));
 }
 
 void batched_solve(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc, int* d_status,

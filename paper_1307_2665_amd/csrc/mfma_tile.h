@@ -30,10 +30,15 @@ struct RowsIndexed {
   __device__ int operator()(int r) const { return as_global(idx)[r]; }
 };
 
-// C0 given element by element (active = true), replacing C0 and acc_c.
+// C0 given element by element (active = true), replacing C0 and acc_c:
+// value(row(r), col(c)) = operator()(r, c), the row and column parts looked
+// up separately so that a tile can load them once per row and column.
 struct NoC0Elem {
   static constexpr bool active = false;
   __device__ double operator()(int, int) const { return 0.0; }
+  __device__ int row(int) const { return 0; }
+  __device__ int col(int) const { return 0; }
+  __device__ double value(int, int) const { return 0.0; }
 };
 
 // ---------------------------------------------------------------------------
@@ -215,6 +220,9 @@ __device__ inline void gemm_tile_map(const double* __restrict__ A, int lda,
       }
     }
   }
+  // Every old or pass-through value of this lane's elements first (loads
+  // only, so they are all in flight together), then the stores.
+  double c0v[T::FM][T::FN][4];
 #pragma unroll
   for (int i = 0; i < T::FM; ++i)
 #pragma unroll
@@ -223,9 +231,8 @@ __device__ inline void gemm_tile_map(const double* __restrict__ A, int lda,
       for (int r = 0; r < 4; ++r) {
         const int gr = row0 + wm * WBM + i * 16 + (lane >> 4) + 4 * r;
         const int gc = col0 + wn * WBN + j * 16 + (lane & 15);
+        double c0 = 0.0;
         if (gr < M && gc < N) {
-          double* cp = C + (size_t)crow(gr) * ldc + gc;
-          double c0 = 0.0;
           if constexpr (C0Elem::active) {
             c0 = c0elem(gr, gc);
           } else if (C0) {
@@ -234,10 +241,20 @@ __device__ inline void gemm_tile_map(const double* __restrict__ A, int lda,
           } else if constexpr (PRE_C) {
             c0 = pc[i][j][r];
           } else if (acc_c) {
-            c0 = *as_global(cp);
+            c0 = as_global(C)[(size_t)crow(gr) * ldc + gc];
           }
-          *cp = c0 + alpha * acc[i][j][r];
         }
+        c0v[i][j][r] = c0;
+      }
+#pragma unroll
+  for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < T::FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = row0 + wm * WBM + i * 16 + (lane >> 4) + 4 * r;
+        const int gc = col0 + wn * WBN + j * 16 + (lane & 15);
+        if (gr < M && gc < N) C[(size_t)crow(gr) * ldc + gc] = c0v[i][j][r] + alpha * acc[i][j][r];
       }
 }
 
@@ -398,8 +415,24 @@ __device__ inline void gemm128_tile(const double* __restrict__ A, int lda,
     }
     __syncthreads();
   }
-  // Per 16-row block: the old or pass-through values first (loads only, so
-  // row and column map lookups are shared), then the stores.
+  // A pass-through's row and column map entries of every element this lane
+  // writes first (one round of loads); then per 16-row block the old or
+  // pass-through values (loads only, all in flight together) and the stores.
+  int kr[4][4], kc[4];
+  if constexpr (C0Elem::active) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = row0 + wm * 64 + i * 16 + (lane >> 4) + 4 * r;
+        kr[i][r] = gr < M ? c0elem.row(gr) : 0;
+      }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gc = col0 + wn * 64 + j * 16 + (lane & 15);
+      kc[j] = gc < N ? c0elem.col(gc) : 0;
+    }
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     double c0v[4][4];
@@ -412,7 +445,7 @@ __device__ inline void gemm128_tile(const double* __restrict__ A, int lda,
         double c0 = 0.0;
         if (gr < M && gc < N) {
           if constexpr (C0Elem::active) {
-            c0 = c0elem(gr, gc);
+            c0 = c0elem.value(kr[i][r], kc[j]);
           } else if (C0) {
             c0 = as_global(C0)[(size_t)gr * ldc0 + gc];
           } else if (acc_c) {

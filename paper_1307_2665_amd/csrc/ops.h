@@ -44,7 +44,7 @@ void add_particular(double* uc, const double* wpart, const int* post_node, int n
                     int nleaf, int nrhs, hipStream_t s);
 // W = [M | I], B and Q of every merge (max_elems: the largest merge's element
 // count of the three), and max|M| into each merge's pivot statistics.
-void merge_gather(const MergeDesc* d_desc, int nmerge, size_t max_elems, hipStream_t s);
+void merge_gather(const MergeDesc* d_desc, const std::vector<MergeDesc>& h_desc, hipStream_t s);
 // Downward pass of one depth; io[i] gives merge i's solution array (io null:
 // every merge uses io0).  s_bytes: bytes of all S of the launch (its
 // algorithmic traffic per RHS chunk).

@@ -252,36 +252,59 @@ void add_particular(double* uc, const double* wpart, const int* post_node, int n
 // diag(T11a, T22b) is not formed: the Schur product reads it from the
 // children's DtNs as it writes T = diag(T11a, T22b) + Q S.
 // ---------------------------------------------------------------------------
+// Rows of W (m3), B (m3) and Q (me) are taken in turn by groups of LPR
+// lanes (64 / LPR rows per wave, four waves per workgroup), each group
+// walking its row in strides of LPR columns: the row's own lookups (a3, b3,
+// pmap of the row) are one load per group, writes are contiguous, and no
+// element index is divided.
+template <int LPR>
 __global__ void __launch_bounds__(256) k_merge_gather(const MergeDesc* __restrict__ descs) {
   const MergeDesc d = descs[blockIdx.y];
   const int m3 = d.m3, me = d.me, ldw = d.ldw;
-  const size_t nW = (size_t)m3 * ldw, nB = (size_t)m3 * me, nQ = (size_t)me * m3;
-  const size_t tot = nW + nB + nQ;
+  const int sub = threadIdx.x % LPR;
+  constexpr int GROUPS = 256 / LPR;
+  const int nrows = 2 * m3 + me;
+  const gptr<double> Ta = as_global(d.Ta), Tb = as_global(d.Tb);
+  const gptr<int> a3 = as_global(d.a3), b3 = as_global(d.b3), pmap = as_global(d.pmap);
   double amax = 0.0;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
-       e += (size_t)gridDim.x * blockDim.x) {
-    if (e < nW) {
-      const int i = (int)(e / ldw), j = (int)(e % ldw);
-      double v;
-      if (j < m3) {
-        v = d.Ta[(size_t)d.a3[i] * d.na + d.a3[j]] - d.Tb[(size_t)d.b3[i] * d.nb + d.b3[j]];
-        amax = fmax(amax, fabs(v));
-      } else {
-        v = (j - m3 == i) ? 1.0 : 0.0;
+  for (int row = blockIdx.x * GROUPS + (int)threadIdx.x / LPR; row < nrows;
+       row += gridDim.x * GROUPS) {
+    if (row < m3) {
+      // W row i = [T33a(i, :) - T33b(i, :) | e_i].
+      const int i = row;
+      const size_t ra = (size_t)a3[i] * d.na, rb = (size_t)b3[i] * d.nb;
+      double* w = d.W + (size_t)i * ldw;
+      for (int j = sub; j < ldw; j += LPR) {
+        double v;
+        if (j < m3) {
+          v = Ta[ra + a3[j]] - Tb[rb + b3[j]];
+          amax = fmax(amax, fabs(v));
+        } else {
+          v = (j - m3 == i) ? 1.0 : 0.0;
+        }
+        w[j] = v;
       }
-      d.W[e] = v;
-    } else if (e < nW + nB) {
-      const size_t f = e - nW;
-      const int i = (int)(f / me), j = (int)(f % me);
-      const int pm = d.pmap[j];
-      d.B[f] = (pm >= 0) ? -d.Ta[(size_t)d.a3[i] * d.na + pm]
-                         : d.Tb[(size_t)d.b3[i] * d.nb + (-pm - 1)];
+    } else if (row < 2 * m3) {
+      // B row i = [-T31a(i, :) | T32b(i, :)] in parent column order.
+      const int i = row - m3;
+      const size_t ra = (size_t)a3[i] * d.na, rb = (size_t)b3[i] * d.nb;
+      double* bp = d.B + (size_t)i * me;
+      for (int j = sub; j < me; j += LPR) {
+        const int pm = pmap[j];
+        bp[j] = pm >= 0 ? -Ta[ra + pm] : Tb[rb + (-pm - 1)];
+      }
     } else {
-      const size_t f = e - nW - nB;
-      const int r = (int)(f / m3), i = (int)(f % m3);
-      const int pm = d.pmap[r];
-      d.Q[f] = (pm >= 0) ? d.Ta[(size_t)pm * d.na + d.a3[i]]
-                         : d.Tb[(size_t)(-pm - 1) * d.nb + d.b3[i]];
+      // Q row r = T13a(r, :) or T23b(r, :) (parent row order).
+      const int r = row - 2 * m3;
+      const int pm = pmap[r];
+      double* qp = d.Q + (size_t)r * m3;
+      if (pm >= 0) {
+        const size_t ra = (size_t)pm * d.na;
+        for (int j = sub; j < m3; j += LPR) qp[j] = Ta[ra + a3[j]];
+      } else {
+        const size_t rb = (size_t)(-pm - 1) * d.nb;
+        for (int j = sub; j < m3; j += LPR) qp[j] = Tb[rb + b3[j]];
+      }
     }
   }
   if (d.pstat) {
@@ -297,10 +320,31 @@ __global__ void __launch_bounds__(256) k_merge_gather(const MergeDesc* __restric
   }
 }
 
-void merge_gather(const MergeDesc* d_desc, int nmerge, size_t max_elems, hipStream_t s) {
-  int bx = (int)std::min<size_t>((max_elems + 255) / 256, 4096);
-  ProfScope ps(PROF_MERGE_GATHER, s, 0, 16.0 * nmerge * (double)max_elems);
-  hipLaunchKernelGGL(k_merge_gather, dim3(bx, nmerge), dim3(256), 0, s, d_desc);
+void merge_gather(const MergeDesc* d_desc, const std::vector<MergeDesc>& h_desc, hipStream_t s) {
+  if (h_desc.empty()) return;
+  int m3 = 0, me = 0;
+  double bytes = 0;
+  for (const MergeDesc& d : h_desc) {
+    m3 = std::max(m3, d.m3);
+    me = std::max(me, d.me);
+    // Written: W (m3 x 2 m3), B, Q; read: two entries per M entry, one per B and Q entry.
+    bytes += 8.0 * (4.0 * d.m3 * d.m3 + 4.0 * d.m3 * d.me);
+  }
+  const int len = std::max(2 * m3, me), rows = 2 * m3 + me;
+  const int np = (int)h_desc.size();
+  ProfScope ps(PROF_MERGE_GATHER, s, 0, bytes);
+#define HPS_GATHER(LPR)                                                                  \
+  {                                                                                      \
+    const int gx = std::min((rows + 256 / LPR - 1) / (256 / LPR), 4096);                 \
+    hipLaunchKernelGGL(k_merge_gather<LPR>, dim3(gx, np), dim3(256), 0, s, d_desc);      \
+  }
+  if (len <= 16)
+    HPS_GATHER(16)
+  else if (len <= 32)
+    HPS_GATHER(32)
+  else
+    HPS_GATHER(64)
+#undef HPS_GATHER
 }
 
 // ---------------------------------------------------------------------------

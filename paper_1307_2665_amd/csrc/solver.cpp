@@ -839,13 +839,10 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
                    : ops[0]->mode == HPS_MIXED_SPLIT32 ? GEMM_SPLIT32
                    : ops[0]->mode == HPS_MIXED_BF16X6 ? GEMM_BF16X6 : GEMM_F64;
   for (int d = maxd; d >= 0; --d) {
-    size_t gmax = 0;
     std::vector<const LevelPlan*> parts;
     for (hps_op* op : ops) {
       if (d >= (int)op->levels.size() || op->levels[d].h.empty()) continue;
-      const LevelPlan& L = op->levels[d];
-      gmax = std::max(gmax, L.gather_max);
-      parts.push_back(&L);
+      parts.push_back(&op->levels[d]);
     }
     if (parts.empty()) continue;
     // One operator at this depth: its own host and device descriptors.  Several:
@@ -882,7 +879,7 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
     const std::vector<SolveDesc>& hs = parts.size() == 1 ? parts[0]->hs : cs;
     const std::vector<GemmDesc>& hg = parts.size() == 1 ? parts[0]->hg : cg;
     const std::vector<GemmDesc>& hsg = parts.size() == 1 ? parts[0]->hsg : csg;
-    merge_gather(dm, (int)hm.size(), gmax, s);
+    merge_gather(dm, hm, s);
     int nmax_level = 0;
     for (const SolveDesc& sd : hs) nmax_level = std::max(nmax_level, sd.n);
     bool solved = false;
@@ -899,7 +896,7 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
       solved = fb == 0;
       if (!solved) {
         g_bgj_fallbacks.fetch_add(1);
-        merge_gather(dm, (int)hm.size(), gmax, s);
+        merge_gather(dm, hm, s);
         pstat_reset_min(dsd, (int)hs.size(), s);
       }
     }

@@ -467,3 +467,24 @@ def test_parked_operator_rebuild_matches_fresh(H, gpu, kw, host):
     assert e < TOL
     H.mem_trim()
     assert H.mem_stats()["in_use"] < in_use_parked
+
+
+def test_blocked_gauss_jordan_lookahead_matches_serial(H, gpu):
+    """The look-ahead (next block's columns first, the rest on a second stream beside the
+    next diagonal-block kernel) gives bit for bit the one-launch-per-step result."""
+    pr = hi.helmholtz_bump(kappa=25.0, nleaf=(16, 16), p=12, q=10, nrhs=2)
+    C, f = library_inputs(pr)
+    us = []
+    H.tune_set("bgj_min_rows", 1)
+    try:
+        for look in (0, 1):
+            H.tune_set("bgj_lookahead", look)
+            op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q)
+            us.append(op.solve(_t(f, gpu)).cpu().numpy())
+            T = op.export_root_dtn()
+            us.append(T)
+            op.destroy()
+    finally:
+        H.tune_set("bgj_min_rows", -1)
+        H.tune_set("bgj_lookahead", -1)
+    assert np.array_equal(us[0], us[2]) and np.array_equal(us[1], us[3])
