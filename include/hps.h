@@ -416,6 +416,10 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
      block pivot of at most 10^-e max|M| (or a zero or non-finite one) is
      gathered again and eliminated with partial pivoting (-1: the default,
      e = 6; 0 makes every level fall back);
+   "merge_small": 1 (default, also -1) builds every merge level whose
+     interfaces have at most 20 nodes in one launch (one workgroup per merge:
+     gather, elimination of [M | I], S and T); 0 uses the level-wise kernels
+     there too;
    "bgj_lookahead": 1 (default, also -1) updates the next diagonal block's
      columns first and the other columns on a second stream (default
      priority) while the next diagonal block is inverted; 0 runs each step's
@@ -454,7 +458,7 @@ hps_status hps_tune_reset(void);
    the kept body operator, 17 leaf T = P0 - P1 Z products (section 3.2),
    18 the merges' S = M^-1 B products (eq:U_parent), 19-21 the blocked
    Gauss-Jordan steps of large merge systems (diagonal-block inverses, block
-   rows, updates of the other rows).  Bit c of mask enables class c; every
+   rows, updates of the other rows), 22 whole small merges in one launch.  Bit c of mask enables class c; every
    later launch of an enabled class records a start and stop event on its
    stream together with its algorithmic FLOPs and bytes.  Costs one event
    pair per launch while enabled. */

@@ -45,6 +45,22 @@ void add_particular(double* uc, const double* wpart, const int* post_node, int n
 // W = [M | I], B and Q of every merge (max_elems: the largest merge's element
 // count of the three), and max|M| into each merge's pivot statistics.
 void merge_gather(const MergeDesc* d_desc, const std::vector<MergeDesc>& h_desc, hipStream_t s);
+// A whole level of small merges (interfaces of at most 64 nodes) in one
+// launch: gather, elimination of [M | I], S and (unless the root's is not
+// wanted) T, all in one workgroup per merge; with keep, M^-1 and Q too.
+// merge_small_lds: the dynamic LDS bytes a merge of that shape needs.
+constexpr size_t MERGE_SMALL_MAX_LDS = 150 * 1024;
+size_t merge_small_lds(int m3, int me);
+// Levels whose interfaces have at most MERGE_SMALL_MAX_M3 nodes use
+// merge_small while it is on (knob "merge_small", default on).  Longer
+// interfaces were measured slower in one workgroup per merge than on the
+// level-wise path (256 x 256 leaves, q = 10: 3.2-3.5 ms against 1.6-1.7 ms
+// for interfaces of 40 nodes), whose kernels spread each merge over the GPU.
+constexpr int MERGE_SMALL_MAX_M3 = 20;
+void set_merge_small(bool on);
+bool merge_small_on();
+void merge_small(const MergeDesc* d_desc, const std::vector<MergeDesc>& h_desc, bool keep,
+                 bool root_T, int* status, hipStream_t s);
 // Downward pass of one depth; io[i] gives merge i's solution array (io null:
 // every merge uses io0).  s_bytes: bytes of all S of the launch (its
 // algorithmic traffic per RHS chunk).

@@ -4,8 +4,10 @@
 #include "mfma_tile.h"
 #include "ops.h"
 #include "prof.h"
+#include "wave_ops.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace hps {
 
@@ -330,21 +332,254 @@ void merge_gather(const MergeDesc* d_desc, const std::vector<MergeDesc>& h_desc,
     // Written: W (m3 x 2 m3), B, Q; read: two entries per M entry, one per B and Q entry.
     bytes += 8.0 * (4.0 * d.m3 * d.m3 + 4.0 * d.m3 * d.me);
   }
-  const int len = std::max(2 * m3, me), rows = 2 * m3 + me;
+  const int rows = 2 * m3 + me;
   const int np = (int)h_desc.size();
   ProfScope ps(PROF_MERGE_GATHER, s, 0, bytes);
-#define HPS_GATHER(LPR)                                                                  \
-  {                                                                                      \
-    const int gx = std::min((rows + 256 / LPR - 1) / (256 / LPR), 4096);                 \
-    hipLaunchKernelGGL(k_merge_gather<LPR>, dim3(gx, np), dim3(256), 0, s, d_desc);      \
+  // Lanes per row by the typical row length (rows of W are 2 m3 long, of B
+  // me, of Q m3); workgroups per merge so that a level has about 4096
+  // workgroups in all (many small merges: one workgroup walks a whole merge).
+  const int typ = (2 * m3 * m3 + 2 * m3 * me) / std::max(rows, 1);
+  const int cap = std::max(1, 4096 / np);
+#define HPS_GATHER(LPR)                                                                      \
+  {                                                                                          \
+    const int gx = std::min((rows + 256 / LPR - 1) / (256 / LPR), cap);                      \
+    hipLaunchKernelGGL(k_merge_gather<LPR>, dim3(gx, np), dim3(256), 0, s, d_desc);          \
   }
-  if (len <= 16)
+  if (typ <= 24)
     HPS_GATHER(16)
-  else if (len <= 32)
+  else if (typ <= 48)
     HPS_GATHER(32)
   else
     HPS_GATHER(64)
 #undef HPS_GATHER
+}
+
+// ---------------------------------------------------------------------------
+// Small merges in one launch (section 4 for one merge, Algorithm 1 for a
+// level): one workgroup per merge gathers M = T33a - T33b next to I in LDS,
+// eliminates [M | I] by Gauss-Jordan with partial pivoting (rows stay in
+// place, pivots are marked), forms S = M^-1 [-T31a | T32b] and
+// T = diag(T11a, T22b) + [T13a; T23b] S on FP64 MFMA, with the right-hand
+// sides and Q gathered from the children's DtNs as operand fragments.  Only
+// S and T (and, with the factors kept, M^-1 and Q) reach HBM.  The same
+// statistics as the level-wise path: max|M| and the smallest pivot, and a
+// zero or non-finite pivot in status (tag: the merge's box).
+// LDS: Wl [m3][2 m3 + 1] and Sl [m3][me + 1] doubles, m3 <= 64.  One to
+// four waves per workgroup (blockDim.x = 64 nw).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_merge_small(const MergeDesc* __restrict__ descs, int keep,
+                                                     int root_T, int* status) {
+  extern __shared__ double smem[];
+  __shared__ int sP[64], sPr;
+  __shared__ unsigned char sChosen[64];
+  __shared__ double sF[64], sRed[4];
+  const MergeDesc d = descs[blockIdx.x];
+  const int m3 = d.m3, me = d.me;
+  const int lw = 2 * m3 + 1, ls = me + 1;
+  double* Wl = smem;
+  double* Sl = smem + (size_t)m3 * lw;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int nw = blockDim.x >> 6, nthr = blockDim.x;
+  const gptr<double> Ta = as_global(d.Ta), Tb = as_global(d.Tb);
+  const gptr<int> a3 = as_global(d.a3), b3 = as_global(d.b3), pmap = as_global(d.pmap);
+  // Stores through global-address-space pointers (flat stores would also
+  // count against the LDS wait counter).
+  typedef double __attribute__((address_space(1))) * gout;
+  const gout gS = (gout)d.S, gT = (gout)d.Tp, gW = (gout)d.W, gQ = (gout)d.Q;
+  // 1. [M | I] into LDS, max|M|.
+  double amax = 0.0;
+  for (int i = wid; i < m3; i += nw) {
+    const size_t ra = (size_t)a3[i] * d.na, rb = (size_t)b3[i] * d.nb;
+    for (int j = lane; j < 2 * m3; j += 64) {
+      double v;
+      if (j < m3) {
+        v = Ta[ra + a3[j]] - Tb[rb + b3[j]];
+        amax = fmax(amax, fabs(v));
+      } else {
+        v = (j - m3 == i) ? 1.0 : 0.0;
+      }
+      Wl[i * lw + j] = v;
+    }
+  }
+  if (tid < 64) sChosen[tid] = 0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+  if (lane == 0) sRed[wid] = amax;
+  __syncthreads();
+  // 2. Gauss-Jordan on [M | I]: wave 0 picks the pivot row (lanes are rows)
+  // and publishes the column's multipliers; then each thread owns columns of
+  // W and walks their rows (no other thread touches its columns in a step).
+  bool bad = false;
+  double minp = INFINITY;
+  for (int c = 0; c < m3; ++c) {
+    if (wid == 0) {
+      const double v = lane < m3 ? Wl[lane * lw + c] : 0.0;
+      const unsigned key = (lane < m3 && !sChosen[lane]) ? pivot_key(v, lane) : 0u;
+      const unsigned g = wave_max_u32(key);
+      const int pr = g != 0 ? 4095 - (int)(g & 4095u) : 0;
+      if (lane < m3) sF[lane] = v;
+      if (lane == 0) {
+        sPr = pr;
+        sP[c] = pr;
+        sChosen[pr] = 1;
+      }
+    }
+    __syncthreads();
+    const int pr = sPr;
+    const double piv = sF[pr];
+    const bool ok = piv != 0.0 && piv == piv && fabs(piv) != INFINITY;
+    bad |= !ok;
+    minp = fmin(minp, fabs(piv));
+    const double inv = ok ? 1.0 / piv : 0.0;
+    for (int j = tid; j < 2 * m3; j += nthr) {
+      if (j == c) {
+        for (int i = 0; i < m3; ++i) Wl[i * lw + j] = i == pr ? 1.0 : 0.0;
+        continue;
+      }
+      const double pj = Wl[pr * lw + j] * inv;
+      for (int i = 0; i < m3; ++i)
+        Wl[i * lw + j] = i == pr ? pj : fma(-sF[i], pj, Wl[i * lw + j]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double m = sRed[0];
+    for (int w = 1; w < nw; ++w) m = fmax(m, sRed[w]);
+    if (d.pstat) {
+      if (m > 0.0) atomicMax(d.pstat, abs_bits(m));
+      if (!bad) atomicMin(d.pstat + 1, abs_bits(minp));
+    }
+    if (bad)
+      if (atomicCAS(status, 0, 1) == 0) status[1] = d.box;
+  }
+  // Row r of M^-1 is row sP[r] of the right block.
+  if (keep)
+    for (int r = wid; r < m3; r += nw)
+      for (int j = lane; j < m3; j += 64)
+        gW[(size_t)r * d.ldw + m3 + j] = Wl[sP[r] * lw + m3 + j];
+  // 3. S = M^-1 B, B[k][col] = -T31a or T32b gathered per fragment.
+  const int nt3 = (m3 + 15) / 16, nte = (me + 15) / 16;
+  for (int t = wid; t < nt3 * nte; t += nw) {
+    const int ti = t / nte, tj = t % nte;
+    const int row = ti * 16 + (lane & 15), col = tj * 16 + (lane & 15);
+    const int pc = col < me ? pmap[col] : 0;
+    // Every B fragment of the tile first (all gathers in flight together).
+    double bf[16];
+#pragma unroll
+    for (int s4 = 0; s4 < 16; ++s4) {
+      const int k = 4 * s4 + (lane >> 4);
+      double b = 0.0;
+      if (k < m3 && col < me)
+        b = pc >= 0 ? -Ta[(size_t)a3[k] * d.na + pc] : Tb[(size_t)b3[k] * d.nb + (-pc - 1)];
+      bf[s4] = b;
+    }
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s4 = 0; s4 < 16; ++s4) {
+      if (4 * s4 >= m3) break;
+      const int k = 4 * s4 + (lane >> 4);
+      const double a = (row < m3 && k < m3) ? Wl[sP[row] * lw + m3 + k] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf[s4], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = ti * 16 + (lane >> 4) + 4 * r;
+      if (i < m3 && col < me) {
+        Sl[i * ls + col] = acc[r];
+        gS[(size_t)i * d.lds + col] = acc[r];
+      }
+    }
+  }
+  __syncthreads();
+  if (d.box == 0 && !root_T) return;
+  // 4. T = diag(T11a, T22b) + Q S, one 16-row block of T per wave at a time:
+  // its Q fragments (gathered once) against every 16-column block of S.
+  for (int ti = wid; ti < nte; ti += nw) {
+    const int row = ti * 16 + (lane & 15);
+    const int prow = row < me ? pmap[row] : 0;
+    double qa[16];
+#pragma unroll
+    for (int s4 = 0; s4 < 16; ++s4) {
+      const int k = 4 * s4 + (lane >> 4);
+      double v = 0.0;
+      if (row < me && k < m3)
+        v = prow >= 0 ? Ta[(size_t)prow * d.na + a3[k]] : Tb[(size_t)(-prow - 1) * d.nb + b3[k]];
+      qa[s4] = v;
+      if (keep && row < me && k < m3) gQ[(size_t)row * m3 + k] = v;
+    }
+    int pr4[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = ti * 16 + (lane >> 4) + 4 * r;
+      pr4[r] = i < me ? pmap[i] : 0;
+    }
+    for (int tj = 0; tj < nte; ++tj) {
+      const int col = tj * 16 + (lane & 15);
+      // The pass-through values first, in flight during the products.
+      const int pcol = col < me ? pmap[col] : 0;
+      double pass[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = ti * 16 + (lane >> 4) + 4 * r;
+        double v = 0.0;
+        if (i < me && col < me) {
+          const int pr = pr4[r];
+          if (pr >= 0 && pcol >= 0) v = Ta[(size_t)pr * d.na + pcol];
+          else if (pr < 0 && pcol < 0) v = Tb[(size_t)(-pr - 1) * d.nb + (-pcol - 1)];
+        }
+        pass[r] = v;
+      }
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s4 = 0; s4 < 16; ++s4) {
+        if (4 * s4 >= m3) break;
+        const int k = 4 * s4 + (lane >> 4);
+        const double b = (k < m3 && col < me) ? Sl[k * ls + col] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[s4], b, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = ti * 16 + (lane >> 4) + 4 * r;
+        if (i < me && col < me) gT[(size_t)i * me + col] = pass[r] + acc[r];
+      }
+    }
+  }
+}
+
+static bool g_merge_small = true;
+void set_merge_small(bool on) { g_merge_small = on; }
+bool merge_small_on() { return g_merge_small; }
+
+size_t merge_small_lds(int m3, int me) {
+  return 8 * ((size_t)m3 * (2 * m3 + 1) + (size_t)m3 * (me + 1));
+}
+
+void merge_small(const MergeDesc* d_desc, const std::vector<MergeDesc>& h_desc, bool keep,
+                 bool root_T, int* status, hipStream_t s) {
+  if (h_desc.empty()) return;
+  int m3 = 0, me = 0;
+  double flops = 0, bytes = 0;
+  for (const MergeDesc& d : h_desc) {
+    m3 = std::max(m3, d.m3);
+    me = std::max(me, d.me);
+    flops += 2.0 * d.m3 * d.m3 * d.m3 + 2.0 * d.m3 * d.m3 * d.me + 2.0 * d.me * d.me * d.m3;
+    bytes += 8.0 * (2.0 * d.m3 * d.m3 + 2.0 * d.m3 * d.me + 1.5 * d.me * d.me + d.m3 * d.me);
+  }
+  HPS_REQUIRE(m3 <= 64, "merge_small: interface longer than 64 nodes");
+  const size_t lds = merge_small_lds(m3, me);
+  HPS_REQUIRE(lds <= MERGE_SMALL_MAX_LDS, "merge_small: merge too large for LDS");
+  static std::once_flag once;
+  std::call_once(once, [] {
+    HPS_HIP(hipFuncSetAttribute((const void*)k_merge_small,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)MERGE_SMALL_MAX_LDS));
+  });
+  ProfScope ps(PROF_MERGE_SMALL, s, flops, bytes);
+  // One wave per merge for interfaces of at most 16 nodes (more merges in
+  // flight per CU), four waves for longer ones.
+  const int threads = m3 <= 16 ? 64 : 256;
+  hipLaunchKernelGGL(k_merge_small, dim3((unsigned)h_desc.size()), dim3(threads), lds, s, d_desc,
+                     keep ? 1 : 0, root_T ? 1 : 0, status);
 }
 
 // ---------------------------------------------------------------------------

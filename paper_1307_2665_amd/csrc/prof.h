@@ -30,6 +30,7 @@ enum ProfClass {
   PROF_BGJ_DIAG = 19,    // blocked Gauss-Jordan: diagonal-block inverses
   PROF_BGJ_ROWS = 20,    // blocked Gauss-Jordan: block rows times the inverse
   PROF_BGJ_UPDATE = 21,  // blocked Gauss-Jordan: updates of the other rows
+  PROF_MERGE_SMALL = 22, // whole small merges in one launch
   PROF_NCLASS = 24
 };
 

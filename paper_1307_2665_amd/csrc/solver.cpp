@@ -879,6 +879,24 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
     const std::vector<SolveDesc>& hs = parts.size() == 1 ? parts[0]->hs : cs;
     const std::vector<GemmDesc>& hg = parts.size() == 1 ? parts[0]->hg : cg;
     const std::vector<GemmDesc>& hsg = parts.size() == 1 ? parts[0]->hsg : csg;
+    int kmax = 0, m3max = 0, memax = 0;
+    for (const MergeDesc& md : hm) {
+      m3max = std::max(m3max, md.m3);
+      memax = std::max(memax, md.me);
+    }
+    for (const GemmDesc& g : hg) kmax = std::max(kmax, g.K);
+    const int schur_prec = prec == GEMM_BF16X6 && kmax < bf16x6_min_k() ? GEMM_F64 : prec;
+    if (merge_small_on() && schur_prec == GEMM_F64 && m3max <= MERGE_SMALL_MAX_M3 &&
+        merge_small_lds(m3max, memax) <= MERGE_SMALL_MAX_LDS) {
+      // Small merges: the whole level in one launch.
+      bool keep = false, root_T = false;
+      for (hps_op* op : ops) {
+        keep = keep || op->opt.keep_factors;
+        root_T = root_T || op->opt.root_dtn;
+      }
+      merge_small(dm, hm, keep, root_T, dstatus, s);
+      continue;
+    }
     merge_gather(dm, hm, s);
     int nmax_level = 0;
     for (const SolveDesc& sd : hs) nmax_level = std::max(nmax_level, sd.n);
@@ -902,9 +920,7 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
     }
     if (!solved) batched_solve(dsd, hs, dstatus, s, panel);
     grouped_gemm(dsg, hsg, s, GEMM_F64, PROF_MERGE_S);
-    int kmax = 0;
-    for (const GemmDesc& g : hg) kmax = std::max(kmax, g.K);
-    grouped_gemm(dgd, hg, s, prec == GEMM_BF16X6 && kmax < bf16x6_min_k() ? GEMM_F64 : prec);
+    grouped_gemm(dgd, hg, s, schur_prec);
   }
   int st[4];
   HPS_HIP(hipMemcpyAsync(st, dstatus, sizeof(st), hipMemcpyDeviceToHost, s));

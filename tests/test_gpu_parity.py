@@ -393,10 +393,12 @@ def test_blocked_gauss_jordan_merges_match_oracle(H, gpu, maker, nleaf):
     C, f = library_inputs(pr)
     before = H.bgj_fallbacks()
     H.tune_set("bgj_min_rows", 1)
+    H.tune_set("merge_small", 0)
     try:
         op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q)
     finally:
         H.tune_set("bgj_min_rows", -1)
+        H.tune_set("merge_small", -1)
     assert H.bgj_fallbacks() == before
     _compare_operator(H, op, op_o)
     u = op.solve(_t(f, gpu)).cpu().numpy()
@@ -414,11 +416,13 @@ def test_blocked_gauss_jordan_fallback(H, gpu):
     before = H.bgj_fallbacks()
     H.tune_set("bgj_min_rows", 1)
     H.tune_set("bgj_fallback_tol_exp", 0)
+    H.tune_set("merge_small", 0)
     try:
         op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q)
     finally:
         H.tune_set("bgj_min_rows", -1)
         H.tune_set("bgj_fallback_tol_exp", -1)
+        H.tune_set("merge_small", -1)
     fell = H.bgj_fallbacks() - before
     say(f"  fallbacks: {fell}")
     assert fell == len([d for d in range(20) if any(b.level == d and not b.is_leaf
@@ -476,6 +480,7 @@ def test_blocked_gauss_jordan_lookahead_matches_serial(H, gpu):
     C, f = library_inputs(pr)
     us = []
     H.tune_set("bgj_min_rows", 1)
+    H.tune_set("merge_small", 0)
     try:
         for look in (0, 1):
             H.tune_set("bgj_lookahead", look)
@@ -487,4 +492,51 @@ def test_blocked_gauss_jordan_lookahead_matches_serial(H, gpu):
     finally:
         H.tune_set("bgj_min_rows", -1)
         H.tune_set("bgj_lookahead", -1)
+        H.tune_set("merge_small", -1)
     assert np.array_equal(us[0], us[2]) and np.array_equal(us[1], us[3])
+
+
+# ---------------------------------------------------------------------------
+# Small merges in one launch per level (interfaces of at most 64 nodes).
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("maker", [
+    lambda: hi.convdiff(nleaf=(16, 16), p=12, q=10),
+    lambda: hi.helmholtz_bump(kappa=25.0, nleaf=(8, 16), p=16, q=14, nrhs=2),
+    lambda: hi.manufactured_variable(nleaf=(7, 5), p=10, q=7),
+])
+def test_small_merges_match_oracle_and_level_path(H, gpu, maker):
+    """The one-launch small-merge path against the oracle (every merge's S, the root DtN, u) and
+    against the level-wise path (gather, elimination, two GEMMs); uneven trees and odd q."""
+    pr = maker()
+    op_o, Co, fo, grid = oracle_problem(pr)
+    C, f = library_inputs(pr)
+    us = []
+    try:
+        for on in (0, 1):
+            H.tune_set("merge_small", on)
+            op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q)
+            if on:
+                _compare_operator(H, op, op_o)
+            us.append(op.solve(_t(f, gpu)).cpu().numpy())
+            op.destroy()
+    finally:
+        H.tune_set("merge_small", -1)
+    e = rel_err(us[1], hps.solve(op_o, fo))
+    say(f"  small merges {pr.name}: u rel err {e:.2e}, against level path {rel_err(us[1], us[0]):.1e}")
+    assert e < TOL
+    assert rel_err(us[1], us[0]) < 1e-12
+
+
+def test_small_merges_keep_factors_refinement(H, gpu):
+    """With the factors kept (M^-1 and Q written by the small-merge kernel), the refined solve
+    of a mixed-precision operator matches the oracle."""
+    pr = hi.convdiff(nleaf=(16, 16), p=12, q=10)
+    op_o, Co, fo, grid = oracle_problem(pr)
+    C, f = library_inputs(pr)
+    op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q,
+                                   mode=H.HPS_MIXED_BF16X6)
+    u = op.solve(_t(f, gpu), refine=True, tol=1e-12, max_iter=10).cpu().numpy()
+    e = rel_err(u, hps.solve(op_o, fo))
+    say(f"  small merges, kept factors, refined: u rel err {e:.2e}")
+    assert e < TOL
