@@ -416,6 +416,10 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
      block pivot of at most 10^-e max|M| (or a zero or non-finite one) is
      gathered again and eliminated with partial pivoting (-1: the default,
      e = 6; 0 makes every level fall back);
+   "gemm_queue": 1 (default, also -1) runs the FP64 products of a batch's
+     merges at one depth (several problems) as one persistent launch of the
+     128 x 128 tile over a tile queue, largest problems first; 0 launches the
+     tuned tile over the largest problem's grid;
    "merge_small": 1 (default, also -1) builds every merge level whose
      interfaces have at most 20 nodes in one launch (one workgroup per merge:
      gather, elimination of [M | I], S and T); 0 uses the level-wise kernels

@@ -535,6 +535,9 @@ hps_status hps_tune_set(const char* knob, int value) {
       hps::set_bf16x6_min_k(value);
     } else if (k == "post_rows") {
       hps::set_post_rows(value);
+    } else if (k == "gemm_queue") {
+      HPS_REQUIRE(value >= -1 && value <= 1, "gemm_queue must be -1, 0 or 1");
+      hps::set_gemm_queue(value != 0);
     } else if (k == "merge_small") {
       HPS_REQUIRE(value >= -1 && value <= 1, "merge_small must be -1, 0 or 1");
       hps::set_merge_small(value != 0);

@@ -29,6 +29,19 @@ int bf16x6_min_k();
 void grouped_gemm(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc, hipStream_t stream,
                   int prec, int prof_cls = 5 /* PROF_GEMM */);
 
+// Heterogeneous grouped FP64 products (the merges of many problems at one
+// depth) as one persistent launch of the 128 x 128 tile: gemm_tile_queue
+// lists every tile, largest problems first; the caller uploads it and
+// passes one int of device scratch for the queue counter.  Workgroups take
+// tiles until the queue is empty.  Knob "gemm_queue" (default on) lets
+// run_build use it for batches.
+std::vector<TileRef> gemm_tile_queue(const std::vector<GemmDesc>& h_desc);
+void grouped_gemm_queue(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc,
+                        const TileRef* d_tiles, int ntiles, int* d_counter, hipStream_t stream,
+                        int prof_cls = 5 /* PROF_GEMM */);
+void set_gemm_queue(bool on);
+bool gemm_queue_on();
+
 // The same with explicit kernel variants (the autotuner times them):
 // gj_variant = update tile * 4 + TRSM block code (see tune.h), -1 = default;
 // variant = FP64 MFMA tile of gemm_tile (0..5), -1 = default.

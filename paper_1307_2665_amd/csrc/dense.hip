@@ -508,6 +508,96 @@ __global__ void __launch_bounds__(256, 2) k_gemm128(const GemmDesc* __restrict__
                       ty * Gemm128::BM, tx * Gemm128::BN, sm, g.overwrite == 0, NoC0Elem{});
 }
 
+// The 128 x 128 tile over a queue of tiles of many problems (one persistent
+// launch): each workgroup takes the next tile from the counter until the
+// queue is empty, so every workgroup exits once all tiles are taken.
+template <int VEC, bool PASS>
+__global__ void __launch_bounds__(256, 2) k_gemm128_queue(const GemmDesc* __restrict__ descs,
+                                                          const TileRef* __restrict__ tiles,
+                                                          int ntiles, int* counter) {
+  __shared__ double sm[Gemm128::SMEM];
+  __shared__ int s_t;
+  for (;;) {
+    if (threadIdx.x == 0) s_t = atomicAdd(counter, 1);
+    __syncthreads();
+    const int t = s_t;
+    __syncthreads();  // every thread has read s_t before it is taken again
+    if (t >= ntiles) return;
+    const TileRef tr = tiles[t];
+    const GemmDesc g = descs[tr.prob];
+    if constexpr (PASS)
+      gemm128_tile<VEC>(g.A, g.lda, g.B, g.ldb, g.C, g.ldc, nullptr, 0, g.M, g.N, g.K, g.alpha,
+                        tr.tm * Gemm128::BM, tr.tn * Gemm128::BN, sm, false, merge_pass(g));
+    else
+      gemm128_tile<VEC>(g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.C0, g.ldc0, g.M, g.N, g.K, g.alpha,
+                        tr.tm * Gemm128::BM, tr.tn * Gemm128::BN, sm, g.overwrite == 0,
+                        NoC0Elem{});
+  }
+}
+
+__global__ void k_set_int(int* p, int v) { *p = v; }
+
+std::vector<TileRef> gemm_tile_queue(const std::vector<GemmDesc>& h_desc) {
+  std::vector<int> order(h_desc.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  // Largest problems first (most work per tile, then most tiles), so the
+  // last tiles taken are the small ones.
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const GemmDesc &x = h_desc[a], &y = h_desc[b];
+    if (x.K != y.K) return x.K > y.K;
+    return (long long)x.M * x.N > (long long)y.M * y.N;
+  });
+  std::vector<TileRef> q;
+  for (int i : order) {
+    const GemmDesc& g = h_desc[i];
+    const int tm = (g.M + Gemm128::BM - 1) / Gemm128::BM, tn = (g.N + Gemm128::BN - 1) / Gemm128::BN;
+    for (int a = 0; a < tm; ++a)
+      for (int b = 0; b < tn; ++b) q.push_back(TileRef{i, a, b, 0});
+  }
+  return q;
+}
+
+void grouped_gemm_queue(const GemmDesc* d_desc, const std::vector<GemmDesc>& h_desc,
+                        const TileRef* d_tiles, int ntiles, int* d_counter, hipStream_t stream,
+                        int prof_cls) {
+  if (h_desc.empty() || ntiles == 0) return;
+  double fl = 0, by = 0;
+  bool v2 = true;
+  const bool pass = h_desc[0].pmap != nullptr;
+  for (auto& g : h_desc) {
+    fl += 2.0 * g.M * g.N * g.K;
+    by += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + 2.0 * g.M * g.N);
+    v2 = v2 && g.lda % 2 == 0 && g.ldb % 2 == 0 && g.K % 2 == 0 && g.N % 2 == 0 &&
+         ((uintptr_t)g.A & 15) == 0 && ((uintptr_t)g.B & 15) == 0;
+    HPS_REQUIRE((g.pmap != nullptr) == pass, "mixed GEMM descriptor kinds");
+  }
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    HPS_HIP(hipGetDevice(&dev));
+    HPS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  const int grid = std::min(ntiles, 2 * cus);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, stream, d_counter, 0);
+  ProfScope ps(prof_cls, stream, fl, by);
+  if (pass && v2)
+    hipLaunchKernelGGL((k_gemm128_queue<2, true>), dim3(grid), dim3(256), 0, stream, d_desc, d_tiles,
+                       ntiles, d_counter);
+  else if (pass)
+    hipLaunchKernelGGL((k_gemm128_queue<1, true>), dim3(grid), dim3(256), 0, stream, d_desc, d_tiles,
+                       ntiles, d_counter);
+  else if (v2)
+    hipLaunchKernelGGL((k_gemm128_queue<2, false>), dim3(grid), dim3(256), 0, stream, d_desc,
+                       d_tiles, ntiles, d_counter);
+  else
+    hipLaunchKernelGGL((k_gemm128_queue<1, false>), dim3(grid), dim3(256), 0, stream, d_desc,
+                       d_tiles, ntiles, d_counter);
+}
+
+static bool g_gemm_queue = true;
+void set_gemm_queue(bool on) { g_gemm_queue = on; }
+bool gemm_queue_on() { return g_gemm_queue; }
+
 // ---------------------------------------------------------------------------
 // Split-FP32 Schur product: A = Ah + Al, B = Bh + Bl with Ah = fl32(A),
 // Al = fl32(A - Ah); C += alpha (Ah Bh + Ah Bl + Al Bh), the three products

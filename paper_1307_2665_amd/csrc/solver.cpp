@@ -919,6 +919,24 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
       }
     }
     if (!solved) batched_solve(dsd, hs, dstatus, s, panel);
+    if (parts.size() > 1 && gemm_queue_on()) {
+      // Merges of several problems: one persistent launch per product over
+      // a largest-first tile queue.
+      int* counter = tmp.alloc<int>(1);
+      std::vector<TileRef> qs = gemm_tile_queue(hsg);
+      TileRef* dqs = tmp.upload(qs, s);
+      grouped_gemm_queue(dsg, hsg, dqs, (int)qs.size(), counter, s, PROF_MERGE_S);
+      if (schur_prec == GEMM_F64) {
+        std::vector<TileRef> qg = gemm_tile_queue(hg);
+        TileRef* dqg = tmp.upload(qg, s);
+        grouped_gemm_queue(dgd, hg, dqg, (int)qg.size(), counter, s, PROF_GEMM);
+        HPS_HIP(hipStreamSynchronize(s));  // the host tile lists die here
+      } else {
+        HPS_HIP(hipStreamSynchronize(s));
+        grouped_gemm(dgd, hg, s, schur_prec);
+      }
+      continue;
+    }
     grouped_gemm(dsg, hsg, s, GEMM_F64, PROF_MERGE_S);
     grouped_gemm(dgd, hg, s, schur_prec);
   }

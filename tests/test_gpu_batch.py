@@ -27,16 +27,27 @@ def _t(x, dev):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
 
 
-def test_small_heterogeneous_batch_matches_oracle(H, gpu):
+# queue: the merges' products as one persistent launch over a largest-first tile
+# queue; small: levels of interfaces up to 20 nodes as whole merges per workgroup.
+@pytest.mark.parametrize("queue,small", [(1, 1), (0, 0), (1, 0)])
+def test_small_heterogeneous_batch_matches_oracle(H, gpu, queue, small):
     probs = [hi.convdiff(seed_g=11, seed_h=12, nleaf=(3, 5), p=8, q=6, nrhs=2),
              hi.convdiff(seed_g=13, seed_h=14, nleaf=(4, 4), p=10, q=8, nrhs=1),
              hi.laplace_log(nleaf=(2, 1), p=12, q=10),
              hi.helmholtz_bump(nleaf=(6, 6), p=10, q=8, nrhs=3),
-             hi.manufactured_variable(nleaf=(5, 3), p=8, q=6)]
-    say("small batch: " + ", ".join(f"{p.name}{p.nleaf}p{p.p}" for p in probs))
+             hi.manufactured_variable(nleaf=(5, 3), p=8, q=6),
+             hi.convdiff(seed_g=15, seed_h=16, nleaf=(12, 9), p=12, q=10, nrhs=1)]
+    say(f"small batch (queue {queue}, small merges {small}): " +
+        ", ".join(f"{p.name}{p.nleaf}p{p.p}" for p in probs))
     inputs = [library_inputs(p) for p in probs]
-    ops = H.build_batch([dict(coeffs=_t(C, gpu), box=p.box, nleaf=p.nleaf, p=p.p, q=p.q)
-                         for p, (C, f) in zip(probs, inputs)])
+    H.tune_set("gemm_queue", queue)
+    H.tune_set("merge_small", small)
+    try:
+        ops = H.build_batch([dict(coeffs=_t(C, gpu), box=p.box, nleaf=p.nleaf, p=p.p, q=p.q)
+                             for p, (C, f) in zip(probs, inputs)])
+    finally:
+        H.tune_set("gemm_queue", -1)
+        H.tune_set("merge_small", -1)
     us = H.solve_batch(ops, [_t(f, gpu) for (C, f) in inputs])
     for p, op, u in zip(probs, ops, us):
         op_o, C_o, f_o, grid = oracle_problem(p)
