@@ -416,6 +416,10 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
      block pivot of at most 10^-e max|M| (or a zero or non-finite one) is
      gathered again and eliminated with partial pivoting (-1: the default,
      e = 6; 0 makes every level fall back);
+   "solve_persist": 1 runs plain solves below 16 right-hand sides as one
+     cooperative launch with a grid-wide barrier between levels (bit for bit
+     the level passes' result); 0 (default, also -1) uses the level passes
+     (a captured graph from the second solve on), measured faster;
    "gemm_queue": 1 (default, also -1) runs the FP64 products of a batch's
      merges at one depth (several problems) as one persistent launch of the
      128 x 128 tile over a tile queue, largest problems first; 0 launches the

@@ -110,6 +110,12 @@ struct MergeDesc {
   unsigned long long* pstat = nullptr;  // the merge system's pivot statistics (SolveDesc)
 };
 
+// One level of the persistent downward pass: nmerge merges of one shape.
+struct PersistLevel {
+  const MergeDesc* d;
+  int nmerge, m3, me, pad;
+};
+
 // Solution array of the problem a merge belongs to (downward pass), and its
 // boundary data (used by the graph-captured solve, which reads both here).
 struct SolveIO {

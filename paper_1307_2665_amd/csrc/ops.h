@@ -69,6 +69,13 @@ void merge_small(const MergeDesc* d_desc, const std::vector<MergeDesc>& h_desc, 
 void downward(const MergeDesc* d_desc, const SolveIO* d_io, const SolveIO& io0, int nmerge,
               int m3_max, int me_max, int nrhs_max, const double* zbase, const long long* zoff,
               hipStream_t s, double s_bytes, bool io_shared = false);
+// Algorithm 2 for one operator as one cooperative launch (levels root
+// first, each with merges of one shape; nrhs <= 15; f [nrhs][nb], u
+// [nrhs][N]); d_bar: 9 x 32 words, d_err: one word, zeroed by the call;
+// *d_err becomes 1 if a level barrier timed out.
+void downward_persist(const PersistLevel* d_levels, int nlev, const double* f, const int* gamma,
+                      int nb, double* u, int N, int nrhs, unsigned* d_bar, int* d_err,
+                      hipStream_t s);
 void set_boundary(const double* f, const int* gamma, int nb, double* u, int N, int nrhs,
                   hipStream_t s);
 // u[r][gamma[i]] = f[r][i] with f, u, N, nrhs read from *io on the device.

@@ -927,6 +927,210 @@ __global__ void __launch_bounds__(256) k_downward(const MergeDesc* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Algorithm 2 as one persistent launch: every level of one operator in a
+// single cooperative kernel, the levels separated by a grid-wide barrier.  Rows are dealt
+// to waves (rows up to 1024 long) or to workgroups (longer rows, split over
+// the four waves and summed through LDS in a fixed order) exactly as in
+// k_downward, so the result is bit for bit the level-by-level one.  A
+// barrier that waits longer than about a second sets *err and lets the
+// workgroup go on (the host then reports a device error): every workgroup
+// always reaches the end.
+// ---------------------------------------------------------------------------
+// The solution u is the only data passed between levels, and every access
+// to it here is a device-scope relaxed atomic (coherent across the XCDs,
+// whose L2 caches are not coherent with each other for plain accesses).  So
+// the barrier needs no cache write-back or invalidation: each thread waits
+// for its own stores, the workgroup meets, thread 0 counts it in and spins.
+__device__ inline double ld_dev(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_dev(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Two-level barrier: the workgroups count in at one of eight group counters
+// (blockIdx mod 8, the XCD the dispatcher sends them to), the last of a
+// group counts the group in at the top counter, and everyone polls the top
+// counter.  bar[0] is the top counter, bar[1..8] the groups' (each in its
+// own 128-byte line).
+__device__ inline void grid_barrier(unsigned* bar, unsigned nblk, unsigned& gen, int* err) {
+  __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have completed
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ++gen;
+    const unsigned g = blockIdx.x & 7u;
+    const unsigned gsize = nblk / 8 + (g < nblk % 8 ? 1u : 0u);
+    const unsigned ngroups = nblk < 8 ? nblk : 8u;
+    const unsigned old =
+        __hip_atomic_fetch_add(bar + 32 * (1 + g), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1 == gen * gsize)
+      __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = gen * ngroups;
+    unsigned spins = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1u << 25)) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_downward_persist(const PersistLevel* __restrict__ levels,
+                                                          int nlev, const double* __restrict__ f,
+                                                          const int* __restrict__ gamma, int nb,
+                                                          double* u, int N, int nrhs,
+                                                          unsigned* bar, int* err) {
+  __shared__ double part[4][DRHS];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const unsigned nblk = gridDim.x;
+  unsigned gen = 0;
+  // Boundary data onto Gamma.
+  const size_t tot = (size_t)nb * nrhs, nthr = (size_t)nblk * blockDim.x;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += nthr) {
+    const int r = (int)(e / nb), i = (int)(e % nb);
+    st_dev(u + (size_t)r * N + gamma[i], f[e]);
+  }
+  for (int lev = 0; lev < nlev; ++lev) {
+    grid_barrier(bar, nblk, gen, err);
+    const PersistLevel P = levels[lev];
+    const int m3 = P.m3, me = P.me;
+    const long long rows = (long long)P.nmerge * m3;
+    if (me <= 64 * DSU) {
+      // One row per wave and task (k_downward<L, false> with L = ceil(me / 64)).
+      const int Lc = (me + 63) / 64;
+      for (long long rr = (long long)blockIdx.x * 4 + wid; rr < rows; rr += (long long)nblk * 4) {
+        const int mi = (int)(rr / m3), r = (int)(rr % m3);
+        const MergeDesc& d = P.d[mi];
+        const gptr<double> Srow = as_global(d.S + (size_t)r * d.lds);
+        const gptr<int> Ie = as_global(d.Ie);
+        double sv[DSU];
+        int ie[DSU];
+#pragma unroll
+        for (int l = 0; l < DSU; ++l) {
+          const int c = lane + 64 * l;
+          const bool in = l < Lc && c < me;
+          sv[l] = in ? Srow[c] : 0.0;
+          ie[l] = in ? Ie[c] : -1;
+        }
+        const int out = d.Ii[r];
+        for (int rb = 0; rb < nrhs; rb += DRHS) {
+          const int nr = min(DRHS, nrhs - rb);
+          double acc[DRHS];
+#pragma unroll
+          for (int j = 0; j < DRHS; ++j) {
+            acc[j] = 0.0;
+            if (j < nr) {
+#pragma unroll
+              for (int l = 0; l < DSU; ++l) {
+                if (l < Lc) {
+                  const double uv = ie[l] >= 0 ? ld_dev(u + (size_t)(rb + j) * N + ie[l]) : 0.0;
+                  acc[j] = fma(sv[l], uv, acc[j]);
+                }
+              }
+#pragma unroll
+              for (int off = 32; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off);
+            }
+          }
+          if (lane == 0)
+#pragma unroll
+            for (int j = 0; j < DRHS; ++j)
+              if (j < nr) st_dev(u + (size_t)(rb + j) * N + out, acc[j]);
+        }
+      }
+    } else {
+      // One row per workgroup and task, the four waves on quarters of it
+      // (k_downward<DSU, true>).
+      const int seg = ((me + 255) / 256) * 64;
+      const int c0 = wid * seg, c1 = min(me, c0 + seg);
+      for (long long rr = blockIdx.x; rr < rows; rr += nblk) {
+        const int mi = (int)(rr / m3), r = (int)(rr % m3);
+        const MergeDesc& d = P.d[mi];
+        const gptr<double> Srow = as_global(d.S + (size_t)r * d.lds);
+        const gptr<int> Ie = as_global(d.Ie);
+        for (int rb = 0; rb < nrhs; rb += DRHS) {
+          const int nr = min(DRHS, nrhs - rb);
+          double acc[DRHS];
+#pragma unroll
+          for (int j = 0; j < DRHS; ++j) acc[j] = 0.0;
+          for (int cb = c0; cb < c1; cb += 64 * DSU) {
+            double sv[DSU];
+            int ie[DSU];
+#pragma unroll
+            for (int l = 0; l < DSU; ++l) {
+              const int c = cb + lane + 64 * l;
+              sv[l] = c < c1 ? Srow[c] : 0.0;
+              ie[l] = c < c1 ? Ie[c] : -1;
+            }
+#pragma unroll
+            for (int j = 0; j < DRHS; ++j) {
+              if (j < nr) {
+                double uv[DSU];
+#pragma unroll
+                for (int l = 0; l < DSU; ++l)
+                  uv[l] = ie[l] >= 0 ? ld_dev(u + (size_t)(rb + j) * N + ie[l]) : 0.0;
+#pragma unroll
+                for (int l = 0; l < DSU; ++l) acc[j] = fma(sv[l], uv[l], acc[j]);
+              }
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < DRHS; ++j) {
+            if (j < nr) {
+              double v = acc[j];
+#pragma unroll
+              for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+              acc[j] = v;
+            }
+          }
+          if (lane == 0)
+#pragma unroll
+            for (int j = 0; j < DRHS; ++j) part[wid][j] = acc[j];
+          __syncthreads();
+          if (threadIdx.x < nr) {
+            const int j = threadIdx.x;
+            st_dev(u + (size_t)(rb + j) * N + d.Ii[r],
+                   ((part[0][j] + part[1][j]) + part[2][j]) + part[3][j]);
+          }
+          __syncthreads();
+        }
+      }
+    }
+  }
+}
+
+__global__ void k_zero_persist(unsigned* bar, int* err) {
+  if (threadIdx.x < 9) bar[32 * threadIdx.x] = 0u;
+  if (threadIdx.x == 0) *err = 0;
+}
+
+int downward_persist_grid() {
+  static int grid = -1;
+  if (grid < 0) {
+    int dev = 0, cus = 0, per = 0;
+    HPS_HIP(hipGetDevice(&dev));
+    HPS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_downward_persist, 256, 0));
+    grid = std::max(0, std::min(per, 4)) * cus;
+  }
+  return grid;
+}
+
+void downward_persist(const PersistLevel* d_levels, int nlev, const double* f, const int* gamma,
+                      int nb, double* u, int N, int nrhs, unsigned* d_bar, int* d_err,
+                      hipStream_t s) {
+  const int grid = downward_persist_grid();
+  HPS_REQUIRE(grid > 0, "persistent downward pass: no resident workgroups");
+  hipLaunchKernelGGL(k_zero_persist, dim3(1), dim3(64), 0, s, d_bar, d_err);
+  void* args[] = {(void*)&d_levels, (void*)&nlev, (void*)&f, (void*)&gamma, (void*)&nb,
+                  (void*)&u, (void*)&N, (void*)&nrhs, (void*)&d_bar, (void*)&d_err};
+  HPS_HIP(hipLaunchCooperativeKernel((const void*)k_downward_persist, dim3(grid), dim3(256), args,
+                                     0, s));
+}
+
 template <int L>
 static void launch_down_rows(dim3 grid, hipStream_t s, const MergeDesc* d_desc,
                              const SolveIO* d_io, const SolveIO& io0, bool io_shared,

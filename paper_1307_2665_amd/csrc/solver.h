@@ -154,6 +154,13 @@ struct hps_op {
   std::map<int, hipGraphExec_t> solve_graphs;
   std::map<int, int> solve_counts;    // plain solves so far, per right-hand-side count
   hps::SolveIO* d_io = nullptr;       // device copy of the current solve's f, u
+  // Persistent downward pass: its level table (root first), barrier word and
+  // error flag (persist_state 0: not planned yet, 1: planned, -1: levels of
+  // mixed merge shapes, not eligible).
+  int persist_state = 0, persist_nlev = 0;
+  hps::PersistLevel* persist_levels = nullptr;
+  unsigned* persist_bar = nullptr;
+  int* persist_err = nullptr;
   hps::SolveIO* h_io = nullptr;       // pinned host staging of it
   hipStream_t capture_stream = nullptr;
 
@@ -188,6 +195,10 @@ void leaf_dtn_batch(const double* coeffs, int nleaf, double hx, double hy, int p
                     hipStream_t s);
 // Algorithm 2 (+ optional interface terms).  u, f device pointers.
 void solve_device(hps_op* op, const double* f, int nrhs, double* u, hipStream_t s);
+// Plain solves below 16 right-hand sides as one cooperative launch (knob
+// "solve_persist", default off: measured slower than the level-by-level
+// passes of the captured graph).
+void set_solve_persist(bool on);
 void solve_batch_device(const std::vector<hps_op*>& ops, const std::vector<const double*>& f,
                         const std::vector<int>& nrhs, const std::vector<double*>& u,
                         hipStream_t s);

@@ -540,3 +540,38 @@ def test_small_merges_keep_factors_refinement(H, gpu):
     e = rel_err(u, hps.solve(op_o, fo))
     say(f"  small merges, kept factors, refined: u rel err {e:.2e}")
     assert e < TOL
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2 as one cooperative launch (grid-wide barrier between levels).
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("maker", [
+    lambda: hi.convdiff(nleaf=(16, 16), p=12, q=10, nrhs=3),
+    lambda: hi.helmholtz_bump(kappa=25.0, nleaf=(32, 32), p=10, q=8, nrhs=2),
+    lambda: hi.manufactured_variable(nleaf=(7, 5), p=10, q=7),
+])
+def test_persistent_solve_matches_level_passes(H, gpu, maker):
+    """The persistent downward pass gives bit for bit the level-by-level passes (eager and
+    graph replay) for 1 to 15 right-hand sides, and u matches the oracle; an operator whose
+    depths hold merges of different shapes keeps the level passes."""
+    pr = maker()
+    op_o, Co, fo, grid = oracle_problem(pr)
+    C, f = library_inputs(pr)
+    op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q)
+    rng = np.random.default_rng(3)
+    try:
+        for nrhs in (1, 4, 15):
+            fr = _t(rng.standard_normal((nrhs, op.n_bdry)), gpu)
+            H.tune_set("solve_persist", 0)
+            ref = [op.solve(fr).cpu().numpy() for _ in range(3)]   # eager, then graph replays
+            H.tune_set("solve_persist", 1)
+            for _ in range(2):
+                up = op.solve(fr).cpu().numpy()
+                assert all(np.array_equal(up, r) for r in ref), nrhs
+    finally:
+        H.tune_set("solve_persist", -1)
+    u = op.solve(_t(f, gpu)).cpu().numpy()
+    e = rel_err(u, hps.solve(op_o, fo))
+    say(f"  persistent solve {pr.name} {pr.nleaf}: u rel err {e:.2e}")
+    assert e < TOL
