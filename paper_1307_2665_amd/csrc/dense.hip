@@ -1114,9 +1114,9 @@ void batched_solve_v(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_de
 // systems).  Step k0 of W = [M | I] (n = m3 rows, kb = min(64, n - k0)):
 //   1. k_bgj_diag: B^-1 of the diagonal block B = W[K, K], K = [k0, k0 + kb),
 //      by in-place Gauss-Jordan with partial pivoting among the kb rows of
-//      the block (one workgroup per system: wave w holds 16 columns of every
-//      row, the pivot row reaches each wave by readlane, the multipliers
-//      through LDS; one barrier per column);
+//      the block (one workgroup per system: each of eight waves holds 8
+//      columns of every row, the pivot row reaches each wave by readlane,
+//      the multipliers through LDS; one barrier per column);
 //   2. k_bgj_rows: the block's rows become B^-1 W[K, k0 + kb:] (FP64 MFMA);
 //   3. k_gj_update: every other row gets W[i, :] -= W[i, K] W_new[K, :].
 // No rows move, so the identity block ends up holding M^-1 in natural
@@ -1128,8 +1128,9 @@ void batched_solve_v(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_de
 // partial pivoting.
 // ---------------------------------------------------------------------------
 constexpr int BGJ_NB = 64;
+constexpr int BGJ_CPW = 8;  // diagonal-block columns per wave (eight waves)
 
-__global__ void __launch_bounds__(256) k_bgj_diag(const SolveDesc* __restrict__ descs, int k0,
+__global__ void __launch_bounds__(64 * BGJ_NB / BGJ_CPW) k_bgj_diag(const SolveDesc* __restrict__ descs, int k0,
                                                   double* __restrict__ binv, double fb_tol,
                                                   int* status) {
   // Multipliers of the current column (double-buffered by column parity, so
@@ -1144,12 +1145,13 @@ __global__ void __launch_bounds__(256) k_bgj_diag(const SolveDesc* __restrict__ 
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const size_t ld = d.ld;
   const double* Bk = d.W + (size_t)k0 * ld + k0;
-  // Wave w holds columns 16 w .. 16 w + 15 of row `lane`; padding (rows or
-  // columns >= kb) is the identity, which no real column can pick.
-  double x[16];
+  // Wave w holds columns CPW w .. CPW w + CPW - 1 of row `lane`; padding
+  // (rows or columns >= kb) is the identity, which no real column can pick.
+  constexpr int CPW = BGJ_CPW;
+  double x[CPW];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int c = 16 * wid + j;
+  for (int j = 0; j < CPW; ++j) {
+    const int c = CPW * wid + j;
     x[j] = (lane < kb && c < kb) ? as_global(Bk)[(size_t)lane * ld + c] : (lane == c ? 1.0 : 0.0);
   }
   // Rows are scaled lazily: the true row is scale * x.  A pivot row keeps
@@ -1158,10 +1160,10 @@ __global__ void __launch_bounds__(256) k_bgj_diag(const SolveDesc* __restrict__ 
   double scale = 1.0;
   bool chosen = false, bad = false;
   double minp = INFINITY;
-  for (int g = 0; g < (kb + 15) / 16; ++g) {
+  for (int g = 0; g < (kb + CPW - 1) / CPW; ++g) {
 #pragma unroll
-    for (int cc = 0; cc < 16; ++cc) {
-      const int c = 16 * g + cc;
+    for (int cc = 0; cc < CPW; ++cc) {
+      const int c = CPW * g + cc;
       if (c >= kb) continue;  // uniform
       const int buf = c & 1;
       if (wid == g) {
@@ -1182,11 +1184,23 @@ __global__ void __launch_bounds__(256) k_bgj_diag(const SolveDesc* __restrict__ 
       const bool ok = piv != 0.0 && piv == piv && fabs(piv) != INFINITY;
       bad |= !ok;
       minp = fmin(minp, fabs(piv));
-      const double inv = ok ? 1.0 / piv : 0.0;
+      // 1/piv: the hardware reciprocal refined by two Newton steps
+      // (r <- r + r (1 - piv r)), within an ulp; far-out pivots divide.
+      double inv = 0.0;
+      if (ok) {
+        const double ap = fabs(piv);
+        if (ap > 1e-290 && ap < 1e290) {
+          double r = __builtin_amdgcn_rcp(piv);
+          r = fma(r, fma(-piv, r, 1.0), r);
+          inv = fma(r, fma(-piv, r, 1.0), r);
+        } else {
+          inv = 1.0 / piv;
+        }
+      }
       const bool me = lane == pr;
       const double gm = me ? 0.0 : -f * inv;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) x[j] = fma(gm, bcast_lane(x[j], pr), x[j]);
+      for (int j = 0; j < CPW; ++j) x[j] = fma(gm, bcast_lane(x[j], pr), x[j]);
       if (wid == g) x[cc] = me ? 1.0 : gm;
       if (me) {
         scale = inv;
@@ -1195,7 +1209,7 @@ __global__ void __launch_bounds__(256) k_bgj_diag(const SolveDesc* __restrict__ 
     }
   }
 #pragma unroll
-  for (int j = 0; j < 16; ++j) x[j] *= scale;
+  for (int j = 0; j < CPW; ++j) x[j] *= scale;
   // Pivot statistics and the fall-back test (block pivots against max|M|);
   // a zero or non-finite block pivot also falls back (the partial-pivoting
   // path then decides whether M itself is singular).
@@ -1214,8 +1228,8 @@ __global__ void __launch_bounds__(256) k_bgj_diag(const SolveDesc* __restrict__ 
   if (lane < kb) {
     const int a = sPi[lane];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int c = 16 * wid + j;
+    for (int j = 0; j < CPW; ++j) {
+      const int c = CPW * wid + j;
       if (c < kb) Bi[(size_t)a * BGJ_NB + sP[c]] = x[j];
     }
   }
@@ -1294,8 +1308,8 @@ void batched_solve_bgj(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_
     }
     {
       ProfScope ps(PROF_BGJ_DIAG, stream, fd, 0);
-      hipLaunchKernelGGL(k_bgj_diag, dim3(np), dim3(256), 0, stream, d_desc, k0, binv,
-                         g_bgj_fb_tol, d_status);
+      hipLaunchKernelGGL(k_bgj_diag, dim3(np), dim3(64 * BGJ_NB / BGJ_CPW), 0, stream, d_desc, k0,
+                         binv, g_bgj_fb_tol, d_status);
     }
     // Columns past the block: the rest of M and the touched part of the
     // identity block, n columns in all (k_bgj_rows and the update clip them
