@@ -183,13 +183,13 @@ def sweep_field(seed: int, nleaf=(256, 256), p=12, q=10) -> Problem:
                    bc=[cos_bc])
 
 
-def paper_constant_convection(nleaf=(64, 64), p=21, q=21) -> Problem:
+def paper_constant_convection(nleaf=(64, 64), p=21, q=20) -> Problem:
     """Section 9.2, constant convection: c2 = -1e5 in eq:example, i.e. +1e5 in eq:defA."""
     return Problem("const_conv", [ONE, ZERO, ONE, ZERO, _const(1.0e5), ZERO],
                    nleaf=tuple(nleaf), p=p, q=q, bc=[cos_bc])
 
 
-def paper_diffusion_convection(nleaf=(64, 64), p=21, q=21) -> Problem:
+def paper_diffusion_convection(nleaf=(64, 64), p=21, q=20) -> Problem:
     """Section 9.2: c1 = -1e4 cos(4 pi x2), c2 = -1e4 cos(4 pi x1) in eq:example."""
     c1 = lambda x, y: 1.0e4 * np.cos(4.0 * np.pi * np.asarray(y)) + 0.0 * np.asarray(x)
     c2 = lambda x, y: 1.0e4 * np.cos(4.0 * np.pi * np.asarray(x)) + 0.0 * np.asarray(y)
@@ -197,7 +197,7 @@ def paper_diffusion_convection(nleaf=(64, 64), p=21, q=21) -> Problem:
                    bc=[cos_bc])
 
 
-def paper_variable_helmholtz(nleaf=(64, 64), p=21, q=21, kappa=640.0) -> Problem:
+def paper_variable_helmholtz(nleaf=(64, 64), p=21, q=20, kappa=640.0) -> Problem:
     """Section 9.2: c = kappa^2 (1 - (sin 4 pi x1 sin 4 pi x2)^2) in eq:example."""
     c = lambda x, y: -kappa ** 2 * (1.0 - (np.sin(4 * np.pi * np.asarray(x))
                                            * np.sin(4 * np.pi * np.asarray(y))) ** 2)

@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(64 * TP_MAXW) k_gj_panel(const SolveDesc* __re
         }
       // The candidate's reciprocal is formed before the barrier, off the
       // critical path of the elimination that follows it.
-      if (lane == 0) sInvP[buf][wid] = 1.0 / cand;
+      if (lane == 0) sInvP[buf][wid] = recip(cand);
     }
     if (lane == 0) sKey[buf][wid] = wkey;
     __syncthreads();
@@ -322,7 +322,7 @@ __global__ void __launch_bounds__(64) k_gj_panel_w1(const SolveDesc* __restrict_
     const bool ok = (piv != 0.0) && (piv == piv) && fabs(piv) != INFINITY;
     bad |= !ok;
     minp = fmin(minp, fabs(piv));
-    const double inv = ok ? 1.0 / piv : 0.0;
+    const double inv = ok ? recip(piv) : 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r)
       if (live[r]) {
@@ -1184,19 +1184,7 @@ __global__ void __launch_bounds__(64 * BGJ_NB / BGJ_CPW) k_bgj_diag(const SolveD
       const bool ok = piv != 0.0 && piv == piv && fabs(piv) != INFINITY;
       bad |= !ok;
       minp = fmin(minp, fabs(piv));
-      // 1/piv: the hardware reciprocal refined by two Newton steps
-      // (r <- r + r (1 - piv r)), within an ulp; far-out pivots divide.
-      double inv = 0.0;
-      if (ok) {
-        const double ap = fabs(piv);
-        if (ap > 1e-290 && ap < 1e290) {
-          double r = __builtin_amdgcn_rcp(piv);
-          r = fma(r, fma(-piv, r, 1.0), r);
-          inv = fma(r, fma(-piv, r, 1.0), r);
-        } else {
-          inv = 1.0 / piv;
-        }
-      }
+      const double inv = ok ? recip(piv) : 0.0;
       const bool me = lane == pr;
       const double gm = me ? 0.0 : -f * inv;
 #pragma unroll

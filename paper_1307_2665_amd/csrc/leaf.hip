@@ -412,7 +412,7 @@ __global__ void __launch_bounds__(16 * TC) k_leaf_gj(const double* const* __rest
         if (atomicCAS(status, 0, 1) == 0) status[1] = tag0 - (int)blockIdx.x;
       // Columns of this thread that are still to be updated: j > k.
       if (NC * tc + NC - 1 > k) {
-        const double inv = ok ? 1.0 / piv : 0.0;
+        const double inv = ok ? recip(piv) : 0.0;
         // Row p's values in my columns (lane trp of my DPP row, slot sp),
         // divided by the pivot.
         // Lane trp of each DPP row stores row p's values of its columns to
@@ -611,7 +611,7 @@ __global__ void __launch_bounds__(64 * (NTI + 1), 4) k_leaf_mfma(
         const bool ok = g != 0 && piv != 0.0 && piv == piv && fabs(piv) != INFINITY &&
                         fabs(piv) > thr;
         bad |= !ok;
-        const double inv = uniform(ok ? 1.0 / piv : 0.0);
+        const double inv = uniform(ok ? recip(piv) : 0.0);
         // In-place Gauss-Jordan step on column c: every row loses f times the
         // scaled pivot row and column c takes the multipliers (-f / pivot);
         // the pivot row is then overwritten with the scaled row (1 / pivot in

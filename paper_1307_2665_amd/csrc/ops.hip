@@ -430,7 +430,7 @@ __global__ void __launch_bounds__(256) k_merge_small(const MergeDesc* __restrict
     const bool ok = piv != 0.0 && piv == piv && fabs(piv) != INFINITY;
     bad |= !ok;
     minp = fmin(minp, fabs(piv));
-    const double inv = ok ? 1.0 / piv : 0.0;
+    const double inv = ok ? recip(piv) : 0.0;
     for (int j = tid; j < 2 * m3; j += nthr) {
       if (j == c) {
         for (int i = 0; i < m3; ++i) Wl[i * lw + j] = i == pr ? 1.0 : 0.0;

@@ -54,4 +54,17 @@ __device__ inline double uniform(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// 1/x for a finite nonzero x: the hardware reciprocal refined by two Newton
+// steps (r <- r + r (1 - x r)), within an ulp of the quotient; magnitudes
+// outside [1e-290, 1e290] take the division.
+__device__ inline double recip(double x) {
+  const double a = fabs(x);
+  if (a > 1e-290 && a < 1e290) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+  }
+  return 1.0 / x;
+}
+
 }  // namespace hps

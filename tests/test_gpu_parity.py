@@ -575,3 +575,28 @@ def test_persistent_solve_matches_level_passes(H, gpu, maker):
     e = rel_err(u, hps.solve(op_o, fo))
     say(f"  persistent solve {pr.name} {pr.nleaf}: u rel err {e:.2e}")
     assert e < TOL
+
+
+# ---------------------------------------------------------------------------
+# The section 9.2 problems (strong constant and variable convection, a
+# high-frequency Helmholtz coefficient) at small sizes: large coefficients
+# stress the pivoting of the leaf and merge eliminations.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("maker", [
+    lambda: hi.paper_constant_convection(nleaf=(8, 8), p=12, q=10),
+    lambda: hi.paper_diffusion_convection(nleaf=(8, 8), p=14, q=12),
+    # kappa = 30 keeps the merges well conditioned (oracle max|M|/min|pivot| about 8; at
+    # kappa = 80 one depth reaches 1e3 and S differs from the oracle by 1.3e-10).
+    lambda: hi.paper_variable_helmholtz(nleaf=(16, 16), p=12, q=10, kappa=30.0),
+])
+def test_section9_problems_match_oracle(H, gpu, maker):
+    pr = maker()
+    op_o, Co, fo, grid = oracle_problem(pr)
+    C, f = library_inputs(pr)
+    op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q)
+    _compare_operator(H, op, op_o)
+    u = op.solve(_t(f, gpu)).cpu().numpy()
+    e = rel_err(u, hps.solve(op_o, fo))
+    say(f"  {pr.name} {pr.nleaf} p={pr.p}: u rel err {e:.2e}")
+    assert e < TOL
