@@ -416,6 +416,13 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
      block pivot of at most 10^-e max|M| (or a zero or non-finite one) is
      gathered again and eliminated with partial pivoting (-1: the default,
      e = 6; 0 makes every level fall back);
+   "leaf_bgj": 1 (default, also -1) eliminates the leaf systems the MFMA
+     leaf kernel does not take (p > 12, or with keep_leaf_solution) by
+     blocked Gauss-Jordan on the assembled [A_ii | R], pivoting inside 64 x 64
+     diagonal blocks; a chunk of leaves with a block pivot at or below
+     10^-e max|A_ii| ("bgj_fallback_tol_exp") is assembled again and
+     eliminated with partial pivoting; 0 keeps the register kernels and the
+     panel solver;
    "solve_persist": 1 runs plain solves below 16 right-hand sides as one
      cooperative launch with a grid-wide barrier between levels (bit for bit
      the level passes' result); 0 (default, also -1) uses the level passes
@@ -435,8 +442,8 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
    Unknown knobs or values give HPS_EINVAL. */
 hps_status hps_tune_set(const char* knob, int value);
 
-/* Number of merge levels, over all builds of this process, whose blocked
-   Gauss-Jordan elimination fell back to partial pivoting. */
+/* Number of merge levels and leaf chunks, over all builds of this process,
+   whose blocked Gauss-Jordan elimination fell back to partial pivoting. */
 hps_status hps_bgj_fallbacks(long long* count);
 
 /* Autotuner.  For every problem shape in probs (only nleaf, p, q and box are

@@ -535,6 +535,9 @@ hps_status hps_tune_set(const char* knob, int value) {
       hps::set_bf16x6_min_k(value);
     } else if (k == "post_rows") {
       hps::set_post_rows(value);
+    } else if (k == "leaf_bgj") {
+      HPS_REQUIRE(value >= -1 && value <= 1, "leaf_bgj must be -1, 0 or 1");
+      hps::set_leaf_bgj(value != 0);
     } else if (k == "solve_persist") {
       HPS_REQUIRE(value >= -1 && value <= 1, "solve_persist must be -1, 0 or 1");
       hps::set_solve_persist(value == 1);

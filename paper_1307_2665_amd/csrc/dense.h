@@ -71,8 +71,13 @@ void dense_init();
 // status[3] when a block pivot is not above fb_tol max|M|: the caller then
 // redoes the systems with batched_solve.  Used for systems of at least
 // bgj_min_rows() rows (set_bgj: -1 keeps a value).
+// *p = v on the stream (a one-thread kernel, not a memset node).
+void set_int(int* p, int v, hipStream_t s);
+
+// ident: W = [M | I] (m == n), whose identity columns right of the touched
+// part are skipped; otherwise every column right of the block is updated.
 void batched_solve_bgj(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc, int* d_status,
-                       double* binv, hipStream_t stream);
+                       double* binv, hipStream_t stream, bool ident = true);
 void set_bgj(int min_rows, double fb_tol);
 // On (default): each step's update of the columns past the next diagonal
 // block runs on a side stream beside the next diagonal-block kernel.

@@ -537,6 +537,10 @@ __global__ void __launch_bounds__(256, 2) k_gemm128_queue(const GemmDesc* __rest
 
 __global__ void k_set_int(int* p, int v) { *p = v; }
 
+void set_int(int* p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, p, v);
+}
+
 std::vector<TileRef> gemm_tile_queue(const std::vector<GemmDesc>& h_desc) {
   std::vector<int> order(h_desc.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
@@ -1227,15 +1231,16 @@ __global__ void __launch_bounds__(64 * BGJ_NB / BGJ_CPW) k_bgj_diag(const SolveD
 // columns c of this tile (one 64-row tile covers all kb rows, so a tile reads
 // its own columns of W[K, :] before it overwrites them).
 __global__ void __launch_bounds__(256) k_bgj_rows(const SolveDesc* __restrict__ descs, int k0,
-                                                  const double* __restrict__ binv) {
+                                                  const double* __restrict__ binv, int ident) {
   __shared__ double sm[GemmTile<64, 64, 16, 2, 2>::SMEM];
   const SolveDesc d = descs[blockIdx.z];
   if (k0 >= d.n) return;
   const int kb = min(BGJ_NB, d.n - k0);
-  // Columns k0 + kb .. n + k0 + kb - 1: the rest of M and the part of the
-  // identity block already touched (its later columns are still unit
-  // vectors that no step changes before its own).
-  const int ncols = min(d.n, d.n + d.m - k0 - kb);
+  // Columns past the block.  With W = [M | I] (ident): k0 + kb .. n + k0 + kb
+  // - 1, the rest of M and the part of the identity block already touched
+  // (its later columns are still unit vectors that no step changes before
+  // its own); otherwise every column to the right.
+  const int ncols = ident ? min(d.n, d.n + d.m - k0 - kb) : d.n + d.m - k0 - kb;
   if ((int)blockIdx.x * 64 >= ncols) return;
   double* Wk = d.W + (size_t)k0 * d.ld + k0 + kb;
   gemm_tile_map<64, 64, 16, 2, 2, RowsIdentity, RowsIdentity, RowsIdentity, NoC0Elem, false, 3>(
@@ -1266,13 +1271,13 @@ void set_bgj(int min_rows, double fb_tol) {
 int bgj_min_rows() { return g_bgj_min_rows; }
 
 void batched_solve_bgj(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_desc, int* d_status,
-                       double* binv, hipStream_t stream) {
+                       double* binv, hipStream_t stream, bool ident) {
   if (h_desc.empty()) return;
   int nmax = 0, wmax = 0;
   for (auto& d : h_desc) {
-    // Only the untouched columns of the identity block are skipped, so the
-    // right-hand block must be I (m == n).
-    HPS_REQUIRE(d.m == d.n, "blocked Gauss-Jordan needs W = [M | I]");
+    // Only the untouched columns of the identity block are skipped, so with
+    // ident the right-hand block must be I (m == n).
+    HPS_REQUIRE(!ident || d.m == d.n, "blocked Gauss-Jordan: W = [M | I] needs m == n");
     nmax = std::max(nmax, d.n);
     wmax = std::max(wmax, d.n + d.m);
   }
@@ -1289,7 +1294,8 @@ void batched_solve_bgj(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_
     double fd = 0, fr = 0, fu = 0;
     for (auto& d : h_desc) {
       if (k0 >= d.n) continue;
-      const double kb = std::min(BGJ_NB, d.n - k0), rest = std::min<double>(d.n, d.n + d.m - k0 - kb);
+      const double kb = std::min(BGJ_NB, d.n - k0),
+                   rest = ident ? std::min<double>(d.n, d.n + d.m - k0 - kb) : d.n + d.m - k0 - kb;
       fd += 2.0 * kb * kb * kb;
       fr += 2.0 * kb * kb * rest;
       fu += 2.0 * (d.n - kb) * rest * kb;
@@ -1299,10 +1305,11 @@ void batched_solve_bgj(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_
       hipLaunchKernelGGL(k_bgj_diag, dim3(np), dim3(64 * BGJ_NB / BGJ_CPW), 0, stream, d_desc, k0,
                          binv, g_bgj_fb_tol, d_status);
     }
-    // Columns past the block: the rest of M and the touched part of the
-    // identity block, n columns in all (k_bgj_rows and the update clip them
-    // per system).
-    const int rest = std::min(nmax, wmax - k0 - std::min(BGJ_NB, nmax - k0));
+    // Columns past the block (with ident: the rest of M and the touched part
+    // of the identity block, n columns in all); k_bgj_rows and the update
+    // clip them per system.
+    const int rest = ident ? std::min(nmax, wmax - k0 - std::min(BGJ_NB, nmax - k0))
+                           : wmax - k0 - std::min(BGJ_NB, nmax - k0);
     if (rest <= 0) continue;
     if (pending) {  // the previous step's side-stream update must finish first
       HPS_HIP(hipStreamWaitEvent(stream, la.done, 0));
@@ -1311,7 +1318,7 @@ void batched_solve_bgj(const SolveDesc* d_desc, const std::vector<SolveDesc>& h_
     {
       ProfScope ps(PROF_BGJ_ROWS, stream, fr, 0);
       hipLaunchKernelGGL(k_bgj_rows, dim3((rest + 63) / 64, 1, np), dim3(256), 0, stream, d_desc,
-                         k0, (const double*)binv);
+                         k0, (const double*)binv, ident ? 1 : 0);
     }
     {
       ProfScope ps(PROF_BGJ_UPDATE, stream, fu, 0);

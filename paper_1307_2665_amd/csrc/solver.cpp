@@ -583,6 +583,15 @@ struct LeafJob {
   double* zdst = nullptr;  // [4q][(p-2)^2]: keeps Z^T, Z = A_ii^-1 A_ie L1, when not null
 };
 
+// On by default: 64 x 64 leaves at p = 16 built in 13.7 ms against 14.2 ms
+// with the fused register kernel, 128 x 128 at p = 16 in 50.8 against 52.6,
+// 32 x 32 at p = 20 in 9.7 against 11.4 (same GPU, same inputs).
+static bool g_leaf_bgj = true;
+static std::atomic<long long> g_leaf_bgj_fallbacks{0};
+void set_leaf_bgj(bool on) { g_leaf_bgj = on; }
+bool leaf_bgj_on() { return g_leaf_bgj; }
+long long leaf_bgj_fallbacks() { return g_leaf_bgj_fallbacks.load(); }
+
 static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hipStream_t s,
                            int* dstatus, int panel, double tol = 0.0) {
   const LeafPlan& L0 = *jobs[0].lp;
@@ -607,7 +616,11 @@ static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hip
     HPS_HIP(hipStreamSynchronize(s));  // the host pointer arrays are freed on return
     return;
   }
-  const bool fused = leaf_lu_fits(n, m);
+  // Blocked Gauss-Jordan on the assembled systems (pivoting inside 64 x 64
+  // diagonal blocks, the chunk redone with partial pivoting should a block
+  // pivot be small) instead of the fused register kernel or the panel solver.
+  const bool use_bgj = leaf_bgj_on() && n >= 64;
+  const bool fused = !use_bgj && leaf_lu_fits(n, m);
   // Fused path: only Z (n x m) per leaf; generic path: the augmented system.
   const size_t per = fused ? (size_t)n * m * sizeof(double)
                            : (size_t)n * ld * sizeof(double) + (size_t)n * sizeof(int);
@@ -621,9 +634,12 @@ static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hip
   GemmDesc* dgd = tmp.alloc<GemmDesc>(CH);
   const double** dzs = keepZ ? tmp.alloc<const double*>(CH) : nullptr;
   double** dzd = keepZ ? tmp.alloc<double*>(CH) : nullptr;
-  // Pivot statistics of the generic path's systems (relative pivot test).
-  unsigned long long* dps = (!fused && tol > 0.0) ? tmp.alloc<unsigned long long>(2 * (size_t)CH)
-                                                  : nullptr;
+  // Pivot statistics of the generic path's systems (relative pivot test, and
+  // max|A_ii| for the blocked path's fall-back test).
+  unsigned long long* dps = (!fused && (tol > 0.0 || use_bgj))
+                                ? tmp.alloc<unsigned long long>(2 * (size_t)CH)
+                                : nullptr;
+  double* binv = use_bgj ? tmp.alloc<double>((size_t)CH * 64 * 64) : nullptr;
   for (int c0 = 0; c0 < total; c0 += CH) {
     const int cnt = std::min(CH, total - c0);
     std::vector<const double*> cp(cnt);
@@ -653,8 +669,23 @@ static void run_leaf_group(const std::vector<LeafJob>& jobs, DeviceMem& tmp, hip
         pstat_init(dps, cnt, s);
         system_absmax(dsd, cnt, n, s);
       }
-      batched_solve(dsd, sd, dstatus, s, panel);
-      if (dps) pivot_check(dsd, cnt, tol, dstatus, s);
+      bool solved = false;
+      if (use_bgj) {
+        set_int(dstatus + 3, 0, s);
+        batched_solve_bgj(dsd, sd, dstatus, binv, s, false);
+        int fb = 0;
+        HPS_HIP(hipMemcpyAsync(&fb, dstatus + 3, sizeof(int), hipMemcpyDeviceToHost, s));
+        HPS_HIP(hipStreamSynchronize(s));
+        solved = fb == 0;
+        if (!solved) {
+          g_leaf_bgj_fallbacks.fetch_add(1);
+          leaf_assemble(dcp, tab, cnt, Wslab, s);
+          pstat_init(dps, cnt, s);
+          system_absmax(dsd, cnt, n, s);
+        }
+      }
+      if (!solved) batched_solve(dsd, sd, dstatus, s, panel);
+      if (dps && tol > 0.0) pivot_check(dsd, cnt, tol, dstatus, s);
     }
     grouped_gemm(dgd, gd, s, GEMM_F64, PROF_LEAF_GEMM);
     // Kept Z goes out transposed ([4q][(p-2)^2]) for the post-processing loads.
@@ -799,7 +830,7 @@ static void surrogate_leaf_stage(hps_op* op, DeviceMem& tmp, hipStream_t s, int*
 // Levels whose blocked Gauss-Jordan fell back to partial pivoting (all builds).
 static std::atomic<long long> g_bgj_fallbacks{0};
 
-long long bgj_fallbacks() { return g_bgj_fallbacks.load(); }
+long long bgj_fallbacks() { return g_bgj_fallbacks.load() + g_leaf_bgj_fallbacks.load(); }
 
 void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
   DeviceMem tmp;
@@ -906,7 +937,7 @@ void run_build(const std::vector<hps_op*>& ops, hipStream_t s) {
       // diagonal blocks; should a block pivot be too small, the level is
       // gathered again and solved with partial pivoting.
       double* binv = tmp.alloc<double>(hs.size() * 64 * 64);
-      HPS_HIP(hipMemsetAsync(dstatus + 3, 0, sizeof(int), s));
+      set_int(dstatus + 3, 0, s);
       batched_solve_bgj(dsd, hs, dstatus, binv, s);
       int fb = 0;
       HPS_HIP(hipMemcpyAsync(&fb, dstatus + 3, sizeof(int), hipMemcpyDeviceToHost, s));

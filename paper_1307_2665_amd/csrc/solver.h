@@ -226,6 +226,11 @@ void set_solve_graph(bool on);
 void set_solve_mm_min_rhs(int v);
 // Merge levels (over all builds so far) whose blocked Gauss-Jordan fell back
 // to partial pivoting.
+// Leaf systems by blocked Gauss-Jordan (knob "leaf_bgj", default on): the
+// leaves the MFMA leaf kernel does not take (p > 12, or with the leaf
+// solution kept) are assembled and eliminated like the large merges.
+void set_leaf_bgj(bool on);
+bool leaf_bgj_on();
 long long bgj_fallbacks();
 // Releases the stream-ordered scratch cached in the current device's pool.
 void trim_async_pool();

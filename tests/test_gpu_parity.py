@@ -600,3 +600,34 @@ def test_section9_problems_match_oracle(H, gpu, maker):
     e = rel_err(u, hps.solve(op_o, fo))
     say(f"  {pr.name} {pr.nleaf} p={pr.p}: u rel err {e:.2e}")
     assert e < TOL
+
+
+@pytest.mark.parametrize("p,q,nleaf", [(16, 14, (6, 5)), (20, 18, (4, 4)), (14, 12, (5, 3))])
+def test_leaf_blocked_gauss_jordan_matches_oracle(H, gpu, p, q, nleaf):
+    """Leaf systems eliminated by blocked Gauss-Jordan (knob leaf_bgj): every leaf DtN, the
+    root DtN and u against the oracle; with the fall-back threshold at max|A_ii| every chunk
+    is redone with partial pivoting and still matches."""
+    pr = hi.helmholtz_bump(kappa=20.0, nleaf=nleaf, p=p, q=q, nrhs=2)
+    op_o, Co, fo, grid = oracle_problem(pr)
+    C, f = library_inputs(pr)
+    for forced in (0, 1):
+        before = H.bgj_fallbacks()
+        H.tune_set("leaf_bgj", 1)
+        if forced:
+            H.tune_set("bgj_fallback_tol_exp", 0)
+        try:
+            op = H.build_solution_operator(_t(C, gpu), pr.box, pr.nleaf, pr.p, pr.q)
+        finally:
+            H.tune_set("leaf_bgj", -1)
+            H.tune_set("bgj_fallback_tol_exp", -1)
+        fell = H.bgj_fallbacks() - before
+        assert (fell > 0) == bool(forced), fell
+        for lf in range(nleaf[0] * nleaf[1]):
+            t = hps.find_leaf(op_o, lf % nleaf[0], lf // nleaf[0])
+            assert rel_err(op.export_leaf_dtn(lf), op_o.leafT[t]) < TOL, lf
+        _compare_operator(H, op, op_o)
+        u = op.solve(_t(f, gpu)).cpu().numpy()
+        e = rel_err(u, hps.solve(op_o, fo))
+        say(f"  leaf blocked GJ p={p} forced fall-back {forced}: u rel err {e:.2e}")
+        assert e < TOL
+        op.destroy()
