@@ -67,7 +67,7 @@ void pivot_check(const SolveDesc* d_desc, int count, double tol, int* status, hi
 void dense_init();
 
 // Blocked Gauss-Jordan with pivoting inside 64 x 64 diagonal blocks (see
-// dense.hip); binv: scratch of 64 x 64 doubles per system.  Raises
+// gj.hip); binv: scratch of 64 x 64 doubles per system.  Raises
 // status[3] when a block pivot is not above fb_tol max|M|: the caller then
 // redoes the systems with batched_solve.  Used for systems of at least
 // bgj_min_rows() rows (set_bgj: -1 keeps a value).

@@ -16,7 +16,7 @@ enum TuneKnob {
 };
 
 constexpr int GEMM_VARIANTS = 8;   // tiles of grouped_gemm_v (dense.hip)
-// Tiles of the Gauss-Jordan trailing update (launch_update in dense.hip):
+// Tiles of the Gauss-Jordan trailing update (launch_update in gj.hip):
 // 0: 64x64x16 on 2x2 waves, 1: 32x32x16 on one wave, 2: 128x128x16 on 4x2
 // waves, 3: 128x64x16, 4: 64x128x16, 5: 64x64x32; each loads its tile's old
 // values with the first operands and keeps one k-slab of loads in flight.
