@@ -24,6 +24,7 @@ namespace {
 struct Entry {
   int variant;
   double ms, ms_default;
+  std::vector<double> all;  // every candidate's time (GEMM buckets), -1 = not run
 };
 using Key = std::array<int, 5>;
 
@@ -65,10 +66,11 @@ void tune_force(int knob, int variant) {
   T.forced[knob] = variant;
 }
 
-void tune_put(int knob, int a, int b, int c, int d, int variant, double ms, double ms_default) {
+void tune_put(int knob, int a, int b, int c, int d, int variant, double ms, double ms_default,
+              const std::vector<double>& all) {
   Table& T = table();
   std::lock_guard<std::mutex> lk(T.mu);
-  T.entries[Key{knob, a, b, c, d}] = Entry{variant, ms, ms_default};
+  T.entries[Key{knob, a, b, c, d}] = Entry{variant, ms, ms_default, all};
 }
 
 void tune_clear() {
@@ -88,10 +90,19 @@ std::string tune_json() {
     char buf[256];
     std::snprintf(buf, sizeof(buf),
                   "    {\"knob\": %d, \"name\": \"%s\", \"key\": [%d, %d, %d, %d], \"variant\": %d, "
-                  "\"ms\": %.6g, \"default_ms\": %.6g}%s\n",
+                  "\"ms\": %.6g, \"default_ms\": %.6g",
                   k[0], knob_name(k[0]), k[1], k[2], k[3], k[4], kv.second.variant, kv.second.ms,
-                  kv.second.ms_default, ++i < T.entries.size() ? "," : "");
+                  kv.second.ms_default);
     o << buf;
+    if (!kv.second.all.empty()) {
+      o << ", \"all_ms\": [";
+      for (size_t j = 0; j < kv.second.all.size(); ++j) {
+        std::snprintf(buf, sizeof(buf), "%s%.6g", j ? ", " : "", kv.second.all[j]);
+        o << buf;
+      }
+      o << "]";
+    }
+    o << (++i < T.entries.size() ? "},\n" : "}\n");
   }
   o << "  ]\n}\n";
   return o.str();
@@ -114,7 +125,7 @@ void tune_load_json(const std::string& text) {
                               &knob, name, &a, &b, &c, &d, &v, &ms, &md);
     HPS_REQUIRE(n == 9 && knob >= 0 && knob < TUNE_NKNOBS && v >= 0,
                 "malformed tuning cache entry: " + line);
-    got.push_back({Key{knob, a, b, c, d}, Entry{v, ms, md}});
+    got.push_back({Key{knob, a, b, c, d}, Entry{v, ms, md, {}}});
   }
   Table& T = table();
   std::lock_guard<std::mutex> lk(T.mu);
@@ -231,17 +242,26 @@ void tune_gemm(const GemmShape& g, hipStream_t s, Timer& tm) {
   for (int i = 0; i < g.count; ++i)
     hd[i] = GemmDesc{A + sa * i, B + sb * i, C + sc * i, nullptr, g.M, g.N, g.K, g.K, g.N, g.N, 0, 1.0};
   GemmDesc* dd = mem.upload(hd, s);
-  double best = 1e300, tdef = 0;
+  // Every variant once to load its code, then three rounds that time each
+  // variant in turn (the best of its three), so a clock that drifts during
+  // the search (power and heat under sustained MFMA load) favours none.
+  std::vector<double> tv(GEMM_VARIANTS, 1e300);
+  for (int v = 0; v < GEMM_VARIANTS; ++v) grouped_gemm_v(dd, hd, s, v, GEMM_F64);
+  for (int round = 0; round < 3; ++round)
+    for (int v = 0; v < GEMM_VARIANTS; ++v) {
+      tm.start();
+      grouped_gemm_v(dd, hd, s, v, GEMM_F64);
+      tv[v] = std::min(tv[v], tm.stop());
+    }
+  double best = 1e300;
   int bv = 0;
-  for (int v = 0; v < GEMM_VARIANTS; ++v) {
-    const double t = best_of(tm, 3, [&] { grouped_gemm_v(dd, hd, s, v, GEMM_F64); });
-    if (v == 0) tdef = t;
-    if (t < best) {
-      best = t;
+  for (int v = 0; v < GEMM_VARIANTS; ++v)
+    if (tv[v] < best) {
+      best = tv[v];
       bv = v;
     }
-  }
-  tune_put(TUNE_GEMM, a, b, c, d, bv, best, tdef);
+  const double tdef = tv[0];
+  tune_put(TUNE_GEMM, a, b, c, d, bv, best, tdef, tv);
 }
 
 void tune_gj(const GjShape& g, hipStream_t s, Timer& tm) {

@@ -107,6 +107,9 @@ def test_autotune_then_build_matches_oracle(H, gpu, tmp_path):
                   for e in entries))
     assert names == {"leaf", "gemm", "gj"} and sec > 0
     assert all(e["ms"] <= e["default_ms"] * 1.0001 for e in entries)
+    # GEMM buckets list every tile's time, the chosen one the fastest.
+    for e in (e for e in entries if e["name"] == "gemm"):
+        assert len(e["all_ms"]) == 8 and e["ms"] == pytest.approx(min(e["all_ms"]), rel=1e-5)
     # A second run finds every bucket already tuned.
     assert H.autotune(shapes) < sec
     # Reloading the cache restores the same table.
