@@ -270,3 +270,33 @@ def manufactured_body(nleaf=(3, 2), p=12, q=10, seed=12) -> Problem:
 
 def rhs_fields(seeds: Sequence[int]) -> List[FourierField]:
     return [field_from_seed(int(s)) for s in seeds]
+
+
+def hbs_factors(seed: int, L: int, m: int, k: int) -> dict:
+    """Seeded random factors of an HBS matrix of m 2^L rows and rank k, in the blocks
+    of the library's factor buffer: D [2^L, m, m], U [2^L, m, k], Vt [2^L, k, m],
+    Up[l] [2^l, 2k, k] and Vtp[l] [2^l, k, 2k] for l = 1 .. L-1, B[l] [2^l, 2k, 2k]
+    for l = 0 .. L-1 (diagonal k x k blocks zero).
+
+    Recipe: D = m I + N(0, 1); basis entries N(0, 1/rows); each row basis is the
+    column basis plus a quarter of an independent draw of the same scale, so the
+    k x k products V* D^-1 U stay well away from singular; the children's
+    interaction blocks N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    nl = 1 << L
+    D = m * np.eye(m)[None] + rng.standard_normal((nl, m, m))
+    U = rng.standard_normal((nl, m, k)) / np.sqrt(m)
+    Vt = np.ascontiguousarray(
+        (U + 0.25 * rng.standard_normal((nl, m, k)) / np.sqrt(m)).transpose(0, 2, 1))
+    Up, Vtp, B = {}, {}, {}
+    for l in range(L - 1, 0, -1):
+        Up[l] = rng.standard_normal((1 << l, 2 * k, k)) / np.sqrt(2 * k)
+        Vtp[l] = np.ascontiguousarray(
+            (Up[l] + 0.25 * rng.standard_normal((1 << l, 2 * k, k)) / np.sqrt(2 * k))
+            .transpose(0, 2, 1))
+    for l in range(L - 1, -1, -1):
+        b = rng.standard_normal((1 << l, 2 * k, 2 * k))
+        b[:, :k, :k] = 0.0
+        b[:, k:, k:] = 0.0
+        B[l] = b
+    return dict(D=D, U=U, Vt=Vt, Up=Up, Vtp=Vtp, B=B)

@@ -41,3 +41,19 @@ def library_inputs(pr: hi.Problem, nleaf=None):
     ids = H.boundary_ids(nleaf, pr.q)
     f = pr.bc_at(gxy[ids])
     return C, f
+
+
+def hbs_oracle_factors(fac: dict, L: int, m: int, k: int) -> dict:
+    """The generator's HBS blocks (library layout: V stored as V*) as the oracle's dict."""
+    F = dict(L=L, m=m, M=m << L, D=[fac["D"][j] for j in range(1 << L)], U={}, V={}, B={})
+    for j in range(1 << L):
+        F["U"][(L, j)] = fac["U"][j]
+        F["V"][(L, j)] = fac["Vt"][j].T
+    for l in range(1, L):
+        for j in range(1 << l):
+            F["U"][(l, j)] = fac["Up"][l][j]
+            F["V"][(l, j)] = fac["Vtp"][l][j].T
+    for l in range(L):
+        for j in range(1 << l):
+            F["B"][(l, j)] = fac["B"][l][j]
+    return F
