@@ -350,6 +350,53 @@ hps_status hps_batched_solve(const double* M, const double* B, int n, int m, int
 hps_status hps_batched_gemm(const double* A, const double* B, double* C, int Mr, int Nc, int K,
                             int nprob, double alpha, int prec, void* stream);
 
+/* ---- HBS matrices (sections 6-7) -----------------------------------------
+   An HBS matrix H of M = m 2^L rows on the uniform binary tree of section 6.3:
+   node (l, j), 0 <= j < 2^l, owns rows and columns [j M/2^l, (j+1) M/2^l); its
+   children are (l+1, 2j) and (l+1, 2j+1).  One rank k at every node
+   (1 <= k <= m).  Device buffers of doubles, every block row-major and
+   contiguous, the blocks of one level in node order.
+
+   Factors (section 6.4, the factor table there), in this order:
+     D    2^L blocks m x m     leaf diagonal blocks H(I_j, I_j)   (eq:def5)
+     U    2^L blocks m x k     leaf column bases
+     Vt   2^L blocks k x m     leaf row bases, as V* (transposed)
+     for l = L-1 down to 1:
+       U_l  2^l blocks 2k x k  parent column bases (eq:def4)
+       Vt_l 2^l blocks k x 2k  parent row bases, as V*
+     for l = L-1 down to 0:
+       B_l  2^l blocks 2k x 2k interaction of the node's children (eq:def6);
+                               the two diagonal k x k blocks are not read.
+   so that H = U(L) Ht(L) V(L)* + D(L) with Ht(l+1) = U(l) Ht(l) V(l)* + B(l)
+   and Ht(1) = B(0) (eq:tele1 - eq:tele3).
+
+   Inverse factors (Algorithm 3), in this order:
+     for l = L down to 1 (n = m at the leaves, 2k above):
+       E_l  2^l blocks n x k;  F_l  2^l blocks k x n (as F*);  G_l  2^l blocks n x n
+     G_0  one block 2k x 2k (the root's).
+
+   Vectors x, y: M x nrhs row-major.  All pointers are device memory owned by
+   the caller; the calls allocate their scratch (the library's pool), run on
+   `stream` and return after it has finished.  Sizes outside the limits
+   (L in [1, 20], 1 <= k <= m, m and 2k at most 3072) give HPS_EINVAL. */
+
+/* Numbers of doubles in the factor and inverse buffers (either may be null). */
+hps_status hps_hbs_sizes(int L, int m, int k, size_t* n_factors, size_t* n_inverse);
+/* y = H x through the telescoping factorization (eq:tele1 - eq:tele3): x-hat up
+   the tree through V*, the children's blocks of each B, y-hat down through U,
+   and D at the leaves.  y must not overlap x. */
+hps_status hps_hbs_apply(int L, int m, int k, const double* factors, const double* x, double* y,
+                         int nrhs, void* stream);
+/* Algorithm 3: the factors {E, F, G} of H^-1 (section 7.1; the blocks it
+   inverts use Gauss-Jordan with partial pivoting).  A zero or non-finite
+   pivot gives HPS_ESINGULAR (inverse is then unspecified). */
+hps_status hps_hbs_invert(int L, int m, int k, const double* factors, double* inverse,
+                          void* stream);
+/* Algorithm 4: y = H^-1 x from the factors of hps_hbs_invert.  E multiplies
+   the parent's y-hat in the downward and leaf steps.  y must not overlap x. */
+hps_status hps_hbs_solve(int L, int m, int k, const double* inverse, const double* x, double* y,
+                         int nrhs, void* stream);
+
 /* ---- host-side planner queries (no device work; used by CPU tests) ------ */
 
 /* Coefficient-independent leaf tables for a hx-by-hy leaf (section 3.2),

@@ -22,7 +22,8 @@ __all__ = ["HpsError", "HPS_FP64", "HPS_MIXED_SPLIT32", "HPS_MIXED_BF16X6", "HPS
            "HPS_ESINGULAR", "HPS_ENOTCONV", "Operator", "cheb_nodes", "gauss_nodes_grid",
            "boundary_ids", "leaf_dtn", "build_solution_operator", "build_batch", "solve_batch",
            "leaf_tables", "plan_box", "version", "lib", "batched_solve", "batched_gemm",
-           "Surrogate"]
+           "Surrogate", "hbs_sizes", "hbs_pack", "hbs_apply", "hbs_invert", "hbs_solve",
+           "hbs_unpack_inverse"]
 
 
 def version() -> str:
@@ -162,6 +163,81 @@ def batched_gemm(A, B, C, alpha: float = 1.0, split32: bool = False, bf16x6: boo
     check(lib.hps_batched_gemm(_ptr(A), _ptr(B), _ptr(C), Mr, Nc, K, nprob, alpha, prec,
                                _stream(A)))
     return C
+
+
+# ---- HBS matrices (sections 6-7) -------------------------------------------
+def hbs_sizes(L: int, m: int, k: int):
+    """(doubles in the factor buffer, doubles in the inverse buffer) of an HBS matrix of
+    m 2^L rows and rank k (layouts in include/hps.h)."""
+    nf, ni = C.c_size_t(), C.c_size_t()
+    check(lib.hps_hbs_sizes(L, m, k, C.byref(nf), C.byref(ni)))
+    return nf.value, ni.value
+
+
+def hbs_pack(D, U, Vt, Up, Vtp, B):
+    """The factor buffer (a 1-D array or tensor) from its blocks: D [2^L, m, m],
+    U [2^L, m, k], Vt [2^L, k, m], Up[l] [2^l, 2k, k] and Vtp[l] [2^l, k, 2k] for
+    l = 1 .. L-1 (dicts or lists indexed by l), B[l] [2^l, 2k, 2k] for l = 0 .. L-1."""
+    L = int(D.shape[0]).bit_length() - 1
+    parts = [D, U, Vt]
+    for l in range(L - 1, 0, -1):
+        parts += [Up[l], Vtp[l]]
+    parts += [B[l] for l in range(L - 1, -1, -1)]
+    if _is_torch(D):
+        import torch
+        return torch.cat([p.reshape(-1) for p in parts]).contiguous()
+    return np.concatenate([np.asarray(p, dtype=np.float64).reshape(-1) for p in parts])
+
+
+def hbs_unpack_inverse(inv, L: int, m: int, k: int):
+    """Views of the inverse buffer: dicts E, Fs (F*), G by level (G[0] the root's block)."""
+    E, Fs, G = {}, {}, {}
+    o = 0
+    for l in range(L, 0, -1):
+        n = m if l == L else 2 * k
+        nn = 1 << l
+        E[l] = inv[o:o + nn * n * k].reshape(nn, n, k)
+        o += nn * n * k
+        Fs[l] = inv[o:o + nn * k * n].reshape(nn, k, n)
+        o += nn * k * n
+        G[l] = inv[o:o + nn * n * n].reshape(nn, n, n)
+        o += nn * n * n
+    G[0] = inv[o:o + 4 * k * k].reshape(2 * k, 2 * k)
+    return E, Fs, G
+
+
+def hbs_apply(factors, x, L: int, m: int, k: int, y=None):
+    """y = H x for the HBS matrix in ``factors`` (device tensors; x, y [m 2^L, nrhs])."""
+    import torch
+    assert _dev(factors) and _dev(x)
+    x = _f64(x)
+    nrhs = x.shape[1] if x.dim() == 2 else 1
+    if y is None:
+        y = torch.empty_like(x)
+    check(lib.hps_hbs_apply(L, m, k, _ptr(factors), _ptr(x), _ptr(y), nrhs, _stream(x)))
+    return y
+
+
+def hbs_invert(factors, L: int, m: int, k: int, inverse=None):
+    """Algorithm 3 on the device: the inverse factors {E, F, G} as one buffer."""
+    import torch
+    assert _dev(factors)
+    if inverse is None:
+        inverse = torch.empty(hbs_sizes(L, m, k)[1], dtype=torch.float64, device=factors.device)
+    check(lib.hps_hbs_invert(L, m, k, _ptr(factors), _ptr(inverse), _stream(factors)))
+    return inverse
+
+
+def hbs_solve(inverse, x, L: int, m: int, k: int, y=None):
+    """Algorithm 4 on the device: y = H^-1 x from the buffer of ``hbs_invert``."""
+    import torch
+    assert _dev(inverse) and _dev(x)
+    x = _f64(x)
+    nrhs = x.shape[1] if x.dim() == 2 else 1
+    if y is None:
+        y = torch.empty_like(x)
+    check(lib.hps_hbs_solve(L, m, k, _ptr(inverse), _ptr(x), _ptr(y), nrhs, _stream(x)))
+    return y
 
 
 def tune_set(knob: str, value: int) -> None:

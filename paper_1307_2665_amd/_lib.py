@@ -88,6 +88,10 @@ SIGNATURES = {
     "hps_leaf_tables": [I, I, D, D, P, P, P, P, P, P, P, P],
     "hps_batched_solve": [P, P, I, I, I, P, P],
     "hps_batched_gemm": [P, P, P, I, I, I, I, D, I, P],
+    "hps_hbs_sizes": [I, I, I, P, P],
+    "hps_hbs_apply": [I, I, I, P, P, P, I, P],
+    "hps_hbs_invert": [I, I, I, P, P, P],
+    "hps_hbs_solve": [I, I, I, P, P, P, I, P],
     "hps_plan_box": [P, I, I, P, P, P, P, P, P, P, IP],
     "hps_tune_set": [C.c_char_p, I],
     "hps_autotune": [C.POINTER(Problem), I, P, C.POINTER(D)],

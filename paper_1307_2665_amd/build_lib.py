@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhps.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["plan.cpp", "pool.cpp", "solver.cpp", "api.cpp", "prof.cpp", "tune.cpp", "dense.hip", "gj.hip", "ops.hip", "leaf.hip", "surrogate.hip", "noalloc.hip"]
+SOURCES = ["plan.cpp", "pool.cpp", "solver.cpp", "api.cpp", "prof.cpp", "tune.cpp", "dense.hip", "gj.hip", "ops.hip", "leaf.hip", "surrogate.hip", "noalloc.hip", "hbs.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ARCH = os.environ.get("HPS_OFFLOAD_ARCH", "gfx950")

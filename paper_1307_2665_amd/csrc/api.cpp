@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "dense.h"
+#include "hbs.h"
 #include "leaf.h"
 #include "ops.h"
 #include "solver.h"
@@ -489,6 +490,44 @@ hps_status hps_batched_gemm(const double* A, const double* B, double* C, int Mr,
     hps::GemmDesc* dd = tmp.upload(hd, s);
     hps::grouped_gemm(dd, hd, s, prec);
     HPS_HIP(hipStreamSynchronize(s));
+  });
+}
+
+hps_status hps_hbs_sizes(int L, int m, int k, size_t* n_factors, size_t* n_inverse) {
+  return guard([&] {
+    hps::hbs_check(L, m, k);
+    const hps::HbsLayout lo(L, m, k);
+    if (n_factors) *n_factors = lo.nfac;
+    if (n_inverse) *n_inverse = lo.ninv;
+  });
+}
+
+hps_status hps_hbs_apply(int L, int m, int k, const double* factors, const double* x, double* y,
+                         int nrhs, void* stream) {
+  return guard([&] {
+    hps::hbs_check(L, m, k);
+    HPS_REQUIRE(factors && x && y && nrhs >= 1, "bad arguments");
+    HPS_REQUIRE(x != y, "y must not overlap x");
+    hps::hbs_apply(hps::HbsLayout(L, m, k), factors, x, y, nrhs, (hipStream_t)stream);
+  });
+}
+
+hps_status hps_hbs_invert(int L, int m, int k, const double* factors, double* inverse,
+                          void* stream) {
+  return guard([&] {
+    hps::hbs_check(L, m, k);
+    HPS_REQUIRE(factors && inverse, "bad arguments");
+    hps::hbs_invert(hps::HbsLayout(L, m, k), factors, inverse, (hipStream_t)stream);
+  });
+}
+
+hps_status hps_hbs_solve(int L, int m, int k, const double* inverse, const double* x, double* y,
+                         int nrhs, void* stream) {
+  return guard([&] {
+    hps::hbs_check(L, m, k);
+    HPS_REQUIRE(inverse && x && y && nrhs >= 1, "bad arguments");
+    HPS_REQUIRE(x != y, "y must not overlap x");
+    hps::hbs_solve(hps::HbsLayout(L, m, k), inverse, x, y, nrhs, (hipStream_t)stream);
   });
 }
 
