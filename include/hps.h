@@ -397,6 +397,26 @@ hps_status hps_hbs_invert(int L, int m, int k, const double* factors, double* in
 hps_status hps_hbs_solve(int L, int m, int k, const double* inverse, const double* x, double* y,
                          int nrhs, void* stream);
 
+/* Brute-force compression (Remark 8.2) of the dense M x M matrix H (device,
+   row stride ldh >= M) into the factor layout above with rank k, from random
+   samples that the caller draws: omega [M][k] and psit [k][M], i.i.d.
+   standard normal (passed in so that a run can be repeated).  Bases are
+   orthonormal and nested: each node's samples of its off-diagonal block row
+   (H Omega less its diagonal block's part) and column (Psi* H likewise) are
+   reduced to the children's bases at a parent (eq:def3) and orthonormalized
+   by Gram-Schmidt with re-orthogonalization; B holds the children's
+   projected interaction blocks (eq:def6).  The error is that of rank-k
+   randomized range finding on every block row and column: choose k above
+   the numerical rank (section 8 reports 10 to 80 at 1e-10 for
+   non-oscillatory problems).  Limits: k <= 90 and m k <= 16384, else
+   HPS_EINVAL. */
+hps_status hps_hbs_compress(int L, int m, int k, const double* H, int ldh, const double* omega,
+                            const double* psit, double* factors, void* stream);
+/* The same for the root DtN T^1 of a built operator (M = n_bdry, m = n_bdry / 2^L;
+   2^L must divide n_bdry): the HBS form that makes T_apply O(M k). */
+hps_status hps_root_dtn_compress(const hps_op* op, int L, int k, const double* omega,
+                                 const double* psit, double* factors, void* stream);
+
 /* ---- host-side planner queries (no device work; used by CPU tests) ------ */
 
 /* Coefficient-independent leaf tables for a hx-by-hy leaf (section 3.2),

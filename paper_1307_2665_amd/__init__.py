@@ -23,7 +23,7 @@ __all__ = ["HpsError", "HPS_FP64", "HPS_MIXED_SPLIT32", "HPS_MIXED_BF16X6", "HPS
            "boundary_ids", "leaf_dtn", "build_solution_operator", "build_batch", "solve_batch",
            "leaf_tables", "plan_box", "version", "lib", "batched_solve", "batched_gemm",
            "Surrogate", "hbs_sizes", "hbs_pack", "hbs_apply", "hbs_invert", "hbs_solve",
-           "hbs_unpack_inverse"]
+           "hbs_unpack_inverse", "hbs_compress"]
 
 
 def version() -> str:
@@ -216,6 +216,33 @@ def hbs_apply(factors, x, L: int, m: int, k: int, y=None):
         y = torch.empty_like(x)
     check(lib.hps_hbs_apply(L, m, k, _ptr(factors), _ptr(x), _ptr(y), nrhs, _stream(x)))
     return y
+
+
+def hbs_compress(H, L: int, k: int, omega, psit, factors=None):
+    """Brute-force compression of a dense device matrix (or of an ``Operator``'s root DtN)
+    into HBS factors of rank k; omega [M, k] and psit [k, M] are the caller's standard
+    normal samples (device tensors)."""
+    import torch
+    assert _dev(omega) and _dev(psit)
+    omega, psit = _f64(omega), _f64(psit)
+    if isinstance(H, Operator):
+        M = H.n_bdry
+        dev = omega.device
+    else:
+        assert _dev(H)
+        H = _f64(H)
+        M = H.shape[0]
+        dev = H.device
+    m = M >> L
+    if factors is None:
+        factors = torch.empty(hbs_sizes(L, m, k)[0], dtype=torch.float64, device=dev)
+    if isinstance(H, Operator):
+        check(lib.hps_root_dtn_compress(H._h, L, k, _ptr(omega), _ptr(psit), _ptr(factors),
+                                        _stream(omega)))
+    else:
+        check(lib.hps_hbs_compress(L, m, k, _ptr(H), H.shape[1], _ptr(omega), _ptr(psit),
+                                   _ptr(factors), _stream(H)))
+    return factors
 
 
 def hbs_invert(factors, L: int, m: int, k: int, inverse=None):

@@ -89,6 +89,8 @@ SIGNATURES = {
     "hps_batched_solve": [P, P, I, I, I, P, P],
     "hps_batched_gemm": [P, P, P, I, I, I, I, D, I, P],
     "hps_hbs_sizes": [I, I, I, P, P],
+    "hps_hbs_compress": [I, I, I, P, I, P, P, P, P],
+    "hps_root_dtn_compress": [P, I, I, P, P, P, P],
     "hps_hbs_apply": [I, I, I, P, P, P, I, P],
     "hps_hbs_invert": [I, I, I, P, P, P],
     "hps_hbs_solve": [I, I, I, P, P, P, I, P],

@@ -531,6 +531,32 @@ hps_status hps_hbs_solve(int L, int m, int k, const double* inverse, const doubl
   });
 }
 
+hps_status hps_hbs_compress(int L, int m, int k, const double* H, int ldh, const double* omega,
+                            const double* psit, double* factors, void* stream) {
+  return guard([&] {
+    hps::hbs_check(L, m, k);
+    HPS_REQUIRE(k <= hps::hbs_max_compress_rank(m), "rank too large to compress (k <= 90, m k <= 16384)");
+    HPS_REQUIRE(H && omega && psit && factors, "bad arguments");
+    HPS_REQUIRE(ldh >= (m << L), "ldh smaller than the matrix");
+    hps::hbs_compress(hps::HbsLayout(L, m, k), H, ldh, omega, psit, factors, (hipStream_t)stream);
+  });
+}
+
+hps_status hps_root_dtn_compress(const hps_op* op, int L, int k, const double* omega,
+                                 const double* psit, double* factors, void* stream) {
+  return guard([&] {
+    HPS_REQUIRE(op && omega && psit && factors, "bad arguments");
+    HPS_REQUIRE(op->opt.root_dtn, "operator was built without the root DtN");
+    HPS_REQUIRE(L >= 1 && L <= 20 && op->n_bdry % (1 << L) == 0,
+                "2^L must divide the number of boundary nodes");
+    const int m = op->n_bdry >> L;
+    hps::hbs_check(L, m, k);
+    HPS_REQUIRE(k <= hps::hbs_max_compress_rank(m), "rank too large to compress (k <= 90, m k <= 16384)");
+    hps::hbs_compress(hps::HbsLayout(L, m, k), op->rootT, op->n_bdry, omega, psit, factors,
+                      (hipStream_t)stream);
+  });
+}
+
 hps_status hps_bgj_fallbacks(long long* count) {
   return guard([&] {
     HPS_REQUIRE(count != nullptr, "null count");

@@ -35,4 +35,12 @@ void hbs_invert(const HbsLayout& lo, const double* fac, double* inv, hipStream_t
 void hbs_solve(const HbsLayout& lo, const double* inv, const double* x, double* y, int nrhs,
                hipStream_t s);
 
+// Brute-force compression of the dense M x M matrix H (row stride ldh, device)
+// into factors of rank k from the caller's random samples omega (M x k) and
+// psit (k x M).  k <= 90 and m k <= 16384 (the bases are orthonormalized in
+// LDS).
+void hbs_compress(const HbsLayout& lo, const double* H, int ldh, const double* omega,
+                  const double* psit, double* fac, hipStream_t s);
+int hbs_max_compress_rank(int m);
+
 }  // namespace hps

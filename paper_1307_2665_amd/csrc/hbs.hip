@@ -58,6 +58,8 @@ HbsLayout::HbsLayout(int L_, int m_, int k_) : L(L_), m(m_), k(k_) {
   ninv = o;
 }
 
+int hbs_max_compress_rank(int m) { return std::min(90, 16384 / std::max(m, 1)); }
+
 void hbs_check(int L, int m, int k) {
   HPS_REQUIRE(L >= 1 && L <= 20, "HBS levels must be in [1, 20]");
   HPS_REQUIRE(k >= 1 && m >= k, "HBS sizes need 1 <= k <= m");
@@ -68,7 +70,7 @@ void hbs_check(int L, int m, int k) {
 namespace {
 
 // One block copy of a batch: dst[r][c] = src[r][c] (mode 0), the identity
-// (mode 1) or zero (mode 2), for r < rows, c < cols.
+// (mode 1), zero (mode 2) or src[c][r] (mode 3), for r < rows, c < cols.
 struct CopyDesc {
   const double* src;
   double* dst;
@@ -83,6 +85,8 @@ __global__ void __launch_bounds__(256) k_block_copy(const CopyDesc* __restrict__
     double v;
     if (d.mode == 0)
       v = d.src[(size_t)r * d.lds + c];
+    else if (d.mode == 3)
+      v = d.src[(size_t)c * d.lds + r];
     else
       v = (d.mode == 1 && r == c) ? 1.0 : 0.0;
     d.dst[(size_t)r * d.ldd + c] = v;
@@ -137,6 +141,92 @@ struct Hats {
     }
   }
 };
+
+// Orthonormalization of `cols` vectors of length `rows`, element i of vector
+// c at A[i rs + c cs], by classical Gram-Schmidt with one re-orthogonalization
+// pass (CGS2), one workgroup per descriptor, the vectors staged in LDS.  A
+// vector that loses all but 1e-13 of its norm to the earlier ones (a sample
+// of rank below `cols`) is replaced by a unit vector e_i orthogonalized the
+// same way, trying i = c, c + 1, ... until one keeps over half of 1/rows of
+// its squared norm, so the basis keeps full rank.
+struct OrthDesc {
+  double* A;
+  int rows, cols, rs, cs;
+};
+constexpr int ORTH_LDS = 16384;  // doubles: rows * cols limit
+
+__global__ void __launch_bounds__(256) k_orth(const OrthDesc* __restrict__ descs) {
+  __shared__ double Q[ORTH_LDS];
+  __shared__ double r[256];
+  __shared__ double red[4];
+  const OrthDesc d = descs[blockIdx.x];
+  const int n = d.rows, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int e = tid; e < n * d.cols; e += 256) {
+    const int c = e / n, i = e % n;
+    Q[e] = d.A[(size_t)i * d.rs + (size_t)c * d.cs];
+  }
+  __syncthreads();
+  auto norm2 = [&](const double* v) {
+    double a = 0.0;
+    for (int i = tid; i < n; i += 256) a += v[i] * v[i];
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+    if (lane == 0) red[w] = a;
+    __syncthreads();
+    const double t = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+    return t;
+  };
+  // v -= Q[0..c) (Q[0..c)^T v), twice.
+  auto project_out = [&](double* v, int c) {
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int q = w; q < c; q += 4) {
+        double a = 0.0;
+        for (int i = lane; i < n; i += 64) a += Q[q * n + i] * v[i];
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+        if (lane == 0) r[q] = a;
+      }
+      __syncthreads();
+      for (int i = tid; i < n; i += 256) {
+        double a = v[i];
+        for (int q = 0; q < c; ++q) a -= r[q] * Q[q * n + i];
+        v[i] = a;
+      }
+      __syncthreads();
+    }
+  };
+  for (int c = 0; c < d.cols; ++c) {
+    double* v = Q + c * n;
+    const double n0 = norm2(v);
+    project_out(v, c);
+    double nv = norm2(v);
+    // Some e_i keeps at least (n - c) / n of its squared norm outside the
+    // span of the c earlier vectors, so the search ends.
+    bool ok = nv > 1e-26 * n0 && nv > 0.0;
+    for (int t = 0; t < n && !ok; ++t) {
+      const int e = (c + t) % n;
+      for (int i = tid; i < n; i += 256) v[i] = i == e ? 1.0 : 0.0;
+      __syncthreads();
+      project_out(v, c);
+      nv = norm2(v);
+      ok = nv > 0.5 / n;
+    }
+    const double inv = 1.0 / sqrt(nv);
+    for (int i = tid; i < n; i += 256) v[i] *= inv;
+    __syncthreads();
+  }
+  for (int e = tid; e < n * d.cols; e += 256) {
+    const int c = e / n, i = e % n;
+    d.A[(size_t)i * d.rs + (size_t)c * d.cs] = Q[e];
+  }
+}
+
+void orthonormalize(DeviceMem& mem, const std::vector<OrthDesc>& h, hipStream_t s) {
+  if (h.empty()) return;
+  for (auto& d : h) HPS_REQUIRE(d.rows >= d.cols && d.rows * d.cols <= ORTH_LDS, "basis too large");
+  const OrthDesc* dd = mem.upload(h, s);
+  hipLaunchKernelGGL(k_orth, dim3((unsigned)h.size()), dim3(256), 0, s, dd);
+  HPS_HIP(hipGetLastError());
+}
 
 void solve_batch(DeviceMem& mem, const std::vector<SolveDesc>& h, int* st, hipStream_t s) {
   const SolveDesc* dd = mem.upload(h, s);
@@ -361,6 +451,149 @@ void hbs_solve(const HbsLayout& lo, const double* inv, const double* x, double* 
                    y + (size_t)j * m * nrhs, nrhs, m, nrhs, k, false));
   P.launch(g);
   P.run(mem, s);
+  HPS_HIP(hipStreamSynchronize(s));
+}
+
+// Brute-force compression (Remark 8.2) of a dense matrix into HBS factors of
+// one rank k, with orthonormal nested bases taken from random samples
+// Y = H Omega and Z* = Psi* H.  Level by level from the leaves: the samples
+// of each node's off-diagonal block row and column are Y and Z* less the
+// node's diagonal block times its part of Omega or Psi*; at a leaf they are
+// orthonormalized into U and V*; at a parent they are first reduced to the
+// children's bases (eq:def3) and then orthonormalized.  The bases in the
+// original indices (Ubig* and Vbig, as k x M and M x k) follow from the
+// children's; the children's interaction blocks of every parent are
+// Ubig*(I_1) H(I_1, I_2) Vbig(I_2) and the reverse (eq:def6).
+void hbs_compress(const HbsLayout& lo, const double* H, int ldh, const double* omega,
+                  const double* psit, double* fac, hipStream_t s) {
+  const int L = lo.L, m = lo.m, k = lo.k, k2 = 2 * k;
+  const long long M = lo.M();
+  DeviceMem mem;
+  double* Y = mem.alloc<double>((size_t)M * k);
+  double* ZT = mem.alloc<double>((size_t)M * k);
+  double* R = mem.alloc<double>((size_t)M * k);
+  double* RT = mem.alloc<double>((size_t)M * k);
+  double* UbT[2] = {mem.alloc<double>((size_t)M * k), mem.alloc<double>((size_t)M * k)};
+  double* Vb[2] = {mem.alloc<double>((size_t)M * k), mem.alloc<double>((size_t)M * k)};
+  double* T1 = mem.alloc<double>((size_t)M * k);
+  double* Ut = mem.alloc<double>(((size_t)1 << L) * k * k);
+  double* Vs = mem.alloc<double>(((size_t)1 << L) * k * k);
+  {
+    GemmPlan P;
+    P.launch({gd(H, ldh, omega, k, Y, k, (int)M, k, (int)M, true)});
+    P.launch({gd(psit, (int)M, H, ldh, ZT, (int)M, k, (int)M, (int)M, true)});
+    P.run(mem, s);
+  }
+  std::vector<CopyDesc> cp;
+  for (int j = 0; j < (1 << L); ++j)
+    cp.push_back({H + (size_t)j * m * ldh + (size_t)j * m, fac + lo.D + (size_t)j * m * m, ldh, m,
+                  m, m, 0, 0});
+  block_copies(mem, cp, s);
+  int cur = 0;  // UbT[cur], Vb[cur]: the bases of level l + 1
+  for (int l = L; l >= 1; --l) {
+    const int nn = 1 << l, nl = (int)(M >> l), nc = nl / 2;
+    double* ubt = UbT[cur ^ 1];
+    double* vb = Vb[cur ^ 1];
+    const double* ubt_c = UbT[cur];
+    const double* vb_c = Vb[cur];
+    {
+      GemmPlan P;
+      std::vector<GemmDesc> g1, g2;
+      for (int j = 0; j < nn; ++j) {
+        const size_t i0 = (size_t)j * nl;
+        const double* Hjj = H + i0 * ldh + i0;
+        g1.push_back(gd(Hjj, ldh, omega + i0 * k, k, R + i0 * k, k, nl, k, nl, false, -1.0,
+                        Y + i0 * k, k));
+        g2.push_back(gd(psit + i0, (int)M, Hjj, ldh, RT + i0, (int)M, k, nl, nl, false, -1.0,
+                        ZT + i0, (int)M));
+      }
+      P.launch(g1);
+      P.launch(g2);
+      P.run(mem, s);
+    }
+    std::vector<OrthDesc> od;
+    cp.clear();
+    if (l == L) {
+      for (int j = 0; j < nn; ++j) {
+        double* Uj = fac + lo.U + (size_t)j * m * k;
+        double* Vtj = fac + lo.Vt + (size_t)j * k * m;
+        cp.push_back({R + (size_t)j * m * k, Uj, k, k, m, k, 0, 0});
+        cp.push_back({RT + (size_t)j * m, Vtj, (int)M, m, k, m, 0, 0});
+        od.push_back({Uj, m, k, k, 1});
+        od.push_back({Vtj, m, k, 1, m});
+      }
+      block_copies(mem, cp, s);
+      orthonormalize(mem, od, s);
+      cp.clear();
+      for (int j = 0; j < nn; ++j) {
+        cp.push_back({fac + lo.U + (size_t)j * m * k, ubt + (size_t)j * m, k, (int)M, k, m, 3, 0});
+        cp.push_back({fac + lo.Vt + (size_t)j * k * m, vb + (size_t)j * m * k, m, k, m, k, 3, 0});
+      }
+      block_copies(mem, cp, s);
+    } else {
+      GemmPlan P;
+      std::vector<GemmDesc> gu, gv;
+      for (int j = 0; j < nn; ++j) {
+        double* Uj = fac + lo.Up[l] + (size_t)j * k2 * k;
+        double* Vtj = fac + lo.Vtp[l] + (size_t)j * k * k2;
+        for (int h = 0; h < 2; ++h) {
+          const size_t ic = (size_t)(2 * j + h) * nc;
+          gu.push_back(gd(ubt_c + ic, (int)M, R + ic * k, k, Uj + (size_t)h * k * k, k, k, k, nc,
+                          true));
+          gv.push_back(gd(RT + ic, (int)M, vb_c + ic * k, k, Vtj + (size_t)h * k, k2, k, k, nc,
+                          true));
+        }
+        od.push_back({Uj, k2, k, k, 1});
+        od.push_back({Vtj, k2, k, 1, k2});
+      }
+      P.launch(gu);
+      P.launch(gv);
+      P.run(mem, s);
+      orthonormalize(mem, od, s);
+      for (int j = 0; j < nn; ++j) {
+        cp.push_back({fac + lo.Up[l] + (size_t)j * k2 * k, Ut + (size_t)j * k * k2, k, k2, k, k2, 3, 0});
+        cp.push_back({fac + lo.Vtp[l] + (size_t)j * k * k2, Vs + (size_t)j * k2 * k, k2, k, k2, k, 3, 0});
+      }
+      block_copies(mem, cp, s);
+      GemmPlan Q;
+      std::vector<GemmDesc> bu, bv;
+      for (int j = 0; j < nn; ++j)
+        for (int h = 0; h < 2; ++h) {
+          const size_t ic = (size_t)(2 * j + h) * nc;
+          bu.push_back(gd(Ut + (size_t)j * k * k2 + (size_t)h * k, k2, ubt_c + ic, (int)M, ubt + ic,
+                          (int)M, k, nc, k, true));
+          bv.push_back(gd(vb_c + ic * k, k, Vs + (size_t)j * k2 * k + (size_t)h * k * k, k,
+                          vb + ic * k, k, nc, k, k, true));
+        }
+      Q.launch(bu);
+      Q.launch(bv);
+      Q.run(mem, s);
+    }
+    // The interaction blocks of the parents one level up: Ubig*(I_1) H(I_1, I_2) Vbig(I_2).
+    {
+      const int np = nn / 2;
+      GemmPlan P;
+      std::vector<GemmDesc> t1, tb;
+      cp.clear();
+      for (int j = 0; j < np; ++j) {
+        const size_t i1 = (size_t)(2 * j) * nl, i2 = i1 + nl;
+        double* Bj = fac + lo.B[l - 1] + (size_t)j * 4 * k * k;
+        double* T1a = T1 + i1 * k;
+        double* T1b = T1 + i2 * k;
+        t1.push_back(gd(H + i1 * ldh + i2, ldh, vb + i2 * k, k, T1a, k, nl, k, nl, true));
+        t1.push_back(gd(H + i2 * ldh + i1, ldh, vb + i1 * k, k, T1b, k, nl, k, nl, true));
+        tb.push_back(gd(ubt + i1, (int)M, T1a, k, Bj + k, k2, k, k, nl, true));
+        tb.push_back(gd(ubt + i2, (int)M, T1b, k, Bj + (size_t)k * k2, k2, k, k, nl, true));
+        cp.push_back({nullptr, Bj, 0, k2, k, k, 2, 0});
+        cp.push_back({nullptr, Bj + (size_t)k * k2 + k, 0, k2, k, k, 2, 0});
+      }
+      P.launch(t1);
+      P.launch(tb);
+      P.run(mem, s);
+      block_copies(mem, cp, s);
+    }
+    cur ^= 1;
+  }
   HPS_HIP(hipStreamSynchronize(s));
 }
 

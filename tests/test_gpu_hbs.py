@@ -81,3 +81,70 @@ def test_singular_leaf_block_is_reported(H, gpu):
     with pytest.raises(H.HpsError) as e:
         H.hbs_invert(torch.from_numpy(buf).to(gpu), L, m, k)
     assert e.value.status == H.HPS_ESINGULAR
+
+
+def _samples(gpu, M, k, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    om = torch.from_numpy(rng.standard_normal((M, k))).to(gpu)
+    pt = torch.from_numpy(rng.standard_normal((k, M))).to(gpu)
+    return om, pt
+
+
+def _semiseparable(M, r, seed):
+    rng = np.random.default_rng(seed)
+    u, v, p, q = (rng.standard_normal((M, r)) for _ in range(4))
+    return np.tril(u @ v.T, -1) + np.triu(p @ q.T, 1) + np.diag(10.0 + M * rng.random(M))
+
+
+@pytest.mark.parametrize("M,L,r,k", [(512, 3, 3, 8), (480, 4, 2, 10), (128, 1, 4, 12)])
+def test_compress_recovers_a_low_rank_structure(H, gpu, M, L, r, k):
+    """Off-diagonal block rows and columns of rank <= 2r <= k: the randomized
+    bases span them exactly, so the compressed matrix equals H to rounding;
+    bases are orthonormal, D is copied, and Algorithms 3 and 4 on the compressed
+    factors solve H y = x (LAPACK reference)."""
+    import torch
+    say(f"hbs compress M={M} L={L} r={r} k={k}")
+    Hm = _semiseparable(M, r, seed=M + k)
+    m = M >> L
+    om, pt = _samples(gpu, M, k, seed=k)
+    fac = H.hbs_compress(torch.from_numpy(Hm).to(gpu), L, k, om, pt)
+    x = np.random.default_rng(9).standard_normal((M, 2))
+    y = H.hbs_apply(fac, torch.from_numpy(x).to(gpu), L, m, k).cpu().numpy()
+    assert rel_err(y, Hm @ x) <= 1e-12
+    f = fac.cpu().numpy()
+    nl = 1 << L
+    D = f[:nl * m * m].reshape(nl, m, m)
+    U = f[nl * m * m:nl * m * (m + k)].reshape(nl, m, k)
+    Vt = f[nl * m * (m + k):nl * m * (m + 2 * k)].reshape(nl, k, m)
+    for j in range(nl):
+        assert np.array_equal(D[j], Hm[j * m:(j + 1) * m, j * m:(j + 1) * m])
+        assert np.abs(U[j].T @ U[j] - np.eye(k)).max() <= 1e-13
+        assert np.abs(Vt[j] @ Vt[j].T - np.eye(k)).max() <= 1e-13
+    inv = H.hbs_invert(fac, L, m, k)
+    ys = H.hbs_solve(inv, torch.from_numpy(x).to(gpu), L, m, k).cpu().numpy()
+    assert rel_err(ys, np.linalg.solve(Hm, x)) <= 1e-10
+
+
+def test_compress_root_dtn(H, gpu):
+    """The root DtN of a built operator in HBS form (Remark 8.2 at the root):
+    the compressed T_apply matches the dense root DtN to within a small multiple
+    of the error of the best bases of the same rank (oracle: truncated SVDs)."""
+    import torch
+    pr = hi.laplace_log(nleaf=(16, 16), p=12, q=10)
+    from .helpers import library_inputs
+    C, f = library_inputs(pr)
+    op = H.build_solution_operator(torch.from_numpy(C).to(gpu), pr.box, pr.nleaf, pr.p, pr.q)
+    T = op.export_root_dtn()
+    M, L, k = T.shape[0], 3, 60
+    m = M >> L
+    say(f"hbs root DtN M={M} L={L} k={k}")
+    om, pt = _samples(gpu, M, k, seed=5)
+    fac = H.hbs_compress(op, L, k, om, pt)
+    x = np.random.default_rng(10).standard_normal((M, 3))
+    y = H.hbs_apply(fac, torch.from_numpy(x).to(gpu), L, m, k).cpu().numpy()
+    err = rel_err(y, T @ x)
+    best = hbs.compress(T, L, rank=k)
+    err_svd = rel_err(np.stack([hbs.apply(best, x[:, c]) for c in range(3)], axis=1), T @ x)
+    say(f"  randomized {err:.2e}, truncated SVD {err_svd:.2e}")
+    assert err <= max(100 * err_svd, 1e-12) and err <= 1e-8
