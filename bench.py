@@ -80,13 +80,14 @@ def parse():
                          "splits (the last two with refinement against the FP64 leaf DtNs); for\n"
                          "the sweep, which form's time is the line's value (fp64 or surrogate)")
     ap.add_argument("--workload", choices=["convdiff", "helmholtz", "batch", "sweep", "post",
-                                           "body"],
+                                           "body", "hbs"],
                     default="sweep",
                     help="sweep (default): 256x256 p12 coefficient fields, plain FP64 leaves and "
                          "the learned surrogate; convdiff: 64x64 p16, one right-hand side; "
                          "helmholtz: 128x128 p16, 64 right-hand sides, FP64 and the mixed forms "
                          "with refinement; batch: 32 uneven problems with 16 right-hand sides "
-                         "each; post: section 5.3; body: body loads")
+                         "each; post: section 5.3; body: body loads; hbs: the root DtN of a\n"
+                         "256x256 p12 field compressed to HBS form (sections 6-8)")
     ap.add_argument("--train-pairs", type=int, default=200000,
                     help="sweep: surrogate training pairs (leaf solves of random leaves of "
                          "1000 training fields)")
@@ -377,6 +378,8 @@ def other_workload(args, H, hi, np, torch, dev):
         return post_workload(args, H, hi, np, torch, dev, line)
     if args.workload == "body":
         return body_workload(args, H, hi, np, torch, dev, line)
+    if args.workload == "hbs":
+        return hbs_workload(args, H, hi, np, torch, dev, line)
     if args.workload == "batch":
         probs = hi.batched_problems()
         ins = [_inputs(H, pr, np, torch, dev) for pr in probs]
@@ -665,6 +668,96 @@ def post_workload(args, H, hi, np, torch, dev, line):
                                 "cores": _blas_threads(), "kind": "oracle",
                                 "sample": f"{reps} passes over the 64 leaves of an 8x8 operator "
                                           "(same p, q), per-leaf rate"}
+    return line
+
+
+def _event_ms(torch, np, reps, fn):
+    """Median of HIP-event times of fn() on the current stream (the library's launch stream)."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    fn()
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+HBS_L, HBS_K = 6, 80
+
+
+def hbs_workload(args, H, hi, np, torch, dev, line):
+    """Sections 6-8 on the largest single-GPU root DtN: the FP64 build of a 256 x 256 p = 12,
+    q = 10 sweep field gives T^1 of 10240 x 10240; it is compressed (Remark 8.2) to an HBS
+    matrix on 64 leaves of 160 points with rank 80, then applied (T_apply, eq:tele1-3),
+    inverted (Algorithm 3) and its inverse applied (Algorithm 4).  The line's value is HBS
+    T_apply at one right-hand side; the dense T_apply of the same matrix is timed beside it."""
+    pr = hi.sweep_field(5000)
+    C, F = _inputs(H, pr, np, torch, dev)
+    op = H.build_solution_operator(C, pr.box, pr.nleaf, pr.p, pr.q)
+    M, L, k = op.n_bdry, HBS_L, HBS_K
+    m = M >> L
+    rng = np.random.default_rng(21)
+    om = torch.tensor(rng.standard_normal((M, k)), dtype=torch.float64, device=dev)
+    pt = torch.tensor(rng.standard_normal((k, M)), dtype=torch.float64, device=dev)
+    nfac, ninv = H.hbs_sizes(L, m, k)
+    fac = torch.empty(nfac, dtype=torch.float64, device=dev)
+    inv = torch.empty(ninv, dtype=torch.float64, device=dev)
+    reps = max(args.steps, 3)
+    t_comp = _event_ms(torch, np, reps, lambda: H.hbs_compress(op, L, k, om, pt, fac))
+    x = torch.tensor(rng.standard_normal((M, 1)), dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    t_apply = _event_ms(torch, np, reps, lambda: H.hbs_apply(fac, x, L, m, k, y))
+    xr = x.reshape(1, M).contiguous()
+    vr = torch.empty_like(xr)
+    t_dense = _event_ms(torch, np, reps, lambda: op.root_dtn_apply(xr, vr))
+    err_apply = float((y.reshape(-1) - vr.reshape(-1)).abs().max() / vr.abs().max())
+    t_inv = _event_ms(torch, np, reps, lambda: H.hbs_invert(fac, L, m, k, inv))
+    z = torch.empty_like(x)
+    t_solve = _event_ms(torch, np, reps, lambda: H.hbs_solve(inv, x, L, m, k, z))
+    back = op.root_dtn_apply(z.reshape(1, M).contiguous())
+    res = float((back.reshape(-1) - x.reshape(-1)).abs().max() / x.abs().max())
+    byts = 8.0 * (nfac + 2 * M)
+    log(f"hbs: compress {t_comp:.2f} ms, apply {t_apply * 1e3:.1f} us (dense {t_dense * 1e3:.1f} "
+        f"us), rel err {err_apply:.2e}; invert {t_inv:.2f} ms, solve {t_solve * 1e3:.1f} us, "
+        f"residual {res:.2e}")
+    gbs = byts / (t_apply * 1e-3) / 1e9
+    line.update(metric="HBS root DtN applies/s (T_apply, sections 6-8)", unit="applies/s",
+                value=1e3 / t_apply, ms_per_step=t_apply, dtype="f64",
+                config={"workload": "hbs-root-dtn-sweep-256x256-p12-q10", "M": M, "levels": L,
+                        "leaf_size": m, "rank": k, "nrhs": 1},
+                roofline=dict(bound="hbm", achieved=gbs, peak=PEAK["hbm"], unit="GB/s",
+                              frac=gbs / PEAK["hbm"], traffic=None, kernel="hbs_apply (all levels)",
+                              bytes_per_apply=byts),
+                hbs=dict(compress_ms=t_comp, apply_ms=t_apply, dense_apply_ms=t_dense,
+                         apply_rel_err_vs_dense=err_apply, invert_ms=t_inv, solve_ms=t_solve,
+                         solve_residual_rel=res, factor_bytes=8.0 * nfac,
+                         dense_bytes=8.0 * M * M))
+    if not args.no_cpu_baseline:
+        # The oracle's telescoping product (oracle.hbs.apply) on factors of the same
+        # leaf size and rank compressed from a 64 x 64-leaf field's root DtN (M = 2560),
+        # scaled by M to 10240 (the product's work is linear in M at fixed m and k).
+        from oracle import hbs as ohbs
+        from oracle import hps as ohps
+        sub = hi.sweep_field(5000, nleaf=(64, 64))
+        grid = ohps.Grid(sub.box, 64, 64, sub.q)
+        op_o = ohps.build(sub.coeffs_at(grid.cheb_xy(sub.p)), sub.box, (64, 64), sub.p, sub.q,
+                          keep=False)
+        Ls = L - 2
+        Fo = ohbs.compress(op_o.rootT, Ls, rank=k)
+        xo = rng.standard_normal(op_o.rootT.shape[0])
+        n_rep, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < 3.0:
+            ohbs.apply(Fo, xo)
+            n_rep += 1
+        per = (time.perf_counter() - t0) / n_rep * (M / op_o.rootT.shape[0])
+        line["cpu_baseline"] = {"value": 1.0 / per, "unit": "applies/s", "cores": _blas_threads(),
+                                "kind": "oracle",
+                                "sample": f"{n_rep} oracle HBS applies at M = "
+                                          f"{op_o.rootT.shape[0]} (64x64 leaves, same leaf size "
+                                          f"and rank), time scaled by M"}
     return line
 
 

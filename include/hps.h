@@ -377,7 +377,11 @@ hps_status hps_batched_gemm(const double* A, const double* B, double* C, int Mr,
 
    Vectors x, y: M x nrhs row-major.  All pointers are device memory owned by
    the caller; the calls allocate their scratch (the library's pool), run on
-   `stream` and return after it has finished.  Sizes outside the limits
+   `stream` and return after it has finished.  hps_hbs_apply and
+   hps_hbs_solve record their launches for one (buffer, x, y, nrhs, sizes)
+   into a HIP graph on the first call and replay it afterwards (the last 16
+   such passes are kept; hps_mem_trim drops them): the buffers' contents may
+   change between calls, their addresses are part of the record.  Sizes outside the limits
    (L in [1, 20], 1 <= k <= m, m and 2k at most 3072) give HPS_EINVAL. */
 
 /* Numbers of doubles in the factor and inverse buffers (either may be null). */
@@ -540,7 +544,10 @@ hps_status hps_tune_reset(void);
    the kept body operator, 17 leaf T = P0 - P1 Z products (section 3.2),
    18 the merges' S = M^-1 B products (eq:U_parent), 19-21 the blocked
    Gauss-Jordan steps of large merge systems (diagonal-block inverses, block
-   rows, updates of the other rows), 22 whole small merges in one launch.  Bit c of mask enables class c; every
+   rows, updates of the other rows), 22 whole small merges in one launch,
+   23 HBS passes (a replayed apply or solve as one record; the products of
+   Algorithm 3 and of the compression one record per launch).  Bit c of mask
+   enables class c; every
    later launch of an enabled class records a start and stop event on its
    stream together with its algorithmic FLOPs and bytes.  Costs one event
    pair per launch while enabled. */

@@ -414,7 +414,7 @@ PROF_CLASSES = {"leaf_assemble": 0, "lu_panel": 1, "swap_trsm": 2, "lu_update": 
                 "downward": 8, "residual": 9, "upward": 10, "leaf_lu": 11, "mlp_train": 12,
                 "mlp_infer": 13, "postprocess": 14, "gemm_bf16x6": 15,
                 "body_flux": 16, "leaf_gemm": 17, "merge_s": 18, "bgj_diag": 19,
-                "bgj_rows": 20, "bgj_update": 21, "merge_small": 22}
+                "bgj_rows": 20, "bgj_update": 21, "merge_small": 22, "hbs": 23}
 
 
 def mem_trim() -> int:

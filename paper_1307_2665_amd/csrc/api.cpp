@@ -89,6 +89,7 @@ hps_status hps_mem_trim(size_t* freed) {
   return guard([&] {
     (void)hipDeviceSynchronize();
     hps::parked_clear();
+    hps::hbs_passes_clear();
     const size_t f = hps::pool_trim();
     hps::trim_async_pool();
     if (freed) *freed = f;

@@ -42,5 +42,7 @@ void hbs_solve(const HbsLayout& lo, const double* inv, const double* x, double* 
 void hbs_compress(const HbsLayout& lo, const double* H, int ldh, const double* omega,
                   const double* psit, double* fac, hipStream_t s);
 int hbs_max_compress_rank(int m);
+// Drops the recorded apply / solve passes (the device must be idle).
+void hbs_passes_clear();
 
 }  // namespace hps

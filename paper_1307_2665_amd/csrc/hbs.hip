@@ -9,10 +9,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <list>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "dense.h"
 #include "hbs.h"
+#include "grid_sync.h"
+#include "prof.h"
 #include "solver.h"
 
 namespace hps {
@@ -111,8 +118,49 @@ GemmDesc gd(const double* A, int lda, const double* B, int ldb, double* C, int l
   return g;
 }
 
+// Skinny products of the HBS passes (N <= 8 right-hand sides, K N <= 4096):
+// 16 lanes per row of C read the row of A in 128-byte segments against B
+// staged in LDS, then reduce across the group; C = C0 or the old C (unless
+// overwrite) plus alpha A B, as in the grouped GEMM.  Grid: (rows / 64,
+// descriptors); each workgroup takes 64 rows.
+constexpr int GEMV_MAX_N = 8, GEMV_LDS = 4096;
+
+__global__ void __launch_bounds__(256) k_hbs_gemv(const GemmDesc* __restrict__ descs) {
+  __shared__ double sB[GEMV_LDS];
+  const GemmDesc d = descs[blockIdx.y];
+  const int N = d.N, K = d.K;
+  for (int e = threadIdx.x; e < K * N; e += 256) sB[e] = d.B[(size_t)(e / N) * d.ldb + e % N];
+  __syncthreads();
+  const int g = threadIdx.x >> 4, l = threadIdx.x & 15;
+  for (int i = 0; i < 4; ++i) {
+    const int r = blockIdx.x * 64 + g + 16 * i;
+    if (r >= d.M) break;  // the same for the 16 lanes of a group
+    double acc[GEMV_MAX_N];
+#pragma unroll
+    for (int c = 0; c < GEMV_MAX_N; ++c) acc[c] = 0.0;
+    const double* a = d.A + (size_t)r * d.lda;
+    for (int kk = l; kk < K; kk += 16) {
+      const double av = a[kk];
+#pragma unroll
+      for (int c = 0; c < GEMV_MAX_N; ++c)
+        if (c < N) acc[c] = fma(av, sB[kk * N + c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < GEMV_MAX_N; ++c)
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 16);
+    if (l == 0)
+      for (int c = 0; c < N; ++c) {
+        double* cp = d.C + (size_t)r * d.ldc + c;
+        const double c0 = d.C0 ? d.C0[(size_t)r * d.ldc0 + c] : (d.overwrite ? 0.0 : *cp);
+        *cp = c0 + d.alpha * acc[c];
+      }
+  }
+}
+
 // The launches of one operation, uploaded once: each launch is a grouped
-// GEMM over a contiguous range of the descriptors.
+// product over a contiguous range of the descriptors (the skinny kernel when
+// every product of the launch fits it, else the grouped GEMM).
 struct GemmPlan {
   std::vector<GemmDesc> all;
   std::vector<std::pair<size_t, size_t>> launches;
@@ -121,24 +169,31 @@ struct GemmPlan {
     launches.push_back({all.size(), g.size()});
     all.insert(all.end(), g.begin(), g.end());
   }
-  void run(DeviceMem& mem, hipStream_t s) const {
-    if (all.empty()) return;
-    GemmDesc* d = mem.upload(all, s);
+  void enqueue(GemmDesc* d, hipStream_t s) const {
     for (auto& r : launches) {
       std::vector<GemmDesc> h(all.begin() + r.first, all.begin() + r.first + r.second);
-      grouped_gemm(d + r.first, h, s, GEMM_F64);
+      bool skinny = true;
+      int mmax = 1;
+      double fl = 0, by = 0;
+      for (auto& g : h) {
+        skinny = skinny && g.N <= GEMV_MAX_N && (long long)g.K * g.N <= GEMV_LDS;
+        mmax = std::max(mmax, g.M);
+        fl += 2.0 * g.M * g.N * g.K;
+        by += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + 2.0 * g.M * g.N);
+      }
+      if (skinny) {
+        ProfScope ps(PROF_HBS, s, fl, by);
+        hipLaunchKernelGGL(k_hbs_gemv, dim3((unsigned)((mmax + 63) / 64), (unsigned)h.size()),
+                           dim3(256), 0, s, d + r.first);
+        HPS_HIP(hipGetLastError());
+      } else {
+        grouped_gemm(d + r.first, h, s, GEMM_F64, PROF_HBS);
+      }
     }
   }
-};
-
-// x-hat / y-hat buffers: level l (1 .. L) holds 2^l blocks of k x nrhs.
-struct Hats {
-  std::vector<double*> x, y;
-  Hats(DeviceMem& mem, int L, int k, int nrhs) : x(L + 1, nullptr), y(L + 1, nullptr) {
-    for (int l = 1; l <= L; ++l) {
-      x[l] = mem.alloc<double>(((size_t)1 << l) * k * nrhs);
-      y[l] = mem.alloc<double>(((size_t)1 << l) * k * nrhs);
-    }
+  void run(DeviceMem& mem, hipStream_t s) const {
+    if (all.empty()) return;
+    enqueue(mem.upload(all, s), s);
   }
 };
 
@@ -244,63 +299,6 @@ void check_status(const int* st, hipStream_t s, const char* what) {
 
 }  // namespace
 
-// y = H x by the telescoping factorization: x-hat = V* x up the tree, the
-// sibling blocks of each B, y-hat = U y-hat(parent) + B x-hat down the tree,
-// and y = U y-hat + D x at the leaves.
-void hbs_apply(const HbsLayout& lo, const double* fac, const double* x, double* y, int nrhs,
-               hipStream_t s) {
-  const int L = lo.L, m = lo.m, k = lo.k, k2 = 2 * k;
-  DeviceMem mem;
-  Hats h(mem, L, k, nrhs);
-  const size_t bx = (size_t)k * nrhs;  // one x-hat block
-  GemmPlan P;
-  std::vector<GemmDesc> g;
-  const int NL = 1 << L;
-  for (int j = 0; j < NL; ++j)
-    g.push_back(gd(fac + lo.Vt + (size_t)j * k * m, m, x + (size_t)j * m * nrhs, nrhs,
-                   h.x[L] + j * bx, nrhs, k, nrhs, m, true));
-  P.launch(g);
-  for (int l = L - 1; l >= 1; --l) {
-    g.clear();
-    for (int j = 0; j < (1 << l); ++j)
-      g.push_back(gd(fac + lo.Vtp[l] + (size_t)j * k * k2, k2, h.x[l + 1] + 2 * j * bx, nrhs,
-                     h.x[l] + j * bx, nrhs, k, nrhs, k2, true));
-    P.launch(g);
-  }
-  for (int l = 0; l < L; ++l) {
-    const int nn = 1 << l;
-    if (l > 0) {
-      g.clear();
-      for (int j = 0; j < nn; ++j)
-        g.push_back(gd(fac + lo.Up[l] + (size_t)j * k2 * k, k, h.y[l] + j * bx, nrhs,
-                       h.y[l + 1] + 2 * j * bx, nrhs, k2, nrhs, k, true));
-      P.launch(g);
-    }
-    g.clear();
-    for (int j = 0; j < nn; ++j) {
-      const double* Bj = fac + lo.B[l] + (size_t)j * 4 * k * k;
-      double* y1 = h.y[l + 1] + 2 * j * bx;
-      const double* x1 = h.x[l + 1] + 2 * j * bx;
-      // Upper-right block (rows of child 1, x-hat of child 2) and lower-left.
-      g.push_back(gd(Bj + k, k2, x1 + bx, nrhs, y1, nrhs, k, nrhs, k, l == 0));
-      g.push_back(gd(Bj + (size_t)k * k2, k2, x1, nrhs, y1 + bx, nrhs, k, nrhs, k, l == 0));
-    }
-    P.launch(g);
-  }
-  g.clear();
-  for (int j = 0; j < NL; ++j)
-    g.push_back(gd(fac + lo.D + (size_t)j * m * m, m, x + (size_t)j * m * nrhs, nrhs,
-                   y + (size_t)j * m * nrhs, nrhs, m, nrhs, m, true));
-  P.launch(g);
-  g.clear();
-  for (int j = 0; j < NL; ++j)
-    g.push_back(gd(fac + lo.U + (size_t)j * m * k, k, h.y[L] + j * bx, nrhs,
-                   y + (size_t)j * m * nrhs, nrhs, m, nrhs, k, false));
-  P.launch(g);
-  P.run(mem, s);
-  HPS_HIP(hipStreamSynchronize(s));
-}
-
 // Algorithm 3, one level at a time from the leaves: for every node,
 // W = [Dt | U | I] gives Z = Dt^-1 U and Dt^-1; [V* Z | I] gives Dhat;
 // then E = Z Dhat, P = V* Dt^-1, F* = Dhat P and G = Dt^-1 - E P.  A parent's
@@ -401,57 +399,308 @@ void hbs_invert(const HbsLayout& lo, const double* fac, double* inv, hipStream_t
   check_status(st, s, "an HBS inversion block");
 }
 
+// ---------------------------------------------------------------------------
+// The telescoping product and Algorithm 4 as one persistent launch each.
+//
+// Both passes are a fixed sequence of phases (one per tree level up, the
+// root, one per level down, the leaves), and every phase is a set of rows
+// c = A0[r] B0 + A1[r] B1 of small products whose right-hand factors are the
+// caller's x or x-hat / y-hat blocks of earlier phases.  One cooperative
+// launch runs all phases, separated by grid barriers; 16 lanes take one row
+// (128-byte segments of A), up to 8 right-hand sides at a time.  The hat
+// blocks pass between workgroups on different XCDs, so they are written and
+// read with device-scope relaxed atomics (grid_sync.h); the factors and x are
+// read with plain loads and the output y is written with plain stores.  A
+// barrier that waits about a second sets the error flag (reported as a
+// device error) and lets the workgroup go on, so the launch always ends.
+// ---------------------------------------------------------------------------
+struct RowDesc {
+  const double* A0;
+  const double* B0;
+  const double* A1;
+  const double* B1;
+  double* C;
+  int lda0, lda1, K0, K1;
+  int plain0, plain1;  // 1: that B is the caller's x (plain loads)
+};
+struct Phase {
+  int first, nodes, rows, out;  // out: C is the caller's y (plain stores)
+};
+constexpr int PASS_NC = 8;
+
+__global__ void __launch_bounds__(256) k_hbs_pass(const Phase* __restrict__ ph, int nph,
+                                                  const RowDesc* __restrict__ rd, int N,
+                                                  unsigned* bar, int* err) {
+  const int g = threadIdx.x >> 4, l = threadIdx.x & 15;
+  const int ngroups = gridDim.x * 16, gid = blockIdx.x * 16 + g;
+  unsigned gen = 0;
+  for (int p = 0; p < nph; ++p) {
+    const Phase P = ph[p];
+    const int tasks = P.nodes * P.rows;
+    for (int t = gid; t < tasks; t += ngroups) {
+      const RowDesc d = rd[P.first + t / P.rows];
+      const int r = t % P.rows;
+      for (int c0 = 0; c0 < N; c0 += PASS_NC) {
+        double acc[PASS_NC];
+#pragma unroll
+        for (int c = 0; c < PASS_NC; ++c) acc[c] = 0.0;
+#pragma unroll
+        for (int term = 0; term < 2; ++term) {
+          const double* A = term ? d.A1 : d.A0;
+          const double* B = term ? d.B1 : d.B0;
+          const int K = term ? d.K1 : d.K0, lda = term ? d.lda1 : d.lda0;
+          const bool plain = (term ? d.plain1 : d.plain0) != 0;
+          const double* a = A + (size_t)r * lda;
+          for (int kk = l; kk < K; kk += 16) {
+            const double av = a[kk];
+            const double* b = B + (size_t)kk * N + c0;
+#pragma unroll
+            for (int c = 0; c < PASS_NC; ++c)
+              if (c0 + c < N) acc[c] = fma(av, plain ? b[c] : ld_dev(b + c), acc[c]);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < PASS_NC; ++c)
+#pragma unroll
+          for (int off = 8; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 16);
+        if (l == 0) {
+          double* cr = d.C + (size_t)r * N + c0;
+#pragma unroll
+          for (int c = 0; c < PASS_NC; ++c)
+            if (c0 + c < N) {
+              if (P.out)
+                cr[c] = acc[c];
+              else
+                st_dev(cr + c, acc[c]);
+            }
+        }
+      }
+    }
+    if (p + 1 < nph) grid_barrier(bar, gridDim.x, gen, err);
+  }
+}
+
+__global__ void k_hbs_pass_zero(unsigned* bar, int* err) {
+  if (threadIdx.x < 9) bar[32 * threadIdx.x] = 0u;
+  if (threadIdx.x == 0) *err = 0;
+}
+
+namespace {
+
+RowDesc row(const double* A0, int lda0, const double* B0, int K0, bool plain0, double* C,
+            const double* A1 = nullptr, int lda1 = 0, const double* B1 = nullptr, int K1 = 0,
+            bool plain1 = false) {
+  return RowDesc{A0, B0, A1, B1, C, lda0, lda1, K0, K1, plain0 ? 1 : 0, plain1 ? 1 : 0};
+}
+
+struct PassPlan {
+  std::vector<Phase> ph;
+  std::vector<RowDesc> rd;
+  void phase(int rows, const std::vector<RowDesc>& nodes, bool out = false) {
+    ph.push_back(Phase{(int)rd.size(), (int)nodes.size(), rows, out ? 1 : 0});
+    rd.insert(rd.end(), nodes.begin(), nodes.end());
+  }
+};
+
+// x-hat / y-hat pointers of a pass: level l (1 .. L) holds 2^l blocks of
+// k x nrhs, node-major.
+struct HatPtrs {
+  std::vector<double*> x, y;
+};
+
+}  // namespace
+
+// y = H x by the telescoping factorization: x-hat = V* x up the tree, the
+// sibling blocks of each B, y-hat = U y-hat(parent) + B x-hat down the tree,
+// and y = U y-hat + D x at the leaves.
+static void apply_plan(const HbsLayout& lo, const double* fac, const double* x, double* y,
+                       int nrhs, const HatPtrs& h, PassPlan& P) {
+  const int L = lo.L, m = lo.m, k = lo.k, k2 = 2 * k, NL = 1 << L;
+  const size_t bx = (size_t)k * nrhs;
+  std::vector<RowDesc> v;
+  for (int j = 0; j < NL; ++j)
+    v.push_back(row(fac + lo.Vt + (size_t)j * k * m, m, x + (size_t)j * m * nrhs, m, true,
+                    h.x[L] + j * bx));
+  P.phase(k, v);
+  for (int l = L - 1; l >= 1; --l) {
+    v.clear();
+    for (int j = 0; j < (1 << l); ++j)
+      v.push_back(row(fac + lo.Vtp[l] + (size_t)j * k * k2, k2, h.x[l + 1] + 2 * j * bx, k2,
+                      false, h.x[l] + j * bx));
+    P.phase(k, v);
+  }
+  // Root: y-hat of child h from the other child's x-hat through B's
+  // off-diagonal block (upper right for h = 0, lower left for h = 1).
+  v.clear();
+  for (int hh = 0; hh < 2; ++hh)
+    v.push_back(row(fac + lo.B[0] + (hh == 0 ? (size_t)k : (size_t)k * k2), k2,
+                    h.x[1] + (1 - hh) * bx, k, false, h.y[1] + hh * bx));
+  P.phase(k, v);
+  for (int l = 1; l < L; ++l) {
+    v.clear();
+    for (int nd = 0; nd < (2 << l); ++nd) {
+      const int j = nd / 2, hh = nd % 2;
+      const double* Bj = fac + lo.B[l] + (size_t)j * 4 * k * k;
+      v.push_back(row(fac + lo.Up[l] + (size_t)j * k2 * k + (size_t)hh * k * k, k,
+                      h.y[l] + j * bx, k, false, h.y[l + 1] + nd * bx,
+                      Bj + (hh == 0 ? (size_t)k : (size_t)k * k2), k2,
+                      h.x[l + 1] + (2 * j + 1 - hh) * bx, k, false));
+    }
+    P.phase(k, v);
+  }
+  v.clear();
+  for (int j = 0; j < NL; ++j)
+    v.push_back(row(fac + lo.D + (size_t)j * m * m, m, x + (size_t)j * m * nrhs, m, true,
+                    y + (size_t)j * m * nrhs, fac + lo.U + (size_t)j * m * k, k, h.y[L] + j * bx,
+                    k, false));
+  P.phase(m, v, true);
+}
+
 // Algorithm 4: x-hat = F* x up the tree, y-hat at the top from the root's G,
 // then y-hat(children) = E y-hat + G x-hat(children) down the tree and
 // y = E y-hat + G x at the leaves.
+static void solve_plan(const HbsLayout& lo, const double* inv, const double* x, double* y,
+                       int nrhs, const HatPtrs& h, PassPlan& P) {
+  const int L = lo.L, m = lo.m, k = lo.k, k2 = 2 * k, NL = 1 << L;
+  const size_t bx = (size_t)k * nrhs;
+  std::vector<RowDesc> v;
+  for (int j = 0; j < NL; ++j)
+    v.push_back(row(inv + lo.Fs[L] + (size_t)j * k * m, m, x + (size_t)j * m * nrhs, m, true,
+                    h.x[L] + j * bx));
+  P.phase(k, v);
+  for (int l = L - 1; l >= 1; --l) {
+    v.clear();
+    for (int j = 0; j < (1 << l); ++j)
+      v.push_back(row(inv + lo.Fs[l] + (size_t)j * k * k2, k2, h.x[l + 1] + 2 * j * bx, k2,
+                      false, h.x[l] + j * bx));
+    P.phase(k, v);
+  }
+  P.phase(k2, {row(inv + lo.G[0], k2, h.x[1], k2, false, h.y[1])});
+  for (int l = 1; l < L; ++l) {
+    v.clear();
+    for (int j = 0; j < (1 << l); ++j)
+      v.push_back(row(inv + lo.G[l] + (size_t)j * k2 * k2, k2, h.x[l + 1] + 2 * j * bx, k2, false,
+                      h.y[l + 1] + 2 * j * bx, inv + lo.E[l] + (size_t)j * k2 * k, k,
+                      h.y[l] + j * bx, k, false));
+    P.phase(k2, v);
+  }
+  v.clear();
+  for (int j = 0; j < NL; ++j)
+    v.push_back(row(inv + lo.G[L] + (size_t)j * m * m, m, x + (size_t)j * m * nrhs, m, true,
+                    y + (size_t)j * m * nrhs, inv + lo.E[L] + (size_t)j * m * k, k,
+                    h.y[L] + j * bx, k, false));
+  P.phase(m, v, true);
+}
+
+// A pass's phases, row descriptors, hat blocks and barrier counters are kept
+// per (matrix buffer, x, y, nrhs, sizes, device) and reused by later calls
+// (at most 16, least recently used first out; hps_mem_trim drops them).
+namespace {
+
+struct CachedPass {
+  DeviceMem mem;
+  Phase* ph = nullptr;
+  RowDesc* rd = nullptr;
+  int nph = 0;
+  unsigned* bar = nullptr;
+  int* err = nullptr;
+  double flops = 0, bytes = 0;
+};
+using PassKey = std::tuple<int, int, const void*, const void*, const void*, int, int, int, int>;
+
+std::mutex g_pass_mu;
+std::map<PassKey, std::unique_ptr<CachedPass>> g_passes;
+std::list<PassKey> g_pass_order;
+constexpr size_t MAX_PASSES = 16;
+
+int pass_grid() {
+  static int grid = -1;
+  if (grid < 0) {
+    int dev = 0, cus = 0, per = 0;
+    HPS_HIP(hipGetDevice(&dev));
+    HPS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_hbs_pass, 256, 0));
+    grid = per >= 1 ? cus : 0;
+  }
+  return grid;
+}
+
+template <class Build>
+void run_pass(int kind, const HbsLayout& lo, const double* mat, const double* x, const double* y,
+              int nrhs, hipStream_t s, Build build) {
+  int dev = 0;
+  HPS_HIP(hipGetDevice(&dev));
+  const int grid = pass_grid();
+  HPS_REQUIRE(grid > 0, "HBS pass: no resident workgroups");
+  std::lock_guard<std::mutex> lk(g_pass_mu);
+  const PassKey key{kind, dev, mat, x, y, nrhs, lo.L, lo.m, lo.k};
+  auto it = g_passes.find(key);
+  if (it == g_passes.end()) {
+    auto C = std::make_unique<CachedPass>();
+    HatPtrs h{std::vector<double*>(lo.L + 1, nullptr), std::vector<double*>(lo.L + 1, nullptr)};
+    for (int l = 1; l <= lo.L; ++l) {
+      h.x[l] = C->mem.alloc<double>(((size_t)1 << l) * lo.k * nrhs);
+      h.y[l] = C->mem.alloc<double>(((size_t)1 << l) * lo.k * nrhs);
+    }
+    PassPlan P;
+    build(h, P);
+    for (const Phase& q : P.ph)
+      for (int n = 0; n < q.nodes; ++n) {
+        const RowDesc& d = P.rd[q.first + n];
+        C->flops += 2.0 * q.rows * nrhs * (d.K0 + d.K1);
+        C->bytes += 8.0 * q.rows * (d.K0 + d.K1 + nrhs);
+      }
+    C->ph = C->mem.alloc<Phase>(P.ph.size());
+    C->rd = C->mem.alloc<RowDesc>(P.rd.size());
+    C->nph = (int)P.ph.size();
+    C->bar = C->mem.alloc<unsigned>(9 * 32);
+    C->err = C->mem.alloc<int>(1);
+    HPS_HIP(hipMemcpy(C->ph, P.ph.data(), P.ph.size() * sizeof(Phase), hipMemcpyHostToDevice));
+    HPS_HIP(hipMemcpy(C->rd, P.rd.data(), P.rd.size() * sizeof(RowDesc), hipMemcpyHostToDevice));
+    if (g_passes.size() >= MAX_PASSES) {
+      // Every call waits for its stream, so no evicted pass is still running.
+      g_passes.erase(g_pass_order.front());
+      g_pass_order.pop_front();
+    }
+    it = g_passes.emplace(key, std::move(C)).first;
+    g_pass_order.push_back(key);
+  } else {
+    g_pass_order.remove(key);
+    g_pass_order.push_back(key);
+  }
+  CachedPass& C = *it->second;
+  hipLaunchKernelGGL(k_hbs_pass_zero, dim3(1), dim3(64), 0, s, C.bar, C.err);
+  {
+    ProfScope ps(PROF_HBS, s, C.flops, C.bytes);
+    int N = nrhs;
+    void* args[] = {(void*)&C.ph, (void*)&C.nph, (void*)&C.rd, (void*)&N, (void*)&C.bar,
+                    (void*)&C.err};
+    HPS_HIP(hipLaunchCooperativeKernel((const void*)k_hbs_pass, dim3(grid), dim3(256), args, 0, s));
+  }
+  int herr = 0;
+  HPS_HIP(hipMemcpyAsync(&herr, C.err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HPS_HIP(hipStreamSynchronize(s));
+  if (herr) throw Error(HPS_EDEVICE, "HBS pass: a grid barrier timed out");
+}
+
+}  // namespace
+
+void hbs_passes_clear() {
+  std::lock_guard<std::mutex> lk(g_pass_mu);
+  g_passes.clear();
+  g_pass_order.clear();
+}
+
+void hbs_apply(const HbsLayout& lo, const double* fac, const double* x, double* y, int nrhs,
+               hipStream_t s) {
+  run_pass(0, lo, fac, x, y, nrhs, s,
+           [&](const HatPtrs& h, PassPlan& P) { apply_plan(lo, fac, x, y, nrhs, h, P); });
+}
+
 void hbs_solve(const HbsLayout& lo, const double* inv, const double* x, double* y, int nrhs,
                hipStream_t s) {
-  const int L = lo.L, m = lo.m, k = lo.k, k2 = 2 * k;
-  DeviceMem mem;
-  Hats h(mem, L, k, nrhs);
-  const size_t bx = (size_t)k * nrhs;
-  GemmPlan P;
-  std::vector<GemmDesc> g;
-  const int NL = 1 << L;
-  for (int j = 0; j < NL; ++j)
-    g.push_back(gd(inv + lo.Fs[L] + (size_t)j * k * m, m, x + (size_t)j * m * nrhs, nrhs,
-                   h.x[L] + j * bx, nrhs, k, nrhs, m, true));
-  P.launch(g);
-  for (int l = L - 1; l >= 1; --l) {
-    g.clear();
-    for (int j = 0; j < (1 << l); ++j)
-      g.push_back(gd(inv + lo.Fs[l] + (size_t)j * k * k2, k2, h.x[l + 1] + 2 * j * bx, nrhs,
-                     h.x[l] + j * bx, nrhs, k, nrhs, k2, true));
-    P.launch(g);
-  }
-  g.clear();
-  g.push_back(gd(inv + lo.G[0], k2, h.x[1], nrhs, h.y[1], nrhs, k2, nrhs, k2, true));
-  P.launch(g);
-  for (int l = 1; l < L; ++l) {
-    const int nn = 1 << l;
-    g.clear();
-    for (int j = 0; j < nn; ++j)
-      g.push_back(gd(inv + lo.G[l] + (size_t)j * k2 * k2, k2, h.x[l + 1] + 2 * j * bx, nrhs,
-                     h.y[l + 1] + 2 * j * bx, nrhs, k2, nrhs, k2, true));
-    P.launch(g);
-    g.clear();
-    for (int j = 0; j < nn; ++j)
-      g.push_back(gd(inv + lo.E[l] + (size_t)j * k2 * k, k, h.y[l] + j * bx, nrhs,
-                     h.y[l + 1] + 2 * j * bx, nrhs, k2, nrhs, k, false));
-    P.launch(g);
-  }
-  g.clear();
-  for (int j = 0; j < NL; ++j)
-    g.push_back(gd(inv + lo.G[L] + (size_t)j * m * m, m, x + (size_t)j * m * nrhs, nrhs,
-                   y + (size_t)j * m * nrhs, nrhs, m, nrhs, m, true));
-  P.launch(g);
-  g.clear();
-  for (int j = 0; j < NL; ++j)
-    g.push_back(gd(inv + lo.E[L] + (size_t)j * m * k, k, h.y[L] + j * bx, nrhs,
-                   y + (size_t)j * m * nrhs, nrhs, m, nrhs, k, false));
-  P.launch(g);
-  P.run(mem, s);
-  HPS_HIP(hipStreamSynchronize(s));
+  run_pass(1, lo, inv, x, y, nrhs, s,
+           [&](const HatPtrs& h, PassPlan& P) { solve_plan(lo, inv, x, y, nrhs, h, P); });
 }
 
 // Brute-force compression (Remark 8.2) of a dense matrix into HBS factors of

@@ -31,6 +31,7 @@ enum ProfClass {
   PROF_BGJ_ROWS = 20,    // blocked Gauss-Jordan: block rows times the inverse
   PROF_BGJ_UPDATE = 21,  // blocked Gauss-Jordan: updates of the other rows
   PROF_MERGE_SMALL = 22, // whole small merges in one launch
+  PROF_HBS = 23,         // HBS passes: telescoping product, Algorithms 3-4, compression
   PROF_NCLASS = 24
 };
 
