@@ -40,6 +40,20 @@ __device__ inline MergePass merge_pass(const GemmDesc& g) {
   return MergePass{g.pmap, g.Ta, g.Tb, g.na, g.nb};
 }
 
+// The old values of a plain product for the 128 tile, through the same
+// row / column form as the pass-through: C0 if given, else C itself when
+// accumulating, else zero (row offsets fit an int for matrices under 2^31
+// elements).
+struct PlainOld {
+  static constexpr bool active = true;
+  const double* __restrict__ src;
+  int ld, use;
+  __device__ int row(int r) const { return r * ld; }
+  __device__ int col(int c) const { return c; }
+  __device__ double value(int pr, int pc) const { return use ? as_global(src)[pr + pc] : 0.0; }
+  __device__ double operator()(int r, int c) const { return value(row(r), col(c)); }
+};
+
 // Grouped GEMM: one launch over problems, grid (tiles_n, tiles_m, nprob).
 // PASS: merge Schur products, C = diag(T11a, T22b) + alpha A B (descs with pmap).
 template <int BM, int BN, int BK, int WM, int WN, bool PASS, int DEPTH = 1>
@@ -70,9 +84,11 @@ __global__ void __launch_bounds__(256, 2) k_gemm128(const GemmDesc* __restrict__
   if constexpr (PASS)
     gemm128_tile<VEC>(g.A, g.lda, g.B, g.ldb, g.C, g.ldc, nullptr, 0, g.M, g.N, g.K, g.alpha,
                       ty * Gemm128::BM, tx * Gemm128::BN, sm, false, merge_pass(g));
-  else
-    gemm128_tile<VEC>(g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.C0, g.ldc0, g.M, g.N, g.K, g.alpha,
-                      ty * Gemm128::BM, tx * Gemm128::BN, sm, g.overwrite == 0, NoC0Elem{});
+  else  // old values through PlainOld: the NoC0Elem form of this tile spills registers
+    gemm128_tile<VEC>(g.A, g.lda, g.B, g.ldb, g.C, g.ldc, nullptr, 0, g.M, g.N, g.K, g.alpha,
+                      ty * Gemm128::BM, tx * Gemm128::BN, sm, false,
+                      PlainOld{g.C0 ? g.C0 : g.C, g.C0 ? g.ldc0 : g.ldc,
+                               (g.C0 || g.overwrite == 0) ? 1 : 0});
 }
 
 // The 128 x 128 tile over a queue of tiles of many problems (one persistent

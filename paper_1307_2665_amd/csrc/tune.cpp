@@ -125,7 +125,18 @@ void tune_load_json(const std::string& text) {
                               &knob, name, &a, &b, &c, &d, &v, &ms, &md);
     HPS_REQUIRE(n == 9 && knob >= 0 && knob < TUNE_NKNOBS && v >= 0,
                 "malformed tuning cache entry: " + line);
-    got.push_back({Key{knob, a, b, c, d}, Entry{v, ms, md, {}}});
+    std::vector<double> all;
+    const size_t q = line.find("\"all_ms\": [");
+    if (q != std::string::npos) {
+      std::istringstream li(line.substr(q + 11));
+      double x;
+      char sep;
+      while (li >> x) {
+        all.push_back(x);
+        if (!(li >> sep) || sep != ',') break;
+      }
+    }
+    got.push_back({Key{knob, a, b, c, d}, Entry{v, ms, md, all}});
   }
   Table& T = table();
   std::lock_guard<std::mutex> lk(T.mu);

@@ -30,8 +30,8 @@ int tune_lg(long long x);
 // table, else -1 (callers fall back to their default).
 int tune_get(int knob, int a, int b, int c, int d);
 void tune_force(int knob, int variant);  // -1 removes the force
-// all: every candidate's time, in variant order (GEMM buckets; written to the
-// cache as "all_ms", which loading ignores).
+// all: every candidate's time, in variant order (GEMM buckets; kept in the
+// cache as "all_ms").
 void tune_put(int knob, int a, int b, int c, int d, int variant, double ms, double ms_default,
               const std::vector<double>& all = {});
 void tune_clear();

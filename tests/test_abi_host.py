@@ -148,7 +148,8 @@ def test_tuning_cache_round_trip(tmp_path):
     import paper_1307_2665_amd as H
     H.tune_reset()
     entries = [
-        {"knob": 1, "name": "gemm", "key": [6, 6, 4, 11], "variant": 2, "ms": 0.5, "default_ms": 0.75},
+        {"knob": 1, "name": "gemm", "key": [6, 6, 4, 11], "variant": 2, "ms": 0.5, "default_ms": 0.75,
+         "all_ms": [0.75, 0.625, 0.5, 1.5, 2.0, 0.875, 0.625, 0.5625]},
         {"knob": 2, "name": "gj", "key": [10, 13, 0, 0], "variant": 9, "ms": 3.25, "default_ms": 4.5},
         {"knob": 0, "name": "leaf", "key": [196, 56, 0, 0], "variant": 4, "ms": 6.0, "default_ms": 6.0},
     ]
@@ -163,6 +164,8 @@ def test_tuning_cache_round_trip(tmp_path):
     key = lambda e: (e["knob"], tuple(e["key"]))
     assert sorted(((key(e), e["variant"]) for e in got["entries"])) == \
         sorted(((key(e), e["variant"]) for e in entries))
+    # Every tile's time of a GEMM bucket survives the round trip.
+    assert sorted(got["entries"], key=key) == sorted(entries, key=key)
     H.tune_reset()
     H.tune_save(out)
     assert json.loads(out.read_text())["entries"] == []
