@@ -47,9 +47,9 @@ ALU_F64_PEAK = 78.6
 # HBM bytes per launch of a kernel class on the default workload, from two rocprofv3 counter runs
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, factors from a 256 MiB copy), valid only while every source
 # the kernel is built from is unchanged (profiles/gemm_schur_sweep_256x256_p12_counters.md).
-TRAFFIC = {"gemm": dict(sources={"paper_1307_2665_amd/csrc/dense.hip": "7c0e074c07849af6",
+TRAFFIC = {"gemm": dict(sources={"paper_1307_2665_amd/csrc/dense.hip": "7b0d7992258c11e4",
                                  "paper_1307_2665_amd/csrc/mfma_tile.h": "e03c7a605340dccd"},
-                        bytes=7.377e+09, workload="sweep-256x256-p12-q10-1rhs")}
+                        bytes=4.700e+09, workload="sweep-256x256-p12-q10-1rhs")}
 
 
 def measured_traffic(cls, workload):
