@@ -529,6 +529,7 @@ __global__ void __launch_bounds__(64 * (NTI + 1), 4) k_leaf_mfma(
   __shared__ int sInv[NR];        // row -> column whose pivot it is
   __shared__ int sIdx[NR];        // interior node j -> (1 + j % (p-2)) | (1 + j / (p-2)) << 8
   __shared__ double sRed[S::NW];
+  __shared__ double sPiv[16];     // the current pivot row (panel wave only)
   double* sX = sbuf;                      // [NR][XS] panel block
   double* sL = sbuf + NR * XS;            // [NR][XS] rows of Z (the step's multipliers)
   double* sWP = sbuf + 2 * NR * XS;       // [16][NC] the chosen rows' values
@@ -572,6 +573,9 @@ __global__ void __launch_bounds__(64 * (NTI + 1), 4) k_leaf_mfma(
     for (int s = 0; s < NS; ++s) cand[s] = s * 64 + lane < NR;
     bool bad = false;
     for (int k = 0; k < NTI; ++k) {
+      int chosen[NS];  // column of this step whose pivot the slot's row became, or -1
+#pragma unroll
+      for (int s = 0; s < NS; ++s) chosen[s] = -1;
       __syncthreads();  // (1) the panel block is in LDS
       double x[NS][16];
 #pragma unroll
@@ -580,45 +584,59 @@ __global__ void __launch_bounds__(64 * (NTI + 1), 4) k_leaf_mfma(
 #pragma unroll
         for (int c = 0; c < 16; ++c) x[s][c] = row < NR ? sX[row * XS + c] : 0.0;
       }
+      // Rows are scaled lazily: the true row is scl * stored, a row chosen as
+      // pivot keeps its stored values and takes scl = 1 / pivot, so a column
+      // costs one FMA per entry and the pivot row needs no rewrite; the
+      // scales are applied once after the 16 columns.  Candidates are never
+      // scaled (scl = 1), so the search sees true magnitudes.
+      double scl[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) scl[s] = 1.0;
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
         unsigned key = 0;
 #pragma unroll
         for (int s = 0; s < NS; ++s)
-          if (cand[s]) key = max(key, pivot_key(x[s][c], s * 64 + lane));
+          key = cand[s] ? max(key, pivot_key(x[s][c], s * 64 + lane)) : key;
         const unsigned g = wave_max_u32(key);
         // Every step leaves at least 16 candidates (NR - 16 k rows), so g != 0.
         const int slot = 4095 - (int)(g & 4095u);
         const int gs = slot >> 6, gl = slot & 63;
         // The pivot row (all 16 columns: those left of c hold its multipliers
-        // of earlier columns, which Gauss-Jordan carries along) goes to scalar
-        // registers by readlane from lane gl of slot gs (gs is the same for the
-        // whole wave).
-        double prow[16];
-#pragma unroll
-        for (int c2 = 0; c2 < 16; ++c2) prow[c2] = 0.0;
+        // of earlier columns, which Gauss-Jordan carries along) goes through
+        // LDS: lane gl of slot gs (gs is the same for the whole wave) writes
+        // it and every lane reads it back, so it stays in vector registers
+        // (as 32 readlanes it filled the scalar registers, which spilled).
 #pragma unroll
         for (int s = 0; s < NS; ++s)
-          if (gs == s) {
+          if (gs == s && lane == gl) {
 #pragma unroll
-            for (int c2 = 0; c2 < 16; ++c2) prow[c2] = bcast_lane(x[s][c2], gl);
-            if (lane == gl) {
-              cand[s] = false;                  // chosen: no longer a candidate
-              sInv[s * 64 + lane] = 16 * k + c;
-            }
+            for (int c2 = 0; c2 < 16; ++c2) sPiv[c2] = x[s][c2];
           }
+        wave_lds_sync();
+        double prow[16];
+#pragma unroll
+        for (int c2 = 0; c2 < 16; ++c2) prow[c2] = sPiv[c2];
+        bool mine[NS];  // this lane's slot s holds the pivot row
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          mine[s] = gs == s && lane == gl;
+          cand[s] = cand[s] && !mine[s];  // chosen: no longer a candidate
+          chosen[s] = mine[s] ? 16 * k + c : chosen[s];
+        }
         const double piv = prow[c];
         const bool ok = g != 0 && piv != 0.0 && piv == piv && fabs(piv) != INFINITY &&
                         fabs(piv) > thr;
         bad |= !ok;
         const double inv = uniform(ok ? recip(piv) : 0.0);
-        // In-place Gauss-Jordan step on column c: every row loses f times the
+        // Gauss-Jordan step on column c: every other row loses f times the
         // scaled pivot row and column c takes the multipliers (-f / pivot);
-        // the pivot row is then overwritten with the scaled row (1 / pivot in
-        // column c).
+        // the pivot row keeps its values (1 in column c) and its scale
+        // becomes 1 / pivot.  In stored form the update does not depend on a
+        // row's scale.
         double f[NS];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) f[s] = x[s][c];
+        for (int s = 0; s < NS; ++s) f[s] = mine[s] ? 0.0 : x[s][c];
 #pragma unroll
         for (int c2 = 0; c2 < 16; ++c2)
           if (c2 != c) {
@@ -627,16 +645,19 @@ __global__ void __launch_bounds__(64 * (NTI + 1), 4) k_leaf_mfma(
             for (int s = 0; s < NS; ++s) x[s][c2] = fma(-f[s], pr, x[s][c2]);
           }
 #pragma unroll
-        for (int s = 0; s < NS; ++s) x[s][c] = -f[s] * inv;
-#pragma unroll
-        for (int s = 0; s < NS; ++s)
-          if (gs == s) {
-            if (lane == gl) {
-#pragma unroll
-              for (int c2 = 0; c2 < 16; ++c2) x[s][c2] = c2 == c ? inv : prow[c2] * inv;
-            }
-          }
+        for (int s = 0; s < NS; ++s) {
+          x[s][c] = mine[s] ? 1.0 : -f[s] * inv;
+          scl[s] = mine[s] ? inv : scl[s];
+        }
       }
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int c2 = 0; c2 < 16; ++c2) x[s][c2] *= scl[s];
+      // Pivot marks of this step (read by the tile waves after barrier 2).
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (chosen[s] >= 0) sInv[s * 64 + lane] = chosen[s];
       // Row i of the panel now holds row i of Z = E[:, P]: the update is
       // W_new = W + Z W[P] with the chosen rows W[P] set to zero first.
 #pragma unroll
