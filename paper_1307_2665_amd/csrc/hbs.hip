@@ -210,15 +210,17 @@ struct OrthDesc {
 };
 constexpr int ORTH_LDS = 16384;  // doubles: rows * cols limit
 
+// The vectors sit in LDS at an odd stride (rows, or rows + 1), so that the
+// lanes that each take one earlier vector's dot product read different banks.
 __global__ void __launch_bounds__(256) k_orth(const OrthDesc* __restrict__ descs) {
-  __shared__ double Q[ORTH_LDS];
-  __shared__ double r[256];
+  __shared__ double Q[ORTH_LDS + 128];
+  __shared__ double r[128];
   __shared__ double red[4];
   const OrthDesc d = descs[blockIdx.x];
-  const int n = d.rows, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int n = d.rows, ld = n | 1, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int e = tid; e < n * d.cols; e += 256) {
     const int c = e / n, i = e % n;
-    Q[e] = d.A[(size_t)i * d.rs + (size_t)c * d.cs];
+    Q[c * ld + i] = d.A[(size_t)i * d.rs + (size_t)c * d.cs];
   }
   __syncthreads();
   auto norm2 = [&](const double* v) {
@@ -231,26 +233,27 @@ __global__ void __launch_bounds__(256) k_orth(const OrthDesc* __restrict__ descs
     __syncthreads();
     return t;
   };
-  // v -= Q[0..c) (Q[0..c)^T v), twice.
+  // v -= Q[0..c) (Q[0..c)^T v), twice: thread q takes the dot product with
+  // vector q, then every thread updates its entries of v.
   auto project_out = [&](double* v, int c) {
     for (int pass = 0; pass < 2; ++pass) {
-      for (int q = w; q < c; q += 4) {
+      if (tid < c) {
+        const double* qv = Q + tid * ld;
         double a = 0.0;
-        for (int i = lane; i < n; i += 64) a += Q[q * n + i] * v[i];
-        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
-        if (lane == 0) r[q] = a;
+        for (int i = 0; i < n; ++i) a = fma(qv[i], v[i], a);
+        r[tid] = a;
       }
       __syncthreads();
       for (int i = tid; i < n; i += 256) {
         double a = v[i];
-        for (int q = 0; q < c; ++q) a -= r[q] * Q[q * n + i];
+        for (int q = 0; q < c; ++q) a = fma(-r[q], Q[q * ld + i], a);
         v[i] = a;
       }
       __syncthreads();
     }
   };
   for (int c = 0; c < d.cols; ++c) {
-    double* v = Q + c * n;
+    double* v = Q + c * ld;
     const double n0 = norm2(v);
     project_out(v, c);
     double nv = norm2(v);
@@ -271,7 +274,7 @@ __global__ void __launch_bounds__(256) k_orth(const OrthDesc* __restrict__ descs
   }
   for (int e = tid; e < n * d.cols; e += 256) {
     const int c = e / n, i = e % n;
-    d.A[(size_t)i * d.rs + (size_t)c * d.cs] = Q[e];
+    d.A[(size_t)i * d.rs + (size_t)c * d.cs] = Q[c * ld + i];
   }
 }
 
