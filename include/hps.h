@@ -494,6 +494,8 @@ hps_status hps_plan_box(const int nleaf[2], int q, int box, int rec[8], int size
      10^-e max|A_ii| ("bgj_fallback_tol_exp") is assembled again and
      eliminated with partial pivoting; 0 keeps the register kernels and the
      panel solver;
+   "hbs_grid": workgroups of the persistent HBS apply / solve launch (0 or
+     -1: two per CU; values are capped at what fits on the device at once);
    "solve_persist": 1 runs plain solves below 16 right-hand sides as one
      cooperative launch with a grid-wide barrier between levels (bit for bit
      the level passes' result); 0 (default, also -1) uses the level passes

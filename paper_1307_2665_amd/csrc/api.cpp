@@ -604,6 +604,9 @@ hps_status hps_tune_set(const char* knob, int value) {
     } else if (k == "leaf_bgj") {
       HPS_REQUIRE(value >= -1 && value <= 1, "leaf_bgj must be -1, 0 or 1");
       hps::set_leaf_bgj(value != 0);
+    } else if (k == "hbs_grid") {
+      HPS_REQUIRE(value >= -1, "hbs_grid must be >= -1");
+      hps::hbs_set_pass_grid(value < 0 ? 0 : value);
     } else if (k == "solve_persist") {
       HPS_REQUIRE(value >= -1 && value <= 1, "solve_persist must be -1, 0 or 1");
       hps::set_solve_persist(value == 1);

@@ -44,5 +44,7 @@ void hbs_compress(const HbsLayout& lo, const double* H, int ldh, const double* o
 int hbs_max_compress_rank(int m);
 // Drops the recorded apply / solve passes (the device must be idle).
 void hbs_passes_clear();
+// Workgroups of the persistent apply / solve launch (0: two per CU).
+void hbs_set_pass_grid(int workgroups);
 
 }  // namespace hps

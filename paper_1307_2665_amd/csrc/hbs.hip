@@ -412,8 +412,9 @@ void hbs_invert(const HbsLayout& lo, const double* fac, double* inv, hipStream_t
 // launch runs all phases, separated by grid barriers; 16 lanes take one row
 // (128-byte segments of A), up to 8 right-hand sides at a time.  The hat
 // blocks pass between workgroups on different XCDs, so they are written and
-// read with device-scope relaxed atomics (grid_sync.h); the factors and x are
-// read with plain loads and the output y is written with plain stores.  A
+// read with device-scope relaxed atomics (grid_sync.h), read once per node
+// and workgroup into LDS; the factors and x are read with plain loads and the
+// output y is written with plain stores.  A
 // barrier that waits about a second sets the error flag (reported as a
 // device error) and lets the workgroup go on, so the launch always ends.
 // ---------------------------------------------------------------------------
@@ -431,53 +432,79 @@ struct Phase {
 };
 constexpr int PASS_NC = 8;
 
+// Each workgroup takes a contiguous share of a phase's rows.  For every node
+// its share touches, the hat blocks that node reads (K x nrhs doubles each,
+// written by other workgroups in the previous phases) are staged once in LDS
+// with device-scope loads, so the rows then read them from LDS; a hat block
+// larger than PASS_LDS doubles is read from memory row by row instead.
+constexpr int PASS_LDS = 4096;
+
 __global__ void __launch_bounds__(256) k_hbs_pass(const Phase* __restrict__ ph, int nph,
                                                   const RowDesc* __restrict__ rd, int N,
                                                   unsigned* bar, int* err) {
+  __shared__ double sB[2][PASS_LDS];
   const int g = threadIdx.x >> 4, l = threadIdx.x & 15;
-  const int ngroups = gridDim.x * 16, gid = blockIdx.x * 16 + g;
   unsigned gen = 0;
   for (int p = 0; p < nph; ++p) {
     const Phase P = ph[p];
-    const int tasks = P.nodes * P.rows;
-    for (int t = gid; t < tasks; t += ngroups) {
-      const RowDesc d = rd[P.first + t / P.rows];
-      const int r = t % P.rows;
-      for (int c0 = 0; c0 < N; c0 += PASS_NC) {
-        double acc[PASS_NC];
+    const long long rows = (long long)P.nodes * P.rows;
+    const long long r0 = rows * blockIdx.x / gridDim.x, r1 = rows * (blockIdx.x + 1) / gridDim.x;
+    for (long long t = r0; t < r1;) {  // the same trip count for the whole workgroup
+      const int node = (int)(t / P.rows);
+      const long long te = min(r1, (long long)(node + 1) * P.rows);
+      const RowDesc d = rd[P.first + node];
+      const bool st0 = !d.plain0 && d.K0 * N <= PASS_LDS;
+      const bool st1 = !d.plain1 && d.K1 * N <= PASS_LDS;
+      __syncthreads();  // the previous node's rows are done with sB
+      if (st0)
+        for (int e = threadIdx.x; e < d.K0 * N; e += 256) sB[0][e] = ld_dev(d.B0 + e);
+      if (st1)
+        for (int e = threadIdx.x; e < d.K1 * N; e += 256) sB[1][e] = ld_dev(d.B1 + e);
+      __syncthreads();
+      for (long long row = t + g; row < te; row += 16) {
+        const int r = (int)(row - (long long)node * P.rows);
+        for (int c0 = 0; c0 < N; c0 += PASS_NC) {
+          double acc[PASS_NC];
 #pragma unroll
-        for (int c = 0; c < PASS_NC; ++c) acc[c] = 0.0;
+          for (int c = 0; c < PASS_NC; ++c) acc[c] = 0.0;
 #pragma unroll
-        for (int term = 0; term < 2; ++term) {
-          const double* A = term ? d.A1 : d.A0;
-          const double* B = term ? d.B1 : d.B0;
-          const int K = term ? d.K1 : d.K0, lda = term ? d.lda1 : d.lda0;
-          const bool plain = (term ? d.plain1 : d.plain0) != 0;
-          const double* a = A + (size_t)r * lda;
-          for (int kk = l; kk < K; kk += 16) {
-            const double av = a[kk];
-            const double* b = B + (size_t)kk * N + c0;
+          for (int term = 0; term < 2; ++term) {
+            const double* A = term ? d.A1 : d.A0;
+            const double* B = term ? d.B1 : d.B0;
+            const int K = term ? d.K1 : d.K0, lda = term ? d.lda1 : d.lda0;
+            const bool plain = (term ? d.plain1 : d.plain0) != 0;
+            const bool staged = term ? st1 : st0;
+            const double* sb = sB[term];
+            const double* a = A + (size_t)r * lda;
+            for (int kk = l; kk < K; kk += 16) {
+              const double av = a[kk];
+              const size_t o = (size_t)kk * N + c0;
 #pragma unroll
-            for (int c = 0; c < PASS_NC; ++c)
-              if (c0 + c < N) acc[c] = fma(av, plain ? b[c] : ld_dev(b + c), acc[c]);
+              for (int c = 0; c < PASS_NC; ++c)
+                if (c0 + c < N) {
+                  const double bv = staged ? sb[o + c] : (plain ? B[o + c] : ld_dev(B + o + c));
+                  acc[c] = fma(av, bv, acc[c]);
+                }
+            }
           }
-        }
-#pragma unroll
-        for (int c = 0; c < PASS_NC; ++c)
-#pragma unroll
-          for (int off = 8; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 16);
-        if (l == 0) {
-          double* cr = d.C + (size_t)r * N + c0;
 #pragma unroll
           for (int c = 0; c < PASS_NC; ++c)
-            if (c0 + c < N) {
-              if (P.out)
-                cr[c] = acc[c];
-              else
-                st_dev(cr + c, acc[c]);
-            }
+#pragma unroll
+            for (int off = 8; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, 16);
+          if (l == 0) {
+            double* cr = d.C + (size_t)r * N + c0;
+#pragma unroll
+            for (int c = 0; c < PASS_NC; ++c)
+              if (c0 + c < N) {
+                if (P.out)
+                  cr[c] = acc[c];
+                else
+                  st_dev(cr + c, acc[c]);
+              }
+          }
         }
       }
+      t = te;
     }
     if (p + 1 < nph) grid_barrier(bar, gridDim.x, gen, err);
   }
@@ -616,16 +643,18 @@ std::map<PassKey, std::unique_ptr<CachedPass>> g_passes;
 std::list<PassKey> g_pass_order;
 constexpr size_t MAX_PASSES = 16;
 
+int g_pass_grid_req = 0;  // knob hbs_grid: workgroups of a pass (0: two per CU)
+
 int pass_grid() {
-  static int grid = -1;
-  if (grid < 0) {
-    int dev = 0, cus = 0, per = 0;
+  static int cus = -1, per = 0;
+  if (cus < 0) {
+    int dev = 0;
     HPS_HIP(hipGetDevice(&dev));
     HPS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     HPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_hbs_pass, 256, 0));
-    grid = per >= 1 ? cus : 0;
   }
-  return grid;
+  if (per < 1) return 0;
+  return std::min(g_pass_grid_req > 0 ? g_pass_grid_req : 2 * cus, cus * per);
 }
 
 template <class Build>
@@ -687,6 +716,8 @@ void run_pass(int kind, const HbsLayout& lo, const double* mat, const double* x,
 }
 
 }  // namespace
+
+void hbs_set_pass_grid(int workgroups) { g_pass_grid_req = std::max(0, workgroups); }
 
 void hbs_passes_clear() {
   std::lock_guard<std::mutex> lk(g_pass_mu);
