@@ -382,7 +382,7 @@ hps_status hps_batched_gemm(const double* A, const double* B, double* C, int Mr,
    into a HIP graph on the first call and replay it afterwards (the last 16
    such passes are kept; hps_mem_trim drops them): the buffers' contents may
    change between calls, their addresses are part of the record.  Sizes outside the limits
-   (L in [1, 20], 1 <= k <= m, m and 2k at most 3072) give HPS_EINVAL. */
+   (L in [1, 14], 1 <= k <= m, m and 2k at most 3072) give HPS_EINVAL. */
 
 /* Numbers of doubles in the factor and inverse buffers (either may be null). */
 hps_status hps_hbs_sizes(int L, int m, int k, size_t* n_factors, size_t* n_inverse);

@@ -548,7 +548,7 @@ hps_status hps_root_dtn_compress(const hps_op* op, int L, int k, const double* o
   return guard([&] {
     HPS_REQUIRE(op && omega && psit && factors, "bad arguments");
     HPS_REQUIRE(op->opt.root_dtn, "operator was built without the root DtN");
-    HPS_REQUIRE(L >= 1 && L <= 20 && op->n_bdry % (1 << L) == 0,
+    HPS_REQUIRE(L >= 1 && L <= 14 && op->n_bdry % (1 << L) == 0,
                 "2^L must divide the number of boundary nodes");
     const int m = op->n_bdry >> L;
     hps::hbs_check(L, m, k);

@@ -68,7 +68,9 @@ HbsLayout::HbsLayout(int L_, int m_, int k_) : L(L_), m(m_), k(k_) {
 int hbs_max_compress_rank(int m) { return std::min(90, 16384 / std::max(m, 1)); }
 
 void hbs_check(int L, int m, int k) {
-  HPS_REQUIRE(L >= 1 && L <= 20, "HBS levels must be in [1, 20]");
+  // At most 2^14 leaves: a level's batched launches keep under 65536
+  // descriptors (the limit of a grid's second and third dimensions).
+  HPS_REQUIRE(L >= 1 && L <= 14, "HBS levels must be in [1, 14]");
   HPS_REQUIRE(k >= 1 && m >= k, "HBS sizes need 1 <= k <= m");
   HPS_REQUIRE(m <= max_solve_rows() && 2 * k <= max_solve_rows(), "HBS blocks too large");
   HPS_REQUIRE(((long long)m << L) <= (1LL << 30), "HBS matrix too large");

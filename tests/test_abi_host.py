@@ -201,3 +201,22 @@ def test_tuning_cache_of_older_format_is_refused(tmp_path):
     with pytest.raises(H.HpsError) as e:
         H.tune_load(old)
     assert e.value.status == H.HPS_EINVAL
+
+
+def test_hbs_sizes_follow_the_documented_layout():
+    """hps_hbs_sizes counts the blocks that include/hps.h lists (host code only),
+    and sizes outside the limits are rejected."""
+    import paper_1307_2665_amd as H
+    for L, m, k in [(1, 16, 4), (3, 40, 12), (6, 160, 80), (14, 8, 2)]:
+        nf, ni = H.hbs_sizes(L, m, k)
+        leaves = (1 << L) * (m * m + 2 * m * k)
+        parents = sum((1 << l) * 4 * k * k for l in range(1, L))
+        b = sum((1 << l) * 4 * k * k for l in range(0, L))
+        assert nf == leaves + parents + b
+        inv = (1 << L) * (2 * m * k + m * m)
+        inv += sum((1 << l) * (2 * 2 * k * k + 4 * k * k) for l in range(1, L)) + 4 * k * k
+        assert ni == inv
+    for L, m, k in [(0, 16, 4), (15, 16, 4), (3, 8, 9), (3, 16, 0), (2, 4000, 4)]:
+        with pytest.raises(H.HpsError) as e:
+            H.hbs_sizes(L, m, k)
+        assert e.value.status == H.HPS_EINVAL
