@@ -93,6 +93,9 @@ def parse():
                          "1000 training fields)")
     ap.add_argument("--train-epochs", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hbs", action="store_true",
+                    help="sweep: skip the HBS form of the root DtN (compression, T_apply, "
+                         "Algorithms 3-4)")
     ap.add_argument("--body-refactor", action="store_true",
                     help="body workload: refactor the leaf systems in every solve instead of\n"
                          "keeping P1 A_ii^-1 from the build")
@@ -501,7 +504,9 @@ def train_sweep_surrogate(args, H, hi, np, torch, dev, p, q, n):
 def sweep_workload(args, H, hi, np, torch, dev, line):
     """Coefficient sweep on 256 x 256 leaves, p = 12, q = 10 (one field per step, four resident
     fields cycled): the plain FP64 form and the learned-surrogate form, each timed over the same
-    steps; the surrogate's solutions are compared with the FP64 form's on every field."""
+    steps; the surrogate's solutions are compared with the FP64 form's on every field.  After the
+    timed steps, one field's root DtN is measured in HBS form (hbs_root_dtn, not part of the
+    step)."""
     p, q, n = 12, 10, 256
     nf = 4
     fields = [hi.sweep_field(5000 + k) for k in range(nf)]
@@ -576,13 +581,20 @@ def sweep_workload(args, H, hi, np, torch, dev, line):
     forms["surrogate"]["rel_err_vs_fp64"] = max(errs)
     forms["bf16x6"]["rel_err_vs_fp64"] = max(_rel(a, b) for a, b in zip(sols["bf16x6"], sols["fp64"]))
     forms["surrogate"]["training"] = train
+    hbs = None
+    if not args.no_hbs:
+        # The last field's root DtN in HBS form (sections 6-8): T_apply compressed and dense.
+        pr, (C, F) = fields[0], ins[0]
+        op = H.build_solution_operator(C, pr.box, pr.nleaf, p, q)
+        hbs = hbs_root_measure(H, np, torch, dev, op, 5)
+        op.destroy()
     sel = args.mode if args.mode in forms else "fp64"
     line.update(value=forms[sel]["unknowns_per_s"], ms_per_step=forms[sel]["ms_per_step"],
                 dtype=DTYPE.get(sel, "f64"),
                 config={"workload": "sweep-256x256-p12-q10-1rhs", "nleaf": [n, n], "p": p, "q": q,
                         "nrhs": 1, "n_tot": n_tot, "fields_resident": nf, "mode": sel},
                 roofline=roofs[sel], forms=forms, autotune_s=tune_s,
-                residual_rel=forms["fp64"]["residual_rel"])
+                residual_rel=forms["fp64"]["residual_rel"], hbs_root_dtn=hbs)
     if not args.no_cpu_baseline:
         cb = chain_cpu_baseline(fields[0], args.cpu_sample_leaves, log)
         t_cpu = cb["t_leaf"] + cb["t_merge"] + cb["t_solve"]
@@ -688,15 +700,10 @@ def _event_ms(torch, np, reps, fn):
 HBS_L, HBS_K = 6, 80
 
 
-def hbs_workload(args, H, hi, np, torch, dev, line):
-    """Sections 6-8 on the largest single-GPU root DtN: the FP64 build of a 256 x 256 p = 12,
-    q = 10 sweep field gives T^1 of 10240 x 10240; it is compressed (Remark 8.2) to an HBS
-    matrix on 64 leaves of 160 points with rank 80, then applied (T_apply, eq:tele1-3),
-    inverted (Algorithm 3) and its inverse applied (Algorithm 4).  The line's value is HBS
-    T_apply at one right-hand side; the dense T_apply of the same matrix is timed beside it."""
-    pr = hi.sweep_field(5000)
-    C, F = _inputs(H, pr, np, torch, dev)
-    op = H.build_solution_operator(C, pr.box, pr.nleaf, pr.p, pr.q)
+def hbs_root_measure(H, np, torch, dev, op, reps):
+    """The root DtN of a built operator in HBS form (sections 6-8): compression on 2^6 leaves
+    with rank 80, T_apply in HBS form and dense, Algorithm 3 and Algorithm 4, each the median of
+    `reps` blocking calls timed with HIP events; errors against the dense DtN."""
     M, L, k = op.n_bdry, HBS_L, HBS_K
     m = M >> L
     rng = np.random.default_rng(21)
@@ -705,7 +712,6 @@ def hbs_workload(args, H, hi, np, torch, dev, line):
     nfac, ninv = H.hbs_sizes(L, m, k)
     fac = torch.empty(nfac, dtype=torch.float64, device=dev)
     inv = torch.empty(ninv, dtype=torch.float64, device=dev)
-    reps = max(args.steps, 3)
     t_comp = _event_ms(torch, np, reps, lambda: H.hbs_compress(op, L, k, om, pt, fac))
     x = torch.tensor(rng.standard_normal((M, 1)), dtype=torch.float64, device=dev)
     y = torch.empty_like(x)
@@ -719,10 +725,30 @@ def hbs_workload(args, H, hi, np, torch, dev, line):
     t_solve = _event_ms(torch, np, reps, lambda: H.hbs_solve(inv, x, L, m, k, z))
     back = op.root_dtn_apply(z.reshape(1, M).contiguous())
     res = float((back.reshape(-1) - x.reshape(-1)).abs().max() / x.abs().max())
-    byts = 8.0 * (nfac + 2 * M)
     log(f"hbs: compress {t_comp:.2f} ms, apply {t_apply * 1e3:.1f} us (dense {t_dense * 1e3:.1f} "
         f"us), rel err {err_apply:.2e}; invert {t_inv:.2f} ms, solve {t_solve * 1e3:.1f} us, "
         f"residual {res:.2e}")
+    return dict(M=M, levels=L, leaf_size=m, rank=k, compress_ms=t_comp, apply_ms=t_apply,
+                dense_apply_ms=t_dense, apply_rel_err_vs_dense=err_apply, invert_ms=t_inv,
+                solve_ms=t_solve, solve_residual_rel=res, factor_bytes=8.0 * nfac,
+                dense_bytes=8.0 * M * M)
+
+
+def hbs_workload(args, H, hi, np, torch, dev, line):
+    """Sections 6-8 on the largest single-GPU root DtN: the FP64 build of a 256 x 256 p = 12,
+    q = 10 sweep field gives T^1 of 10240 x 10240; it is compressed (Remark 8.2) to an HBS
+    matrix on 64 leaves of 160 points with rank 80, then applied (T_apply, eq:tele1-3),
+    inverted (Algorithm 3) and its inverse applied (Algorithm 4).  The line's value is HBS
+    T_apply at one right-hand side; the dense T_apply of the same matrix is timed beside it."""
+    pr = hi.sweep_field(5000)
+    C, F = _inputs(H, pr, np, torch, dev)
+    op = H.build_solution_operator(C, pr.box, pr.nleaf, pr.p, pr.q)
+    h = hbs_root_measure(H, np, torch, dev, op, max(args.steps, 3))
+    M, L, k, m = h["M"], h["levels"], h["rank"], h["leaf_size"]
+    nfac = h["factor_bytes"] / 8.0
+    t_apply = h["apply_ms"]
+    rng = np.random.default_rng(22)
+    byts = 8.0 * (nfac + 2 * M)
     gbs = byts / (t_apply * 1e-3) / 1e9
     line.update(metric="HBS root DtN applies/s (T_apply, sections 6-8)", unit="applies/s",
                 value=1e3 / t_apply, ms_per_step=t_apply, dtype="f64",
@@ -731,10 +757,7 @@ def hbs_workload(args, H, hi, np, torch, dev, line):
                 roofline=dict(bound="hbm", achieved=gbs, peak=PEAK["hbm"], unit="GB/s",
                               frac=gbs / PEAK["hbm"], traffic=None, kernel="hbs_apply (all levels)",
                               bytes_per_apply=byts),
-                hbs=dict(compress_ms=t_comp, apply_ms=t_apply, dense_apply_ms=t_dense,
-                         apply_rel_err_vs_dense=err_apply, invert_ms=t_inv, solve_ms=t_solve,
-                         solve_residual_rel=res, factor_bytes=8.0 * nfac,
-                         dense_bytes=8.0 * M * M))
+                hbs=h)
     if not args.no_cpu_baseline:
         # The oracle's telescoping product (oracle.hbs.apply) on factors of the same
         # leaf size and rank compressed from a 64 x 64-leaf field's root DtN (M = 2560),
