@@ -239,17 +239,32 @@ __global__ void __launch_bounds__(256) k_orth(const OrthDesc* __restrict__ descs
   // vector q, then every thread updates its entries of v.
   auto project_out = [&](double* v, int c) {
     for (int pass = 0; pass < 2; ++pass) {
+      // Four partial sums each, so the FMA chains overlap.
       if (tid < c) {
         const double* qv = Q + tid * ld;
-        double a = 0.0;
-        for (int i = 0; i < n; ++i) a = fma(qv[i], v[i], a);
-        r[tid] = a;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int i = 0;
+        for (; i + 4 <= n; i += 4) {
+          a0 = fma(qv[i], v[i], a0);
+          a1 = fma(qv[i + 1], v[i + 1], a1);
+          a2 = fma(qv[i + 2], v[i + 2], a2);
+          a3 = fma(qv[i + 3], v[i + 3], a3);
+        }
+        for (; i < n; ++i) a0 = fma(qv[i], v[i], a0);
+        r[tid] = (a0 + a1) + (a2 + a3);
       }
       __syncthreads();
       for (int i = tid; i < n; i += 256) {
-        double a = v[i];
-        for (int q = 0; q < c; ++q) a = fma(-r[q], Q[q * ld + i], a);
-        v[i] = a;
+        double a0 = v[i], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int q = 0;
+        for (; q + 4 <= c; q += 4) {
+          a0 = fma(-r[q], Q[q * ld + i], a0);
+          a1 = fma(-r[q + 1], Q[(q + 1) * ld + i], a1);
+          a2 = fma(-r[q + 2], Q[(q + 2) * ld + i], a2);
+          a3 = fma(-r[q + 3], Q[(q + 3) * ld + i], a3);
+        }
+        for (; q < c; ++q) a0 = fma(-r[q], Q[q * ld + i], a0);
+        v[i] = (a0 + a1) + (a2 + a3);
       }
       __syncthreads();
     }
