@@ -19,7 +19,11 @@ from .helpers import hbs_oracle_factors, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
-CASES = [(1, 16, 4, 1), (3, 40, 12, 3), (4, 100, 30, 5), (5, 64, 24, 2), (6, 160, 48, 1)]
+# (L, m, k, nrhs); 11 right-hand sides take two column chunks of the pass, and at
+# k = 30 with 70 right-hand sides a parent's hat blocks (2k x nrhs) exceed the pass's
+# LDS staging and are read from memory row by row.
+CASES = [(1, 16, 4, 1), (3, 40, 12, 3), (4, 100, 30, 5), (5, 64, 24, 2), (6, 160, 48, 1),
+         (3, 48, 16, 11), (3, 64, 30, 70)]
 
 
 @pytest.fixture(scope="module")
