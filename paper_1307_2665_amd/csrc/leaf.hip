@@ -801,13 +801,27 @@ __global__ void __launch_bounds__(64 * (NTI + 1), 4) k_leaf_mfma(
   for (int tt = wid; tt < NTR * NTR; tt += S::NW) {
     const int ta = tt / NTR, tb = tt % NTR;
     const int trow = 16 * ta + (lane & 15);
+    // P1 operands a chunk at a time, the chunk's loads in flight together
+    // (clamped addresses and a select, no branches), then its products.
+    constexpr int KS = NR / 4, CH = (KS + 1) / 2;
+    const int tr_c = min(trow, m - 1);
     d4 t = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int ks = 0; ks < NR / 4; ++ks) {
-      const int kk = 4 * ks + (lane >> 4);
-      const double a = (trow < m && kk < n) ? P1[(size_t)trow * n + kk] : 0.0;
-      const double b = sR[kk * S::LDR + 16 * tb + (lane & 15)];
-      t = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, t, 0, 0, 0);
+    for (int k0 = 0; k0 < KS; k0 += CH) {
+      double af[CH];
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        const int kk = 4 * (k0 + j) + (lane >> 4);
+        const double v = as_global(P1)[(size_t)tr_c * n + min(kk, n - 1)];
+        af[j] = (k0 + j < KS && trow < m && kk < n) ? v : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < CH; ++j)
+        if (k0 + j < KS) {
+          const int kk = 4 * (k0 + j) + (lane >> 4);
+          const double b = sR[kk * S::LDR + 16 * tb + (lane & 15)];
+          t = __builtin_amdgcn_mfma_f64_16x16x4f64(af[j], b, t, 0, 0, 0);
+        }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
