@@ -1,11 +1,13 @@
-// HBS matrices on the device (sections 6-7): the telescoping product
-// (eq:tele1 - eq:tele3), Algorithm 3 and Algorithm 4.
+// HBS matrices on the device (sections 6-8): brute-force compression of a
+// dense matrix (Remark 8.2), the telescoping product (eq:tele1 - eq:tele3),
+// Algorithm 3 and Algorithm 4.
 //
-// Every step is a batch over the nodes of one tree level: the products are
-// grouped FP64 GEMM launches (one descriptor per node and block), and the
-// inverses of Algorithm 3 (Dt^-1 and Dhat) are batched Gauss-Jordan solves
-// with partial pivoting on [Dt | U | I] and [V* Dt^-1 U | I].  The levels run
-// in order on the caller's stream; nodes of a level are independent.
+// Compression and Algorithm 3 run level by level, each step a batch over the
+// nodes of one tree level: products are grouped launches (one descriptor per
+// node and block), the inverses of Algorithm 3 (Dt^-1 and Dhat) batched
+// Gauss-Jordan solves with partial pivoting on [Dt | U | I] and
+// [V* Dt^-1 U | I].  The product and Algorithm 4 are one persistent launch
+// each (below).  Everything runs in order on the caller's stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -120,7 +122,7 @@ GemmDesc gd(const double* A, int lda, const double* B, int ldb, double* C, int l
   return g;
 }
 
-// Skinny products of the HBS passes (N <= 8 right-hand sides, K N <= 4096):
+// Skinny products of compression and Algorithm 3 (N <= 8 columns, K N <= 4096):
 // 16 lanes per row of C read the row of A in 128-byte segments against B
 // staged in LDS, then reduce across the group; C = C0 or the old C (unless
 // overwrite) plus alpha A B, as in the grouped GEMM.  Grid: (rows / 64,
