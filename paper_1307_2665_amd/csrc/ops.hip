@@ -1592,7 +1592,9 @@ static void launch_down_mm(const MergeDesc* d_desc, int nmerge, int m3_max, int 
   hipLaunchKernelGGL((k_down_mm<HPS_MMT(BM, BN)>), grid, dim3(MmCfg<BM, BN>::NT), 0, s, d_desc, U,
                      nrhs, zbase, zoff, io, ks, P, m3_max);
   if (ks > 1) {
-    const int bx = std::max(1, std::min(64, (m3_max * nrhs + 255) / 256));
+    // One thread per output element: the top levels (one to a few merges)
+    // would otherwise leave most of the chip idle while summing the chunks.
+    const int bx = std::max(1, (m3_max * nrhs + 255) / 256);
     hipLaunchKernelGGL(k_down_reduce, dim3(bx, nmerge), dim3(256), 0, s, d_desc, U, nrhs, zbase,
                        zoff, ks, P, m3_max);
     HPS_HIP(hipFreeAsync(P, s));
