@@ -1874,7 +1874,8 @@ static void launch_up_mm(const MergeDesc* d_desc, int nmerge, int m3_max, int me
   if (ksz > 1 || ksh > 1)
     HPS_HIP(hipMallocAsync((void**)&P, std::max(ksz > 1 ? pz : 0, ksh > 1 ? ph : 0) *
                                            sizeof(double), st));
-  const int bx = std::max(1, std::min(64, ((m3_max + me_max) * nrhs + 255) / 256));
+  // Chunk sums: one thread per output element (see launch_down_mm).
+  const int bx = std::max(1, ((m3_max + me_max) * nrhs + 255) / 256);
   dim3 gz(ct, (m3_max + BMZ - 1) / BMZ, nmerge * ksz);
   hipLaunchKernelGGL((k_up_z_mm<HPS_MMT(BMZ, BN)>), gz, dim3(MmCfg<BMZ, BN>::NT), 0, st, d_desc,
                      rbuf, zbuf, z_off, nrhs, ksz, P, m3_max);
@@ -1912,7 +1913,7 @@ void upward_level_nm(const MergeDesc* d_desc, int nmerge, int m3_max, int me_max
                      int nrhs, double flops, hipStream_t st) {
   if (nmerge == 0) return;
   ProfScope ps(PROF_UPWARD, st, flops, 8.0 * flops / (2.0 * nrhs));
-  const int bx = std::min(64, std::max(1, (m3_max + 3) / 4));
+  const int bx = std::max(1, (m3_max + 3) / 4);  // one row per group of 64 threads
   hipLaunchKernelGGL(k_up_gather_nm, dim3(bx, nmerge), dim3(64, 4), 0, st, d_desc, src, hbase,
                      ha_off, hb_off, z_off, nrhs, rbuf);
   const int bm = mm_rows(m3_max);
