@@ -17,6 +17,9 @@ Everything here is plain, slow, FP64 NumPy/SciPy written from the paper:
   one dense system) and the dense interface system built from leaf DtNs; both
   pin Remark 5.1 (the merges are exact).
 * ``oracle.mlp``   -- FP64 forward/backward of the leaf-DtN surrogate network.
+* ``oracle.hbs``   -- sections 6-7: HBS matrices on a uniform binary tree (brute-force
+  compression with nested orthonormal bases, the telescoping factorization and product,
+  Algorithms 3 and 4) and thin factors of low-rank matrices.
 
 Parity status: every function is pinned by tests under ``tests/`` except the
 surrogate network's *target quality*, which the paper does not cover ("parity
